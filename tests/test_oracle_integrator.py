@@ -1,0 +1,124 @@
+"""Pins for the oracle's leapfrog (KDK), block-step levels and SMBH pairs.
+
+References: a Kepler two-body orbit (energy error falls as dt^2, the
+paper's tau^2 scaling in its time-step study), time reversibility of the
+symmetric leapfrog, and the reduction of block steps on a single level to
+the global-step leapfrog, bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _kepler_step(x, v, m, eps, dt, n):
+    """n KDK steps of two bodies using the oracle's pair forces."""
+    acc, _ = oracle.direct_pairs(x, m, eps, x, eps, self_pairs=True)
+    for _ in range(n):
+        oracle.kick(v, acc, dt)
+        oracle.drift(x, v, dt)
+        acc, _ = oracle.direct_pairs(x, m, eps, x, eps, self_pairs=True)
+        oracle.kick(v, acc, dt)
+    return x, v
+
+
+def _energy(x, v, m, eps):
+    _, pot = oracle.direct_pairs(x, m, eps, x, eps, self_pairs=True)
+    return 0.5 * np.sum(m * np.sum(v * v, 1)) + 0.5 * np.sum(m * pot)
+
+
+def _binary():
+    m = np.array([0.6, 0.4])
+    x = np.array([[-0.4, 0.0, 0.0], [0.6, 0.0, 0.0]])
+    vt = np.sqrt(1.0 / 1.0) * 0.8           # sub-circular: eccentric orbit
+    v = np.array([[0.0, -0.4 * vt, 0.0], [0.0, 0.6 * vt, 0.0]])
+    return x, v, m
+
+
+def test_kepler_energy_error_scales_dt_squared():
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        x, v, m = _binary()
+        e0 = _energy(x, v, m, 0.0)
+        x, v = _kepler_step(x, v, m, 0.0, dt, int(round(6.0 / dt)))
+        errs.append(abs(_energy(x, v, m, 0.0) - e0) / abs(e0))
+    assert 3.0 < errs[0] / errs[1] < 5.5
+    assert 3.0 < errs[1] / errs[2] < 5.5
+
+
+def test_leapfrog_time_reversible():
+    x, v, m = _binary()
+    x0, v0 = x.copy(), v.copy()
+    x, v = _kepler_step(x, v, m, 0.01, 0.01, 200)
+    v *= -1.0
+    x, v = _kepler_step(x, v, m, 0.01, 0.01, 200)
+    v *= -1.0
+    assert np.allclose(x, x0, atol=1e-11) and np.allclose(v, v0, atol=1e-11)
+
+
+def test_direct_pairs_softening_is_pair_max():
+    s = np.array([[0.0, 0.0, 0.0]])
+    t = np.array([[0.3, 0.4, 0.0]])
+    a, p = oracle.direct_pairs(s, np.array([2.0]), np.array([0.1]), t, np.array([0.2]))
+    r2 = 0.25 + 0.04
+    assert p[0] == pytest.approx(-2.0 / np.sqrt(r2), rel=1e-15)
+    assert np.allclose(a[0], -2.0 * t[0] / r2 ** 1.5, rtol=1e-15)
+
+
+def test_levels_thresholds():
+    nlev, dtmax = 8, 2.0 ** -6
+    tau, eps = 0.3, 0.01
+    # choose |a| so that dt = tau sqrt(eps/|a|) sits just either side of dt_l
+    acc, want = [], []
+    for l in range(nlev):
+        dl = dtmax * 2.0 ** -l
+        amag = tau * tau * eps / (dl * dl)
+        for f, lev in ((1.0 - 1e-9, l), (1.0 + 1e-9, min(l + 1, nlev - 1))):
+            acc.append([amag * f, 0.0, 0.0])
+            want.append(lev)
+    acc = np.array(acc)
+    level = np.zeros(len(acc), np.uint8)
+    oracle.levels(acc, np.full(len(acc), tau ** 4 * eps ** 2), level, dtmax, nlev, 0)
+    assert list(level) == want
+    # at substep k = 2 only levels with step dividing 2 are allowed
+    level[:] = 7
+    oracle.levels(np.zeros((len(acc), 3)), np.ones(len(acc)), level, dtmax, nlev, 2)
+    assert np.all(level == 6)
+
+
+def test_active_sets():
+    level = np.array([0, 7, 6, 3, 7], np.uint8)
+    assert list(oracle.active_at(level, 8, 0)) == [0, 1, 2, 3, 4]
+    assert list(oracle.active_at(level, 8, 1)) == [1, 4]
+    assert list(oracle.active_at(level, 8, 2)) == [1, 2, 4]
+    assert list(oracle.active_at(level, 8, 16)) == [1, 2, 3, 4]
+    assert list(oracle.active_at(level, 8, 128)) == [0, 1, 2, 3, 4]
+
+
+def _block_run(x, v, m, eps, level_const, nlev, dtmax, nsub):
+    """Block-step KDK with every particle pinned to one level."""
+    n = x.shape[0]
+    level = np.full(n, level_const, np.uint8)
+    dtmin = dtmax * 2.0 ** -(nlev - 1)
+    acc, _ = oracle.direct_pairs(x, m, eps, x, eps, self_pairs=True)
+    for k in range(nsub):
+        act = oracle.active_at(level, nlev, k)
+        if k > 0:
+            oracle.kick(v, acc, dtmax, idx=act, level=level)      # closing
+        oracle.kick(v, acc, dtmax, idx=act, level=level)          # opening
+        oracle.drift(x, v, dtmin)
+        nxt = oracle.active_at(level, nlev, k + 1)
+        if nxt.size:
+            a2, _ = oracle.direct_pairs(x, m, eps, x, eps, self_pairs=True)
+            acc[nxt] = a2[nxt]
+    act = oracle.active_at(level, nlev, nsub)
+    oracle.kick(v, acc, dtmax, idx=act, level=level)
+    return x, v
+
+
+def test_block_steps_on_one_level_equal_global_kdk_bitwise():
+    nlev, dtmax = 8, 2.0 ** -6
+    x, v, m = _binary()
+    xb, vb = _block_run(x.copy(), v.copy(), m, 0.01, 7, nlev, dtmax, 16)
+    xg, vg = _kepler_step(x.copy(), v.copy(), m, 0.01, dtmax * 2.0 ** -7, 16)
+    assert np.array_equal(xb, xg) and np.array_equal(vb, vg)

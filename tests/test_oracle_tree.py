@@ -1,0 +1,237 @@
+"""Pins for the oracle's keys, sort, octree, moments and groups.
+
+Each check is independent of the oracle's own code: a recursive geometric
+subdivision on the integer cell coordinates, a magic-number bit spreader for
+the Morton keys, numpy's stable sort, the parallel-axis theorem and closed
+forms for simple mass layouts.
+"""
+from collections import deque
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st, HealthCheck
+
+import oracle
+from paper_1507_01009_amd import ics
+
+NB = 21
+
+
+def _q_coords(pos, lo, L):
+    t = pos - lo[None, :]
+    u = t * (2.0 ** NB / L)
+    q = np.floor(u).astype(np.int64)
+    return np.clip(q, 0, 2 ** NB - 1)
+
+
+def _spread3(v):
+    """Insert two zero bits between the 21 low bits of v (magic masks)."""
+    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
+    v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+    v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+    v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+    v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+    v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
+    return v
+
+
+def _geometric_tree(q, nleaf):
+    """Breadth-first octree by splitting integer boxes at their midpoints."""
+    out = []
+    dq = deque([(0, np.arange(q.shape[0]), np.zeros(3, np.int64))])
+    while dq:
+        lev, mem, corner = dq.popleft()
+        rec = {"level": lev, "members": set(mem.tolist()), "children": []}
+        out.append(rec)
+        if len(mem) > nleaf and lev < NB:
+            half = 2 ** (NB - lev - 1)
+            side = (q[mem] - corner[None, :]) >= half
+            for o in range(8):
+                b = np.array([(o >> 2) & 1, (o >> 1) & 1, o & 1], bool)
+                sel = mem[np.all(side == b[None, :], axis=1)]
+                if sel.size:
+                    rec["children"].append(len(out) + len(dq))
+                    dq.append((lev + 1, sel, corner + half * b.astype(np.int64)))
+    return out
+
+
+def _check_tree_against_geometry(pos, nleaf):
+    t = oracle.build_tree(pos, None, nleaf)
+    lo = pos.min(0)
+    L = float((pos.max(0) - lo).max()) or 1.0
+    assert np.array_equal(t.cube[0], np.r_[lo, L])
+    q = _q_coords(pos, lo, L)
+    key = (_spread3(q[:, 0]) << np.uint64(2)) | (_spread3(q[:, 1]) << np.uint64(1)) | _spread3(q[:, 2])
+    assert np.array_equal(t.keys, key)
+    ref_perm = np.lexsort((np.arange(pos.shape[0]), key))
+    assert np.array_equal(t.perm.astype(np.int64), ref_perm)
+    ref = _geometric_tree(q, nleaf)
+    assert t.nn == len(ref)
+    for v, r in enumerate(ref):
+        assert t.level[v] == r["level"]
+        mem = set(t.perm[t.first[v]:t.first[v] + t.count[v]].tolist())
+        assert mem == r["members"]
+        assert t.nchild[v] == len(r["children"])
+        if r["children"]:
+            assert list(range(t.child[v], t.child[v] + t.nchild[v])) == r["children"]
+    return t
+
+
+def test_tree_matches_geometric_subdivision_plummer():
+    pos, _, _ = ics.plummer(1500, 7)
+    _check_tree_against_geometry(pos, 8)
+
+
+def test_tree_overfull_leaves_at_max_level():
+    rng = np.random.default_rng(3)
+    base = rng.normal(size=(40, 3))
+    pos = np.concatenate([base, np.repeat(base[:3], 12, axis=0)])  # duplicates
+    t = _check_tree_against_geometry(pos, 4)
+    deep = (t.nchild == 0) & (t.count > 4)
+    assert deep.any() and np.all(t.level[deep] == NB)
+
+
+_pos_strategy = st.integers(1, 200).flatmap(
+    lambda n: st.tuples(st.just(n), st.integers(0, 2 ** 31 - 1),
+                        st.sampled_from([1, 2, 8, 16]),
+                        st.sampled_from(["normal", "grid", "dup", "line"])))
+
+
+def _make(n, seed, kind):
+    rng = np.random.default_rng(seed)
+    if kind == "normal":
+        return rng.normal(size=(n, 3)) * 10.0 ** rng.uniform(-3, 3)
+    if kind == "grid":
+        return rng.integers(0, 4, size=(n, 3)).astype(np.float64)
+    if kind == "dup":
+        b = rng.normal(size=(max(1, n // 4), 3))
+        return b[rng.integers(0, b.shape[0], n)]
+    x = rng.uniform(-1, 1, n)
+    return np.stack([x, 0 * x + 0.5, 2 * x], 1)
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(_pos_strategy)
+def test_tree_invariants_and_geometry(args):
+    n, seed, nleaf, kind = args
+    pos = _make(n, seed, kind)
+    t = _check_tree_against_geometry(pos, nleaf)
+    pre = t.prefix()
+    for v in range(t.nn):
+        a, b = int(t.first[v]), int(t.first[v] + t.count[v])
+        sh = np.uint64(3 * (NB - int(t.level[v])))
+        assert np.all((t.skeys[a:b] >> sh) == pre[v])
+        if t.nchild[v]:
+            assert t.count[v] > nleaf and t.level[v] < NB
+            c0, c1 = int(t.child[v]), int(t.child[v] + t.nchild[v])
+            assert t.first[c0] == t.first[v]
+            assert np.all(t.first[c0 + 1:c1] == t.first[c0:c1 - 1] + t.count[c0:c1 - 1])
+            assert int(t.count[c0:c1].sum()) == int(t.count[v])
+            assert np.all(t.parent[c0:c1] == v)
+        else:
+            assert t.count[v] <= nleaf or t.level[v] == NB
+
+
+def test_keys_shift_by_power_of_two_is_invariant():
+    pos, _, _ = ics.plummer(500, 11)
+    t0 = oracle.build_tree(pos)
+    t1 = oracle.build_tree(pos + 64.0)
+    assert np.array_equal(t0.keys, t1.keys)
+    assert np.array_equal(t0.first, t1.first) and np.array_equal(t0.count, t1.count)
+
+
+def test_particles_lie_in_their_leaf_cells():
+    pos, _, _ = ics.dehnen(3000, 1.5, 5)
+    t = oracle.build_tree(pos, None, 8)
+    lo, L = t.cube[0, :3], t.cube[0, 3]
+    pre = t.prefix()
+    for v in np.nonzero(t.nchild == 0)[0]:
+        lev = int(t.level[v])
+        p = int(pre[v])
+        ijk = np.zeros(3, np.int64)
+        for b in range(lev):            # de-interleave the prefix digits
+            d = (p >> (3 * (lev - 1 - b))) & 7
+            ijk = ijk * 2 + np.array([(d >> 2) & 1, (d >> 1) & 1, d & 1])
+        s = L * 2.0 ** -lev
+        xs = pos[t.perm[t.first[v]:t.first[v] + t.count[v]].astype(np.int64)]
+        assert np.all(xs >= lo + ijk * s - 1e-12 * L)
+        assert np.all(xs <= lo + (ijk + 1) * s + 1e-12 * L)
+
+
+def test_multiple_systems_match_separate_builds():
+    parts = [ics.plummer(300, 1)[0], ics.dehnen(700, 1.0, 2)[0], ics.plummer(5, 3)[0]]
+    off = np.r_[0, np.cumsum([p.shape[0] for p in parts])]
+    tb = oracle.build_tree(np.concatenate(parts), off, 8)
+    roots = np.nonzero(tb.level == 0)[0]
+    assert list(tb.sys[roots]) == [0, 1, 2]
+    for s, p in enumerate(parts):
+        ts = oracle.build_tree(p, None, 8)
+        assert np.array_equal(tb.keys[off[s]:off[s + 1]], ts.keys)
+        assert np.array_equal(tb.perm[off[s]:off[s + 1]] - off[s], ts.perm)
+        sel = tb.sys == s
+        # same level/count multiset per level (ids interleave across systems)
+        for lev in range(NB + 1):
+            a = np.sort(tb.count[sel & (tb.level == lev)])
+            b = np.sort(ts.count[ts.level == lev])
+            assert np.array_equal(a, b)
+
+
+def test_empty_systems_are_skipped():
+    p = ics.plummer(100, 4)[0]
+    t = oracle.build_tree(p, np.array([0, 0, 100, 100]), 8)
+    assert int((t.level == 0).sum()) == 1 and t.sys[0] == 1
+
+
+# ---------------------------------------------------------------- moments
+def test_moments_cube_corners_closed_form():
+    b, m = 0.25, 0.125
+    c0 = np.array([0.3, -1.2, 2.0])
+    corners = np.array([[i, j, k] for i in (-1, 1) for j in (-1, 1) for k in (-1, 1)], float)
+    pos = c0 + b * corners
+    mass = np.full(8, m)
+    t = oracle.build_tree(pos, None, 8)
+    sp, sm = oracle.sorted_arrays(t, pos, mass)
+    mom = oracle.moments(t, sp, sm)
+    assert mom[0, 0] == pytest.approx(8 * m, rel=1e-15)
+    assert np.allclose(mom[0, 1:4], c0, rtol=0, atol=1e-15)
+    assert np.allclose(mom[0, 4:7], 8 * m * b * b, rtol=1e-14)
+    assert np.allclose(mom[0, 7:10], 0.0, atol=1e-15)
+
+
+def test_moments_parallel_axis_from_children():
+    pos, _, mass = ics.dehnen(5000, 1.0, 9)
+    mass = mass * np.random.default_rng(1).uniform(0.5, 1.5, mass.shape)
+    t = oracle.build_tree(pos, None, 8)
+    sp, sm = oracle.sorted_arrays(t, pos, mass)
+    mom = oracle.moments(t, sp, sm)
+    for v in np.nonzero(t.nchild > 0)[0]:
+        ch = np.arange(t.child[v], t.child[v] + t.nchild[v])
+        M = mom[ch, 0].sum()
+        c = (mom[ch, 0, None] * mom[ch, 1:4]).sum(0) / M
+        d = mom[ch, 1:4] - c
+        S = mom[ch, 4:10].sum(0) + np.stack([
+            (mom[ch, 0] * d[:, 0] * d[:, 0]).sum(), (mom[ch, 0] * d[:, 1] * d[:, 1]).sum(),
+            (mom[ch, 0] * d[:, 2] * d[:, 2]).sum(), (mom[ch, 0] * d[:, 0] * d[:, 1]).sum(),
+            (mom[ch, 0] * d[:, 0] * d[:, 2]).sum(), (mom[ch, 0] * d[:, 1] * d[:, 2]).sum()])
+        scale = abs(mom[v, 4:7]).max()
+        assert abs(M - mom[v, 0]) <= 1e-14 * M
+        assert np.all(np.abs(c - mom[v, 1:4]) <= 1e-13 * (1 + np.abs(c)))
+        assert np.all(np.abs(S - mom[v, 4:10]) <= 1e-12 * scale)
+
+
+# ---------------------------------------------------------------- groups
+@pytest.mark.parametrize("nl,ng", [(8, 64), (8, 8), (16, 32), (4, 1)])
+def test_groups_partition_and_definition(nl, ng):
+    pos = np.concatenate([ics.dehnen(4000, 1.5, 12)[0], np.zeros((30, 3))])
+    t = oracle.build_tree(pos, None, nl)
+    g = oracle.groups(t, ng).astype(np.int64)
+    assert g[0, 0] == 0 and np.all(g[1:, 0] == g[:-1, 0] + g[:-1, 1])
+    assert g[-1, 0] + g[-1, 1] == pos.shape[0]
+    assert np.all(g[:, 1] <= ng) and np.all(g[:, 1] >= 1)
+    for f, c, v, s in g:
+        if t.count[v] <= ng:
+            assert t.first[v] == f and t.count[v] == c
+            p = t.parent[v]
+            assert p == 0xFFFFFFFF or t.count[p] > ng
+        else:
+            assert t.nchild[v] == 0 and (f - t.first[v]) % ng == 0
