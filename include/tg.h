@@ -1,0 +1,267 @@
+/*
+ * tg.h -- C ABI of libtg.so: softened Barnes-Hut tree gravity on one MI355X
+ * (gfx950), after the tree part of the hybrid tree + chain-regularisation
+ * code of Karl, Aarseth, Naab, Haehnelt & Spurzem (rVINE).
+ *
+ * What the library computes (paper passages):
+ *   - gravity of distant groups of particles from a multipole expansion about
+ *     the group's centre of mass, near particles summed directly (Sec. 1 and
+ *     the list of integration regions in Sec. 2);
+ *   - Plummer-softened pair forces (Sec. 3, softening paragraph);
+ *   - forces only for the active particles of a block-time-step scheme, a
+ *     leapfrog integrator, and FP64 direct forces between the SMBHs/chain
+ *     members and nearby stars (Sec. 2, the hybrid time-step steps (1), (6),
+ *     (7) and the perturber force-correction paragraph).
+ * Readings where the paper is silent: an octree over 21-bit Morton keys, a
+ * geometric opening angle theta (cell side s, distance d from the target
+ * group's box to the cell's centre of mass, accept iff s^2 < theta^2 d^2),
+ * monopole + quadrupole moments with the softened expansion
+ *   a += G(-M D3 x + D5 Q x - 2.5 D7 W x),  phi += G(-M D1 - 0.5 D5 W),
+ *   x = x_i - com, D_n = (|x|^2 + eps^2)^(-n/2), Q = 3S - tr(S) I,
+ *   W = x.Q.x - tr(S) eps^2,
+ * and kick-drift-kick leapfrog with power-of-two block levels.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev are device (HBM) pointers, owned by the caller and
+ *     only read or written during the call's stream work.  Pointers named
+ *     *_host are host memory, read before the call returns.
+ *   - Positions, velocities and accelerations are row-major [n][3] doubles in
+ *     the caller's particle order; outputs come back in that order.
+ *   - All work is enqueued asynchronously on the context's stream; nothing is
+ *     synchronised unless stated.  tg_sync() waits and reports device-side
+ *     errors.
+ *   - Every function returns TG_OK or a negative tg_status; tg_last_error()
+ *     gives the message of the last failure on the calling thread.  Argument
+ *     errors are detected on the host before anything is enqueued.
+ *   - A context allocates all of its device memory in tg_create(); no later
+ *     call allocates, so any sequence of calls between tg_graph_begin() and
+ *     tg_graph_end() can be captured into a HIP graph and replayed.
+ *   - One context per stream and per host thread at a time.
+ */
+#ifndef TG_H
+#define TG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TG_OK = 0,
+  TG_EINVAL = -1,     /* bad argument (NULL pointer, size, range) */
+  TG_ENOMEM = -2,     /* device allocation failed in tg_create */
+  TG_EHIP = -3,       /* a HIP runtime call failed */
+  TG_ECAPACITY = -4,  /* a capacity given at tg_create was exceeded */
+  TG_ESTATE = -5,     /* call out of order (e.g. forces before a tree) */
+  TG_EDATA = -6       /* device found non-finite positions or mass <= 0 */
+} tg_status;
+
+typedef enum { TG_FP64 = 0, TG_MIXED = 1 } tg_precision;
+
+/* Device error bits reported through tg_sync() / tg_error_bits(). */
+#define TG_ERR_NONFINITE   0x1u  /* a position is NaN or infinite */
+#define TG_ERR_MASS        0x2u  /* a mass is <= 0 or not finite */
+#define TG_ERR_NODES       0x4u  /* octree needed more than max_nodes */
+#define TG_ERR_FRONTIER    0x8u  /* walk frontier exceeded frontier_cap */
+#define TG_ERR_LISTS       0x10u /* list dump exceeded its capacity */
+
+typedef struct {
+  int64_t max_particles;   /* capacity N for every call (>= 1) */
+  int32_t max_systems;     /* capacity of independent systems S (1..256) */
+  int32_t leaf_size;       /* n_L: a node with more particles is refined (1..16) */
+  int32_t group_size;      /* n_G: particles sharing one walk (1..64) */
+  int32_t precision;       /* tg_precision of the walk and P2P/P2M sums */
+  int64_t max_nodes;       /* octree node capacity; 0 = 2 * max_particles + 64 * max_systems */
+  int32_t frontier_cap;    /* walk frontier entries per wave; 0 = 16384 */
+  int32_t waves_per_cu;    /* resident walk waves per compute unit; 0 = 8 */
+  double G;                /* gravitational constant (paper units: 1) */
+} tg_config;
+
+typedef struct tg_ctx tg_ctx;
+
+/* Fill *cfg with defaults: N = 1, S = 1, n_L = 8, n_G = 64, FP64, G = 1. */
+void tg_default_config(tg_config *cfg);
+
+/* Create a context on the current HIP device, working on `stream`
+ * (a hipStream_t; NULL = the default stream).  Allocates every device
+ * buffer for the capacities in *cfg.  Errors: TG_EINVAL, TG_ENOMEM, TG_EHIP. */
+tg_status tg_create(const tg_config *cfg, void *stream, tg_ctx **out);
+
+/* Free the context and its device memory (waits for its stream first). */
+void tg_destroy(tg_ctx *ctx);
+
+/* Use another stream for subsequent work. */
+tg_status tg_set_stream(tg_ctx *ctx, void *stream);
+
+/* Change n_L / n_G between builds (n_G also applies to tg_tree_forces);
+ * bounds as in tg_config.  Takes effect at the next tg_build_tree. */
+tg_status tg_set_sizes(tg_ctx *ctx, int32_t leaf_size, int32_t group_size);
+
+/* ---- a1..a6: cube, Morton keys, radix sort, gather, octree, groups ----
+ * Builds the octree of N particles split into S independent systems, the
+ * contiguous ranges sys_off_host[s] .. sys_off_host[s+1] (NULL with S = 1
+ * means one system [0, N)).  One root per non-empty system; a node with
+ * more than n_L particles below level 21 is refined into its non-empty
+ * octants; node ids are breadth first with children in octant order.
+ * Non-finite positions set TG_ERR_NONFINITE (reported by tg_sync).
+ * N = 0 is allowed (empty tree).  Errors: TG_EINVAL (N > capacity, S out of
+ * range, offsets not ascending), TG_ESTATE (system layout changed during
+ * graph capture). */
+tg_status tg_build_tree(tg_ctx *ctx, const double *pos_dev, int64_t n,
+                        const int64_t *sys_off_host, int32_t n_sys);
+
+/* ---- a7: monopole + quadrupole moments about each node's centre of mass
+ * (upward pass; leaves from their particles, internal nodes from children).
+ * mass_dev: [N] doubles, caller order, each > 0 (else TG_ERR_MASS).
+ * Requires a tree.  Errors: TG_ESTATE. */
+tg_status tg_compute_moments(tg_ctx *ctx, const double *mass_dev);
+
+/* ---- a6, a8..a10: group walk with the opening-angle test, P2P and P2M --
+ * Forces and potentials on the active particles from all particles of their
+ * own system.  active_idx_dev: caller-order indices of the targets, int32,
+ * distinct, n_active_dev[0] of them (both device; NULL active_idx_dev means
+ * all particles).  Rows of acc_dev ([N][3]) and pot_dev ([N], may be NULL)
+ * belonging to targets are overwritten; other rows are untouched.  The self
+ * pair is excluded.  0 < eps, 0 <= theta < 1/sqrt(3).
+ * Errors: TG_EINVAL, TG_ESTATE (no tree or moments). */
+tg_status tg_tree_forces(tg_ctx *ctx, double eps, double theta,
+                         const int32_t *active_idx_dev,
+                         const int32_t *n_active_dev, double *acc_dev,
+                         double *pot_dev);
+
+/* Interaction counts (synchronises the stream).  out[0..3] for the last
+ * tg_tree_forces: P2P pairs (target, source particle, j != i), particle-cell
+ * (P2M) pairs, targets, active groups walked; out[4..7] the same summed over
+ * every tg_tree_forces since the context was created or tg_reset_counts. */
+tg_status tg_get_counts(tg_ctx *ctx, int64_t out[8]);
+tg_status tg_reset_counts(tg_ctx *ctx);
+
+/* Parity/diagnostic mode of the walk: for every active group (ordered by
+ * its first particle, as numbered by the groups of the current tree) write
+ * its P2M cell ids and P2P leaf ids (unsorted, node ids of the current
+ * tree).  group_info_dev: [cap_groups][4] int64 = group index, P2M offset,
+ * P2M count, P2P count (P2P ids follow the P2M ids of the same group);
+ * ids_dev: [cap_ids] uint32.  Synchronises; *n_groups_out and *n_ids_out get
+ * the sizes (if larger than the caps nothing beyond the caps is written and
+ * TG_ECAPACITY is returned). */
+tg_status tg_walk_lists(tg_ctx *ctx, double theta,
+                        const int32_t *active_idx_dev,
+                        const int32_t *n_active_dev, int64_t *group_info_dev,
+                        int64_t cap_groups, uint32_t *ids_dev, int64_t cap_ids,
+                        int64_t *n_groups_out, int64_t *n_ids_out);
+
+/* ---- a11: double-precision direct forces (SMBH <-> stars, perturber <->
+ * chain members; Sec. 2).  Targets [nt] at tgt_pos_dev with softening
+ * tgt_eps_dev feel sources [ns] (src_pos_dev, src_mass_dev, src_eps_dev)
+ * with pair softening max(eps_i, eps_j).  With segments (nseg > 0,
+ * src_seg_host/tgt_seg_host ascending offsets [nseg+1]) only pairs in the
+ * same segment interact.  If self_pairs != 0 the two sets are the same
+ * particles and i == j is skipped.  accumulate != 0 adds to acc/pot, else
+ * overwrites.  pot_dev may be NULL.  Sums are compensated (double-double
+ * style Neumaier) and deterministic. */
+tg_status tg_direct_fp64(tg_ctx *ctx, const double *src_pos_dev,
+                         const double *src_mass_dev, const double *src_eps_dev,
+                         int64_t ns, const double *tgt_pos_dev,
+                         const double *tgt_eps_dev, int64_t nt,
+                         const int64_t *src_seg_host,
+                         const int64_t *tgt_seg_host, int32_t nseg,
+                         int32_t self_pairs, int32_t accumulate,
+                         double *acc_dev, double *pot_dev);
+
+/* ---- a12: leapfrog (kick-drift-kick) and block time-steps -------------
+ * kick: v += a h for the listed particles (all n when active_idx_dev is
+ * NULL; then n_active_dev is ignored and n gives the count).  h = dt / 2,
+ * or with level_dev != NULL, h = (dt * 2^-level_i) / 2 with dt = dt_max.
+ * If skip_at_k0 != 0 and k_dev[0] == 0 the kick is skipped (the closing
+ * half-kick of the first block step). */
+tg_status tg_kick(tg_ctx *ctx, double *vel_dev, const double *acc_dev,
+                  int64_t n, const int32_t *active_idx_dev,
+                  const int32_t *n_active_dev, const uint8_t *level_dev,
+                  double dt, const int64_t *k_dev, int32_t skip_at_k0);
+
+/* drift: x += v dt for all n particles. */
+tg_status tg_drift(tg_ctx *ctx, double *pos_dev, const double *vel_dev,
+                   int64_t n, double dt);
+
+/* Block levels of the listed particles at substep k_dev[0]: the smallest l
+ * in 0..nlev-1 with dt_max 2^-l <= tau_i sqrt(eps_i/|a_i|), decided as
+ * (dt_l^2)^2 |a|^2 <= tau4eps2_dev[i] = (tau_i^2)^2 eps_i^2, else nlev-1;
+ * then raised to the smallest level whose step divides k. */
+tg_status tg_levels(tg_ctx *ctx, const double *acc_dev,
+                    const double *tau4eps2_dev, int64_t n,
+                    const int32_t *active_idx_dev,
+                    const int32_t *n_active_dev, double dt_max, int32_t nlev,
+                    const int64_t *k_dev, uint8_t *level_dev);
+
+/* Indices (ascending) of the particles active at substep k_dev[0] + k_add:
+ * (k mod 2^(nlev-1-level_i)) == 0.  Writes idx_dev[0..m) and n_out_dev[0]=m. */
+tg_status tg_active_set(tg_ctx *ctx, const uint8_t *level_dev, int64_t n,
+                        int32_t nlev, const int64_t *k_dev, int32_t k_add,
+                        int32_t *idx_dev, int32_t *n_out_dev);
+
+/* k_dev[0] += inc (device-side substep counter for replayed graphs). */
+tg_status tg_counter_add(tg_ctx *ctx, int64_t *k_dev, int64_t inc);
+
+/* ---- a13: HIP graphs over any sequence of the calls above ------------- */
+typedef struct tg_graph tg_graph;
+tg_status tg_graph_begin(tg_ctx *ctx);
+tg_status tg_graph_end(tg_ctx *ctx, tg_graph **out);
+tg_status tg_graph_launch(tg_graph *g, void *stream);
+void tg_graph_destroy(tg_graph *g);
+
+/* ---- tree inspection (device pointers valid until the next build) ------ */
+typedef struct {
+  int64_t n, n_nodes, n_groups;
+  int32_t n_sys;
+  const uint64_t *skeys;     /* [n] sorted keys */
+  const uint32_t *perm;      /* [n] sorted rank -> caller index */
+  const uint8_t *level;      /* [n_nodes] */
+  const uint8_t *nchild;     /* [n_nodes] */
+  const uint32_t *first;     /* [n_nodes] first sorted particle */
+  const uint32_t *count;     /* [n_nodes] */
+  const uint32_t *child;     /* [n_nodes] first child id (0 for leaves) */
+  const uint32_t *parent;    /* [n_nodes] (0xffffffff for roots) */
+  const double *cube;        /* [n_sys][4] lo x, y, z, side */
+  const double *com;         /* [n_nodes][4] com x, y, z, side^2 */
+  const double *mom;         /* [n_nodes][8] M, Sxx, Syy, Szz, Sxy, Sxz, Syz, 0 */
+  const uint32_t *groups;    /* [n_groups][4] first, count, node, system */
+} tg_tree_view;
+
+/* Synchronises the stream to read the counts. */
+tg_status tg_get_tree(tg_ctx *ctx, tg_tree_view *out);
+
+/* ---- autotuning (n_L, n_G, resident waves) -----------------------------
+ * Times build + moments + forces on the given particles for every candidate
+ * (leaf sizes x group sizes x waves per CU, 0-terminated lists; NULL = the
+ * built-in lists), keeps the fastest in the context and reports it in
+ * best[3] = {leaf_size, group_size, waves_per_cu} and *best_ms. */
+tg_status tg_autotune(tg_ctx *ctx, const double *pos_dev,
+                      const double *mass_dev, int64_t n,
+                      const int64_t *sys_off_host, int32_t n_sys, double eps,
+                      double theta, const int32_t *leaf_list,
+                      const int32_t *group_list, const int32_t *waves_list,
+                      int32_t repeats, int32_t best[3], double *best_ms);
+
+/* ---- measurement ---------------------------------------------------------
+ * With profiling on, every tg_tree_forces outside graph capture records a
+ * pair of HIP events on the context's stream around its walk kernel (the
+ * group walk with its P2P/P2M sums).  tg_get_profile waits for them and
+ * returns the summed kernel time in ms and the number of walks since
+ * profiling was last switched on. */
+tg_status tg_set_profiling(tg_ctx *ctx, int32_t on);
+tg_status tg_get_profile(tg_ctx *ctx, double *walk_ms, int64_t *n_walks);
+
+/* Wait for the stream; return TG_EDATA / TG_ECAPACITY if the device set an
+ * error bit since the last tg_sync (bits in *bits if non-NULL), then clear. */
+tg_status tg_sync(tg_ctx *ctx, uint32_t *bits);
+
+const char *tg_last_error(void);
+
+/* Library build description (arch, flags), static string. */
+const char *tg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TG_H */

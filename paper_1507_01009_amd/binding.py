@@ -1,0 +1,368 @@
+"""ctypes binding of libtg.so (include/tg.h): argument marshalling only.
+
+Every call forwards device pointers from torch tensors (torch supplies HBM
+and streams; all arithmetic runs in the library's HIP kernels).  There is no
+fallback: if libtg.so is missing or no GPU is visible the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtg.so")
+
+TG_FP64, TG_MIXED = 0, 1
+ERR_NONFINITE, ERR_MASS, ERR_NODES, ERR_FRONTIER, ERR_LISTS = 1, 2, 4, 8, 16
+STATUS = {0: "TG_OK", -1: "TG_EINVAL", -2: "TG_ENOMEM", -3: "TG_EHIP",
+          -4: "TG_ECAPACITY", -5: "TG_ESTATE", -6: "TG_EDATA"}
+
+
+class TGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class tg_config(C.Structure):
+    _fields_ = [("max_particles", C.c_int64), ("max_systems", C.c_int32),
+                ("leaf_size", C.c_int32), ("group_size", C.c_int32),
+                ("precision", C.c_int32), ("max_nodes", C.c_int64),
+                ("frontier_cap", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("G", C.c_double)]
+
+
+class tg_tree_view(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_nodes", C.c_int64), ("n_groups", C.c_int64),
+                ("n_sys", C.c_int32),
+                ("skeys", C.c_void_p), ("perm", C.c_void_p), ("level", C.c_void_p),
+                ("nchild", C.c_void_p), ("first", C.c_void_p), ("count", C.c_void_p),
+                ("child", C.c_void_p), ("parent", C.c_void_p), ("cube", C.c_void_p),
+                ("com", C.c_void_p), ("mom", C.c_void_p), ("groups", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtg.so; raise if it was not built."""
+    global _lib
+    if _lib is None:
+        # torch first: libtg.so then binds to the HIP runtime torch loaded
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libtg.so not built (run __graft_entry__.build() "
+                              "or python paper_1507_01009_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        P, i64, i32, f64, st = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int
+        sigs = {
+            "tg_default_config": (None, [P]),
+            "tg_create": (st, [P, P, P]),
+            "tg_destroy": (None, [P]),
+            "tg_set_stream": (st, [P, P]),
+            "tg_set_sizes": (st, [P, i32, i32]),
+            "tg_build_tree": (st, [P, P, i64, P, i32]),
+            "tg_compute_moments": (st, [P, P]),
+            "tg_tree_forces": (st, [P, f64, f64, P, P, P, P]),
+            "tg_get_counts": (st, [P, P]),
+            "tg_reset_counts": (st, [P]),
+            "tg_walk_lists": (st, [P, f64, P, P, P, i64, P, i64, P, P]),
+            "tg_direct_fp64": (st, [P, P, P, P, i64, P, P, i64, P, P, i32, i32,
+                                    i32, P, P]),
+            "tg_kick": (st, [P, P, P, i64, P, P, P, f64, P, i32]),
+            "tg_drift": (st, [P, P, P, i64, f64]),
+            "tg_levels": (st, [P, P, P, i64, P, P, f64, i32, P, P]),
+            "tg_active_set": (st, [P, P, i64, i32, P, i32, P, P]),
+            "tg_counter_add": (st, [P, P, i64]),
+            "tg_graph_begin": (st, [P]),
+            "tg_graph_end": (st, [P, P]),
+            "tg_graph_launch": (st, [P, P]),
+            "tg_graph_destroy": (None, [P]),
+            "tg_get_tree": (st, [P, P]),
+            "tg_autotune": (st, [P, P, P, i64, P, i32, f64, f64, P, P, P, i32,
+                                 P, P]),
+            "tg_set_profiling": (st, [P, i32]),
+            "tg_get_profile": (st, [P, P, P]),
+            "tg_sync": (st, [P, P]),
+            "tg_last_error": (C.c_char_p, []),
+            "tg_version": (C.c_char_p, []),
+        }
+        for name, (res, args) in sigs.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
+            "tg_set_sizes", "tg_build_tree", "tg_compute_moments",
+            "tg_tree_forces", "tg_get_counts", "tg_reset_counts", "tg_walk_lists",
+            "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels",
+            "tg_active_set", "tg_counter_add", "tg_graph_begin",
+            "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
+            "tg_get_tree", "tg_autotune", "tg_set_profiling",
+            "tg_get_profile", "tg_sync", "tg_last_error",
+            "tg_version")
+
+
+def _check(rc):
+    if rc != 0:
+        raise TGError(rc, lib().tg_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None passes NULL)."""
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _i64_host(a):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(a, dtype=np.int64)
+    return arr, arr.ctypes.data_as(C.c_void_p)
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Graph:
+    def __init__(self, handle):
+        self.h = handle
+
+    def launch(self, stream=None):
+        _check(lib().tg_graph_launch(self.h, _stream_handle(stream)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.tg_graph_destroy(self.h)
+            self.h = None
+
+
+class Context:
+    """One libtg context (tg_create ... tg_destroy) bound to a torch stream."""
+
+    def __init__(self, max_particles, max_systems=1, leaf_size=8, group_size=64,
+                 precision=TG_FP64, max_nodes=0, frontier_cap=0, waves_per_cu=0,
+                 G=1.0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libtg needs a visible MI355X (no CPU fallback)")
+        L = lib()
+        cfg = tg_config()
+        L.tg_default_config(C.byref(cfg))
+        cfg.max_particles = int(max_particles)
+        cfg.max_systems = int(max_systems)
+        cfg.leaf_size = int(leaf_size)
+        cfg.group_size = int(group_size)
+        cfg.precision = int(precision)
+        cfg.max_nodes = int(max_nodes)
+        cfg.frontier_cap = int(frontier_cap)
+        cfg.waves_per_cu = int(waves_per_cu)
+        cfg.G = float(G)
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = C.c_void_p()
+        _check(L.tg_create(C.byref(cfg), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.cfg = cfg
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- configuration
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().tg_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def set_sizes(self, leaf_size, group_size):
+        _check(lib().tg_set_sizes(self.h, int(leaf_size), int(group_size)))
+
+    # -- a1..a7
+    def build_tree(self, pos, sys_off=None):
+        n = pos.shape[0]
+        arr, p = _i64_host(sys_off)
+        S = 1 if arr is None else arr.shape[0] - 1
+        _check(lib().tg_build_tree(self.h, _ptr(pos), n, p, S))
+
+    def compute_moments(self, mass):
+        _check(lib().tg_compute_moments(self.h, _ptr(mass)))
+
+    def tree_forces(self, eps, theta, acc, pot=None, active_idx=None, n_active=None):
+        _check(lib().tg_tree_forces(self.h, float(eps), float(theta),
+                                    _ptr(active_idx), _ptr(n_active), _ptr(acc),
+                                    _ptr(pot)))
+
+    def get_counts(self):
+        out = np.zeros(8, np.int64)
+        _check(lib().tg_get_counts(self.h, out.ctypes.data_as(C.c_void_p)))
+        return {"n_p2p": int(out[0]), "n_p2m": int(out[1]),
+                "n_targets": int(out[2]), "n_groups": int(out[3])}
+
+    def get_cumulative_counts(self):
+        out = np.zeros(8, np.int64)
+        _check(lib().tg_get_counts(self.h, out.ctypes.data_as(C.c_void_p)))
+        return {"n_p2p": int(out[4]), "n_p2m": int(out[5]),
+                "n_targets": int(out[6]), "n_groups": int(out[7])}
+
+    def reset_counts(self):
+        _check(lib().tg_reset_counts(self.h))
+
+    def walk_lists(self, theta, active_idx=None, n_active=None):
+        """(info [ng, 4] int64, ids uint32) as numpy; see tg_walk_lists."""
+        import torch
+        ng = C.c_int64()
+        ni = C.c_int64()
+        rc = lib().tg_walk_lists(self.h, float(theta), _ptr(active_idx), _ptr(n_active),
+                                 None, 0, None, 0, C.byref(ng), C.byref(ni))
+        if rc not in (0, -4):
+            _check(rc)
+        dev = self.stream.device if hasattr(self.stream, "device") else "cuda"
+        info = torch.zeros((max(ng.value, 1), 4), dtype=torch.int64, device=dev)
+        ids = torch.zeros(max(ni.value, 1), dtype=torch.int32, device=dev)
+        _check(lib().tg_walk_lists(self.h, float(theta), _ptr(active_idx), _ptr(n_active),
+                                   _ptr(info), info.shape[0], _ptr(ids), ids.shape[0],
+                                   C.byref(ng), C.byref(ni)))
+        return (info[:ng.value].cpu().numpy(),
+                ids[:ni.value].cpu().numpy().view(np.uint32))
+
+    # -- a11
+    def direct_fp64(self, src_pos, src_mass, src_eps, tgt_pos, tgt_eps, acc, pot=None,
+                    src_seg=None, tgt_seg=None, self_pairs=False, accumulate=False):
+        sa, sp = _i64_host(src_seg)
+        ta, tp = _i64_host(tgt_seg)
+        nseg = 0 if sa is None else sa.shape[0] - 1
+        _check(lib().tg_direct_fp64(self.h, _ptr(src_pos), _ptr(src_mass), _ptr(src_eps),
+                                    src_mass.shape[0], _ptr(tgt_pos), _ptr(tgt_eps),
+                                    tgt_pos.shape[0], sp, tp, nseg, int(bool(self_pairs)),
+                                    int(bool(accumulate)), _ptr(acc), _ptr(pot)))
+
+    # -- a12
+    def kick(self, vel, acc, dt, active_idx=None, n_active=None, level=None, k=None,
+             skip_at_k0=False):
+        _check(lib().tg_kick(self.h, _ptr(vel), _ptr(acc), vel.shape[0], _ptr(active_idx),
+                             _ptr(n_active), _ptr(level), float(dt), _ptr(k),
+                             int(bool(skip_at_k0))))
+
+    def drift(self, pos, vel, dt):
+        _check(lib().tg_drift(self.h, _ptr(pos), _ptr(vel), pos.shape[0], float(dt)))
+
+    def levels(self, acc, tau4eps2, level, dt_max, nlev, k=None, active_idx=None,
+               n_active=None):
+        _check(lib().tg_levels(self.h, _ptr(acc), _ptr(tau4eps2), acc.shape[0],
+                               _ptr(active_idx), _ptr(n_active), float(dt_max), int(nlev),
+                               _ptr(k), _ptr(level)))
+
+    def active_set(self, level, nlev, k, idx, n_out, k_add=0):
+        _check(lib().tg_active_set(self.h, _ptr(level), level.shape[0], int(nlev), _ptr(k),
+                                   int(k_add), _ptr(idx), _ptr(n_out)))
+
+    def counter_add(self, k, inc=1):
+        _check(lib().tg_counter_add(self.h, _ptr(k), int(inc)))
+
+    # -- a13
+    def graph_begin(self):
+        _check(lib().tg_graph_begin(self.h))
+
+    def graph_end(self):
+        g = C.c_void_p()
+        _check(lib().tg_graph_end(self.h, C.byref(g)))
+        return Graph(g)
+
+    # -- inspection
+    def get_tree(self):
+        v = tg_tree_view()
+        _check(lib().tg_get_tree(self.h, C.byref(v)))
+        return v
+
+    def tree_arrays(self):
+        """Copy the current tree to numpy (for parity checks)."""
+        import torch
+        v = self.get_tree()
+        n, nn, ng, S = v.n, v.n_nodes, v.n_groups, v.n_sys
+
+        torch.cuda.synchronize()
+
+        def grab(ptr, count, dtype):
+            out = np.zeros(count, dtype)
+            if count:
+                _memcpy_d2h(out.ctypes.data, ptr, out.nbytes)
+            return out
+
+        return {
+            "skeys": grab(v.skeys, n, np.uint64), "perm": grab(v.perm, n, np.uint32),
+            "level": grab(v.level, nn, np.uint8), "nchild": grab(v.nchild, nn, np.uint8),
+            "first": grab(v.first, nn, np.uint32), "count": grab(v.count, nn, np.uint32),
+            "child": grab(v.child, nn, np.uint32), "parent": grab(v.parent, nn, np.uint32),
+            "cube": grab(v.cube, 4 * S, np.float64).reshape(S, 4),
+            "com": grab(v.com, 4 * nn, np.float64).reshape(nn, 4),
+            "mom": grab(v.mom, 8 * nn, np.float64).reshape(nn, 8),
+            "groups": grab(v.groups, 4 * ng, np.uint32).reshape(ng, 4),
+        }
+
+    def autotune(self, pos, mass, eps, theta, sys_off=None, leaf_list=None,
+                 group_list=None, waves_list=None, repeats=3):
+        def lst(x):
+            if x is None:
+                return None, None
+            a = np.array(list(x) + [0], np.int32)
+            return a, a.ctypes.data_as(C.c_void_p)
+        arr, p = _i64_host(sys_off)
+        S = 1 if arr is None else arr.shape[0] - 1
+        la, lp = lst(leaf_list)
+        ga, gp = lst(group_list)
+        wa, wp = lst(waves_list)
+        best = np.zeros(3, np.int32)
+        ms = C.c_double()
+        _check(lib().tg_autotune(self.h, _ptr(pos), _ptr(mass), pos.shape[0], p, S,
+                                 float(eps), float(theta), lp, gp, wp, int(repeats),
+                                 best.ctypes.data_as(C.c_void_p), C.byref(ms)))
+        return {"leaf_size": int(best[0]), "group_size": int(best[1]),
+                "waves_per_cu": int(best[2]), "ms": ms.value}
+
+    def set_profiling(self, on=True):
+        _check(lib().tg_set_profiling(self.h, int(bool(on))))
+
+    def get_profile(self):
+        """(summed walk-kernel ms, number of walks) since profiling was set."""
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().tg_get_profile(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def sync(self):
+        bits = C.c_uint32()
+        rc = lib().tg_sync(self.h, C.byref(bits))
+        if rc != 0:
+            raise TGError(rc, lib().tg_last_error().decode() + " (bits 0x%x)" % bits.value)
+        return bits.value
+
+
+_hip = None
+
+
+def _memcpy_d2h(dst, src, nbytes):
+    """Blocking device-to-host copy through the HIP runtime torch loaded."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so.7")
+        _hip.hipMemcpy.restype = C.c_int
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), C.c_size_t(nbytes), 2)
+    if rc != 0:
+        raise RuntimeError("hipMemcpy failed: %d" % rc)

@@ -1,0 +1,140 @@
+// a11: double-precision direct forces between a source set and a target set
+// (SMBH <-> stars; perturber <-> chain-member corrections), Plummer
+// softening max(eps_i, eps_j) per pair.
+//
+// Work is the grid of (target, source chunk) pairs, chunk-major so that
+// consecutive threads own consecutive targets.  With many targets (stars
+// feeling the SMBHs) each thread takes every source of its segment; with
+// few targets (SMBHs feeling a million stars) the sources are cut into
+// chunks whose partial sums are combined in a second, ordered pass.  Every
+// sum is compensated (error-free TwoSum with a running correction), so the
+// result does not depend on the chunking beyond the last bit and is
+// deterministic.
+#include "tg_internal.h"
+
+namespace tg {
+
+struct CSum {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double x) {
+    double t = s + x;
+    double bp = t - s;
+    c += (s - (t - bp)) + (x - bp);
+    s = t;
+  }
+  __device__ __forceinline__ double get() const { return s + c; }
+};
+
+__device__ __forceinline__ int seg_of(const int64_t *off, int nseg, int64_t i) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_direct(const double *__restrict__ spos, const double *__restrict__ sm,
+                         const double *__restrict__ seps, const double *__restrict__ tpos,
+                         const double *__restrict__ teps, int64_t nt,
+                         const int64_t *__restrict__ sseg, const int64_t *__restrict__ tseg,
+                         int nseg, int64_t chunk, int nchunks, int self_pairs,
+                         int accumulate, double *__restrict__ acc,
+                         double *__restrict__ pot, double *__restrict__ part) {
+  const int64_t total = nt * (int64_t)nchunks;
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < total;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = w % nt;
+    const int c = (int)(w / nt);
+    const int s = seg_of(tseg, nseg, i);
+    const int64_t j0 = sseg[s] + (int64_t)c * chunk;
+    const int64_t j1 = min(sseg[s + 1], j0 + chunk);
+    const double xi = tpos[3 * i], yi = tpos[3 * i + 1], zi = tpos[3 * i + 2];
+    const double ei = teps[i];
+    CSum ax, ay, az, ph;
+    for (int64_t j = j0; j < j1; ++j) {
+      if (self_pairs && j == i) continue;
+      const double ep = fmax(seps[j], ei);
+      const double dx = xi - spos[3 * j], dy = yi - spos[3 * j + 1], dz = zi - spos[3 * j + 2];
+      const double r2 = dx * dx + dy * dy + dz * dz + ep * ep;
+      const double D1 = 1.0 / sqrt(r2);
+      const double mD1 = sm[j] * D1;
+      const double mD3 = mD1 * D1 * D1;
+      ax.add(-mD3 * dx);
+      ay.add(-mD3 * dy);
+      az.add(-mD3 * dz);
+      ph.add(-mD1);
+    }
+    if (nchunks == 1) {
+      double a0 = ax.get(), a1 = ay.get(), a2 = az.get(), p = ph.get();
+      if (accumulate) {
+        acc[3 * i] += a0; acc[3 * i + 1] += a1; acc[3 * i + 2] += a2;
+        if (pot) pot[i] += p;
+      } else {
+        acc[3 * i] = a0; acc[3 * i + 1] = a1; acc[3 * i + 2] = a2;
+        if (pot) pot[i] = p;
+      }
+    } else {
+      double *o = part + 8 * (size_t)w;
+      o[0] = ax.s; o[1] = ax.c; o[2] = ay.s; o[3] = ay.c;
+      o[4] = az.s; o[5] = az.c; o[6] = ph.s; o[7] = ph.c;
+    }
+  }
+}
+
+__global__ void k_direct_reduce(int64_t nt, int nchunks, int accumulate,
+                                const double *__restrict__ part,
+                                double *__restrict__ acc, double *__restrict__ pot) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    CSum r[4];
+    for (int c = 0; c < nchunks; ++c) {
+      const double *o = part + 8 * (size_t)(c * nt + i);
+      for (int k = 0; k < 4; ++k) {
+        r[k].add(o[2 * k]);
+        r[k].add(o[2 * k + 1]);
+      }
+    }
+    if (accumulate) {
+      acc[3 * i] += r[0].get(); acc[3 * i + 1] += r[1].get(); acc[3 * i + 2] += r[2].get();
+      if (pot) pot[i] += r[3].get();
+    } else {
+      acc[3 * i] = r[0].get(); acc[3 * i + 1] = r[1].get(); acc[3 * i + 2] = r[2].get();
+      if (pot) pot[i] = r[3].get();
+    }
+  }
+}
+
+hipError_t launch_direct(tg_ctx *c, const double *spos, const double *sm,
+                         const double *seps, int64_t ns, const double *tpos,
+                         const double *teps, int64_t nt, int nseg,
+                         int64_t max_seg_src, int self_pairs, int accumulate,
+                         double *acc, double *pot) {
+  (void)ns;
+  if (nt == 0) return hipSuccess;
+  // aim for >= 2^16 independent (target, chunk) sums
+  int64_t nchunks = 1, chunk = std::max<int64_t>(max_seg_src, 1);
+  if (nt < 65536 && max_seg_src > 256) {
+    int64_t want = (65536 + nt - 1) / nt;
+    chunk = std::max<int64_t>(256, (max_seg_src + want - 1) / want);
+    nchunks = (max_seg_src + chunk - 1) / chunk;
+    while (nchunks * nt * 8 > c->b.dpart_cap) {
+      chunk *= 2;
+      nchunks = (max_seg_src + chunk - 1) / chunk;
+    }
+  }
+  const int64_t total = nt * nchunks;
+  const int g = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_direct, dim3(g), dim3(256), 0, c->stream, spos, sm, seps,
+                     tpos, teps, nt, c->b.dseg, c->b.dseg + (nseg + 1), nseg,
+                     chunk, (int)nchunks, self_pairs, accumulate, acc, pot,
+                     c->b.dpart);
+  if (nchunks > 1) {
+    const int g2 = (int)std::min<int64_t>((nt + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_direct_reduce, dim3(g2), dim3(256), 0, c->stream, nt,
+                       (int)nchunks, accumulate, c->b.dpart, acc, pot);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tg

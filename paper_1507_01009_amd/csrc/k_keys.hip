@@ -1,0 +1,295 @@
+// a1-a4: bounding cube per system, 21-bit Morton keys, stable LSD radix sort
+// of (key, index), and the gather of positions into sorted order.
+//
+// Work is cut into tiles of kSortTile consecutive particles that never cross
+// a system boundary, so one launch handles every system of a batch and the
+// histogram layout [system][digit][tile-of-system] makes the sort segmented
+// for free: the exclusive scan of the whole histogram already places each
+// system after the previous one.
+//
+// Bit-exactness: the quantisation is t = x - lo, u = t * (2^21 / L), floor,
+// clamp, with no contraction possible (one subtract, one multiply), and the
+// division 2^21 / L is IEEE-rounded; keys and the stable permutation are
+// therefore identical to any correct implementation of the same definition.
+#include "tg_internal.h"
+
+namespace tg {
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Per-tile min/max of each coordinate; flags non-finite positions.
+__global__ __launch_bounds__(256) void k_cube_part(const double *__restrict__ pos,
+                                                   const Tile *__restrict__ tiles,
+                                                   double *__restrict__ part,
+                                                   uint32_t *err) {
+  __shared__ double sh[4][6];
+  const Tile t = tiles[blockIdx.x];
+  double lo[3] = {INFINITY, INFINITY, INFINITY};
+  double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double x = pos[3 * (size_t)i + k];
+      bad |= !isfinite(x);
+      lo[k] = fmin(lo[k], x);
+      hi[k] = fmax(hi[k], x);
+    }
+  }
+  if (bad) set_err(err, TG_ERR_NONFINITE);
+  const unsigned lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = wave_min(lo[k]);
+    hi[k] = wave_max(hi[k]);
+  }
+  if (lane == 0)
+    for (int k = 0; k < 3; ++k) { sh[w][k] = lo[k]; sh[w][3 + k] = hi[k]; }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double v = sh[0][threadIdx.x];
+    for (int i = 1; i < 4; ++i)
+      v = threadIdx.x < 3 ? fmin(v, sh[i][threadIdx.x]) : fmax(v, sh[i][threadIdx.x]);
+    part[6 * (size_t)blockIdx.x + threadIdx.x] = v;
+  }
+}
+
+// One thread per system: lo = coordinate minimum, L = largest extent (1 if
+// every particle coincides or the system is empty).
+__global__ void k_cube_final(const double *__restrict__ part,
+                             const uint32_t *__restrict__ sys_tile0, int S,
+                             double *__restrict__ cube) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  uint32_t a = sys_tile0[s], b = sys_tile0[s + 1];
+  double lo[3] = {0.0, 0.0, 0.0}, L = 1.0;
+  if (b > a) {
+    double hi[3];
+    for (int k = 0; k < 3; ++k) { lo[k] = part[6 * (size_t)a + k]; hi[k] = part[6 * (size_t)a + 3 + k]; }
+    for (uint32_t t = a + 1; t < b; ++t)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = fmin(lo[k], part[6 * (size_t)t + k]);
+        hi[k] = fmax(hi[k], part[6 * (size_t)t + 3 + k]);
+      }
+    L = 0.0;
+    for (int k = 0; k < 3; ++k) L = fmax(L, hi[k] - lo[k]);
+    if (L == 0.0) L = 1.0;
+  }
+  cube[4 * s + 0] = lo[0]; cube[4 * s + 1] = lo[1]; cube[4 * s + 2] = lo[2];
+  cube[4 * s + 3] = L;
+}
+
+// Spread the low 21 bits of v so that bit j lands on bit 3j.
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1FFFFFull;
+  v = (v | (v << 32)) & 0x1F00000000FFFFull;
+  v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+  v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+  v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+__device__ __forceinline__ uint64_t quantise(double x, double lo, double sigma) {
+  double t = __dsub_rn(x, lo);
+  double u = __dmul_rn(t, sigma);
+  double f = floor(u);
+  uint64_t q = f <= 0.0 ? 0ull : (uint64_t)f;
+  return q > 0x1FFFFFull ? 0x1FFFFFull : q;
+}
+
+// Keys (x bit above y above z at every level) and the identity values.
+__global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos,
+                                              const Tile *__restrict__ tiles,
+                                              const uint32_t *__restrict__ sys_tile0,
+                                              int S, const double *__restrict__ cube,
+                                              uint64_t *__restrict__ key,
+                                              uint32_t *__restrict__ val) {
+  const Tile t = tiles[blockIdx.x];
+  // system of this tile: last s with sys_tile0[s] <= tile
+  int lo_s = 0, hi_s = S - 1;
+  while (lo_s < hi_s) {
+    int mid = (lo_s + hi_s + 1) >> 1;
+    if (sys_tile0[mid] <= blockIdx.x) lo_s = mid; else hi_s = mid - 1;
+  }
+  const double *c = cube + 4 * lo_s;
+  const double sigma = 2097152.0 / c[3];
+  for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u) {
+    uint64_t qx = quantise(pos[3 * (size_t)i + 0], c[0], sigma);
+    uint64_t qy = quantise(pos[3 * (size_t)i + 1], c[1], sigma);
+    uint64_t qz = quantise(pos[3 * (size_t)i + 2], c[2], sigma);
+    key[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    val[i] = i;
+  }
+}
+
+// ---- radix sort, 8-bit digits ----------------------------------------
+__global__ __launch_bounds__(256) void k_sort_hist(const uint64_t *__restrict__ key,
+                                                   const Tile *__restrict__ tiles,
+                                                   int shift,
+                                                   uint32_t *__restrict__ hist) {
+  __shared__ uint32_t cnt[256];
+  const Tile t = tiles[blockIdx.x];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u)
+    atomicAdd(&cnt[(uint32_t)(key[i] >> shift) & 255u], 1u);
+  __syncthreads();
+  hist[t.hist0 + threadIdx.x * t.hstride] = cnt[threadIdx.x];
+}
+
+// Stable scatter of one tile: ranks are computed round by round (256 keys
+// per round, in index order) from wave match masks built with ballots, keys
+// are staged in LDS in tile-sorted order, then written out so that runs of
+// one digit become contiguous stores.
+__global__ __launch_bounds__(256) void k_sort_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+    const Tile *__restrict__ tiles, int shift,
+    const uint32_t *__restrict__ hist) {
+  __shared__ uint64_t sk[kSortTile];
+  __shared__ uint32_t sv[kSortTile];
+  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t loc_off[256];
+  __shared__ uint32_t glob_off[256];
+  __shared__ uint32_t scan_sh[4];
+  const Tile t = tiles[blockIdx.x];
+  const uint32_t cnt = t.end - t.start;
+  const unsigned tid = threadIdx.x, w = tid >> 6;
+  running[tid] = 0;
+  glob_off[tid] = hist[t.hist0 + tid * t.hstride];
+
+  uint64_t k[kSortItems];
+  uint32_t v[kSortItems], rk[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    uint32_t idx = r * 256u + tid;
+    if (idx < cnt) {
+      k[r] = kin[t.start + idx];
+      v[r] = vin[t.start + idx];
+    } else {
+      k[r] = 0;
+      v[r] = 0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t idx = r * 256u + tid;
+    const bool valid = idx < cnt;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+    wcnt[0][tid] = 0; wcnt[1][tid] = 0; wcnt[2][tid] = 0; wcnt[3][tid] = 0;
+    __syncthreads();
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      unsigned long long bb = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t lr = lanes_below(peers);
+    if (valid && lr == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = running[d];
+      for (unsigned q = 0; q < w; ++q) pre += wcnt[q][d];
+      rk[r] = pre + lr;
+    }
+    __syncthreads();
+    running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+    __syncthreads();
+  }
+  uint32_t tot;
+  loc_off[tid] = block_exclusive_scan(running[tid], scan_sh, tot);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    uint32_t idx = r * 256u + tid;
+    if (idx < cnt) {
+      uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+      uint32_t p = loc_off[d] + rk[r];
+      sk[p] = k[r];
+      sv[p] = v[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    uint32_t idx = r * 256u + tid;
+    if (idx < cnt) {
+      uint64_t kk = sk[idx];
+      uint32_t d = (uint32_t)(kk >> shift) & 255u;
+      uint32_t dst = glob_off[d] + (idx - loc_off[d]);
+      kout[dst] = kk;
+      vout[dst] = sv[idx];
+    }
+  }
+}
+
+// Sorted positions {x, y, z, 0} (mass filled by the moments pass) and the
+// inverse permutation.
+__global__ void k_gather(const double *__restrict__ pos,
+                         const uint32_t *__restrict__ perm, int64_t n,
+                         double4 *__restrict__ spart,
+                         uint32_t *__restrict__ rank) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t o = perm[r];
+    spart[r] = make_double4(pos[3 * (size_t)o], pos[3 * (size_t)o + 1],
+                            pos[3 * (size_t)o + 2], 0.0);
+    rank[o] = (uint32_t)r;
+  }
+}
+
+hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
+  Buffers &b = c->b;
+  const int nt = (int)c->n_tiles;
+  if (nt > 0)
+    hipLaunchKernelGGL(k_cube_part, dim3(nt), dim3(256), 0, c->stream, pos,
+                       b.tiles, b.cube_part, b.err);
+  hipLaunchKernelGGL(k_cube_final, dim3((c->S + 63) / 64), dim3(64), 0,
+                     c->stream, b.cube_part, b.sys_tile0, c->S, b.cube);
+  if (nt > 0)
+    hipLaunchKernelGGL(k_keys, dim3(nt), dim3(256), 0, c->stream, pos, b.tiles,
+                       b.sys_tile0, c->S, b.cube, b.key[0], b.val[0]);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(tg_ctx *c) {
+  Buffers &b = c->b;
+  const int nt = (int)c->n_tiles;
+  if (nt == 0) return hipSuccess;
+  const uint32_t nh = 256u * (uint32_t)nt;
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 8 * pass;
+    const int src = pass & 1, dst = src ^ 1;
+    hipLaunchKernelGGL(k_sort_hist, dim3(nt), dim3(256), 0, c->stream,
+                       b.key[src], b.tiles, shift, b.hist);
+    hipError_t e = scan_u32(b.hist, b.hist, nh, nullptr, nullptr, b.scan_part,
+                            c->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nt), dim3(256), 0, c->stream,
+                       b.key[src], b.val[src], b.key[dst], b.val[dst], b.tiles,
+                       shift, b.hist);
+  }
+  return hipGetLastError();   // 8 passes: result back in key[0] / val[0]
+}
+
+hipError_t launch_gather(tg_ctx *c, const double *pos) {
+  if (c->n == 0) return hipSuccess;
+  int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, pos,
+                     c->b.val[0], c->n, c->b.spart, c->b.rank);
+  return hipGetLastError();
+}
+
+}  // namespace tg

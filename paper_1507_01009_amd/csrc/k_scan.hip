@@ -1,0 +1,108 @@
+// Device-wide exclusive scan of u32 (reduce-then-scan over a fixed grid, so
+// the element count may live in device memory and the launch shape never
+// depends on it), and fill kernels used instead of memset so that every
+// sequence of calls can be captured into a HIP graph.
+#include "tg_internal.h"
+
+namespace tg {
+
+__device__ __forceinline__ void chunk_of(uint32_t n, uint32_t &a, uint32_t &b) {
+  uint32_t chunk = ((n + gridDim.x - 1) / gridDim.x + 255u) & ~255u;
+  a = min(n, blockIdx.x * chunk);
+  b = min(n, a + chunk);
+}
+
+__global__ __launch_bounds__(256) void k_scan_part(const uint32_t *in,
+                                                   uint32_t n_host,
+                                                   const uint32_t *n_dev,
+                                                   uint32_t *part) {
+  __shared__ uint32_t sh[4];
+  uint32_t n = n_dev ? *n_dev : n_host;
+  uint32_t a, b;
+  chunk_of(n, a, b);
+  uint32_t s = 0;
+  for (uint32_t i = a + threadIdx.x; i < b; i += 256u) s += in[i];
+  uint32_t tot;
+  block_exclusive_scan(s, sh, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t *part, int nb,
+                                                  uint32_t *total) {
+  __shared__ uint32_t sh[4];
+  uint32_t v = (int)threadIdx.x < nb ? part[threadIdx.x] : 0u;
+  uint32_t tot;
+  uint32_t e = block_exclusive_scan(v, sh, tot);
+  if ((int)threadIdx.x < nb) part[threadIdx.x] = e;
+  if (threadIdx.x == 0) {
+    part[nb] = tot;
+    if (total) *total = tot;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_final(const uint32_t *in,
+                                                    uint32_t *out,
+                                                    uint32_t n_host,
+                                                    const uint32_t *n_dev,
+                                                    const uint32_t *part) {
+  __shared__ uint32_t sh[4];
+  uint32_t n = n_dev ? *n_dev : n_host;
+  uint32_t a, b;
+  chunk_of(n, a, b);
+  uint32_t base = part[blockIdx.x];
+  for (uint32_t t0 = a; t0 < b; t0 += 256u) {
+    uint32_t i = t0 + threadIdx.x;
+    uint32_t v = i < b ? in[i] : 0u;
+    uint32_t tot;
+    uint32_t e = block_exclusive_scan(v, sh, tot);
+    if (i < b) out[i] = base + e;
+    base += tot;
+  }
+}
+
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, uint32_t n_host,
+                    const uint32_t *n_dev, uint32_t *total_dev, uint32_t *part,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_part, dim3(kScanBlocks), dim3(256), 0, s, in,
+                     n_host, n_dev, part);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, part, kScanBlocks,
+                     total_dev);
+  hipLaunchKernelGGL(k_scan_final, dim3(kScanBlocks), dim3(256), 0, s, in,
+                     out, n_host, n_dev, part);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static inline int grid_for(int64_t n, int threads) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > 4096) g = 4096;
+  return (int)g;
+}
+
+hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v,
+                     n);
+  return hipGetLastError();
+}
+
+}  // namespace tg

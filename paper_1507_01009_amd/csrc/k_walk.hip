@@ -1,0 +1,726 @@
+// a6, a8-a10: active groups, the group tree walk with the opening-angle
+// test, and the softened P2P / quadrupole P2M force sums.
+//
+// One 64-lane wavefront owns one group of targets at a time (persistent
+// grid, groups taken from an atomic queue).  The walk is breadth first: the
+// wave tests 64 frontier cells at once against the group's box,
+//   accept iff side^2 < theta^2 d^2,  d = box-to-centre-of-mass distance,
+// evaluated in double precision with no contraction (bit-identical decisions
+// to the plain definition).  Ballot + mbcnt compaction appends accepted
+// cells to an LDS P2M list and the particles of refused leaves to an LDS
+// P2P queue; refused internal cells push their children onto the next
+// frontier (wave prefix sum of child counts).  Whenever a list holds 64
+// sources it is flushed: the 64 sources are staged in LDS once and every
+// lane, owning one target (or one target x source slice when the group has
+// fewer than 33 targets), sums their forces on the vector ALUs.  No MFMA:
+// nothing here is a dense contraction.
+//
+// Precision modes.  FP64: all sums in double, rsqrt from the hardware
+// estimate plus one third-order correction (Householder).  MIXED: the walk
+// decisions stay double; targets and sources are taken relative to the
+// group's box centre c_g in double and rounded to float, the interaction
+// arithmetic is float with the hardware rsqrt, each 64-source tile is summed
+// in float and folded into a (hi, lo) float pair with an error-free
+// TwoSum; the result is hi + lo in double.
+//
+// Flops per interaction (FMA = 2; the rsqrt is counted apart):
+//   P2P 19: 3 sub, 6 for r^2 + eps^2, 3 for m D1, m D3, 6 for the three
+//          accelerations, 1 for the potential.
+//   P2M 61: 3 sub, 6 for r^2 + eps^2, 4 for D2..D7, 15 for S x, 5 for x.Sx,
+//          3 for W, 7 for the radial coefficient, 1 for 3 D5, 12 for the
+//          accelerations, 5 for the potential.
+#include "tg_internal.h"
+
+namespace tg {
+
+constexpr int kQCap = 64 + 64 * kMaxLeaf;   // P2P particle queue (LDS)
+constexpr int kMCap = 128;                  // P2M cell list (LDS)
+
+struct WalkArgs {
+  const uint8_t *nchild;
+  const uint32_t *first, *count, *child;
+  const double4 *com;
+  const double *mom;
+  const double4 *spart;
+  const uint32_t *root_of;
+  const uint4 *groups;
+  const uint32_t *alist;
+  const double *abox;
+  const uint8_t *sact;
+  const uint32_t *perm;
+  TreeCounters *ctr;
+  uint32_t *err;
+  uint32_t *frontier;
+  int fcap;
+  double th2, eps2, G;
+  double *acc, *pot;
+  // list mode
+  uint32_t *wl_count;
+  const uint32_t *wl_off;
+  uint32_t *ids;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t &tot) {
+  const unsigned lane = lane_id();
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= (unsigned)o) x += y;
+  }
+  tot = __shfl(x, 63, 64);
+  return x - v;
+}
+
+// Opening-angle test, the same operations in the same order as the plain
+// definition: d^2 = sum_k max(max(lo_k - c_k, c_k - hi_k), 0)^2, accept iff
+// side^2 < theta^2 * d^2.
+__device__ __forceinline__ bool mac_accept(const double lo[3], const double hi[3],
+                                           double4 c, double th2) {
+#pragma clang fp contract(off)
+  double d2 = 0.0;
+  {
+    double a = __dsub_rn(lo[0], c.x), b = __dsub_rn(c.x, hi[0]);
+    double m = a > b ? a : b;
+    if (m < 0.0) m = 0.0;
+    d2 = __dadd_rn(d2, __dmul_rn(m, m));
+  }
+  {
+    double a = __dsub_rn(lo[1], c.y), b = __dsub_rn(c.y, hi[1]);
+    double m = a > b ? a : b;
+    if (m < 0.0) m = 0.0;
+    d2 = __dadd_rn(d2, __dmul_rn(m, m));
+  }
+  {
+    double a = __dsub_rn(lo[2], c.z), b = __dsub_rn(c.z, hi[2]);
+    double m = a > b ? a : b;
+    if (m < 0.0) m = 0.0;
+    d2 = __dadd_rn(d2, __dmul_rn(m, m));
+  }
+  return c.w < __dmul_rn(th2, d2);
+}
+
+// 1/sqrt(x) in double: hardware estimate, then one third-order Householder
+// step y <- y (1 + e/2 + 3e^2/8), e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt_dp(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double t = x * y;
+  double e = fma(-t, y, 1.0);
+  double p = fma(0.375, e, 0.5);
+  return fma(y * e, p, y);
+}
+
+__device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float x) {
+  float t = hi + x;
+  float bp = t - hi;
+  float err = (hi - (t - bp)) + (x - bp);
+  hi = t;
+  lo += err;
+}
+
+// ---------------------------------------------------------------- tiles
+struct P2MTileD { double4 a, b, c; };   // {cx,cy,cz,M} {Sxx,Syy,Szz,T} {Sxy,Sxz,Syz,0}
+struct P2MTileF { float4 a, b, c; };
+
+union __align__(16) TileMem {
+  P2MTileD md[64];
+  double4 pd[64];
+  P2MTileF mf[64];
+  float4 pf[64];
+};
+
+template <bool kMixed>
+struct Target {
+  // double path
+  double x, y, z;
+  double ax, ay, az, ph;
+  // mixed path
+  float fx, fy, fz;
+  float tax, tay, taz, tph;    // current tile partial sums
+  float hax, hay, haz, hph;    // compensated totals (hi)
+  float lax, lay, laz, lph;    // (lo)
+};
+
+// ------------------------------------------------------- force-mode sink
+template <bool kMixed>
+struct ForceSink {
+  uint32_t *s_m;
+  uint32_t *s_q;
+  TileMem *tile;
+  uint32_t nm, nq;
+  unsigned long long cells, parts;   // wave-uniform totals
+  int my_s, slices;
+  double cgx, cgy, cgz;
+  double eps2;
+  float eps2f;
+  Target<kMixed> t;
+
+  __device__ void fold() {
+    if constexpr (kMixed) {
+      two_sum_acc(t.hax, t.lax, t.tax);
+      two_sum_acc(t.hay, t.lay, t.tay);
+      two_sum_acc(t.haz, t.laz, t.taz);
+      two_sum_acc(t.hph, t.lph, t.tph);
+      t.tax = t.tay = t.taz = t.tph = 0.0f;
+    }
+  }
+
+  __device__ void flush_p2m(const WalkArgs &A, const uint32_t *list, int k) {
+    const unsigned lane = lane_id();
+    if ((int)lane < k) {
+      const uint32_t v = list[lane];
+      const double4 c = A.com[v];
+      const double *o = A.mom + 8 * (size_t)v;
+      const double T = o[1] + o[2] + o[3];
+      if constexpr (kMixed) {
+        tile->mf[lane].a = make_float4((float)(c.x - cgx), (float)(c.y - cgy),
+                                       (float)(c.z - cgz), (float)o[0]);
+        tile->mf[lane].b = make_float4((float)o[1], (float)o[2], (float)o[3], (float)T);
+        tile->mf[lane].c = make_float4((float)o[4], (float)o[5], (float)o[6], 0.0f);
+      } else {
+        tile->md[lane].a = make_double4(c.x, c.y, c.z, o[0]);
+        tile->md[lane].b = make_double4(o[1], o[2], o[3], T);
+        tile->md[lane].c = make_double4(o[4], o[5], o[6], 0.0);
+      }
+    }
+    __syncthreads();
+    if constexpr (kMixed) {
+      float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+#pragma unroll 2
+      for (int j = my_s; j < k; j += slices) {
+        const P2MTileF s = tile->mf[j];
+        const float x = t.fx - s.a.x, y = t.fy - s.a.y, z = t.fz - s.a.z;
+        const float r2 = x * x + y * y + z * z + eps2f;
+        const float D1 = __builtin_amdgcn_rsqf(r2);
+        const float D2 = D1 * D1, D3 = D1 * D2, D5 = D3 * D2, D7 = D5 * D2;
+        const float Sx = s.b.x * x + s.c.x * y + s.c.y * z;
+        const float Sy = s.c.x * x + s.b.y * y + s.c.z * z;
+        const float Sz = s.c.y * x + s.c.z * y + s.b.z * z;
+        const float xSx = x * Sx + y * Sy + z * Sz;
+        const float W = 3.0f * xSx - s.b.w * r2;
+        const float A = -s.a.w * D3 - s.b.w * D5 - 2.5f * D7 * W;
+        const float B = 3.0f * D5;
+        ax += A * x + B * Sx;
+        ay += A * y + B * Sy;
+        az += A * z + B * Sz;
+        ph += -s.a.w * D1 - 0.5f * D5 * W;
+      }
+      t.tax += ax; t.tay += ay; t.taz += az; t.tph += ph;
+      fold();
+    } else {
+      double ax = 0., ay = 0., az = 0., ph = 0.;
+#pragma unroll 2
+      for (int j = my_s; j < k; j += slices) {
+        const P2MTileD s = tile->md[j];
+        const double x = t.x - s.a.x, y = t.y - s.a.y, z = t.z - s.a.z;
+        const double r2 = x * x + y * y + z * z + eps2;
+        const double D1 = rsqrt_dp(r2);
+        const double D2 = D1 * D1, D3 = D1 * D2, D5 = D3 * D2, D7 = D5 * D2;
+        const double Sx = s.b.x * x + s.c.x * y + s.c.y * z;
+        const double Sy = s.c.x * x + s.b.y * y + s.c.z * z;
+        const double Sz = s.c.y * x + s.c.z * y + s.b.z * z;
+        const double xSx = x * Sx + y * Sy + z * Sz;
+        const double W = 3.0 * xSx - s.b.w * r2;
+        const double A = -s.a.w * D3 - s.b.w * D5 - 2.5 * D7 * W;
+        const double B = 3.0 * D5;
+        ax += A * x + B * Sx;
+        ay += A * y + B * Sy;
+        az += A * z + B * Sz;
+        ph += -s.a.w * D1 - 0.5 * D5 * W;
+      }
+      t.ax += ax; t.ay += ay; t.az += az; t.ph += ph;
+    }
+    __syncthreads();
+  }
+
+  __device__ void flush_p2p(const WalkArgs &A, const uint32_t *list, int k) {
+    const unsigned lane = lane_id();
+    if ((int)lane < k) {
+      const double4 p = A.spart[list[lane]];
+      if constexpr (kMixed)
+        tile->pf[lane] = make_float4((float)(p.x - cgx), (float)(p.y - cgy),
+                                     (float)(p.z - cgz), (float)p.w);
+      else
+        tile->pd[lane] = p;
+    }
+    __syncthreads();
+    if constexpr (kMixed) {
+      float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+#pragma unroll 4
+      for (int j = my_s; j < k; j += slices) {
+        const float4 s = tile->pf[j];
+        const float dx = t.fx - s.x, dy = t.fy - s.y, dz = t.fz - s.z;
+        const float r2 = dx * dx + dy * dy + dz * dz + eps2f;
+        const float D1 = __builtin_amdgcn_rsqf(r2);
+        const float mD1 = s.w * D1;
+        const float mD3 = mD1 * D1 * D1;
+        ax -= mD3 * dx; ay -= mD3 * dy; az -= mD3 * dz;
+        ph -= mD1;
+      }
+      t.tax += ax; t.tay += ay; t.taz += az; t.tph += ph;
+      fold();
+    } else {
+      double ax = 0., ay = 0., az = 0., ph = 0.;
+#pragma unroll 4
+      for (int j = my_s; j < k; j += slices) {
+        const double4 s = tile->pd[j];
+        const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
+        const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+        const double D1 = rsqrt_dp(r2);
+        const double mD1 = s.w * D1;
+        const double mD3 = mD1 * D1 * D1;
+        ax -= mD3 * dx; ay -= mD3 * dy; az -= mD3 * dz;
+        ph -= mD1;
+      }
+      t.ax += ax; t.ay += ay; t.az += az; t.ph += ph;
+    }
+    __syncthreads();
+  }
+
+  __device__ void p2m(const WalkArgs &A, bool pred, uint32_t node) {
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    if (pred) s_m[nm + lanes_below(mask)] = node;
+    const uint32_t c = (uint32_t)__popcll(mask);
+    nm += c;
+    cells += c;
+    __syncthreads();
+    if (nm >= 64) {
+      flush_p2m(A, s_m + (nm - 64), 64);
+      nm -= 64;
+    }
+  }
+
+  __device__ void drain_q(const WalkArgs &A) {
+    while (nq >= 64) {
+      flush_p2p(A, s_q + (nq - 64), 64);
+      nq -= 64;
+    }
+  }
+
+  __device__ void p2p(const WalkArgs &A, bool pred, uint32_t node, uint32_t f,
+                      uint32_t cnt) {
+    (void)node;
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    const uint32_t c = pred ? cnt : 0u;
+    uint32_t tot;
+    const uint32_t pre = wave_excl_scan(c, tot);
+    parts += tot;
+    if (nq + tot <= (uint32_t)kQCap) {
+      for (uint32_t k = 0; k < c; ++k) s_q[nq + pre + k] = f + k;
+      nq += tot;
+      __syncthreads();
+      drain_q(A);
+      return;
+    }
+    // rare: leaves larger than n_L (level-21 leaves); one leaf at a time
+    unsigned long long m = mask;
+    while (m) {
+      const int L = __ffsll((long long)m) - 1;
+      m &= m - 1ull;
+      const uint32_t lf = __shfl(f, L, 64), lc = __shfl(c, L, 64);
+      uint32_t o = 0;
+      while (o < lc) {
+        const uint32_t take = min(lc - o, (uint32_t)kQCap - nq);
+        for (uint32_t j = lane_id(); j < take; j += 64u) s_q[nq + j] = lf + o + j;
+        nq += take;
+        o += take;
+        __syncthreads();
+        drain_q(A);
+      }
+    }
+  }
+
+  __device__ void finish(const WalkArgs &A) {
+    if (nm > 0) flush_p2m(A, s_m, (int)nm);
+    if (nq > 0) flush_p2p(A, s_q, (int)nq);
+    nm = nq = 0;
+  }
+};
+
+// -------------------------------------------------------- list-mode sinks
+struct CountSink {
+  uint32_t nm = 0, np = 0;
+  __device__ void p2m(const WalkArgs &, bool pred, uint32_t) {
+    nm += (uint32_t)__popcll(__ballot(pred));
+  }
+  __device__ void p2p(const WalkArgs &, bool pred, uint32_t, uint32_t, uint32_t) {
+    np += (uint32_t)__popcll(__ballot(pred));
+  }
+  __device__ void finish(const WalkArgs &) {}
+};
+
+struct FillSink {
+  uint32_t nm = 0, np = 0;
+  uint32_t base_m = 0, base_p = 0;
+  __device__ void p2m(const WalkArgs &A, bool pred, uint32_t node) {
+    const unsigned long long mask = __ballot(pred);
+    if (pred) A.ids[base_m + nm + lanes_below(mask)] = node;
+    nm += (uint32_t)__popcll(mask);
+  }
+  __device__ void p2p(const WalkArgs &A, bool pred, uint32_t node, uint32_t, uint32_t) {
+    const unsigned long long mask = __ballot(pred);
+    if (pred) A.ids[base_p + np + lanes_below(mask)] = node;
+    np += (uint32_t)__popcll(mask);
+  }
+  __device__ void finish(const WalkArgs &) {}
+};
+
+// ---------------------------------------------------------- traversal
+// Breadth-first walk of the group's system tree.  Returns false if the
+// frontier overflowed (the group's results are then invalid).
+template <class Sink>
+__device__ bool traverse(const WalkArgs &A, Sink &sink, uint32_t root,
+                         const double lo[3], const double hi[3]) {
+  const unsigned lane = lane_id();
+  uint32_t *cur = A.frontier + (size_t)blockIdx.x * 2 * A.fcap;
+  uint32_t *nxt = cur + A.fcap;
+  if (lane == 0) cur[0] = root;
+  __threadfence_block();
+  __syncthreads();
+  uint32_t fsize = 1;
+  while (fsize > 0) {
+    uint32_t nf = 0;
+    for (uint32_t base = 0; base < fsize; base += 64) {
+      const uint32_t i = base + lane;
+      const bool valid = i < fsize;
+      uint32_t node = 0, nch = 0, ch = 0, f = 0, cnt = 0;
+      bool acc = false;
+      if (valid) {
+        node = cur[i];
+        const double4 c = A.com[node];
+        nch = A.nchild[node];
+        ch = A.child[node];
+        f = A.first[node];
+        cnt = A.count[node];
+        acc = mac_accept(lo, hi, c, A.th2);
+      }
+      const bool leaf = valid && !acc && nch == 0;
+      const bool open = valid && !acc && nch > 0;
+      sink.p2m(A, acc, node);
+      sink.p2p(A, leaf, node, f, cnt);
+      uint32_t tot;
+      const uint32_t c = open ? nch : 0u;
+      const uint32_t pre = wave_excl_scan(c, tot);
+      if (nf + tot > (uint32_t)A.fcap) {
+        if (lane == 0) set_err(A.err, TG_ERR_FRONTIER);
+        return false;
+      }
+      for (uint32_t k = 0; k < c; ++k) nxt[nf + pre + k] = ch + k;
+      nf += tot;
+    }
+    __threadfence_block();
+    __syncthreads();
+    uint32_t *tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    fsize = nf;
+  }
+  sink.finish(A);
+  return true;
+}
+
+__device__ __forceinline__ uint32_t next_group(TreeCounters *ctr) {
+  uint32_t g = 0;
+  if (lane_id() == 0) g = atomicAdd(&ctr->queue, 1u);
+  return __shfl(g, 0, 64);
+}
+
+// ------------------------------------------------------------ force kernel
+template <bool kMixed>
+__global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
+  __shared__ uint32_t s_tgt[64];
+  __shared__ uint32_t s_m[kMCap];
+  __shared__ uint32_t s_q[kQCap];
+  __shared__ TileMem tile;
+  const unsigned lane = lane_id();
+  const uint32_t n_groups = A.ctr->n_active_groups;
+  unsigned long long tot_p2p = 0, tot_p2m = 0, tot_t = 0, tot_g = 0;
+  for (;;) {
+    const uint32_t gi = next_group(A.ctr);
+    if (gi >= n_groups) break;
+    const uint32_t g = A.alist[gi];
+    const uint4 gr = A.groups[g];
+    double lo[3], hi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { lo[k] = A.abox[6 * (size_t)g + k]; hi[k] = A.abox[6 * (size_t)g + 3 + k]; }
+    // compact the active targets of the group
+    const bool act = lane < gr.y && A.sact[gr.x + lane];
+    const unsigned long long amask = __ballot(act);
+    if (act) s_tgt[lanes_below(amask)] = gr.x + lane;
+    const int nt = __popcll(amask);
+    __syncthreads();
+    if (nt == 0) continue;   // cannot happen for a listed group; keeps s_tgt reads defined
+    int lg = 0;
+    while ((1 << lg) < nt) ++lg;
+    const int tpw = 1 << lg;
+    ForceSink<kMixed> S;
+    S.s_m = s_m; S.s_q = s_q; S.tile = &tile;
+    S.nm = 0; S.nq = 0; S.cells = 0; S.parts = 0;
+    S.slices = 64 >> lg;
+    S.my_s = (int)(lane >> lg);
+    const int my_t = (int)(lane & (tpw - 1));
+    const bool has_t = my_t < nt;
+    const uint32_t r_t = s_tgt[has_t ? my_t : 0];
+    const double4 p = A.spart[r_t];
+    S.cgx = 0.5 * (lo[0] + hi[0]);
+    S.cgy = 0.5 * (lo[1] + hi[1]);
+    S.cgz = 0.5 * (lo[2] + hi[2]);
+    S.eps2 = A.eps2;
+    S.eps2f = (float)A.eps2;
+    S.t.x = p.x; S.t.y = p.y; S.t.z = p.z;
+    S.t.ax = S.t.ay = S.t.az = S.t.ph = 0.0;
+    S.t.fx = (float)(p.x - S.cgx); S.t.fy = (float)(p.y - S.cgy); S.t.fz = (float)(p.z - S.cgz);
+    S.t.tax = S.t.tay = S.t.taz = S.t.tph = 0.f;
+    S.t.hax = S.t.hay = S.t.haz = S.t.hph = 0.f;
+    S.t.lax = S.t.lay = S.t.laz = S.t.lph = 0.f;
+    const bool ok = traverse(A, S, A.root_of[gr.w], lo, hi);
+    double ax, ay, az, ph, self;
+    if constexpr (kMixed) {
+      ax = (double)S.t.hax + (double)S.t.lax;
+      ay = (double)S.t.hay + (double)S.t.lay;
+      az = (double)S.t.haz + (double)S.t.laz;
+      ph = (double)S.t.hph + (double)S.t.lph;
+      self = (double)((float)p.w * __builtin_amdgcn_rsqf(S.eps2f));
+    } else {
+      ax = S.t.ax; ay = S.t.ay; az = S.t.az; ph = S.t.ph;
+      self = p.w * rsqrt_dp(A.eps2);
+    }
+    for (int o = tpw; o < 64; o <<= 1) {
+      ax += __shfl_xor(ax, o, 64);
+      ay += __shfl_xor(ay, o, 64);
+      az += __shfl_xor(az, o, 64);
+      ph += __shfl_xor(ph, o, 64);
+    }
+    if (S.my_s == 0 && has_t) {
+      const uint32_t orig = A.perm[r_t];
+      const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+      A.acc[3 * (size_t)orig + 0] = ok ? A.G * ax : nanv;
+      A.acc[3 * (size_t)orig + 1] = ok ? A.G * ay : nanv;
+      A.acc[3 * (size_t)orig + 2] = ok ? A.G * az : nanv;
+      if (A.pot) A.pot[orig] = ok ? A.G * (ph + self) : nanv;
+    }
+    tot_p2m += S.cells * (unsigned long long)nt;
+    tot_p2p += S.parts * (unsigned long long)nt - (unsigned long long)nt;
+    tot_t += (unsigned long long)nt;
+    tot_g += 1;
+    __syncthreads();
+  }
+  if (lane == 0 && tot_g) {
+    atomicAdd(&A.ctr->n_p2p, tot_p2p);
+    atomicAdd(&A.ctr->n_p2m, tot_p2m);
+    atomicAdd(&A.ctr->n_targets, tot_t);
+    atomicAdd(&A.ctr->n_walked, tot_g);
+    atomicAdd(&A.ctr->cum_p2p, tot_p2p);
+    atomicAdd(&A.ctr->cum_p2m, tot_p2m);
+    atomicAdd(&A.ctr->cum_targets, tot_t);
+    atomicAdd(&A.ctr->cum_walked, tot_g);
+  }
+}
+
+// -------------------------------------------------------- list kernels
+// pass 0: sizes per active group into wl_count[2 gi + {0,1}];
+// pass 1: ids at the offsets wl_off (exclusive scan of wl_count).
+template <int kPass>
+__global__ __launch_bounds__(64) void k_walk_lists(WalkArgs A) {
+  const uint32_t n_groups = A.ctr->n_active_groups;
+  for (;;) {
+    const uint32_t gi = next_group(A.ctr);
+    if (gi >= n_groups) break;
+    const uint32_t g = A.alist[gi];
+    const uint4 gr = A.groups[g];
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) { lo[k] = A.abox[6 * (size_t)g + k]; hi[k] = A.abox[6 * (size_t)g + 3 + k]; }
+    if constexpr (kPass == 0) {
+      // the fill pass repeats this walk exactly (also up to a frontier
+      // overflow), so these counts bound what it writes
+      CountSink S;
+      traverse(A, S, A.root_of[gr.w], lo, hi);
+      if (lane_id() == 0) {
+        A.wl_count[2 * (size_t)gi] = S.nm;
+        A.wl_count[2 * (size_t)gi + 1] = S.np;
+      }
+    } else {
+      FillSink S;
+      S.base_m = A.wl_off[2 * (size_t)gi];
+      S.base_p = A.wl_off[2 * (size_t)gi + 1];
+      traverse(A, S, A.root_of[gr.w], lo, hi);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ active groups
+__global__ void k_mark_active(const int32_t *__restrict__ idx,
+                              const int32_t *__restrict__ n_act, int64_t n,
+                              const uint32_t *__restrict__ rank,
+                              uint8_t *__restrict__ sact) {
+  const int64_t m = idx ? (int64_t)min((int64_t)n_act[0], n) : n;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (idx) {
+      const int32_t i = idx[k];
+      if (i >= 0 && i < n) sact[rank[i]] = 1;
+    } else {
+      sact[k] = 1;
+    }
+  }
+}
+
+__device__ __forceinline__ double wmin(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One wave per group: flag groups with an active particle and store the
+// box of their active particles.
+__global__ __launch_bounds__(256) void k_group_active(const TreeCounters *ctr,
+                                                      const uint4 *__restrict__ groups,
+                                                      const uint8_t *__restrict__ sact,
+                                                      const double4 *__restrict__ spart,
+                                                      uint32_t *__restrict__ aflag,
+                                                      double *__restrict__ abox) {
+  const uint32_t ng = ctr->n_groups;
+  const unsigned lane = threadIdx.x & 63u;
+  const uint32_t wpb = blockDim.x >> 6;
+  for (uint32_t g = blockIdx.x * wpb + (threadIdx.x >> 6); g < ng;
+       g += gridDim.x * wpb) {
+    const uint4 gr = groups[g];
+    const bool in = lane < gr.y;
+    const bool a = in && sact[gr.x + lane];
+    const unsigned long long m = __ballot(a);
+    double4 p = in ? spart[gr.x + lane] : make_double4(0, 0, 0, 0);
+    double lx = a ? p.x : INFINITY, ly = a ? p.y : INFINITY, lz = a ? p.z : INFINITY;
+    double hx = a ? p.x : -INFINITY, hy = a ? p.y : -INFINITY, hz = a ? p.z : -INFINITY;
+    lx = wmin(lx); ly = wmin(ly); lz = wmin(lz);
+    hx = wmax(hx); hy = wmax(hy); hz = wmax(hz);
+    if (lane == 0) {
+      aflag[g] = m ? 1u : 0u;
+      double *b = abox + 6 * (size_t)g;
+      b[0] = lx; b[1] = ly; b[2] = lz; b[3] = hx; b[4] = hy; b[5] = hz;
+    }
+  }
+}
+
+__global__ void k_compact_groups(const TreeCounters *ctr,
+                                 const uint32_t *__restrict__ aflag,
+                                 const uint32_t *__restrict__ aidx,
+                                 uint32_t *__restrict__ alist) {
+  const uint32_t ng = ctr->n_groups;
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += gridDim.x * blockDim.x)
+    if (aflag[g]) alist[aidx[g]] = g;
+}
+
+__global__ void k_counts_reset(TreeCounters *ctr) {
+  if (threadIdx.x == 0) {
+    ctr->cum_p2p = 0;
+    ctr->cum_p2m = 0;
+    ctr->cum_targets = 0;
+    ctr->cum_walked = 0;
+  }
+}
+
+hipError_t launch_counts_reset(tg_ctx *c) {
+  hipLaunchKernelGGL(k_counts_reset, dim3(1), dim3(64), 0, c->stream, c->b.ctr);
+  return hipGetLastError();
+}
+
+__global__ void k_walk_reset(TreeCounters *ctr) {
+  if (threadIdx.x == 0) {
+    ctr->queue = 0;
+    ctr->n_p2p = 0;
+    ctr->n_p2m = 0;
+    ctr->n_targets = 0;
+    ctr->n_walked = 0;
+  }
+}
+
+hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
+                                const int32_t *n_act) {
+  Buffers &b = c->b;
+  if (c->n == 0) return fill_u32(&b.ctr->n_active_groups, 0u, 1, c->stream);
+  hipError_t e = fill_u8(b.sact, 0, c->n, c->stream);
+  if (e != hipSuccess) return e;
+  int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_mark_active, dim3(g), dim3(256), 0, c->stream, idx,
+                     n_act, c->n, b.rank, b.sact);
+  hipLaunchKernelGGL(k_group_active, dim3(2048), dim3(256), 0, c->stream,
+                     b.ctr, b.groups, b.sact, b.spart, b.aflag, b.abox);
+  // the group-start scan buffer is free after the build: reuse it
+  e = scan_u32(b.aflag, b.gflag, 0u, &b.ctr->n_groups, &b.ctr->n_active_groups,
+               b.scan_part, c->stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compact_groups, dim3(1024), dim3(256), 0, c->stream,
+                     b.ctr, b.aflag, b.gflag, b.alist);
+  return hipGetLastError();
+}
+
+static WalkArgs make_args(tg_ctx *c, double theta) {
+  Buffers &b = c->b;
+  WalkArgs A;
+  A.nchild = b.nchild; A.first = b.first; A.count = b.count; A.child = b.child;
+  A.com = b.com; A.mom = b.mom; A.spart = b.spart; A.root_of = b.root_of;
+  A.groups = b.groups; A.alist = b.alist; A.abox = b.abox; A.sact = b.sact;
+  A.perm = b.val[0]; A.ctr = b.ctr; A.err = b.err; A.frontier = b.frontier;
+  A.fcap = c->cfg.frontier_cap;
+  A.th2 = theta * theta;
+  A.eps2 = 0.0; A.G = c->cfg.G;
+  A.acc = nullptr; A.pot = nullptr;
+  A.wl_count = b.wl_count; A.wl_off = b.wl_off; A.ids = nullptr;
+  return A;
+}
+
+static int walk_grid(tg_ctx *c) {
+  return std::max(1, c->n_cu * c->waves_per_cu);
+}
+
+hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
+                              double *acc, double *pot, hipEvent_t before,
+                              hipEvent_t after) {
+  WalkArgs A = make_args(c, theta);
+  A.eps2 = eps * eps;
+  A.acc = acc;
+  A.pot = pot;
+  hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, c->stream, c->b.ctr);
+  if (before) {
+    hipError_t e = hipEventRecord(before, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  if (c->cfg.precision == TG_MIXED)
+    hipLaunchKernelGGL(k_walk_forces<true>, dim3(walk_grid(c)), dim3(64), 0,
+                       c->stream, A);
+  else
+    hipLaunchKernelGGL(k_walk_forces<false>, dim3(walk_grid(c)), dim3(64), 0,
+                       c->stream, A);
+  if (after) {
+    hipError_t e = hipEventRecord(after, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_lists(tg_ctx *c, double theta, int pass, int64_t *info,
+                             int64_t cap_groups, uint32_t *ids, int64_t cap_ids) {
+  (void)info; (void)cap_groups; (void)cap_ids;
+  WalkArgs A = make_args(c, theta);
+  A.ids = ids;
+  hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, c->stream, c->b.ctr);
+  if (pass == 0)
+    hipLaunchKernelGGL(k_walk_lists<0>, dim3(walk_grid(c)), dim3(64), 0,
+                       c->stream, A);
+  else
+    hipLaunchKernelGGL(k_walk_lists<1>, dim3(walk_grid(c)), dim3(64), 0,
+                       c->stream, A);
+  return hipGetLastError();
+}
+
+}  // namespace tg

@@ -1,0 +1,235 @@
+// Internal declarations shared by the HIP translation units of libtg.so.
+// Device data layouts (all in HBM, owned by the context):
+//   sorted particles   spart[N]   double4 {x, y, z, m}      (32 B each)
+//   sort keys / perm   key[N] u64, perm[N] u32 (sorted rank -> caller index),
+//                      rank[N] u32 (caller index -> sorted rank)
+//   nodes (SoA)        level u8, nchild u8, first u32, count u32, child u32,
+//                      parent u32, sys u32; com double4 {cx, cy, cz, side^2};
+//                      mom double[8] {M, Sxx, Syy, Szz, Sxy, Sxz, Syz, 0}
+//   groups             uint4 {first, count, node, system}
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tg.h"
+
+namespace tg {
+
+constexpr int kBits = 21;             // key bits per axis
+constexpr int kMaxLevel = 21;         // deepest octree level
+constexpr int kLevels = kMaxLevel + 1;
+constexpr uint32_t kNone = 0xffffffffu;
+constexpr int kMaxLeaf = 16;          // largest n_L (bounds the walk's LDS queue)
+constexpr int kMaxGroup = 64;         // one wavefront of targets
+constexpr int kMaxSys = 256;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per tile
+constexpr int kScanBlocks = 256;
+constexpr int kMaxWavesPerCU = 16;
+
+// A tile of consecutive particles inside one system (sort, cube, keys).
+struct Tile {
+  uint32_t start, end;    // particle range
+  uint32_t hist0;         // histogram slot of digit 0 for this tile
+  uint32_t hstride;       // slots between digits (= tiles of the system)
+};
+
+// Per-level bookkeeping kept on the device so that graph replays need no
+// host round trip.  lvl[l] = first node id of level l, lvl[l+1] = end.
+struct TreeCounters {
+  uint32_t lvl[kLevels + 2];
+  uint32_t n_nodes;
+  uint32_t n_groups;
+  uint32_t n_active_groups;
+  uint32_t overflow;         // node capacity exceeded during this build
+  uint32_t queue;            // walk work counter
+  uint32_t pad[3];
+  unsigned long long n_p2p, n_p2m, n_targets, n_walked;      // last walk
+  unsigned long long cum_p2p, cum_p2m, cum_targets, cum_walked;  // since reset
+};
+
+struct Buffers {
+  // system layout
+  int64_t *sysoff = nullptr;      // [S+1]
+  double *cube = nullptr;         // [S][4]
+  double *cube_part = nullptr;    // [tiles][6] per-tile min / max
+  Tile *tiles = nullptr;          // [tiles]
+  uint32_t *sys_tile0 = nullptr;  // [S+1] first tile of each system
+  uint32_t *root_of = nullptr;    // [S]
+  // sort
+  uint64_t *key[2] = {nullptr, nullptr};
+  uint32_t *val[2] = {nullptr, nullptr};
+  uint32_t *hist = nullptr;       // [256 * tiles]
+  uint32_t *rank = nullptr;       // [N]
+  double4 *spart = nullptr;       // [N]
+  // nodes
+  uint8_t *level = nullptr, *nchild = nullptr;
+  uint32_t *first = nullptr, *count = nullptr, *child = nullptr,
+           *parent = nullptr, *nsys = nullptr;
+  double4 *com = nullptr;
+  double *mom = nullptr;          // [nodes][8]
+  uint32_t *lvl_tmp = nullptr;    // [nodes] per-level child counts
+  // groups
+  uint32_t *gflag = nullptr;      // [N + 1] group starts / scan
+  uint4 *groups = nullptr;        // [N]
+  uint32_t *aflag = nullptr;      // [N + 1] active-group flags / scan
+  uint32_t *alist = nullptr;      // [N] active group ids
+  double *abox = nullptr;         // [N][6] box of active targets per group
+  uint8_t *sact = nullptr;        // [N] active flag per sorted particle
+  // walk
+  uint32_t *frontier = nullptr;   // [waves][2][frontier_cap]
+  uint32_t *wl_count = nullptr;   // [N][2] list sizes (list mode)
+  uint32_t *wl_off = nullptr;     // [2N + 1] list offsets (list mode)
+  // scan scratch and counters
+  uint32_t *scan_part = nullptr;  // [kScanBlocks + 1]
+  uint32_t *scan_total = nullptr; // [4]
+  TreeCounters *ctr = nullptr;
+  uint32_t *err = nullptr;        // device error bits
+  // direct sums
+  double *dpart = nullptr;        // partial sums for few-target direct sums
+  int64_t *dseg = nullptr;        // [2 * (S+1)] segment offsets
+  int64_t dpart_cap = 0;
+};
+
+}  // namespace tg
+
+struct tg_ctx {
+  tg_config cfg;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 256;
+  int64_t n = 0;
+  int32_t S = 0;
+  int32_t leaf_size = 8, group_size = 64, waves_per_cu = 8;
+  int64_t max_nodes = 0;
+  int64_t max_tiles = 0;
+  int64_t n_tiles = 0;
+  bool have_tree = false, have_moments = false;
+  bool capturing = false;
+  // walk-kernel timing (tg_set_profiling): ring of event pairs
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int64_t ev_head = 0, ev_tail = 0;     // recorded / resolved pairs
+  double prof_ms = 0.0;
+  int64_t prof_n = 0;
+  std::vector<int64_t> sysoff_host;   // layout of the last build
+  std::vector<int64_t> dseg_host;     // segment table of the last direct sum
+  tg::Buffers b;
+};
+
+struct tg_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace tg {
+
+// error reporting (tg_runtime.hip)
+tg_status fail(tg_status st, const std::string &msg);
+tg_status hip_fail(hipError_t e, const char *what);
+
+#define TG_HIP(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return tg::hip_fail(e_, #call); \
+  } while (0)
+
+// ---- launchers (each .hip file owns its kernels) ----
+// k_scan.hip: exclusive scan of u32; n from n_dev (if non-null) else n_host.
+// Writes the total to *total_dev (if non-null).  in may equal out.
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, uint32_t n_host,
+                    const uint32_t *n_dev, uint32_t *total_dev,
+                    uint32_t *part, hipStream_t s);
+hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+
+// k_keys.hip
+hipError_t launch_cube_keys(tg_ctx *c, const double *pos);
+hipError_t launch_sort(tg_ctx *c);
+hipError_t launch_gather(tg_ctx *c, const double *pos);
+
+// k_tree.hip
+hipError_t launch_tree_build(tg_ctx *c);
+hipError_t launch_groups(tg_ctx *c);
+
+// k_moments.hip
+hipError_t launch_moments(tg_ctx *c, const double *mass);
+
+// k_walk.hip
+hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
+                                const int32_t *n_act);
+hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
+                              double *acc, double *pot, hipEvent_t before,
+                              hipEvent_t after);
+hipError_t launch_counts_reset(tg_ctx *c);
+hipError_t launch_walk_lists(tg_ctx *c, double theta, int pass,
+                             int64_t *info, int64_t cap_groups, uint32_t *ids,
+                             int64_t cap_ids);
+
+// k_direct.hip
+hipError_t launch_direct(tg_ctx *c, const double *spos, const double *sm,
+                         const double *seps, int64_t ns, const double *tpos,
+                         const double *teps, int64_t nt, int nseg,
+                         int64_t max_seg_src, int self_pairs, int accumulate,
+                         double *acc, double *pot);
+
+// k_integrate.hip
+hipError_t launch_kick(tg_ctx *c, double *vel, const double *acc, int64_t n,
+                       const int32_t *idx, const int32_t *n_act,
+                       const uint8_t *level, double dt, const int64_t *k,
+                       int skip_k0);
+hipError_t launch_drift(tg_ctx *c, double *pos, const double *vel, int64_t n,
+                        double dt);
+hipError_t launch_levels(tg_ctx *c, const double *acc, const double *t4e2,
+                         int64_t n, const int32_t *idx, const int32_t *n_act,
+                         double dt_max, int nlev, const int64_t *k,
+                         uint8_t *level);
+hipError_t launch_active_set(tg_ctx *c, const uint8_t *level, int64_t n,
+                             int nlev, const int64_t *k, int k_add,
+                             int32_t *idx, int32_t *n_out);
+hipError_t launch_counter_add(tg_ctx *c, int64_t *k, int64_t inc);
+
+// ---- small device helpers ----
+__device__ __forceinline__ unsigned lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// number of set bits of `mask` in lanes below this one
+__device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+__device__ __forceinline__ void set_err(uint32_t *err, uint32_t bit) {
+  atomicOr(err, bit);
+}
+
+// Exclusive scan of one value per thread across the block (multiple of 64
+// threads); sh needs blockDim/64 entries.  Contains two barriers.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh,
+                                         uint32_t &total) {
+  const unsigned lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= (unsigned)o) x += y;
+  }
+  if (lane == 63u) sh[w] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  const unsigned nw = blockDim.x >> 6;
+  for (unsigned i = 0; i < nw; ++i) {
+    uint32_t t = sh[i];
+    base += (i < w) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return base + x - v;
+}
+
+}  // namespace tg

@@ -1,0 +1,675 @@
+// Host side of libtg.so: the C ABI declared in include/tg.h.  Validates
+// arguments on the host, owns every device buffer (allocated once in
+// tg_create, so any sequence of calls is graph-capturable), sequences the
+// kernel launches of each step on the context's stream, and reports device
+// error bits through tg_sync.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tg_internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+namespace tg {
+
+tg_status fail(tg_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+tg_status hip_fail(hipError_t e, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return TG_EHIP;
+}
+
+template <class T>
+static hipError_t dalloc(T **p, size_t count) {
+  return hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+}  // namespace tg
+
+using namespace tg;
+
+extern "C" {
+
+const char *tg_last_error(void) { return g_last_error.c_str(); }
+
+const char *tg_version(void) {
+  return "libtg gfx950 (HIP, wave64, FP64 + mixed walk)";
+}
+
+void tg_default_config(tg_config *cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->max_particles = 1;
+  cfg->max_systems = 1;
+  cfg->leaf_size = 8;
+  cfg->group_size = 64;
+  cfg->precision = TG_FP64;
+  cfg->max_nodes = 0;
+  cfg->frontier_cap = 0;
+  cfg->waves_per_cu = 0;
+  cfg->G = 1.0;
+}
+
+static void free_all(tg_ctx *c) {
+  Buffers &b = c->b;
+  void *ptrs[] = {b.sysoff, b.cube, b.cube_part, b.tiles, b.sys_tile0,
+                  b.root_of, b.key[0], b.key[1], b.val[0], b.val[1], b.hist,
+                  b.rank, b.spart, b.level, b.nchild, b.first, b.count,
+                  b.child, b.parent, b.nsys, b.com, b.mom, b.lvl_tmp, b.gflag,
+                  b.groups, b.aflag, b.alist, b.abox, b.sact, b.frontier,
+                  b.wl_count, b.wl_off, b.scan_part, b.scan_total, b.ctr,
+                  b.err, b.dpart, b.dseg};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  b = Buffers();
+}
+
+tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
+  if (!cfg_in || !out) return fail(TG_EINVAL, "tg_create: NULL argument");
+  *out = nullptr;
+  tg_config cfg = *cfg_in;
+  if (cfg.max_particles < 1 || cfg.max_particles > (int64_t)0x7fffffff / 2)
+    return fail(TG_EINVAL, "tg_create: max_particles out of range");
+  if (cfg.max_systems < 1 || cfg.max_systems > kMaxSys)
+    return fail(TG_EINVAL, "tg_create: max_systems must be in 1..256");
+  if (cfg.leaf_size < 1 || cfg.leaf_size > kMaxLeaf)
+    return fail(TG_EINVAL, "tg_create: leaf_size must be in 1..16");
+  if (cfg.group_size < 1 || cfg.group_size > kMaxGroup)
+    return fail(TG_EINVAL, "tg_create: group_size must be in 1..64");
+  if (cfg.precision != TG_FP64 && cfg.precision != TG_MIXED)
+    return fail(TG_EINVAL, "tg_create: unknown precision");
+  if (!(cfg.G > 0.0) || !std::isfinite(cfg.G))
+    return fail(TG_EINVAL, "tg_create: G must be positive");
+  if (cfg.max_nodes == 0)
+    cfg.max_nodes = 2 * cfg.max_particles + 64 * (int64_t)cfg.max_systems;
+  if (cfg.max_nodes < cfg.max_systems || cfg.max_nodes > (int64_t)0xfffffff0)
+    return fail(TG_EINVAL, "tg_create: max_nodes out of range");
+  if (cfg.frontier_cap == 0) cfg.frontier_cap = 16384;
+  if (cfg.frontier_cap < 64) return fail(TG_EINVAL, "tg_create: frontier_cap < 64");
+  if (cfg.waves_per_cu == 0) cfg.waves_per_cu = 8;
+  if (cfg.waves_per_cu < 1 || cfg.waves_per_cu > kMaxWavesPerCU)
+    return fail(TG_EINVAL, "tg_create: waves_per_cu must be in 1..16");
+
+  tg_ctx *c = new tg_ctx();
+  c->cfg = cfg;
+  c->stream = (hipStream_t)stream;
+  c->leaf_size = cfg.leaf_size;
+  c->group_size = cfg.group_size;
+  c->waves_per_cu = cfg.waves_per_cu;
+  c->max_nodes = cfg.max_nodes;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
+                              c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "tg_create: device query");
+  }
+  const int64_t N = cfg.max_particles, S = cfg.max_systems, NN = cfg.max_nodes;
+  c->max_tiles = (N + kSortTile - 1) / kSortTile + S;
+  Buffers &b = c->b;
+  b.dpart_cap = (int64_t)8 * 131072;
+  const int64_t waves = (int64_t)c->n_cu * kMaxWavesPerCU;
+  hipError_t a = hipSuccess;
+  auto A = [&](hipError_t r) { if (a == hipSuccess) a = r; };
+  A(dalloc(&b.sysoff, S + 1));
+  A(dalloc(&b.cube, 4 * S));
+  A(dalloc(&b.cube_part, 6 * c->max_tiles));
+  A(dalloc(&b.tiles, c->max_tiles));
+  A(dalloc(&b.sys_tile0, S + 1));
+  A(dalloc(&b.root_of, S));
+  A(dalloc(&b.key[0], N)); A(dalloc(&b.key[1], N));
+  A(dalloc(&b.val[0], N)); A(dalloc(&b.val[1], N));
+  A(dalloc(&b.hist, 256 * c->max_tiles));
+  A(dalloc(&b.rank, N));
+  A(dalloc(&b.spart, N));
+  A(dalloc(&b.level, NN)); A(dalloc(&b.nchild, NN));
+  A(dalloc(&b.first, NN)); A(dalloc(&b.count, NN)); A(dalloc(&b.child, NN));
+  A(dalloc(&b.parent, NN)); A(dalloc(&b.nsys, NN));
+  A(dalloc(&b.com, NN)); A(dalloc(&b.mom, 8 * NN));
+  A(dalloc(&b.lvl_tmp, NN));
+  A(dalloc(&b.gflag, N + 1));
+  A(dalloc(&b.groups, N));
+  A(dalloc(&b.aflag, N + 1));
+  A(dalloc(&b.alist, N));
+  A(dalloc(&b.abox, 6 * N));
+  A(dalloc(&b.sact, N));
+  A(dalloc(&b.frontier, waves * 2 * (int64_t)cfg.frontier_cap));
+  A(dalloc(&b.wl_count, 2 * N + 2));
+  A(dalloc(&b.wl_off, 2 * N + 2));
+  A(dalloc(&b.scan_part, kScanBlocks + 1));
+  A(dalloc(&b.scan_total, 4));
+  A(dalloc(&b.ctr, 1));
+  A(dalloc(&b.err, 1));
+  A(dalloc(&b.dpart, b.dpart_cap));
+  A(dalloc(&b.dseg, 2 * (kMaxSys + 1)));
+  if (a != hipSuccess) {
+    free_all(c);
+    delete c;
+    return fail(TG_ENOMEM, std::string("tg_create: hipMalloc: ") + hipGetErrorString(a));
+  }
+  A(hipMemset(b.ctr, 0, sizeof(TreeCounters)));
+  A(hipMemset(b.err, 0, sizeof(uint32_t)));
+  A(hipDeviceSynchronize());
+  if (a != hipSuccess) {
+    free_all(c);
+    delete c;
+    return hip_fail(a, "tg_create: init");
+  }
+  *out = c;
+  return TG_OK;
+}
+
+void tg_destroy(tg_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_start) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_stop) (void)hipEventDestroy(e);
+  free_all(c);
+  delete c;
+}
+
+tg_status tg_set_stream(tg_ctx *c, void *stream) {
+  if (!c) return fail(TG_EINVAL, "tg_set_stream: NULL context");
+  if (c->capturing) return fail(TG_ESTATE, "tg_set_stream: during capture");
+  c->stream = (hipStream_t)stream;
+  return TG_OK;
+}
+
+tg_status tg_set_sizes(tg_ctx *c, int32_t leaf_size, int32_t group_size) {
+  if (!c) return fail(TG_EINVAL, "tg_set_sizes: NULL context");
+  if (leaf_size < 1 || leaf_size > kMaxLeaf)
+    return fail(TG_EINVAL, "tg_set_sizes: leaf_size must be in 1..16");
+  if (group_size < 1 || group_size > kMaxGroup)
+    return fail(TG_EINVAL, "tg_set_sizes: group_size must be in 1..64");
+  c->leaf_size = leaf_size;
+  c->group_size = group_size;
+  c->have_tree = c->have_moments = false;
+  return TG_OK;
+}
+
+// Upload the system layout and tile table if it changed since the last
+// build (never during graph capture).
+static tg_status set_layout(tg_ctx *c, int64_t n, const int64_t *off, int32_t S) {
+  std::vector<int64_t> so(S + 1);
+  if (off) {
+    for (int s = 0; s <= S; ++s) so[s] = off[s];
+  } else {
+    so[0] = 0;
+    so[1] = n;
+  }
+  if (so[0] != 0 || so[S] != n)
+    return fail(TG_EINVAL, "tg_build_tree: sys_off must start at 0 and end at N");
+  for (int s = 0; s < S; ++s)
+    if (so[s + 1] < so[s]) return fail(TG_EINVAL, "tg_build_tree: sys_off not ascending");
+  if (so == c->sysoff_host && c->n == n && c->S == S) return TG_OK;
+  if (c->capturing)
+    return fail(TG_ESTATE, "tg_build_tree: system layout changed during graph capture");
+  std::vector<Tile> tiles;
+  std::vector<uint32_t> t0(S + 1);
+  uint32_t hbase = 0;
+  for (int s = 0; s < S; ++s) {
+    t0[s] = (uint32_t)tiles.size();
+    const int64_t ns = so[s + 1] - so[s];
+    const uint32_t nts = (uint32_t)((ns + kSortTile - 1) / kSortTile);
+    for (uint32_t k = 0; k < nts; ++k) {
+      Tile t;
+      t.start = (uint32_t)(so[s] + (int64_t)k * kSortTile);
+      t.end = (uint32_t)std::min<int64_t>(so[s + 1], so[s] + (int64_t)(k + 1) * kSortTile);
+      t.hist0 = hbase + k;
+      t.hstride = nts;
+      tiles.push_back(t);
+    }
+    hbase += 256u * nts;
+  }
+  t0[S] = (uint32_t)tiles.size();
+  if ((int64_t)tiles.size() > c->max_tiles)
+    return fail(TG_ECAPACITY, "tg_build_tree: tile table too large");
+  Buffers &b = c->b;
+  TG_HIP(hipMemcpyAsync(b.sysoff, so.data(), sizeof(int64_t) * (S + 1),
+                        hipMemcpyHostToDevice, c->stream));
+  TG_HIP(hipMemcpyAsync(b.sys_tile0, t0.data(), sizeof(uint32_t) * (S + 1),
+                        hipMemcpyHostToDevice, c->stream));
+  if (!tiles.empty())
+    TG_HIP(hipMemcpyAsync(b.tiles, tiles.data(), sizeof(Tile) * tiles.size(),
+                          hipMemcpyHostToDevice, c->stream));
+  TG_HIP(hipStreamSynchronize(c->stream));
+  c->sysoff_host = so;
+  c->n = n;
+  c->S = S;
+  c->n_tiles = (int64_t)tiles.size();
+  return TG_OK;
+}
+
+tg_status tg_build_tree(tg_ctx *c, const double *pos, int64_t n,
+                        const int64_t *sys_off, int32_t S) {
+  if (!c) return fail(TG_EINVAL, "tg_build_tree: NULL context");
+  if (n < 0 || n > c->cfg.max_particles)
+    return fail(TG_EINVAL, "tg_build_tree: N exceeds max_particles");
+  if (S < 1 || S > c->cfg.max_systems)
+    return fail(TG_EINVAL, "tg_build_tree: number of systems out of range");
+  if (!sys_off && S != 1)
+    return fail(TG_EINVAL, "tg_build_tree: sys_off required for S > 1");
+  if (n > 0 && !pos) return fail(TG_EINVAL, "tg_build_tree: NULL positions");
+  tg_status st = set_layout(c, n, sys_off, S);
+  if (st != TG_OK) return st;
+  c->have_tree = c->have_moments = false;
+  TG_HIP(launch_cube_keys(c, pos));
+  TG_HIP(launch_sort(c));
+  TG_HIP(launch_gather(c, pos));
+  TG_HIP(launch_tree_build(c));
+  TG_HIP(launch_groups(c));
+  c->have_tree = true;
+  return TG_OK;
+}
+
+tg_status tg_compute_moments(tg_ctx *c, const double *mass) {
+  if (!c) return fail(TG_EINVAL, "tg_compute_moments: NULL context");
+  if (!c->have_tree) return fail(TG_ESTATE, "tg_compute_moments: no tree");
+  if (c->n > 0 && !mass) return fail(TG_EINVAL, "tg_compute_moments: NULL mass");
+  TG_HIP(launch_moments(c, mass));
+  c->have_moments = true;
+  return TG_OK;
+}
+
+static tg_status check_walk_args(tg_ctx *c, double theta, const int32_t *idx,
+                                 const int32_t *n_act, const char *who) {
+  if (!c) return fail(TG_EINVAL, std::string(who) + ": NULL context");
+  if (!c->have_moments) return fail(TG_ESTATE, std::string(who) + ": no tree/moments");
+  if (!(theta >= 0.0) || !(theta * theta * 3.0 < 1.0))
+    return fail(TG_EINVAL, std::string(who) + ": theta must be in [0, 1/sqrt(3))");
+  if (idx && !n_act) return fail(TG_EINVAL, std::string(who) + ": n_active required");
+  return TG_OK;
+}
+
+tg_status tg_tree_forces(tg_ctx *c, double eps, double theta,
+                         const int32_t *idx, const int32_t *n_act, double *acc,
+                         double *pot) {
+  tg_status st = check_walk_args(c, theta, idx, n_act, "tg_tree_forces");
+  if (st != TG_OK) return st;
+  if (!(eps > 0.0) || !std::isfinite(eps))
+    return fail(TG_EINVAL, "tg_tree_forces: eps must be positive");
+  if (c->n > 0 && !acc) return fail(TG_EINVAL, "tg_tree_forces: NULL acc");
+  if (c->n == 0) return TG_OK;
+  TG_HIP(launch_active_groups(c, idx, n_act));
+  hipEvent_t before = nullptr, after = nullptr;
+  if (c->profiling && !c->capturing) {
+    const int64_t ring = (int64_t)c->ev_start.size();
+    if (c->ev_head - c->ev_tail == ring) {      // ring full: resolve the oldest
+      const int64_t k = c->ev_tail % ring;
+      float ms = 0.f;
+      TG_HIP(hipEventSynchronize(c->ev_stop[k]));
+      TG_HIP(hipEventElapsedTime(&ms, c->ev_start[k], c->ev_stop[k]));
+      c->prof_ms += ms;
+      c->prof_n += 1;
+      c->ev_tail += 1;
+    }
+    const int64_t k = c->ev_head % ring;
+    before = c->ev_start[k];
+    after = c->ev_stop[k];
+    c->ev_head += 1;
+  }
+  TG_HIP(launch_walk_forces(c, eps, theta, acc, pot, before, after));
+  return TG_OK;
+}
+
+tg_status tg_set_profiling(tg_ctx *c, int32_t on) {
+  if (!c) return fail(TG_EINVAL, "tg_set_profiling: NULL context");
+  if (c->capturing) return fail(TG_ESTATE, "tg_set_profiling: during capture");
+  if (on && c->ev_start.empty()) {
+    const int ring = 256;
+    c->ev_start.resize(ring);
+    c->ev_stop.resize(ring);
+    for (int k = 0; k < ring; ++k) {
+      TG_HIP(hipEventCreate(&c->ev_start[k]));
+      TG_HIP(hipEventCreate(&c->ev_stop[k]));
+    }
+  }
+  if (c->profiling) TG_HIP(hipStreamSynchronize(c->stream));
+  c->profiling = on != 0;
+  c->ev_head = c->ev_tail = 0;
+  c->prof_ms = 0.0;
+  c->prof_n = 0;
+  return TG_OK;
+}
+
+tg_status tg_get_profile(tg_ctx *c, double *walk_ms, int64_t *n_walks) {
+  if (!c || !walk_ms || !n_walks) return fail(TG_EINVAL, "tg_get_profile: NULL argument");
+  if (c->capturing) return fail(TG_ESTATE, "tg_get_profile: during capture");
+  const int64_t ring = (int64_t)c->ev_start.size();
+  while (c->ev_tail < c->ev_head) {
+    const int64_t k = c->ev_tail % ring;
+    float ms = 0.f;
+    TG_HIP(hipEventSynchronize(c->ev_stop[k]));
+    TG_HIP(hipEventElapsedTime(&ms, c->ev_start[k], c->ev_stop[k]));
+    c->prof_ms += ms;
+    c->prof_n += 1;
+    c->ev_tail += 1;
+  }
+  *walk_ms = c->prof_ms;
+  *n_walks = c->prof_n;
+  return TG_OK;
+}
+
+tg_status tg_reset_counts(tg_ctx *c) {
+  if (!c) return fail(TG_EINVAL, "tg_reset_counts: NULL context");
+  TG_HIP(launch_counts_reset(c));
+  return TG_OK;
+}
+
+tg_status tg_get_counts(tg_ctx *c, int64_t out[8]) {
+  if (!c || !out) return fail(TG_EINVAL, "tg_get_counts: NULL argument");
+  if (c->capturing) return fail(TG_ESTATE, "tg_get_counts: during capture");
+  TreeCounters h;
+  TG_HIP(hipMemcpyAsync(&h, c->b.ctr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  TG_HIP(hipStreamSynchronize(c->stream));
+  out[0] = (int64_t)h.n_p2p;
+  out[1] = (int64_t)h.n_p2m;
+  out[2] = (int64_t)h.n_targets;
+  out[3] = (int64_t)h.n_walked;
+  out[4] = (int64_t)h.cum_p2p;
+  out[5] = (int64_t)h.cum_p2m;
+  out[6] = (int64_t)h.cum_targets;
+  out[7] = (int64_t)h.cum_walked;
+  return TG_OK;
+}
+
+tg_status tg_walk_lists(tg_ctx *c, double theta, const int32_t *idx,
+                        const int32_t *n_act, int64_t *info, int64_t cap_groups,
+                        uint32_t *ids, int64_t cap_ids, int64_t *n_groups_out,
+                        int64_t *n_ids_out) {
+  tg_status st = check_walk_args(c, theta, idx, n_act, "tg_walk_lists");
+  if (st != TG_OK) return st;
+  if (c->capturing) return fail(TG_ESTATE, "tg_walk_lists: during capture");
+  if (!n_groups_out || !n_ids_out) return fail(TG_EINVAL, "tg_walk_lists: NULL outputs");
+  *n_groups_out = 0;
+  *n_ids_out = 0;
+  if (c->n == 0) return TG_OK;
+  Buffers &b = c->b;
+  TG_HIP(launch_active_groups(c, idx, n_act));
+  TG_HIP(launch_walk_lists(c, theta, 0, nullptr, 0, nullptr, 0));
+  TreeCounters h;
+  TG_HIP(hipMemcpyAsync(&h, b.ctr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  TG_HIP(hipStreamSynchronize(c->stream));
+  const uint32_t nag = h.n_active_groups;
+  TG_HIP(scan_u32(b.wl_count, b.wl_off, 2u * nag, nullptr, b.scan_total,
+                  b.scan_part, c->stream));
+  uint32_t total = 0;
+  TG_HIP(hipMemcpyAsync(&total, b.scan_total, sizeof(uint32_t),
+                        hipMemcpyDeviceToHost, c->stream));
+  TG_HIP(hipStreamSynchronize(c->stream));
+  *n_groups_out = nag;
+  *n_ids_out = total;
+  if ((int64_t)nag > cap_groups || (int64_t)total > cap_ids || !info || !ids)
+    return fail(TG_ECAPACITY, "tg_walk_lists: output capacity too small");
+  TG_HIP(launch_walk_lists(c, theta, 1, nullptr, 0, ids, cap_ids));
+  std::vector<uint32_t> cnt(2 * (size_t)nag), off(2 * (size_t)nag), al(nag);
+  if (nag) {
+    TG_HIP(hipMemcpyAsync(cnt.data(), b.wl_count, sizeof(uint32_t) * 2 * nag,
+                          hipMemcpyDeviceToHost, c->stream));
+    TG_HIP(hipMemcpyAsync(off.data(), b.wl_off, sizeof(uint32_t) * 2 * nag,
+                          hipMemcpyDeviceToHost, c->stream));
+    TG_HIP(hipMemcpyAsync(al.data(), b.alist, sizeof(uint32_t) * nag,
+                          hipMemcpyDeviceToHost, c->stream));
+  }
+  TG_HIP(hipStreamSynchronize(c->stream));
+  std::vector<int64_t> inf(4 * (size_t)nag);
+  for (uint32_t g = 0; g < nag; ++g) {
+    inf[4 * g + 0] = al[g];
+    inf[4 * g + 1] = off[2 * g];
+    inf[4 * g + 2] = cnt[2 * g];
+    inf[4 * g + 3] = cnt[2 * g + 1];
+  }
+  if (nag)
+    TG_HIP(hipMemcpy(info, inf.data(), sizeof(int64_t) * inf.size(), hipMemcpyHostToDevice));
+  return TG_OK;
+}
+
+tg_status tg_direct_fp64(tg_ctx *c, const double *spos, const double *sm,
+                         const double *seps, int64_t ns, const double *tpos,
+                         const double *teps, int64_t nt, const int64_t *sseg,
+                         const int64_t *tseg, int32_t nseg, int32_t self_pairs,
+                         int32_t accumulate, double *acc, double *pot) {
+  if (!c) return fail(TG_EINVAL, "tg_direct_fp64: NULL context");
+  if (ns < 0 || nt < 0) return fail(TG_EINVAL, "tg_direct_fp64: negative size");
+  if (nt == 0) return TG_OK;
+  if (!tpos || !teps || !acc || (ns > 0 && (!spos || !sm || !seps)))
+    return fail(TG_EINVAL, "tg_direct_fp64: NULL pointer");
+  if (nseg < 0 || nseg > kMaxSys)
+    return fail(TG_EINVAL, "tg_direct_fp64: nseg must be in 0..256");
+  if (self_pairs && ns != nt)
+    return fail(TG_EINVAL, "tg_direct_fp64: self_pairs needs ns == nt");
+  std::vector<int64_t> seg;
+  int ns_eff = nseg;
+  if (nseg == 0) {
+    seg = {0, ns, 0, nt};
+    ns_eff = 1;
+  } else {
+    if (!sseg || !tseg) return fail(TG_EINVAL, "tg_direct_fp64: NULL segments");
+    seg.resize(2 * (nseg + 1));
+    for (int s = 0; s <= nseg; ++s) { seg[s] = sseg[s]; seg[nseg + 1 + s] = tseg[s]; }
+    if (seg[0] != 0 || seg[nseg] != ns || seg[nseg + 1] != 0 || seg[2 * nseg + 1] != nt)
+      return fail(TG_EINVAL, "tg_direct_fp64: segment offsets must span 0..n");
+    for (int s = 0; s < nseg; ++s)
+      if (seg[s + 1] < seg[s] || seg[nseg + 2 + s] < seg[nseg + 1 + s])
+        return fail(TG_EINVAL, "tg_direct_fp64: segment offsets not ascending");
+  }
+  int64_t max_src = 0;
+  for (int s = 0; s < ns_eff; ++s) max_src = std::max(max_src, seg[s + 1] - seg[s]);
+  // segment table lives in a small device buffer; re-upload only if changed
+  if (seg != c->dseg_host) {
+    if (c->capturing)
+      return fail(TG_ESTATE, "tg_direct_fp64: segment layout changed during capture");
+    TG_HIP(hipMemcpyAsync(c->b.dseg, seg.data(), sizeof(int64_t) * seg.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    TG_HIP(hipStreamSynchronize(c->stream));
+    c->dseg_host = seg;
+  }
+  TG_HIP(launch_direct(c, spos, sm, seps, ns, tpos, teps, nt, ns_eff, max_src,
+                       self_pairs, accumulate, acc, pot));
+  return TG_OK;
+}
+
+tg_status tg_kick(tg_ctx *c, double *vel, const double *acc, int64_t n,
+                  const int32_t *idx, const int32_t *n_act,
+                  const uint8_t *level, double dt, const int64_t *k,
+                  int32_t skip_k0) {
+  if (!c) return fail(TG_EINVAL, "tg_kick: NULL context");
+  if (n < 0) return fail(TG_EINVAL, "tg_kick: negative n");
+  if (n > 0 && (!vel || !acc)) return fail(TG_EINVAL, "tg_kick: NULL pointer");
+  if (idx && !n_act) return fail(TG_EINVAL, "tg_kick: n_active required");
+  if (skip_k0 && !k) return fail(TG_EINVAL, "tg_kick: skip_at_k0 needs k");
+  if (!std::isfinite(dt)) return fail(TG_EINVAL, "tg_kick: dt not finite");
+  TG_HIP(launch_kick(c, vel, acc, n, idx, n_act, level, dt, k, skip_k0));
+  return TG_OK;
+}
+
+tg_status tg_drift(tg_ctx *c, double *pos, const double *vel, int64_t n, double dt) {
+  if (!c) return fail(TG_EINVAL, "tg_drift: NULL context");
+  if (n < 0) return fail(TG_EINVAL, "tg_drift: negative n");
+  if (n > 0 && (!pos || !vel)) return fail(TG_EINVAL, "tg_drift: NULL pointer");
+  if (!std::isfinite(dt)) return fail(TG_EINVAL, "tg_drift: dt not finite");
+  TG_HIP(launch_drift(c, pos, vel, n, dt));
+  return TG_OK;
+}
+
+tg_status tg_levels(tg_ctx *c, const double *acc, const double *t4e2, int64_t n,
+                    const int32_t *idx, const int32_t *n_act, double dt_max,
+                    int32_t nlev, const int64_t *k, uint8_t *level) {
+  if (!c) return fail(TG_EINVAL, "tg_levels: NULL context");
+  if (n < 0) return fail(TG_EINVAL, "tg_levels: negative n");
+  if (nlev < 1 || nlev > 30) return fail(TG_EINVAL, "tg_levels: nlev must be in 1..30");
+  if (!(dt_max > 0.0)) return fail(TG_EINVAL, "tg_levels: dt_max must be positive");
+  if (n > 0 && (!acc || !t4e2 || !level)) return fail(TG_EINVAL, "tg_levels: NULL pointer");
+  if (idx && !n_act) return fail(TG_EINVAL, "tg_levels: n_active required");
+  TG_HIP(launch_levels(c, acc, t4e2, n, idx, n_act, dt_max, nlev, k, level));
+  return TG_OK;
+}
+
+tg_status tg_active_set(tg_ctx *c, const uint8_t *level, int64_t n, int32_t nlev,
+                        const int64_t *k, int32_t k_add, int32_t *idx,
+                        int32_t *n_out) {
+  if (!c) return fail(TG_EINVAL, "tg_active_set: NULL context");
+  if (n < 0 || n > c->cfg.max_particles)
+    return fail(TG_EINVAL, "tg_active_set: n out of range");
+  if (nlev < 1 || nlev > 30) return fail(TG_EINVAL, "tg_active_set: nlev must be in 1..30");
+  if (!n_out || (n > 0 && (!level || !idx)))
+    return fail(TG_EINVAL, "tg_active_set: NULL pointer");
+  TG_HIP(launch_active_set(c, level, n, nlev, k, k_add, idx, n_out));
+  return TG_OK;
+}
+
+tg_status tg_counter_add(tg_ctx *c, int64_t *k, int64_t inc) {
+  if (!c || !k) return fail(TG_EINVAL, "tg_counter_add: NULL argument");
+  TG_HIP(launch_counter_add(c, k, inc));
+  return TG_OK;
+}
+
+tg_status tg_graph_begin(tg_ctx *c) {
+  if (!c) return fail(TG_EINVAL, "tg_graph_begin: NULL context");
+  if (c->capturing) return fail(TG_ESTATE, "tg_graph_begin: already capturing");
+  if (!c->stream) return fail(TG_ESTATE, "tg_graph_begin: needs a non-default stream");
+  TG_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  return TG_OK;
+}
+
+tg_status tg_graph_end(tg_ctx *c, tg_graph **out) {
+  if (!c || !out) return fail(TG_EINVAL, "tg_graph_end: NULL argument");
+  if (!c->capturing) return fail(TG_ESTATE, "tg_graph_end: not capturing");
+  c->capturing = false;
+  tg_graph *g = new tg_graph();
+  hipError_t e = hipStreamEndCapture(c->stream, &g->graph);
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return hip_fail(e, "tg_graph_end");
+  }
+  *out = g;
+  return TG_OK;
+}
+
+tg_status tg_graph_launch(tg_graph *g, void *stream) {
+  if (!g) return fail(TG_EINVAL, "tg_graph_launch: NULL graph");
+  TG_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return TG_OK;
+}
+
+void tg_graph_destroy(tg_graph *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+tg_status tg_get_tree(tg_ctx *c, tg_tree_view *v) {
+  if (!c || !v) return fail(TG_EINVAL, "tg_get_tree: NULL argument");
+  if (!c->have_tree) return fail(TG_ESTATE, "tg_get_tree: no tree");
+  if (c->capturing) return fail(TG_ESTATE, "tg_get_tree: during capture");
+  TreeCounters h;
+  TG_HIP(hipMemcpyAsync(&h, c->b.ctr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  TG_HIP(hipStreamSynchronize(c->stream));
+  Buffers &b = c->b;
+  v->n = c->n;
+  v->n_nodes = c->n ? h.n_nodes : 0;
+  v->n_groups = c->n ? h.n_groups : 0;
+  v->n_sys = c->S;
+  v->skeys = b.key[0];
+  v->perm = b.val[0];
+  v->level = b.level;
+  v->nchild = b.nchild;
+  v->first = b.first;
+  v->count = b.count;
+  v->child = b.child;
+  v->parent = b.parent;
+  v->cube = b.cube;
+  v->com = (const double *)b.com;
+  v->mom = b.mom;
+  v->groups = (const uint32_t *)b.groups;
+  return TG_OK;
+}
+
+tg_status tg_autotune(tg_ctx *c, const double *pos, const double *mass,
+                      int64_t n, const int64_t *sys_off, int32_t S, double eps,
+                      double theta, const int32_t *leaf_list,
+                      const int32_t *group_list, const int32_t *waves_list,
+                      int32_t repeats, int32_t best[3], double *best_ms) {
+  if (!c || !best || !best_ms) return fail(TG_EINVAL, "tg_autotune: NULL argument");
+  if (c->capturing) return fail(TG_ESTATE, "tg_autotune: during capture");
+  static const int32_t dl[] = {4, 8, 12, 16, 0};
+  static const int32_t dg[] = {16, 32, 48, 64, 0};
+  static const int32_t dw[] = {4, 8, 12, 0};
+  if (!leaf_list) leaf_list = dl;
+  if (!group_list) group_list = dg;
+  if (!waves_list) waves_list = dw;
+  if (repeats < 1) repeats = 3;
+  double *acc = nullptr;
+  TG_HIP(hipMalloc((void **)&acc, sizeof(double) * 3 * std::max<int64_t>(n, 1)));
+  hipEvent_t e0, e1;
+  TG_HIP(hipEventCreate(&e0));
+  TG_HIP(hipEventCreate(&e1));
+  double bms = 1e300;
+  int32_t b3[3] = {c->leaf_size, c->group_size, c->waves_per_cu};
+  tg_status st = TG_OK;
+  for (const int32_t *L = leaf_list; *L && st == TG_OK; ++L)
+    for (const int32_t *Gs = group_list; *Gs && st == TG_OK; ++Gs)
+      for (const int32_t *W = waves_list; *W && st == TG_OK; ++W) {
+        if (*W < 1 || *W > kMaxWavesPerCU) { st = fail(TG_EINVAL, "tg_autotune: bad waves"); break; }
+        if ((st = tg_set_sizes(c, *L, *Gs)) != TG_OK) break;
+        c->waves_per_cu = *W;
+        double tmin = 1e300;
+        for (int r = 0; r < repeats + 1 && st == TG_OK; ++r) {
+          (void)hipEventRecord(e0, c->stream);
+          st = tg_build_tree(c, pos, n, sys_off, S);
+          if (st == TG_OK) st = tg_compute_moments(c, mass);
+          if (st == TG_OK) st = tg_tree_forces(c, eps, theta, nullptr, nullptr, acc, nullptr);
+          (void)hipEventRecord(e1, c->stream);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (r > 0) tmin = std::min(tmin, (double)ms);   // first run warms up
+        }
+        uint32_t bits = 0;
+        if (st == TG_OK) st = tg_sync(c, &bits);
+        if (st == TG_OK && tmin < bms) {
+          bms = tmin;
+          b3[0] = *L; b3[1] = *Gs; b3[2] = *W;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(acc);
+  if (st != TG_OK) return st;
+  tg_set_sizes(c, b3[0], b3[1]);
+  c->waves_per_cu = b3[2];
+  best[0] = b3[0]; best[1] = b3[1]; best[2] = b3[2];
+  *best_ms = bms;
+  return TG_OK;
+}
+
+tg_status tg_sync(tg_ctx *c, uint32_t *bits) {
+  if (!c) return fail(TG_EINVAL, "tg_sync: NULL context");
+  if (c->capturing) return fail(TG_ESTATE, "tg_sync: during capture");
+  uint32_t h = 0;
+  TG_HIP(hipStreamSynchronize(c->stream));
+  TG_HIP(hipMemcpy(&h, c->b.err, sizeof(h), hipMemcpyDeviceToHost));
+  if (h) TG_HIP(hipMemset(c->b.err, 0, sizeof(uint32_t)));
+  if (bits) *bits = h;
+  if (h & (TG_ERR_NONFINITE | TG_ERR_MASS))
+    return fail(TG_EDATA, "device: non-finite position or non-positive mass");
+  if (h & (TG_ERR_NODES | TG_ERR_FRONTIER | TG_ERR_LISTS))
+    return fail(TG_ECAPACITY, "device: node, frontier or list capacity exceeded");
+  return TG_OK;
+}
+
+}  // extern "C"
