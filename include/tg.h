@@ -74,7 +74,7 @@ typedef struct {
   int32_t precision;       /* tg_precision of the walk and P2P/P2M sums */
   int64_t max_nodes;       /* octree node capacity; 0 = 2 * max_particles + 64 * max_systems */
   int32_t frontier_cap;    /* walk frontier entries per wave; 0 = 16384 */
-  int32_t waves_per_cu;    /* resident walk waves per compute unit; 0 = 8 */
+  int32_t waves_per_cu;    /* resident walk waves per compute unit; 0 = 16 */
   double G;                /* gravitational constant (paper units: 1) */
 } tg_config;
 

@@ -82,30 +82,55 @@ __global__ void k_direct(const double *__restrict__ spos, const double *__restri
   }
 }
 
-__global__ void k_direct_reduce(int64_t nt, int nchunks, int accumulate,
-                                const double *__restrict__ part,
-                                double *__restrict__ acc, double *__restrict__ pot) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt;
-       i += (int64_t)gridDim.x * blockDim.x) {
+// One block per target: each thread sums a strided subset of the chunks,
+// then the block combines the compensated pairs in a fixed tree order.
+__global__ __launch_bounds__(256) void k_direct_reduce(int64_t nt, int nchunks,
+                                                       int accumulate,
+                                                       const double *__restrict__ part,
+                                                       double *__restrict__ acc,
+                                                       double *__restrict__ pot) {
+  __shared__ double ss[4][256], sc[4][256];
+  for (int64_t i = blockIdx.x; i < nt; i += gridDim.x) {
     CSum r[4];
-    for (int c = 0; c < nchunks; ++c) {
+    for (int c = threadIdx.x; c < nchunks; c += 256) {
       const double *o = part + 8 * (size_t)(c * nt + i);
       for (int k = 0; k < 4; ++k) {
         r[k].add(o[2 * k]);
         r[k].add(o[2 * k + 1]);
       }
     }
-    if (accumulate) {
-      acc[3 * i] += r[0].get(); acc[3 * i + 1] += r[1].get(); acc[3 * i + 2] += r[2].get();
-      if (pot) pot[i] += r[3].get();
-    } else {
-      acc[3 * i] = r[0].get(); acc[3 * i + 1] = r[1].get(); acc[3 * i + 2] = r[2].get();
-      if (pot) pot[i] = r[3].get();
+    for (int k = 0; k < 4; ++k) { ss[k][threadIdx.x] = r[k].s; sc[k][threadIdx.x] = r[k].c; }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        for (int k = 0; k < 4; ++k) {
+          CSum x;
+          x.s = ss[k][threadIdx.x];
+          x.c = sc[k][threadIdx.x] + sc[k][threadIdx.x + h];
+          x.add(ss[k][threadIdx.x + h]);
+          ss[k][threadIdx.x] = x.s;
+          sc[k][threadIdx.x] = x.c;
+        }
+      }
+      __syncthreads();
     }
+    if (threadIdx.x == 0) {
+      const double v0 = ss[0][0] + sc[0][0], v1 = ss[1][0] + sc[1][0];
+      const double v2 = ss[2][0] + sc[2][0], v3 = ss[3][0] + sc[3][0];
+      if (accumulate) {
+        acc[3 * i] += v0; acc[3 * i + 1] += v1; acc[3 * i + 2] += v2;
+        if (pot) pot[i] += v3;
+      } else {
+        acc[3 * i] = v0; acc[3 * i + 1] = v1; acc[3 * i + 2] = v2;
+        if (pot) pot[i] = v3;
+      }
+    }
+    __syncthreads();
   }
 }
 
-hipError_t launch_direct(tg_ctx *c, const double *spos, const double *sm,
+hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
+                         const double *sm,
                          const double *seps, int64_t ns, const double *tpos,
                          const double *teps, int64_t nt, int nseg,
                          int64_t max_seg_src, int self_pairs, int accumulate,
@@ -126,11 +151,11 @@ hipError_t launch_direct(tg_ctx *c, const double *spos, const double *sm,
   const int64_t total = nt * nchunks;
   const int g = (int)std::min<int64_t>((total + 255) / 256, 8192);
   hipLaunchKernelGGL(k_direct, dim3(g), dim3(256), 0, c->stream, spos, sm, seps,
-                     tpos, teps, nt, c->b.dseg, c->b.dseg + (nseg + 1), nseg,
+                     tpos, teps, nt, dseg, dseg + (nseg + 1), nseg,
                      chunk, (int)nchunks, self_pairs, accumulate, acc, pot,
                      c->b.dpart);
   if (nchunks > 1) {
-    const int g2 = (int)std::min<int64_t>((nt + 255) / 256, 4096);
+    const int g2 = (int)std::min<int64_t>(nt, 4096);
     hipLaunchKernelGGL(k_direct_reduce, dim3(g2), dim3(256), 0, c->stream, nt,
                        (int)nchunks, accumulate, c->b.dpart, acc, pot);
   }

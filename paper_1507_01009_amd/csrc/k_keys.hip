@@ -63,29 +63,41 @@ __global__ __launch_bounds__(256) void k_cube_part(const double *__restrict__ po
   }
 }
 
-// One thread per system: lo = coordinate minimum, L = largest extent (1 if
+// One block per system: lo = coordinate minimum, L = largest extent (1 if
 // every particle coincides or the system is empty).
-__global__ void k_cube_final(const double *__restrict__ part,
-                             const uint32_t *__restrict__ sys_tile0, int S,
-                             double *__restrict__ cube) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  uint32_t a = sys_tile0[s], b = sys_tile0[s + 1];
-  double lo[3] = {0.0, 0.0, 0.0}, L = 1.0;
-  if (b > a) {
-    double hi[3];
-    for (int k = 0; k < 3; ++k) { lo[k] = part[6 * (size_t)a + k]; hi[k] = part[6 * (size_t)a + 3 + k]; }
-    for (uint32_t t = a + 1; t < b; ++t)
+__global__ __launch_bounds__(256) void k_cube_final(const double *__restrict__ part,
+                                                    const uint32_t *__restrict__ sys_tile0,
+                                                    double *__restrict__ cube) {
+  __shared__ double sh[4][6];
+  const int s = blockIdx.x;
+  const uint32_t a = sys_tile0[s], b = sys_tile0[s + 1];
+  double lo[3] = {INFINITY, INFINITY, INFINITY};
+  double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (uint32_t t = a + threadIdx.x; t < b; t += 256u)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fmin(lo[k], part[6 * (size_t)t + k]);
+      hi[k] = fmax(hi[k], part[6 * (size_t)t + 3 + k]);
+    }
+  const unsigned lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
+  if (lane == 0)
+    for (int k = 0; k < 3; ++k) { sh[w][k] = lo[k]; sh[w][3 + k] = hi[k]; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double L = 1.0, l3[3] = {0.0, 0.0, 0.0};
+    if (b > a) {
+      double h3[3];
       for (int k = 0; k < 3; ++k) {
-        lo[k] = fmin(lo[k], part[6 * (size_t)t + k]);
-        hi[k] = fmax(hi[k], part[6 * (size_t)t + 3 + k]);
+        l3[k] = fmin(fmin(sh[0][k], sh[1][k]), fmin(sh[2][k], sh[3][k]));
+        h3[k] = fmax(fmax(sh[0][3 + k], sh[1][3 + k]), fmax(sh[2][3 + k], sh[3][3 + k]));
       }
-    L = 0.0;
-    for (int k = 0; k < 3; ++k) L = fmax(L, hi[k] - lo[k]);
-    if (L == 0.0) L = 1.0;
+      L = 0.0;
+      for (int k = 0; k < 3; ++k) L = fmax(L, h3[k] - l3[k]);
+      if (L == 0.0) L = 1.0;
+    }
+    cube[4 * s + 0] = l3[0]; cube[4 * s + 1] = l3[1]; cube[4 * s + 2] = l3[2];
+    cube[4 * s + 3] = L;
   }
-  cube[4 * s + 0] = lo[0]; cube[4 * s + 1] = lo[1]; cube[4 * s + 2] = lo[2];
-  cube[4 * s + 3] = L;
 }
 
 // Spread the low 21 bits of v so that bit j lands on bit 3j.
@@ -256,8 +268,8 @@ hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
   if (nt > 0)
     hipLaunchKernelGGL(k_cube_part, dim3(nt), dim3(256), 0, c->stream, pos,
                        b.tiles, b.cube_part, b.err);
-  hipLaunchKernelGGL(k_cube_final, dim3((c->S + 63) / 64), dim3(64), 0,
-                     c->stream, b.cube_part, b.sys_tile0, c->S, b.cube);
+  hipLaunchKernelGGL(k_cube_final, dim3(c->S), dim3(256), 0, c->stream,
+                     b.cube_part, b.sys_tile0, b.cube);
   if (nt > 0)
     hipLaunchKernelGGL(k_keys, dim3(nt), dim3(256), 0, c->stream, pos, b.tiles,
                        b.sys_tile0, c->S, b.cube, b.key[0], b.val[0]);

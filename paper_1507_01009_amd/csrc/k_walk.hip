@@ -23,17 +23,20 @@
 // in float and folded into a (hi, lo) float pair with an error-free
 // TwoSum; the result is hi + lo in double.
 //
-// Flops per interaction (FMA = 2; the rsqrt is counted apart):
-//   P2P 19: 3 sub, 6 for r^2 + eps^2, 3 for m D1, m D3, 6 for the three
+// Flops per interaction as written in p2p_term / p2m_term (FMA = 2; the
+// rsqrt and, in FP64, its refinement are not counted):
+//   P2P 19: 3 sub, 6 for r^2 + eps^2, 3 for m D1 and m D3, 6 for the three
 //          accelerations, 1 for the potential.
-//   P2M 61: 3 sub, 6 for r^2 + eps^2, 4 for D2..D7, 15 for S x, 5 for x.Sx,
-//          3 for W, 7 for the radial coefficient, 1 for 3 D5, 12 for the
-//          accelerations, 5 for the potential.
+//   P2M 58: 3 sub, 6 for r^2 + eps^2, 4 for D2..D7, 15 for S x, 5 for x.S.x,
+//          2 for W, 6 for the radial coefficient, 12 for the accelerations,
+//          5 for the potential (the 3S and tr S of a cell are formed once
+//          per tile, not per interaction).
 #include "tg_internal.h"
 
 namespace tg {
 
-constexpr int kQCap = 64 + 64 * kMaxLeaf;   // P2P particle queue (LDS)
+constexpr int kQCap = 64 + 64 * 8;          // P2P particle queue (LDS); larger leaves take the slow path
+constexpr int kTile = 128;                  // source tile: 64 live entries + 64 zero-mass pads
 constexpr int kMCap = 128;                  // P2M cell list (LDS)
 
 struct WalkArgs {
@@ -119,15 +122,73 @@ __device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float x) {
   lo += err;
 }
 
+// ---------------------------------------------------------------- terms
+template <class R> struct Vec4;
+template <> struct Vec4<float> { using T = float4; };
+template <> struct Vec4<double> { using T = double4; };
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return rsqrt_dp(x); }
+
+// Softened quadrupole term.  Cell: a = {c, M}, b = {3Sxx, 3Syy, 3Szz, T},
+// c = {3Sxy, 3Sxz, 3Syz, -}, with x = target - c:
+//   W = 3 x.S.x - T r^2   (= x.Q.x - T eps^2 since r^2 = |x|^2 + eps^2)
+//   a -= (M D3 + T D5 + 2.5 D7 W) x - 3 D5 S x,  phi -= M D1 + 0.5 D5 W
+// which is a = -M D3 x + D5 Q x - 2.5 D7 W x with Q = 3S - T I.
+template <class R>
+__device__ __forceinline__ void p2m_term(typename Vec4<R>::T a, typename Vec4<R>::T b,
+                                         typename Vec4<R>::T c, R tx, R ty, R tz, R e2,
+                                         R &ax, R &ay, R &az, R &ph) {
+  const R x = tx - a.x, y = ty - a.y, z = tz - a.z;
+  const R r2 = fma(z, z, fma(y, y, fma(x, x, e2)));
+  const R D1 = rsq(r2);
+  const R D2 = D1 * D1, D3 = D1 * D2, D5 = D3 * D2, D7 = D5 * D2;
+  const R Sx = fma(c.y, z, fma(c.x, y, b.x * x));
+  const R Sy = fma(c.z, z, fma(b.y, y, c.x * x));
+  const R Sz = fma(b.z, z, fma(c.z, y, c.y * x));
+  const R xSx = fma(z, Sz, fma(y, Sy, x * Sx));
+  const R W = fma(-b.w, r2, xSx);
+  const R C = fma(R(2.5) * D7, W, fma(b.w, D5, a.w * D3));
+  ax = fma(D5, Sx, fma(-C, x, ax));
+  ay = fma(D5, Sy, fma(-C, y, ay));
+  az = fma(D5, Sz, fma(-C, z, az));
+  ph -= fma(R(0.5) * D5, W, a.w * D1);
+}
+
+// Softened particle term, source s = {position, m}.
+template <class R>
+__device__ __forceinline__ void p2p_term(typename Vec4<R>::T s, R tx, R ty, R tz, R e2,
+                                         R &ax, R &ay, R &az, R &ph) {
+  const R dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
+  const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+  const R D1 = rsq(r2);
+  const R mD1 = s.w * D1;
+  const R mD3 = mD1 * (D1 * D1);
+  ax = fma(-mD3, dx, ax);
+  ay = fma(-mD3, dy, ay);
+  az = fma(-mD3, dz, az);
+  ph -= mD1;
+}
+
 // ---------------------------------------------------------------- tiles
 struct P2MTileD { double4 a, b, c; };   // {cx,cy,cz,M} {Sxx,Syy,Szz,T} {Sxy,Sxz,Syz,0}
 struct P2MTileF { float4 a, b, c; };
 
-union __align__(16) TileMem {
-  P2MTileD md[64];
-  double4 pd[64];
-  P2MTileF mf[64];
-  float4 pf[64];
+// Source tiles in LDS.  Entries [k, 128) of a tile holding k sources have
+// zero mass, so every lane runs the same trip count with no masking: lane
+// slice s reads entries s, s + slices, ...  The P2M half [64, 128) is zeroed
+// once per kernel (nothing else overlaps it); the P2P half is rewritten per
+// flush because the P2M entries overlap it.
+template <bool kMixed> union TileMem;
+template <> union __align__(16) TileMem<true> {
+  P2MTileF m[kTile];
+  float4 p[kTile];
+  double red[256];
+};
+template <> union __align__(16) TileMem<false> {
+  P2MTileD m[kTile];
+  double4 p[kTile];
+  double red[256];
 };
 
 template <bool kMixed>
@@ -147,7 +208,7 @@ template <bool kMixed>
 struct ForceSink {
   uint32_t *s_m;
   uint32_t *s_q;
-  TileMem *tile;
+  TileMem<kMixed> *tile;
   uint32_t nm, nq;
   unsigned long long cells, parts;   // wave-uniform totals
   int my_s, slices;
@@ -168,66 +229,50 @@ struct ForceSink {
 
   __device__ void flush_p2m(const WalkArgs &A, const uint32_t *list, int k) {
     const unsigned lane = lane_id();
-    if ((int)lane < k) {
-      const uint32_t v = list[lane];
-      const double4 c = A.com[v];
-      const double *o = A.mom + 8 * (size_t)v;
-      const double T = o[1] + o[2] + o[3];
-      if constexpr (kMixed) {
-        tile->mf[lane].a = make_float4((float)(c.x - cgx), (float)(c.y - cgy),
-                                       (float)(c.z - cgz), (float)o[0]);
-        tile->mf[lane].b = make_float4((float)o[1], (float)o[2], (float)o[3], (float)T);
-        tile->mf[lane].c = make_float4((float)o[4], (float)o[5], (float)o[6], 0.0f);
-      } else {
-        tile->md[lane].a = make_double4(c.x, c.y, c.z, o[0]);
-        tile->md[lane].b = make_double4(o[1], o[2], o[3], T);
-        tile->md[lane].c = make_double4(o[4], o[5], o[6], 0.0);
+    // tile: {com - c, M} {3Sxx, 3Syy, 3Szz, T} {3Sxy, 3Sxz, 3Syz, 0}; lanes
+    // past k write zero-mass entries
+    if constexpr (kMixed) {
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
+      if ((int)lane < k) {
+        const uint32_t v = list[lane];
+        const double4 cm = A.com[v];
+        const double *o = A.mom + 8 * (size_t)v;
+        a = make_float4((float)(cm.x - cgx), (float)(cm.y - cgy), (float)(cm.z - cgz),
+                        (float)o[0]);
+        b = make_float4((float)(3.0 * o[1]), (float)(3.0 * o[2]), (float)(3.0 * o[3]),
+                        (float)(o[1] + o[2] + o[3]));
+        c = make_float4((float)(3.0 * o[4]), (float)(3.0 * o[5]), (float)(3.0 * o[6]), 0.f);
       }
+      tile->m[lane].a = a; tile->m[lane].b = b; tile->m[lane].c = c;
+    } else {
+      double4 a = make_double4(0., 0., 0., 0.), b = a, c = a;
+      if ((int)lane < k) {
+        const uint32_t v = list[lane];
+        const double4 cm = A.com[v];
+        const double *o = A.mom + 8 * (size_t)v;
+        a = make_double4(cm.x, cm.y, cm.z, o[0]);
+        b = make_double4(3.0 * o[1], 3.0 * o[2], 3.0 * o[3], o[1] + o[2] + o[3]);
+        c = make_double4(3.0 * o[4], 3.0 * o[5], 3.0 * o[6], 0.0);
+      }
+      tile->m[lane].a = a; tile->m[lane].b = b; tile->m[lane].c = c;
     }
     __syncthreads();
+    const int trips = (k + slices - 1) / slices;
     if constexpr (kMixed) {
       float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
 #pragma unroll 2
-      for (int j = my_s; j < k; j += slices) {
-        const P2MTileF s = tile->mf[j];
-        const float x = t.fx - s.a.x, y = t.fy - s.a.y, z = t.fz - s.a.z;
-        const float r2 = x * x + y * y + z * z + eps2f;
-        const float D1 = __builtin_amdgcn_rsqf(r2);
-        const float D2 = D1 * D1, D3 = D1 * D2, D5 = D3 * D2, D7 = D5 * D2;
-        const float Sx = s.b.x * x + s.c.x * y + s.c.y * z;
-        const float Sy = s.c.x * x + s.b.y * y + s.c.z * z;
-        const float Sz = s.c.y * x + s.c.z * y + s.b.z * z;
-        const float xSx = x * Sx + y * Sy + z * Sz;
-        const float W = 3.0f * xSx - s.b.w * r2;
-        const float A = -s.a.w * D3 - s.b.w * D5 - 2.5f * D7 * W;
-        const float B = 3.0f * D5;
-        ax += A * x + B * Sx;
-        ay += A * y + B * Sy;
-        az += A * z + B * Sz;
-        ph += -s.a.w * D1 - 0.5f * D5 * W;
+      for (int it = 0; it < trips; ++it) {
+        const P2MTileF &e = tile->m[my_s + it * slices];
+        p2m_term<float>(e.a, e.b, e.c, t.fx, t.fy, t.fz, eps2f, ax, ay, az, ph);
       }
       t.tax += ax; t.tay += ay; t.taz += az; t.tph += ph;
       fold();
     } else {
       double ax = 0., ay = 0., az = 0., ph = 0.;
 #pragma unroll 2
-      for (int j = my_s; j < k; j += slices) {
-        const P2MTileD s = tile->md[j];
-        const double x = t.x - s.a.x, y = t.y - s.a.y, z = t.z - s.a.z;
-        const double r2 = x * x + y * y + z * z + eps2;
-        const double D1 = rsqrt_dp(r2);
-        const double D2 = D1 * D1, D3 = D1 * D2, D5 = D3 * D2, D7 = D5 * D2;
-        const double Sx = s.b.x * x + s.c.x * y + s.c.y * z;
-        const double Sy = s.c.x * x + s.b.y * y + s.c.z * z;
-        const double Sz = s.c.y * x + s.c.z * y + s.b.z * z;
-        const double xSx = x * Sx + y * Sy + z * Sz;
-        const double W = 3.0 * xSx - s.b.w * r2;
-        const double A = -s.a.w * D3 - s.b.w * D5 - 2.5 * D7 * W;
-        const double B = 3.0 * D5;
-        ax += A * x + B * Sx;
-        ay += A * y + B * Sy;
-        az += A * z + B * Sz;
-        ph += -s.a.w * D1 - 0.5 * D5 * W;
+      for (int it = 0; it < trips; ++it) {
+        const P2MTileD &e = tile->m[my_s + it * slices];
+        p2m_term<double>(e.a, e.b, e.c, t.x, t.y, t.z, eps2, ax, ay, az, ph);
       }
       t.ax += ax; t.ay += ay; t.az += az; t.ph += ph;
     }
@@ -236,43 +281,34 @@ struct ForceSink {
 
   __device__ void flush_p2p(const WalkArgs &A, const uint32_t *list, int k) {
     const unsigned lane = lane_id();
-    if ((int)lane < k) {
-      const double4 p = A.spart[list[lane]];
-      if constexpr (kMixed)
-        tile->pf[lane] = make_float4((float)(p.x - cgx), (float)(p.y - cgy),
-                                     (float)(p.z - cgz), (float)p.w);
-      else
-        tile->pd[lane] = p;
+    if constexpr (kMixed) {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if ((int)lane < k) {
+        const double4 p = A.spart[list[lane]];
+        v = make_float4((float)(p.x - cgx), (float)(p.y - cgy), (float)(p.z - cgz), (float)p.w);
+      }
+      tile->p[lane] = v;
+      tile->p[64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      double4 v = make_double4(0., 0., 0., 0.);
+      if ((int)lane < k) v = A.spart[list[lane]];
+      tile->p[lane] = v;
+      tile->p[64 + lane] = make_double4(0., 0., 0., 0.);
     }
     __syncthreads();
+    const int trips = (k + slices - 1) / slices;
     if constexpr (kMixed) {
       float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
 #pragma unroll 4
-      for (int j = my_s; j < k; j += slices) {
-        const float4 s = tile->pf[j];
-        const float dx = t.fx - s.x, dy = t.fy - s.y, dz = t.fz - s.z;
-        const float r2 = dx * dx + dy * dy + dz * dz + eps2f;
-        const float D1 = __builtin_amdgcn_rsqf(r2);
-        const float mD1 = s.w * D1;
-        const float mD3 = mD1 * D1 * D1;
-        ax -= mD3 * dx; ay -= mD3 * dy; az -= mD3 * dz;
-        ph -= mD1;
-      }
+      for (int it = 0; it < trips; ++it)
+        p2p_term<float>(tile->p[my_s + it * slices], t.fx, t.fy, t.fz, eps2f, ax, ay, az, ph);
       t.tax += ax; t.tay += ay; t.taz += az; t.tph += ph;
       fold();
     } else {
       double ax = 0., ay = 0., az = 0., ph = 0.;
 #pragma unroll 4
-      for (int j = my_s; j < k; j += slices) {
-        const double4 s = tile->pd[j];
-        const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
-        const double r2 = dx * dx + dy * dy + dz * dz + eps2;
-        const double D1 = rsqrt_dp(r2);
-        const double mD1 = s.w * D1;
-        const double mD3 = mD1 * D1 * D1;
-        ax -= mD3 * dx; ay -= mD3 * dy; az -= mD3 * dz;
-        ph -= mD1;
-      }
+      for (int it = 0; it < trips; ++it)
+        p2p_term<double>(tile->p[my_s + it * slices], t.x, t.y, t.z, eps2, ax, ay, az, ph);
       t.ax += ax; t.ay += ay; t.az += az; t.ph += ph;
     }
     __syncthreads();
@@ -422,24 +458,48 @@ __device__ bool traverse(const WalkArgs &A, Sink &sink, uint32_t root,
   return true;
 }
 
-__device__ __forceinline__ uint32_t next_group(TreeCounters *ctr) {
-  uint32_t g = 0;
-  if (lane_id() == 0) g = atomicAdd(&ctr->queue, 1u);
-  return __shfl(g, 0, 64);
-}
+// Work distribution aware of the 8 XCDs (each with its own L2): queue q
+// holds the contiguous, hence spatially coherent, active groups
+// [q G / 8, (q + 1) G / 8); workgroups are dispatched to the XCDs round
+// robin, so block b drains queue b mod 8 first and then helps the others.
+struct GroupQueue {
+  uint32_t q, tried;
+  __device__ explicit GroupQueue(uint32_t home) : q(home & 7u), tried(0) {}
+  __device__ uint32_t next(TreeCounters *ctr, uint32_t G) {
+    while (tried < 8u) {
+      const uint32_t lo = (uint32_t)(((uint64_t)q * G) >> 3);
+      const uint32_t hi = (uint32_t)(((uint64_t)(q + 1u) * G) >> 3);
+      uint32_t g = 0;
+      if (lane_id() == 0) g = atomicAdd(&ctr->xq[q], 1u);
+      g = (uint32_t)__shfl((int)g, 0, 64);
+      if (lo + g < hi) return lo + g;
+      q = (q + 1u) & 7u;
+      ++tried;
+    }
+    return G;
+  }
+};
 
 // ------------------------------------------------------------ force kernel
 template <bool kMixed>
-__global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_walk_forces(WalkArgs A) {
   __shared__ uint32_t s_tgt[64];
   __shared__ uint32_t s_m[kMCap];
   __shared__ uint32_t s_q[kQCap];
-  __shared__ TileMem tile;
+  __shared__ TileMem<kMixed> tile;
   const unsigned lane = lane_id();
   const uint32_t n_groups = A.ctr->n_active_groups;
   unsigned long long tot_p2p = 0, tot_p2m = 0, tot_t = 0, tot_g = 0;
+  // zero-mass pads of the P2M tile (never overwritten afterwards)
+  if constexpr (kMixed) {
+    tile.m[64 + lane].a = tile.m[64 + lane].b = tile.m[64 + lane].c = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    tile.m[64 + lane].a = tile.m[64 + lane].b = tile.m[64 + lane].c = make_double4(0., 0., 0., 0.);
+  }
+  __syncthreads();
+  GroupQueue Q(blockIdx.x);
   for (;;) {
-    const uint32_t gi = next_group(A.ctr);
+    const uint32_t gi = Q.next(A.ctr, n_groups);
     if (gi >= n_groups) break;
     const uint32_t g = A.alist[gi];
     const uint4 gr = A.groups[g];
@@ -453,17 +513,18 @@ __global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
     const int nt = __popcll(amask);
     __syncthreads();
     if (nt == 0) continue;   // cannot happen for a listed group; keeps s_tgt reads defined
-    int lg = 0;
-    while ((1 << lg) < nt) ++lg;
-    const int tpw = 1 << lg;
+    // lanes = target x source slice: slices = floor(64 / nt) copies of the
+    // target set, slice s taking sources s, s + slices, ...
+    const int slices = 64 / nt;
     ForceSink<kMixed> S;
     S.s_m = s_m; S.s_q = s_q; S.tile = &tile;
     S.nm = 0; S.nq = 0; S.cells = 0; S.parts = 0;
-    S.slices = 64 >> lg;
-    S.my_s = (int)(lane >> lg);
-    const int my_t = (int)(lane & (tpw - 1));
-    const bool has_t = my_t < nt;
-    const uint32_t r_t = s_tgt[has_t ? my_t : 0];
+    S.slices = slices;
+    const int my_t = (int)lane % nt;
+    const int sl = (int)lane / nt;
+    S.my_s = sl < slices ? sl : 64;          // idle lanes take no sources
+    const bool has_t = sl < slices;
+    const uint32_t r_t = s_tgt[my_t];
     const double4 p = A.spart[r_t];
     S.cgx = 0.5 * (lo[0] + hi[0]);
     S.cgy = 0.5 * (lo[1] + hi[1]);
@@ -488,13 +549,16 @@ __global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
       ax = S.t.ax; ay = S.t.ay; az = S.t.az; ph = S.t.ph;
       self = p.w * rsqrt_dp(A.eps2);
     }
-    for (int o = tpw; o < 64; o <<= 1) {
-      ax += __shfl_xor(ax, o, 64);
-      ay += __shfl_xor(ay, o, 64);
-      az += __shfl_xor(az, o, 64);
-      ph += __shfl_xor(ph, o, 64);
-    }
-    if (S.my_s == 0 && has_t) {
+    // sum the slices of each target in slice order (deterministic)
+    double *red = tile.red;
+    red[4 * lane + 0] = ax; red[4 * lane + 1] = ay;
+    red[4 * lane + 2] = az; red[4 * lane + 3] = ph;
+    __syncthreads();
+    if ((int)lane < nt) {
+      for (int q = 1; q < slices; ++q) {
+        const double *o = red + 4 * (q * nt + (int)lane);
+        ax += o[0]; ay += o[1]; az += o[2]; ph += o[3];
+      }
       const uint32_t orig = A.perm[r_t];
       const double nanv = __longlong_as_double(0x7ff8000000000000ll);
       A.acc[3 * (size_t)orig + 0] = ok ? A.G * ax : nanv;
@@ -502,6 +566,7 @@ __global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
       A.acc[3 * (size_t)orig + 2] = ok ? A.G * az : nanv;
       if (A.pot) A.pot[orig] = ok ? A.G * (ph + self) : nanv;
     }
+    (void)has_t;
     tot_p2m += S.cells * (unsigned long long)nt;
     tot_p2p += S.parts * (unsigned long long)nt - (unsigned long long)nt;
     tot_t += (unsigned long long)nt;
@@ -526,8 +591,9 @@ __global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
 template <int kPass>
 __global__ __launch_bounds__(64) void k_walk_lists(WalkArgs A) {
   const uint32_t n_groups = A.ctr->n_active_groups;
+  GroupQueue Q(blockIdx.x);
   for (;;) {
-    const uint32_t gi = next_group(A.ctr);
+    const uint32_t gi = Q.next(A.ctr, n_groups);
     if (gi >= n_groups) break;
     const uint32_t g = A.alist[gi];
     const uint4 gr = A.groups[g];
@@ -635,8 +701,8 @@ hipError_t launch_counts_reset(tg_ctx *c) {
 }
 
 __global__ void k_walk_reset(TreeCounters *ctr) {
+  if (threadIdx.x < 8) ctr->xq[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
-    ctr->queue = 0;
     ctr->n_p2p = 0;
     ctr->n_p2m = 0;
     ctr->n_targets = 0;

@@ -30,7 +30,10 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per tile
 constexpr int kScanBlocks = 256;
+constexpr int kLevelBlocks = 1024;                // octree level kernels (multiple of 256)
 constexpr int kMaxWavesPerCU = 16;
+constexpr int kSegSlots = 8;                     // cached direct-sum segment tables
+constexpr int kSegSlotLen = 2 * (kMaxSys + 1);
 
 // A tile of consecutive particles inside one system (sort, cube, keys).
 struct Tile {
@@ -47,7 +50,7 @@ struct TreeCounters {
   uint32_t n_groups;
   uint32_t n_active_groups;
   uint32_t overflow;         // node capacity exceeded during this build
-  uint32_t queue;            // walk work counter
+  uint32_t xq[8];            // walk work counters, one queue per XCD
   uint32_t pad[3];
   unsigned long long n_p2p, n_p2m, n_targets, n_walked;      // last walk
   unsigned long long cum_p2p, cum_p2m, cum_targets, cum_walked;  // since reset
@@ -74,6 +77,9 @@ struct Buffers {
   double4 *com = nullptr;
   double *mom = nullptr;          // [nodes][8]
   uint32_t *lvl_tmp = nullptr;    // [nodes] per-level child counts
+  uint32_t *lvl_bnd = nullptr;    // [nodes][8] octant starts of splitting nodes
+  uint32_t *lvl_part = nullptr;   // [kLevelBlocks] per-block child counts / scan
+  uint8_t *lcp = nullptr;         // [N + 16] common leading digits with predecessor
   // groups
   uint32_t *gflag = nullptr;      // [N + 1] group starts / scan
   uint4 *groups = nullptr;        // [N]
@@ -92,7 +98,7 @@ struct Buffers {
   uint32_t *err = nullptr;        // device error bits
   // direct sums
   double *dpart = nullptr;        // partial sums for few-target direct sums
-  int64_t *dseg = nullptr;        // [2 * (S+1)] segment offsets
+  int64_t *dseg = nullptr;        // [kSegSlots][2 * (S+1)] segment offsets
   int64_t dpart_cap = 0;
 };
 
@@ -118,7 +124,8 @@ struct tg_ctx {
   double prof_ms = 0.0;
   int64_t prof_n = 0;
   std::vector<int64_t> sysoff_host;   // layout of the last build
-  std::vector<int64_t> dseg_host;     // segment table of the last direct sum
+  std::vector<std::vector<int64_t>> dseg_host;  // tables held in the device slots
+  int dseg_next = 0;
   tg::Buffers b;
 };
 
@@ -172,7 +179,8 @@ hipError_t launch_walk_lists(tg_ctx *c, double theta, int pass,
                              int64_t cap_ids);
 
 // k_direct.hip
-hipError_t launch_direct(tg_ctx *c, const double *spos, const double *sm,
+hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
+                         const double *sm,
                          const double *seps, int64_t ns, const double *tpos,
                          const double *teps, int64_t nt, int nseg,
                          int64_t max_seg_src, int self_pairs, int accumulate,

@@ -64,7 +64,7 @@ static void free_all(tg_ctx *c) {
   void *ptrs[] = {b.sysoff, b.cube, b.cube_part, b.tiles, b.sys_tile0,
                   b.root_of, b.key[0], b.key[1], b.val[0], b.val[1], b.hist,
                   b.rank, b.spart, b.level, b.nchild, b.first, b.count,
-                  b.child, b.parent, b.nsys, b.com, b.mom, b.lvl_tmp, b.gflag,
+                  b.child, b.parent, b.nsys, b.com, b.mom, b.lvl_tmp, b.lvl_bnd, b.lvl_part, b.lcp, b.gflag,
                   b.groups, b.aflag, b.alist, b.abox, b.sact, b.frontier,
                   b.wl_count, b.wl_off, b.scan_part, b.scan_total, b.ctr,
                   b.err, b.dpart, b.dseg};
@@ -95,7 +95,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
     return fail(TG_EINVAL, "tg_create: max_nodes out of range");
   if (cfg.frontier_cap == 0) cfg.frontier_cap = 16384;
   if (cfg.frontier_cap < 64) return fail(TG_EINVAL, "tg_create: frontier_cap < 64");
-  if (cfg.waves_per_cu == 0) cfg.waves_per_cu = 8;
+  if (cfg.waves_per_cu == 0) cfg.waves_per_cu = 16;
   if (cfg.waves_per_cu < 1 || cfg.waves_per_cu > kMaxWavesPerCU)
     return fail(TG_EINVAL, "tg_create: waves_per_cu must be in 1..16");
 
@@ -137,6 +137,9 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.parent, NN)); A(dalloc(&b.nsys, NN));
   A(dalloc(&b.com, NN)); A(dalloc(&b.mom, 8 * NN));
   A(dalloc(&b.lvl_tmp, NN));
+  A(dalloc(&b.lvl_bnd, 8 * NN));
+  A(dalloc(&b.lvl_part, kLevelBlocks));
+  A(dalloc(&b.lcp, N + 64));
   A(dalloc(&b.gflag, N + 1));
   A(dalloc(&b.groups, N));
   A(dalloc(&b.aflag, N + 1));
@@ -151,7 +154,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.ctr, 1));
   A(dalloc(&b.err, 1));
   A(dalloc(&b.dpart, b.dpart_cap));
-  A(dalloc(&b.dseg, 2 * (kMaxSys + 1)));
+  A(dalloc(&b.dseg, kSegSlots * kSegSlotLen));
   if (a != hipSuccess) {
     free_all(c);
     delete c;
@@ -465,17 +468,31 @@ tg_status tg_direct_fp64(tg_ctx *c, const double *spos, const double *sm,
   }
   int64_t max_src = 0;
   for (int s = 0; s < ns_eff; ++s) max_src = std::max(max_src, seg[s + 1] - seg[s]);
-  // segment table lives in a small device buffer; re-upload only if changed
-  if (seg != c->dseg_host) {
+  // segment tables live in a few device slots keyed by their contents, so
+  // a step that uses several tables can still be graph-captured once each
+  // table has been seen eagerly
+  int slot = -1;
+  for (int k = 0; k < (int)c->dseg_host.size(); ++k)
+    if (c->dseg_host[k] == seg) slot = k;
+  if (slot < 0) {
     if (c->capturing)
-      return fail(TG_ESTATE, "tg_direct_fp64: segment layout changed during capture");
-    TG_HIP(hipMemcpyAsync(c->b.dseg, seg.data(), sizeof(int64_t) * seg.size(),
-                          hipMemcpyHostToDevice, c->stream));
+      return fail(TG_ESTATE, "tg_direct_fp64: new segment layout during capture");
+    if ((int)c->dseg_host.size() < kSegSlots) {
+      c->dseg_host.push_back(seg);
+      slot = (int)c->dseg_host.size() - 1;
+    } else {
+      slot = c->dseg_next;
+      c->dseg_next = (c->dseg_next + 1) % kSegSlots;
+      c->dseg_host[slot] = seg;
+    }
+    TG_HIP(hipMemcpyAsync(c->b.dseg + slot * kSegSlotLen, seg.data(),
+                          sizeof(int64_t) * seg.size(), hipMemcpyHostToDevice,
+                          c->stream));
     TG_HIP(hipStreamSynchronize(c->stream));
-    c->dseg_host = seg;
   }
-  TG_HIP(launch_direct(c, spos, sm, seps, ns, tpos, teps, nt, ns_eff, max_src,
-                       self_pairs, accumulate, acc, pot));
+  const int64_t *dseg = c->b.dseg + slot * kSegSlotLen;
+  TG_HIP(launch_direct(c, dseg, spos, sm, seps, ns, tpos, teps, nt, ns_eff,
+                       max_src, self_pairs, accumulate, acc, pot));
   return TG_OK;
 }
 
