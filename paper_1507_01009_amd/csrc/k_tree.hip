@@ -103,6 +103,7 @@ __global__ __launch_bounds__(256) void k_roots(const int64_t *__restrict__ sysof
     ctr->lvl[0] = 0;
     for (int l = 1; l < kLevels + 2; ++l) ctr->lvl[l] = tot;
     ctr->overflow = 0;
+    ctr->big_n = 0;
     ctr->n_nodes = tot;
   }
 }
@@ -143,23 +144,22 @@ __device__ __forceinline__ uint64_t byte_window(uint32_t p, uint32_t lo, uint32_
 // counts.  The children of a node [f, e) start at f and at every i in
 // (f, e) with d[i] == l, stored in order: bnd[8 k + j] = start of child j
 // (j >= 1).  Nodes of at most 512 particles: one lane scans their d bytes
-// eight words (64 bytes) per batch with the loads of a batch independent; up
-// to 4096: the wave scans the words coalesced; bigger nodes (top levels):
-// the wave narrows the octant starts on the keys (wave_octants).
+// eight words (64 bytes) per batch with the loads of a batch independent;
+// bigger ones are listed for k_level_big.
 __global__ __launch_bounds__(256) void k_level_count(int l, int nleaf,
-                                                     const TreeCounters *ctr,
+                                                     TreeCounters *ctr,
                                                      const uint64_t *__restrict__ skey,
                                                      const uint8_t *__restrict__ dl,
                                                      const uint32_t *__restrict__ first,
                                                      const uint32_t *__restrict__ count,
                                                      uint32_t *__restrict__ tmp,
                                                      uint32_t *__restrict__ bnd,
-                                                     uint32_t *__restrict__ part) {
+                                                     uint32_t *__restrict__ part,
+                                                     uint32_t *__restrict__ biglist) {
   __shared__ uint32_t sh[4];
   const uint32_t a0 = ctr->lvl[l], n = ctr->lvl[l + 1] - a0;
   uint32_t ca, cb;
   chunk_range(n, ca, cb);
-  const int shift = 3 * (kMaxLevel - 1 - l);
   const unsigned lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   const uint64_t *dw = reinterpret_cast<const uint64_t *>(dl);
   uint32_t sum = 0;
@@ -200,13 +200,49 @@ __global__ __launch_bounds__(256) void k_level_count(int l, int nleaf,
       tmp[i] = nch;
       sum += nch;
     }
-    unsigned long long mid = __ballot(split && !small && cnt <= 4096u);
-    while (mid) {
-      const int L = __ffsll((long long)mid) - 1;
-      mid &= mid - 1ull;
-      const uint32_t f = (uint32_t)__shfl((int)fst, L, 64);
-      const uint32_t c = (uint32_t)__shfl((int)cnt, L, 64);
-      const uint32_t vi = base + (uint32_t)L;
+    // nodes above 512 particles go to a work list for k_level_big, which
+    // spreads them over the whole grid (they cluster in the dense centre)
+    const unsigned long long bigm = __ballot(split && !small);
+    if (bigm) {
+      uint32_t b0 = 0;
+      if (lane == 0) b0 = atomicAdd(&ctr->big_n, (uint32_t)__popcll(bigm));
+      b0 = (uint32_t)__shfl((int)b0, 0, 64);
+      if (split && !small) biglist[b0 + lanes_below(bigm)] = i;
+    }
+  }
+  uint32_t tot;
+  block_exclusive_scan(sum, sh, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// Splitting nodes of more than 512 particles listed by k_level_count: one
+// wave per node over the whole grid.  Up to 4096 particles the wave scans
+// the d bytes coalesced (512 per round); bigger nodes are narrowed on the
+// keys (wave_octants).  The child count is added to the sum of the block
+// chunk that owns the node.
+__global__ __launch_bounds__(256) void k_level_big(int l, const TreeCounters *ctr,
+                                                   const uint64_t *__restrict__ skey,
+                                                   const uint8_t *__restrict__ dl,
+                                                   const uint32_t *__restrict__ first,
+                                                   const uint32_t *__restrict__ count,
+                                                   const uint32_t *__restrict__ biglist,
+                                                   uint32_t *__restrict__ tmp,
+                                                   uint32_t *__restrict__ bnd,
+                                                   uint32_t *__restrict__ part) {
+  const uint32_t nbig = ctr->big_n;
+  if (nbig == 0) return;
+  const uint32_t a0 = ctr->lvl[l], n = ctr->lvl[l + 1] - a0;
+  const uint32_t chunk = (n + kLevelBlocks - 1) / kLevelBlocks;   // as k_level_count
+  const int shift = 3 * (kMaxLevel - 1 - l);
+  const unsigned lane = threadIdx.x & 63u;
+  const uint32_t wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+  const uint64_t *dw = reinterpret_cast<const uint64_t *>(dl);
+  for (uint32_t e = wid; e < nbig; e += nw) {
+    const uint32_t vi = biglist[e];
+    const uint32_t f = first[a0 + vi], c = count[a0 + vi];
+    uint32_t nch;
+    if (c <= 4096u) {
       const uint32_t lo = f + 1u, hi = f + c, p0 = lo & ~7u;
       uint32_t found = 0;
       for (uint32_t r = p0; r < hi; r += 512u) {
@@ -223,24 +259,13 @@ __global__ __launch_bounds__(256) void k_level_count(int l, int nleaf,
         }
         found += tot;
       }
-      if (lane == 0) {
-        const uint32_t nch = min(1u + found, 8u);
-        tmp[vi] = nch;
-        sum += nch;
-      }
-    }
-    unsigned long long big = __ballot(split && cnt > 4096u);
-    while (big) {
-      const int L = __ffsll((long long)big) - 1;
-      big &= big - 1ull;
-      const uint32_t f = (uint32_t)__shfl((int)fst, L, 64);
-      const uint32_t c = (uint32_t)__shfl((int)cnt, L, 64);
+      nch = min(1u + found, 8u);
+    } else {
       uint32_t b[9];
       wave_octants(skey, f, c, shift, b);
       b[0] = f;
       b[8] = f + c;
-      const uint32_t vi = base + (uint32_t)L;
-      uint32_t nch = 0;
+      nch = 0;
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
         if (b[o + 1] > b[o]) {
@@ -248,15 +273,12 @@ __global__ __launch_bounds__(256) void k_level_count(int l, int nleaf,
           ++nch;
         }
       }
-      if (lane == 0) {
-        tmp[vi] = nch;
-        sum += nch;
-      }
+    }
+    if (lane == 0) {
+      tmp[vi] = nch;
+      atomicAdd(&part[vi / chunk], nch);
     }
   }
-  uint32_t tot;
-  block_exclusive_scan(sum, sh, tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 // Exclusive scan of the per-block child counts (one block, 4 per thread);
@@ -284,6 +306,7 @@ __global__ __launch_bounds__(256) void k_level_top(int l, int64_t max_nodes,
     e += loc[q];
   }
   if (threadIdx.x == 0) {
+    ctr->big_n = 0;
     const uint32_t start = ctr->lvl[l + 1];
     if (ctr->overflow || (int64_t)start + all > max_nodes) {
       if (!ctr->overflow) set_err(err, TG_ERR_NODES);
@@ -357,7 +380,11 @@ hipError_t launch_tree_build(tg_ctx *c) {
   for (int l = 0; l < kMaxLevel; ++l) {
     hipLaunchKernelGGL(k_level_count, dim3(kLevelBlocks), dim3(256), 0,
                        c->stream, l, c->leaf_size, b.ctr, b.key[0], b.lcp,
-                       b.first, b.count, b.lvl_tmp, b.lvl_bnd, b.lvl_part);
+                       b.first, b.count, b.lvl_tmp, b.lvl_bnd, b.lvl_part,
+                       b.lvl_big);
+    hipLaunchKernelGGL(k_level_big, dim3(kLevelBlocks), dim3(256), 0, c->stream,
+                       l, b.ctr, b.key[0], b.lcp, b.first, b.count, b.lvl_big,
+                       b.lvl_tmp, b.lvl_bnd, b.lvl_part);
     hipLaunchKernelGGL(k_level_top, dim3(1), dim3(256), 0, c->stream, l,
                        c->max_nodes, b.ctr, b.lvl_part, b.err);
     hipLaunchKernelGGL(k_level_emit, dim3(kLevelBlocks), dim3(256), 0,

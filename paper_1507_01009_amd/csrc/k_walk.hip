@@ -482,7 +482,7 @@ struct GroupQueue {
 
 // ------------------------------------------------------------ force kernel
 template <bool kMixed>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_walk_forces(WalkArgs A) {
+__global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
   __shared__ uint32_t s_tgt[64];
   __shared__ uint32_t s_m[kMCap];
   __shared__ uint32_t s_q[kQCap];

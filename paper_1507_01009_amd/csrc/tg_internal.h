@@ -51,7 +51,8 @@ struct TreeCounters {
   uint32_t n_active_groups;
   uint32_t overflow;         // node capacity exceeded during this build
   uint32_t xq[8];            // walk work counters, one queue per XCD
-  uint32_t pad[3];
+  uint32_t big_n;            // nodes listed for k_level_big at this level
+  uint32_t pad[2];
   unsigned long long n_p2p, n_p2m, n_targets, n_walked;      // last walk
   unsigned long long cum_p2p, cum_p2m, cum_targets, cum_walked;  // since reset
 };
@@ -79,7 +80,8 @@ struct Buffers {
   uint32_t *lvl_tmp = nullptr;    // [nodes] per-level child counts
   uint32_t *lvl_bnd = nullptr;    // [nodes][8] octant starts of splitting nodes
   uint32_t *lvl_part = nullptr;   // [kLevelBlocks] per-block child counts / scan
-  uint8_t *lcp = nullptr;         // [N + 16] common leading digits with predecessor
+  uint8_t *lcp = nullptr;         // [N + 64] common leading digits with predecessor
+  uint32_t *lvl_big = nullptr;    // [nodes] nodes of more than 512 particles at a level
   // groups
   uint32_t *gflag = nullptr;      // [N + 1] group starts / scan
   uint4 *groups = nullptr;        // [N]

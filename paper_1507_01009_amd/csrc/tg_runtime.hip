@@ -64,7 +64,7 @@ static void free_all(tg_ctx *c) {
   void *ptrs[] = {b.sysoff, b.cube, b.cube_part, b.tiles, b.sys_tile0,
                   b.root_of, b.key[0], b.key[1], b.val[0], b.val[1], b.hist,
                   b.rank, b.spart, b.level, b.nchild, b.first, b.count,
-                  b.child, b.parent, b.nsys, b.com, b.mom, b.lvl_tmp, b.lvl_bnd, b.lvl_part, b.lcp, b.gflag,
+                  b.child, b.parent, b.nsys, b.com, b.mom, b.lvl_tmp, b.lvl_bnd, b.lvl_part, b.lcp, b.lvl_big, b.gflag,
                   b.groups, b.aflag, b.alist, b.abox, b.sact, b.frontier,
                   b.wl_count, b.wl_off, b.scan_part, b.scan_total, b.ctr,
                   b.err, b.dpart, b.dseg};
@@ -140,6 +140,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.lvl_bnd, 8 * NN));
   A(dalloc(&b.lvl_part, kLevelBlocks));
   A(dalloc(&b.lcp, N + 64));
+  A(dalloc(&b.lvl_big, NN));
   A(dalloc(&b.gflag, N + 1));
   A(dalloc(&b.groups, N));
   A(dalloc(&b.aflag, N + 1));
