@@ -203,6 +203,59 @@ tg_status tg_active_set(tg_ctx *ctx, const uint8_t *level_dev, int64_t n,
 /* k_dev[0] += inc (device-side substep counter for replayed graphs). */
 tg_status tg_counter_add(tg_ctx *ctx, int64_t *k_dev, int64_t inc);
 
+/* ---- a11 inside the walk: SMBHs as external point masses ----------------
+ * Register n_ext point masses (device arrays pos [n_ext][3], mass, eps) whose
+ * FP64 Plummer force, pair softening max(eps, eps_ext), every later
+ * tg_tree_forces adds to each target of the same system (seg_host [n_sys+1]
+ * ascending offsets into the externals; NULL with n_sys = 1 means all).
+ * The arrays are read at walk time, so new positions need no new call.
+ * n_ext = 0 clears them.  n_ext <= 1024.  Errors: TG_EINVAL, TG_ESTATE (a
+ * new segment table during graph capture). */
+tg_status tg_set_external(tg_ctx *ctx, const double *pos_dev,
+                          const double *mass_dev, const double *eps_dev,
+                          int32_t n_ext, const int64_t *seg_host, int32_t n_sys);
+
+/* ---- whole steps (a1..a12 in one call; capturable) ---------------------- */
+typedef struct {
+  double *pos, *vel, *acc, *pot;   /* stars [n][3], pot [n] may be NULL */
+  const double *mass;              /* [n] */
+  int64_t n;
+  const int64_t *sys_off;          /* host [n_sys+1], NULL for one system */
+  int32_t n_sys;
+  double *bh_pos, *bh_vel, *bh_acc, *bh_pot;   /* SMBHs [n_bh][3]; pot may be NULL */
+  const double *bh_mass, *bh_eps;              /* [n_bh] */
+  int32_t n_bh;
+  const int64_t *bh_seg;           /* host [n_sys+1]: SMBHs of each system */
+  double eps, theta;               /* star softening, opening angle */
+} tg_system;
+
+/* Forces for the listed stars (all when active_idx_dev is NULL): tree +
+ * FP64 SMBH terms, and the FP64 forces on every SMBH from the stars and the
+ * other SMBHs of its system (Sec. 2: the perturber/chain force hand-off). */
+tg_status tg_forces(tg_ctx *ctx, const tg_system *sys,
+                    const int32_t *active_idx_dev, const int32_t *n_active_dev);
+
+/* One kick-drift-kick step of length dt for stars and SMBHs (acc must hold
+ * the forces of the current positions, e.g. from tg_forces). */
+tg_status tg_step_kdk(tg_ctx *ctx, const tg_system *sys, double dt);
+
+typedef struct {
+  uint8_t *level;                  /* [n] block level of each star */
+  const double *tau4eps2;          /* [n] (tau^2)^2 eps^2 per star */
+  int32_t *active_idx;             /* [n] scratch: active stars */
+  int32_t *n_active;               /* [1] */
+  int64_t *k;                      /* [1] substep counter (units of the smallest step) */
+  double dt_max;                   /* step of level 0 */
+  int32_t nlev;                    /* levels 0..nlev-1; smallest step dt_max 2^-(nlev-1) */
+} tg_blocks;
+
+/* One substep of the smallest step: closing half kicks of the stars whose
+ * step ends at k (none at k = 0), new levels, opening half kicks, drift of
+ * everything, k += 1, forces for the stars active at the new k.  SMBHs take
+ * the smallest step every substep.  All counts live on the device, so one
+ * captured substep can be replayed. */
+tg_status tg_step_block(tg_ctx *ctx, const tg_system *sys, const tg_blocks *blocks);
+
 /* ---- a13: HIP graphs over any sequence of the calls above ------------- */
 typedef struct tg_graph tg_graph;
 tg_status tg_graph_begin(tg_ctx *ctx);

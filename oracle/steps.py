@@ -1,0 +1,118 @@
+"""Plain CPU oracle of whole steps (TEST INFRASTRUCTURE ONLY).
+
+Composes the oracle's primitives in the order of the paper's hybrid step
+(Sec. 2, steps (1), (6), (7)), read as kick-drift-kick:
+
+* forces: tree forces on the listed stars plus the FP64 Plummer force of the
+  SMBHs of the star's system (pair softening max(eps_star, eps_bh)); every
+  SMBH feels all stars of its system and the other SMBHs (Sec. 2, the
+  perturber / chain force-correction paragraph).
+* KDK step: v += a dt/2 (stars, SMBHs), x += v dt, forces, v += a dt/2.
+* block substep (power-of-two levels, smallest step dt_min):
+  closing half kicks of the stars active at k (not at k = 0) with their old
+  level, new levels at k, opening half kicks with the new level, SMBH half
+  kicks of dt_min/2 (SMBHs always on the smallest step), drift of all by
+  dt_min, k += 1, forces for the stars active at the new k.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import oracle
+
+
+@dataclass
+class State:
+    pos: np.ndarray
+    vel: np.ndarray
+    mass: np.ndarray
+    eps: float
+    theta: float
+    sys_off: np.ndarray
+    bh_pos: np.ndarray
+    bh_vel: np.ndarray
+    bh_mass: np.ndarray
+    bh_eps: np.ndarray
+    bh_seg: np.ndarray
+    leaf_size: int = 8
+    group_size: int = 64
+    acc: np.ndarray = field(default=None)
+    pot: np.ndarray = field(default=None)
+    bh_acc: np.ndarray = field(default=None)
+    bh_pot: np.ndarray = field(default=None)
+
+    def __post_init__(self):
+        n, nb = self.pos.shape[0], self.bh_mass.shape[0]
+        if self.acc is None:
+            self.acc = np.zeros((n, 3))
+            self.pot = np.zeros(n)
+        if self.bh_acc is None:
+            self.bh_acc = np.zeros((nb, 3))
+            self.bh_pot = np.zeros(nb)
+
+
+def forces(st: State, active=None):
+    """Tree + SMBH forces for the listed stars; SMBH forces for all SMBHs."""
+    n = st.pos.shape[0]
+    S = st.sys_off.shape[0] - 1
+    ev = oracle.tree_forces(st.pos, st.mass, st.eps, st.theta, st.leaf_size,
+                            st.group_size, active=active, sys_off=st.sys_off)
+    rows = np.arange(n) if active is None else np.asarray(active, np.int64)
+    st.acc[rows] = ev.acc[rows]
+    st.pot[rows] = ev.pot[rows]
+    for s in range(S):
+        b0, b1 = int(st.bh_seg[s]), int(st.bh_seg[s + 1])
+        if b1 == b0:
+            continue
+        lo, hi = int(st.sys_off[s]), int(st.sys_off[s + 1])
+        r = rows[(rows >= lo) & (rows < hi)]
+        if r.size:
+            a, p = oracle.direct_pairs(st.bh_pos[b0:b1], st.bh_mass[b0:b1],
+                                       st.bh_eps[b0:b1], st.pos[r], st.eps)
+            st.acc[r] += a
+            st.pot[r] += p
+        a, p = oracle.direct_pairs(st.pos[lo:hi], st.mass[lo:hi], st.eps,
+                                   st.bh_pos[b0:b1], st.bh_eps[b0:b1])
+        oracle.direct_pairs(st.bh_pos[b0:b1], st.bh_mass[b0:b1], st.bh_eps[b0:b1],
+                            st.bh_pos[b0:b1], st.bh_eps[b0:b1], self_pairs=True,
+                            acc=a, pot=p)
+        st.bh_acc[b0:b1] = a
+        st.bh_pot[b0:b1] = p
+    return ev
+
+
+def kdk_step(st: State, dt: float):
+    oracle.kick(st.vel, st.acc, dt)
+    if st.bh_mass.size:
+        oracle.kick(st.bh_vel, st.bh_acc, dt)
+    oracle.drift(st.pos, st.vel, dt)
+    if st.bh_mass.size:
+        oracle.drift(st.bh_pos, st.bh_vel, dt)
+    forces(st)
+    oracle.kick(st.vel, st.acc, dt)
+    if st.bh_mass.size:
+        oracle.kick(st.bh_vel, st.bh_acc, dt)
+
+
+def block_substep(st: State, level: np.ndarray, tau4eps2: np.ndarray, k: int,
+                  dt_max: float, nlev: int):
+    """One substep at counter k; returns k + 1 and the new active set."""
+    dt_min = dt_max * 2.0 ** -(nlev - 1)
+    act = oracle.active_at(level, nlev, k)
+    if k > 0:
+        oracle.kick(st.vel, st.acc, dt_max, idx=act, level=level)
+        if st.bh_mass.size:
+            oracle.kick(st.bh_vel, st.bh_acc, dt_min)
+    oracle.levels(st.acc, tau4eps2, level, dt_max, nlev, k, idx=act)
+    oracle.kick(st.vel, st.acc, dt_max, idx=act, level=level)
+    if st.bh_mass.size:
+        oracle.kick(st.bh_vel, st.bh_acc, dt_min)
+    oracle.drift(st.pos, st.vel, dt_min)
+    if st.bh_mass.size:
+        oracle.drift(st.bh_pos, st.bh_vel, dt_min)
+    k += 1
+    act = oracle.active_at(level, nlev, k)
+    forces(st, act)
+    return k, act

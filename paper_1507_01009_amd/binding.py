@@ -43,6 +43,22 @@ class tg_tree_view(C.Structure):
                 ("com", C.c_void_p), ("mom", C.c_void_p), ("groups", C.c_void_p)]
 
 
+class tg_system(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("acc", C.c_void_p),
+                ("pot", C.c_void_p), ("mass", C.c_void_p), ("n", C.c_int64),
+                ("sys_off", C.c_void_p), ("n_sys", C.c_int32),
+                ("bh_pos", C.c_void_p), ("bh_vel", C.c_void_p), ("bh_acc", C.c_void_p),
+                ("bh_pot", C.c_void_p), ("bh_mass", C.c_void_p), ("bh_eps", C.c_void_p),
+                ("n_bh", C.c_int32), ("bh_seg", C.c_void_p), ("eps", C.c_double),
+                ("theta", C.c_double)]
+
+
+class tg_blocks(C.Structure):
+    _fields_ = [("level", C.c_void_p), ("tau4eps2", C.c_void_p),
+                ("active_idx", C.c_void_p), ("n_active", C.c_void_p), ("k", C.c_void_p),
+                ("dt_max", C.c_double), ("nlev", C.c_int32)]
+
+
 _lib = None
 
 
@@ -76,6 +92,10 @@ def lib():
             "tg_levels": (st, [P, P, P, i64, P, P, f64, i32, P, P]),
             "tg_active_set": (st, [P, P, i64, i32, P, i32, P, P]),
             "tg_counter_add": (st, [P, P, i64]),
+            "tg_set_external": (st, [P, P, P, P, i32, P, i32]),
+            "tg_forces": (st, [P, P, P, P]),
+            "tg_step_kdk": (st, [P, P, f64]),
+            "tg_step_block": (st, [P, P, P]),
             "tg_graph_begin": (st, [P]),
             "tg_graph_end": (st, [P, P]),
             "tg_graph_launch": (st, [P, P]),
@@ -101,7 +121,8 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_set_sizes", "tg_build_tree", "tg_compute_moments",
             "tg_tree_forces", "tg_get_counts", "tg_reset_counts", "tg_walk_lists",
             "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels",
-            "tg_active_set", "tg_counter_add", "tg_graph_begin",
+            "tg_active_set", "tg_counter_add", "tg_set_external", "tg_forces",
+            "tg_step_kdk", "tg_step_block", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
             "tg_get_profile", "tg_sync", "tg_last_error",
@@ -274,6 +295,49 @@ class Context:
 
     def counter_add(self, k, inc=1):
         _check(lib().tg_counter_add(self.h, _ptr(k), int(inc)))
+
+    def set_external(self, pos, mass, eps, seg=None):
+        """SMBHs as external point masses added to every later tree_forces."""
+        arr, p = _i64_host(seg)
+        nsys = 1 if arr is None else arr.shape[0] - 1
+        n = 0 if mass is None else mass.shape[0]
+        _check(lib().tg_set_external(self.h, _ptr(pos), _ptr(mass), _ptr(eps), n, p, nsys))
+
+    # -- whole steps
+    def make_system(self, pos, vel, acc, mass, eps, theta, pot=None, sys_off=None,
+                    bh_pos=None, bh_vel=None, bh_acc=None, bh_mass=None, bh_eps=None,
+                    bh_pot=None, bh_seg=None):
+        """A tg_system describing device tensors (kept alive by the caller)."""
+        y = tg_system()
+        y.pos, y.vel, y.acc, y.pot = (_ptr(pos), _ptr(vel), _ptr(acc), _ptr(pot))
+        y.mass, y.n = _ptr(mass), pos.shape[0]
+        so, sp = _i64_host(sys_off)
+        y.sys_off, y.n_sys = sp, 1 if so is None else so.shape[0] - 1
+        nb = 0 if bh_mass is None else bh_mass.shape[0]
+        y.bh_pos, y.bh_vel, y.bh_acc = _ptr(bh_pos), _ptr(bh_vel), _ptr(bh_acc)
+        y.bh_pot, y.bh_mass, y.bh_eps = _ptr(bh_pot), _ptr(bh_mass), _ptr(bh_eps)
+        y.n_bh = nb
+        bs, bp = _i64_host(bh_seg)
+        y.bh_seg = bp
+        y.eps, y.theta = float(eps), float(theta)
+        y._keep = (so, bs)   # host arrays must outlive the calls
+        return y
+
+    def forces(self, system, active_idx=None, n_active=None):
+        _check(lib().tg_forces(self.h, C.byref(system), _ptr(active_idx), _ptr(n_active)))
+
+    def step_kdk(self, system, dt):
+        _check(lib().tg_step_kdk(self.h, C.byref(system), float(dt)))
+
+    def make_blocks(self, level, tau4eps2, active_idx, n_active, k, dt_max, nlev):
+        b = tg_blocks()
+        b.level, b.tau4eps2 = _ptr(level), _ptr(tau4eps2)
+        b.active_idx, b.n_active, b.k = _ptr(active_idx), _ptr(n_active), _ptr(k)
+        b.dt_max, b.nlev = float(dt_max), int(nlev)
+        return b
+
+    def step_block(self, system, blocks):
+        _check(lib().tg_step_block(self.h, C.byref(system), C.byref(blocks)))
 
     # -- a13
     def graph_begin(self):

@@ -35,7 +35,8 @@ __device__ __forceinline__ int seg_of(const int64_t *off, int nseg, int64_t i) {
 }
 
 __global__ void k_direct(const double *__restrict__ spos, const double *__restrict__ sm,
-                         const double *__restrict__ seps, const double *__restrict__ tpos,
+                         const double *__restrict__ seps, double seps_all,
+                         const double *__restrict__ tpos,
                          const double *__restrict__ teps, int64_t nt,
                          const int64_t *__restrict__ sseg, const int64_t *__restrict__ tseg,
                          int nseg, int64_t chunk, int nchunks, int self_pairs,
@@ -54,7 +55,7 @@ __global__ void k_direct(const double *__restrict__ spos, const double *__restri
     CSum ax, ay, az, ph;
     for (int64_t j = j0; j < j1; ++j) {
       if (self_pairs && j == i) continue;
-      const double ep = fmax(seps[j], ei);
+      const double ep = fmax(seps ? seps[j] : seps_all, ei);
       const double dx = xi - spos[3 * j], dy = yi - spos[3 * j + 1], dz = zi - spos[3 * j + 2];
       const double r2 = dx * dx + dy * dy + dz * dz + ep * ep;
       const double D1 = 1.0 / sqrt(r2);
@@ -130,8 +131,8 @@ __global__ __launch_bounds__(256) void k_direct_reduce(int64_t nt, int nchunks,
 }
 
 hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
-                         const double *sm,
-                         const double *seps, int64_t ns, const double *tpos,
+                         const double *sm, const double *seps, double seps_all,
+                         int64_t ns, const double *tpos,
                          const double *teps, int64_t nt, int nseg,
                          int64_t max_seg_src, int self_pairs, int accumulate,
                          double *acc, double *pot) {
@@ -151,7 +152,7 @@ hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
   const int64_t total = nt * nchunks;
   const int g = (int)std::min<int64_t>((total + 255) / 256, 8192);
   hipLaunchKernelGGL(k_direct, dim3(g), dim3(256), 0, c->stream, spos, sm, seps,
-                     tpos, teps, nt, dseg, dseg + (nseg + 1), nseg,
+                     seps_all, tpos, teps, nt, dseg, dseg + (nseg + 1), nseg,
                      chunk, (int)nchunks, self_pairs, accumulate, acc, pot,
                      c->b.dpart);
   if (nchunks > 1) {

@@ -57,6 +57,10 @@ struct WalkArgs {
   int fcap;
   double th2, eps2, G;
   double *acc, *pot;
+  // external point masses (SMBHs) of each system, added in FP64 per target
+  const double *ext_pos, *ext_mass, *ext_eps;
+  const int32_t *ext_seg;   // [S+1]: externals of system s
+  double eps;
   // list mode
   uint32_t *wl_count;
   const uint32_t *wl_off;
@@ -561,10 +565,22 @@ __global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
       }
       const uint32_t orig = A.perm[r_t];
       const double nanv = __longlong_as_double(0x7ff8000000000000ll);
-      A.acc[3 * (size_t)orig + 0] = ok ? A.G * ax : nanv;
-      A.acc[3 * (size_t)orig + 1] = ok ? A.G * ay : nanv;
-      A.acc[3 * (size_t)orig + 2] = ok ? A.G * az : nanv;
-      if (A.pot) A.pot[orig] = ok ? A.G * (ph + self) : nanv;
+      double ex = 0.0, ey = 0.0, ez = 0.0, ep = 0.0;
+      if (A.ext_seg) {   // SMBH terms, FP64 in both precision modes
+        for (int32_t j = A.ext_seg[gr.w]; j < A.ext_seg[gr.w + 1]; ++j) {
+          const double e = fmax(A.eps, A.ext_eps[j]);
+          const double dx = p.x - A.ext_pos[3 * j], dy = p.y - A.ext_pos[3 * j + 1],
+                       dz = p.z - A.ext_pos[3 * j + 2];
+          const double r2 = dx * dx + dy * dy + dz * dz + e * e;
+          const double D1 = 1.0 / sqrt(r2);
+          const double mD1 = A.ext_mass[j] * D1, mD3 = mD1 * D1 * D1;
+          ex -= mD3 * dx; ey -= mD3 * dy; ez -= mD3 * dz; ep -= mD1;
+        }
+      }
+      A.acc[3 * (size_t)orig + 0] = ok ? A.G * (ax + ex) : nanv;
+      A.acc[3 * (size_t)orig + 1] = ok ? A.G * (ay + ey) : nanv;
+      A.acc[3 * (size_t)orig + 2] = ok ? A.G * (az + ez) : nanv;
+      if (A.pot) A.pot[orig] = ok ? A.G * (ph + self + ep) : nanv;
     }
     (void)has_t;
     tot_p2m += S.cells * (unsigned long long)nt;
@@ -741,6 +757,9 @@ static WalkArgs make_args(tg_ctx *c, double theta) {
   A.th2 = theta * theta;
   A.eps2 = 0.0; A.G = c->cfg.G;
   A.acc = nullptr; A.pot = nullptr;
+  A.ext_pos = c->ext_pos; A.ext_mass = c->ext_mass; A.ext_eps = c->ext_eps;
+  A.ext_seg = c->n_ext > 0 ? c->b.ext_seg : nullptr;
+  A.eps = 0.0;
   A.wl_count = b.wl_count; A.wl_off = b.wl_off; A.ids = nullptr;
   return A;
 }
@@ -754,6 +773,7 @@ hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
                               hipEvent_t after) {
   WalkArgs A = make_args(c, theta);
   A.eps2 = eps * eps;
+  A.eps = eps;
   A.acc = acc;
   A.pot = pot;
   hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, c->stream, c->b.ctr);

@@ -32,6 +32,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per tile
 constexpr int kScanBlocks = 256;
 constexpr int kLevelBlocks = 1024;                // octree level kernels (multiple of 256)
 constexpr int kMaxWavesPerCU = 16;
+constexpr int kMaxExternal = 1024;               // SMBHs / external point masses
 constexpr int kSegSlots = 8;                     // cached direct-sum segment tables
 constexpr int kSegSlotLen = 2 * (kMaxSys + 1);
 
@@ -101,6 +102,7 @@ struct Buffers {
   // direct sums
   double *dpart = nullptr;        // partial sums for few-target direct sums
   int64_t *dseg = nullptr;        // [kSegSlots][2 * (S+1)] segment offsets
+  int32_t *ext_seg = nullptr;     // [S+1] external masses of each system
   int64_t dpart_cap = 0;
 };
 
@@ -126,6 +128,10 @@ struct tg_ctx {
   double prof_ms = 0.0;
   int64_t prof_n = 0;
   std::vector<int64_t> sysoff_host;   // layout of the last build
+  // external point masses (tg_set_external)
+  const double *ext_pos = nullptr, *ext_mass = nullptr, *ext_eps = nullptr;
+  int32_t n_ext = 0;
+  std::vector<int32_t> ext_seg_host;
   std::vector<std::vector<int64_t>> dseg_host;  // tables held in the device slots
   int dseg_next = 0;
   tg::Buffers b;
@@ -182,8 +188,8 @@ hipError_t launch_walk_lists(tg_ctx *c, double theta, int pass,
 
 // k_direct.hip
 hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
-                         const double *sm,
-                         const double *seps, int64_t ns, const double *tpos,
+                         const double *sm, const double *seps, double seps_all,
+                         int64_t ns, const double *tpos,
                          const double *teps, int64_t nt, int nseg,
                          int64_t max_seg_src, int self_pairs, int accumulate,
                          double *acc, double *pot);

@@ -67,7 +67,7 @@ static void free_all(tg_ctx *c) {
                   b.child, b.parent, b.nsys, b.com, b.mom, b.lvl_tmp, b.lvl_bnd, b.lvl_part, b.lcp, b.lvl_big, b.gflag,
                   b.groups, b.aflag, b.alist, b.abox, b.sact, b.frontier,
                   b.wl_count, b.wl_off, b.scan_part, b.scan_total, b.ctr,
-                  b.err, b.dpart, b.dseg};
+                  b.err, b.dpart, b.dseg, b.ext_seg};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   b = Buffers();
@@ -156,6 +156,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.err, 1));
   A(dalloc(&b.dpart, b.dpart_cap));
   A(dalloc(&b.dseg, kSegSlots * kSegSlotLen));
+  A(dalloc(&b.ext_seg, kMaxSys + 1));
   if (a != hipSuccess) {
     free_all(c);
     delete c;
@@ -492,8 +493,44 @@ tg_status tg_direct_fp64(tg_ctx *c, const double *spos, const double *sm,
     TG_HIP(hipStreamSynchronize(c->stream));
   }
   const int64_t *dseg = c->b.dseg + slot * kSegSlotLen;
-  TG_HIP(launch_direct(c, dseg, spos, sm, seps, ns, tpos, teps, nt, ns_eff,
+  TG_HIP(launch_direct(c, dseg, spos, sm, seps, 0.0, ns, tpos, teps, nt, ns_eff,
                        max_src, self_pairs, accumulate, acc, pot));
+  return TG_OK;
+}
+
+// Direct sums where every source shares one softening (stars): the same
+// kernels with a broadcast softening.
+static tg_status tg_direct_fp64_eps(tg_ctx *c, const double *spos, const double *sm,
+                             double seps, int64_t ns, const double *tpos,
+                             const double *teps, int64_t nt,
+                             const int64_t *sseg, const int64_t *tseg, int32_t nseg,
+                             double *acc, double *pot) {
+  if (!c) return fail(TG_EINVAL, "tg_direct_fp64_eps: NULL context");
+  if (nt == 0) return TG_OK;
+  int slot = -1;
+  std::vector<int64_t> seg(2 * (nseg + 1));
+  for (int s = 0; s <= nseg; ++s) { seg[s] = sseg[s]; seg[nseg + 1 + s] = tseg[s]; }
+  int64_t max_src = 0;
+  for (int s = 0; s < nseg; ++s) max_src = std::max(max_src, seg[s + 1] - seg[s]);
+  for (int k = 0; k < (int)c->dseg_host.size(); ++k)
+    if (c->dseg_host[k] == seg) slot = k;
+  if (slot < 0) {
+    if (c->capturing)
+      return fail(TG_ESTATE, "tg_direct_fp64_eps: new segment layout during capture");
+    if ((int)c->dseg_host.size() < kSegSlots) {
+      c->dseg_host.push_back(seg);
+      slot = (int)c->dseg_host.size() - 1;
+    } else {
+      slot = c->dseg_next;
+      c->dseg_next = (c->dseg_next + 1) % kSegSlots;
+      c->dseg_host[slot] = seg;
+    }
+    TG_HIP(hipMemcpyAsync(c->b.dseg + slot * kSegSlotLen, seg.data(),
+                          sizeof(int64_t) * seg.size(), hipMemcpyHostToDevice, c->stream));
+    TG_HIP(hipStreamSynchronize(c->stream));
+  }
+  TG_HIP(launch_direct(c, c->b.dseg + slot * kSegSlotLen, spos, sm, nullptr, seps, ns,
+                       tpos, teps, nt, nseg, max_src, 0, 0, acc, pot));
   return TG_OK;
 }
 
@@ -673,6 +710,143 @@ tg_status tg_autotune(tg_ctx *c, const double *pos, const double *mass,
   best[0] = b3[0]; best[1] = b3[1]; best[2] = b3[2];
   *best_ms = bms;
   return TG_OK;
+}
+
+tg_status tg_set_external(tg_ctx *c, const double *pos, const double *mass,
+                          const double *eps, int32_t n_ext,
+                          const int64_t *seg_host, int32_t n_sys) {
+  if (!c) return fail(TG_EINVAL, "tg_set_external: NULL context");
+  if (n_ext < 0 || n_ext > kMaxExternal)
+    return fail(TG_EINVAL, "tg_set_external: n_ext must be in 0..1024");
+  if (n_ext == 0) {
+    c->n_ext = 0;
+    c->ext_pos = c->ext_mass = c->ext_eps = nullptr;
+    return TG_OK;
+  }
+  if (!pos || !mass || !eps) return fail(TG_EINVAL, "tg_set_external: NULL pointer");
+  if (n_sys < 1 || n_sys > c->cfg.max_systems)
+    return fail(TG_EINVAL, "tg_set_external: n_sys out of range");
+  std::vector<int32_t> seg(kMaxSys + 1, 0);
+  if (seg_host) {
+    if (seg_host[0] != 0 || seg_host[n_sys] != n_ext)
+      return fail(TG_EINVAL, "tg_set_external: segments must span 0..n_ext");
+    for (int s = 0; s <= n_sys; ++s) {
+      if (s > 0 && seg_host[s] < seg_host[s - 1])
+        return fail(TG_EINVAL, "tg_set_external: segments not ascending");
+      seg[s] = (int32_t)seg_host[s];
+    }
+  } else {
+    if (n_sys != 1) return fail(TG_EINVAL, "tg_set_external: segments needed for n_sys > 1");
+    seg[0] = 0;
+    seg[1] = n_ext;
+  }
+  seg.resize(n_sys + 1);
+  if (seg != c->ext_seg_host) {
+    if (c->capturing)
+      return fail(TG_ESTATE, "tg_set_external: new segment layout during capture");
+    TG_HIP(hipMemcpyAsync(c->b.ext_seg, seg.data(), sizeof(int32_t) * (n_sys + 1),
+                          hipMemcpyHostToDevice, c->stream));
+    TG_HIP(hipStreamSynchronize(c->stream));
+    c->ext_seg_host = seg;
+  }
+  c->ext_pos = pos;
+  c->ext_mass = mass;
+  c->ext_eps = eps;
+  c->n_ext = n_ext;
+  return TG_OK;
+}
+
+static tg_status check_system(const tg_system *y, const char *who) {
+  if (!y) return fail(TG_EINVAL, std::string(who) + ": NULL system");
+  if (y->n < 0 || (y->n > 0 && (!y->pos || !y->vel || !y->acc || !y->mass)))
+    return fail(TG_EINVAL, std::string(who) + ": star arrays missing");
+  if (y->n_bh < 0 || (y->n_bh > 0 && (!y->bh_pos || !y->bh_vel || !y->bh_acc ||
+                                      !y->bh_mass || !y->bh_eps)))
+    return fail(TG_EINVAL, std::string(who) + ": SMBH arrays missing");
+  if (y->n_bh > 0 && y->n_sys > 1 && !y->bh_seg)
+    return fail(TG_EINVAL, std::string(who) + ": bh_seg needed for several systems");
+  return TG_OK;
+}
+
+tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
+                    const int32_t *n_act) {
+  tg_status st = check_system(y, "tg_forces");
+  if (st != TG_OK) return st;
+  if ((st = tg_build_tree(c, y->pos, y->n, y->sys_off, y->n_sys)) != TG_OK) return st;
+  if ((st = tg_compute_moments(c, y->mass)) != TG_OK) return st;
+  if ((st = tg_set_external(c, y->bh_pos, y->bh_mass, y->bh_eps, y->n_bh,
+                            y->n_bh ? y->bh_seg : nullptr, y->n_sys)) != TG_OK)
+    return st;
+  if ((st = tg_tree_forces(c, y->eps, y->theta, idx, n_act, y->acc, y->pot)) != TG_OK)
+    return st;
+  if (y->n_bh > 0) {
+    // SMBHs feel the stars of their own system, then each other
+    std::vector<int64_t> so = c->sysoff_host;
+    std::vector<int64_t> bs(y->n_sys + 1);
+    for (int s = 0; s <= y->n_sys; ++s) bs[s] = y->bh_seg ? y->bh_seg[s] : (s ? y->n_bh : 0);
+    const int nseg = y->n_sys;
+    // star softening: the stars' eps for every star
+    st = tg_direct_fp64_eps(c, y->pos, y->mass, y->eps, y->n, y->bh_pos, y->bh_eps,
+                            y->n_bh, so.data(), bs.data(), nseg, y->bh_acc, y->bh_pot);
+    if (st != TG_OK) return st;
+    st = tg_direct_fp64(c, y->bh_pos, y->bh_mass, y->bh_eps, y->n_bh, y->bh_pos,
+                        y->bh_eps, y->n_bh, bs.data(), bs.data(), nseg, 1, 1, y->bh_acc,
+                        y->bh_pot);
+    if (st != TG_OK) return st;
+  }
+  return TG_OK;
+}
+
+tg_status tg_step_kdk(tg_ctx *c, const tg_system *y, double dt) {
+  tg_status st = check_system(y, "tg_step_kdk");
+  if (st != TG_OK) return st;
+  if ((st = tg_kick(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, dt, nullptr, 0)))
+    return st;
+  if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt,
+                    nullptr, 0)))
+    return st;
+  if ((st = tg_drift(c, y->pos, y->vel, y->n, dt))) return st;
+  if ((st = tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, dt))) return st;
+  if ((st = tg_forces(c, y, nullptr, nullptr))) return st;
+  if ((st = tg_kick(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, dt, nullptr, 0)))
+    return st;
+  return tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt, nullptr, 0);
+}
+
+tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
+  tg_status st = check_system(y, "tg_step_block");
+  if (st != TG_OK) return st;
+  if (!b || !b->level || !b->tau4eps2 || !b->active_idx || !b->n_active || !b->k)
+    return fail(TG_EINVAL, "tg_step_block: block arrays missing");
+  if (b->nlev < 1 || b->nlev > 30 || !(b->dt_max > 0.0))
+    return fail(TG_EINVAL, "tg_step_block: bad levels");
+  const double dt_min = std::ldexp(b->dt_max, -(b->nlev - 1));
+  // closing half kicks of the particles whose step ends now (not at k = 0)
+  if ((st = tg_active_set(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active)))
+    return st;
+  if ((st = tg_kick(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
+                    b->dt_max, b->k, 1)))
+    return st;
+  if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt_min,
+                    b->k, 1)))
+    return st;
+  // new levels, then opening half kicks with the new steps
+  if ((st = tg_levels(c, y->acc, b->tau4eps2, y->n, b->active_idx, b->n_active, b->dt_max,
+                      b->nlev, b->k, b->level)))
+    return st;
+  if ((st = tg_kick(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
+                    b->dt_max, nullptr, 0)))
+    return st;
+  if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt_min,
+                    nullptr, 0)))
+    return st;
+  // everyone drifts by the smallest step; then forces for the next active set
+  if ((st = tg_drift(c, y->pos, y->vel, y->n, dt_min))) return st;
+  if ((st = tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, dt_min))) return st;
+  if ((st = tg_counter_add(c, b->k, 1))) return st;
+  if ((st = tg_active_set(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active)))
+    return st;
+  return tg_forces(c, y, b->active_idx, b->n_active);
 }
 
 tg_status tg_sync(tg_ctx *c, uint32_t *bits) {

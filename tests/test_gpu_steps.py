@@ -1,0 +1,261 @@
+"""GPU parity of whole steps (rows a11-a13) against the oracle's steps.
+
+Forces with SMBHs (FP64 SMBH terms in both precision modes), KDK steps,
+block-time-step substeps with device-side active sets and levels, graph
+replays of captured steps, a batch of systems in one launch, and the
+autotuner.  Multi-step runs compare trajectories after a few steps, where
+forces agree to the FP64 bar and no level sits on a threshold.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import steps as osteps
+from paper_1507_01009_amd import ics
+from gpu_helpers import rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class Dev:
+    """Device copies of a workload and its tg_system view."""
+
+    def __init__(self, ctx, w):
+        import torch
+        f64 = dict(dtype=torch.float64, device="cuda")
+        self.pos, self.vel, self.mass = to_dev(w.pos), to_dev(w.vel), to_dev(w.mass)
+        self.acc = torch.zeros((w.n, 3), **f64)
+        self.pot = torch.zeros(w.n, **f64)
+        nb = w.bh_mass.shape[0]
+        self.bpos, self.bvel = to_dev(w.bh_pos.reshape(-1, 3)), to_dev(w.bh_vel.reshape(-1, 3))
+        self.bm, self.be = to_dev(w.bh_mass), to_dev(w.bh_eps)
+        self.bacc = torch.zeros((max(nb, 1), 3), **f64)
+        self.bpot = torch.zeros(max(nb, 1), **f64)
+        S = w.sys_off.shape[0] - 1
+        bseg = np.zeros(S + 1, np.int64)
+        for s in range(S):
+            bseg[s + 1] = bseg[s] + int((w.bh_sys == s).sum())
+        self.bseg = bseg
+        self.sys = ctx.make_system(self.pos, self.vel, self.acc, self.mass, w.eps, w.theta,
+                                   pot=self.pot, sys_off=w.sys_off if S > 1 else None,
+                                   bh_pos=self.bpos if nb else None,
+                                   bh_vel=self.bvel if nb else None,
+                                   bh_acc=self.bacc if nb else None,
+                                   bh_mass=self.bm if nb else None,
+                                   bh_eps=self.be if nb else None,
+                                   bh_pot=self.bpot if nb else None,
+                                   bh_seg=bseg if nb else None)
+
+    def host(self):
+        return {k: getattr(self, k).cpu().numpy() for k in
+                ("pos", "vel", "acc", "pot", "bpos", "bvel", "bacc", "bpot")}
+
+
+def ostate(w, leaf=8, group=64):
+    S = w.sys_off.shape[0] - 1
+    bseg = np.zeros(S + 1, np.int64)
+    for s in range(S):
+        bseg[s + 1] = bseg[s] + int((w.bh_sys == s).sum())
+    return osteps.State(w.pos.copy(), w.vel.copy(), w.mass.copy(), w.eps, w.theta,
+                        w.sys_off.copy(), w.bh_pos.reshape(-1, 3).copy(),
+                        w.bh_vel.reshape(-1, 3).copy(), w.bh_mass.copy(), w.bh_eps.copy(),
+                        bseg, leaf, group)
+
+
+def bh_scale(pos, mass, eps, bpos):
+    d = np.linalg.norm(pos[None, :, :] - bpos[:, None, :], axis=2)
+    return (mass[None, :] / (d ** 2 + eps ** 2)).sum(1)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_forces_with_smbh_binary(prec):
+    say("forces smbh", prec)
+    from paper_1507_01009_amd import binding as B
+    w = ics.cusp_c3(n=65536)
+    ctx = B.Context(w.n, precision=prec)
+    d = Dev(ctx, w)
+    ctx.forces(d.sys)
+    ctx.sync()
+    h = d.host()
+    st = ostate(w)
+    osteps.forces(st)
+    e = rel_err(h["acc"], st.acc)
+    if prec == 0:
+        assert e.max() <= 1e-12
+    else:
+        assert np.median(e) <= 1e-5 and np.percentile(e, 99) <= 1e-4
+    # SMBH forces are FP64 in both modes (compensated on the GPU)
+    sc = bh_scale(w.pos, w.mass, w.eps, w.bh_pos)
+    assert np.all(np.linalg.norm(h["bacc"] - st.bh_acc, axis=1) <= 1e-12 * sc)
+    assert np.allclose(h["bpot"], st.bh_pot, rtol=1e-12, atol=0)
+
+
+def test_kdk_steps_with_smbh():
+    say("kdk steps")
+    from paper_1507_01009_amd import binding as B
+    w = ics.hernquist_c2(n=32768)
+    dt = 1e-3
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    ctx.forces(d.sys)
+    for _ in range(3):
+        ctx.step_kdk(d.sys, dt)
+    ctx.sync()
+    h = d.host()
+    st = ostate(w)
+    osteps.forces(st)
+    for _ in range(3):
+        osteps.kdk_step(st, dt)
+    assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-13 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-12 * np.abs(st.vel).max()
+    assert rel_err(h["acc"], st.acc).max() <= 1e-11
+    assert np.allclose(h["bpos"], st.bh_pos, rtol=0, atol=1e-15)
+
+
+def _blocks(ctx, w, nlev=8, dt_max=2.0 ** -6):
+    import torch
+    n = w.n
+    level = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    t4e2 = to_dev(np.full(n, 0.3 ** 4 * w.eps ** 2))
+    idx = torch.zeros(n, dtype=torch.int32, device="cuda")
+    na = torch.zeros(1, dtype=torch.int32, device="cuda")
+    k = torch.zeros(1, dtype=torch.int64, device="cuda")
+    blk = ctx.make_blocks(level, t4e2, idx, na, k, dt_max, nlev)
+    return blk, (level, t4e2, idx, na, k)
+
+
+def test_block_substeps_match_oracle():
+    say("block substeps")
+    from paper_1507_01009_amd import binding as B
+    w = ics.hernquist_c4(n=8192)
+    # a coarse top step so that a small sphere spreads over the levels
+    nlev, dt_max = 8, 0.25
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    blk, keep = _blocks(ctx, w, nlev, dt_max)
+    ctx.forces(d.sys)
+    nsub = 40
+    for _ in range(nsub):
+        ctx.step_block(d.sys, blk)
+    ctx.sync()
+    h = d.host()
+    glev = keep[0].cpu().numpy()
+    st = ostate(w)
+    osteps.forces(st)
+    level = np.zeros(w.n, np.uint8)
+    t4e2 = np.full(w.n, 0.3 ** 4 * w.eps ** 2)
+    k = 0
+    counts = []
+    for _ in range(nsub):
+        k, act = osteps.block_substep(st, level, t4e2, k, dt_max, nlev)
+        counts.append(act.size)
+    assert int(keep[4].item()) == nsub
+    assert np.array_equal(glev, level)
+    assert len(set(counts)) > 1                       # uneven active sets
+    assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-12 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-11 * np.abs(st.vel).max()
+    act_dev = keep[2].cpu().numpy()[:int(keep[3].item())]
+    assert np.array_equal(act_dev, oracle.active_at(level, nlev, k))
+
+
+def test_block_substep_graph_replay():
+    say("block graph")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    w = ics.hernquist_c4(n=8192)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        runs = []
+        for mode in ("eager", "graph"):
+            ctx = B.Context(w.n, stream=s)
+            d = Dev(ctx, w)
+            blk, keep = _blocks(ctx, w, 8, 0.25)
+            ctx.forces(d.sys)
+            ctx.step_block(d.sys, blk)        # first substep eagerly (tables seen)
+            ctx.sync()
+            if mode == "eager":
+                for _ in range(8):
+                    ctx.step_block(d.sys, blk)
+            else:
+                ctx.graph_begin()
+                ctx.step_block(d.sys, blk)
+                g = ctx.graph_end()
+                for _ in range(8):
+                    g.launch(s)
+                    s.synchronize()
+            s.synchronize()
+            ctx.sync()
+            runs.append((d.host(), keep[0].cpu().numpy(), int(keep[4].item())))
+        (a, la, ka), (b, lb, kb) = runs
+        assert ka == kb == 9
+        assert np.array_equal(la, lb)
+        for key in ("pos", "vel", "acc", "bpos", "bvel"):
+            assert np.array_equal(a[key], b[key]), key
+
+
+def test_batch_kdk_graph_matches_separate_oracle_runs():
+    say("batch kdk graph")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    w = ics.batch_c5(S=5, nmin=2000, nmax=12000)
+    dt = 1e-3
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = B.Context(w.n, max_systems=5, stream=s)
+        d = Dev(ctx, w)
+        ctx.forces(d.sys)
+        ctx.step_kdk(d.sys, dt)
+        ctx.sync()
+        ctx.graph_begin()
+        ctx.step_kdk(d.sys, dt)
+        g = ctx.graph_end()
+        g.launch(s)
+        s.synchronize()
+        ctx.sync()
+        h = d.host()
+    st = ostate(w)
+    osteps.forces(st)
+    for _ in range(2):
+        osteps.kdk_step(st, dt)
+    assert rel_err(h["acc"], st.acc).max() <= 1e-11
+    assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-13 * np.abs(st.pos).max()
+    # each system evolved alone gives the same result
+    for sidx in (0, 3):
+        lo, hi = w.sys_off[sidx], w.sys_off[sidx + 1]
+        one = ics.Workload("one", w.pos[lo:hi], w.vel[lo:hi], w.mass[lo:hi], w.eps, w.theta,
+                           np.array([0, hi - lo]), w.bh_pos[sidx:sidx + 1],
+                           w.bh_vel[sidx:sidx + 1], w.bh_mass[sidx:sidx + 1],
+                           w.bh_eps[sidx:sidx + 1], np.zeros(1, np.int32))
+        o1 = ostate(one)
+        osteps.forces(o1)
+        for _ in range(2):
+            osteps.kdk_step(o1, dt)
+        assert np.array_equal(o1.pos, st.pos[lo:hi])
+
+
+def test_autotune_returns_a_listed_config():
+    say("autotune")
+    from paper_1507_01009_amd import binding as B
+    w = ics.plummer_c1()
+    ctx = B.Context(w.n)
+    pos, mass = to_dev(w.pos), to_dev(w.mass)
+    best = ctx.autotune(pos, mass, w.eps, w.theta, leaf_list=[4, 8], group_list=[32, 64],
+                        waves_list=[8, 16], repeats=2)
+    assert best["leaf_size"] in (4, 8) and best["group_size"] in (32, 64)
+    assert best["waves_per_cu"] in (8, 16) and best["ms"] > 0
+    import torch
+    acc = torch.zeros((w.n, 3), dtype=torch.float64, device="cuda")
+    ctx.build_tree(pos)
+    ctx.compute_moments(mass)
+    ctx.tree_forces(w.eps, w.theta, acc)
+    ctx.sync()
+    ev = oracle.tree_forces(w.pos, w.mass, w.eps, w.theta, best["leaf_size"],
+                            best["group_size"])
+    assert rel_err(acc.cpu().numpy(), ev.acc).max() <= 1e-12
