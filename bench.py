@@ -1,18 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the tree-gravity hot path on one MI355X.
 
-One step = one pass of the whole path over the workload: half kick, drift,
+One step = one native kick-drift-kick call (tg_step_kdk): half kick, drift,
 tree build (cube, Morton keys, radix sort, gather, octree, groups), moments,
-group walk with P2P/P2M sums for every star, FP64 direct SMBH <-> star and
-SMBH <-> SMBH forces, half kick.  Default workload: Dehnen gamma = 1.5 cusp,
-N = 1 048 576 equal-mass stars, SMBH binary 2 x 0.005 at separation 0.01,
-eps = 1e-3, theta = 0.5, leaf 8, group 64.  Inputs are seeded synthetic
-draws of that model, resident in HBM before timing starts.
+group walk with P2P/P2M sums for every star (FP64 SMBH terms added per
+star), FP64 direct SMBH <- star and SMBH <-> SMBH forces, half kick.
+Default workload: Dehnen gamma = 1.5 cusp, N = 1 048 576 equal-mass stars,
+SMBH binary 2 x 0.005 at separation 0.01, eps = 1e-3, theta = 0.5, leaf 8,
+group 64.  Inputs are seeded synthetic draws of that model, resident in HBM
+before timing starts.
 
 Prints ONE JSON line.  value = interactions/s (P2P pairs + particle-cell
 pairs per second of whole-step wall time) of the mixed-precision path; the
-FP64 path, forces/s, the mixed-vs-FP64 error, the walk kernel's roofline and
-the CPU oracle baseline are reported beside it.
+FP64 path, forces/s, the errors (mixed vs FP64, both vs the direct sum), the
+walk kernel's roofline and the CPU oracle baseline are reported beside it,
+plus measurements of the other workloads (KDK energy check, block steps,
+batched realisations) unless --no-extra.
 """
 from __future__ import annotations
 
@@ -51,61 +54,87 @@ def parse():
     ap.add_argument("--dt", type=float, default=1e-5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     return ap.parse_args()
 
 
+def percentiles(e):
+    import numpy as np
+    return {"p50": float(np.median(e)), "p90": float(np.percentile(e, 90)),
+            "p99": float(np.percentile(e, 99)), "p999": float(np.percentile(e, 99.9)),
+            "max": float(e.max())}
+
+
+class DevState:
+    """A workload resident in HBM and its tg_system view (native steps)."""
+
+    def __init__(self, ctx, w):
+        import numpy as np
+        import torch
+        f64 = dict(dtype=torch.float64, device="cuda")
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+        self.w = w
+        self.pos, self.vel, self.mass = t(w.pos), t(w.vel), t(w.mass)
+        self.acc = torch.zeros((w.n, 3), **f64)
+        self.pot = torch.zeros(w.n, **f64)
+        nb = w.bh_mass.shape[0]
+        self.nb = nb
+        self.bpos, self.bvel = t(w.bh_pos.reshape(-1, 3)), t(w.bh_vel.reshape(-1, 3))
+        self.bm, self.be = t(w.bh_mass), t(w.bh_eps)
+        self.bacc = torch.zeros((max(nb, 1), 3), **f64)
+        self.bpot = torch.zeros(max(nb, 1), **f64)
+        S = w.sys_off.shape[0] - 1
+        bseg = np.zeros(S + 1, np.int64)
+        for s in range(S):
+            bseg[s + 1] = bseg[s] + int((w.bh_sys == s).sum())
+        self.bseg = bseg
+        self.sys = self.view(ctx, 0, w.n, 0, nb, w.sys_off if S > 1 else None,
+                             bseg if nb else None)
+
+    def view(self, ctx, lo, hi, blo, bhi, sys_off=None, bseg=None):
+        """tg_system over stars [lo, hi) and SMBHs [blo, bhi) (slices)."""
+        w = self.w
+        nb = bhi - blo
+        return ctx.make_system(
+            self.pos[lo:hi], self.vel[lo:hi], self.acc[lo:hi], self.mass[lo:hi], w.eps,
+            w.theta, pot=self.pot[lo:hi], sys_off=sys_off,
+            bh_pos=self.bpos[blo:bhi] if nb else None,
+            bh_vel=self.bvel[blo:bhi] if nb else None,
+            bh_acc=self.bacc[blo:bhi] if nb else None,
+            bh_mass=self.bm[blo:bhi] if nb else None,
+            bh_eps=self.be[blo:bhi] if nb else None,
+            bh_pot=self.bpot[blo:bhi] if nb else None, bh_seg=bseg)
+
+    def energy(self):
+        """Kinetic + potential energy of stars and SMBHs (pot includes G)."""
+        m, v, p = self.mass.cpu().numpy(), self.vel.cpu().numpy(), self.pot.cpu().numpy()
+        e = 0.5 * (m * (v * v).sum(1)).sum() + 0.5 * (m * p).sum()
+        if self.nb:
+            bm = self.bm.cpu().numpy()
+            bv = self.bvel.cpu().numpy()[:self.nb]
+            bp = self.bpot.cpu().numpy()[:self.nb]
+            e += 0.5 * (bm * (bv * bv).sum(1)).sum() + 0.5 * (bm * bp).sum()
+        return float(e)
+
+
 class Step:
-    """Device state and one full step through the C ABI."""
+    """The benchmark step: one native kick-drift-kick call (tg_step_kdk)."""
 
     def __init__(self, w, precision, leaf, group, waves, dt):
-        import torch
         from paper_1507_01009_amd import binding as B
-        self.B = B
         self.w = w
         self.dt = dt
         self.ctx = B.Context(w.n, leaf_size=leaf, group_size=group, precision=precision,
                              waves_per_cu=waves)
-        dev = "cuda"
-        f64 = torch.float64
-        self.pos = torch.from_numpy(w.pos.copy()).to(dev)
-        self.vel = torch.from_numpy(w.vel.copy()).to(dev)
-        self.mass = torch.from_numpy(w.mass.copy()).to(dev)
-        self.eps_s = torch.full((w.n,), w.eps, dtype=f64, device=dev)
-        self.acc = torch.zeros((w.n, 3), dtype=f64, device=dev)
-        self.pot = torch.zeros(w.n, dtype=f64, device=dev)
-        self.bpos = torch.from_numpy(w.bh_pos.copy()).to(dev)
-        self.bvel = torch.from_numpy(w.bh_vel.copy()).to(dev)
-        self.bm = torch.from_numpy(w.bh_mass.copy()).to(dev)
-        self.be = torch.from_numpy(w.bh_eps.copy()).to(dev)
-        self.bacc = torch.zeros((w.bh_mass.shape[0], 3), dtype=f64, device=dev)
-        self.bpot = torch.zeros(w.bh_mass.shape[0], dtype=f64, device=dev)
-        self.forces()
-
-    def forces(self):
-        c, w = self.ctx, self.w
-        c.build_tree(self.pos)
-        c.compute_moments(self.mass)
-        c.tree_forces(w.eps, w.theta, self.acc, self.pot)
-        if self.bm.shape[0]:
-            c.direct_fp64(self.bpos, self.bm, self.be, self.pos, self.eps_s, self.acc,
-                          self.pot, accumulate=True)
-            c.direct_fp64(self.pos, self.mass, self.eps_s, self.bpos, self.be, self.bacc,
-                          self.bpot)
-            c.direct_fp64(self.bpos, self.bm, self.be, self.bpos, self.be, self.bacc,
-                          self.bpot, self_pairs=True, accumulate=True)
+        self.d = DevState(self.ctx, w)
+        self.ctx.forces(self.d.sys)
+        self.acc = self.d.acc
 
     def step(self):
-        c, dt = self.ctx, self.dt
-        c.kick(self.vel, self.acc, dt)
-        c.kick(self.bvel, self.bacc, dt)
-        c.drift(self.pos, self.vel, dt)
-        c.drift(self.bpos, self.bvel, dt)
-        self.forces()
-        c.kick(self.vel, self.acc, dt)
-        c.kick(self.bvel, self.bacc, dt)
+        self.ctx.step_kdk(self.d.sys, self.dt)
 
 
 def time_path(st, steps, warmup):
@@ -142,17 +171,18 @@ def time_path(st, steps, warmup):
     }
 
 
-def graph_ms(st, steps):
-    """Same step captured once into a HIP graph and replayed."""
+def graph_ms(ctx, step, steps):
+    """The same step captured once into a HIP graph and replayed."""
     import torch
+    torch.cuda.synchronize()
     s = torch.cuda.Stream()
-    st.ctx.set_stream(s)
+    ctx.set_stream(s)
     with torch.cuda.stream(s):
-        st.step()
+        step()
         s.synchronize()
-        st.ctx.graph_begin()
-        st.step()
-        g = st.ctx.graph_end()
+        ctx.graph_begin()
+        step()
+        g = ctx.graph_end()
         g.launch(s)
         s.synchronize()
         t0 = time.perf_counter()
@@ -160,8 +190,8 @@ def graph_ms(st, steps):
             g.launch(s)
         s.synchronize()
         t1 = time.perf_counter()
-    st.ctx.sync()
-    st.ctx.set_stream(torch.cuda.current_stream())
+    ctx.sync()
+    ctx.set_stream(torch.cuda.current_stream())
     return 1e3 * (t1 - t0) / steps
 
 
@@ -185,6 +215,23 @@ def traffic_for(kernel_file, workload):
         return None
 
 
+def direct_errors(w, accs, n_samples=128):
+    """Per-percentile error of each path against the exact direct sum (stars
+    and SMBHs, long double) on seeded sample targets."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(99)
+    tg = np.sort(rng.choice(w.n, n_samples, replace=False))
+    ref, _ = oracle.direct(w.pos, w.mass, w.eps, tg, xpos=w.bh_pos, xmass=w.bh_mass,
+                           xeps=w.bh_eps)
+    out = {}
+    for name, a in accs.items():
+        e = np.linalg.norm(a[tg] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        out[name + "_vs_direct_sum"] = percentiles(e)
+    out["direct_sum_samples"] = int(n_samples)
+    return out
+
+
 def cpu_baseline(w, leaf, group, seconds):
     """The oracle (plain C, all host threads) on a bounded sample of the same
     step: full tree build, then the walk + evaluation of random groups until
@@ -195,7 +242,7 @@ def cpu_baseline(w, leaf, group, seconds):
     t0 = time.perf_counter()
     tree = oracle.build_tree(w.pos, None, leaf)
     spos, smass = oracle.sorted_arrays(tree, w.pos, w.mass)
-    mom = oracle.moments(tree, spos, smass)
+    oracle.moments(tree, spos, smass)
     g = oracle.groups(tree, group)
     t_build = time.perf_counter() - t0
     rng = np.random.default_rng(1234)
@@ -221,6 +268,130 @@ def cpu_baseline(w, leaf, group, seconds):
             "step_seconds_est": t_step}
 
 
+# ---------------------------------------------------------------- extras
+def extra_kdk_energy(steps=100):
+    """Hernquist N = 131 072 + SMBH, dt = 1e-3: both precisions, energy error."""
+    import torch
+    from paper_1507_01009_amd import binding as B, ics
+    w = ics.hernquist_c2()
+    out = {"workload": w.name, "steps": steps, "dt": 1e-3}
+    for name, prec in (("fp64", B.TG_FP64), ("mixed", B.TG_MIXED)):
+        st = Step(w, prec, 8, 64, 0, 1e-3)
+        st.ctx.sync()
+        e0 = st.d.energy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st.ctx.sync()
+        e1 = st.d.energy()
+        out[name] = {"ms_per_step": 1e3 * (t1 - t0) / steps,
+                     "rel_energy_error": abs(e1 - e0) / abs(e0)}
+        st.ctx.close()
+    return out
+
+
+def extra_blocksteps(substeps=1000, n=None):
+    """Hernquist N = 4 194 304 + SMBH, 8 levels, dt_max = 2^-6, tau = 0.3 for
+    the stars (the SMBH takes the smallest step): one captured substep,
+    replayed."""
+    import numpy as np
+    import torch
+    from paper_1507_01009_amd import binding as B, ics
+    w = ics.hernquist_c4() if n is None else ics.hernquist_c4(n=n)
+    nlev, dt_max = 8, 2.0 ** -6
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = B.Context(w.n, precision=B.TG_MIXED, stream=s)
+        d = DevState(ctx, w)
+        level = torch.zeros(w.n, dtype=torch.uint8, device="cuda")
+        t4e2 = torch.full((w.n,), 0.3 ** 4 * w.eps ** 2, dtype=torch.float64, device="cuda")
+        idx = torch.zeros(w.n, dtype=torch.int32, device="cuda")
+        na = torch.zeros(1, dtype=torch.int32, device="cuda")
+        k = torch.zeros(1, dtype=torch.int64, device="cuda")
+        blk = ctx.make_blocks(level, t4e2, idx, na, k, dt_max, nlev)
+        ctx.forces(d.sys)
+        ctx.step_block(d.sys, blk)
+        ctx.sync()
+        ctx.graph_begin()
+        ctx.step_block(d.sys, blk)
+        g = ctx.graph_end()
+        fr = []
+        for _ in range(128):              # one full cycle of level 0, untimed
+            g.launch(s)
+            s.synchronize()
+            fr.append(int(na.item()) / w.n)
+        ctx.reset_counts()
+        ctx.sync()
+        t0 = time.perf_counter()
+        for _ in range(substeps):
+            g.launch(s)
+        s.synchronize()
+        t1 = time.perf_counter()
+        ctx.sync()
+        cnt = ctx.get_cumulative_counts()
+        lv = np.bincount(level.cpu().numpy(), minlength=nlev)
+        ctx.close()
+    sec = t1 - t0
+    fr = np.array(fr)
+    return {"workload": w.name, "substeps": substeps, "ms_per_substep": 1e3 * sec / substeps,
+            "interactions_per_s": (cnt["n_p2p"] + cnt["n_p2m"]) / sec,
+            "forces_per_s": cnt["n_targets"] / sec,
+            "level_histogram": lv.tolist(),
+            "active_fraction": {"min": float(fr.min()), "median": float(np.median(fr)),
+                                "max": float(fr.max()), "mean": float(fr.mean())},
+            "precision": "mixed", "graph": True}
+
+
+def extra_batch(steps=20):
+    """32 realisations (N log-uniform in [2^14, 2^19], gamma 0.5/1/1.5, one
+    SMBH each) in one context: autotuned sizes, one captured KDK step; and
+    the same systems stepped one after another."""
+    import torch
+    from paper_1507_01009_amd import binding as B, ics
+    w = ics.batch_c5()
+    S = w.sys_off.shape[0] - 1
+    ctx = B.Context(w.n, max_systems=S, precision=B.TG_MIXED)
+    d = DevState(ctx, w)
+    best = ctx.autotune(d.pos, d.mass, w.eps, w.theta, sys_off=w.sys_off,
+                        leaf_list=[8, 12, 16], group_list=[48, 64], waves_list=[12, 16],
+                        repeats=2)
+    ctx.forces(d.sys)
+    ctx.reset_counts()
+    ms_graph = graph_ms(ctx, lambda: ctx.step_kdk(d.sys, 1e-3), steps)
+    cnt = ctx.get_cumulative_counts()
+    n_steps = steps + 2                       # eager + first replay + timed replays
+    # one system at a time through a single-system context (same sizes)
+    nmax = int(max(w.sys_off[1:] - w.sys_off[:-1]))
+    one = B.Context(nmax, leaf_size=best["leaf_size"], group_size=best["group_size"],
+                    precision=B.TG_MIXED, waves_per_cu=best["waves_per_cu"])
+    views = [d.view(one, int(w.sys_off[s]), int(w.sys_off[s + 1]), s, s + 1)
+             for s in range(S)]
+    for v in views:
+        one.forces(v)
+    one.sync()
+    reps = max(3, steps // 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for v in views:
+            one.step_kdk(v, 1e-3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    one.sync()
+    ms_sep = 1e3 * (t1 - t0) / reps
+    out = {"workload": w.name, "systems": S, "n_total": int(w.n), "autotuned": best,
+           "ms_per_step_batched_graph": ms_graph,
+           "interactions_per_s_batched": (cnt["n_p2p"] + cnt["n_p2m"]) / n_steps / (ms_graph * 1e-3),
+           "ms_per_step_separate_systems": ms_sep,
+           "speedup_batched_vs_separate": ms_sep / ms_graph, "precision": "mixed"}
+    one.close()
+    ctx.close()
+    return out
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -244,19 +415,20 @@ def main():
         st.ctx.sync()
         accs[name] = st.acc.cpu().numpy().copy()
         r = time_path(st, a.steps, a.warmup)
-        r["graph_ms_per_step"] = graph_ms(st, max(3, a.steps // 2))
+        r["graph_ms_per_step"] = graph_ms(st.ctx, st.step, max(3, a.steps // 2))
         res[name] = r
         log("bench: %s %.3f ms/step, %.3g interactions/s, walk %.3f ms (%.2f TFLOP/s)" % (
             name, r["ms_per_step"], r["interactions_per_s"], r["walk_ms_avg"],
             r["walk_tflops"]))
+        st.ctx.close()
         del st
         torch.cuda.empty_cache()
-    err = None
+    err = {}
     if "mixed" in accs and "fp64" in accs:
         e = np.linalg.norm(accs["mixed"] - accs["fp64"], axis=1) / np.linalg.norm(accs["fp64"], axis=1)
-        err = {"mixed_vs_fp64": {"p50": float(np.median(e)), "p90": float(np.percentile(e, 90)),
-                                 "p99": float(np.percentile(e, 99)),
-                                 "p999": float(np.percentile(e, 99.9)), "max": float(e.max())}}
+        err["mixed_vs_fp64"] = percentiles(e)
+    if not a.no_cpu:
+        err.update(direct_errors(w, accs))
     head = res["mixed"] if "mixed" in res else res["fp64"]
     head_name = "mixed" if "mixed" in res else "fp64"
     peak = PEAK_FP32 if head_name == "mixed" else PEAK_FP64
@@ -292,6 +464,16 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 2 * src.numel() * 4
         del src, dst
+    if not a.no_extra:
+        log("bench: KDK energy check (Hernquist 131k)")
+        out["kdk_energy"] = extra_kdk_energy()
+        torch.cuda.empty_cache()
+        log("bench: block steps (Hernquist 4M)")
+        out["blocksteps"] = extra_blocksteps()
+        torch.cuda.empty_cache()
+        log("bench: batch of 32 realisations")
+        out["batch"] = extra_batch()
+        torch.cuda.empty_cache()
     if not a.no_cpu:
         log("bench: CPU oracle baseline (~%.0f s)" % a.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(w, a.leaf, a.group, a.cpu_seconds)
