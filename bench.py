@@ -35,7 +35,7 @@ PEAK_FP64 = 78.6      # TFLOP/s, MI355X vector FP64
 PEAK_FP32 = 157.3     # TFLOP/s, MI355X vector FP32 (published, packed)
 PEAK_FP32_UNPACKED = 78.6
 FLOPS_P2P = 19
-FLOPS_P2M = 58
+FLOPS_P2M = 54
 
 
 def log(*a):

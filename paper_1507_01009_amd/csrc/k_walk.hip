@@ -2,42 +2,61 @@
 // test, and the softened P2P / quadrupole P2M force sums.
 //
 // One 64-lane wavefront owns one group of targets at a time (persistent
-// grid, groups taken from an atomic queue).  The walk is breadth first: the
+// grid, groups taken from per-XCD queues).  The walk is breadth first: the
 // wave tests 64 frontier cells at once against the group's box,
 //   accept iff side^2 < theta^2 d^2,  d = box-to-centre-of-mass distance,
 // evaluated in double precision with no contraction (bit-identical decisions
 // to the plain definition).  Ballot + mbcnt compaction appends accepted
 // cells to an LDS P2M list and the particles of refused leaves to an LDS
 // P2P queue; refused internal cells push their children onto the next
-// frontier (wave prefix sum of child counts).  Whenever a list holds 64
-// sources it is flushed: the 64 sources are staged in LDS once and every
-// lane, owning one target (or one target x source slice when the group has
-// fewer than 33 targets), sums their forces on the vector ALUs.  No MFMA:
-// nothing here is a dense contraction.
+// frontier (wave prefix sum of child counts).  Whenever a list holds a full
+// tile it is flushed: the sources are staged in LDS once and each lane sums
+// a contiguous slice of them onto the T (1..3) targets it holds, on the
+// vector ALUs.  No MFMA: a P2M pair is a chain of dependent scalar
+// operations around one rsqrt, and the bilinear parts that could be cast as
+// products have an N dimension of 1-9, which FP32 MFMA (twice the unpacked
+// VALU rate) would mostly pad.
 //
 // Precision modes.  FP64: all sums in double, rsqrt from the hardware
 // estimate plus one third-order correction (Householder).  MIXED: the walk
 // decisions stay double; targets and sources are taken relative to the
 // group's box centre c_g in double and rounded to float, the interaction
-// arithmetic is float with the hardware rsqrt, each 64-source tile is summed
-// in float and folded into a (hi, lo) float pair with an error-free
-// TwoSum; the result is hi + lo in double.
+// arithmetic is float with the hardware rsqrt, each tile's partial sums are
+// folded into a (hi, lo) float pair with an error-free TwoSum; the result is
+// hi + lo in double.
 //
 // Flops per interaction as written in p2p_term / p2m_term (FMA = 2; the
 // rsqrt and, in FP64, its refinement are not counted):
 //   P2P 19: 3 sub, 6 for r^2 + eps^2, 3 for m D1 and m D3, 6 for the three
 //          accelerations, 1 for the potential.
-//   P2M 58: 3 sub, 6 for r^2 + eps^2, 4 for D2..D7, 15 for S x, 5 for x.S.x,
-//          2 for W, 6 for the radial coefficient, 12 for the accelerations,
-//          5 for the potential (the 3S and tr S of a cell are formed once
-//          per tile, not per interaction).
+//   P2M 54: 3 sub, 6 for r^2 + eps^2, 3 for D2..D5, 15 for Q x, 6 for W,
+//          2 for D4 W, 3 for the radial coefficient, 12 for the
+//          accelerations, 4 for the potential (Q = 3S - T I and T eps^2 of a
+//          cell are formed once per tile, not per interaction).
+#include <type_traits>
+
 #include "tg_internal.h"
 
 namespace tg {
 
-constexpr int kQCap = 64 + 64 * 8;          // P2P particle queue (LDS); larger leaves take the slow path
-constexpr int kTile = 128;                  // source tile: 64 live entries + 64 zero-mass pads
-constexpr int kMCap = 128;                  // P2M cell list (LDS)
+// Most targets a lane holds (the per-group choice is 1..this), and the
+// occupancy the kernel is compiled for, per precision mode.
+#ifndef TG_WALK_MAXT_MIXED
+#define TG_WALK_MAXT_MIXED 2
+#endif
+#ifndef TG_WALK_MAXT_FP64
+#define TG_WALK_MAXT_FP64 2
+#endif
+#ifndef TG_WALK_WAVES_MIXED
+#define TG_WALK_WAVES_MIXED 4
+#endif
+#ifndef TG_WALK_WAVES_FP64
+#define TG_WALK_WAVES_FP64 3
+#endif
+
+constexpr int kTile = 128;                  // source tile entries (a flush uses <= 127)
+constexpr int kMCap = 128 + 64;             // P2M cell list (LDS): < one flush + one append
+constexpr int kQCap = 128 + 64 * 8;         // P2P particle queue (LDS); overflow goes leaf by leaf
 
 struct WalkArgs {
   const uint8_t *nchild;
@@ -134,11 +153,16 @@ template <> struct Vec4<double> { using T = double4; };
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return rsqrt_dp(x); }
 
-// Softened quadrupole term.  Cell: a = {c, M}, b = {3Sxx, 3Syy, 3Szz, T},
-// c = {3Sxy, 3Sxz, 3Syz, -}, with x = target - c:
-//   W = 3 x.S.x - T r^2   (= x.Q.x - T eps^2 since r^2 = |x|^2 + eps^2)
-//   a -= (M D3 + T D5 + 2.5 D7 W) x - 3 D5 S x,  phi -= M D1 + 0.5 D5 W
-// which is a = -M D3 x + D5 Q x - 2.5 D7 W x with Q = 3S - T I.
+// Softened quadrupole term of one cell on one target, x = target - com.
+// Cell: a = {com, M}, b = {Qxx, Qyy, Qzz, T eps^2}, c = {Qxy, Qxz, Qyz, -}
+// with the traceless Q = 3S - T I, T = tr S.  With r^2 = |x|^2 + eps^2 and
+// D_n = r^-n, the expansion of the softened potential about the centre of
+// mass gives
+//   W = x.Q.x - T eps^2      (= 3 x.S.x - T r^2)
+//   a += -(M D3 + 2.5 D7 W) x + D5 Q x
+//   phi -= M D1 + 0.5 D5 W
+// (the same as -(M D3 + T D5 + 2.5 D7 W) x + 3 D5 S x, with T x folded
+// into Q x).
 template <class R>
 __device__ __forceinline__ void p2m_term(typename Vec4<R>::T a, typename Vec4<R>::T b,
                                          typename Vec4<R>::T c, R tx, R ty, R tz, R e2,
@@ -146,17 +170,17 @@ __device__ __forceinline__ void p2m_term(typename Vec4<R>::T a, typename Vec4<R>
   const R x = tx - a.x, y = ty - a.y, z = tz - a.z;
   const R r2 = fma(z, z, fma(y, y, fma(x, x, e2)));
   const R D1 = rsq(r2);
-  const R D2 = D1 * D1, D3 = D1 * D2, D5 = D3 * D2, D7 = D5 * D2;
-  const R Sx = fma(c.y, z, fma(c.x, y, b.x * x));
-  const R Sy = fma(c.z, z, fma(b.y, y, c.x * x));
-  const R Sz = fma(b.z, z, fma(c.z, y, c.y * x));
-  const R xSx = fma(z, Sz, fma(y, Sy, x * Sx));
-  const R W = fma(-b.w, r2, xSx);
-  const R C = fma(R(2.5) * D7, W, fma(b.w, D5, a.w * D3));
-  ax = fma(D5, Sx, fma(-C, x, ax));
-  ay = fma(D5, Sy, fma(-C, y, ay));
-  az = fma(D5, Sz, fma(-C, z, az));
-  ph -= fma(R(0.5) * D5, W, a.w * D1);
+  const R u = D1 * D1, D3 = D1 * u, D5 = D3 * u;
+  const R Qx = fma(c.y, z, fma(c.x, y, b.x * x));
+  const R Qy = fma(c.z, z, fma(b.y, y, c.x * x));
+  const R Qz = fma(b.z, z, fma(c.z, y, c.y * x));
+  const R W = fma(z, Qz, fma(y, Qy, x * Qx)) - b.w;
+  const R k = (u * W) * u;                     // D4 W
+  const R C = D3 * fma(R(2.5), k, a.w);        // M D3 + 2.5 D7 W
+  ax = fma(D5, Qx, fma(-C, x, ax));
+  ay = fma(D5, Qy, fma(-C, y, ay));
+  az = fma(D5, Qz, fma(-C, z, az));
+  ph = fma(-D1, fma(R(0.5), k, a.w), ph);      // M D1 + 0.5 D5 W
 }
 
 // Softened particle term, source s = {position, m}.
@@ -175,145 +199,174 @@ __device__ __forceinline__ void p2p_term(typename Vec4<R>::T s, R tx, R ty, R tz
 }
 
 // ---------------------------------------------------------------- tiles
-struct P2MTileD { double4 a, b, c; };   // {cx,cy,cz,M} {Sxx,Syy,Szz,T} {Sxy,Sxz,Syz,0}
+struct P2MTileD { double4 a, b, c; };
 struct P2MTileF { float4 a, b, c; };
 
-// Source tiles in LDS.  Entries [k, 128) of a tile holding k sources have
-// zero mass, so every lane runs the same trip count with no masking: lane
-// slice s reads entries s, s + slices, ...  The P2M half [64, 128) is zeroed
-// once per kernel (nothing else overlaps it); the P2P half is rewritten per
-// flush because the P2M entries overlap it.
+// Targets per lane: a group of nt targets is spread over the 64 lanes as
+// lt = ceil(nt / T) lane-targets (each lane holding up to T targets) times
+// slices = floor(64 / lt) source slices; T is chosen per group to minimise
+// the evaluations per source, T / slices.
+template <bool kMixed> struct Shape {
+  static constexpr int kMaxT = kMixed ? TG_WALK_MAXT_MIXED : TG_WALK_MAXT_FP64;
+  static_assert(kMaxT >= 1 && kMaxT <= 3, "1..3 targets per lane");
+};
+
+// Source tiles in LDS.  A flush of k sources fills entries [0, slices *
+// trips) with trips = ceil(k / slices), the entries past k with zero mass;
+// slice s evaluates the contiguous entries [s trips, (s + 1) trips), so every
+// lane runs the same trip count with no masking.  Full flushes take exactly
+// slices * ceil(64 / slices) (<= 127) sources.  `red` holds the per-lane
+// sums of the final slice reduction.
 template <bool kMixed> union TileMem;
 template <> union __align__(16) TileMem<true> {
   P2MTileF m[kTile];
   float4 p[kTile];
-  double red[256];
+  double red[Shape<true>::kMaxT * 256];
 };
 template <> union __align__(16) TileMem<false> {
   P2MTileD m[kTile];
   double4 p[kTile];
-  double red[256];
-};
-
-template <bool kMixed>
-struct Target {
-  // double path
-  double x, y, z;
-  double ax, ay, az, ph;
-  // mixed path
-  float fx, fy, fz;
-  float tax, tay, taz, tph;    // current tile partial sums
-  float hax, hay, haz, hph;    // compensated totals (hi)
-  float lax, lay, laz, lph;    // (lo)
+  double red[Shape<false>::kMaxT * 256];
 };
 
 // ------------------------------------------------------- force-mode sink
 template <bool kMixed>
 struct ForceSink {
+  using R = typename std::conditional<kMixed, float, double>::type;
+  using R4 = typename Vec4<R>::T;
+  static constexpr int kMaxT = Shape<kMixed>::kMaxT;
   uint32_t *s_m;
   uint32_t *s_q;
   TileMem<kMixed> *tile;
   uint32_t nm, nq;
   unsigned long long cells, parts;   // wave-uniform totals
-  int my_s, slices;
-  double cgx, cgy, cgz;
-  double eps2;
-  float eps2f;
-  Target<kMixed> t;
+  int T, lt, slices, tfull, F, my_s;
+  double cgx, cgy, cgz;              // coordinate origin of the group (0 in FP64)
+  R e2;
+  double e2d;
+  R tx[kMaxT], ty[kMaxT], tz[kMaxT];
+  // FP64: plain sums in h*; mixed: compensated (h*, l*) float pairs
+  R hax[kMaxT], hay[kMaxT], haz[kMaxT], hph[kMaxT];
+  R lax[kMaxT], lay[kMaxT], laz[kMaxT], lph[kMaxT];
 
-  __device__ void fold() {
+  __device__ void add(int k, R ax, R ay, R az, R ph) {
     if constexpr (kMixed) {
-      two_sum_acc(t.hax, t.lax, t.tax);
-      two_sum_acc(t.hay, t.lay, t.tay);
-      two_sum_acc(t.haz, t.laz, t.taz);
-      two_sum_acc(t.hph, t.lph, t.tph);
-      t.tax = t.tay = t.taz = t.tph = 0.0f;
+      two_sum_acc(hax[k], lax[k], ax);
+      two_sum_acc(hay[k], lay[k], ay);
+      two_sum_acc(haz[k], laz[k], az);
+      two_sum_acc(hph[k], lph[k], ph);
+    } else {
+      hax[k] += ax; hay[k] += ay; haz[k] += az; hph[k] += ph;
+    }
+  }
+
+  template <int kT>
+  __device__ void eval_m(int base, int trips) {
+    R ax[kT], ay[kT], az[kT], ph[kT];
+#pragma unroll
+    for (int k = 0; k < kT; ++k) ax[k] = ay[k] = az[k] = ph[k] = R(0);
+    const auto *e = &tile->m[base];
+    if constexpr (kT == 1) {
+#pragma unroll 2
+      for (int it = 0; it < trips; ++it)
+        p2m_term<R>(e[it].a, e[it].b, e[it].c, tx[0], ty[0], tz[0], e2, ax[0], ay[0], az[0], ph[0]);
+    } else {
+      for (int it = 0; it < trips; ++it) {
+        const R4 a = e[it].a, b = e[it].b, c = e[it].c;
+#pragma unroll
+        for (int k = 0; k < kT; ++k)
+          p2m_term<R>(a, b, c, tx[k], ty[k], tz[k], e2, ax[k], ay[k], az[k], ph[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kT; ++k) add(k, ax[k], ay[k], az[k], ph[k]);
+  }
+
+  template <int kT>
+  __device__ void eval_p(int base, int trips) {
+    R ax[kT], ay[kT], az[kT], ph[kT];
+#pragma unroll
+    for (int k = 0; k < kT; ++k) ax[k] = ay[k] = az[k] = ph[k] = R(0);
+    const R4 *e = &tile->p[base];
+    if constexpr (kT == 1) {
+#pragma unroll 4
+      for (int it = 0; it < trips; ++it)
+        p2p_term<R>(e[it], tx[0], ty[0], tz[0], e2, ax[0], ay[0], az[0], ph[0]);
+    } else {
+#pragma unroll 2
+      for (int it = 0; it < trips; ++it) {
+        const R4 s = e[it];
+#pragma unroll
+        for (int k = 0; k < kT; ++k)
+          p2p_term<R>(s, tx[k], ty[k], tz[k], e2, ax[k], ay[k], az[k], ph[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kT; ++k) add(k, ax[k], ay[k], az[k], ph[k]);
+  }
+
+  __device__ int trips_for(int k) const {
+    return k == F ? tfull : (k + slices - 1) / slices;
+  }
+
+  // P2M tile entry of cell v, relative to the group origin
+  __device__ void stage_cell(const WalkArgs &A, int e, bool live, uint32_t v) {
+    if (live) {
+      const double4 cm = A.com[v];
+      const double4 m0 = reinterpret_cast<const double4 *>(A.mom)[2 * (size_t)v];
+      const double4 m1 = reinterpret_cast<const double4 *>(A.mom)[2 * (size_t)v + 1];
+      // m0 = {M, Sxx, Syy, Szz}, m1 = {Sxy, Sxz, Syz, -}
+      const double T = m0.y + m0.z + m0.w;
+      tile->m[e].a = R4{(R)(cm.x - cgx), (R)(cm.y - cgy), (R)(cm.z - cgz), (R)m0.x};
+      tile->m[e].b = R4{(R)(3.0 * m0.y - T), (R)(3.0 * m0.z - T), (R)(3.0 * m0.w - T),
+                        (R)(T * e2d)};
+      tile->m[e].c = R4{(R)(3.0 * m1.x), (R)(3.0 * m1.y), (R)(3.0 * m1.z), R(0)};
+    } else {
+      tile->m[e].a = tile->m[e].b = tile->m[e].c = R4{R(0), R(0), R(0), R(0)};
     }
   }
 
   __device__ void flush_p2m(const WalkArgs &A, const uint32_t *list, int k) {
-    const unsigned lane = lane_id();
-    // tile: {com - c, M} {3Sxx, 3Syy, 3Szz, T} {3Sxy, 3Sxz, 3Syz, 0}; lanes
-    // past k write zero-mass entries
-    if constexpr (kMixed) {
-      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
-      if ((int)lane < k) {
-        const uint32_t v = list[lane];
-        const double4 cm = A.com[v];
-        const double *o = A.mom + 8 * (size_t)v;
-        a = make_float4((float)(cm.x - cgx), (float)(cm.y - cgy), (float)(cm.z - cgz),
-                        (float)o[0]);
-        b = make_float4((float)(3.0 * o[1]), (float)(3.0 * o[2]), (float)(3.0 * o[3]),
-                        (float)(o[1] + o[2] + o[3]));
-        c = make_float4((float)(3.0 * o[4]), (float)(3.0 * o[5]), (float)(3.0 * o[6]), 0.f);
-      }
-      tile->m[lane].a = a; tile->m[lane].b = b; tile->m[lane].c = c;
-    } else {
-      double4 a = make_double4(0., 0., 0., 0.), b = a, c = a;
-      if ((int)lane < k) {
-        const uint32_t v = list[lane];
-        const double4 cm = A.com[v];
-        const double *o = A.mom + 8 * (size_t)v;
-        a = make_double4(cm.x, cm.y, cm.z, o[0]);
-        b = make_double4(3.0 * o[1], 3.0 * o[2], 3.0 * o[3], o[1] + o[2] + o[3]);
-        c = make_double4(3.0 * o[4], 3.0 * o[5], 3.0 * o[6], 0.0);
-      }
-      tile->m[lane].a = a; tile->m[lane].b = b; tile->m[lane].c = c;
-    }
+    const int lane = (int)lane_id();
+    const int trips = trips_for(k);
+    const int ne = slices * trips;
+    const int e0 = lane, e1 = lane + 64;
+    const uint32_t v0 = e0 < k ? list[e0] : 0u, v1 = e1 < k ? list[e1] : 0u;
+    if (e0 < ne) stage_cell(A, e0, e0 < k, v0);
+    if (e1 < ne) stage_cell(A, e1, e1 < k, v1);
     __syncthreads();
-    const int trips = (k + slices - 1) / slices;
-    if constexpr (kMixed) {
-      float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-#pragma unroll 2
-      for (int it = 0; it < trips; ++it) {
-        const P2MTileF &e = tile->m[my_s + it * slices];
-        p2m_term<float>(e.a, e.b, e.c, t.fx, t.fy, t.fz, eps2f, ax, ay, az, ph);
-      }
-      t.tax += ax; t.tay += ay; t.taz += az; t.tph += ph;
-      fold();
-    } else {
-      double ax = 0., ay = 0., az = 0., ph = 0.;
-#pragma unroll 2
-      for (int it = 0; it < trips; ++it) {
-        const P2MTileD &e = tile->m[my_s + it * slices];
-        p2m_term<double>(e.a, e.b, e.c, t.x, t.y, t.z, eps2, ax, ay, az, ph);
-      }
-      t.ax += ax; t.ay += ay; t.az += az; t.ph += ph;
+    const int base = my_s * trips;
+    if (T == 1) eval_m<1>(base, trips);
+    else if constexpr (kMaxT >= 2) {
+      if (T == 2) eval_m<2>(base, trips);
+      else if constexpr (kMaxT >= 3) eval_m<3>(base, trips);
     }
     __syncthreads();
   }
 
-  __device__ void flush_p2p(const WalkArgs &A, const uint32_t *list, int k) {
-    const unsigned lane = lane_id();
-    if constexpr (kMixed) {
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if ((int)lane < k) {
-        const double4 p = A.spart[list[lane]];
-        v = make_float4((float)(p.x - cgx), (float)(p.y - cgy), (float)(p.z - cgz), (float)p.w);
-      }
-      tile->p[lane] = v;
-      tile->p[64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-    } else {
-      double4 v = make_double4(0., 0., 0., 0.);
-      if ((int)lane < k) v = A.spart[list[lane]];
-      tile->p[lane] = v;
-      tile->p[64 + lane] = make_double4(0., 0., 0., 0.);
+  __device__ void stage_part(const WalkArgs &A, int e, bool live, uint32_t j) {
+    R4 v = R4{R(0), R(0), R(0), R(0)};
+    if (live) {
+      const double4 p = A.spart[j];
+      v = R4{(R)(p.x - cgx), (R)(p.y - cgy), (R)(p.z - cgz), (R)p.w};
     }
+    tile->p[e] = v;
+  }
+
+  __device__ void flush_p2p(const WalkArgs &A, const uint32_t *list, int k) {
+    const int lane = (int)lane_id();
+    const int trips = trips_for(k);
+    const int ne = slices * trips;
+    const int e0 = lane, e1 = lane + 64;
+    const uint32_t j0 = e0 < k ? list[e0] : 0u, j1 = e1 < k ? list[e1] : 0u;
+    if (e0 < ne) stage_part(A, e0, e0 < k, j0);
+    if (e1 < ne) stage_part(A, e1, e1 < k, j1);
     __syncthreads();
-    const int trips = (k + slices - 1) / slices;
-    if constexpr (kMixed) {
-      float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-#pragma unroll 4
-      for (int it = 0; it < trips; ++it)
-        p2p_term<float>(tile->p[my_s + it * slices], t.fx, t.fy, t.fz, eps2f, ax, ay, az, ph);
-      t.tax += ax; t.tay += ay; t.taz += az; t.tph += ph;
-      fold();
-    } else {
-      double ax = 0., ay = 0., az = 0., ph = 0.;
-#pragma unroll 4
-      for (int it = 0; it < trips; ++it)
-        p2p_term<double>(tile->p[my_s + it * slices], t.x, t.y, t.z, eps2, ax, ay, az, ph);
-      t.ax += ax; t.ay += ay; t.az += az; t.ph += ph;
+    const int base = my_s * trips;
+    if (T == 1) eval_p<1>(base, trips);
+    else if constexpr (kMaxT >= 2) {
+      if (T == 2) eval_p<2>(base, trips);
+      else if constexpr (kMaxT >= 3) eval_p<3>(base, trips);
     }
     __syncthreads();
   }
@@ -326,16 +379,16 @@ struct ForceSink {
     nm += c;
     cells += c;
     __syncthreads();
-    if (nm >= 64) {
-      flush_p2m(A, s_m + (nm - 64), 64);
-      nm -= 64;
+    if (nm >= (uint32_t)F) {          // nm < F + 64 <= 2 F: one flush
+      flush_p2m(A, s_m + (nm - F), F);
+      nm -= F;
     }
   }
 
   __device__ void drain_q(const WalkArgs &A) {
-    while (nq >= 64) {
-      flush_p2p(A, s_q + (nq - 64), 64);
-      nq -= 64;
+    while (nq >= (uint32_t)F) {
+      flush_p2p(A, s_q + (nq - F), F);
+      nq -= F;
     }
   }
 
@@ -355,7 +408,7 @@ struct ForceSink {
       drain_q(A);
       return;
     }
-    // rare: leaves larger than n_L (level-21 leaves); one leaf at a time
+    // rare: many large leaves at once; one leaf at a time
     unsigned long long m = mask;
     while (m) {
       const int L = __ffsll((long long)m) - 1;
@@ -486,21 +539,18 @@ struct GroupQueue {
 
 // ------------------------------------------------------------ force kernel
 template <bool kMixed>
-__global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMixed ? TG_WALK_WAVES_MIXED : TG_WALK_WAVES_FP64)))
+void k_walk_forces(WalkArgs A) {
   __shared__ uint32_t s_tgt[64];
   __shared__ uint32_t s_m[kMCap];
   __shared__ uint32_t s_q[kQCap];
   __shared__ TileMem<kMixed> tile;
+  using Sink = ForceSink<kMixed>;
+  using R = typename Sink::R;
+  constexpr int kMaxT = Sink::kMaxT;
   const unsigned lane = lane_id();
   const uint32_t n_groups = A.ctr->n_active_groups;
   unsigned long long tot_p2p = 0, tot_p2m = 0, tot_t = 0, tot_g = 0;
-  // zero-mass pads of the P2M tile (never overwritten afterwards)
-  if constexpr (kMixed) {
-    tile.m[64 + lane].a = tile.m[64 + lane].b = tile.m[64 + lane].c = make_float4(0.f, 0.f, 0.f, 0.f);
-  } else {
-    tile.m[64 + lane].a = tile.m[64 + lane].b = tile.m[64 + lane].c = make_double4(0., 0., 0., 0.);
-  }
-  __syncthreads();
   GroupQueue Q(blockIdx.x);
   for (;;) {
     const uint32_t gi = Q.next(A.ctr, n_groups);
@@ -517,63 +567,84 @@ __global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
     const int nt = __popcll(amask);
     __syncthreads();
     if (nt == 0) continue;   // cannot happen for a listed group; keeps s_tgt reads defined
-    // lanes = target x source slice: slices = floor(64 / nt) copies of the
-    // target set, slice s taking sources s, s + slices, ...
-    const int slices = 64 / nt;
-    ForceSink<kMixed> S;
+    // shape: T targets per lane, lt lane-targets, slices source slices;
+    // minimise T / slices, ties to the larger T
+    int T = 1, lt = nt, slices = 64 / nt;
+#pragma unroll
+    for (int t = 2; t <= kMaxT; ++t) {
+      const int l2 = (nt + t - 1) / t, s2 = 64 / l2;
+      if (t * slices <= T * s2) { T = t; lt = l2; slices = s2; }
+    }
+    Sink S;
     S.s_m = s_m; S.s_q = s_q; S.tile = &tile;
     S.nm = 0; S.nq = 0; S.cells = 0; S.parts = 0;
-    S.slices = slices;
-    const int my_t = (int)lane % nt;
-    const int sl = (int)lane / nt;
-    S.my_s = sl < slices ? sl : 64;          // idle lanes take no sources
-    const bool has_t = sl < slices;
-    const uint32_t r_t = s_tgt[my_t];
-    const double4 p = A.spart[r_t];
-    S.cgx = 0.5 * (lo[0] + hi[0]);
-    S.cgy = 0.5 * (lo[1] + hi[1]);
-    S.cgz = 0.5 * (lo[2] + hi[2]);
-    S.eps2 = A.eps2;
-    S.eps2f = (float)A.eps2;
-    S.t.x = p.x; S.t.y = p.y; S.t.z = p.z;
-    S.t.ax = S.t.ay = S.t.az = S.t.ph = 0.0;
-    S.t.fx = (float)(p.x - S.cgx); S.t.fy = (float)(p.y - S.cgy); S.t.fz = (float)(p.z - S.cgz);
-    S.t.tax = S.t.tay = S.t.taz = S.t.tph = 0.f;
-    S.t.hax = S.t.hay = S.t.haz = S.t.hph = 0.f;
-    S.t.lax = S.t.lay = S.t.laz = S.t.lph = 0.f;
-    const bool ok = traverse(A, S, A.root_of[gr.w], lo, hi);
-    double ax, ay, az, ph, self;
+    S.T = T; S.lt = lt; S.slices = slices;
+    S.tfull = (64 + slices - 1) / slices;
+    S.F = slices * S.tfull;
+    const int j = (int)lane % lt;
+    const int sl = (int)lane / lt;
+    S.my_s = sl < slices ? sl : 0;           // idle lanes shadow slice 0 (discarded)
     if constexpr (kMixed) {
-      ax = (double)S.t.hax + (double)S.t.lax;
-      ay = (double)S.t.hay + (double)S.t.lay;
-      az = (double)S.t.haz + (double)S.t.laz;
-      ph = (double)S.t.hph + (double)S.t.lph;
-      self = (double)((float)p.w * __builtin_amdgcn_rsqf(S.eps2f));
+      S.cgx = 0.5 * (lo[0] + hi[0]);
+      S.cgy = 0.5 * (lo[1] + hi[1]);
+      S.cgz = 0.5 * (lo[2] + hi[2]);
     } else {
-      ax = S.t.ax; ay = S.t.ay; az = S.t.az; ph = S.t.ph;
-      self = p.w * rsqrt_dp(A.eps2);
+      S.cgx = S.cgy = S.cgz = 0.0;
     }
-    // sum the slices of each target in slice order (deterministic)
+    S.e2d = A.eps2;
+    S.e2 = (R)A.eps2;
+#pragma unroll
+    for (int k = 0; k < kMaxT; ++k) {
+      // lane-target j holds targets j, j + lt, ...; missing ones repeat j
+      const int i = j + k * lt;
+      const double4 p = A.spart[s_tgt[i < nt ? i : j]];
+      S.tx[k] = (R)(p.x - S.cgx); S.ty[k] = (R)(p.y - S.cgy); S.tz[k] = (R)(p.z - S.cgz);
+      S.hax[k] = S.hay[k] = S.haz[k] = S.hph[k] = R(0);
+      S.lax[k] = S.lay[k] = S.laz[k] = S.lph[k] = R(0);
+    }
+    const bool ok = traverse(A, S, A.root_of[gr.w], lo, hi);
+    // per-lane totals -> LDS, [k][lane][4]
     double *red = tile.red;
-    red[4 * lane + 0] = ax; red[4 * lane + 1] = ay;
-    red[4 * lane + 2] = az; red[4 * lane + 3] = ph;
+#pragma unroll
+    for (int k = 0; k < kMaxT; ++k) {
+      double *o = red + 4 * (64 * k + (int)lane);
+      if constexpr (kMixed) {
+        o[0] = (double)S.hax[k] + (double)S.lax[k];
+        o[1] = (double)S.hay[k] + (double)S.lay[k];
+        o[2] = (double)S.haz[k] + (double)S.laz[k];
+        o[3] = (double)S.hph[k] + (double)S.lph[k];
+      } else {
+        o[0] = S.hax[k]; o[1] = S.hay[k]; o[2] = S.haz[k]; o[3] = S.hph[k];
+      }
+    }
     __syncthreads();
     if ((int)lane < nt) {
-      for (int q = 1; q < slices; ++q) {
-        const double *o = red + 4 * (q * nt + (int)lane);
+      // target i sits at k = i / lt, lane-target i % lt of every slice; sum
+      // the slices in slice order (deterministic)
+      const int k = (int)lane / lt, jj = (int)lane % lt;
+      double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+      for (int q = 0; q < slices; ++q) {
+        const double *o = red + 4 * (64 * k + q * lt + jj);
         ax += o[0]; ay += o[1]; az += o[2]; ph += o[3];
       }
+      const uint32_t r_t = s_tgt[lane];
+      const double4 p = A.spart[r_t];
+      double self;
+      if constexpr (kMixed)
+        self = (double)((float)p.w * __builtin_amdgcn_rsqf((float)A.eps2));
+      else
+        self = p.w * rsqrt_dp(A.eps2);
       const uint32_t orig = A.perm[r_t];
       const double nanv = __longlong_as_double(0x7ff8000000000000ll);
       double ex = 0.0, ey = 0.0, ez = 0.0, ep = 0.0;
       if (A.ext_seg) {   // SMBH terms, FP64 in both precision modes
-        for (int32_t j = A.ext_seg[gr.w]; j < A.ext_seg[gr.w + 1]; ++j) {
-          const double e = fmax(A.eps, A.ext_eps[j]);
-          const double dx = p.x - A.ext_pos[3 * j], dy = p.y - A.ext_pos[3 * j + 1],
-                       dz = p.z - A.ext_pos[3 * j + 2];
-          const double r2 = dx * dx + dy * dy + dz * dz + e * e;
+        for (int32_t e = A.ext_seg[gr.w]; e < A.ext_seg[gr.w + 1]; ++e) {
+          const double es = fmax(A.eps, A.ext_eps[e]);
+          const double dx = p.x - A.ext_pos[3 * e], dy = p.y - A.ext_pos[3 * e + 1],
+                       dz = p.z - A.ext_pos[3 * e + 2];
+          const double r2 = dx * dx + dy * dy + dz * dz + es * es;
           const double D1 = 1.0 / sqrt(r2);
-          const double mD1 = A.ext_mass[j] * D1, mD3 = mD1 * D1 * D1;
+          const double mD1 = A.ext_mass[e] * D1, mD3 = mD1 * D1 * D1;
           ex -= mD3 * dx; ey -= mD3 * dy; ez -= mD3 * dz; ep -= mD1;
         }
       }
@@ -582,7 +653,6 @@ __global__ __launch_bounds__(64) void k_walk_forces(WalkArgs A) {
       A.acc[3 * (size_t)orig + 2] = ok ? A.G * (az + ez) : nanv;
       if (A.pot) A.pot[orig] = ok ? A.G * (ph + self + ep) : nanv;
     }
-    (void)has_t;
     tot_p2m += S.cells * (unsigned long long)nt;
     tot_p2p += S.parts * (unsigned long long)nt - (unsigned long long)nt;
     tot_t += (unsigned long long)nt;
