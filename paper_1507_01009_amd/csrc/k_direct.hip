@@ -2,14 +2,15 @@
 // (SMBH <-> stars; perturber <-> chain-member corrections), Plummer
 // softening max(eps_i, eps_j) per pair.
 //
-// Work is the grid of (target, source chunk) pairs, chunk-major so that
-// consecutive threads own consecutive targets.  With many targets (stars
-// feeling the SMBHs) each thread takes every source of its segment; with
-// few targets (SMBHs feeling a million stars) the sources are cut into
-// chunks whose partial sums are combined in a second, ordered pass.  Every
-// sum is compensated (error-free TwoSum with a running correction), so the
-// result does not depend on the chunking beyond the last bit and is
-// deterministic.
+// Many targets (stars feeling the SMBHs): one thread per target takes every
+// source of its segment (or of a source chunk, combined in a second ordered
+// pass when targets are too few to fill the chip).  Few targets (SMBHs
+// feeling a million stars): one 256-thread block per (target, range of
+// kFewPerBlock sources), threads striding through the range with coalesced
+// loads, the block's sums combined in a fixed tree order and the per-block
+// partials summed in a second ordered pass.  Every sum is compensated
+// (error-free TwoSum with a running correction), so the result does not
+// depend on the split beyond the last bit and is deterministic.
 #include "tg_internal.h"
 
 namespace tg {
@@ -83,6 +84,63 @@ __global__ void k_direct(const double *__restrict__ spos, const double *__restri
   }
 }
 
+// Compensated sums of a 256-thread block combined in a fixed tree order;
+// thread 0 returns with the totals in ss[k][0] + sc[k][0].
+__device__ void block_csum4(CSum r[4], double (*ss)[256], double (*sc)[256]) {
+  for (int k = 0; k < 4; ++k) { ss[k][threadIdx.x] = r[k].s; sc[k][threadIdx.x] = r[k].c; }
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      for (int k = 0; k < 4; ++k) {
+        CSum x;
+        x.s = ss[k][threadIdx.x];
+        x.c = sc[k][threadIdx.x] + sc[k][threadIdx.x + h];
+        x.add(ss[k][threadIdx.x + h]);
+        ss[k][threadIdx.x] = x.s;
+        sc[k][threadIdx.x] = x.c;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int kFewPerBlock = 4096;   // sources per block in the few-target path
+
+// grid (blocks per target, targets): block b of target i sums sources
+// [b kFewPerBlock, (b + 1) kFewPerBlock) of i's segment into part[b nt + i].
+__global__ __launch_bounds__(256) void k_direct_few(
+    const double *__restrict__ spos, const double *__restrict__ sm,
+    const double *__restrict__ seps, double seps_all, const double *__restrict__ tpos,
+    const double *__restrict__ teps, int64_t nt, const int64_t *__restrict__ sseg,
+    const int64_t *__restrict__ tseg, int nseg, int self_pairs, double *__restrict__ part) {
+  __shared__ double ss[4][256], sc[4][256];
+  const int64_t i = blockIdx.y;
+  const int s = seg_of(tseg, nseg, i);
+  const int64_t j0 = sseg[s] + (int64_t)blockIdx.x * kFewPerBlock;
+  const int64_t j1 = min(sseg[s + 1], j0 + kFewPerBlock);
+  const double xi = tpos[3 * i], yi = tpos[3 * i + 1], zi = tpos[3 * i + 2];
+  const double ei = teps[i];
+  CSum r[4];
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+    if (self_pairs && j == i) continue;
+    const double ep = fmax(seps ? seps[j] : seps_all, ei);
+    const double dx = xi - spos[3 * j], dy = yi - spos[3 * j + 1], dz = zi - spos[3 * j + 2];
+    const double r2 = dx * dx + dy * dy + dz * dz + ep * ep;
+    const double D1 = 1.0 / sqrt(r2);
+    const double mD1 = sm[j] * D1;
+    const double mD3 = mD1 * D1 * D1;
+    r[0].add(-mD3 * dx);
+    r[1].add(-mD3 * dy);
+    r[2].add(-mD3 * dz);
+    r[3].add(-mD1);
+  }
+  block_csum4(r, ss, sc);
+  if (threadIdx.x == 0) {
+    double *o = part + 8 * (size_t)(blockIdx.x * nt + i);
+    for (int k = 0; k < 4; ++k) { o[2 * k] = ss[k][0]; o[2 * k + 1] = sc[k][0]; }
+  }
+}
+
 // One block per target: each thread sums a strided subset of the chunks,
 // then the block combines the compensated pairs in a fixed tree order.
 __global__ __launch_bounds__(256) void k_direct_reduce(int64_t nt, int nchunks,
@@ -100,21 +158,7 @@ __global__ __launch_bounds__(256) void k_direct_reduce(int64_t nt, int nchunks,
         r[k].add(o[2 * k + 1]);
       }
     }
-    for (int k = 0; k < 4; ++k) { ss[k][threadIdx.x] = r[k].s; sc[k][threadIdx.x] = r[k].c; }
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if ((int)threadIdx.x < h) {
-        for (int k = 0; k < 4; ++k) {
-          CSum x;
-          x.s = ss[k][threadIdx.x];
-          x.c = sc[k][threadIdx.x] + sc[k][threadIdx.x + h];
-          x.add(ss[k][threadIdx.x + h]);
-          ss[k][threadIdx.x] = x.s;
-          sc[k][threadIdx.x] = x.c;
-        }
-      }
-      __syncthreads();
-    }
+    block_csum4(r, ss, sc);
     if (threadIdx.x == 0) {
       const double v0 = ss[0][0] + sc[0][0], v1 = ss[1][0] + sc[1][0];
       const double v2 = ss[2][0] + sc[2][0], v3 = ss[3][0] + sc[3][0];
@@ -138,6 +182,18 @@ hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
                          double *acc, double *pot) {
   (void)ns;
   if (nt == 0) return hipSuccess;
+  if (nt <= 4096 && max_seg_src >= 2 * kFewPerBlock) {
+    const int64_t bpt = (max_seg_src + kFewPerBlock - 1) / kFewPerBlock;
+    if (bpt * nt * 8 <= c->b.dpart_cap && bpt <= 65535) {
+      hipLaunchKernelGGL(k_direct_few, dim3((unsigned)bpt, (unsigned)nt), dim3(256), 0,
+                         c->stream, spos, sm, seps, seps_all, tpos, teps, nt, dseg,
+                         dseg + (nseg + 1), nseg, self_pairs, c->b.dpart);
+      hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)std::min<int64_t>(nt, 4096)),
+                         dim3(256), 0, c->stream, nt, (int)bpt, accumulate, c->b.dpart,
+                         acc, pot);
+      return hipGetLastError();
+    }
+  }
   // aim for >= 2^16 independent (target, chunk) sums
   int64_t nchunks = 1, chunk = std::max<int64_t>(max_seg_src, 1);
   if (nt < 65536 && max_seg_src > 256) {

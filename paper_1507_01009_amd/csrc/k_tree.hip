@@ -1,123 +1,62 @@
-// a5-a6: octree over the sorted keys, level by level, and the walk groups.
+// a5-a6: octree over the sorted keys, all levels at once, and the walk groups.
 //
-// Level l is the node-id range [lvl[l], lvl[l+1]).  For every node of the
-// level that holds more than n_L particles (and l < 21) the starts of its
-// non-empty octants inside its sorted particle range are found (from the
-// common-prefix lengths of neighbouring keys, or for the largest nodes by a
-// wave-wide search on the next key digit); they become its children.
-// Children ids come from an exclusive scan of the child counts over the
-// level, so the numbering is breadth first with children in octant order,
-// exactly the canonical order, without atomics.  Three launches per level,
-// each of fixed shape, reading its range from device memory (graph-
-// capturable): find the children, scan their counts, write them.
+// d[i] = number of equal leading key digits of sorted particles i-1 and i
+// (0 at the first particle of every system and at the end, 21 for equal
+// keys).  A level-l run is a maximal range of equal first l digits; one
+// starts at i exactly when d[i] < l (l >= 1; level 0 is the whole system).
+// A node is a run whose parent run holds more than n_L particles (and
+// splits only if l < 21), so with lo = d[i] + 1 the nodes starting at i are
+// the levels [lo, top] with
+//   top = min(21, max(lo, m + 1)),  m = min(d[i+1 .. i+n_L]),
+// provided the parent run of the first of them is longer than n_L, which
+// is decided inside a window of n_L bytes on either side of i.  A system's
+// root always exists and splits if the system holds more than n_L.
+//
+// Canonical ids order the nodes by level, then by first particle, which is
+// the breadth-first order with children in octant order.  So a node's id is
+// the start of its level plus its rank among the level's node starts,
+// counted with per-level bitmaps and per-tile prefix sums; its parent is
+// the last node of the level above starting at or before it, its children
+// the nodes of the level below starting inside it, and its end the first
+// position after it with d < l (searched inside the tile, else taken from
+// a per-tile suffix minimum of the run starts of later tiles).
+//
+// Four launches, each of fixed shape for a given N (graph-capturable):
+// k_lcp, k_flat_flags (per 256-particle tile: node levels per particle,
+// bitmaps, counts, first run starts), k_flat_scan (one block per level:
+// prefix of the counts, suffix minimum of the run starts), k_flat_emit.
 #include "tg_internal.h"
 
 namespace tg {
 
-// Contiguous share of [0, n) for this block (no rounding, so that a small
-// level still spreads over every block).
-__device__ __forceinline__ void chunk_range(uint32_t n, uint32_t &a, uint32_t &b) {
-  const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  a = min(n, blockIdx.x * chunk);
-  b = min(n, a + chunk);
+constexpr int kFT = 256;                 // particles per tile of the flat build
+constexpr int kHalo = 16;                // >= max leaf size
+
+__device__ __forceinline__ int sys_of(const int64_t *so, int S, int64_t i) {
+  int lo = 0, hi = S - 1;                // last s with so[s] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (so[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
-// Exclusive prefix of v over the wave; tot = wave sum.
-__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t &tot) {
-  const unsigned lane = lane_id();
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= (unsigned)o) x += y;
-  }
-  tot = (uint32_t)__shfl((int)x, 63, 64);
-  return x - v;
+__device__ void load_sysoff(int64_t *so, const int64_t *sysoff, int S) {
+  for (int k = threadIdx.x; k <= S; k += blockDim.x) so[k] = sysoff[k];
+  __syncthreads();
 }
 
-__device__ __forceinline__ uint32_t digit_at(const uint64_t *__restrict__ skey,
-                                             uint32_t i, int shift) {
-  return (uint32_t)(skey[i] >> shift) & 7u;
-}
-
-// Octant starts of one node's sorted range [first, first + count), found by
-// the whole wave: b[o] = first index whose digit (at bit `shift`) is >= o,
-// for o = 1..7 (digits are sorted inside a node).  Up to 64 particles: one
-// load per lane and one ballot per octant.  Larger nodes: lane group o
-// (8 lanes) narrows the interval holding b[o] nine-fold per round with 8
-// probes, so a million-particle node needs 7 rounds of parallel loads
-// instead of 7 x 20 dependent ones.  The result is the same in every lane.
-__device__ void wave_octants(const uint64_t *__restrict__ skey, uint32_t first,
-                             uint32_t count, int shift, uint32_t b[9]) {
-  const unsigned lane = lane_id();
-  if (count <= 64) {
-    const bool valid = lane < count;
-    const uint32_t d = valid ? digit_at(skey, first + lane, shift) : 8u;
-#pragma unroll
-    for (uint32_t o = 1; o < 8; ++o)
-      b[o] = first + (uint32_t)__popcll(__ballot(valid && d < o));
-    return;
-  }
-  const uint32_t o = lane >> 3, k = lane & 7u;
-  uint32_t lo = first, hi = first + count;   // b[o] lies in [lo, hi]
-  while (__ballot(hi - lo > 8u)) {
-    const bool act = hi - lo > 8u;
-    const uint32_t step = act ? (hi - lo + 8u) / 9u : 0u;
-    const uint32_t p = lo + (k + 1u) * step;
-    const bool valid = act && p < hi;
-    const bool pred = valid && digit_at(skey, p, shift) < o;
-    const uint32_t c = (uint32_t)__popcll((__ballot(pred) >> (8 * o)) & 0xffull);
-    const uint32_t nv = (uint32_t)__popcll((__ballot(valid) >> (8 * o)) & 0xffull);
-    if (act) {
-      const uint32_t lo0 = lo;
-      if (c > 0) lo = lo0 + c * step + 1u;       // probe c-1 is below o
-      if (c < nv) hi = lo0 + (c + 1u) * step;     // probe c is not
-    }
-  }
-  const uint32_t p = lo + k;
-  const bool pred = p < hi && digit_at(skey, p, shift) < o;
-  const uint32_t mine = lo + (uint32_t)__popcll((__ballot(pred) >> (8 * o)) & 0xffull);
-#pragma unroll
-  for (int q = 1; q < 8; ++q) b[q] = (uint32_t)__shfl((int)mine, 8 * q, 64);
-}
-
-// Roots: one per non-empty system, in system order.
-__global__ __launch_bounds__(256) void k_roots(const int64_t *__restrict__ sysoff,
-                                               int S, TreeCounters *ctr,
-                                               uint32_t *root_of, uint8_t *level,
-                                               uint8_t *nchild, uint32_t *first,
-                                               uint32_t *count, uint32_t *child,
-                                               uint32_t *parent, uint32_t *nsys) {
-  __shared__ uint32_t sh[4];
-  const int s = threadIdx.x;
-  int64_t ns = s < S ? sysoff[s + 1] - sysoff[s] : 0;
-  uint32_t ne = ns > 0 ? 1u : 0u;
-  uint32_t tot;
-  uint32_t id = block_exclusive_scan(ne, sh, tot);
-  if (s < S) root_of[s] = ne ? id : kNone;
-  if (ne) {
-    level[id] = 0; nchild[id] = 0; child[id] = 0; parent[id] = kNone;
-    first[id] = (uint32_t)sysoff[s]; count[id] = (uint32_t)ns; nsys[id] = (uint32_t)s;
-  }
-  if (s == 0) {
-    ctr->lvl[0] = 0;
-    for (int l = 1; l < kLevels + 2; ++l) ctr->lvl[l] = tot;
-    ctr->overflow = 0;
-    ctr->big_n = 0;
-    ctr->n_nodes = tot;
-  }
-}
-
-// Common leading key digits of each sorted particle with its predecessor:
-// d[i] = number of equal top digits of key[i-1] and key[i] (21 if equal).
-// Inside a node of level l every d >= l, and its children start at the
-// node's first particle and wherever d == l (the digit of level l+1 changes).
-__global__ void k_lcp(const uint64_t *__restrict__ skey, int64_t n,
-                      uint8_t *__restrict__ d) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+// d for [0, n + 64): the common leading digits with the predecessor, 0 at
+// every system start and from n on.
+__global__ __launch_bounds__(256) void k_lcp(const uint64_t *__restrict__ skey, int64_t n,
+                                             const int64_t *__restrict__ sysoff, int S,
+                                             uint8_t *__restrict__ d) {
+  __shared__ int64_t so[kMaxSys + 1];
+  load_sysoff(so, sysoff, S);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n + 64;
        i += (int64_t)gridDim.x * blockDim.x) {
     uint32_t v = 0;
-    if (i > 0) {
+    if (i > 0 && i < n && so[sys_of(so, S, i)] != i) {
       const uint64_t x = skey[i - 1] ^ skey[i];
       v = x == 0 ? 21u : (uint32_t)(__clzll((long long)x) - 1) / 3u;   // bit 63 is 0
     }
@@ -125,273 +64,266 @@ __global__ void k_lcp(const uint64_t *__restrict__ skey, int64_t n,
   }
 }
 
-// 0x80 in every byte of w equal to l, 0 elsewhere (no false positives).
-__device__ __forceinline__ uint64_t bytes_equal(uint64_t w, uint32_t l) {
-  const uint64_t x = w ^ (0x0101010101010101ull * l);
-  const uint64_t t = (x & 0x7f7f7f7f7f7f7f7full) + 0x7f7f7f7f7f7f7f7full;
-  return ~(t | x | 0x7f7f7f7f7f7f7f7full);
-}
-
-// Bytes of the aligned word at p (p multiple of 8) that lie in [lo, hi).
-__device__ __forceinline__ uint64_t byte_window(uint32_t p, uint32_t lo, uint32_t hi) {
-  const int a = (int)lo - (int)p, b = (int)hi - (int)p;   // keep bytes j in [a, b)
-  const uint64_t upto_b = b >= 8 ? ~0ull : (b <= 0 ? 0ull : (1ull << (8 * b)) - 1ull);
-  const uint64_t from_a = a <= 0 ? ~0ull : (a >= 8 ? 0ull : ~((1ull << (8 * a)) - 1ull));
-  return upto_b & from_a;
-}
-
-// Children of the nodes of level l that split, and per-block sums of their
-// counts.  The children of a node [f, e) start at f and at every i in
-// (f, e) with d[i] == l, stored in order: bnd[8 k + j] = start of child j
-// (j >= 1).  Nodes of at most 512 particles: one lane scans their d bytes
-// eight words (64 bytes) per batch with the loads of a batch independent;
-// bigger ones are listed for k_level_big.
-__global__ __launch_bounds__(256) void k_level_count(int l, int nleaf,
-                                                     TreeCounters *ctr,
-                                                     const uint64_t *__restrict__ skey,
-                                                     const uint8_t *__restrict__ dl,
-                                                     const uint32_t *__restrict__ first,
-                                                     const uint32_t *__restrict__ count,
-                                                     uint32_t *__restrict__ tmp,
-                                                     uint32_t *__restrict__ bnd,
-                                                     uint32_t *__restrict__ part,
-                                                     uint32_t *__restrict__ biglist) {
-  __shared__ uint32_t sh[4];
-  const uint32_t a0 = ctr->lvl[l], n = ctr->lvl[l + 1] - a0;
-  uint32_t ca, cb;
-  chunk_range(n, ca, cb);
-  const unsigned lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint64_t *dw = reinterpret_cast<const uint64_t *>(dl);
-  uint32_t sum = 0;
-  for (uint32_t base = ca + 64u * w; base < cb; base += 256u) {
-    const uint32_t i = base + lane;
-    const bool in = i < cb;
-    const uint32_t cnt = in ? count[a0 + i] : 0u;
-    const uint32_t fst = in ? first[a0 + i] : 0u;
-    const bool split = in && cnt > (uint32_t)nleaf;
-    const bool small = split && cnt <= 512u;
-    if (in && !split) tmp[i] = 0u;
-    if (small) {
-      // d bytes of (fst, fst + cnt), eight aligned words per batch, every
-      // load of a batch independent of the others
-      const uint32_t lo = fst + 1u, hi = fst + cnt;
-      const uint32_t p0 = lo & ~7u;
-      uint32_t nch = 1;
-      for (uint32_t pb = p0; pb < hi; pb += 64u) {
-        uint64_t wd[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const uint32_t p = pb + 8u * q;
-          wd[q] = p < hi ? dw[p >> 3] : 0ull;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const uint32_t p = pb + 8u * q;
-          uint64_t m = p < hi ? bytes_equal(wd[q], (uint32_t)l) & byte_window(p, lo, hi) : 0ull;
-          while (m) {
-            const uint32_t j = (uint32_t)(__ffsll((long long)m) - 1) / 8u;   // byte of the 0x80 bit
-            m &= m - 1ull;
-            if (nch < 8u) bnd[8 * (size_t)i + nch] = p + j;
-            ++nch;
+// Per tile b of kFT particles: lt[i] = lo | top << 8 of the nodes starting
+// at i (0xffff: none); bits[l][4 b + w] = ballot of "a level-l node starts
+// here" of wave w; cnt[l][b] = nodes of level l in the tile; fst[l][b] =
+// first run start of level l in the tile (first i with d[i] < l).
+__global__ __launch_bounds__(kFT) void k_flat_flags(int64_t n, int nleaf, int S,
+                                                    const int64_t *__restrict__ sysoff,
+                                                    const uint8_t *__restrict__ d,
+                                                    uint16_t *__restrict__ lt,
+                                                    uint64_t *__restrict__ bits, int64_t wl,
+                                                    uint32_t *__restrict__ cnt,
+                                                    uint32_t *__restrict__ fst, int64_t tl) {
+  __shared__ uint8_t sd[kHalo + kFT + 2 * kHalo];
+  __shared__ int64_t so[kMaxSys + 1];
+  __shared__ uint32_t wc[kFT / 64][kLevels];
+  __shared__ uint32_t mj[kLevels];
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x, t0 = b * kFT, i = t0 + tid;
+  for (int k = tid; k < kHalo + kFT + 2 * kHalo; k += kFT) {
+    const int64_t p = t0 - kHalo + k;
+    sd[k] = (p >= 0 && p < n + 64) ? d[p] : (uint8_t)0;
+  }
+  if (tid < kLevels) mj[tid] = 0xffffffffu;
+  load_sysoff(so, sysoff, S);
+  const bool valid = i < n;
+  bool ex = false;
+  uint32_t lo = 0, top = 0;
+  const uint8_t *di = sd + kHalo + tid;       // di[k] = d[i + k]
+  if (valid) {
+    const int s = sys_of(so, S, i);
+    const int64_t size = so[s + 1] - so[s];
+    const bool seg = so[s] == i;
+    uint32_t m = 255;
+    for (int k = 1; k <= nleaf; ++k) m = min(m, (uint32_t)di[k]);
+    if (seg) {
+      ex = true;
+      lo = 0;
+      top = size > nleaf ? min(21u, max(1u, m + 1)) : 0u;
+    } else {
+      const uint32_t p = di[0];
+      lo = p + 1;
+      if (lo <= 21u) {
+        if (p == 0) {
+          ex = size > nleaf;                  // the parent is the root
+        } else {
+          // parent run [s0, e0) at level p: short iff e0 - s0 <= n_L
+          int back = 0;
+          for (int k = 1; k < nleaf; ++k)
+            if (di[-k] < p) { back = k; break; }
+          ex = true;
+          if (back > 0) {
+            for (int k = 1; k <= nleaf - back; ++k)
+              if (di[k] < p) { ex = false; break; }
           }
         }
+        top = min(21u, max(lo, m + 1));
       }
-      nch = min(nch, 8u);
-      tmp[i] = nch;
-      sum += nch;
     }
-    // nodes above 512 particles go to a work list for k_level_big, which
-    // spreads them over the whole grid (they cluster in the dense centre)
-    const unsigned long long bigm = __ballot(split && !small);
-    if (bigm) {
-      uint32_t b0 = 0;
-      if (lane == 0) b0 = atomicAdd(&ctr->big_n, (uint32_t)__popcll(bigm));
-      b0 = (uint32_t)__shfl((int)b0, 0, 64);
-      if (split && !small) biglist[b0 + lanes_below(bigm)] = i;
-    }
+    atomicMin(&mj[di[0]], (uint32_t)i);
   }
-  uint32_t tot;
-  block_exclusive_scan(sum, sh, tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-// Splitting nodes of more than 512 particles listed by k_level_count: one
-// wave per node over the whole grid.  Up to 4096 particles the wave scans
-// the d bytes coalesced (512 per round); bigger nodes are narrowed on the
-// keys (wave_octants).  The child count is added to the sum of the block
-// chunk that owns the node.
-__global__ __launch_bounds__(256) void k_level_big(int l, const TreeCounters *ctr,
-                                                   const uint64_t *__restrict__ skey,
-                                                   const uint8_t *__restrict__ dl,
-                                                   const uint32_t *__restrict__ first,
-                                                   const uint32_t *__restrict__ count,
-                                                   const uint32_t *__restrict__ biglist,
-                                                   uint32_t *__restrict__ tmp,
-                                                   uint32_t *__restrict__ bnd,
-                                                   uint32_t *__restrict__ part) {
-  const uint32_t nbig = ctr->big_n;
-  if (nbig == 0) return;
-  const uint32_t a0 = ctr->lvl[l], n = ctr->lvl[l + 1] - a0;
-  const uint32_t chunk = (n + kLevelBlocks - 1) / kLevelBlocks;   // as k_level_count
-  const int shift = 3 * (kMaxLevel - 1 - l);
-  const unsigned lane = threadIdx.x & 63u;
-  const uint32_t wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  const uint64_t *dw = reinterpret_cast<const uint64_t *>(dl);
-  for (uint32_t e = wid; e < nbig; e += nw) {
-    const uint32_t vi = biglist[e];
-    const uint32_t f = first[a0 + vi], c = count[a0 + vi];
-    uint32_t nch;
-    if (c <= 4096u) {
-      const uint32_t lo = f + 1u, hi = f + c, p0 = lo & ~7u;
-      uint32_t found = 0;
-      for (uint32_t r = p0; r < hi; r += 512u) {
-        const uint32_t p = r + 8u * lane;
-        uint64_t m = p < hi ? bytes_equal(dw[p >> 3], (uint32_t)l) & byte_window(p, lo, hi) : 0ull;
-        uint32_t tot;
-        const uint32_t pre = wave_prefix(__popcll(m), tot);
-        uint32_t k = 1u + found + pre;
-        while (m) {
-          const uint32_t j = (uint32_t)(__ffsll((long long)m) - 1) / 8u;
-          m &= m - 1ull;
-          if (k < 8u) bnd[8 * (size_t)vi + k] = p + j;
-          ++k;
-        }
-        found += tot;
-      }
-      nch = min(1u + found, 8u);
-    } else {
-      uint32_t b[9];
-      wave_octants(skey, f, c, shift, b);
-      b[0] = f;
-      b[8] = f + c;
-      nch = 0;
+  if (valid) lt[i] = ex ? (uint16_t)(lo | (top << 8)) : (uint16_t)0xffff;
+  const int w = tid >> 6, lane = tid & 63;
 #pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        if (b[o + 1] > b[o]) {
-          if (nch > 0 && lane == 0) bnd[8 * (size_t)vi + nch] = b[o];
-          ++nch;
-        }
-      }
-    }
+  for (int l = 0; l < kLevels; ++l) {
+    const unsigned long long msk = __ballot(ex && lo <= (uint32_t)l && (uint32_t)l <= top);
     if (lane == 0) {
-      tmp[vi] = nch;
-      atomicAdd(&part[vi / chunk], nch);
+      bits[l * wl + 4 * b + w] = msk;
+      wc[w][l] = (uint32_t)__popcll(msk);
     }
+  }
+  __syncthreads();
+  if (tid < kLevels) {
+    const int l = tid;
+    uint32_t c = 0;
+    for (int q = 0; q < kFT / 64; ++q) c += wc[q][l];
+    cnt[l * tl + b] = c;
+    uint32_t f = 0xffffffffu;
+    for (int v = 0; v < l; ++v) f = min(f, mj[v]);
+    fst[l * tl + b] = f;
   }
 }
 
-// Exclusive scan of the per-block child counts (one block, 4 per thread);
-// sets the end of level l+1, guarding the node capacity.  A separate launch:
-// a "last block" hand-off inside k_level_count would need an agent-scope
-// fence in every block, which writes back the per-XCD L2 caches.
-__global__ __launch_bounds__(256) void k_level_top(int l, int64_t max_nodes,
-                                                   TreeCounters *ctr,
-                                                   uint32_t *__restrict__ part,
-                                                   uint32_t *err) {
-  __shared__ uint32_t sh[4];
-  constexpr int per = kLevelBlocks / 256;
-  uint32_t loc[per];
-  uint32_t my = 0;
-#pragma unroll
-  for (int q = 0; q < per; ++q) {
-    loc[q] = part[threadIdx.x * per + q];
-    my += loc[q];
+// One block per level: exclusive prefix of cnt[l][0..T) in place with
+// cnt[l][T] = total (also tot[l]); fst[l][b] <- first run start of level l
+// after tile b (suffix minimum over later tiles; n past the last).
+__global__ __launch_bounds__(1024) void k_flat_scan(int64_t T, int64_t n,
+                                                    uint32_t *__restrict__ cnt,
+                                                    uint32_t *__restrict__ fst, int64_t tl,
+                                                    uint32_t *__restrict__ tot) {
+  __shared__ uint32_t sh[16];
+  const int l = blockIdx.x;
+  uint32_t *c = cnt + l * tl, *f = fst + l * tl;
+  const int tid = threadIdx.x;
+  uint32_t run = 0;
+  for (int64_t base = 0; base < T; base += 1024) {
+    const int64_t k = base + tid;
+    const uint32_t v = k < T ? c[k] : 0u;
+    uint32_t t;
+    const uint32_t e = block_exclusive_scan(v, sh, t);
+    if (k < T) c[k] = run + e;
+    run += t;
   }
-  uint32_t all;
-  uint32_t e = block_exclusive_scan(my, sh, all);
+  if (tid == 0) { c[T] = run; tot[l] = run; }
+  // suffix minimum, chunks from the end
+  uint32_t carry = (uint32_t)n;
+  for (int64_t hi = T; hi > 0; hi -= 1024) {
+    const int64_t k = hi - 1 - tid;           // thread tid takes the tid-th from the end
+    const uint32_t v = k >= 0 ? f[k] : 0xffffffffu;
+    // exclusive suffix minimum across the chunk: min over threads < tid
+    uint32_t x = v;
+    const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
-  for (int q = 0; q < per; ++q) {
-    part[threadIdx.x * per + q] = e;
-    e += loc[q];
-  }
-  if (threadIdx.x == 0) {
-    ctr->big_n = 0;
-    const uint32_t start = ctr->lvl[l + 1];
-    if (ctr->overflow || (int64_t)start + all > max_nodes) {
-      if (!ctr->overflow) set_err(err, TG_ERR_NODES);
-      ctr->overflow = 1;
-      all = 0;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x = min(x, y);
     }
-    ctr->lvl[l + 2] = start + all;
-    ctr->n_nodes = start + all;
+    __syncthreads();
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    uint32_t before = carry, all = carry;
+    for (int q = 0; q < 16; ++q) {
+      const uint32_t t = sh[q];
+      if (q < wv) before = min(before, t);
+      all = min(all, t);
+    }
+    // x - own value: exclusive within the wave
+    uint32_t ex = __shfl_up(x, 1, 64);
+    if (lane == 0) ex = 0xffffffffu;
+    if (k >= 0) f[k] = min(before, ex);
+    carry = all;
   }
 }
 
-// Emit the children of level l's nodes from the stored octant starts.
-__global__ __launch_bounds__(256) void k_level_emit(int l, const TreeCounters *ctr,
-                                                    const uint32_t *__restrict__ bnd,
-                                                    const uint32_t *__restrict__ tmp,
-                                                    const uint32_t *__restrict__ part,
-                                                    uint8_t *level, uint8_t *nchild,
-                                                    uint32_t *first, uint32_t *count,
-                                                    uint32_t *child, uint32_t *parent,
-                                                    uint32_t *nsys) {
-  __shared__ uint32_t sh[4];
-  const uint32_t a0 = ctr->lvl[l], n = ctr->lvl[l + 1] - a0;
-  const uint32_t c_start = ctr->lvl[l + 1];
-  const bool ovf = ctr->overflow != 0;
-  uint32_t ca, cb;
-  chunk_range(n, ca, cb);
-  uint32_t base = part[blockIdx.x];
-  for (uint32_t t0 = ca; t0 < cb; t0 += 256u) {
-    const uint32_t i = t0 + threadIdx.x;
-    const bool in = i < cb;
-    uint32_t nch = (in && !ovf) ? tmp[i] : 0u;
-    uint32_t tot;
-    uint32_t off = block_exclusive_scan(nch, sh, tot);
-    if (in) {
-      const uint32_t v = a0 + i;
-      if (nch > 0) {
-        const uint32_t f = first[v], e = f + count[v];
-        uint32_t c = c_start + base + off;
-        child[v] = c;
-        nchild[v] = (uint8_t)nch;
-        const uint32_t sy = nsys[v];
-        uint32_t st = f;
-        for (uint32_t k = 0; k < nch; ++k, ++c) {
-          const uint32_t nx = k + 1 < nch ? bnd[8 * (size_t)i + k + 1] : e;
-          level[c] = (uint8_t)(l + 1);
-          nchild[c] = 0;
-          child[c] = 0;
-          first[c] = st;
-          count[c] = nx - st;
-          parent[c] = v;
-          nsys[c] = sy;
-          st = nx;
-        }
-      } else {
-        child[v] = 0;
-        nchild[v] = 0;
+// rank of x among the level-l node starts: base of x's tile + bits before x
+__device__ __forceinline__ uint32_t rank_of(const uint64_t *__restrict__ bl,
+                                            const uint32_t *__restrict__ cl, int64_t x) {
+  const int64_t q = x >> 8;
+  uint32_t r = cl[q];
+  const int wq = (int)((x & 255) >> 6), bq = (int)(x & 63);
+  for (int k = 0; k < wq; ++k) r += (uint32_t)__popcll(bl[4 * q + k]);
+  if (bq) r += (uint32_t)__popcll(bl[4 * q + wq] & ((1ull << bq) - 1ull));
+  return r;
+}
+
+// Nodes of tile b written at their canonical ids.
+__global__ __launch_bounds__(kFT) void k_flat_emit(
+    int64_t n, int S, const int64_t *__restrict__ sysoff, const uint8_t *__restrict__ d,
+    const uint16_t *__restrict__ lt, const uint64_t *__restrict__ bits, int64_t wl,
+    const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ fst, int64_t tl,
+    const uint32_t *__restrict__ tot, int64_t max_nodes, TreeCounters *ctr, uint32_t *err,
+    uint32_t *__restrict__ root_of, uint8_t *__restrict__ level,
+    uint8_t *__restrict__ nchild, uint32_t *__restrict__ first,
+    uint32_t *__restrict__ count, uint32_t *__restrict__ child,
+    uint32_t *__restrict__ parent, uint32_t *__restrict__ nsys) {
+  __shared__ uint8_t sd[kFT];
+  __shared__ uint8_t mn8[kFT / 8], mn64[kFT / 64];
+  __shared__ int64_t so[kMaxSys + 1];
+  __shared__ uint32_t lv[kLevels + 1];
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x, t0 = b * kFT, i = t0 + tid;
+  if (tid == 0) {
+    uint32_t a = 0;
+    for (int l = 0; l < kLevels; ++l) { lv[l] = a; a += tot[l]; }
+    lv[kLevels] = a;
+  }
+  sd[tid] = i < n + 64 ? d[i] : (uint8_t)0;
+  load_sysoff(so, sysoff, S);               // (includes a barrier)
+  const uint32_t nn = lv[kLevels];
+  const bool ovf = (int64_t)nn > max_nodes;
+  if (b == 0 && tid == 0) {
+    for (int l = 0; l <= kLevels; ++l) ctr->lvl[l] = ovf ? 0u : lv[l];
+    ctr->lvl[kLevels + 1] = ovf ? 0u : nn;
+    ctr->n_nodes = ovf ? 0u : nn;
+    ctr->overflow = ovf ? 1u : 0u;
+    if (ovf) set_err(err, TG_ERR_NODES);
+  }
+  if (ovf) return;
+  if (b == 0) {
+    for (int s = tid; s < S; s += kFT)
+      root_of[s] = so[s + 1] > so[s] ? rank_of(bits, cnt, so[s]) : kNone;
+  }
+  if (tid < kFT / 8) {
+    uint8_t v = 255;
+    for (int k = 0; k < 8; ++k) v = min(v, sd[8 * tid + k]);
+    mn8[tid] = v;
+  }
+  __syncthreads();
+  if (tid < kFT / 64) {
+    uint8_t v = 255;
+    for (int k = 0; k < 8; ++k) v = min(v, mn8[8 * tid + k]);
+    mn64[tid] = v;
+  }
+  __syncthreads();
+  if (i >= n) return;
+  const uint16_t code = lt[i];
+  if (code == 0xffff) return;
+  const uint32_t lo = code & 0xffu, top = code >> 8;
+  const int s = sys_of(so, S, i);
+  for (uint32_t l = lo; l <= top; ++l) {
+    const uint64_t *bl = bits + l * wl;
+    const uint32_t *cl = cnt + l * tl;
+    const uint32_t id = lv[l] + rank_of(bl, cl, i);
+    // end: first j > i with d[j] < l (root: the system end)
+    int64_t e;
+    if (l == 0) {
+      e = so[s + 1];
+    } else {
+      int k = tid + 1;
+      int found = -1;
+      for (; k < kFT && (k & 7); ++k)
+        if (sd[k] < l) { found = k; break; }
+      if (found < 0) {
+        for (; k < kFT && (k & 63); k += 8)
+          if (mn8[k >> 3] < l) break;
+        if (k < kFT && (k & 63) == 0)
+          for (; k < kFT; k += 64)
+            if (mn64[k >> 6] < l) {
+              while (mn8[k >> 3] >= l) k += 8;
+              break;
+            }
+        if (k < kFT)
+          for (int q = 0; q < 8; ++q)
+            if (sd[k + q] < l) { found = k + q; break; }
       }
+      e = found >= 0 ? t0 + found : (int64_t)fst[l * tl + b];
     }
-    base += tot;
+    level[id] = (uint8_t)l;
+    first[id] = (uint32_t)i;
+    count[id] = (uint32_t)(e - i);
+    nsys[id] = (uint32_t)s;
+    parent[id] = l == 0 ? kNone : lv[l - 1] + rank_of(bits + (l - 1) * wl, cnt + (l - 1) * tl, i + 1) - 1u;
+    if (l < top) {
+      const uint64_t *bc = bits + (l + 1) * wl;
+      const uint32_t *cc = cnt + (l + 1) * tl;
+      const uint32_t r0 = rank_of(bc, cc, i);
+      child[id] = lv[l + 1] + r0;
+      nchild[id] = (uint8_t)(rank_of(bc, cc, e) - r0);
+    } else {
+      child[id] = 0;
+      nchild[id] = 0;
+    }
   }
 }
 
 hipError_t launch_tree_build(tg_ctx *c) {
   Buffers &b = c->b;
-  if (c->n > 0)
-    hipLaunchKernelGGL(k_lcp, dim3((int)std::min<int64_t>((c->n + 255) / 256, 4096)),
-                       dim3(256), 0, c->stream, b.key[0], c->n, b.lcp);
-  hipLaunchKernelGGL(k_roots, dim3(1), dim3(256), 0, c->stream, b.sysoff, c->S,
-                     b.ctr, b.root_of, b.level, b.nchild, b.first, b.count,
-                     b.child, b.parent, b.nsys);
-  for (int l = 0; l < kMaxLevel; ++l) {
-    hipLaunchKernelGGL(k_level_count, dim3(kLevelBlocks), dim3(256), 0,
-                       c->stream, l, c->leaf_size, b.ctr, b.key[0], b.lcp,
-                       b.first, b.count, b.lvl_tmp, b.lvl_bnd, b.lvl_part,
-                       b.lvl_big);
-    hipLaunchKernelGGL(k_level_big, dim3(kLevelBlocks), dim3(256), 0, c->stream,
-                       l, b.ctr, b.key[0], b.lcp, b.first, b.count, b.lvl_big,
-                       b.lvl_tmp, b.lvl_bnd, b.lvl_part);
-    hipLaunchKernelGGL(k_level_top, dim3(1), dim3(256), 0, c->stream, l,
-                       c->max_nodes, b.ctr, b.lvl_part, b.err);
-    hipLaunchKernelGGL(k_level_emit, dim3(kLevelBlocks), dim3(256), 0,
-                       c->stream, l, b.ctr, b.lvl_bnd, b.lvl_tmp, b.lvl_part,
-                       b.level, b.nchild, b.first, b.count, b.child, b.parent,
-                       b.nsys);
-  }
+  const int64_t n = c->n, T = (n + kFT - 1) / kFT;
+  const int64_t wl = 4 * (c->flat_tiles + 1), tl = c->flat_tiles + 1;
+  hipLaunchKernelGGL(k_lcp, dim3((int)std::min<int64_t>((n + 64 + 255) / 256, 4096)),
+                     dim3(256), 0, c->stream, b.key[0], n, b.sysoff, c->S, b.lcp);
+  if (T > 0)
+    hipLaunchKernelGGL(k_flat_flags, dim3((unsigned)T), dim3(kFT), 0, c->stream, n,
+                       c->leaf_size, c->S, b.sysoff, b.lcp, b.fl_lt, b.fl_bits, wl,
+                       b.fl_cnt, b.fl_fst, tl);
+  hipLaunchKernelGGL(k_flat_scan, dim3(kLevels), dim3(1024), 0, c->stream, T, n,
+                     b.fl_cnt, b.fl_fst, tl, b.fl_tot);
+  hipLaunchKernelGGL(k_flat_emit, dim3((unsigned)std::max<int64_t>(T, 1)), dim3(kFT), 0,
+                     c->stream, n, c->S, b.sysoff, b.lcp, b.fl_lt, b.fl_bits, wl,
+                     b.fl_cnt, b.fl_fst, tl, b.fl_tot, c->max_nodes, b.ctr, b.err,
+                     b.root_of, b.level, b.nchild, b.first, b.count, b.child, b.parent,
+                     b.nsys);
   return hipGetLastError();
 }
 

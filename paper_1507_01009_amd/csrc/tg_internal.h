@@ -30,7 +30,6 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per tile
 constexpr int kScanBlocks = 256;
-constexpr int kLevelBlocks = 1024;                // octree level kernels (multiple of 256)
 constexpr int kMaxWavesPerCU = 16;
 constexpr int kMaxExternal = 1024;               // SMBHs / external point masses
 constexpr int kSegSlots = 8;                     // cached direct-sum segment tables
@@ -52,8 +51,7 @@ struct TreeCounters {
   uint32_t n_active_groups;
   uint32_t overflow;         // node capacity exceeded during this build
   uint32_t xq[8];            // walk work counters, one queue per XCD
-  uint32_t big_n;            // nodes listed for k_level_big at this level
-  uint32_t pad[2];
+  uint32_t pad[3];
   unsigned long long n_p2p, n_p2m, n_targets, n_walked;      // last walk
   unsigned long long cum_p2p, cum_p2m, cum_targets, cum_walked;  // since reset
 };
@@ -78,11 +76,13 @@ struct Buffers {
            *parent = nullptr, *nsys = nullptr;
   double4 *com = nullptr;
   double *mom = nullptr;          // [nodes][8]
-  uint32_t *lvl_tmp = nullptr;    // [nodes] per-level child counts
-  uint32_t *lvl_bnd = nullptr;    // [nodes][8] octant starts of splitting nodes
-  uint32_t *lvl_part = nullptr;   // [kLevelBlocks] per-block child counts / scan
   uint8_t *lcp = nullptr;         // [N + 64] common leading digits with predecessor
-  uint32_t *lvl_big = nullptr;    // [nodes] nodes of more than 512 particles at a level
+  // flat octree build, per 256-particle tile (FT = tiles of max_particles)
+  uint16_t *fl_lt = nullptr;      // [N] first | last node level starting at a particle
+  uint64_t *fl_bits = nullptr;    // [levels][4 (FT + 1)] node-start bitmaps
+  uint32_t *fl_cnt = nullptr;     // [levels][FT + 1] nodes per tile -> prefix
+  uint32_t *fl_fst = nullptr;     // [levels][FT + 1] first run start -> next after tile
+  uint32_t *fl_tot = nullptr;     // [levels] nodes per level
   // groups
   uint32_t *gflag = nullptr;      // [N + 1] group starts / scan
   uint4 *groups = nullptr;        // [N]
@@ -118,6 +118,7 @@ struct tg_ctx {
   int32_t leaf_size = 8, group_size = 64, waves_per_cu = 8;
   int64_t max_nodes = 0;
   int64_t max_tiles = 0;
+  int64_t flat_tiles = 0;          // 256-particle tiles of max_particles
   int64_t n_tiles = 0;
   bool have_tree = false, have_moments = false;
   bool capturing = false;
