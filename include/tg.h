@@ -54,7 +54,8 @@ typedef enum {
   TG_EHIP = -3,       /* a HIP runtime call failed */
   TG_ECAPACITY = -4,  /* a capacity given at tg_create was exceeded */
   TG_ESTATE = -5,     /* call out of order (e.g. forces before a tree) */
-  TG_EDATA = -6       /* device found non-finite positions or mass <= 0 */
+  TG_EDATA = -6,      /* device found non-finite positions or mass <= 0 */
+  TG_EINTERNAL = -7   /* a bounded device-side wait gave up (TG_ERR_SORT) */
 } tg_status;
 
 typedef enum { TG_FP64 = 0, TG_MIXED = 1 } tg_precision;
@@ -65,6 +66,7 @@ typedef enum { TG_FP64 = 0, TG_MIXED = 1 } tg_precision;
 #define TG_ERR_NODES       0x4u  /* octree needed more than max_nodes */
 #define TG_ERR_FRONTIER    0x8u  /* walk frontier exceeded frontier_cap */
 #define TG_ERR_LISTS       0x10u /* list dump exceeded its capacity */
+#define TG_ERR_SORT        0x20u /* a radix-sort tile waited too long for its predecessor */
 
 typedef struct {
   int64_t max_particles;   /* capacity N for every call (>= 1) */

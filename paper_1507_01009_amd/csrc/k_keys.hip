@@ -145,29 +145,56 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos,
 }
 
 // ---- radix sort, 8-bit digits ----------------------------------------
-__global__ __launch_bounds__(256) void k_sort_hist(const uint64_t *__restrict__ key,
-                                                   const Tile *__restrict__ tiles,
-                                                   int shift,
-                                                   uint32_t *__restrict__ hist) {
-  __shared__ uint32_t cnt[256];
-  const Tile t = tiles[blockIdx.x];
-  cnt[threadIdx.x] = 0;
-  __syncthreads();
-  for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u)
-    atomicAdd(&cnt[(uint32_t)(key[i] >> shift) & 255u], 1u);
-  __syncthreads();
-  hist[t.hist0 + threadIdx.x * t.hstride] = cnt[threadIdx.x];
+// Stable LSD sort of (key, index), 8 passes of 8 bits, each system sorted
+// on its own (tiles never straddle systems).  One counting kernel gives the
+// digit totals of all passes per system; then one kernel per pass: a tile
+// (taken in dispatch order from a ticket) ranks its keys in LDS, publishes
+// its per-digit counts, adds up the counts of the earlier tiles of its
+// system by looking back through their published words (each a flag and a
+// count in one 32-bit word, written and read with agent-scope atomics), and
+// scatters.  The lowest waiting tile never waits on a later one, so every
+// wait ends; a wait is still bounded and reports TG_ERR_SORT if exceeded.
+constexpr uint32_t kStAgg = 1u << 30, kStIncl = 2u << 30, kStVal = (1u << 30) - 1u;
+
+__device__ __forceinline__ int tile_system(const uint32_t *sys_tile0, int S, uint32_t t) {
+  int lo = 0, hi = S - 1;      // last s with sys_tile0[s] <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sys_tile0[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
-// Stable scatter of one tile: ranks are computed round by round (256 keys
-// per round, in index order) from wave match masks built with ballots, keys
-// are staged in LDS in tile-sorted order, then written out so that runs of
-// one digit become contiguous stores.
-__global__ __launch_bounds__(256) void k_sort_scatter(
+// cnt[s][p][d]: keys of system s with digit d in pass p (cleared beforehand)
+__global__ __launch_bounds__(256) void k_sort_count(const uint64_t *__restrict__ key,
+                                                    const Tile *__restrict__ tiles,
+                                                    const uint32_t *__restrict__ sys_tile0,
+                                                    int S, uint32_t *__restrict__ cnt) {
+  __shared__ uint32_t c[8][256];
+  const Tile t = tiles[blockIdx.x];
+  const int s = tile_system(sys_tile0, S, blockIdx.x);
+#pragma unroll
+  for (int p = 0; p < 8; ++p) c[p][threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u) {
+    const uint64_t k = key[i];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) atomicAdd(&c[p][(uint32_t)(k >> (8 * p)) & 255u], 1u);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const uint32_t v = c[p][threadIdx.x];
+    if (v) atomicAdd(&cnt[(size_t)(s * 8 + p) * 256 + threadIdx.x], v);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sort_pass(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
-    const Tile *__restrict__ tiles, int shift,
-    const uint32_t *__restrict__ hist) {
+    const Tile *__restrict__ tiles, const uint32_t *__restrict__ sys_tile0, int S,
+    const int64_t *__restrict__ sysoff, int pass, const uint32_t *__restrict__ cnt,
+    uint32_t *status, uint32_t *ticket, uint32_t *err) {
   __shared__ uint64_t sk[kSortTile];
   __shared__ uint32_t sv[kSortTile];
   __shared__ uint32_t wcnt[4][256];
@@ -175,38 +202,40 @@ __global__ __launch_bounds__(256) void k_sort_scatter(
   __shared__ uint32_t loc_off[256];
   __shared__ uint32_t glob_off[256];
   __shared__ uint32_t scan_sh[4];
-  const Tile t = tiles[blockIdx.x];
-  const uint32_t cnt = t.end - t.start;
+  __shared__ uint32_t s_tile;
   const unsigned tid = threadIdx.x, w = tid >> 6;
+  const int shift = 8 * pass;
+  if (tid == 0) s_tile = atomicAdd(ticket, 1u);
   running[tid] = 0;
-  glob_off[tid] = hist[t.hist0 + tid * t.hstride];
+  __syncthreads();
+  const uint32_t tb = s_tile;
+  const Tile t = tiles[tb];
+  const int s = tile_system(sys_tile0, S, tb);
+  const uint32_t first_tile = sys_tile0[s];
+  const uint32_t n_in = t.end - t.start;
 
   uint64_t k[kSortItems];
   uint32_t v[kSortItems], rk[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    uint32_t idx = r * 256u + tid;
-    if (idx < cnt) {
-      k[r] = kin[t.start + idx];
-      v[r] = vin[t.start + idx];
-    } else {
-      k[r] = 0;
-      v[r] = 0;
-    }
+    const uint32_t idx = r * 256u + tid;
+    k[r] = idx < n_in ? kin[t.start + idx] : 0ull;
+    v[r] = idx < n_in ? vin[t.start + idx] : 0u;
   }
-  __syncthreads();
+  // stable ranks inside the tile: 256 keys per round in index order, peers
+  // of equal digit found with ballots
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const uint32_t idx = r * 256u + tid;
-    const bool valid = idx < cnt;
+    const bool valid = idx < n_in;
     const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
     wcnt[0][tid] = 0; wcnt[1][tid] = 0; wcnt[2][tid] = 0; wcnt[3][tid] = 0;
     __syncthreads();
     unsigned long long peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      unsigned long long bb = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? bb : ~bb;
+    for (int bit = 0; bit < 8; ++bit) {
+      const unsigned long long bb = __ballot((d >> bit) & 1u);
+      peers &= ((d >> bit) & 1u) ? bb : ~bb;
     }
     const uint32_t lr = lanes_below(peers);
     if (valid && lr == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
@@ -220,15 +249,47 @@ __global__ __launch_bounds__(256) void k_sort_scatter(
     running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
     __syncthreads();
   }
+  // publish this tile's count of digit tid, then look back for the prefix
+  const uint32_t mine = running[tid];
+  uint32_t *st = status + (size_t)tb * 256 + tid;
+  __hip_atomic_store(st, (tb == first_tile ? kStIncl : kStAgg) | mine, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t prefix = 0;
+  if (tb != first_tile) {
+    uint32_t q = tb;
+    bool done = false;
+    while (!done) {
+      --q;
+      uint32_t *sq = status + (size_t)q * 256 + tid;
+      uint32_t x = __hip_atomic_load(sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (uint32_t spin = 0; (x >> 30) == 0u; ++spin) {
+        if (spin >= (1u << 18)) {
+          set_err(err, TG_ERR_SORT);
+          x = kStIncl;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        x = __hip_atomic_load(sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      prefix += x & kStVal;
+      done = (x & kStIncl) != 0u || q == first_tile;
+    }
+    __hip_atomic_store(st, kStIncl | (prefix + mine), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // digit starts inside the system: sysoff + counts of smaller digits
   uint32_t tot;
-  loc_off[tid] = block_exclusive_scan(running[tid], scan_sh, tot);
+  const uint32_t dbase = block_exclusive_scan(cnt[(size_t)(s * 8 + pass) * 256 + tid],
+                                              scan_sh, tot);
+  glob_off[tid] = (uint32_t)sysoff[s] + dbase + prefix;
+  loc_off[tid] = block_exclusive_scan(mine, scan_sh, tot);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    uint32_t idx = r * 256u + tid;
-    if (idx < cnt) {
-      uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
-      uint32_t p = loc_off[d] + rk[r];
+    const uint32_t idx = r * 256u + tid;
+    if (idx < n_in) {
+      const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+      const uint32_t p = loc_off[d] + rk[r];
       sk[p] = k[r];
       sv[p] = v[r];
     }
@@ -236,11 +297,11 @@ __global__ __launch_bounds__(256) void k_sort_scatter(
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    uint32_t idx = r * 256u + tid;
-    if (idx < cnt) {
-      uint64_t kk = sk[idx];
-      uint32_t d = (uint32_t)(kk >> shift) & 255u;
-      uint32_t dst = glob_off[d] + (idx - loc_off[d]);
+    const uint32_t idx = r * 256u + tid;
+    if (idx < n_in) {
+      const uint64_t kk = sk[idx];
+      const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+      const uint32_t dst = glob_off[d] + (idx - loc_off[d]);
       kout[dst] = kk;
       vout[dst] = sv[idx];
     }
@@ -280,18 +341,20 @@ hipError_t launch_sort(tg_ctx *c) {
   Buffers &b = c->b;
   const int nt = (int)c->n_tiles;
   if (nt == 0) return hipSuccess;
-  const uint32_t nh = 256u * (uint32_t)nt;
+  // [8 tickets | pad | counts [S][8][256] | status [8][nt][256]], all zero
+  uint32_t *tickets = b.hist, *cnt = b.hist + kSortStatusBase;
+  uint32_t *status = cnt + (size_t)c->S * 8 * 256;
+  hipError_t e = fill_u32(b.hist, 0u, kSortStatusBase + (int64_t)8 * 256 * (c->S + nt),
+                          c->stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sort_count, dim3(nt), dim3(256), 0, c->stream, b.key[0], b.tiles,
+                     b.sys_tile0, c->S, cnt);
   for (int pass = 0; pass < 8; ++pass) {
-    const int shift = 8 * pass;
     const int src = pass & 1, dst = src ^ 1;
-    hipLaunchKernelGGL(k_sort_hist, dim3(nt), dim3(256), 0, c->stream,
-                       b.key[src], b.tiles, shift, b.hist);
-    hipError_t e = scan_u32(b.hist, b.hist, nh, nullptr, nullptr, b.scan_part,
-                            c->stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sort_scatter, dim3(nt), dim3(256), 0, c->stream,
-                       b.key[src], b.val[src], b.key[dst], b.val[dst], b.tiles,
-                       shift, b.hist);
+    hipLaunchKernelGGL(k_sort_pass, dim3(nt), dim3(256), 0, c->stream, b.key[src],
+                       b.val[src], b.key[dst], b.val[dst], b.tiles, b.sys_tile0, c->S,
+                       b.sysoff, pass, cnt, status + (size_t)pass * 256 * nt,
+                       tickets + pass, b.err);
   }
   return hipGetLastError();   // 8 passes: result back in key[0] / val[0]
 }

@@ -29,6 +29,7 @@ constexpr int kMaxSys = 256;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per tile
+constexpr int kSortStatusBase = 64;               // words before the digit counts (8 tickets + pad)
 constexpr int kScanBlocks = 256;
 constexpr int kMaxWavesPerCU = 16;
 constexpr int kMaxExternal = 1024;               // SMBHs / external point masses
@@ -67,7 +68,7 @@ struct Buffers {
   // sort
   uint64_t *key[2] = {nullptr, nullptr};
   uint32_t *val[2] = {nullptr, nullptr};
-  uint32_t *hist = nullptr;       // [256 * tiles]
+  uint32_t *hist = nullptr;       // sort: [tickets | digit counts [S][8][256] | tile status [8][tiles][256]]
   uint32_t *rank = nullptr;       // [N]
   double4 *spart = nullptr;       // [N]
   // nodes

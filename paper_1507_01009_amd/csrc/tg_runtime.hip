@@ -129,7 +129,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.root_of, S));
   A(dalloc(&b.key[0], N)); A(dalloc(&b.key[1], N));
   A(dalloc(&b.val[0], N)); A(dalloc(&b.val[1], N));
-  A(dalloc(&b.hist, 256 * c->max_tiles));
+  A(dalloc(&b.hist, kSortStatusBase + 8 * 256 * (S + c->max_tiles)));
   A(dalloc(&b.rank, N));
   A(dalloc(&b.spart, N));
   A(dalloc(&b.level, NN)); A(dalloc(&b.nchild, NN));
@@ -863,6 +863,8 @@ tg_status tg_sync(tg_ctx *c, uint32_t *bits) {
     return fail(TG_EDATA, "device: non-finite position or non-positive mass");
   if (h & (TG_ERR_NODES | TG_ERR_FRONTIER | TG_ERR_LISTS))
     return fail(TG_ECAPACITY, "device: node, frontier or list capacity exceeded");
+  if (h & TG_ERR_SORT)
+    return fail(TG_EINTERNAL, "device: radix-sort tile hand-off gave up waiting");
   return TG_OK;
 }
 
