@@ -256,23 +256,39 @@ __global__ __launch_bounds__(256) void k_sort_pass(
                      __HIP_MEMORY_SCOPE_AGENT);
   uint32_t prefix = 0;
   if (tb != first_tile) {
-    uint32_t q = tb;
-    bool done = false;
-    while (!done) {
-      --q;
-      uint32_t *sq = status + (size_t)q * 256 + tid;
-      uint32_t x = __hip_atomic_load(sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      for (uint32_t spin = 0; (x >> 30) == 0u; ++spin) {
-        if (spin >= (1u << 18)) {
+    // windows of up to 16 predecessors read at once; walk down from the
+    // nearest, adding counts, until a tile that holds its inclusive prefix
+    uint32_t q = tb;                 // tiles [first_tile, q) remain
+    uint32_t spin = 0;
+    for (;;) {
+      constexpr int kW = 16;
+      const uint32_t avail = min(q - first_tile, (uint32_t)kW);
+      uint32_t x[kW];
+#pragma unroll
+      for (int j = 0; j < kW; ++j)
+        x[j] = (uint32_t)j < avail
+                   ? __hip_atomic_load(status + (size_t)(q - 1 - j) * 256 + tid,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   : 0u;
+      uint32_t used = 0;
+      bool done = false;
+#pragma unroll
+      for (int j = 0; j < kW; ++j) {
+        if (done || (uint32_t)j != used || used >= avail) continue;
+        if ((x[j] >> 30) == 0u) continue;          // not published yet: poll again
+        prefix += x[j] & kStVal;
+        ++used;
+        done = (x[j] & kStIncl) != 0u;
+      }
+      if (done) break;
+      q -= used;                                   // q > first_tile: the first tile is inclusive
+      if (used == 0) {
+        if (++spin >= (1u << 18)) {
           set_err(err, TG_ERR_SORT);
-          x = kStIncl;
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        x = __hip_atomic_load(sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      prefix += x & kStVal;
-      done = (x & kStIncl) != 0u || q == first_tile;
     }
     __hip_atomic_store(st, kStIncl | (prefix + mine), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);

@@ -1,11 +1,11 @@
 // a7: monopole and quadrupole moments about each node's centre of mass
 // (the multipole expansion of a distant group about its centre of mass).
 //
-// Upward pass, one launch per level from 21 to 0 over the level's node
-// range.  A leaf sums its particles in sorted order, two passes (mass and
-// first moment, then the second moment about the centre of mass) with no
-// contraction, so leaf moments equal the plain definition bit for bit.  An
-// internal node combines its children with the parallel-axis theorem:
+// Leaves first, all in one launch: a leaf sums its particles in sorted
+// order, two passes (mass and first moment, then the second moment about
+// the centre of mass) with no contraction, so leaf moments equal the plain
+// definition bit for bit.  Then internal nodes, one launch per level from
+// 20 to 0, each combining its children with the parallel-axis theorem:
 //   M = sum M_c,  com = (sum M_c com_c) / M,
 //   S = sum (S_c + M_c d d^T),  d = com_c - com.
 // The cell side s = L 2^-level (exact) is stored squared beside the centre
@@ -27,64 +27,84 @@ __global__ void k_mass_gather(const double *__restrict__ mass,
   if (bad) set_err(err, TG_ERR_MASS);
 }
 
-__global__ __launch_bounds__(256) void k_moments_level(
-    int l, const TreeCounters *ctr, const double *__restrict__ cube,
-    const uint8_t *__restrict__ nchild, const uint32_t *__restrict__ first,
-    const uint32_t *__restrict__ count, const uint32_t *__restrict__ child,
+__device__ __forceinline__ void store_moments(uint32_t v, int l, const double *cube,
+                                              const uint32_t *nsys, double M, double cx,
+                                              double cy, double cz, const double S[6],
+                                              double4 *com, double *mom) {
+  const double s = ldexp(cube[4 * nsys[v] + 3], -l);
+  com[v] = make_double4(cx, cy, cz, s * s);
+  double *o = mom + 8 * (size_t)v;
+  o[0] = M;
+  for (int k = 0; k < 6; ++k) o[1 + k] = S[k];
+  o[7] = 0.0;
+}
+
+// Every leaf of the tree (nodes without children), any level.
+__global__ __launch_bounds__(256) void k_moments_leaves(
+    const TreeCounters *ctr, const double *__restrict__ cube,
+    const uint8_t *__restrict__ level, const uint8_t *__restrict__ nchild,
+    const uint32_t *__restrict__ first, const uint32_t *__restrict__ count,
     const uint32_t *__restrict__ nsys, const double4 *__restrict__ spart,
     double4 *__restrict__ com, double *__restrict__ mom) {
+#pragma clang fp contract(off)
+  const uint32_t nn = ctr->n_nodes;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
+       v += gridDim.x * blockDim.x) {
+    if (nchild[v] != 0) continue;
+    const uint32_t f = first[v], end = f + count[v];
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    for (uint32_t j = f; j < end; ++j) {
+      const double4 p = spart[j];
+      M += p.w;
+      sx += p.w * p.x;
+      sy += p.w * p.y;
+      sz += p.w * p.z;
+    }
+    const double cx = sx / M, cy = sy / M, cz = sz / M;
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (uint32_t j = f; j < end; ++j) {
+      const double4 p = spart[j];
+      const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+      S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
+      S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
+    }
+    store_moments(v, level[v], cube, nsys, M, cx, cy, cz, S, com, mom);
+  }
+}
+
+// Internal nodes of level l from their children (level l + 1, done).
+__global__ __launch_bounds__(256) void k_moments_level(
+    int l, const TreeCounters *ctr, const double *__restrict__ cube,
+    const uint8_t *__restrict__ nchild, const uint32_t *__restrict__ child,
+    const uint32_t *__restrict__ nsys, double4 *__restrict__ com, double *__restrict__ mom) {
 #pragma clang fp contract(off)
   const uint32_t a = ctr->lvl[l], e = ctr->lvl[l + 1];
   for (uint32_t v = a + blockIdx.x * blockDim.x + threadIdx.x; v < e;
        v += gridDim.x * blockDim.x) {
-    double M = 0.0, cx, cy, cz;
-    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const uint32_t nch = nchild[v];
-    if (nch == 0) {
-      const uint32_t f = first[v], end = f + count[v];
-      double sx = 0.0, sy = 0.0, sz = 0.0;
-      for (uint32_t j = f; j < end; ++j) {
-        const double4 p = spart[j];
-        M += p.w;
-        sx += p.w * p.x;
-        sy += p.w * p.y;
-        sz += p.w * p.z;
-      }
-      cx = sx / M; cy = sy / M; cz = sz / M;
-      for (uint32_t j = f; j < end; ++j) {
-        const double4 p = spart[j];
-        const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
-        S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
-        S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
-      }
-    } else {
-      const uint32_t c0 = child[v];
-      double sx = 0.0, sy = 0.0, sz = 0.0;
-      for (uint32_t k = 0; k < nch; ++k) {
-        const double mc = mom[8 * (size_t)(c0 + k)];
-        const double4 cc = com[c0 + k];
-        M += mc;
-        sx += mc * cc.x;
-        sy += mc * cc.y;
-        sz += mc * cc.z;
-      }
-      cx = sx / M; cy = sy / M; cz = sz / M;
-      for (uint32_t k = 0; k < nch; ++k) {
-        const double *o = mom + 8 * (size_t)(c0 + k);
-        const double4 cc = com[c0 + k];
-        const double dx = cc.x - cx, dy = cc.y - cy, dz = cc.z - cz;
-        const double mc = o[0];
-        S[0] += o[1] + mc * dx * dx; S[1] += o[2] + mc * dy * dy;
-        S[2] += o[3] + mc * dz * dz; S[3] += o[4] + mc * dx * dy;
-        S[4] += o[5] + mc * dx * dz; S[5] += o[6] + mc * dy * dz;
-      }
+    if (nch == 0) continue;
+    const uint32_t c0 = child[v];
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    for (uint32_t k = 0; k < nch; ++k) {
+      const double mc = mom[8 * (size_t)(c0 + k)];
+      const double4 cc = com[c0 + k];
+      M += mc;
+      sx += mc * cc.x;
+      sy += mc * cc.y;
+      sz += mc * cc.z;
     }
-    const double s = ldexp(cube[4 * nsys[v] + 3], -l);
-    com[v] = make_double4(cx, cy, cz, s * s);
-    double *o = mom + 8 * (size_t)v;
-    o[0] = M;
-    for (int k = 0; k < 6; ++k) o[1 + k] = S[k];
-    o[7] = 0.0;
+    const double cx = sx / M, cy = sy / M, cz = sz / M;
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (uint32_t k = 0; k < nch; ++k) {
+      const double *o = mom + 8 * (size_t)(c0 + k);
+      const double4 cc = com[c0 + k];
+      const double dx = cc.x - cx, dy = cc.y - cy, dz = cc.z - cz;
+      const double mc = o[0];
+      S[0] += o[1] + mc * dx * dx; S[1] += o[2] + mc * dy * dy;
+      S[2] += o[3] + mc * dz * dz; S[3] += o[4] + mc * dx * dy;
+      S[4] += o[5] + mc * dx * dz; S[5] += o[6] + mc * dy * dz;
+    }
+    store_moments(v, l, cube, nsys, M, cx, cy, cz, S, com, mom);
   }
 }
 
@@ -94,10 +114,12 @@ hipError_t launch_moments(tg_ctx *c, const double *mass) {
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_mass_gather, dim3(g), dim3(256), 0, c->stream, mass,
                      b.val[0], c->n, b.spart, b.err);
-  for (int l = kMaxLevel; l >= 0; --l)
-    hipLaunchKernelGGL(k_moments_level, dim3(1024), dim3(256), 0, c->stream, l,
-                       b.ctr, b.cube, b.nchild, b.first, b.count, b.child,
-                       b.nsys, b.spart, b.com, b.mom);
+  hipLaunchKernelGGL(k_moments_leaves, dim3(1024), dim3(256), 0, c->stream, b.ctr,
+                     b.cube, b.level, b.nchild, b.first, b.count, b.nsys, b.spart, b.com,
+                     b.mom);
+  for (int l = kMaxLevel - 1; l >= 0; --l)     // level 21 holds only leaves
+    hipLaunchKernelGGL(k_moments_level, dim3(256), dim3(256), 0, c->stream, l, b.ctr,
+                       b.cube, b.nchild, b.child, b.nsys, b.com, b.mom);
   return hipGetLastError();
 }
 

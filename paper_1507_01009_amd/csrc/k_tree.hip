@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(
     uint32_t *__restrict__ root_of, uint8_t *__restrict__ level,
     uint8_t *__restrict__ nchild, uint32_t *__restrict__ first,
     uint32_t *__restrict__ count, uint32_t *__restrict__ child,
-    uint32_t *__restrict__ parent, uint32_t *__restrict__ nsys) {
+    uint32_t *__restrict__ parent, uint32_t *__restrict__ nsys, uint4 *__restrict__ ninfo) {
   __shared__ uint8_t sd[kFT];
   __shared__ uint8_t mn8[kFT / 8], mn64[kFT / 64];
   __shared__ int64_t so[kMaxSys + 1];
@@ -294,16 +294,17 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(
     count[id] = (uint32_t)(e - i);
     nsys[id] = (uint32_t)s;
     parent[id] = l == 0 ? kNone : lv[l - 1] + rank_of(bits + (l - 1) * wl, cnt + (l - 1) * tl, i + 1) - 1u;
+    uint32_t ch = 0, nch = 0;
     if (l < top) {
       const uint64_t *bc = bits + (l + 1) * wl;
       const uint32_t *cc = cnt + (l + 1) * tl;
       const uint32_t r0 = rank_of(bc, cc, i);
-      child[id] = lv[l + 1] + r0;
-      nchild[id] = (uint8_t)(rank_of(bc, cc, e) - r0);
-    } else {
-      child[id] = 0;
-      nchild[id] = 0;
+      ch = lv[l + 1] + r0;
+      nch = rank_of(bc, cc, e) - r0;
     }
+    child[id] = ch;
+    nchild[id] = (uint8_t)nch;
+    ninfo[id] = make_uint4((uint32_t)i, (uint32_t)(e - i), ch, nch);
   }
 }
 
@@ -323,7 +324,7 @@ hipError_t launch_tree_build(tg_ctx *c) {
                      c->stream, n, c->S, b.sysoff, b.lcp, b.fl_lt, b.fl_bits, wl,
                      b.fl_cnt, b.fl_fst, tl, b.fl_tot, c->max_nodes, b.ctr, b.err,
                      b.root_of, b.level, b.nchild, b.first, b.count, b.child, b.parent,
-                     b.nsys);
+                     b.nsys, b.ninfo);
   return hipGetLastError();
 }
 

@@ -31,8 +31,8 @@
 //          accelerations, 1 for the potential.
 //   P2M 54: 3 sub, 6 for r^2 + eps^2, 3 for D2..D5, 15 for Q x, 6 for W,
 //          2 for D4 W, 3 for the radial coefficient, 12 for the
-//          accelerations, 4 for the potential (Q = 3S - T I and T eps^2 of a
-//          cell are formed once per tile, not per interaction).
+//          accelerations, 4 for the potential (Q = 3S - T I, -T eps^2 and M
+//          of every node are formed once per evaluation, k_cell_records).
 #include <type_traits>
 
 #include "tg_internal.h"
@@ -59,10 +59,9 @@ constexpr int kMCap = 128 + 64;             // P2M cell list (LDS): < one flush 
 constexpr int kQCap = 128 + 64 * 8;         // P2P particle queue (LDS); overflow goes leaf by leaf
 
 struct WalkArgs {
-  const uint8_t *nchild;
-  const uint32_t *first, *count, *child;
+  const uint4 *ninfo;       // {first, count, child, nchild} per node
   const double4 *com;
-  const double *mom;
+  const void *cell;         // walk records per node (float4[2] mixed, double4[2] FP64)
   const double4 *spart;
   const uint32_t *root_of;
   const uint4 *groups;
@@ -154,7 +153,7 @@ __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x);
 __device__ __forceinline__ double rsq(double x) { return rsqrt_dp(x); }
 
 // Softened quadrupole term of one cell on one target, x = target - com.
-// Cell: a = {com, M}, b = {Qxx, Qyy, Qzz, T eps^2}, c = {Qxy, Qxz, Qyz, -}
+// Cell: a = {com, M}, b = {Qxx, Qyy, Qzz, -T eps^2}, c = {Qxy, Qxz, Qyz, -}
 // with the traceless Q = 3S - T I, T = tr S.  With r^2 = |x|^2 + eps^2 and
 // D_n = r^-n, the expansion of the softened potential about the centre of
 // mass gives
@@ -174,7 +173,7 @@ __device__ __forceinline__ void p2m_term(typename Vec4<R>::T a, typename Vec4<R>
   const R Qx = fma(c.y, z, fma(c.x, y, b.x * x));
   const R Qy = fma(c.z, z, fma(b.y, y, c.x * x));
   const R Qz = fma(b.z, z, fma(c.z, y, c.y * x));
-  const R W = fma(z, Qz, fma(y, Qy, x * Qx)) - b.w;
+  const R W = fma(z, Qz, fma(y, Qy, fma(x, Qx, b.w)));
   const R k = (u * W) * u;                     // D4 W
   const R C = D3 * fma(R(2.5), k, a.w);        // M D3 + 2.5 D7 W
   ax = fma(D5, Qx, fma(-C, x, ax));
@@ -243,7 +242,6 @@ struct ForceSink {
   int T, lt, slices, tfull, F, my_s;
   double cgx, cgy, cgz;              // coordinate origin of the group (0 in FP64)
   R e2;
-  double e2d;
   R tx[kMaxT], ty[kMaxT], tz[kMaxT];
   // FP64: plain sums in h*; mixed: compensated (h*, l*) float pairs
   R hax[kMaxT], hay[kMaxT], haz[kMaxT], hph[kMaxT];
@@ -313,14 +311,11 @@ struct ForceSink {
   __device__ void stage_cell(const WalkArgs &A, int e, bool live, uint32_t v) {
     if (live) {
       const double4 cm = A.com[v];
-      const double4 m0 = reinterpret_cast<const double4 *>(A.mom)[2 * (size_t)v];
-      const double4 m1 = reinterpret_cast<const double4 *>(A.mom)[2 * (size_t)v + 1];
-      // m0 = {M, Sxx, Syy, Szz}, m1 = {Sxy, Sxz, Syz, -}
-      const double T = m0.y + m0.z + m0.w;
-      tile->m[e].a = R4{(R)(cm.x - cgx), (R)(cm.y - cgy), (R)(cm.z - cgz), (R)m0.x};
-      tile->m[e].b = R4{(R)(3.0 * m0.y - T), (R)(3.0 * m0.z - T), (R)(3.0 * m0.w - T),
-                        (R)(T * e2d)};
-      tile->m[e].c = R4{(R)(3.0 * m1.x), (R)(3.0 * m1.y), (R)(3.0 * m1.z), R(0)};
+      const R4 *r = reinterpret_cast<const R4 *>(A.cell) + 2 * (size_t)v;
+      const R4 q0 = r[0], q1 = r[1];
+      tile->m[e].a = R4{(R)(cm.x - cgx), (R)(cm.y - cgy), (R)(cm.z - cgz), q1.w};
+      tile->m[e].b = q0;
+      tile->m[e].c = q1;
     } else {
       tile->m[e].a = tile->m[e].b = tile->m[e].c = R4{R(0), R(0), R(0), R(0)};
     }
@@ -484,10 +479,8 @@ __device__ bool traverse(const WalkArgs &A, Sink &sink, uint32_t root,
       if (valid) {
         node = cur[i];
         const double4 c = A.com[node];
-        nch = A.nchild[node];
-        ch = A.child[node];
-        f = A.first[node];
-        cnt = A.count[node];
+        const uint4 nf = A.ninfo[node];
+        f = nf.x; cnt = nf.y; ch = nf.z; nch = nf.w;
         acc = mac_accept(lo, hi, c, A.th2);
       }
       const bool leaf = valid && !acc && nch == 0;
@@ -591,7 +584,6 @@ void k_walk_forces(WalkArgs A) {
     } else {
       S.cgx = S.cgy = S.cgz = 0.0;
     }
-    S.e2d = A.eps2;
     S.e2 = (R)A.eps2;
 #pragma unroll
     for (int k = 0; k < kMaxT; ++k) {
@@ -721,19 +713,21 @@ __global__ void k_mark_active(const int32_t *__restrict__ idx,
   }
 }
 
-__device__ __forceinline__ double wmin(double v) {
+// Min / max over the 16 lanes of a quarter wave.
+__device__ __forceinline__ double qmin(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  for (int o = 8; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
   return v;
 }
-__device__ __forceinline__ double wmax(double v) {
+__device__ __forceinline__ double qmax(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  for (int o = 8; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
 
-// One wave per group: flag groups with an active particle and store the
-// box of their active particles.
+// Sixteen lanes per group (a group holds at most 64 particles: four loads
+// per lane): flag groups with an active particle and store the box of
+// their active particles.
 __global__ __launch_bounds__(256) void k_group_active(const TreeCounters *ctr,
                                                       const uint4 *__restrict__ groups,
                                                       const uint8_t *__restrict__ sact,
@@ -741,21 +735,32 @@ __global__ __launch_bounds__(256) void k_group_active(const TreeCounters *ctr,
                                                       uint32_t *__restrict__ aflag,
                                                       double *__restrict__ abox) {
   const uint32_t ng = ctr->n_groups;
-  const unsigned lane = threadIdx.x & 63u;
-  const uint32_t wpb = blockDim.x >> 6;
-  for (uint32_t g = blockIdx.x * wpb + (threadIdx.x >> 6); g < ng;
-       g += gridDim.x * wpb) {
-    const uint4 gr = groups[g];
-    const bool in = lane < gr.y;
-    const bool a = in && sact[gr.x + lane];
-    const unsigned long long m = __ballot(a);
-    double4 p = in ? spart[gr.x + lane] : make_double4(0, 0, 0, 0);
-    double lx = a ? p.x : INFINITY, ly = a ? p.y : INFINITY, lz = a ? p.z : INFINITY;
-    double hx = a ? p.x : -INFINITY, hy = a ? p.y : -INFINITY, hz = a ? p.z : -INFINITY;
-    lx = wmin(lx); ly = wmin(ly); lz = wmin(lz);
-    hx = wmax(hx); hy = wmax(hy); hz = wmax(hz);
-    if (lane == 0) {
-      aflag[g] = m ? 1u : 0u;
+  const unsigned q = threadIdx.x & 15u;
+  const uint32_t qpb = blockDim.x >> 4;
+  for (uint32_t g0 = blockIdx.x * qpb; g0 < ng; g0 += gridDim.x * qpb) {
+    const uint32_t g = g0 + (threadIdx.x >> 4);     // quarter-waves stay in step
+    const bool live = g < ng;
+    const uint4 gr = live ? groups[g] : make_uint4(0, 0, 0, 0);
+    double lx = INFINITY, ly = INFINITY, lz = INFINITY;
+    double hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t j = q + 16u * r;
+      const bool a = j < gr.y && sact[gr.x + j];
+      if (a) {
+        const double4 p = spart[gr.x + j];
+        lx = fmin(lx, p.x); ly = fmin(ly, p.y); lz = fmin(lz, p.z);
+        hx = fmax(hx, p.x); hy = fmax(hy, p.y); hz = fmax(hz, p.z);
+        any = true;
+      }
+    }
+    lx = qmin(lx); ly = qmin(ly); lz = qmin(lz);
+    hx = qmax(hx); hy = qmax(hy); hz = qmax(hz);
+    const unsigned long long m = __ballot(any);
+    const unsigned long long mine = (m >> (threadIdx.x & 48u)) & 0xffffull;
+    if (live && q == 0) {
+      aflag[g] = mine ? 1u : 0u;
       double *b = abox + 6 * (size_t)g;
       b[0] = lx; b[1] = ly; b[2] = lz; b[3] = hx; b[4] = hy; b[5] = hz;
     }
@@ -819,8 +824,8 @@ hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
 static WalkArgs make_args(tg_ctx *c, double theta) {
   Buffers &b = c->b;
   WalkArgs A;
-  A.nchild = b.nchild; A.first = b.first; A.count = b.count; A.child = b.child;
-  A.com = b.com; A.mom = b.mom; A.spart = b.spart; A.root_of = b.root_of;
+  A.ninfo = b.ninfo; A.com = b.com; A.cell = b.cell;
+  A.spart = b.spart; A.root_of = b.root_of;
   A.groups = b.groups; A.alist = b.alist; A.abox = b.abox; A.sact = b.sact;
   A.perm = b.val[0]; A.ctr = b.ctr; A.err = b.err; A.frontier = b.frontier;
   A.fcap = c->cfg.frontier_cap;
@@ -832,6 +837,27 @@ static WalkArgs make_args(tg_ctx *c, double theta) {
   A.eps = 0.0;
   A.wl_count = b.wl_count; A.wl_off = b.wl_off; A.ids = nullptr;
   return A;
+}
+
+// Walk records of every node: Q = 3S - T I, -T eps^2 and M, in the walk's
+// precision, formed once per evaluation instead of once per staged cell.
+template <class R>
+__global__ __launch_bounds__(256) void k_cell_records(const TreeCounters *ctr,
+                                                      const double *__restrict__ mom,
+                                                      double eps2, void *cell) {
+  using R4 = typename Vec4<R>::T;
+  R4 *out = reinterpret_cast<R4 *>(cell);
+  const uint32_t nn = ctr->n_nodes;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
+       v += gridDim.x * blockDim.x) {
+    const double4 m0 = reinterpret_cast<const double4 *>(mom)[2 * (size_t)v];
+    const double4 m1 = reinterpret_cast<const double4 *>(mom)[2 * (size_t)v + 1];
+    // m0 = {M, Sxx, Syy, Szz}, m1 = {Sxy, Sxz, Syz, -}
+    const double T = m0.y + m0.z + m0.w;
+    out[2 * (size_t)v] = R4{(R)(3.0 * m0.y - T), (R)(3.0 * m0.z - T), (R)(3.0 * m0.w - T),
+                            (R)(-(T * eps2))};
+    out[2 * (size_t)v + 1] = R4{(R)(3.0 * m1.x), (R)(3.0 * m1.y), (R)(3.0 * m1.z), (R)m0.x};
+  }
 }
 
 static int walk_grid(tg_ctx *c) {
@@ -846,6 +872,12 @@ hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
   A.eps = eps;
   A.acc = acc;
   A.pot = pot;
+  if (c->cfg.precision == TG_MIXED)
+    hipLaunchKernelGGL(k_cell_records<float>, dim3(1024), dim3(256), 0, c->stream, c->b.ctr,
+                       c->b.mom, A.eps2, (void *)c->b.cell);
+  else
+    hipLaunchKernelGGL(k_cell_records<double>, dim3(1024), dim3(256), 0, c->stream, c->b.ctr,
+                       c->b.mom, A.eps2, (void *)c->b.cell);
   hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, c->stream, c->b.ctr);
   if (before) {
     hipError_t e = hipEventRecord(before, c->stream);

@@ -77,6 +77,9 @@ struct Buffers {
            *parent = nullptr, *nsys = nullptr;
   double4 *com = nullptr;
   double *mom = nullptr;          // [nodes][8]
+  uint4 *ninfo = nullptr;         // [nodes] {first, count, child, nchild} for the walk
+  double4 *cell = nullptr;        // [nodes][2] walk records {Qxx,Qyy,Qzz,-T eps^2} {Qxy,Qxz,Qyz,M}
+                                  // (FP64; the mixed path uses the first half as float4[nodes][2])
   uint8_t *lcp = nullptr;         // [N + 64] common leading digits with predecessor
   // flat octree build, per 256-particle tile (FT = tiles of max_particles)
   uint16_t *fl_lt = nullptr;      // [N] first | last node level starting at a particle

@@ -64,7 +64,7 @@ static void free_all(tg_ctx *c) {
   void *ptrs[] = {b.sysoff, b.cube, b.cube_part, b.tiles, b.sys_tile0,
                   b.root_of, b.key[0], b.key[1], b.val[0], b.val[1], b.hist,
                   b.rank, b.spart, b.level, b.nchild, b.first, b.count,
-                  b.child, b.parent, b.nsys, b.com, b.mom, b.lcp, b.fl_lt, b.fl_bits, b.fl_cnt, b.fl_fst, b.fl_tot, b.gflag,
+                  b.child, b.parent, b.nsys, b.com, b.mom, b.ninfo, b.cell, b.lcp, b.fl_lt, b.fl_bits, b.fl_cnt, b.fl_fst, b.fl_tot, b.gflag,
                   b.groups, b.aflag, b.alist, b.abox, b.sact, b.frontier,
                   b.wl_count, b.wl_off, b.scan_part, b.scan_total, b.ctr,
                   b.err, b.dpart, b.dseg, b.ext_seg};
@@ -136,6 +136,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.first, NN)); A(dalloc(&b.count, NN)); A(dalloc(&b.child, NN));
   A(dalloc(&b.parent, NN)); A(dalloc(&b.nsys, NN));
   A(dalloc(&b.com, NN)); A(dalloc(&b.mom, 8 * NN));
+  A(dalloc(&b.ninfo, NN)); A(dalloc(&b.cell, 2 * NN));
   c->flat_tiles = (N + 255) / 256;
   A(dalloc(&b.lcp, N + 64));
   A(dalloc(&b.fl_lt, std::max<int64_t>(N, 1)));
