@@ -45,7 +45,7 @@ namespace tg {
 #define TG_WALK_MAXT_MIXED 2
 #endif
 #ifndef TG_WALK_MAXT_FP64
-#define TG_WALK_MAXT_FP64 2
+#define TG_WALK_MAXT_FP64 3
 #endif
 #ifndef TG_WALK_WAVES_MIXED
 #define TG_WALK_WAVES_MIXED 4
@@ -86,15 +86,18 @@ struct WalkArgs {
 };
 
 // ---------------------------------------------------------------- helpers
+// Exclusive prefix sum over the 64 lanes and the wave total, on DPP lane
+// moves: shifts by 1, 2, 4, 8 inside each row of 16, then row 0's total to
+// rows 1 and 3 and the first 32 lanes' total to rows 2 and 3.
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t &tot) {
-  const unsigned lane = lane_id();
   uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= (unsigned)o) x += y;
-  }
-  tot = __shfl(x, 63, 64);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  tot = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
   return x - v;
 }
 
@@ -387,14 +390,13 @@ struct ForceSink {
     }
   }
 
+  // pred: this lane's leaf is refused; c = its particle count (0 if not
+  // pred), pre / tot = exclusive prefix and wave total of c
   __device__ void p2p(const WalkArgs &A, bool pred, uint32_t node, uint32_t f,
-                      uint32_t cnt) {
+                      uint32_t c, uint32_t pre, uint32_t tot) {
     (void)node;
     const unsigned long long mask = __ballot(pred);
     if (mask == 0ull) return;
-    const uint32_t c = pred ? cnt : 0u;
-    uint32_t tot;
-    const uint32_t pre = wave_excl_scan(c, tot);
     parts += tot;
     if (nq + tot <= (uint32_t)kQCap) {
       for (uint32_t k = 0; k < c; ++k) s_q[nq + pre + k] = f + k;
@@ -434,7 +436,8 @@ struct CountSink {
   __device__ void p2m(const WalkArgs &, bool pred, uint32_t) {
     nm += (uint32_t)__popcll(__ballot(pred));
   }
-  __device__ void p2p(const WalkArgs &, bool pred, uint32_t, uint32_t, uint32_t) {
+  __device__ void p2p(const WalkArgs &, bool pred, uint32_t, uint32_t, uint32_t, uint32_t,
+                      uint32_t) {
     np += (uint32_t)__popcll(__ballot(pred));
   }
   __device__ void finish(const WalkArgs &) {}
@@ -448,7 +451,8 @@ struct FillSink {
     if (pred) A.ids[base_m + nm + lanes_below(mask)] = node;
     nm += (uint32_t)__popcll(mask);
   }
-  __device__ void p2p(const WalkArgs &A, bool pred, uint32_t node, uint32_t, uint32_t) {
+  __device__ void p2p(const WalkArgs &A, bool pred, uint32_t node, uint32_t, uint32_t,
+                      uint32_t, uint32_t) {
     const unsigned long long mask = __ballot(pred);
     if (pred) A.ids[base_p + np + lanes_below(mask)] = node;
     np += (uint32_t)__popcll(mask);
@@ -485,11 +489,23 @@ __device__ bool traverse(const WalkArgs &A, Sink &sink, uint32_t root,
       }
       const bool leaf = valid && !acc && nch == 0;
       const bool open = valid && !acc && nch > 0;
-      sink.p2m(A, acc, node);
-      sink.p2p(A, leaf, node, f, cnt);
-      uint32_t tot;
+      // prefix sums of the particles of refused leaves and of the children
+      // of opened cells: one scan of packed 16-bit halves unless a leaf
+      // holds 1024 or more particles
+      const uint32_t pc = leaf ? cnt : 0u;
       const uint32_t c = open ? nch : 0u;
-      const uint32_t pre = wave_excl_scan(c, tot);
+      uint32_t ppre, ptot, pre, tot;
+      if (__ballot(pc >= 1024u) == 0ull) {
+        uint32_t t2;
+        const uint32_t e2 = wave_excl_scan(pc | (c << 16), t2);
+        ppre = e2 & 0xffffu; ptot = t2 & 0xffffu;
+        pre = e2 >> 16; tot = t2 >> 16;
+      } else {
+        ppre = wave_excl_scan(pc, ptot);
+        pre = wave_excl_scan(c, tot);
+      }
+      sink.p2m(A, acc, node);
+      sink.p2p(A, leaf, node, f, pc, ppre, ptot);
       if (nf + tot > (uint32_t)A.fcap) {
         if (lane == 0) set_err(A.err, TG_ERR_FRONTIER);
         return false;
