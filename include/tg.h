@@ -72,7 +72,7 @@ typedef struct {
   int64_t max_particles;   /* capacity N for every call (>= 1) */
   int32_t max_systems;     /* capacity of independent systems S (1..256) */
   int32_t leaf_size;       /* n_L: a node with more particles is refined (1..16) */
-  int32_t group_size;      /* n_G: particles sharing one walk (1..64) */
+  int32_t group_size;      /* n_G: particles sharing one walk (1..128) */
   int32_t precision;       /* tg_precision of the walk and P2P/P2M sums */
   int64_t max_nodes;       /* octree node capacity; 0 = 2 * max_particles + 64 * max_systems */
   int32_t frontier_cap;    /* walk frontier entries per wave; 0 = 16384 */

@@ -550,7 +550,7 @@ struct GroupQueue {
 template <bool kMixed>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMixed ? TG_WALK_WAVES_MIXED : TG_WALK_WAVES_FP64)))
 void k_walk_forces(WalkArgs A) {
-  __shared__ uint32_t s_tgt[64];
+  __shared__ uint32_t s_tgt[kMaxGroup];
   __shared__ uint32_t s_m[kMCap];
   __shared__ uint32_t s_q[kQCap];
   __shared__ TileMem<kMixed> tile;
@@ -570,17 +570,22 @@ void k_walk_forces(WalkArgs A) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) { lo[k] = A.abox[6 * (size_t)g + k]; hi[k] = A.abox[6 * (size_t)g + 3 + k]; }
     // compact the active targets of the group
-    const bool act = lane < gr.y && A.sact[gr.x + lane];
-    const unsigned long long amask = __ballot(act);
-    if (act) s_tgt[lanes_below(amask)] = gr.x + lane;
-    const int nt = __popcll(amask);
+    int nt = 0;
+    for (uint32_t c0 = 0; c0 < gr.y; c0 += 64u) {
+      const bool act = c0 + lane < gr.y && A.sact[gr.x + c0 + lane];
+      const unsigned long long amask = __ballot(act);
+      if (act) s_tgt[nt + lanes_below(amask)] = gr.x + c0 + lane;
+      nt += __popcll(amask);
+    }
     __syncthreads();
     if (nt == 0) continue;   // cannot happen for a listed group; keeps s_tgt reads defined
-    // shape: T targets per lane, lt lane-targets, slices source slices;
-    // minimise T / slices, ties to the larger T
-    int T = 1, lt = nt, slices = 64 / nt;
+    // shape: T targets per lane (at least ceil(nt / 64)), lt lane-targets,
+    // slices source slices; minimise T / slices, ties to the larger T
+    int T = (nt + 63) / 64;
+    int lt = (nt + T - 1) / T, slices = 64 / lt;
 #pragma unroll
     for (int t = 2; t <= kMaxT; ++t) {
+      if (t <= T) continue;
       const int l2 = (nt + t - 1) / t, s2 = 64 / l2;
       if (t * slices <= T * s2) { T = t; lt = l2; slices = s2; }
     }
@@ -626,16 +631,16 @@ void k_walk_forces(WalkArgs A) {
       }
     }
     __syncthreads();
-    if ((int)lane < nt) {
+    for (int i = (int)lane; i < nt; i += 64) {
       // target i sits at k = i / lt, lane-target i % lt of every slice; sum
       // the slices in slice order (deterministic)
-      const int k = (int)lane / lt, jj = (int)lane % lt;
+      const int k = i / lt, jj = i % lt;
       double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
       for (int q = 0; q < slices; ++q) {
         const double *o = red + 4 * (64 * k + q * lt + jj);
         ax += o[0]; ay += o[1]; az += o[2]; ph += o[3];
       }
-      const uint32_t r_t = s_tgt[lane];
+      const uint32_t r_t = s_tgt[i];
       const double4 p = A.spart[r_t];
       double self;
       if constexpr (kMixed)
@@ -741,9 +746,9 @@ __device__ __forceinline__ double qmax(double v) {
   return v;
 }
 
-// Sixteen lanes per group (a group holds at most 64 particles: four loads
-// per lane): flag groups with an active particle and store the box of
-// their active particles.
+// Sixteen lanes per group (a group holds at most kMaxGroup particles):
+// flag groups with an active particle and store the box of their active
+// particles.
 __global__ __launch_bounds__(256) void k_group_active(const TreeCounters *ctr,
                                                       const uint4 *__restrict__ groups,
                                                       const uint8_t *__restrict__ sact,
@@ -761,7 +766,7 @@ __global__ __launch_bounds__(256) void k_group_active(const TreeCounters *ctr,
     double hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
     bool any = false;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kMaxGroup / 16; ++r) {
       const uint32_t j = q + 16u * r;
       const bool a = j < gr.y && sact[gr.x + j];
       if (a) {

@@ -24,7 +24,7 @@ constexpr int kMaxLevel = 21;         // deepest octree level
 constexpr int kLevels = kMaxLevel + 1;
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int kMaxLeaf = 16;          // largest n_L (bounds the walk's LDS queue)
-constexpr int kMaxGroup = 64;         // one wavefront of targets
+constexpr int kMaxGroup = 128;        // targets of one walk (one wave, up to 3 per lane)
 constexpr int kMaxSys = 256;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;

@@ -84,7 +84,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   if (cfg.leaf_size < 1 || cfg.leaf_size > kMaxLeaf)
     return fail(TG_EINVAL, "tg_create: leaf_size must be in 1..16");
   if (cfg.group_size < 1 || cfg.group_size > kMaxGroup)
-    return fail(TG_EINVAL, "tg_create: group_size must be in 1..64");
+    return fail(TG_EINVAL, "tg_create: group_size must be in 1..128");
   if (cfg.precision != TG_FP64 && cfg.precision != TG_MIXED)
     return fail(TG_EINVAL, "tg_create: unknown precision");
   if (!(cfg.G > 0.0) || !std::isfinite(cfg.G))
@@ -198,7 +198,7 @@ tg_status tg_set_sizes(tg_ctx *c, int32_t leaf_size, int32_t group_size) {
   if (leaf_size < 1 || leaf_size > kMaxLeaf)
     return fail(TG_EINVAL, "tg_set_sizes: leaf_size must be in 1..16");
   if (group_size < 1 || group_size > kMaxGroup)
-    return fail(TG_EINVAL, "tg_set_sizes: group_size must be in 1..64");
+    return fail(TG_EINVAL, "tg_set_sizes: group_size must be in 1..128");
   c->leaf_size = leaf_size;
   c->group_size = group_size;
   c->have_tree = c->have_moments = false;

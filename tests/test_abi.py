@@ -62,7 +62,7 @@ def test_create_rejects_bad_config_without_gpu(libtg):
     from paper_1507_01009_amd import binding as B
     cfg = B.tg_config()
     libtg.tg_default_config(ctypes.byref(cfg))
-    cfg.group_size = 65
+    cfg.group_size = 129
     h = ctypes.c_void_p()
     libtg.tg_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     assert libtg.tg_create(ctypes.byref(cfg), None, ctypes.byref(h)) == -1

@@ -60,7 +60,7 @@ def _tree_equal(t_or, g, groups_or=None):
 
 @pytest.mark.parametrize("name,nl,ng", [("plummer4096", 8, 64), ("plummer4096", 1, 1),
                                         ("plummer4096", 16, 48), ("hernquist131k", 8, 64),
-                                        ("clustered", 4, 16)])
+                                        ("clustered", 4, 16), ("hernquist32k", 8, 128)])
 def test_tree_and_groups_bit_exact(name, nl, ng):
     say("tree", name, nl, ng)
     pos, m, eps = _w(name)
@@ -136,7 +136,8 @@ def _check_lists(pos, m, eps, theta, nl, ng, active=None):
 @pytest.mark.parametrize("name,theta,nl,ng,every", [
     ("plummer4096", 0.5, 8, 64, 1), ("plummer4096", 0.3, 8, 32, 3),
     ("plummer4096", 0.0, 8, 64, 7), ("hernquist32k", 0.5, 8, 64, 1),
-    ("clustered", 0.55, 4, 16, 2)])
+    ("clustered", 0.55, 4, 16, 2), ("hernquist32k", 0.5, 8, 128, 1),
+    ("hernquist32k", 0.5, 12, 100, 3)])
 def test_interaction_lists_match(name, theta, nl, ng, every):
     say("lists", name, theta)
     pos, m, eps = _w(name)
@@ -147,7 +148,9 @@ def test_interaction_lists_match(name, theta, nl, ng, every):
 @pytest.mark.parametrize("name,nl,ng,every", [("plummer4096", 8, 64, 1),
                                               ("plummer4096", 4, 20, 5),
                                               ("hernquist131k", 8, 64, 1),
-                                              ("clustered", 4, 16, 1)])
+                                              ("clustered", 4, 16, 1),
+                                              ("hernquist32k", 8, 128, 1),
+                                              ("hernquist32k", 16, 97, 2)])
 def test_forces_fp64(name, nl, ng, every):
     say("fp64", name)
     pos, m, eps = _w(name)
@@ -166,12 +169,13 @@ def test_forces_fp64(name, nl, ng, every):
     assert (c["n_p2p"], c["n_p2m"], c["n_targets"]) == (ev.n_p2p, ev.n_p2m, ev.n_targets)
 
 
-@pytest.mark.parametrize("name", ["plummer4096", "hernquist131k"])
-def test_forces_mixed_precision(name):
-    say("mixed", name)
+@pytest.mark.parametrize("name,ng", [("plummer4096", 64), ("hernquist131k", 64),
+                                     ("hernquist131k", 128)])
+def test_forces_mixed_precision(name, ng):
+    say("mixed", name, ng)
     pos, m, eps = _w(name)
-    g = gpu_run(pos, m, eps, 0.5, 8, 64, precision=1)
-    ev = oracle.tree_forces(pos, m, eps, 0.5, 8, 64)
+    g = gpu_run(pos, m, eps, 0.5, 8, ng, precision=1)
+    ev = oracle.tree_forces(pos, m, eps, 0.5, 8, ng)
     e = rel_err(g["acc"], ev.acc)
     say("  mixed p50 %.3g p99 %.3g max %.3g" % tuple(np.percentile(e, [50, 99, 100])))
     assert np.median(e) <= 1e-5 and np.percentile(e, 99) <= 1e-4
