@@ -21,9 +21,9 @@
 // estimate plus one third-order correction (Householder).  MIXED: the walk
 // decisions stay double; targets and sources are taken relative to the
 // group's box centre c_g in double and rounded to float, the interaction
-// arithmetic is float with the hardware rsqrt, each tile's partial sums are
-// folded into a (hi, lo) float pair with an error-free TwoSum; the result is
-// hi + lo in double.
+// arithmetic is float with the hardware rsqrt, and each tile's float
+// partial sums (at most 127 sources per lane slice) are added into per-target
+// double accumulators (one conversion and one FP64 add, both full rate).
 //
 // Flops per interaction as written in p2p_term / p2m_term (FMA = 2; the
 // rsqrt and, in FP64, its refinement are not counted):
@@ -103,27 +103,25 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t &tot) {
 
 // Opening-angle test, the same operations in the same order as the plain
 // definition: d^2 = sum_k max(max(lo_k - c_k, c_k - hi_k), 0)^2, accept iff
-// side^2 < theta^2 * d^2.
+// side^2 < theta^2 * d^2.  fmax (one v_max_f64) equals the compare-and-
+// select of the definition for the finite inputs the build guarantees.
 __device__ __forceinline__ bool mac_accept(const double lo[3], const double hi[3],
                                            double4 c, double th2) {
 #pragma clang fp contract(off)
   double d2 = 0.0;
   {
     double a = __dsub_rn(lo[0], c.x), b = __dsub_rn(c.x, hi[0]);
-    double m = a > b ? a : b;
-    if (m < 0.0) m = 0.0;
+    const double m = fmax(fmax(a, b), 0.0);
     d2 = __dadd_rn(d2, __dmul_rn(m, m));
   }
   {
     double a = __dsub_rn(lo[1], c.y), b = __dsub_rn(c.y, hi[1]);
-    double m = a > b ? a : b;
-    if (m < 0.0) m = 0.0;
+    const double m = fmax(fmax(a, b), 0.0);
     d2 = __dadd_rn(d2, __dmul_rn(m, m));
   }
   {
     double a = __dsub_rn(lo[2], c.z), b = __dsub_rn(c.z, hi[2]);
-    double m = a > b ? a : b;
-    if (m < 0.0) m = 0.0;
+    const double m = fmax(fmax(a, b), 0.0);
     d2 = __dadd_rn(d2, __dmul_rn(m, m));
   }
   return c.w < __dmul_rn(th2, d2);
@@ -139,13 +137,6 @@ __device__ __forceinline__ double rsqrt_dp(double x) {
   return fma(y * e, p, y);
 }
 
-__device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float x) {
-  float t = hi + x;
-  float bp = t - hi;
-  float err = (hi - (t - bp)) + (x - bp);
-  hi = t;
-  lo += err;
-}
 
 // ---------------------------------------------------------------- terms
 template <class R> struct Vec4;
@@ -246,19 +237,12 @@ struct ForceSink {
   double cgx, cgy, cgz;              // coordinate origin of the group (0 in FP64)
   R e2;
   R tx[kMaxT], ty[kMaxT], tz[kMaxT];
-  // FP64: plain sums in h*; mixed: compensated (h*, l*) float pairs
-  R hax[kMaxT], hay[kMaxT], haz[kMaxT], hph[kMaxT];
-  R lax[kMaxT], lay[kMaxT], laz[kMaxT], lph[kMaxT];
+  // per-target totals in FP64 (mixed: each tile's FP32 partial sums are
+  // added here, so rounding accumulates only within a tile)
+  double hax[kMaxT], hay[kMaxT], haz[kMaxT], hph[kMaxT];
 
   __device__ void add(int k, R ax, R ay, R az, R ph) {
-    if constexpr (kMixed) {
-      two_sum_acc(hax[k], lax[k], ax);
-      two_sum_acc(hay[k], lay[k], ay);
-      two_sum_acc(haz[k], laz[k], az);
-      two_sum_acc(hph[k], lph[k], ph);
-    } else {
-      hax[k] += ax; hay[k] += ay; haz[k] += az; hph[k] += ph;
-    }
+    hax[k] += (double)ax; hay[k] += (double)ay; haz[k] += (double)az; hph[k] += (double)ph;
   }
 
   template <int kT>
@@ -612,8 +596,7 @@ void k_walk_forces(WalkArgs A) {
       const int i = j + k * lt;
       const double4 p = A.spart[s_tgt[i < nt ? i : j]];
       S.tx[k] = (R)(p.x - S.cgx); S.ty[k] = (R)(p.y - S.cgy); S.tz[k] = (R)(p.z - S.cgz);
-      S.hax[k] = S.hay[k] = S.haz[k] = S.hph[k] = R(0);
-      S.lax[k] = S.lay[k] = S.laz[k] = S.lph[k] = R(0);
+      S.hax[k] = S.hay[k] = S.haz[k] = S.hph[k] = 0.0;
     }
     const bool ok = traverse(A, S, A.root_of[gr.w], lo, hi);
     // per-lane totals -> LDS, [k][lane][4]
@@ -621,14 +604,7 @@ void k_walk_forces(WalkArgs A) {
 #pragma unroll
     for (int k = 0; k < kMaxT; ++k) {
       double *o = red + 4 * (64 * k + (int)lane);
-      if constexpr (kMixed) {
-        o[0] = (double)S.hax[k] + (double)S.lax[k];
-        o[1] = (double)S.hay[k] + (double)S.lay[k];
-        o[2] = (double)S.haz[k] + (double)S.laz[k];
-        o[3] = (double)S.hph[k] + (double)S.lph[k];
-      } else {
-        o[0] = S.hax[k]; o[1] = S.hay[k]; o[2] = S.haz[k]; o[3] = S.hph[k];
-      }
+      o[0] = S.hax[k]; o[1] = S.hay[k]; o[2] = S.haz[k]; o[3] = S.hph[k];
     }
     __syncthreads();
     for (int i = (int)lane; i < nt; i += 64) {
