@@ -45,6 +45,13 @@ def _w(name):
         base = rng.normal(size=(300, 3))
         p = np.concatenate([base, np.repeat(base[:5], 40, axis=0), rng.normal(size=(900, 3)) * 1e-7])
         return p, np.full(p.shape[0], 1.0 / p.shape[0]), 1e-3
+    if name == "coincident":
+        # 1500 particles on one point (a level-21 leaf of 1500, walked with
+        # the unpacked prefix sums) inside a Plummer sphere
+        p, _, _ = ics.plummer(3000, 17)
+        dup = np.repeat(np.array([[0.01, -0.02, 0.03]]), 1500, axis=0)
+        p = np.concatenate([p, dup])
+        return p, np.full(p.shape[0], 1.0 / p.shape[0]), 0.01
     raise KeyError(name)
 
 
@@ -60,7 +67,8 @@ def _tree_equal(t_or, g, groups_or=None):
 
 @pytest.mark.parametrize("name,nl,ng", [("plummer4096", 8, 64), ("plummer4096", 1, 1),
                                         ("plummer4096", 16, 48), ("hernquist131k", 8, 64),
-                                        ("clustered", 4, 16), ("hernquist32k", 8, 128)])
+                                        ("clustered", 4, 16), ("hernquist32k", 8, 128),
+                                        ("coincident", 8, 64)])
 def test_tree_and_groups_bit_exact(name, nl, ng):
     say("tree", name, nl, ng)
     pos, m, eps = _w(name)
@@ -137,7 +145,7 @@ def _check_lists(pos, m, eps, theta, nl, ng, active=None):
     ("plummer4096", 0.5, 8, 64, 1), ("plummer4096", 0.3, 8, 32, 3),
     ("plummer4096", 0.0, 8, 64, 7), ("hernquist32k", 0.5, 8, 64, 1),
     ("clustered", 0.55, 4, 16, 2), ("hernquist32k", 0.5, 8, 128, 1),
-    ("hernquist32k", 0.5, 12, 100, 3)])
+    ("hernquist32k", 0.5, 12, 100, 3), ("coincident", 0.5, 8, 64, 1)])
 def test_interaction_lists_match(name, theta, nl, ng, every):
     say("lists", name, theta)
     pos, m, eps = _w(name)
@@ -150,7 +158,9 @@ def test_interaction_lists_match(name, theta, nl, ng, every):
                                               ("hernquist131k", 8, 64, 1),
                                               ("clustered", 4, 16, 1),
                                               ("hernquist32k", 8, 128, 1),
-                                              ("hernquist32k", 16, 97, 2)])
+                                              ("hernquist32k", 16, 97, 2),
+                                              ("coincident", 8, 64, 1),
+                                              ("coincident", 4, 128, 3)])
 def test_forces_fp64(name, nl, ng, every):
     say("fp64", name)
     pos, m, eps = _w(name)
