@@ -27,10 +27,11 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Per-tile min/max of each coordinate; flags non-finite positions.
-__global__ __launch_bounds__(256) void k_cube_part(const double *__restrict__ pos,
+__global__ __launch_bounds__(256) void k_cube_part(const int32_t *__restrict__ gate, const double *__restrict__ pos,
                                                    const Tile *__restrict__ tiles,
                                                    double *__restrict__ part,
                                                    uint32_t *err) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ double sh[4][6];
   const Tile t = tiles[blockIdx.x];
   double lo[3] = {INFINITY, INFINITY, INFINITY};
@@ -65,9 +66,10 @@ __global__ __launch_bounds__(256) void k_cube_part(const double *__restrict__ po
 
 // One block per system: lo = coordinate minimum, L = largest extent (1 if
 // every particle coincides or the system is empty).
-__global__ __launch_bounds__(256) void k_cube_final(const double *__restrict__ part,
+__global__ __launch_bounds__(256) void k_cube_final(const int32_t *__restrict__ gate, const double *__restrict__ part,
                                                     const uint32_t *__restrict__ sys_tile0,
                                                     double *__restrict__ cube) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ double sh[4][6];
   const int s = blockIdx.x;
   const uint32_t a = sys_tile0[s], b = sys_tile0[s + 1];
@@ -120,12 +122,13 @@ __device__ __forceinline__ uint64_t quantise(double x, double lo, double sigma) 
 }
 
 // Keys (x bit above y above z at every level) and the identity values.
-__global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos,
+__global__ __launch_bounds__(256) void k_keys(const int32_t *__restrict__ gate, const double *__restrict__ pos,
                                               const Tile *__restrict__ tiles,
                                               const uint32_t *__restrict__ sys_tile0,
                                               int S, const double *__restrict__ cube,
                                               uint64_t *__restrict__ key,
                                               uint32_t *__restrict__ val) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   const Tile t = tiles[blockIdx.x];
   // system of this tile: last s with sys_tile0[s] <= tile
   int lo_s = 0, hi_s = S - 1;
@@ -166,10 +169,11 @@ __device__ __forceinline__ int tile_system(const uint32_t *sys_tile0, int S, uin
 }
 
 // cnt[s][p][d]: keys of system s with digit d in pass p (cleared beforehand)
-__global__ __launch_bounds__(256) void k_sort_count(const uint64_t *__restrict__ key,
+__global__ __launch_bounds__(256) void k_sort_count(const int32_t *__restrict__ gate, const uint64_t *__restrict__ key,
                                                     const Tile *__restrict__ tiles,
                                                     const uint32_t *__restrict__ sys_tile0,
                                                     int S, uint32_t *__restrict__ cnt) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint32_t c[8][256];
   const Tile t = tiles[blockIdx.x];
   const int s = tile_system(sys_tile0, S, blockIdx.x);
@@ -189,12 +193,13 @@ __global__ __launch_bounds__(256) void k_sort_count(const uint64_t *__restrict__
   }
 }
 
-__global__ __launch_bounds__(256) void k_sort_pass(
+__global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ gate, 
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
     const Tile *__restrict__ tiles, const uint32_t *__restrict__ sys_tile0, int S,
     const int64_t *__restrict__ sysoff, int pass, const uint32_t *__restrict__ cnt,
     uint32_t *status, uint32_t *ticket, uint32_t *err) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint64_t sk[kSortTile];
   __shared__ uint32_t sv[kSortTile];
   __shared__ uint32_t wcnt[4][256];
@@ -326,10 +331,11 @@ __global__ __launch_bounds__(256) void k_sort_pass(
 
 // Sorted positions {x, y, z, 0} (mass filled by the moments pass) and the
 // inverse permutation.
-__global__ void k_gather(const double *__restrict__ pos,
+__global__ void k_gather(const int32_t *__restrict__ gate, const double *__restrict__ pos,
                          const uint32_t *__restrict__ perm, int64_t n,
                          double4 *__restrict__ spart,
                          uint32_t *__restrict__ rank) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
     uint32_t o = perm[r];
@@ -343,12 +349,12 @@ hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
   Buffers &b = c->b;
   const int nt = (int)c->n_tiles;
   if (nt > 0)
-    hipLaunchKernelGGL(k_cube_part, dim3(nt), dim3(256), 0, c->stream, pos,
+    hipLaunchKernelGGL(k_cube_part, dim3(nt), dim3(256), 0, c->stream, c->gate, pos,
                        b.tiles, b.cube_part, b.err);
-  hipLaunchKernelGGL(k_cube_final, dim3(c->S), dim3(256), 0, c->stream,
+  hipLaunchKernelGGL(k_cube_final, dim3(c->S), dim3(256), 0, c->stream, c->gate,
                      b.cube_part, b.sys_tile0, b.cube);
   if (nt > 0)
-    hipLaunchKernelGGL(k_keys, dim3(nt), dim3(256), 0, c->stream, pos, b.tiles,
+    hipLaunchKernelGGL(k_keys, dim3(nt), dim3(256), 0, c->stream, c->gate, pos, b.tiles,
                        b.sys_tile0, c->S, b.cube, b.key[0], b.val[0]);
   return hipGetLastError();
 }
@@ -361,13 +367,13 @@ hipError_t launch_sort(tg_ctx *c) {
   uint32_t *tickets = b.hist, *cnt = b.hist + kSortStatusBase;
   uint32_t *status = cnt + (size_t)c->S * 8 * 256;
   hipError_t e = fill_u32(b.hist, 0u, kSortStatusBase + (int64_t)8 * 256 * (c->S + nt),
-                          c->stream);
+                          c->stream, c->gate);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sort_count, dim3(nt), dim3(256), 0, c->stream, b.key[0], b.tiles,
+  hipLaunchKernelGGL(k_sort_count, dim3(nt), dim3(256), 0, c->stream, c->gate, b.key[0], b.tiles,
                      b.sys_tile0, c->S, cnt);
   for (int pass = 0; pass < 8; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
-    hipLaunchKernelGGL(k_sort_pass, dim3(nt), dim3(256), 0, c->stream, b.key[src],
+    hipLaunchKernelGGL(k_sort_pass, dim3(nt), dim3(256), 0, c->stream, c->gate, b.key[src],
                        b.val[src], b.key[dst], b.val[dst], b.tiles, b.sys_tile0, c->S,
                        b.sysoff, pass, cnt, status + (size_t)pass * 256 * nt,
                        tickets + pass, b.err);
@@ -378,7 +384,7 @@ hipError_t launch_sort(tg_ctx *c) {
 hipError_t launch_gather(tg_ctx *c, const double *pos) {
   if (c->n == 0) return hipSuccess;
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, pos,
+  hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, c->gate, pos,
                      c->b.val[0], c->n, c->b.spart, c->b.rank);
   return hipGetLastError();
 }

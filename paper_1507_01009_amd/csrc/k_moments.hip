@@ -14,9 +14,10 @@
 
 namespace tg {
 
-__global__ void k_mass_gather(const double *__restrict__ mass,
+__global__ void k_mass_gather(const int32_t *__restrict__ gate, const double *__restrict__ mass,
                               const uint32_t *__restrict__ perm, int64_t n,
                               double4 *__restrict__ spart, uint32_t *err) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   bool bad = false;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
@@ -40,13 +41,14 @@ __device__ __forceinline__ void store_moments(uint32_t v, int l, const double *c
 }
 
 // Every leaf of the tree (nodes without children), any level.
-__global__ __launch_bounds__(256) void k_moments_leaves(
+__global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restrict__ gate, 
     const TreeCounters *ctr, const double *__restrict__ cube,
     const uint8_t *__restrict__ level, const uint8_t *__restrict__ nchild,
     const uint32_t *__restrict__ first, const uint32_t *__restrict__ count,
     const uint32_t *__restrict__ nsys, const double4 *__restrict__ spart,
     double4 *__restrict__ com, double *__restrict__ mom) {
 #pragma clang fp contract(off)
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t nn = ctr->n_nodes;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
        v += gridDim.x * blockDim.x) {
@@ -73,11 +75,12 @@ __global__ __launch_bounds__(256) void k_moments_leaves(
 }
 
 // Internal nodes of level l from their children (level l + 1, done).
-__global__ __launch_bounds__(256) void k_moments_level(
+__global__ __launch_bounds__(256) void k_moments_level(const int32_t *__restrict__ gate, 
     int l, const TreeCounters *ctr, const double *__restrict__ cube,
     const uint8_t *__restrict__ nchild, const uint32_t *__restrict__ child,
     const uint32_t *__restrict__ nsys, double4 *__restrict__ com, double *__restrict__ mom) {
 #pragma clang fp contract(off)
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t a = ctr->lvl[l], e = ctr->lvl[l + 1];
   for (uint32_t v = a + blockIdx.x * blockDim.x + threadIdx.x; v < e;
        v += gridDim.x * blockDim.x) {
@@ -112,13 +115,13 @@ hipError_t launch_moments(tg_ctx *c, const double *mass) {
   Buffers &b = c->b;
   if (c->n == 0) return hipSuccess;
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_mass_gather, dim3(g), dim3(256), 0, c->stream, mass,
+  hipLaunchKernelGGL(k_mass_gather, dim3(g), dim3(256), 0, c->stream, c->gate, mass,
                      b.val[0], c->n, b.spart, b.err);
-  hipLaunchKernelGGL(k_moments_leaves, dim3(1024), dim3(256), 0, c->stream, b.ctr,
+  hipLaunchKernelGGL(k_moments_leaves, dim3(1024), dim3(256), 0, c->stream, c->gate, b.ctr,
                      b.cube, b.level, b.nchild, b.first, b.count, b.nsys, b.spart, b.com,
                      b.mom);
   for (int l = kMaxLevel - 1; l >= 0; --l)     // level 21 holds only leaves
-    hipLaunchKernelGGL(k_moments_level, dim3(256), dim3(256), 0, c->stream, l, b.ctr,
+    hipLaunchKernelGGL(k_moments_level, dim3(256), dim3(256), 0, c->stream, c->gate, l, b.ctr,
                        b.cube, b.nchild, b.child, b.nsys, b.com, b.mom);
   return hipGetLastError();
 }

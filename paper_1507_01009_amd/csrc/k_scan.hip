@@ -12,10 +12,11 @@ __device__ __forceinline__ void chunk_of(uint32_t n, uint32_t &a, uint32_t &b) {
   b = min(n, a + chunk);
 }
 
-__global__ __launch_bounds__(256) void k_scan_part(const uint32_t *in,
+__global__ __launch_bounds__(256) void k_scan_part(const int32_t *__restrict__ gate, const uint32_t *in,
                                                    uint32_t n_host,
                                                    const uint32_t *n_dev,
                                                    uint32_t *part) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint32_t sh[4];
   uint32_t n = n_dev ? *n_dev : n_host;
   uint32_t a, b;
@@ -27,8 +28,9 @@ __global__ __launch_bounds__(256) void k_scan_part(const uint32_t *in,
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_top(uint32_t *part, int nb,
+__global__ __launch_bounds__(256) void k_scan_top(const int32_t *__restrict__ gate, uint32_t *part, int nb,
                                                   uint32_t *total) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint32_t sh[4];
   uint32_t v = (int)threadIdx.x < nb ? part[threadIdx.x] : 0u;
   uint32_t tot;
@@ -40,11 +42,12 @@ __global__ __launch_bounds__(256) void k_scan_top(uint32_t *part, int nb,
   }
 }
 
-__global__ __launch_bounds__(256) void k_scan_final(const uint32_t *in,
+__global__ __launch_bounds__(256) void k_scan_final(const int32_t *__restrict__ gate, const uint32_t *in,
                                                     uint32_t *out,
                                                     uint32_t n_host,
                                                     const uint32_t *n_dev,
                                                     const uint32_t *part) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint32_t sh[4];
   uint32_t n = n_dev ? *n_dev : n_host;
   uint32_t a, b;
@@ -62,23 +65,25 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t *in,
 
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, uint32_t n_host,
                     const uint32_t *n_dev, uint32_t *total_dev, uint32_t *part,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_part, dim3(kScanBlocks), dim3(256), 0, s, in,
+                    hipStream_t s, const int32_t *gate) {
+  hipLaunchKernelGGL(k_scan_part, dim3(kScanBlocks), dim3(256), 0, s, gate, in,
                      n_host, n_dev, part);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, part, kScanBlocks,
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, gate, part, kScanBlocks,
                      total_dev);
-  hipLaunchKernelGGL(k_scan_final, dim3(kScanBlocks), dim3(256), 0, s, in,
+  hipLaunchKernelGGL(k_scan_final, dim3(kScanBlocks), dim3(256), 0, s, gate, in,
                      out, n_host, n_dev, part);
   return hipGetLastError();
 }
 
-__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+__global__ void k_fill_u32(const int32_t *__restrict__ gate, uint32_t *p, uint32_t v, int64_t n) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
 
-__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n) {
+__global__ void k_fill_u8(const int32_t *__restrict__ gate, uint8_t *p, uint8_t v, int64_t n) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -91,16 +96,16 @@ static inline int grid_for(int64_t n, int threads) {
   return (int)g;
 }
 
-hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s, const int32_t *gate) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v,
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, gate, p, v,
                      n);
   return hipGetLastError();
 }
 
-hipError_t fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
+hipError_t fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s, const int32_t *gate) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v,
+  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256)), dim3(256), 0, s, gate, p, v,
                      n);
   return hipGetLastError();
 }

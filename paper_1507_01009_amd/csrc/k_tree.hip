@@ -48,9 +48,10 @@ __device__ void load_sysoff(int64_t *so, const int64_t *sysoff, int S) {
 
 // d for [0, n + 64): the common leading digits with the predecessor, 0 at
 // every system start and from n on.
-__global__ __launch_bounds__(256) void k_lcp(const uint64_t *__restrict__ skey, int64_t n,
+__global__ __launch_bounds__(256) void k_lcp(const int32_t *__restrict__ gate, const uint64_t *__restrict__ skey, int64_t n,
                                              const int64_t *__restrict__ sysoff, int S,
                                              uint8_t *__restrict__ d) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ int64_t so[kMaxSys + 1];
   load_sysoff(so, sysoff, S);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n + 64;
@@ -68,13 +69,14 @@ __global__ __launch_bounds__(256) void k_lcp(const uint64_t *__restrict__ skey, 
 // at i (0xffff: none); bits[l][4 b + w] = ballot of "a level-l node starts
 // here" of wave w; cnt[l][b] = nodes of level l in the tile; fst[l][b] =
 // first run start of level l in the tile (first i with d[i] < l).
-__global__ __launch_bounds__(kFT) void k_flat_flags(int64_t n, int nleaf, int S,
+__global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ gate, int64_t n, int nleaf, int S,
                                                     const int64_t *__restrict__ sysoff,
                                                     const uint8_t *__restrict__ d,
                                                     uint16_t *__restrict__ lt,
                                                     uint64_t *__restrict__ bits, int64_t wl,
                                                     uint32_t *__restrict__ cnt,
                                                     uint32_t *__restrict__ fst, int64_t tl) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint8_t sd[kHalo + kFT + 2 * kHalo];
   __shared__ int64_t so[kMaxSys + 1];
   __shared__ uint32_t wc[kFT / 64][kLevels];
@@ -148,10 +150,11 @@ __global__ __launch_bounds__(kFT) void k_flat_flags(int64_t n, int nleaf, int S,
 // One block per level: exclusive prefix of cnt[l][0..T) in place with
 // cnt[l][T] = total (also tot[l]); fst[l][b] <- first run start of level l
 // after tile b (suffix minimum over later tiles; n past the last).
-__global__ __launch_bounds__(1024) void k_flat_scan(int64_t T, int64_t n,
+__global__ __launch_bounds__(1024) void k_flat_scan(const int32_t *__restrict__ gate, int64_t T, int64_t n,
                                                     uint32_t *__restrict__ cnt,
                                                     uint32_t *__restrict__ fst, int64_t tl,
                                                     uint32_t *__restrict__ tot) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint32_t sh[16];
   const int l = blockIdx.x;
   uint32_t *c = cnt + l * tl, *f = fst + l * tl;
@@ -208,7 +211,7 @@ __device__ __forceinline__ uint32_t rank_of(const uint64_t *__restrict__ bl,
 }
 
 // Nodes of tile b written at their canonical ids.
-__global__ __launch_bounds__(kFT) void k_flat_emit(
+__global__ __launch_bounds__(kFT) void k_flat_emit(const int32_t *__restrict__ gate, 
     int64_t n, int S, const int64_t *__restrict__ sysoff, const uint8_t *__restrict__ d,
     const uint16_t *__restrict__ lt, const uint64_t *__restrict__ bits, int64_t wl,
     const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ fst, int64_t tl,
@@ -217,6 +220,7 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(
     uint8_t *__restrict__ nchild, uint32_t *__restrict__ first,
     uint32_t *__restrict__ count, uint32_t *__restrict__ child,
     uint32_t *__restrict__ parent, uint32_t *__restrict__ nsys, uint4 *__restrict__ ninfo) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint8_t sd[kFT];
   __shared__ uint8_t mn8[kFT / 8], mn64[kFT / 64];
   __shared__ int64_t so[kMaxSys + 1];
@@ -313,15 +317,15 @@ hipError_t launch_tree_build(tg_ctx *c) {
   const int64_t n = c->n, T = (n + kFT - 1) / kFT;
   const int64_t wl = 4 * (c->flat_tiles + 1), tl = c->flat_tiles + 1;
   hipLaunchKernelGGL(k_lcp, dim3((int)std::min<int64_t>((n + 64 + 255) / 256, 4096)),
-                     dim3(256), 0, c->stream, b.key[0], n, b.sysoff, c->S, b.lcp);
+                     dim3(256), 0, c->stream, c->gate, b.key[0], n, b.sysoff, c->S, b.lcp);
   if (T > 0)
-    hipLaunchKernelGGL(k_flat_flags, dim3((unsigned)T), dim3(kFT), 0, c->stream, n,
+    hipLaunchKernelGGL(k_flat_flags, dim3((unsigned)T), dim3(kFT), 0, c->stream, c->gate, n,
                        c->leaf_size, c->S, b.sysoff, b.lcp, b.fl_lt, b.fl_bits, wl,
                        b.fl_cnt, b.fl_fst, tl);
-  hipLaunchKernelGGL(k_flat_scan, dim3(kLevels), dim3(1024), 0, c->stream, T, n,
+  hipLaunchKernelGGL(k_flat_scan, dim3(kLevels), dim3(1024), 0, c->stream, c->gate, T, n,
                      b.fl_cnt, b.fl_fst, tl, b.fl_tot);
   hipLaunchKernelGGL(k_flat_emit, dim3((unsigned)std::max<int64_t>(T, 1)), dim3(kFT), 0,
-                     c->stream, n, c->S, b.sysoff, b.lcp, b.fl_lt, b.fl_bits, wl,
+                     c->stream, c->gate, n, c->S, b.sysoff, b.lcp, b.fl_lt, b.fl_bits, wl,
                      b.fl_cnt, b.fl_fst, tl, b.fl_tot, c->max_nodes, b.ctr, b.err,
                      b.root_of, b.level, b.nchild, b.first, b.count, b.child, b.parent,
                      b.nsys, b.ninfo);
@@ -340,12 +344,13 @@ __device__ __forceinline__ bool is_group(uint32_t v, uint32_t ng,
   return count[v] <= ng && (p == kNone || count[p] > ng);
 }
 
-__global__ void k_group_flags(const TreeCounters *ctr, uint32_t ng,
+__global__ void k_group_flags(const int32_t *__restrict__ gate, const TreeCounters *ctr, uint32_t ng,
                               const uint8_t *__restrict__ nchild,
                               const uint32_t *__restrict__ first,
                               const uint32_t *__restrict__ count,
                               const uint32_t *__restrict__ parent,
                               uint32_t *__restrict__ gflag) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t nn = ctr->n_nodes;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
        v += gridDim.x * blockDim.x) {
@@ -357,7 +362,7 @@ __global__ void k_group_flags(const TreeCounters *ctr, uint32_t ng,
   }
 }
 
-__global__ void k_group_write(const TreeCounters *ctr, uint32_t ng,
+__global__ void k_group_write(const int32_t *__restrict__ gate, const TreeCounters *ctr, uint32_t ng,
                               const uint8_t *__restrict__ nchild,
                               const uint32_t *__restrict__ first,
                               const uint32_t *__restrict__ count,
@@ -365,6 +370,7 @@ __global__ void k_group_write(const TreeCounters *ctr, uint32_t ng,
                               const uint32_t *__restrict__ nsys,
                               const uint32_t *__restrict__ gidx,
                               uint4 *__restrict__ groups) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t nn = ctr->n_nodes;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
        v += gridDim.x * blockDim.x) {
@@ -383,16 +389,16 @@ hipError_t launch_groups(tg_ctx *c) {
   if (c->n == 0) {
     return fill_u32(&b.ctr->n_groups, 0u, 1, c->stream);
   }
-  hipError_t e = fill_u32(b.gflag, 0u, c->n + 1, c->stream);
+  hipError_t e = fill_u32(b.gflag, 0u, c->n + 1, c->stream, c->gate);
   if (e != hipSuccess) return e;
   const int g = 1024;
-  hipLaunchKernelGGL(k_group_flags, dim3(g), dim3(256), 0, c->stream, b.ctr,
+  hipLaunchKernelGGL(k_group_flags, dim3(g), dim3(256), 0, c->stream, c->gate, b.ctr,
                      (uint32_t)c->group_size, b.nchild, b.first, b.count,
                      b.parent, b.gflag);
   e = scan_u32(b.gflag, b.gflag, (uint32_t)c->n, nullptr, &b.ctr->n_groups,
-               b.scan_part, c->stream);
+               b.scan_part, c->stream, c->gate);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_group_write, dim3(g), dim3(256), 0, c->stream, b.ctr,
+  hipLaunchKernelGGL(k_group_write, dim3(g), dim3(256), 0, c->stream, c->gate, b.ctr,
                      (uint32_t)c->group_size, b.nchild, b.first, b.count,
                      b.parent, b.nsys, b.gflag, b.groups);
   return hipGetLastError();

@@ -533,7 +533,8 @@ struct GroupQueue {
 // ------------------------------------------------------------ force kernel
 template <bool kMixed>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMixed ? TG_WALK_WAVES_MIXED : TG_WALK_WAVES_FP64)))
-void k_walk_forces(WalkArgs A) {
+void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint32_t s_tgt[kMaxGroup];
   __shared__ uint32_t s_m[kMCap];
   __shared__ uint32_t s_q[kQCap];
@@ -694,10 +695,11 @@ __global__ __launch_bounds__(64) void k_walk_lists(WalkArgs A) {
 }
 
 // ------------------------------------------------------ active groups
-__global__ void k_mark_active(const int32_t *__restrict__ idx,
+__global__ void k_mark_active(const int32_t *__restrict__ gate, const int32_t *__restrict__ idx,
                               const int32_t *__restrict__ n_act, int64_t n,
                               const uint32_t *__restrict__ rank,
                               uint8_t *__restrict__ sact) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   const int64_t m = idx ? (int64_t)min((int64_t)n_act[0], n) : n;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
        k += (int64_t)gridDim.x * blockDim.x) {
@@ -725,12 +727,13 @@ __device__ __forceinline__ double qmax(double v) {
 // Sixteen lanes per group (a group holds at most kMaxGroup particles):
 // flag groups with an active particle and store the box of their active
 // particles.
-__global__ __launch_bounds__(256) void k_group_active(const TreeCounters *ctr,
+__global__ __launch_bounds__(256) void k_group_active(const int32_t *__restrict__ gate, const TreeCounters *ctr,
                                                       const uint4 *__restrict__ groups,
                                                       const uint8_t *__restrict__ sact,
                                                       const double4 *__restrict__ spart,
                                                       uint32_t *__restrict__ aflag,
                                                       double *__restrict__ abox) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t ng = ctr->n_groups;
   const unsigned q = threadIdx.x & 15u;
   const uint32_t qpb = blockDim.x >> 4;
@@ -764,10 +767,11 @@ __global__ __launch_bounds__(256) void k_group_active(const TreeCounters *ctr,
   }
 }
 
-__global__ void k_compact_groups(const TreeCounters *ctr,
+__global__ void k_compact_groups(const int32_t *__restrict__ gate, const TreeCounters *ctr,
                                  const uint32_t *__restrict__ aflag,
                                  const uint32_t *__restrict__ aidx,
                                  uint32_t *__restrict__ alist) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t ng = ctr->n_groups;
   for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ng;
        g += gridDim.x * blockDim.x)
@@ -802,18 +806,18 @@ hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
                                 const int32_t *n_act) {
   Buffers &b = c->b;
   if (c->n == 0) return fill_u32(&b.ctr->n_active_groups, 0u, 1, c->stream);
-  hipError_t e = fill_u8(b.sact, 0, c->n, c->stream);
+  hipError_t e = fill_u8(b.sact, 0, c->n, c->stream, c->gate);
   if (e != hipSuccess) return e;
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_mark_active, dim3(g), dim3(256), 0, c->stream, idx,
+  hipLaunchKernelGGL(k_mark_active, dim3(g), dim3(256), 0, c->stream, c->gate, idx,
                      n_act, c->n, b.rank, b.sact);
-  hipLaunchKernelGGL(k_group_active, dim3(2048), dim3(256), 0, c->stream,
+  hipLaunchKernelGGL(k_group_active, dim3(2048), dim3(256), 0, c->stream, c->gate,
                      b.ctr, b.groups, b.sact, b.spart, b.aflag, b.abox);
   // the group-start scan buffer is free after the build: reuse it
   e = scan_u32(b.aflag, b.gflag, 0u, &b.ctr->n_groups, &b.ctr->n_active_groups,
-               b.scan_part, c->stream);
+               b.scan_part, c->stream, c->gate);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compact_groups, dim3(1024), dim3(256), 0, c->stream,
+  hipLaunchKernelGGL(k_compact_groups, dim3(1024), dim3(256), 0, c->stream, c->gate,
                      b.ctr, b.aflag, b.gflag, b.alist);
   return hipGetLastError();
 }
@@ -839,9 +843,10 @@ static WalkArgs make_args(tg_ctx *c, double theta) {
 // Walk records of every node: Q = 3S - T I, -T eps^2 and M, in the walk's
 // precision, formed once per evaluation instead of once per staged cell.
 template <class R>
-__global__ __launch_bounds__(256) void k_cell_records(const TreeCounters *ctr,
+__global__ __launch_bounds__(256) void k_cell_records(const int32_t *__restrict__ gate, const TreeCounters *ctr,
                                                       const double *__restrict__ mom,
                                                       double eps2, void *cell) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
   using R4 = typename Vec4<R>::T;
   R4 *out = reinterpret_cast<R4 *>(cell);
   const uint32_t nn = ctr->n_nodes;
@@ -870,10 +875,10 @@ hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
   A.acc = acc;
   A.pot = pot;
   if (c->cfg.precision == TG_MIXED)
-    hipLaunchKernelGGL(k_cell_records<float>, dim3(1024), dim3(256), 0, c->stream, c->b.ctr,
+    hipLaunchKernelGGL(k_cell_records<float>, dim3(1024), dim3(256), 0, c->stream, c->gate, c->b.ctr,
                        c->b.mom, A.eps2, (void *)c->b.cell);
   else
-    hipLaunchKernelGGL(k_cell_records<double>, dim3(1024), dim3(256), 0, c->stream, c->b.ctr,
+    hipLaunchKernelGGL(k_cell_records<double>, dim3(1024), dim3(256), 0, c->stream, c->gate, c->b.ctr,
                        c->b.mom, A.eps2, (void *)c->b.cell);
   hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, c->stream, c->b.ctr);
   if (before) {
@@ -882,10 +887,10 @@ hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
   }
   if (c->cfg.precision == TG_MIXED)
     hipLaunchKernelGGL(k_walk_forces<true>, dim3(walk_grid(c)), dim3(64), 0,
-                       c->stream, A);
+                       c->stream, c->gate, A);
   else
     hipLaunchKernelGGL(k_walk_forces<false>, dim3(walk_grid(c)), dim3(64), 0,
-                       c->stream, A);
+                       c->stream, c->gate, A);
   if (after) {
     hipError_t e = hipEventRecord(after, c->stream);
     if (e != hipSuccess) return e;

@@ -123,6 +123,9 @@ struct tg_ctx {
   int64_t max_nodes = 0;
   int64_t max_tiles = 0;
   int64_t flat_tiles = 0;          // 256-particle tiles of max_particles
+  // device count that gates the build, moments and walk kernels (they
+  // return at once when it is <= 0: no active particle); null = always run
+  const int32_t *gate = nullptr;
   int64_t n_tiles = 0;
   bool have_tree = false, have_moments = false;
   bool capturing = false;
@@ -164,9 +167,12 @@ tg_status hip_fail(hipError_t e, const char *what);
 // Writes the total to *total_dev (if non-null).  in may equal out.
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, uint32_t n_host,
                     const uint32_t *n_dev, uint32_t *total_dev,
-                    uint32_t *part, hipStream_t s);
-hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-hipError_t fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+                    uint32_t *part, hipStream_t s,
+                    const int32_t *gate = nullptr);
+hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s,
+                    const int32_t *gate = nullptr);
+hipError_t fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s,
+                   const int32_t *gate = nullptr);
 
 // k_keys.hip
 hipError_t launch_cube_keys(tg_ctx *c, const double *pos);

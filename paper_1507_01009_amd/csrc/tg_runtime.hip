@@ -308,6 +308,13 @@ tg_status tg_tree_forces(tg_ctx *c, double eps, double theta,
     return fail(TG_EINVAL, "tg_tree_forces: eps must be positive");
   if (c->n > 0 && !acc) return fail(TG_EINVAL, "tg_tree_forces: NULL acc");
   if (c->n == 0) return TG_OK;
+  // with an active list, every kernel of the evaluation returns at once when
+  // the device-side count is 0 (graph replays of block steps)
+  struct Gate {
+    tg_ctx *c; const int32_t *saved;
+    Gate(tg_ctx *c_, const int32_t *g) : c(c_), saved(c_->gate) { if (g) c->gate = g; }
+    ~Gate() { c->gate = saved; }
+  } gate(c, idx ? n_act : nullptr);
   TG_HIP(launch_active_groups(c, idx, n_act));
   hipEvent_t before = nullptr, after = nullptr;
   if (c->profiling && !c->capturing) {
@@ -775,8 +782,13 @@ tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
                     const int32_t *n_act) {
   tg_status st = check_system(y, "tg_forces");
   if (st != TG_OK) return st;
-  if ((st = tg_build_tree(c, y->pos, y->n, y->sys_off, y->n_sys)) != TG_OK) return st;
-  if ((st = tg_compute_moments(c, y->mass)) != TG_OK) return st;
+  // with an active list, the build, moments and walk are skipped on the
+  // device when it is empty (the SMBH sums below always run)
+  c->gate = idx ? n_act : nullptr;
+  st = tg_build_tree(c, y->pos, y->n, y->sys_off, y->n_sys);
+  if (st == TG_OK) st = tg_compute_moments(c, y->mass);
+  c->gate = nullptr;
+  if (st != TG_OK) return st;
   if ((st = tg_set_external(c, y->bh_pos, y->bh_mass, y->bh_eps, y->n_bh,
                             y->n_bh ? y->bh_seg : nullptr, y->n_sys)) != TG_OK)
     return st;

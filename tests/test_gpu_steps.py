@@ -259,3 +259,64 @@ def test_autotune_returns_a_listed_config():
     ev = oracle.tree_forces(w.pos, w.mass, w.eps, w.theta, best["leaf_size"],
                             best["group_size"])
     assert rel_err(acc.cpu().numpy(), ev.acc).max() <= 1e-12
+
+
+def test_empty_active_set_skips_stars_but_not_smbh():
+    say("empty active set")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    w = ics.hernquist_c2(n=16384)
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    ctx.forces(d.sys)
+    ctx.sync()
+    before = d.host()
+    d.bpos += 0.01                       # the SMBH moves; no star is active
+    idx = torch.zeros(w.n, dtype=torch.int32, device="cuda")
+    na = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.forces(d.sys, idx, na)
+    ctx.sync()
+    h = d.host()
+    assert np.array_equal(h["acc"], before["acc"]) and np.array_equal(h["pot"], before["pot"])
+    st = ostate(w)
+    st.bh_pos += 0.01
+    osteps.forces(st, np.zeros(0, np.int64))
+    sc = bh_scale(w.pos, w.mass, w.eps, st.bh_pos)
+    assert np.all(np.linalg.norm(h["bacc"] - st.bh_acc, axis=1) <= 1e-12 * sc)
+    # a full evaluation afterwards rebuilds everything
+    ctx.forces(d.sys)
+    ctx.sync()
+    osteps.forces(st)
+    assert rel_err(d.host()["acc"], st.acc).max() <= 1e-12
+
+
+def test_block_substeps_mostly_empty_match_oracle():
+    """The paper's dt_max = 2^-6: most substeps have no active star (only the
+    SMBH moves), so the device skips the tree for them."""
+    say("block substeps, paper dt_max")
+    from paper_1507_01009_amd import binding as B
+    w = ics.hernquist_c4(n=8192)
+    nlev, dt_max = 8, 2.0 ** -6
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    blk, keep = _blocks(ctx, w, nlev, dt_max)
+    ctx.forces(d.sys)
+    nsub = 66                          # stars on levels 0-2 first move at k = 32, 64
+    for _ in range(nsub):
+        ctx.step_block(d.sys, blk)
+    ctx.sync()
+    h = d.host()
+    st = ostate(w)
+    osteps.forces(st)
+    level = np.zeros(w.n, np.uint8)
+    t4e2 = np.full(w.n, 0.3 ** 4 * w.eps ** 2)
+    k = 0
+    counts = []
+    for _ in range(nsub):
+        k, act = osteps.block_substep(st, level, t4e2, k, dt_max, nlev)
+        counts.append(act.size)
+    assert min(counts) == 0 and max(counts) > 0
+    assert np.array_equal(keep[0].cpu().numpy(), level)
+    assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-12 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-11 * np.abs(st.vel).max()
+    assert np.max(np.abs(h["bpos"] - st.bh_pos)) <= 1e-14
