@@ -208,10 +208,11 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   __shared__ uint32_t glob_off[256];
   __shared__ uint32_t scan_sh[4];
   __shared__ uint32_t s_tile;
-  const unsigned tid = threadIdx.x, w = tid >> 6;
+  const unsigned tid = threadIdx.x, w = tid >> 6, lane = tid & 63u;
   const int shift = 8 * pass;
   if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-  running[tid] = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wcnt[q][tid] = 0;
   __syncthreads();
   const uint32_t tb = s_tile;
   const Tile t = tiles[tb];
@@ -219,23 +220,23 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   const uint32_t first_tile = sys_tile0[s];
   const uint32_t n_in = t.end - t.start;
 
+  // wave w holds the tile's keys [512 w, 512 (w + 1)) in index order
   uint64_t k[kSortItems];
   uint32_t v[kSortItems], rk[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t idx = r * 256u + tid;
+    const uint32_t idx = 512u * w + 64u * r + lane;
     k[r] = idx < n_in ? kin[t.start + idx] : 0ull;
     v[r] = idx < n_in ? vin[t.start + idx] : 0u;
   }
-  // stable ranks inside the tile: 256 keys per round in index order, peers
-  // of equal digit found with ballots
+  // stable ranks inside each wave: rounds of 64 keys in index order, peers
+  // of equal digit found with ballots, counts kept in the wave's own LDS row
+  // (one wave's LDS accesses execute in order: no barrier between rounds)
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t idx = r * 256u + tid;
+    const uint32_t idx = 512u * w + 64u * r + lane;
     const bool valid = idx < n_in;
     const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
-    wcnt[0][tid] = 0; wcnt[1][tid] = 0; wcnt[2][tid] = 0; wcnt[3][tid] = 0;
-    __syncthreads();
     unsigned long long peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
@@ -243,16 +244,25 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
       peers &= ((d >> bit) & 1u) ? bb : ~bb;
     }
     const uint32_t lr = lanes_below(peers);
-    if (valid && lr == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pre = running[d];
-      for (unsigned q = 0; q < w; ++q) pre += wcnt[q][d];
-      rk[r] = pre + lr;
-    }
-    __syncthreads();
-    running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-    __syncthreads();
+    const uint32_t base = valid ? wcnt[w][d] : 0u;
+    rk[r] = base + lr;
+    if (valid && lr == 0) wcnt[w][d] = base + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // digit tid: counts of the four waves -> their exclusive offsets in place
+  {
+    const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
+    wcnt[0][tid] = 0u;
+    wcnt[1][tid] = c0;
+    wcnt[2][tid] = c0 + c1;
+    wcnt[3][tid] = c0 + c1 + c2;
+    running[tid] = c0 + c1 + c2 + c3;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+    rk[r] += wcnt[w][d];
   }
   // publish this tile's count of digit tid, then look back for the prefix
   const uint32_t mine = running[tid];
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t idx = r * 256u + tid;
+    const uint32_t idx = 512u * w + 64u * r + lane;
     if (idx < n_in) {
       const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
       const uint32_t p = loc_off[d] + rk[r];
