@@ -220,12 +220,12 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   const uint32_t first_tile = sys_tile0[s];
   const uint32_t n_in = t.end - t.start;
 
-  // wave w holds the tile's keys [512 w, 512 (w + 1)) in index order
+  // wave w holds the tile's keys [64 kSortItems w, 64 kSortItems (w + 1)) in index order
   uint64_t k[kSortItems];
   uint32_t v[kSortItems], rk[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t idx = 512u * w + 64u * r + lane;
+    const uint32_t idx = 64u * kSortItems * w + 64u * r + lane;
     k[r] = idx < n_in ? kin[t.start + idx] : 0ull;
     v[r] = idx < n_in ? vin[t.start + idx] : 0u;
   }
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   // (one wave's LDS accesses execute in order: no barrier between rounds)
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t idx = 512u * w + 64u * r + lane;
+    const uint32_t idx = 64u * kSortItems * w + 64u * r + lane;
     const bool valid = idx < n_in;
     const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
     unsigned long long peers = __ballot(valid);
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t idx = 512u * w + 64u * r + lane;
+    const uint32_t idx = 64u * kSortItems * w + 64u * r + lane;
     if (idx < n_in) {
       const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
       const uint32_t p = loc_off[d] + rk[r];
