@@ -27,8 +27,8 @@ constexpr int kMaxLeaf = 16;          // largest n_L (bounds the walk's LDS queu
 constexpr int kMaxGroup = 128;        // targets of one walk (one wave, up to 3 per lane)
 constexpr int kMaxSys = 256;
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per tile
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
 constexpr int kSortStatusBase = 64;               // words before the digit counts (8 tickets + pad)
 constexpr int kScanBlocks = 256;
 constexpr int kMaxWavesPerCU = 16;
