@@ -74,7 +74,16 @@ __global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restric
   }
 }
 
-// Internal nodes of level l from their children (level l + 1, done).
+// Sum over the 8 lanes of an aligned lane octet (xor tree: deterministic).
+__device__ __forceinline__ double oct_sum(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  return v;
+}
+
+// Internal nodes of level l from their children (level l + 1, done): eight
+// lanes per node, lane k holding child k.
 __global__ __launch_bounds__(256) void k_moments_level(const int32_t *__restrict__ gate, 
     int l, const TreeCounters *ctr, const double *__restrict__ cube,
     const uint8_t *__restrict__ nchild, const uint32_t *__restrict__ child,
@@ -82,32 +91,36 @@ __global__ __launch_bounds__(256) void k_moments_level(const int32_t *__restrict
 #pragma clang fp contract(off)
   if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t a = ctr->lvl[l], e = ctr->lvl[l + 1];
-  for (uint32_t v = a + blockIdx.x * blockDim.x + threadIdx.x; v < e;
-       v += gridDim.x * blockDim.x) {
-    const uint32_t nch = nchild[v];
-    if (nch == 0) continue;
-    const uint32_t c0 = child[v];
-    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-    for (uint32_t k = 0; k < nch; ++k) {
-      const double mc = mom[8 * (size_t)(c0 + k)];
-      const double4 cc = com[c0 + k];
-      M += mc;
-      sx += mc * cc.x;
-      sy += mc * cc.y;
-      sz += mc * cc.z;
+  const uint32_t k = threadIdx.x & 7u;
+  const uint32_t oct = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const uint32_t n_oct = (gridDim.x * blockDim.x) >> 3;
+  for (uint32_t v0 = a; v0 < e; v0 += n_oct) {      // uniform over the wave
+    const uint32_t v = v0 + oct;
+    const bool live = v < e;
+    const uint32_t nch = live ? nchild[v] : 0u;
+    const bool mine = k < nch;
+    const uint32_t c = mine ? child[v] + k : 0u;
+    double mc = 0.0, cx_ = 0.0, cy_ = 0.0, cz_ = 0.0;
+    double4 cc = make_double4(0.0, 0.0, 0.0, 0.0);
+    double o1 = 0.0, o2 = 0.0, o3 = 0.0, o4 = 0.0, o5 = 0.0, o6 = 0.0;
+    if (mine) {
+      const double *o = mom + 8 * (size_t)c;
+      cc = com[c];
+      mc = o[0];
+      o1 = o[1]; o2 = o[2]; o3 = o[3]; o4 = o[4]; o5 = o[5]; o6 = o[6];
+      cx_ = mc * cc.x; cy_ = mc * cc.y; cz_ = mc * cc.z;
     }
-    const double cx = sx / M, cy = sy / M, cz = sz / M;
-    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (uint32_t k = 0; k < nch; ++k) {
-      const double *o = mom + 8 * (size_t)(c0 + k);
-      const double4 cc = com[c0 + k];
-      const double dx = cc.x - cx, dy = cc.y - cy, dz = cc.z - cz;
-      const double mc = o[0];
-      S[0] += o[1] + mc * dx * dx; S[1] += o[2] + mc * dy * dy;
-      S[2] += o[3] + mc * dz * dz; S[3] += o[4] + mc * dx * dy;
-      S[4] += o[5] + mc * dx * dz; S[5] += o[6] + mc * dy * dz;
-    }
-    store_moments(v, l, cube, nsys, M, cx, cy, cz, S, com, mom);
+    const double M = oct_sum(mc);
+    const double cx = oct_sum(cx_) / M, cy = oct_sum(cy_) / M, cz = oct_sum(cz_) / M;
+    const double dx = cc.x - cx, dy = cc.y - cy, dz = cc.z - cz;
+    double S[6];
+    S[0] = oct_sum(mine ? o1 + mc * dx * dx : 0.0);
+    S[1] = oct_sum(mine ? o2 + mc * dy * dy : 0.0);
+    S[2] = oct_sum(mine ? o3 + mc * dz * dz : 0.0);
+    S[3] = oct_sum(mine ? o4 + mc * dx * dy : 0.0);
+    S[4] = oct_sum(mine ? o5 + mc * dx * dz : 0.0);
+    S[5] = oct_sum(mine ? o6 + mc * dy * dz : 0.0);
+    if (live && nch > 0 && k == 0) store_moments(v, l, cube, nsys, M, cx, cy, cz, S, com, mom);
   }
 }
 
@@ -121,7 +134,7 @@ hipError_t launch_moments(tg_ctx *c, const double *mass) {
                      b.cube, b.level, b.nchild, b.first, b.count, b.nsys, b.spart, b.com,
                      b.mom);
   for (int l = kMaxLevel - 1; l >= 0; --l)     // level 21 holds only leaves
-    hipLaunchKernelGGL(k_moments_level, dim3(256), dim3(256), 0, c->stream, c->gate, l, b.ctr,
+    hipLaunchKernelGGL(k_moments_level, dim3(512), dim3(256), 0, c->stream, c->gate, l, b.ctr,
                        b.cube, b.nchild, b.child, b.nsys, b.com, b.mom);
   return hipGetLastError();
 }
