@@ -260,12 +260,31 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(const int32_t *__restrict__ g
     mn64[tid] = v;
   }
   __syncthreads();
-  if (i >= n) return;
-  const uint16_t code = lt[i];
-  if (code == 0xffff) return;
-  const uint32_t lo = code & 0xffu, top = code >> 8;
-  const int s = sys_of(so, S, i);
-  for (uint32_t l = lo; l <= top; ++l) {
+  // one slot per (particle, level) node starting in this tile, spread over
+  // the block so that a particle starting many nodes is not one long thread
+  __shared__ uint32_t pre[kFT + 1];
+  __shared__ uint16_t codes[kFT];
+  __shared__ uint32_t scan_sh[kFT / 64];
+  const uint16_t code_i = i < n ? lt[i] : (uint16_t)0xffff;
+  const uint32_t nl_i = code_i == 0xffff ? 0u : (uint32_t)(code_i >> 8) - (code_i & 0xffu) + 1u;
+  uint32_t n_slots;
+  pre[tid] = block_exclusive_scan(nl_i, scan_sh, n_slots);
+  codes[tid] = code_i;
+  if (tid == 0) pre[kFT] = n_slots;
+  __syncthreads();
+  for (uint32_t slot = tid; slot < n_slots; slot += kFT) {
+    int jl = 0, jh = kFT - 1;             // last j with pre[j] <= slot
+    while (jl < jh) {
+      const int mid = (jl + jh + 1) >> 1;
+      if (pre[mid] <= slot) jl = mid; else jh = mid - 1;
+    }
+    const int j = jl;
+    const uint32_t lo = codes[j] & 0xffu, top = codes[j] >> 8;
+    const uint32_t l = lo + (slot - pre[j]);
+    const int64_t i = t0 + j;
+    const int sk = j;                     // position of i inside the tile
+    const int s = sys_of(so, S, i);
+    {
     const uint64_t *bl = bits + l * wl;
     const uint32_t *cl = cnt + l * tl;
     const uint32_t id = lv[l] + rank_of(bl, cl, i);
@@ -274,7 +293,7 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(const int32_t *__restrict__ g
     if (l == 0) {
       e = so[s + 1];
     } else {
-      int k = tid + 1;
+      int k = sk + 1;
       int found = -1;
       for (; k < kFT && (k & 7); ++k)
         if (sd[k] < l) { found = k; break; }
@@ -309,6 +328,7 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(const int32_t *__restrict__ g
     child[id] = ch;
     nchild[id] = (uint8_t)nch;
     ninfo[id] = make_uint4((uint32_t)i, (uint32_t)(e - i), ch, nch);
+    }
   }
 }
 
