@@ -339,20 +339,34 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   }
 }
 
-// Sorted positions {x, y, z, 0} (mass filled by the moments pass) and the
-// inverse permutation.
+// Sorted particles {x, y, z, m}; the masses come with them when the caller
+// has them at build time (else the moments pass fills them in).
 __global__ void k_gather(const int32_t *__restrict__ gate, const double *__restrict__ pos,
-                         const uint32_t *__restrict__ perm, int64_t n,
-                         double4 *__restrict__ spart,
-                         uint32_t *__restrict__ rank) {
+                         const double *__restrict__ mass, const uint32_t *__restrict__ perm,
+                         int64_t n, double4 *__restrict__ spart, uint32_t *err) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
+  bool bad = false;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t o = perm[r];
+    const uint32_t o = perm[r];
+    double m = 0.0;
+    if (mass) {
+      m = mass[o];
+      bad |= !(m > 0.0) || !isfinite(m);
+    }
     spart[r] = make_double4(pos[3 * (size_t)o], pos[3 * (size_t)o + 1],
-                            pos[3 * (size_t)o + 2], 0.0);
-    rank[o] = (uint32_t)r;
+                            pos[3 * (size_t)o + 2], m);
   }
+  if (bad) set_err(err, TG_ERR_MASS);
+}
+
+// Inverse permutation (caller index -> sorted rank), needed for active lists.
+__global__ void k_rank(const int32_t *__restrict__ gate, const uint32_t *__restrict__ perm,
+                       int64_t n, uint32_t *__restrict__ rank) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x)
+    rank[perm[r]] = (uint32_t)r;
 }
 
 hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
@@ -391,11 +405,19 @@ hipError_t launch_sort(tg_ctx *c) {
   return hipGetLastError();   // 8 passes: result back in key[0] / val[0]
 }
 
-hipError_t launch_gather(tg_ctx *c, const double *pos) {
+hipError_t launch_gather(tg_ctx *c, const double *pos, const double *mass) {
   if (c->n == 0) return hipSuccess;
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, c->gate, pos,
-                     c->b.val[0], c->n, c->b.spart, c->b.rank);
+  hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, c->gate, pos, mass,
+                     c->b.val[0], c->n, c->b.spart, c->b.err);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank(tg_ctx *c) {
+  if (c->n == 0) return hipSuccess;
+  int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_rank, dim3(g), dim3(256), 0, c->stream, c->gate, c->b.val[0], c->n,
+                     c->b.rank);
   return hipGetLastError();
 }
 

@@ -124,12 +124,13 @@ __global__ __launch_bounds__(256) void k_moments_level(const int32_t *__restrict
   }
 }
 
-hipError_t launch_moments(tg_ctx *c, const double *mass) {
+hipError_t launch_moments(tg_ctx *c, const double *mass, bool gathered) {
   Buffers &b = c->b;
   if (c->n == 0) return hipSuccess;
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_mass_gather, dim3(g), dim3(256), 0, c->stream, c->gate, mass,
-                     b.val[0], c->n, b.spart, b.err);
+  if (!gathered)        // else the build's gather brought the masses already
+    hipLaunchKernelGGL(k_mass_gather, dim3(g), dim3(256), 0, c->stream, c->gate, mass,
+                       b.val[0], c->n, b.spart, b.err);
   hipLaunchKernelGGL(k_moments_leaves, dim3(1024), dim3(256), 0, c->stream, c->gate, b.ctr,
                      b.cube, b.level, b.nchild, b.first, b.count, b.nsys, b.spart, b.com,
                      b.mom);

@@ -126,6 +126,8 @@ struct tg_ctx {
   // device count that gates the build, moments and walk kernels (they
   // return at once when it is <= 0: no active particle); null = always run
   const int32_t *gate = nullptr;
+  // masses gathered into the sorted particles by the last build (or null)
+  const double *mass_gathered = nullptr;
   int64_t n_tiles = 0;
   bool have_tree = false, have_moments = false;
   bool capturing = false;
@@ -177,14 +179,15 @@ hipError_t fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s,
 // k_keys.hip
 hipError_t launch_cube_keys(tg_ctx *c, const double *pos);
 hipError_t launch_sort(tg_ctx *c);
-hipError_t launch_gather(tg_ctx *c, const double *pos);
+hipError_t launch_gather(tg_ctx *c, const double *pos, const double *mass);
+hipError_t launch_rank(tg_ctx *c);
 
 // k_tree.hip
 hipError_t launch_tree_build(tg_ctx *c);
 hipError_t launch_groups(tg_ctx *c);
 
 // k_moments.hip
-hipError_t launch_moments(tg_ctx *c, const double *mass);
+hipError_t launch_moments(tg_ctx *c, const double *mass, bool gathered);
 
 // k_walk.hip
 hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,

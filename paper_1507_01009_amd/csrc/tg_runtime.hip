@@ -258,8 +258,9 @@ static tg_status set_layout(tg_ctx *c, int64_t n, const int64_t *off, int32_t S)
   return TG_OK;
 }
 
-tg_status tg_build_tree(tg_ctx *c, const double *pos, int64_t n,
-                        const int64_t *sys_off, int32_t S) {
+// mass (may be null): gathered with the positions when the caller has it
+static tg_status build_tree_impl(tg_ctx *c, const double *pos, const double *mass,
+                                 int64_t n, const int64_t *sys_off, int32_t S) {
   if (!c) return fail(TG_EINVAL, "tg_build_tree: NULL context");
   if (n < 0 || n > c->cfg.max_particles)
     return fail(TG_EINVAL, "tg_build_tree: N exceeds max_particles");
@@ -273,18 +274,27 @@ tg_status tg_build_tree(tg_ctx *c, const double *pos, int64_t n,
   c->have_tree = c->have_moments = false;
   TG_HIP(launch_cube_keys(c, pos));
   TG_HIP(launch_sort(c));
-  TG_HIP(launch_gather(c, pos));
+  TG_HIP(launch_gather(c, pos, mass));
   TG_HIP(launch_tree_build(c));
   TG_HIP(launch_groups(c));
   c->have_tree = true;
+  c->mass_gathered = mass;
   return TG_OK;
+}
+
+tg_status tg_build_tree(tg_ctx *c, const double *pos, int64_t n,
+                        const int64_t *sys_off, int32_t S) {
+  return build_tree_impl(c, pos, nullptr, n, sys_off, S);
 }
 
 tg_status tg_compute_moments(tg_ctx *c, const double *mass) {
   if (!c) return fail(TG_EINVAL, "tg_compute_moments: NULL context");
   if (!c->have_tree) return fail(TG_ESTATE, "tg_compute_moments: no tree");
   if (c->n > 0 && !mass) return fail(TG_EINVAL, "tg_compute_moments: NULL mass");
-  TG_HIP(launch_moments(c, mass));
+  // the build gathered these masses only for the moments right after it
+  const bool gathered = mass == c->mass_gathered;
+  c->mass_gathered = nullptr;
+  TG_HIP(launch_moments(c, mass, gathered));
   c->have_moments = true;
   return TG_OK;
 }
@@ -785,7 +795,7 @@ tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
   // with an active list, the build, moments and walk are skipped on the
   // device when it is empty (the SMBH sums below always run)
   c->gate = idx ? n_act : nullptr;
-  st = tg_build_tree(c, y->pos, y->n, y->sys_off, y->n_sys);
+  st = build_tree_impl(c, y->pos, y->mass, y->n, y->sys_off, y->n_sys);
   if (st == TG_OK) st = tg_compute_moments(c, y->mass);
   c->gate = nullptr;
   if (st != TG_OK) return st;
