@@ -232,6 +232,37 @@ def direct_errors(w, accs, n_samples=128):
     return out
 
 
+def direct_errors_gpu(w, accs, n_samples=65536):
+    """Per-percentile error of each path against the FP64 direct sum (stars
+    and SMBHs, compensated, tg_direct_fp64, itself parity-tested against the
+    oracle) on seeded sample targets.  A target's own pair adds no force."""
+    import numpy as np
+    import torch
+    from paper_1507_01009_amd import binding as B
+    rng = np.random.default_rng(98)
+    tg = np.sort(rng.choice(w.n, min(n_samples, w.n), replace=False))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    ctx = B.Context(w.n)
+    pos, m = dev(w.pos), dev(w.mass)
+    seps = torch.full((w.n,), w.eps, dtype=torch.float64, device="cuda")
+    tpos = dev(w.pos[tg])
+    teps = torch.full((tg.size,), w.eps, dtype=torch.float64, device="cuda")
+    acc = torch.zeros((tg.size, 3), dtype=torch.float64, device="cuda")
+    ctx.direct_fp64(pos, m, seps, tpos, teps, acc)
+    if w.bh_mass.shape[0]:
+        ctx.direct_fp64(dev(w.bh_pos.reshape(-1, 3)), dev(w.bh_mass), dev(w.bh_eps), tpos, teps,
+                        acc, accumulate=True)
+    ctx.sync()
+    ref = acc.cpu().numpy()
+    ctx.close()
+    out = {}
+    for name, a in accs.items():
+        e = np.linalg.norm(a[tg] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        out[name + "_vs_direct_sum_fp64_gpu"] = percentiles(e)
+    out["direct_sum_fp64_gpu_samples"] = int(tg.size)
+    return out
+
+
 def cpu_baseline(w, leaf, group, seconds):
     """The oracle (plain C, all host threads) on a bounded sample of the same
     step: full tree build, then the walk + evaluation of random groups until
@@ -427,6 +458,7 @@ def main():
     if "mixed" in accs and "fp64" in accs:
         e = np.linalg.norm(accs["mixed"] - accs["fp64"], axis=1) / np.linalg.norm(accs["fp64"], axis=1)
         err["mixed_vs_fp64"] = percentiles(e)
+    err.update(direct_errors_gpu(w, accs))
     if not a.no_cpu:
         err.update(direct_errors(w, accs))
     head = res["mixed"] if "mixed" in res else res["fp64"]
