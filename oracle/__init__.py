@@ -73,6 +73,7 @@ def lib():
             "or_kick": (None, [P, P, P, i64, P, f64]),
             "or_drift": (None, [P, P, i64, f64]),
             "or_levels": (None, [P, P, P, i64, f64, i32, i64, P]),
+            "or_levels_v": (None, [P, P, P, P, P, i64, f64, i32, i64, P]),
             "or_active_at": (i64, [P, i64, i32, i64, P]),
             "or_p2m_single": (None, [P, P, f64, f64, P]),
             "or_p2p_single": (None, [P, f64, P, f64, f64, P]),
@@ -370,14 +371,20 @@ def drift(pos, vel, dt):
     lib().or_drift(_p(pos), _p(_c(vel, np.float64)), pos.shape[0], float(dt))
 
 
-def levels(acc, tau4eps2, level, dt_max, nlev, k, idx=None):
-    """In place: new block levels for the listed (active) particles."""
+def levels(acc, tau4eps2, level, dt_max, nlev, k, idx=None, vel=None, tau2eps2v=None):
+    """In place: new block levels for the listed (active) particles; with vel
+    and tau2eps2v = tau_vel^2 eps^2 also the velocity criterion."""
     assert level.dtype == np.uint8 and level.flags.c_contiguous
     acc = _c(acc, np.float64)
     n = acc.shape[0] if idx is None else len(idx)
     idx = None if idx is None else _c(idx, np.int32)
-    lib().or_levels(_p(acc), _p(_c(tau4eps2, np.float64)), _p(idx), n,
-                    float(dt_max), int(nlev), int(k), _p(level))
+    if vel is None:
+        lib().or_levels(_p(acc), _p(_c(tau4eps2, np.float64)), _p(idx), n,
+                        float(dt_max), int(nlev), int(k), _p(level))
+    else:
+        lib().or_levels_v(_p(acc), _p(_c(vel, np.float64)), _p(_c(tau4eps2, np.float64)),
+                          _p(_c(tau2eps2v, np.float64)), _p(idx), n, float(dt_max),
+                          int(nlev), int(k), _p(level))
 
 
 def active_at(level, nlev, k):

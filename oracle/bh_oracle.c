@@ -616,24 +616,40 @@ void or_drift(double *pos, const double *vel, int64_t n, double dt) {
 /* with k mod 2^(nlev-1-l) == 0.  tau4eps2[i] = (tau_i^2)^2 * eps^2.  Only  */
 /* the listed (active) particles are updated.                               */
 /* ---------------------------------------------------------------------- */
-void or_levels(const double *acc, const double *tau4eps2, const int32_t *idx,
-               int64_t n, double dt_max, int32_t nlev, int64_t k,
-               uint8_t *level) {
+/* Levels with an optional velocity criterion (READING: the VINE criterion  */
+/* dt_vel = tau_vel eps / |v|, the paper quoting tau_vel beside tau_acc).    */
+/* A level c is admissible iff (dt_c^2)^2 |a|^2 <= tau4eps2[i] and, with     */
+/* vel, dt_c^2 |v|^2 <= tau2eps2v[i]; the particle takes the smallest        */
+/* admissible level (else the finest), raised to the coarsest one whose step */
+/* divides k.                                                                */
+void or_levels_v(const double *acc, const double *vel, const double *tau4eps2,
+                 const double *tau2eps2v, const int32_t *idx, int64_t n,
+                 double dt_max, int32_t nlev, int64_t k, uint8_t *level) {
   int lmin = 0;
   while (lmin < nlev - 1 && (k % ((int64_t)1 << (nlev - 1 - lmin))) != 0) ++lmin;
   for (int64_t t = 0; t < n; ++t) {
     int64_t i = idx ? idx[t] : t;
     double a2 = acc[3 * i] * acc[3 * i] + acc[3 * i + 1] * acc[3 * i + 1] +
                 acc[3 * i + 2] * acc[3 * i + 2];
+    double v2 = 0.0;
+    if (vel)
+      v2 = vel[3 * i] * vel[3 * i] + vel[3 * i + 1] * vel[3 * i + 1] +
+           vel[3 * i + 2] * vel[3 * i + 2];
     int l = nlev - 1;
     for (int c = 0; c < nlev; ++c) {
       double dl = ldexp(dt_max, -c);
       double d2 = dl * dl;
-      if (d2 * d2 * a2 <= tau4eps2[i]) { l = c; break; }
+      if (d2 * d2 * a2 <= tau4eps2[i] && (!vel || d2 * v2 <= tau2eps2v[i])) { l = c; break; }
     }
     if (l < lmin) l = lmin;
     level[i] = (uint8_t)l;
   }
+}
+
+void or_levels(const double *acc, const double *tau4eps2, const int32_t *idx,
+               int64_t n, double dt_max, int32_t nlev, int64_t k,
+               uint8_t *level) {
+  or_levels_v(acc, 0, tau4eps2, 0, idx, n, dt_max, nlev, k, level);
 }
 
 /* Particles active at substep k: k mod 2^(nlev-1-level) == 0, in index    */

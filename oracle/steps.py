@@ -96,16 +96,36 @@ def kdk_step(st: State, dt: float):
         oracle.kick(st.bh_vel, st.bh_acc, dt)
 
 
+def dkd_step(st: State, dt: float):
+    """Drift-kick-drift (Sec. 2, step 6): x += v dt/2, forces, v += a dt,
+    x += v dt/2 (stars and SMBHs)."""
+    oracle.drift(st.pos, st.vel, 0.5 * dt)
+    if st.bh_mass.size:
+        oracle.drift(st.bh_pos, st.bh_vel, 0.5 * dt)
+    forces(st)
+    oracle.kick(st.vel, st.acc, 2.0 * dt)          # kick() applies half its dt
+    if st.bh_mass.size:
+        oracle.kick(st.bh_vel, st.bh_acc, 2.0 * dt)
+    oracle.drift(st.pos, st.vel, 0.5 * dt)
+    if st.bh_mass.size:
+        oracle.drift(st.bh_pos, st.bh_vel, 0.5 * dt)
+
+
 def block_substep(st: State, level: np.ndarray, tau4eps2: np.ndarray, k: int,
-                  dt_max: float, nlev: int):
-    """One substep at counter k; returns k + 1 and the new active set."""
+                  dt_max: float, nlev: int, tau2eps2v=None):
+    """One substep at counter k; returns k + 1 and the new active set.  With
+    tau2eps2v the levels also take the velocity criterion."""
     dt_min = dt_max * 2.0 ** -(nlev - 1)
     act = oracle.active_at(level, nlev, k)
     if k > 0:
         oracle.kick(st.vel, st.acc, dt_max, idx=act, level=level)
         if st.bh_mass.size:
             oracle.kick(st.bh_vel, st.bh_acc, dt_min)
-    oracle.levels(st.acc, tau4eps2, level, dt_max, nlev, k, idx=act)
+    if tau2eps2v is None:
+        oracle.levels(st.acc, tau4eps2, level, dt_max, nlev, k, idx=act)
+    else:
+        oracle.levels(st.acc, tau4eps2, level, dt_max, nlev, k, idx=act, vel=st.vel,
+                      tau2eps2v=tau2eps2v)
     oracle.kick(st.vel, st.acc, dt_max, idx=act, level=level)
     if st.bh_mass.size:
         oracle.kick(st.bh_vel, st.bh_acc, dt_min)

@@ -122,3 +122,61 @@ def test_block_steps_on_one_level_equal_global_kdk_bitwise():
     xb, vb = _block_run(x.copy(), v.copy(), m, 0.01, 7, nlev, dtmax, 16)
     xg, vg = _kepler_step(x.copy(), v.copy(), m, 0.01, dtmax * 2.0 ** -7, 16)
     assert np.array_equal(xb, xg) and np.array_equal(vb, vg)
+
+
+def test_levels_velocity_criterion_thresholds():
+    """dt_vel = tau_vel eps / |v| just either side of every dt_l; zero
+    acceleration, so the velocity alone decides."""
+    nlev, dtmax = 8, 2.0 ** -6
+    tau, eps = 0.3, 0.01
+    vel, want = [], []
+    for l in range(nlev):
+        dl = dtmax * 2.0 ** -l
+        vmag = tau * eps / dl
+        for f, lev in ((1.0 - 1e-9, l), (1.0 + 1e-9, min(l + 1, nlev - 1))):
+            vel.append([0.0, vmag * f, 0.0])
+            want.append(lev)
+    vel = np.array(vel)
+    n = len(vel)
+    level = np.zeros(n, np.uint8)
+    oracle.levels(np.zeros((n, 3)), np.ones(n), level, dtmax, nlev, 0, vel=vel,
+                  tau2eps2v=np.full(n, tau ** 2 * eps ** 2))
+    assert list(level) == want
+
+
+def test_levels_take_the_stricter_criterion():
+    nlev, dtmax, tau, eps = 8, 2.0 ** -6, 0.3, 0.01
+    dl3 = dtmax * 2.0 ** -3
+    acc = np.array([[tau * tau * eps / dl3 ** 2 * 0.999, 0.0, 0.0]] * 2)   # level 3 by |a|
+    vel = np.array([[0.0, 0.0, tau * eps / (dtmax * 2.0 ** -5) * 0.999],    # level 5 by |v|
+                    [0.0, 0.0, tau * eps / (dtmax * 2.0 ** -1) * 0.999]])   # level 1 by |v|
+    level = np.zeros(2, np.uint8)
+    oracle.levels(acc, np.full(2, tau ** 4 * eps ** 2), level, dtmax, nlev, 0, vel=vel,
+                  tau2eps2v=np.full(2, tau ** 2 * eps ** 2))
+    assert list(level) == [5, 3]
+
+
+def _kepler_dkd(x, v, m, eps, dt, n):
+    for _ in range(n):
+        oracle.drift(x, v, 0.5 * dt)
+        acc, _ = oracle.direct_pairs(x, m, eps, x, eps, self_pairs=True)
+        oracle.kick(v, acc, 2.0 * dt)
+        oracle.drift(x, v, 0.5 * dt)
+    return x, v
+
+
+def test_dkd_energy_error_scales_dt_squared_and_is_reversible():
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        x, v, m = _binary()
+        e0 = _energy(x, v, m, 0.0)
+        x, v = _kepler_dkd(x, v, m, 0.0, dt, int(round(6.0 / dt)))
+        errs.append(abs(_energy(x, v, m, 0.0) - e0) / abs(e0))
+    assert 3.0 < errs[0] / errs[1] < 5.5 and 3.0 < errs[1] / errs[2] < 5.5
+    x, v, m = _binary()
+    x0, v0 = x.copy(), v.copy()
+    x, v = _kepler_dkd(x, v, m, 0.01, 0.01, 200)
+    v *= -1.0
+    x, v = _kepler_dkd(x, v, m, 0.01, 0.01, 200)
+    v *= -1.0
+    assert np.allclose(x, x0, atol=1e-11) and np.allclose(v, v0, atol=1e-11)
