@@ -196,6 +196,17 @@ tg_status tg_levels(tg_ctx *ctx, const double *acc_dev,
                     const int32_t *n_active_dev, double dt_max, int32_t nlev,
                     const int64_t *k_dev, uint8_t *level_dev);
 
+/* As tg_levels, with the velocity criterion dt_vel = tau_vel eps / |v| as
+ * well (a reading of the VINE criterion the paper sets tau_vel for, Sec. 3):
+ * a level is admissible only if also dt_l^2 |v|^2 <= tau2eps2v_dev[i] =
+ * tau_vel,i^2 eps_i^2.  vel_dev [n][3] and tau2eps2v_dev [n] are both given
+ * or both NULL (NULL: tg_levels). */
+tg_status tg_levels_v(tg_ctx *ctx, const double *acc_dev, const double *vel_dev,
+                      const double *tau4eps2_dev, const double *tau2eps2v_dev,
+                      int64_t n, const int32_t *active_idx_dev,
+                      const int32_t *n_active_dev, double dt_max, int32_t nlev,
+                      const int64_t *k_dev, uint8_t *level_dev);
+
 /* Indices (ascending) of the particles active at substep k_dev[0] + k_add:
  * (k mod 2^(nlev-1-level_i)) == 0.  Writes idx_dev[0..m) and n_out_dev[0]=m. */
 tg_status tg_active_set(tg_ctx *ctx, const uint8_t *level_dev, int64_t n,
@@ -241,6 +252,11 @@ tg_status tg_forces(tg_ctx *ctx, const tg_system *sys,
  * the forces of the current positions, e.g. from tg_forces). */
 tg_status tg_step_kdk(tg_ctx *ctx, const tg_system *sys, double dt);
 
+/* One drift-kick-drift step (the paper's tree step, Sec. 2 step 6): x += v
+ * dt/2, forces at the half step, v += a dt, x += v dt/2, stars and SMBHs.
+ * acc holds the half-step forces afterwards. */
+tg_status tg_step_dkd(tg_ctx *ctx, const tg_system *sys, double dt);
+
 typedef struct {
   uint8_t *level;                  /* [n] block level of each star */
   const double *tau4eps2;          /* [n] (tau^2)^2 eps^2 per star */
@@ -249,6 +265,7 @@ typedef struct {
   int64_t *k;                      /* [1] substep counter (units of the smallest step) */
   double dt_max;                   /* step of level 0 */
   int32_t nlev;                    /* levels 0..nlev-1; smallest step dt_max 2^-(nlev-1) */
+  const double *tau2eps2v;         /* [n] tau_vel^2 eps^2 per star (velocity criterion), or NULL */
 } tg_blocks;
 
 /* One substep of the smallest step: closing half kicks of the stars whose

@@ -56,7 +56,7 @@ class tg_system(C.Structure):
 class tg_blocks(C.Structure):
     _fields_ = [("level", C.c_void_p), ("tau4eps2", C.c_void_p),
                 ("active_idx", C.c_void_p), ("n_active", C.c_void_p), ("k", C.c_void_p),
-                ("dt_max", C.c_double), ("nlev", C.c_int32)]
+                ("dt_max", C.c_double), ("nlev", C.c_int32), ("tau2eps2v", C.c_void_p)]
 
 
 _lib = None
@@ -90,11 +90,13 @@ def lib():
             "tg_kick": (st, [P, P, P, i64, P, P, P, f64, P, i32]),
             "tg_drift": (st, [P, P, P, i64, f64]),
             "tg_levels": (st, [P, P, P, i64, P, P, f64, i32, P, P]),
+            "tg_levels_v": (st, [P, P, P, P, P, i64, P, P, f64, i32, P, P]),
             "tg_active_set": (st, [P, P, i64, i32, P, i32, P, P]),
             "tg_counter_add": (st, [P, P, i64]),
             "tg_set_external": (st, [P, P, P, P, i32, P, i32]),
             "tg_forces": (st, [P, P, P, P]),
             "tg_step_kdk": (st, [P, P, f64]),
+            "tg_step_dkd": (st, [P, P, f64]),
             "tg_step_block": (st, [P, P, P]),
             "tg_graph_begin": (st, [P]),
             "tg_graph_end": (st, [P, P]),
@@ -120,9 +122,9 @@ def lib():
 EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_set_sizes", "tg_build_tree", "tg_compute_moments",
             "tg_tree_forces", "tg_get_counts", "tg_reset_counts", "tg_walk_lists",
-            "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels",
+            "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
             "tg_active_set", "tg_counter_add", "tg_set_external", "tg_forces",
-            "tg_step_kdk", "tg_step_block", "tg_graph_begin",
+            "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
             "tg_get_profile", "tg_sync", "tg_last_error",
@@ -284,10 +286,12 @@ class Context:
         _check(lib().tg_drift(self.h, _ptr(pos), _ptr(vel), pos.shape[0], float(dt)))
 
     def levels(self, acc, tau4eps2, level, dt_max, nlev, k=None, active_idx=None,
-               n_active=None):
-        _check(lib().tg_levels(self.h, _ptr(acc), _ptr(tau4eps2), acc.shape[0],
-                               _ptr(active_idx), _ptr(n_active), float(dt_max), int(nlev),
-                               _ptr(k), _ptr(level)))
+               n_active=None, vel=None, tau2eps2v=None):
+        """Block levels; with vel and tau2eps2v also the velocity criterion."""
+        _check(lib().tg_levels_v(self.h, _ptr(acc), _ptr(vel), _ptr(tau4eps2),
+                                 _ptr(tau2eps2v), acc.shape[0], _ptr(active_idx),
+                                 _ptr(n_active), float(dt_max), int(nlev), _ptr(k),
+                                 _ptr(level)))
 
     def active_set(self, level, nlev, k, idx, n_out, k_add=0):
         _check(lib().tg_active_set(self.h, _ptr(level), level.shape[0], int(nlev), _ptr(k),
@@ -329,11 +333,16 @@ class Context:
     def step_kdk(self, system, dt):
         _check(lib().tg_step_kdk(self.h, C.byref(system), float(dt)))
 
-    def make_blocks(self, level, tau4eps2, active_idx, n_active, k, dt_max, nlev):
+    def step_dkd(self, system, dt):
+        _check(lib().tg_step_dkd(self.h, C.byref(system), float(dt)))
+
+    def make_blocks(self, level, tau4eps2, active_idx, n_active, k, dt_max, nlev,
+                    tau2eps2v=None):
         b = tg_blocks()
         b.level, b.tau4eps2 = _ptr(level), _ptr(tau4eps2)
         b.active_idx, b.n_active, b.k = _ptr(active_idx), _ptr(n_active), _ptr(k)
         b.dt_max, b.nlev = float(dt_max), int(nlev)
+        b.tau2eps2v = _ptr(tau2eps2v)
         return b
 
     def step_block(self, system, blocks):

@@ -49,7 +49,9 @@ __device__ __forceinline__ int lmin_at(int64_t k, int nlev) {
 }
 
 __global__ void k_levels(const double *__restrict__ acc,
-                         const double *__restrict__ t4e2, int64_t n,
+                         const double *__restrict__ vel,
+                         const double *__restrict__ t4e2,
+                         const double *__restrict__ t2e2v, int64_t n,
                          const int32_t *__restrict__ idx,
                          const int32_t *__restrict__ n_act, double dt_max,
                          int nlev, const int64_t *__restrict__ kctr,
@@ -63,11 +65,16 @@ __global__ void k_levels(const double *__restrict__ acc,
     if (i < 0 || i >= n) continue;
     const double ax = acc[3 * i], ay = acc[3 * i + 1], az = acc[3 * i + 2];
     const double a2 = ax * ax + ay * ay + az * az;
+    double v2 = 0.0;
+    if (vel) {
+      const double vx = vel[3 * i], vy = vel[3 * i + 1], vz = vel[3 * i + 2];
+      v2 = vx * vx + vy * vy + vz * vz;
+    }
     int l = nlev - 1;
     for (int c = 0; c < nlev; ++c) {
       const double dl = ldexp(dt_max, -c);
       const double d2 = dl * dl;
-      if (d2 * d2 * a2 <= t4e2[i]) { l = c; break; }
+      if (d2 * d2 * a2 <= t4e2[i] && (!vel || d2 * v2 <= t2e2v[i])) { l = c; break; }
     }
     level[i] = (uint8_t)(l < lmin ? lmin : l);
   }
@@ -121,13 +128,13 @@ hipError_t launch_drift(tg_ctx *c, double *pos, const double *vel, int64_t n,
   return hipGetLastError();
 }
 
-hipError_t launch_levels(tg_ctx *c, const double *acc, const double *t4e2,
-                         int64_t n, const int32_t *idx, const int32_t *n_act,
-                         double dt_max, int nlev, const int64_t *k,
-                         uint8_t *level) {
+hipError_t launch_levels(tg_ctx *c, const double *acc, const double *vel,
+                         const double *t4e2, const double *t2e2v, int64_t n,
+                         const int32_t *idx, const int32_t *n_act, double dt_max, int nlev,
+                         const int64_t *k, uint8_t *level) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_levels, dim3(grid_n(n)), dim3(256), 0, c->stream, acc,
-                     t4e2, n, idx, n_act, dt_max, nlev, k, level);
+  hipLaunchKernelGGL(k_levels, dim3(grid_n(n)), dim3(256), 0, c->stream, acc, vel,
+                     t4e2, t2e2v, n, idx, n_act, dt_max, nlev, k, level);
   return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ namespace tg {
 #define TG_WALK_WAVES_MIXED 4
 #endif
 #ifndef TG_WALK_WAVES_FP64
-#define TG_WALK_WAVES_FP64 3
+#define TG_WALK_WAVES_FP64 2
 #endif
 
 constexpr int kTile = 128;                  // source tile entries (a flush uses <= 127)

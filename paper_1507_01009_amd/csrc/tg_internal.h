@@ -215,10 +215,10 @@ hipError_t launch_kick(tg_ctx *c, double *vel, const double *acc, int64_t n,
                        int skip_k0);
 hipError_t launch_drift(tg_ctx *c, double *pos, const double *vel, int64_t n,
                         double dt);
-hipError_t launch_levels(tg_ctx *c, const double *acc, const double *t4e2,
-                         int64_t n, const int32_t *idx, const int32_t *n_act,
-                         double dt_max, int nlev, const int64_t *k,
-                         uint8_t *level);
+hipError_t launch_levels(tg_ctx *c, const double *acc, const double *vel,
+                         const double *t4e2, const double *t2e2v, int64_t n,
+                         const int32_t *idx, const int32_t *n_act, double dt_max, int nlev,
+                         const int64_t *k, uint8_t *level);
 hipError_t launch_active_set(tg_ctx *c, const uint8_t *level, int64_t n,
                              int nlev, const int64_t *k, int k_add,
                              int32_t *idx, int32_t *n_out);

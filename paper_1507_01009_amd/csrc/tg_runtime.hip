@@ -577,17 +577,26 @@ tg_status tg_drift(tg_ctx *c, double *pos, const double *vel, int64_t n, double 
   return TG_OK;
 }
 
-tg_status tg_levels(tg_ctx *c, const double *acc, const double *t4e2, int64_t n,
-                    const int32_t *idx, const int32_t *n_act, double dt_max,
-                    int32_t nlev, const int64_t *k, uint8_t *level) {
+tg_status tg_levels_v(tg_ctx *c, const double *acc, const double *vel,
+                      const double *t4e2, const double *t2e2v, int64_t n,
+                      const int32_t *idx, const int32_t *n_act, double dt_max,
+                      int32_t nlev, const int64_t *k, uint8_t *level) {
   if (!c) return fail(TG_EINVAL, "tg_levels: NULL context");
   if (n < 0) return fail(TG_EINVAL, "tg_levels: negative n");
   if (nlev < 1 || nlev > 30) return fail(TG_EINVAL, "tg_levels: nlev must be in 1..30");
   if (!(dt_max > 0.0)) return fail(TG_EINVAL, "tg_levels: dt_max must be positive");
   if (n > 0 && (!acc || !t4e2 || !level)) return fail(TG_EINVAL, "tg_levels: NULL pointer");
   if (idx && !n_act) return fail(TG_EINVAL, "tg_levels: n_active required");
-  TG_HIP(launch_levels(c, acc, t4e2, n, idx, n_act, dt_max, nlev, k, level));
+  if ((vel == nullptr) != (t2e2v == nullptr))
+    return fail(TG_EINVAL, "tg_levels_v: vel and tau2eps2v go together");
+  TG_HIP(launch_levels(c, acc, vel, t4e2, t2e2v, n, idx, n_act, dt_max, nlev, k, level));
   return TG_OK;
+}
+
+tg_status tg_levels(tg_ctx *c, const double *acc, const double *t4e2, int64_t n,
+                    const int32_t *idx, const int32_t *n_act, double dt_max,
+                    int32_t nlev, const int64_t *k, uint8_t *level) {
+  return tg_levels_v(c, acc, nullptr, t4e2, nullptr, n, idx, n_act, dt_max, nlev, k, level);
 }
 
 tg_status tg_active_set(tg_ctx *c, const uint8_t *level, int64_t n, int32_t nlev,
@@ -838,6 +847,22 @@ tg_status tg_step_kdk(tg_ctx *c, const tg_system *y, double dt) {
   return tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt, nullptr, 0);
 }
 
+tg_status tg_step_dkd(tg_ctx *c, const tg_system *y, double dt) {
+  tg_status st = check_system(y, "tg_step_dkd");
+  if (st != TG_OK) return st;
+  // tg_kick applies half of its dt: 2 dt gives the full kick
+  if ((st = tg_drift(c, y->pos, y->vel, y->n, 0.5 * dt))) return st;
+  if ((st = tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, 0.5 * dt))) return st;
+  if ((st = tg_forces(c, y, nullptr, nullptr))) return st;
+  if ((st = tg_kick(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, 2.0 * dt, nullptr, 0)))
+    return st;
+  if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, 2.0 * dt,
+                    nullptr, 0)))
+    return st;
+  if ((st = tg_drift(c, y->pos, y->vel, y->n, 0.5 * dt))) return st;
+  return tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, 0.5 * dt);
+}
+
 tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
   tg_status st = check_system(y, "tg_step_block");
   if (st != TG_OK) return st;
@@ -856,8 +881,9 @@ tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
                     b->k, 1)))
     return st;
   // new levels, then opening half kicks with the new steps
-  if ((st = tg_levels(c, y->acc, b->tau4eps2, y->n, b->active_idx, b->n_active, b->dt_max,
-                      b->nlev, b->k, b->level)))
+  if ((st = tg_levels_v(c, y->acc, b->tau2eps2v ? y->vel : nullptr, b->tau4eps2,
+                        b->tau2eps2v, y->n, b->active_idx, b->n_active, b->dt_max, b->nlev,
+                        b->k, b->level)))
     return st;
   if ((st = tg_kick(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
                     b->dt_max, nullptr, 0)))

@@ -320,3 +320,85 @@ def test_block_substeps_mostly_empty_match_oracle():
     assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-12 * np.abs(st.pos).max()
     assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-11 * np.abs(st.vel).max()
     assert np.max(np.abs(h["bpos"] - st.bh_pos)) <= 1e-14
+
+
+def test_dkd_steps_with_smbh():
+    say("dkd steps")
+    from paper_1507_01009_amd import binding as B
+    w = ics.hernquist_c2(n=32768)
+    dt = 1e-3
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    for _ in range(3):
+        ctx.step_dkd(d.sys, dt)
+    ctx.sync()
+    h = d.host()
+    st = ostate(w)
+    for _ in range(3):
+        osteps.dkd_step(st, dt)
+    assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-13 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-12 * np.abs(st.vel).max()
+    assert rel_err(h["acc"], st.acc).max() <= 1e-11
+    assert np.allclose(h["bpos"], st.bh_pos, rtol=0, atol=1e-15)
+
+
+def test_levels_with_velocity_criterion_bit_exact():
+    say("levels_v")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    rng = np.random.default_rng(31)
+    n, nlev, dtmax = 50000, 8, 2.0 ** -6
+    # magnitudes whose steps tau sqrt(eps/|a|) and tau eps/|v| span the levels
+    unit = lambda m: m / np.linalg.norm(m, axis=1, keepdims=True)
+    acc = unit(rng.normal(size=(n, 3))) * np.exp(rng.uniform(np.log(1.0), np.log(1e5), (n, 1)))
+    vel = unit(rng.normal(size=(n, 3))) * np.exp(rng.uniform(np.log(0.05), np.log(50.0), (n, 1)))
+    t4 = np.full(n, 0.3 ** 4 * 0.01 ** 2)
+    t2 = np.full(n, 0.3 ** 2 * 0.01 ** 2)
+    ctx = B.Context(n)
+    for k in (0, 3, 64):
+        lev = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        kk = torch.tensor([k], dtype=torch.int64, device="cuda")
+        ctx.levels(to_dev(acc), to_dev(t4), lev, dtmax, nlev, k=kk, vel=to_dev(vel),
+                   tau2eps2v=to_dev(t2))
+        ctx.sync()
+        want = np.zeros(n, np.uint8)
+        oracle.levels(acc, t4, want, dtmax, nlev, k, vel=vel, tau2eps2v=t2)
+        assert np.array_equal(lev.cpu().numpy(), want), k
+        # the velocity criterion is what decides for some particles
+        acc_only = np.zeros(n, np.uint8)
+        oracle.levels(acc, t4, acc_only, dtmax, nlev, k)
+        if k != 3:                 # at k = 3 only the finest step divides k
+            assert np.any(acc_only != want) and len(np.unique(want)) >= 3
+
+
+def test_block_substeps_with_velocity_criterion_match_oracle():
+    say("block substeps, velocity criterion")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    w = ics.hernquist_c4(n=8192)
+    nlev, dt_max = 8, 0.25
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    level = torch.zeros(w.n, dtype=torch.uint8, device="cuda")
+    t4e2 = np.full(w.n, 0.3 ** 4 * w.eps ** 2)
+    t2e2 = np.full(w.n, 0.3 ** 2 * w.eps ** 2)
+    idx = torch.zeros(w.n, dtype=torch.int32, device="cuda")
+    na = torch.zeros(1, dtype=torch.int32, device="cuda")
+    k = torch.zeros(1, dtype=torch.int64, device="cuda")
+    t4d, t2d = to_dev(t4e2), to_dev(t2e2)
+    blk = ctx.make_blocks(level, t4d, idx, na, k, dt_max, nlev, tau2eps2v=t2d)
+    ctx.forces(d.sys)
+    nsub = 24
+    for _ in range(nsub):
+        ctx.step_block(d.sys, blk)
+    ctx.sync()
+    h = d.host()
+    st = ostate(w)
+    osteps.forces(st)
+    olev = np.zeros(w.n, np.uint8)
+    kk = 0
+    for _ in range(nsub):
+        kk, act = osteps.block_substep(st, olev, t4e2, kk, dt_max, nlev, tau2eps2v=t2e2)
+    assert np.array_equal(level.cpu().numpy(), olev)
+    assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-12 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-11 * np.abs(st.vel).max()
