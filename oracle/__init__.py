@@ -62,10 +62,11 @@ def lib():
             "or_moments": (None, [P, P, i64, P, P, P]),
             "or_groups": (i64, [i64, P, P, P, P, P, P, i32, i64, P]),
             "or_group_boxes": (None, [P, P, i64, P, P, P]),
+            "or_rel_records": (None, [i64, P, P, P, P, P, P, f64, P]),
             "or_walk_lists": (C.c_int, [i64, P, P, P, P, P, P, P, P, P, i64, f64,
-                                        P, P, P, P]),
+                                        P, P, P, P, P, P]),
             "or_tree_forces": (C.c_int, [i64, P, P, P, P, P, P, P, P, P, P, P, i64,
-                                         P, P, P, f64, f64, f64, P, P, P]),
+                                         P, P, P, f64, f64, P, P, f64, P, P, P]),
             "or_direct": (None, [P, P, P, i32, P, P, i64, f64, P, P, P, i64, f64,
                                  P, P]),
             "or_direct_pairs": (None, [P, P, P, i64, P, P, i64, C.c_int, f64,
@@ -230,16 +231,45 @@ def active_mask(n, active=None):
     return m
 
 
-def walk_lists(tree: Tree, mom, g, box, sel, theta: float):
-    """Sorted P2M and P2P node-id lists for each selected group."""
+def rel_records(tree: Tree, mom, G=1.0) -> np.ndarray:
+    """[nn, 8] per cell: the 1.2x cube {lo x, y, z, P = (G M) s^2, hi x, y, z, 0}
+    of the relative opening test."""
+    rel = np.zeros((tree.nn, 8), np.float64)
+    lib().or_rel_records(tree.nn, _p(tree.level), _p(tree.first), _p(tree.sys),
+                         _p(tree.skeys), _p(tree.cube), _p(_c(mom, np.float64)),
+                         float(G), _p(rel))
+    return rel
+
+
+def group_arel(tree: Tree, g, sactive, acc_old, alpha: float) -> np.ndarray:
+    """Per group: (alpha alpha) * min over its active targets of |a_old|^2,
+    |a|^2 = (ax ax + ay ay) + az az (acc_old in original order; 0 for a
+    group without active targets)."""
+    n = tree.perm.shape[0]
+    out = np.zeros(g.shape[0], np.float64)
+    if n == 0 or g.shape[0] == 0:
+        return out
+    a = _c(acc_old, np.float64).reshape(-1, 3)[tree.perm.astype(np.int64)]
+    a2 = (a[:, 0] * a[:, 0] + a[:, 1] * a[:, 1]) + a[:, 2] * a[:, 2]
+    a2 = np.where(np.asarray(sactive, bool), a2, np.inf)
+    m = np.minimum.reduceat(a2, g[:, 0].astype(np.int64))
+    aa = float(alpha) * float(alpha)
+    return np.where(np.isfinite(m), aa * m, 0.0)
+
+
+def walk_lists(tree: Tree, mom, g, box, sel, theta: float, rel=None, arel=None):
+    """Sorted P2M and P2P node-id lists for each selected group (relative
+    opening test when rel / arel are given, see :func:`rel_records`)."""
     sel = _c(sel, np.int32)
     ns = sel.shape[0]
     np2m = np.zeros(ns, np.int64)
     np2p = np.zeros(ns, np.int64)
+    rel = None if rel is None else _c(rel, np.float64)
+    arel = None if arel is None else _c(arel, np.float64)
     args = (tree.nn, _p(tree.level), _p(tree.child), _p(tree.nchild),
             _p(tree.sys), _p(_c(mom, np.float64)), _p(tree.cube),
             _p(_c(g, np.uint32)), _p(_c(box, np.float64)), _p(sel), ns,
-            float(theta), _p(np2m), _p(np2p))
+            float(theta), _p(rel), _p(arel), _p(np2m), _p(np2p))
     if lib().or_walk_lists(*args, None, None) != 0:
         raise MemoryError("oracle walk")
     sizes = np.stack([np2m, np2p], 1).reshape(-1)
@@ -269,14 +299,19 @@ class Evaluation:
     n_p2p: int
     n_p2m: int
     n_targets: int
+    rel: np.ndarray = None   # relative test: cell records and per-group A
+    arel: np.ndarray = None
 
 
 def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
-                sys_off=None, G=1.0, sel_groups=None, tree=None):
+                sys_off=None, G=1.0, sel_groups=None, tree=None, alpha=None,
+                acc_old=None):
     """Build, moments, groups, walk and evaluation, all in the oracle.
 
     ``active``: original indices of the targets (None = all).  ``sel_groups``:
     evaluate only these group indices (None = every group with a target).
+    With ``alpha`` (and ``acc_old``, [N, 3] original order) the walk uses the
+    relative opening test instead of theta.
     Returns an :class:`Evaluation`; acc/pot are NaN for rows not evaluated.
     """
     pos = _c(pos, np.float64).reshape(-1, 3)
@@ -293,6 +328,10 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
     else:
         sel = _c(sel_groups, np.int32)
         sel = sel[nact[sel] > 0]
+    rel = arel = None
+    if alpha is not None:
+        rel = rel_records(tree, mom, G)
+        arel = group_arel(tree, g, sact, acc_old, alpha)
     sacc = np.full((n, 3), np.nan)
     spot = np.full(n, np.nan)
     counts = np.zeros(3, np.int64)
@@ -300,7 +339,8 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
         tree.nn, _p(tree.level), _p(tree.first), _p(tree.count),
         _p(tree.child), _p(tree.nchild), _p(tree.sys), _p(mom), _p(tree.cube),
         _p(g), _p(box), _p(sel), sel.shape[0], _p(spos), _p(smass), _p(sact),
-        float(eps), float(theta), float(G), _p(sacc), _p(spot), _p(counts))
+        float(eps), float(theta), _p(rel), _p(arel), float(G), _p(sacc), _p(spot),
+        _p(counts))
     if rc != 0:
         raise MemoryError("oracle tree forces")
     acc = np.full((n, 3), np.nan)
@@ -309,7 +349,7 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
     acc[p] = sacc
     pot[p] = spot
     return Evaluation(tree, mom, g, box, nact, sel, acc, pot, int(counts[0]),
-                      int(counts[1]), int(counts[2]))
+                      int(counts[1]), int(counts[2]), rel, arel)
 
 
 def direct(pos, mass, eps, targets=None, sys_off=None, xpos=None, xmass=None,

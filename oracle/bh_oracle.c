@@ -323,12 +323,77 @@ static int or_push(or_vec *a, uint32_t x) {
   return 0;
 }
 
-/* Walk one group; lists come back sorted ascending.  Root of the group's   */
-/* system: roots are the level-0 nodes in system order.                     */
+/* ---------------------------------------------------------------------- */
+/* Relative opening test (READING: the paper names a "Gadget" criterion     */
+/* with an error tolerance, Sec. 4 run set-up, but prints no formula; this  */
+/* is the relative criterion of Springel 2005, MNRAS 364, 1105, Sec. 3.1,   */
+/* taken for a group of targets).  A cell of mass M and side s is accepted  */
+/* for a target with old acceleration |a| at distance r from the cell's     */
+/* centre of mass iff G M s^2 / r^4 <= alpha |a|, and the target lies       */
+/* outside the cell's cube enlarged by 20 % about its geometric centre.     */
+/* Group form: r is the group-box distance d of the geometric test, |a| the */
+/* smallest old acceleration of the group's active targets, and the whole   */
+/* group box must miss the enlarged cube.  Squared to avoid roots:          */
+/*   P = (G M) s^2,   accept iff  P P <= A ((d^2 d^2)(d^2 d^2))  and the     */
+/*   box misses [g - h, g + h] on some axis, h = 0.6 s,                     */
+/* with A = (alpha alpha) a2min per group, a2min = min (ax ax + ay ay) + az */
+/* az.  Cell centre: g_k = lo_k + (i_k + 0.5) s from the integer cell       */
+/* coordinates i_k in the key prefix of the cell's first particle.          */
+/* rel[8 v] = {g_x - h, g_y - h, g_z - h, P, g_x + h, g_y + h, g_z + h, 0}. */
+/* ---------------------------------------------------------------------- */
+void or_rel_records(int64_t nn, const uint8_t *level, const uint32_t *first,
+                    const int32_t *sys, const uint64_t *skeys,
+                    const double *cube, const double *mom, double G,
+                    double *rel) {
+  for (int64_t v = 0; v < nn; ++v) {
+    const double *c = cube + 4 * (int64_t)sys[v];
+    int l = (int)level[v];
+    double s = ldexp(c[3], -l);
+    uint64_t pre = skeys[first[v]] >> (3 * (OR_MAXLEVEL - l));
+    uint64_t ic[3] = {0, 0, 0};
+    for (int j = 0; j < l; ++j) {          /* digit j from the bottom */
+      uint64_t d = (pre >> (3 * j)) & 7u;
+      ic[0] |= ((d >> 2) & 1u) << j;
+      ic[1] |= ((d >> 1) & 1u) << j;
+      ic[2] |= (d & 1u) << j;
+    }
+    double h = 0.6 * s;
+    double *o = rel + 8 * v;
+    for (int k = 0; k < 3; ++k) {
+      double g = c[k] + ((double)ic[k] + 0.5) * s;
+      o[k] = g - h;
+      o[4 + k] = g + h;
+    }
+    o[3] = (G * mom[10 * v]) * (s * s);
+    o[7] = 0.0;
+  }
+}
+
+static int or_rel_accept(const double *glo, const double *ghi,
+                         const double *com, const double *r, double A) {
+  double d2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double a = glo[k] - com[k];
+    double b = com[k] - ghi[k];
+    double m = a > b ? a : b;
+    if (m < 0.0) m = 0.0;
+    d2 = d2 + m * m;
+  }
+  double d4 = d2 * d2;
+  if (!(r[3] * r[3] <= A * (d4 * d4))) return 0;
+  for (int k = 0; k < 3; ++k)
+    if (glo[k] > r[4 + k] || ghi[k] < r[k]) return 1;   /* box misses the cube */
+  return 0;
+}
+
+/* Walk one group; lists come back sorted ascending.  rel == NULL: the      */
+/* geometric test with theta; else the relative test with A = arel.  Root   */
+/* of the group's system: roots are the level-0 nodes in system order.      */
 static int or_walk_one(uint32_t root, const uint8_t *level,
                        const uint32_t *child, const uint8_t *nchild,
                        const int32_t *sys, const double *mom,
                        const double *cube, const double *box, double theta,
+                       const double *rel, double arel,
                        or_vec *p2m, or_vec *p2p, or_vec *work) {
   double th2 = theta * theta;
   p2m->n = p2p->n = work->n = 0;
@@ -337,7 +402,9 @@ static int or_walk_one(uint32_t root, const uint8_t *level,
     uint32_t c = work->v[--work->n];
     double s = ldexp(cube[4 * (int64_t)sys[c] + 3], -(int)level[c]);
     const double *com = mom + 10 * (int64_t)c + 1;
-    if (or_mac_accept(box, box + 3, com, s * s, th2)) {
+    int acc = rel ? or_rel_accept(box, box + 3, com, rel + 8 * (int64_t)c, arel)
+                  : or_mac_accept(box, box + 3, com, s * s, th2);
+    if (acc) {
       if (or_push(p2m, c)) return -1;
     } else if (nchild[c] == 0) {
       if (or_push(p2p, c)) return -1;
@@ -365,6 +432,7 @@ int or_walk_lists(int64_t nn, const uint8_t *level, const uint32_t *child,
                   const uint8_t *nchild, const int32_t *sys, const double *mom,
                   const double *cube, const uint32_t *g, const double *box,
                   const int32_t *sel, int64_t nsel, double theta,
+                  const double *rel, const double *arel,
                   int64_t *np2m, int64_t *np2p, const int64_t *lofs,
                   uint32_t *ids) {
   int err = 0;
@@ -376,7 +444,9 @@ int or_walk_lists(int64_t nn, const uint8_t *level, const uint32_t *child,
       int64_t k = sel[t];
       uint32_t root = or_root_of((int32_t)g[4 * k + 3], nn, level, sys);
       if (or_walk_one(root, level, child, nchild, sys, mom, cube, box + 6 * k,
-                      theta, &p2m, &p2p, &work)) { err = 1; continue; }
+                      theta, rel, rel ? arel[k] : 0.0, &p2m, &p2p, &work)) {
+        err = 1; continue;
+      }
       np2m[t] = p2m.n; np2p[t] = p2p.n;
       if (ids) {
         memcpy(ids + lofs[2 * t], p2m.v, sizeof(uint32_t) * (size_t)p2m.n);
@@ -482,8 +552,8 @@ int or_tree_forces(int64_t nn, const uint8_t *level, const uint32_t *first,
                    const double *cube, const uint32_t *g, const double *box,
                    const int32_t *sel, int64_t nsel, const double *spos,
                    const double *smass, const uint8_t *sactive, double eps,
-                   double theta, double G, double *acc, double *pot,
-                   int64_t *counts) {
+                   double theta, const double *rel, const double *arel,
+                   double G, double *acc, double *pot, int64_t *counts) {
   int err = 0;
   int64_t npp = 0, npm = 0, ntg = 0;
 #pragma omp parallel reduction(+ : npp, npm, ntg)
@@ -494,7 +564,9 @@ int or_tree_forces(int64_t nn, const uint8_t *level, const uint32_t *first,
       int64_t k = sel[t];
       uint32_t root = or_root_of((int32_t)g[4 * k + 3], nn, level, sys);
       if (or_walk_one(root, level, child, nchild, sys, mom, cube, box + 6 * k,
-                      theta, &p2m, &p2p, &work)) { err = 1; continue; }
+                      theta, rel, rel ? arel[k] : 0.0, &p2m, &p2p, &work)) {
+        err = 1; continue;
+      }
       for (uint32_t i = g[4 * k]; i < g[4 * k] + g[4 * k + 1]; ++i) {
         if (!sactive[i]) continue;
         or_eval_target(i, spos, smass, first, count, mom, &p2m, &p2p, eps, G,
