@@ -100,7 +100,7 @@ tg_status tg_set_stream(tg_ctx *ctx, void *stream);
  * bounds as in tg_config.  Takes effect at the next tg_build_tree. */
 tg_status tg_set_sizes(tg_ctx *ctx, int32_t leaf_size, int32_t group_size);
 
-/* ---- a1..a6: cube, Morton keys, radix sort, gather, octree, groups ----
+/* ---- cube, Morton keys, radix sort, gather, octree, groups -----------
  * Builds the octree of N particles split into S independent systems, the
  * contiguous ranges sys_off_host[s] .. sys_off_host[s+1] (NULL with S = 1
  * means one system [0, N)).  One root per non-empty system; a node with
@@ -113,13 +113,13 @@ tg_status tg_set_sizes(tg_ctx *ctx, int32_t leaf_size, int32_t group_size);
 tg_status tg_build_tree(tg_ctx *ctx, const double *pos_dev, int64_t n,
                         const int64_t *sys_off_host, int32_t n_sys);
 
-/* ---- a7: monopole + quadrupole moments about each node's centre of mass
+/* ---- monopole + quadrupole moments about each node's centre of mass
  * (upward pass; leaves from their particles, internal nodes from children).
  * mass_dev: [N] doubles, caller order, each > 0 (else TG_ERR_MASS).
  * Requires a tree.  Errors: TG_ESTATE. */
 tg_status tg_compute_moments(tg_ctx *ctx, const double *mass_dev);
 
-/* ---- a6, a8..a10: group walk with the opening-angle test, P2P and P2M --
+/* ---- group walk with the opening-angle test, P2P and P2M --------------
  * Forces and potentials on the active particles from all particles of their
  * own system.  active_idx_dev: caller-order indices of the targets, int32,
  * distinct, n_active_dev[0] of them (both device; NULL active_idx_dev means
@@ -131,6 +131,32 @@ tg_status tg_tree_forces(tg_ctx *ctx, double eps, double theta,
                          const int32_t *active_idx_dev,
                          const int32_t *n_active_dev, double *acc_dev,
                          double *pot_dev);
+
+/* ---- relative opening test (alternative to the opening angle) ---------
+ * The paper's tree runs open cells with a relative ("Gadget") criterion and
+ * an error tolerance (Sec. 4, run set-up) but print no formula; this is the
+ * relative criterion of Springel 2005 (MNRAS 364, 1105, Sec. 3.1) for a
+ * group of targets: a cell of mass M and side s is accepted iff
+ *   (G M s^2)^2 <= alpha^2 min|a_old|^2 d^8
+ * with d the distance from the group's box of active targets to the cell's
+ * centre of mass and the minimum over those targets, and the box misses the
+ * cell's cube enlarged by 20 % about its geometric centre (the cube with
+ * corner lo + i s for integer cell coordinates i).  All in FP64 with every
+ * operation rounded separately.
+ * kind TG_MAC_GEOMETRIC (the default) restores the opening angle;
+ * TG_MAC_RELATIVE makes every later tg_tree_forces, tg_walk_lists and
+ * tg_forces (hence the steps) use it with tolerance alpha (finite, >= 0;
+ * the paper's runs use 1e-3) and theta is ignored.  acc_old_dev: [N][3]
+ * doubles, caller order, finite, read at walk time (before any output row
+ * is written, so it may be the acc_dev of the same call); NULL makes
+ * tg_forces use the system's acc and tg_tree_forces / tg_walk_lists fail
+ * with TG_ESTATE.  A zero old acceleration opens every cell of its group
+ * (the first evaluation of a run should use the opening angle).
+ * Errors: TG_EINVAL. */
+#define TG_MAC_GEOMETRIC 0
+#define TG_MAC_RELATIVE 1
+tg_status tg_set_mac(tg_ctx *ctx, int32_t kind, double alpha,
+                     const double *acc_old_dev);
 
 /* Interaction counts (synchronises the stream).  out[0..3] for the last
  * tg_tree_forces: P2P pairs (target, source particle, j != i), particle-cell
@@ -153,7 +179,7 @@ tg_status tg_walk_lists(tg_ctx *ctx, double theta,
                         int64_t cap_groups, uint32_t *ids_dev, int64_t cap_ids,
                         int64_t *n_groups_out, int64_t *n_ids_out);
 
-/* ---- a11: double-precision direct forces (SMBH <-> stars, perturber <->
+/* ---- double-precision direct forces (SMBH <-> stars, perturber <->
  * chain members; Sec. 2).  Targets [nt] at tgt_pos_dev with softening
  * tgt_eps_dev feel sources [ns] (src_pos_dev, src_mass_dev, src_eps_dev)
  * with pair softening max(eps_i, eps_j).  With segments (nseg > 0,
@@ -171,7 +197,7 @@ tg_status tg_direct_fp64(tg_ctx *ctx, const double *src_pos_dev,
                          int32_t self_pairs, int32_t accumulate,
                          double *acc_dev, double *pot_dev);
 
-/* ---- a12: leapfrog (kick-drift-kick) and block time-steps -------------
+/* ---- leapfrog (kick-drift-kick) and block time-steps ------------------
  * kick: v += a h for the listed particles (all n when active_idx_dev is
  * NULL; then n_active_dev is ignored and n gives the count).  h = dt / 2,
  * or with level_dev != NULL, h = (dt * 2^-level_i) / 2 with dt = dt_max.
@@ -216,7 +242,7 @@ tg_status tg_active_set(tg_ctx *ctx, const uint8_t *level_dev, int64_t n,
 /* k_dev[0] += inc (device-side substep counter for replayed graphs). */
 tg_status tg_counter_add(tg_ctx *ctx, int64_t *k_dev, int64_t inc);
 
-/* ---- a11 inside the walk: SMBHs as external point masses ----------------
+/* ---- direct forces inside the walk: SMBHs as external point masses ----
  * Register n_ext point masses (device arrays pos [n_ext][3], mass, eps) whose
  * FP64 Plummer force, pair softening max(eps, eps_ext), every later
  * tg_tree_forces adds to each target of the same system (seg_host [n_sys+1]
@@ -228,7 +254,7 @@ tg_status tg_set_external(tg_ctx *ctx, const double *pos_dev,
                           const double *mass_dev, const double *eps_dev,
                           int32_t n_ext, const int64_t *seg_host, int32_t n_sys);
 
-/* ---- whole steps (a1..a12 in one call; capturable) ---------------------- */
+/* ---- whole steps (every stage above in one call; capturable) ---------- */
 typedef struct {
   double *pos, *vel, *acc, *pot;   /* stars [n][3], pot [n] may be NULL */
   const double *mass;              /* [n] */
@@ -239,7 +265,7 @@ typedef struct {
   const double *bh_mass, *bh_eps;              /* [n_bh] */
   int32_t n_bh;
   const int64_t *bh_seg;           /* host [n_sys+1]: SMBHs of each system */
-  double eps, theta;               /* star softening, opening angle */
+  double eps, theta;               /* star softening, opening angle (see tg_set_mac) */
 } tg_system;
 
 /* Forces for the listed stars (all when active_idx_dev is NULL): tree +
@@ -275,7 +301,7 @@ typedef struct {
  * captured substep can be replayed. */
 tg_status tg_step_block(tg_ctx *ctx, const tg_system *sys, const tg_blocks *blocks);
 
-/* ---- a13: HIP graphs over any sequence of the calls above ------------- */
+/* ---- HIP graphs over any sequence of the calls above ------------------ */
 typedef struct tg_graph tg_graph;
 tg_status tg_graph_begin(tg_ctx *ctx);
 tg_status tg_graph_end(tg_ctx *ctx, tg_graph **out);

@@ -254,7 +254,7 @@ def group_arel(tree: Tree, g, sactive, acc_old, alpha: float) -> np.ndarray:
     a2 = np.where(np.asarray(sactive, bool), a2, np.inf)
     m = np.minimum.reduceat(a2, g[:, 0].astype(np.int64))
     aa = float(alpha) * float(alpha)
-    return np.where(np.isfinite(m), aa * m, 0.0)
+    return aa * np.where(np.isfinite(m), m, 0.0)
 
 
 def walk_lists(tree: Tree, mom, g, box, sel, theta: float, rel=None, arel=None):

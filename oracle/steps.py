@@ -3,7 +3,9 @@
 Composes the oracle's primitives in the order of the paper's hybrid step
 (Sec. 2, steps (1), (6), (7)), read as kick-drift-kick:
 
-* forces: tree forces on the listed stars plus the FP64 Plummer force of the
+* forces: tree forces on the listed stars (opening angle, or with ``alpha``
+  the relative test against the stars' current accelerations) plus the FP64
+  Plummer force of the
   SMBHs of the star's system (pair softening max(eps_star, eps_bh)); every
   SMBH feels all stars of its system and the other SMBHs (Sec. 2, the
   perturber / chain force-correction paragraph).
@@ -38,6 +40,7 @@ class State:
     bh_seg: np.ndarray
     leaf_size: int = 8
     group_size: int = 64
+    alpha: float = None      # relative opening test (None: opening angle theta)
     acc: np.ndarray = field(default=None)
     pot: np.ndarray = field(default=None)
     bh_acc: np.ndarray = field(default=None)
@@ -57,8 +60,9 @@ def forces(st: State, active=None):
     """Tree + SMBH forces for the listed stars; SMBH forces for all SMBHs."""
     n = st.pos.shape[0]
     S = st.sys_off.shape[0] - 1
+    rel = {} if st.alpha is None else {"alpha": st.alpha, "acc_old": st.acc.copy()}
     ev = oracle.tree_forces(st.pos, st.mass, st.eps, st.theta, st.leaf_size,
-                            st.group_size, active=active, sys_off=st.sys_off)
+                            st.group_size, active=active, sys_off=st.sys_off, **rel)
     rows = np.arange(n) if active is None else np.asarray(active, np.int64)
     st.acc[rows] = ev.acc[rows]
     st.pot[rows] = ev.pot[rows]

@@ -94,6 +94,7 @@ def lib():
             "tg_active_set": (st, [P, P, i64, i32, P, i32, P, P]),
             "tg_counter_add": (st, [P, P, i64]),
             "tg_set_external": (st, [P, P, P, P, i32, P, i32]),
+            "tg_set_mac": (st, [P, i32, f64, P]),
             "tg_forces": (st, [P, P, P, P]),
             "tg_step_kdk": (st, [P, P, f64]),
             "tg_step_dkd": (st, [P, P, f64]),
@@ -123,7 +124,8 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_set_sizes", "tg_build_tree", "tg_compute_moments",
             "tg_tree_forces", "tg_get_counts", "tg_reset_counts", "tg_walk_lists",
             "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
-            "tg_active_set", "tg_counter_add", "tg_set_external", "tg_forces",
+            "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac",
+            "tg_forces",
             "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
@@ -216,7 +218,7 @@ class Context:
     def set_sizes(self, leaf_size, group_size):
         _check(lib().tg_set_sizes(self.h, int(leaf_size), int(group_size)))
 
-    # -- a1..a7
+    # -- tree build and moments
     def build_tree(self, pos, sys_off=None):
         n = pos.shape[0]
         arr, p = _i64_host(sys_off)
@@ -246,6 +248,13 @@ class Context:
     def reset_counts(self):
         _check(lib().tg_reset_counts(self.h))
 
+    def set_mac(self, relative=False, alpha=0.0, acc_old=None):
+        """Opening test of later walks: the opening angle (default), or the
+        relative test with tolerance alpha and old accelerations acc_old
+        ([N, 3] device, caller order; None = the system's acc in forces)."""
+        _check(lib().tg_set_mac(self.h, 1 if relative else 0, float(alpha),
+                                _ptr(acc_old)))
+
     def walk_lists(self, theta, active_idx=None, n_active=None):
         """(info [ng, 4] int64, ids uint32) as numpy; see tg_walk_lists."""
         import torch
@@ -264,7 +273,7 @@ class Context:
         return (info[:ng.value].cpu().numpy(),
                 ids[:ni.value].cpu().numpy().view(np.uint32))
 
-    # -- a11
+    # -- FP64 direct forces
     def direct_fp64(self, src_pos, src_mass, src_eps, tgt_pos, tgt_eps, acc, pot=None,
                     src_seg=None, tgt_seg=None, self_pairs=False, accumulate=False):
         sa, sp = _i64_host(src_seg)
@@ -275,7 +284,7 @@ class Context:
                                     tgt_pos.shape[0], sp, tp, nseg, int(bool(self_pairs)),
                                     int(bool(accumulate)), _ptr(acc), _ptr(pot)))
 
-    # -- a12
+    # -- leapfrog and block steps
     def kick(self, vel, acc, dt, active_idx=None, n_active=None, level=None, k=None,
              skip_at_k0=False):
         _check(lib().tg_kick(self.h, _ptr(vel), _ptr(acc), vel.shape[0], _ptr(active_idx),
@@ -348,7 +357,7 @@ class Context:
     def step_block(self, system, blocks):
         _check(lib().tg_step_block(self.h, C.byref(system), C.byref(blocks)))
 
-    # -- a13
+    # -- HIP graphs
     def graph_begin(self):
         _check(lib().tg_graph_begin(self.h))
 

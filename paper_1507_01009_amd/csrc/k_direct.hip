@@ -1,4 +1,4 @@
-// a11: double-precision direct forces between a source set and a target set
+// Double-precision direct forces between a source set and a target set
 // (SMBH <-> stars; perturber <-> chain-member corrections), Plummer
 // softening max(eps_i, eps_j) per pair.
 //

@@ -1,4 +1,4 @@
-// a12: kick-drift-kick leapfrog and power-of-two block time-steps.
+// Kick-drift-kick leapfrog and power-of-two block time-steps.
 //
 // Element-wise double arithmetic with no contraction, in the order of the
 // plain definition, so kick, drift and level decisions are bit-identical to

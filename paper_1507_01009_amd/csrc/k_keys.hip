@@ -1,4 +1,4 @@
-// a1-a4: bounding cube per system, 21-bit Morton keys, stable LSD radix sort
+// Bounding cube per system, 21-bit Morton keys, stable LSD radix sort
 // of (key, index), and the gather of positions into sorted order.
 //
 // Work is cut into tiles of kSortTile consecutive particles that never cross

@@ -1,4 +1,4 @@
-// a5-a6: octree over the sorted keys, all levels at once, and the walk groups.
+// Octree over the sorted keys, all levels at once, and the walk groups.
 //
 // d[i] = number of equal leading key digits of sorted particles i-1 and i
 // (0 at the first particle of every system and at the end, 21 for equal

@@ -1,4 +1,4 @@
-// a6, a8-a10: active groups, the group tree walk with the opening-angle
+// Active groups, the group tree walk with the opening-angle
 // test, and the softened P2P / quadrupole P2M force sums.
 //
 // One 64-lane wavefront owns one group of targets at a time (persistent
@@ -6,7 +6,10 @@
 // wave tests 64 frontier cells at once against the group's box,
 //   accept iff side^2 < theta^2 d^2,  d = box-to-centre-of-mass distance,
 // evaluated in double precision with no contraction (bit-identical decisions
-// to the plain definition).  Ballot + mbcnt compaction appends accepted
+// to the plain definition).  A second mode replaces it by the relative
+// test (G M s^2 / d^4 <= alpha min|a_old|, group box outside the cell cube
+// enlarged by 20 %; the paper's "Gadget" criterion, Sec. 4 run set-up, in
+// the form of Springel 2005, Sec. 3.1).  Ballot + mbcnt compaction appends accepted
 // cells to an LDS P2M list and the particles of refused leaves to an LDS
 // P2P queue; refused internal cells push their children onto the next
 // frontier (wave prefix sum of child counts).  Whenever a list holds a full
@@ -61,6 +64,8 @@ constexpr int kQCap = 128 + 64 * 8;         // P2P particle queue (LDS); overflo
 struct WalkArgs {
   const uint4 *ninfo;       // {first, count, child, nchild} per node
   const double4 *com;
+  const double4 *rel;       // relative test: per node {lo, P}, {hi, 0} (enlarged cube)
+  const double *arel;       // relative test: per group (alpha alpha) min |a_old|^2
   const void *cell;         // walk records per node (float4[2] mixed, double4[2] FP64)
   const double4 *spart;
   const uint32_t *root_of;
@@ -101,12 +106,12 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t &tot) {
   return x - v;
 }
 
-// Opening-angle test, the same operations in the same order as the plain
-// definition: d^2 = sum_k max(max(lo_k - c_k, c_k - hi_k), 0)^2, accept iff
-// side^2 < theta^2 * d^2.  fmax (one v_max_f64) equals the compare-and-
-// select of the definition for the finite inputs the build guarantees.
-__device__ __forceinline__ bool mac_accept(const double lo[3], const double hi[3],
-                                           double4 c, double th2) {
+// Squared distance from the group box to the centre of mass, the same
+// operations in the same order as the plain definition: d^2 = sum_k
+// max(max(lo_k - c_k, c_k - hi_k), 0)^2.  fmax (one v_max_f64) equals the
+// compare-and-select of the definition for the finite inputs the build
+// guarantees.
+__device__ __forceinline__ double box_d2(const double lo[3], const double hi[3], double4 c) {
 #pragma clang fp contract(off)
   double d2 = 0.0;
   {
@@ -124,7 +129,26 @@ __device__ __forceinline__ bool mac_accept(const double lo[3], const double hi[3
     const double m = fmax(fmax(a, b), 0.0);
     d2 = __dadd_rn(d2, __dmul_rn(m, m));
   }
-  return c.w < __dmul_rn(th2, d2);
+  return d2;
+}
+
+// Opening-angle test: accept iff side^2 < theta^2 d^2 (c.w = side^2).
+__device__ __forceinline__ bool mac_accept(const double lo[3], const double hi[3],
+                                           double4 c, double th2) {
+  return c.w < __dmul_rn(th2, box_d2(lo, hi, c));
+}
+
+// Relative test: accept iff P P <= A (d^2 d^2)(d^2 d^2), P = (G M) s^2,
+// A = (alpha alpha) min |a_old|^2 of the group, and the box misses the
+// enlarged cube [r0.xyz, r1.xyz] on some axis (touching counts as a hit).
+__device__ __forceinline__ bool mac_rel(const double lo[3], const double hi[3], double4 c,
+                                        double4 r0, double4 r1, double A) {
+  const double d2 = box_d2(lo, hi, c);
+  const double d4 = __dmul_rn(d2, d2);
+  const bool near = __dmul_rn(r0.w, r0.w) <= __dmul_rn(A, __dmul_rn(d4, d4));
+  const bool apart = lo[0] > r1.x || hi[0] < r0.x || lo[1] > r1.y || hi[1] < r0.y ||
+                     lo[2] > r1.z || hi[2] < r0.z;
+  return near && apart;
 }
 
 // 1/sqrt(x) in double: hardware estimate, then one third-order Householder
@@ -447,9 +471,9 @@ struct FillSink {
 // ---------------------------------------------------------- traversal
 // Breadth-first walk of the group's system tree.  Returns false if the
 // frontier overflowed (the group's results are then invalid).
-template <class Sink>
+template <bool kRel, class Sink>
 __device__ bool traverse(const WalkArgs &A, Sink &sink, uint32_t root,
-                         const double lo[3], const double hi[3]) {
+                         const double lo[3], const double hi[3], double arel) {
   const unsigned lane = lane_id();
   uint32_t *cur = A.frontier + (size_t)blockIdx.x * 2 * A.fcap;
   uint32_t *nxt = cur + A.fcap;
@@ -469,7 +493,10 @@ __device__ bool traverse(const WalkArgs &A, Sink &sink, uint32_t root,
         const double4 c = A.com[node];
         const uint4 nf = A.ninfo[node];
         f = nf.x; cnt = nf.y; ch = nf.z; nch = nf.w;
-        acc = mac_accept(lo, hi, c, A.th2);
+        if constexpr (kRel)
+          acc = mac_rel(lo, hi, c, A.rel[2 * (size_t)node], A.rel[2 * (size_t)node + 1], arel);
+        else
+          acc = mac_accept(lo, hi, c, A.th2);
       }
       const bool leaf = valid && !acc && nch == 0;
       const bool open = valid && !acc && nch > 0;
@@ -531,7 +558,7 @@ struct GroupQueue {
 };
 
 // ------------------------------------------------------------ force kernel
-template <bool kMixed>
+template <bool kMixed, bool kRel>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMixed ? TG_WALK_WAVES_MIXED : TG_WALK_WAVES_FP64)))
 void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
@@ -599,7 +626,7 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
       S.tx[k] = (R)(p.x - S.cgx); S.ty[k] = (R)(p.y - S.cgy); S.tz[k] = (R)(p.z - S.cgz);
       S.hax[k] = S.hay[k] = S.haz[k] = S.hph[k] = 0.0;
     }
-    const bool ok = traverse(A, S, A.root_of[gr.w], lo, hi);
+    const bool ok = traverse<kRel>(A, S, A.root_of[gr.w], lo, hi, kRel ? A.arel[g] : 0.0);
     // per-lane totals -> LDS, [k][lane][4]
     double *red = tile.red;
 #pragma unroll
@@ -664,7 +691,7 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
 // -------------------------------------------------------- list kernels
 // pass 0: sizes per active group into wl_count[2 gi + {0,1}];
 // pass 1: ids at the offsets wl_off (exclusive scan of wl_count).
-template <int kPass>
+template <int kPass, bool kRel>
 __global__ __launch_bounds__(64) void k_walk_lists(WalkArgs A) {
   const uint32_t n_groups = A.ctr->n_active_groups;
   GroupQueue Q(blockIdx.x);
@@ -675,11 +702,12 @@ __global__ __launch_bounds__(64) void k_walk_lists(WalkArgs A) {
     const uint4 gr = A.groups[g];
     double lo[3], hi[3];
     for (int k = 0; k < 3; ++k) { lo[k] = A.abox[6 * (size_t)g + k]; hi[k] = A.abox[6 * (size_t)g + 3 + k]; }
+    const double arel = kRel ? A.arel[g] : 0.0;
     if constexpr (kPass == 0) {
       // the fill pass repeats this walk exactly (also up to a frontier
       // overflow), so these counts bound what it writes
       CountSink S;
-      traverse(A, S, A.root_of[gr.w], lo, hi);
+      traverse<kRel>(A, S, A.root_of[gr.w], lo, hi, arel);
       if (lane_id() == 0) {
         A.wl_count[2 * (size_t)gi] = S.nm;
         A.wl_count[2 * (size_t)gi + 1] = S.np;
@@ -688,7 +716,7 @@ __global__ __launch_bounds__(64) void k_walk_lists(WalkArgs A) {
       FillSink S;
       S.base_m = A.wl_off[2 * (size_t)gi];
       S.base_p = A.wl_off[2 * (size_t)gi + 1];
-      traverse(A, S, A.root_of[gr.w], lo, hi);
+      traverse<kRel>(A, S, A.root_of[gr.w], lo, hi, arel);
     }
     __syncthreads();
   }
@@ -726,13 +754,20 @@ __device__ __forceinline__ double qmax(double v) {
 
 // Sixteen lanes per group (a group holds at most kMaxGroup particles):
 // flag groups with an active particle and store the box of their active
-// particles.
+// particles.  With old accelerations (caller order, reached through perm)
+// also the relative test's group threshold (alpha alpha) min |a_old|^2,
+// |a|^2 = (ax ax + ay ay) + az az unfused.
 __global__ __launch_bounds__(256) void k_group_active(const int32_t *__restrict__ gate, const TreeCounters *ctr,
                                                       const uint4 *__restrict__ groups,
                                                       const uint8_t *__restrict__ sact,
                                                       const double4 *__restrict__ spart,
+                                                      const double *__restrict__ acc_old,
+                                                      const uint32_t *__restrict__ perm,
+                                                      double alpha2,
                                                       uint32_t *__restrict__ aflag,
-                                                      double *__restrict__ abox) {
+                                                      double *__restrict__ abox,
+                                                      double *__restrict__ arel) {
+#pragma clang fp contract(off)
   if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t ng = ctr->n_groups;
   const unsigned q = threadIdx.x & 15u;
@@ -743,6 +778,7 @@ __global__ __launch_bounds__(256) void k_group_active(const int32_t *__restrict_
     const uint4 gr = live ? groups[g] : make_uint4(0, 0, 0, 0);
     double lx = INFINITY, ly = INFINITY, lz = INFINITY;
     double hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+    double a2min = INFINITY;
     bool any = false;
 #pragma unroll
     for (int r = 0; r < kMaxGroup / 16; ++r) {
@@ -753,16 +789,24 @@ __global__ __launch_bounds__(256) void k_group_active(const int32_t *__restrict_
         lx = fmin(lx, p.x); ly = fmin(ly, p.y); lz = fmin(lz, p.z);
         hx = fmax(hx, p.x); hy = fmax(hy, p.y); hz = fmax(hz, p.z);
         any = true;
+        if (acc_old) {
+          const double *ao = acc_old + 3 * (size_t)perm[gr.x + j];
+          const double a2 = __dadd_rn(__dadd_rn(__dmul_rn(ao[0], ao[0]), __dmul_rn(ao[1], ao[1])),
+                                      __dmul_rn(ao[2], ao[2]));
+          a2min = fmin(a2min, a2);
+        }
       }
     }
     lx = qmin(lx); ly = qmin(ly); lz = qmin(lz);
     hx = qmax(hx); hy = qmax(hy); hz = qmax(hz);
+    if (acc_old) a2min = qmin(a2min);
     const unsigned long long m = __ballot(any);
     const unsigned long long mine = (m >> (threadIdx.x & 48u)) & 0xffffull;
     if (live && q == 0) {
       aflag[g] = mine ? 1u : 0u;
       double *b = abox + 6 * (size_t)g;
       b[0] = lx; b[1] = ly; b[2] = lz; b[3] = hx; b[4] = hy; b[5] = hz;
+      if (acc_old) arel[g] = mine ? __dmul_rn(alpha2, a2min) : 0.0;
     }
   }
 }
@@ -803,7 +847,8 @@ __global__ void k_walk_reset(TreeCounters *ctr) {
 }
 
 hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
-                                const int32_t *n_act) {
+                                const int32_t *n_act, const double *acc_old,
+                                double alpha) {
   Buffers &b = c->b;
   if (c->n == 0) return fill_u32(&b.ctr->n_active_groups, 0u, 1, c->stream);
   hipError_t e = fill_u8(b.sact, 0, c->n, c->stream, c->gate);
@@ -813,7 +858,8 @@ hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
   hipLaunchKernelGGL(k_mark_active, dim3(g), dim3(256), 0, c->stream, c->gate, idx,
                      n_act, c->n, b.rank, b.sact);
   hipLaunchKernelGGL(k_group_active, dim3(2048), dim3(256), 0, c->stream, c->gate,
-                     b.ctr, b.groups, b.sact, b.spart, b.aflag, b.abox);
+                     b.ctr, b.groups, b.sact, b.spart, acc_old, b.val[0], alpha * alpha,
+                     b.aflag, b.abox, b.arel);
   // the group-start scan buffer is free after the build: reuse it
   e = scan_u32(b.aflag, b.gflag, 0u, &b.ctr->n_groups, &b.ctr->n_active_groups,
                b.scan_part, c->stream, c->gate);
@@ -827,6 +873,7 @@ static WalkArgs make_args(tg_ctx *c, double theta) {
   Buffers &b = c->b;
   WalkArgs A;
   A.ninfo = b.ninfo; A.com = b.com; A.cell = b.cell;
+  A.rel = b.rel; A.arel = b.arel;
   A.spart = b.spart; A.root_of = b.root_of;
   A.groups = b.groups; A.alist = b.alist; A.abox = b.abox; A.sact = b.sact;
   A.perm = b.val[0]; A.ctr = b.ctr; A.err = b.err; A.frontier = b.frontier;
@@ -863,13 +910,74 @@ __global__ __launch_bounds__(256) void k_cell_records(const int32_t *__restrict_
   }
 }
 
+// Relative-test records of every node: the cell cube enlarged by 20 %
+// about its geometric centre and P = (G M) s^2.  The centre comes from the
+// integer cell coordinates in the key prefix of the node's first particle:
+// g_k = lo_k + (i_k + 0.5) s, s = L 2^-level, every operation rounded
+// separately (no contraction).
+__global__ __launch_bounds__(256) void k_rel_records(const int32_t *__restrict__ gate,
+                                                     const TreeCounters *ctr,
+                                                     const uint8_t *__restrict__ level,
+                                                     const uint32_t *__restrict__ first,
+                                                     const uint32_t *__restrict__ nsys,
+                                                     const uint64_t *__restrict__ skey,
+                                                     const double *__restrict__ cube,
+                                                     const double *__restrict__ mom, double G,
+                                                     double4 *__restrict__ rel) {
+#pragma clang fp contract(off)
+  if (gate && *gate <= 0) return;   // nothing active: skipped
+  const uint32_t nn = ctr->n_nodes;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
+       v += gridDim.x * blockDim.x) {
+    const int l = level[v];
+    const double *cb = cube + 4 * (size_t)nsys[v];
+    const double s = ldexp(cb[3], -l);
+    const uint64_t pre = l ? skey[first[v]] >> (3 * (kMaxLevel - l)) : 0ull;
+    uint32_t ic[3] = {0u, 0u, 0u};
+    for (int j = 0; j < l; ++j) {
+      const uint32_t d = (uint32_t)(pre >> (3 * j)) & 7u;
+      ic[0] |= ((d >> 2) & 1u) << j;
+      ic[1] |= ((d >> 1) & 1u) << j;
+      ic[2] |= (d & 1u) << j;
+    }
+    const double h = __dmul_rn(0.6, s);
+    double lo[3], hi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double g = __dadd_rn(cb[k], __dmul_rn(__dadd_rn((double)ic[k], 0.5), s));
+      lo[k] = __dsub_rn(g, h);
+      hi[k] = __dadd_rn(g, h);
+    }
+    const double P = __dmul_rn(__dmul_rn(G, mom[8 * (size_t)v]), __dmul_rn(s, s));
+    rel[2 * (size_t)v] = make_double4(lo[0], lo[1], lo[2], P);
+    rel[2 * (size_t)v + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
+  }
+}
+
+static hipError_t launch_rel_records(tg_ctx *c) {
+  Buffers &b = c->b;
+  hipLaunchKernelGGL(k_rel_records, dim3(1024), dim3(256), 0, c->stream, c->gate, b.ctr,
+                     b.level, b.first, b.nsys, b.key[0], b.cube, b.mom, c->cfg.G, b.rel);
+  return hipGetLastError();
+}
+
 static int walk_grid(tg_ctx *c) {
   return std::max(1, c->n_cu * c->waves_per_cu);
 }
 
+template <bool kRel>
+static void launch_force_kernel(tg_ctx *c, const WalkArgs &A) {
+  if (c->cfg.precision == TG_MIXED)
+    hipLaunchKernelGGL((k_walk_forces<true, kRel>), dim3(walk_grid(c)), dim3(64), 0,
+                       c->stream, c->gate, A);
+  else
+    hipLaunchKernelGGL((k_walk_forces<false, kRel>), dim3(walk_grid(c)), dim3(64), 0,
+                       c->stream, c->gate, A);
+}
+
 hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
                               double *acc, double *pot, hipEvent_t before,
-                              hipEvent_t after) {
+                              hipEvent_t after, bool rel) {
   WalkArgs A = make_args(c, theta);
   A.eps2 = eps * eps;
   A.eps = eps;
@@ -881,17 +989,19 @@ hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
   else
     hipLaunchKernelGGL(k_cell_records<double>, dim3(1024), dim3(256), 0, c->stream, c->gate, c->b.ctr,
                        c->b.mom, A.eps2, (void *)c->b.cell);
+  if (rel) {
+    hipError_t e = launch_rel_records(c);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, c->stream, c->b.ctr);
   if (before) {
     hipError_t e = hipEventRecord(before, c->stream);
     if (e != hipSuccess) return e;
   }
-  if (c->cfg.precision == TG_MIXED)
-    hipLaunchKernelGGL(k_walk_forces<true>, dim3(walk_grid(c)), dim3(64), 0,
-                       c->stream, c->gate, A);
+  if (rel)
+    launch_force_kernel<true>(c, A);
   else
-    hipLaunchKernelGGL(k_walk_forces<false>, dim3(walk_grid(c)), dim3(64), 0,
-                       c->stream, c->gate, A);
+    launch_force_kernel<false>(c, A);
   if (after) {
     hipError_t e = hipEventRecord(after, c->stream);
     if (e != hipSuccess) return e;
@@ -900,17 +1010,25 @@ hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
 }
 
 hipError_t launch_walk_lists(tg_ctx *c, double theta, int pass, int64_t *info,
-                             int64_t cap_groups, uint32_t *ids, int64_t cap_ids) {
+                             int64_t cap_groups, uint32_t *ids, int64_t cap_ids,
+                             bool rel) {
   (void)info; (void)cap_groups; (void)cap_ids;
   WalkArgs A = make_args(c, theta);
   A.ids = ids;
+  if (rel && pass == 0) {
+    hipError_t e = launch_rel_records(c);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, c->stream, c->b.ctr);
-  if (pass == 0)
-    hipLaunchKernelGGL(k_walk_lists<0>, dim3(walk_grid(c)), dim3(64), 0,
-                       c->stream, A);
+  const dim3 grid(walk_grid(c));
+  if (pass == 0 && !rel)
+    hipLaunchKernelGGL((k_walk_lists<0, false>), grid, dim3(64), 0, c->stream, A);
+  else if (pass == 0)
+    hipLaunchKernelGGL((k_walk_lists<0, true>), grid, dim3(64), 0, c->stream, A);
+  else if (!rel)
+    hipLaunchKernelGGL((k_walk_lists<1, false>), grid, dim3(64), 0, c->stream, A);
   else
-    hipLaunchKernelGGL(k_walk_lists<1>, dim3(walk_grid(c)), dim3(64), 0,
-                       c->stream, A);
+    hipLaunchKernelGGL((k_walk_lists<1, true>), grid, dim3(64), 0, c->stream, A);
   return hipGetLastError();
 }
 

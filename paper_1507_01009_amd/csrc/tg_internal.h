@@ -78,6 +78,7 @@ struct Buffers {
   double4 *com = nullptr;
   double *mom = nullptr;          // [nodes][8]
   uint4 *ninfo = nullptr;         // [nodes] {first, count, child, nchild} for the walk
+  double4 *rel = nullptr;         // [nodes][2] relative test {enlarged cube lo, (G M) s^2} {hi, 0}
   double4 *cell = nullptr;        // [nodes][2] walk records {Qxx,Qyy,Qzz,-T eps^2} {Qxy,Qxz,Qyz,M}
                                   // (FP64; the mixed path uses the first half as float4[nodes][2])
   uint8_t *lcp = nullptr;         // [N + 64] common leading digits with predecessor
@@ -93,6 +94,7 @@ struct Buffers {
   uint32_t *aflag = nullptr;      // [N + 1] active-group flags / scan
   uint32_t *alist = nullptr;      // [N] active group ids
   double *abox = nullptr;         // [N][6] box of active targets per group
+  double *arel = nullptr;         // [N] relative test: (alpha alpha) min |a_old|^2 per group
   uint8_t *sact = nullptr;        // [N] active flag per sorted particle
   // walk
   uint32_t *frontier = nullptr;   // [waves][2][frontier_cap]
@@ -126,6 +128,11 @@ struct tg_ctx {
   // device count that gates the build, moments and walk kernels (they
   // return at once when it is <= 0: no active particle); null = always run
   const int32_t *gate = nullptr;
+  // opening test of the walk: TG_MAC_GEOMETRIC, or TG_MAC_RELATIVE with
+  // alpha and the old accelerations (null: the system's acc in tg_forces)
+  int32_t mac = 0;
+  double alpha = 0.0;
+  const double *acc_old = nullptr;
   // masses gathered into the sorted particles by the last build (or null)
   const double *mass_gathered = nullptr;
   int64_t n_tiles = 0;
@@ -190,15 +197,18 @@ hipError_t launch_groups(tg_ctx *c);
 hipError_t launch_moments(tg_ctx *c, const double *mass, bool gathered);
 
 // k_walk.hip
+// acc_old != nullptr: also the relative test's per-group thresholds
 hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
-                                const int32_t *n_act);
+                                const int32_t *n_act, const double *acc_old,
+                                double alpha);
+// rel: relative opening test (needs launch_active_groups with acc_old)
 hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
                               double *acc, double *pot, hipEvent_t before,
-                              hipEvent_t after);
+                              hipEvent_t after, bool rel);
 hipError_t launch_counts_reset(tg_ctx *c);
 hipError_t launch_walk_lists(tg_ctx *c, double theta, int pass,
                              int64_t *info, int64_t cap_groups, uint32_t *ids,
-                             int64_t cap_ids);
+                             int64_t cap_ids, bool rel);
 
 // k_direct.hip
 hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,

@@ -136,7 +136,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.first, NN)); A(dalloc(&b.count, NN)); A(dalloc(&b.child, NN));
   A(dalloc(&b.parent, NN)); A(dalloc(&b.nsys, NN));
   A(dalloc(&b.com, NN)); A(dalloc(&b.mom, 8 * NN));
-  A(dalloc(&b.ninfo, NN)); A(dalloc(&b.cell, 2 * NN));
+  A(dalloc(&b.ninfo, NN)); A(dalloc(&b.cell, 2 * NN)); A(dalloc(&b.rel, 2 * NN));
   c->flat_tiles = (N + 255) / 256;
   A(dalloc(&b.lcp, N + 64));
   A(dalloc(&b.fl_lt, std::max<int64_t>(N, 1)));
@@ -148,7 +148,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.groups, N));
   A(dalloc(&b.aflag, N + 1));
   A(dalloc(&b.alist, N));
-  A(dalloc(&b.abox, 6 * N));
+  A(dalloc(&b.abox, 6 * N)); A(dalloc(&b.arel, N));
   A(dalloc(&b.sact, N));
   A(dalloc(&b.frontier, waves * 2 * (int64_t)cfg.frontier_cap));
   A(dalloc(&b.wl_count, 2 * N + 2));
@@ -303,17 +303,31 @@ static tg_status check_walk_args(tg_ctx *c, double theta, const int32_t *idx,
                                  const int32_t *n_act, const char *who) {
   if (!c) return fail(TG_EINVAL, std::string(who) + ": NULL context");
   if (!c->have_moments) return fail(TG_ESTATE, std::string(who) + ": no tree/moments");
-  if (!(theta >= 0.0) || !(theta * theta * 3.0 < 1.0))
+  if (c->mac == TG_MAC_GEOMETRIC && (!(theta >= 0.0) || !(theta * theta * 3.0 < 1.0)))
     return fail(TG_EINVAL, std::string(who) + ": theta must be in [0, 1/sqrt(3))");
   if (idx && !n_act) return fail(TG_EINVAL, std::string(who) + ": n_active required");
   return TG_OK;
 }
 
-tg_status tg_tree_forces(tg_ctx *c, double eps, double theta,
-                         const int32_t *idx, const int32_t *n_act, double *acc,
-                         double *pot) {
+// Old accelerations of the relative test for a walk (nullptr: the opening-
+// angle test); sys_acc stands in when the context holds none.
+static tg_status mac_acc_old(tg_ctx *c, const double *sys_acc, const char *who,
+                             const double **out) {
+  *out = nullptr;
+  if (c->mac != TG_MAC_RELATIVE) return TG_OK;
+  *out = c->acc_old ? c->acc_old : sys_acc;
+  if (!*out && c->n > 0)
+    return fail(TG_ESTATE, std::string(who) + ": relative test without old accelerations");
+  return TG_OK;
+}
+
+static tg_status tree_forces_impl(tg_ctx *c, double eps, double theta,
+                                  const int32_t *idx, const int32_t *n_act, double *acc,
+                                  double *pot, const double *sys_acc) {
   tg_status st = check_walk_args(c, theta, idx, n_act, "tg_tree_forces");
   if (st != TG_OK) return st;
+  const double *aold = nullptr;
+  if ((st = mac_acc_old(c, sys_acc, "tg_tree_forces", &aold)) != TG_OK) return st;
   if (!(eps > 0.0) || !std::isfinite(eps))
     return fail(TG_EINVAL, "tg_tree_forces: eps must be positive");
   if (c->n > 0 && !acc) return fail(TG_EINVAL, "tg_tree_forces: NULL acc");
@@ -325,7 +339,7 @@ tg_status tg_tree_forces(tg_ctx *c, double eps, double theta,
     Gate(tg_ctx *c_, const int32_t *g) : c(c_), saved(c_->gate) { if (g) c->gate = g; }
     ~Gate() { c->gate = saved; }
   } gate(c, idx ? n_act : nullptr);
-  TG_HIP(launch_active_groups(c, idx, n_act));
+  TG_HIP(launch_active_groups(c, idx, n_act, aold, c->alpha));
   hipEvent_t before = nullptr, after = nullptr;
   if (c->profiling && !c->capturing) {
     const int64_t ring = (int64_t)c->ev_start.size();
@@ -343,7 +357,26 @@ tg_status tg_tree_forces(tg_ctx *c, double eps, double theta,
     after = c->ev_stop[k];
     c->ev_head += 1;
   }
-  TG_HIP(launch_walk_forces(c, eps, theta, acc, pot, before, after));
+  TG_HIP(launch_walk_forces(c, eps, theta, acc, pot, before, after, aold != nullptr));
+  return TG_OK;
+}
+
+tg_status tg_tree_forces(tg_ctx *c, double eps, double theta,
+                         const int32_t *idx, const int32_t *n_act, double *acc,
+                         double *pot) {
+  return tree_forces_impl(c, eps, theta, idx, n_act, acc, pot, nullptr);
+}
+
+tg_status tg_set_mac(tg_ctx *c, int32_t kind, double alpha, const double *acc_old) {
+  if (!c) return fail(TG_EINVAL, "tg_set_mac: NULL context");
+  if (kind == TG_MAC_GEOMETRIC) {
+    c->mac = kind; c->alpha = 0.0; c->acc_old = nullptr;
+    return TG_OK;
+  }
+  if (kind != TG_MAC_RELATIVE) return fail(TG_EINVAL, "tg_set_mac: unknown kind");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha))
+    return fail(TG_EINVAL, "tg_set_mac: alpha must be finite and >= 0");
+  c->mac = kind; c->alpha = alpha; c->acc_old = acc_old;
   return TG_OK;
 }
 
@@ -414,14 +447,16 @@ tg_status tg_walk_lists(tg_ctx *c, double theta, const int32_t *idx,
                         int64_t *n_ids_out) {
   tg_status st = check_walk_args(c, theta, idx, n_act, "tg_walk_lists");
   if (st != TG_OK) return st;
+  const double *aold = nullptr;
+  if ((st = mac_acc_old(c, nullptr, "tg_walk_lists", &aold)) != TG_OK) return st;
   if (c->capturing) return fail(TG_ESTATE, "tg_walk_lists: during capture");
   if (!n_groups_out || !n_ids_out) return fail(TG_EINVAL, "tg_walk_lists: NULL outputs");
   *n_groups_out = 0;
   *n_ids_out = 0;
   if (c->n == 0) return TG_OK;
   Buffers &b = c->b;
-  TG_HIP(launch_active_groups(c, idx, n_act));
-  TG_HIP(launch_walk_lists(c, theta, 0, nullptr, 0, nullptr, 0));
+  TG_HIP(launch_active_groups(c, idx, n_act, aold, c->alpha));
+  TG_HIP(launch_walk_lists(c, theta, 0, nullptr, 0, nullptr, 0, aold != nullptr));
   TreeCounters h;
   TG_HIP(hipMemcpyAsync(&h, b.ctr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   TG_HIP(hipStreamSynchronize(c->stream));
@@ -436,7 +471,7 @@ tg_status tg_walk_lists(tg_ctx *c, double theta, const int32_t *idx,
   *n_ids_out = total;
   if ((int64_t)nag > cap_groups || (int64_t)total > cap_ids || !info || !ids)
     return fail(TG_ECAPACITY, "tg_walk_lists: output capacity too small");
-  TG_HIP(launch_walk_lists(c, theta, 1, nullptr, 0, ids, cap_ids));
+  TG_HIP(launch_walk_lists(c, theta, 1, nullptr, 0, ids, cap_ids, aold != nullptr));
   std::vector<uint32_t> cnt(2 * (size_t)nag), off(2 * (size_t)nag), al(nag);
   if (nag) {
     TG_HIP(hipMemcpyAsync(cnt.data(), b.wl_count, sizeof(uint32_t) * 2 * nag,
@@ -811,7 +846,10 @@ tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
   if ((st = tg_set_external(c, y->bh_pos, y->bh_mass, y->bh_eps, y->n_bh,
                             y->n_bh ? y->bh_seg : nullptr, y->n_sys)) != TG_OK)
     return st;
-  if ((st = tg_tree_forces(c, y->eps, y->theta, idx, n_act, y->acc, y->pot)) != TG_OK)
+  // relative test: the system's current accelerations are the old ones
+  // (each group's threshold is formed before any of them is overwritten)
+  if ((st = tree_forces_impl(c, y->eps, y->theta, idx, n_act, y->acc, y->pot, y->acc)) !=
+      TG_OK)
     return st;
   if (y->n_bh > 0) {
     // SMBHs feel the stars of their own system, then each other

@@ -22,8 +22,9 @@ def to_dev(a, dtype=None):
 
 def gpu_run(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
             sys_off=None, precision=0, lists=False, ctx=None, pot=True,
-            waves_per_cu=0, frontier_cap=0, max_nodes=0):
-    """Build + moments + forces on the GPU; returns a dict of numpy arrays."""
+            waves_per_cu=0, frontier_cap=0, max_nodes=0, alpha=None, acc_old=None):
+    """Build + moments + forces on the GPU; returns a dict of numpy arrays.
+    With alpha the walk uses the relative test against acc_old ([N, 3])."""
     torch = torch_dev()
     from paper_1507_01009_amd import binding as B
     n = pos.shape[0]
@@ -43,6 +44,10 @@ def gpu_run(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
         dna = to_dev(np.array([len(active)], np.int32))
     else:
         didx = dna = None
+    dold = None
+    if alpha is not None:
+        dold = to_dev(np.asarray(acc_old, np.float64).reshape(-1, 3))
+        ctx.set_mac(True, alpha, dold)
     ctx.build_tree(dpos, sys_off)
     ctx.compute_moments(dm)
     ctx.tree_forces(eps, theta, acc, dpot, didx, dna)
@@ -51,6 +56,8 @@ def gpu_run(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
            "counts": ctx.get_counts(), "tree": ctx.tree_arrays(), "ctx": ctx}
     if lists:
         out["lists"] = ctx.walk_lists(theta, didx, dna)
+    if alpha is not None:
+        ctx.set_mac(False)
     return out
 
 
@@ -59,8 +66,10 @@ def rel_err(a, b):
 
 
 def oracle_lists(ev, theta):
-    """Oracle sorted lists for every evaluated group, keyed by group index."""
-    L = oracle.walk_lists(ev.tree, ev.mom, ev.groups, ev.box, ev.sel, theta)
+    """Oracle sorted lists for every evaluated group, keyed by group index
+    (relative test when the evaluation used it)."""
+    L = oracle.walk_lists(ev.tree, ev.mom, ev.groups, ev.box, ev.sel, theta,
+                          rel=ev.rel, arel=ev.arel)
     return {int(g): l for g, l in zip(ev.sel, L)}
 
 
@@ -82,3 +91,16 @@ def mac_margin(tree, mom, box, node, theta):
     m = np.maximum(np.maximum(lo - c, c - hi), 0.0)
     d2 = float(np.sum(m * m))
     return abs(s * s - theta * theta * d2) / (s * s)
+
+
+def rel_margin(ev, k, node):
+    """Relative distance of one relative-test decision from its threshold
+    P^2 = A d^8 (the separation rule uses only exact cell geometry and the
+    box, so only this part can differ between the two sides)."""
+    box = ev.box[k]
+    c = ev.mom[node, 1:4]
+    m = np.maximum(np.maximum(box[:3] - c, c - box[3:]), 0.0)
+    d2 = float(np.sum(m * m))
+    P = ev.rel[node, 3]
+    rhs = ev.arel[k] * d2 ** 4
+    return abs(P * P - rhs) / max(P * P, 1e-300)

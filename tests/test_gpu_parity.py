@@ -238,7 +238,7 @@ def test_full_size_cusp_sampled():
     assert g64["counts"] == g32["counts"]
 
 
-# ---------------------------------------------------------------- a11
+# ---------------------------------------------------- FP64 direct forces
 def test_direct_fp64_smbh_pairs():
     say("direct")
     import torch
@@ -289,7 +289,7 @@ def test_direct_fp64_segments():
         assert rel_err(a[sl], ra).max() <= 1e-13
 
 
-# ---------------------------------------------------------------- a12
+# ---------------------------------------------------- leapfrog and levels
 def test_kick_drift_levels_bit_exact():
     say("integrator")
     import torch
@@ -352,7 +352,7 @@ def test_kdk_step_matches_oracle():
     assert rel_err(acc.cpu().numpy(), a1).max() <= FP64_TOL
 
 
-# ---------------------------------------------------------------- a13 / runtime
+# ---------------------------------------------------- graphs / runtime
 def test_graph_replay_equals_eager():
     say("graph")
     import torch

@@ -1,0 +1,221 @@
+"""GPU parity of the relative opening test (through the C ABI) against the
+oracle's relative walk on identical inputs and identical old accelerations.
+
+Bar as for the opening angle: lists and interaction counts equal (a list may
+differ only where a decision sits on its threshold within the rounding of
+the internal nodes' mass and centre of mass), FP64 forces max relative error
+<= 1e-12, mixed precision median <= 1e-5 and p99 <= 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import steps as osteps
+from paper_1507_01009_amd import ics
+from gpu_helpers import (gpu_run, rel_err, oracle_lists, gpu_lists_by_group, rel_margin,
+                         to_dev)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _work(name):
+    if name == "plummer4096":
+        w = ics.plummer_c1()
+        return w.pos, w.mass, w.eps
+    if name == "hernquist32k":
+        p, _, m = ics.dehnen(32768, 1.0, ics.SEED_BASE + 22)
+        return p, m, 0.01
+    if name == "cusp65k":
+        p, _, m = ics.dehnen(65536, 1.5, ics.SEED_BASE + 23)
+        return p, m, 1e-3
+    if name == "clustered":
+        rng = np.random.default_rng(5)
+        base = rng.normal(size=(300, 3))
+        p = np.concatenate([base, np.repeat(base[:5], 40, axis=0),
+                            rng.normal(size=(900, 3)) * 1e-7])
+        return p, np.full(p.shape[0], 1.0 / p.shape[0]), 1e-3
+    raise KeyError(name)
+
+
+def _aold(pos, m, eps):
+    """Old accelerations: the oracle's opening-angle forces (theta = 0.5)."""
+    return oracle.tree_forces(pos, m, eps, 0.5).acc
+
+
+@pytest.mark.parametrize("name,alpha,nl,ng,every", [
+    ("plummer4096", 1e-3, 8, 64, 1), ("plummer4096", 1e-2, 8, 32, 3),
+    ("hernquist32k", 1e-3, 8, 64, 1), ("hernquist32k", 1e-4, 12, 100, 2),
+    ("clustered", 1e-3, 4, 16, 1), ("plummer4096", 0.0, 8, 64, 5)])
+def test_lists_match(name, alpha, nl, ng, every):
+    say("rel lists", name, alpha)
+    pos, m, eps = _work(name)
+    aold = _aold(pos, m, eps)
+    active = None if every == 1 else np.arange(0, pos.shape[0], every)
+    g = gpu_run(pos, m, eps, 0.5, nl, ng, active=active, lists=True, alpha=alpha,
+                acc_old=aold)
+    ev = oracle.tree_forces(pos, m, eps, 0.5, nl, ng, active=active, alpha=alpha,
+                            acc_old=aold)
+    ol = oracle_lists(ev, 0.5)
+    gl = gpu_lists_by_group(*g["lists"])
+    assert sorted(gl) == sorted(ol)
+    flips = 0
+    for k, (om, op) in ol.items():
+        gm, gp = gl[k]
+        if np.array_equal(gm, om) and np.array_equal(gp, op):
+            continue
+        diff = set(np.setxor1d(gm, om)) | set(np.setxor1d(gp, op))
+        for v in diff:
+            anc = v
+            while anc != 0xFFFFFFFF:
+                if rel_margin(ev, k, anc) < 1e-12:
+                    break
+                anc = ev.tree.parent[anc]
+            assert anc != 0xFFFFFFFF, (k, v)
+        flips += 1
+    say("  groups %d flips %d" % (len(ol), flips))
+    assert flips <= max(1, len(ol) // 10000)
+    if alpha == 0.0:
+        assert g["counts"]["n_p2m"] == 0
+
+
+@pytest.mark.parametrize("name,alpha,nl,ng,every", [
+    ("plummer4096", 1e-3, 8, 64, 1), ("hernquist32k", 1e-3, 8, 64, 1),
+    ("hernquist32k", 1e-2, 16, 97, 3), ("cusp65k", 1e-3, 8, 128, 1),
+    ("clustered", 1e-3, 4, 16, 1)])
+def test_forces_fp64(name, alpha, nl, ng, every):
+    say("rel fp64", name, alpha)
+    pos, m, eps = _work(name)
+    aold = _aold(pos, m, eps)
+    active = None if every == 1 else np.arange(1, pos.shape[0], every)
+    g = gpu_run(pos, m, eps, 0.5, nl, ng, active=active, alpha=alpha, acc_old=aold)
+    ev = oracle.tree_forces(pos, m, eps, 0.5, nl, ng, active=active, alpha=alpha,
+                            acc_old=aold)
+    rows = np.arange(pos.shape[0]) if active is None else active
+    e = rel_err(g["acc"][rows], ev.acc[rows])
+    ep = np.abs(g["pot"][rows] - ev.pot[rows]) / np.abs(ev.pot[rows])
+    say("  max rel acc %.3g pot %.3g" % (e.max(), ep.max()))
+    assert e.max() <= FP64_TOL and ep.max() <= FP64_TOL
+    c = g["counts"]
+    assert (c["n_p2p"], c["n_p2m"], c["n_targets"]) == (ev.n_p2p, ev.n_p2m, ev.n_targets)
+
+
+@pytest.mark.parametrize("name", ["hernquist32k", "cusp65k"])
+def test_forces_mixed_precision(name):
+    say("rel mixed", name)
+    pos, m, eps = _work(name)
+    aold = _aold(pos, m, eps)
+    g = gpu_run(pos, m, eps, 0.5, 8, 64, precision=1, alpha=1e-3, acc_old=aold)
+    ev = oracle.tree_forces(pos, m, eps, 0.5, 8, 64, alpha=1e-3, acc_old=aold)
+    e = rel_err(g["acc"], ev.acc)
+    say("  mixed p50 %.3g p99 %.3g" % (np.median(e), np.percentile(e, 99)))
+    assert np.median(e) <= 1e-5 and np.percentile(e, 99) <= 1e-4
+    assert g["counts"]["n_p2p"] == ev.n_p2p and g["counts"]["n_p2m"] == ev.n_p2m
+
+
+def test_old_accelerations_may_be_the_output():
+    say("rel in place")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    pos, m, eps = _work("hernquist32k")
+    aold = _aold(pos, m, eps)
+    act = np.arange(0, pos.shape[0], 2)
+    ref = gpu_run(pos, m, eps, 0.5, 8, 64, active=act, alpha=1e-3, acc_old=aold)
+    ctx = B.Context(pos.shape[0])
+    acc = to_dev(aold.copy())
+    ctx.set_mac(True, 1e-3, acc)
+    ctx.build_tree(to_dev(pos))
+    ctx.compute_moments(to_dev(m))
+    ctx.tree_forces(eps, 0.5, acc, None, to_dev(act.astype(np.int32)),
+                    to_dev(np.array([act.size], np.int32)))
+    ctx.sync()
+    h = acc.cpu().numpy()
+    assert np.array_equal(h[act], ref["acc"][act])
+    rest = np.setdiff1d(np.arange(pos.shape[0]), act)
+    assert np.array_equal(h[rest], aold[rest])
+    assert ctx.get_counts() == ref["counts"]
+
+
+def test_full_size_cusp_sampled():
+    """N = 1 048 576 Dehnen gamma = 1.5, alpha = 1e-3 with the model's own
+    enclosed-mass acceleration as the old one; whole-tree GPU walk, the
+    oracle walks a sample of groups."""
+    say("rel cusp1m")
+    w = ics.cusp_c3()
+    pos, m, eps = w.pos, w.mass, w.eps
+    r = np.linalg.norm(pos, axis=1)
+    aold = -(m.sum() * ics.dehnen_mass(r, 1.5) / (r ** 3 + 1e-300))[:, None] * pos
+    g = gpu_run(pos, m, eps, 0.5, 8, 64, alpha=1e-3, acc_old=aold)
+    t = oracle.build_tree(pos, None, 8)
+    groups = oracle.groups(t, 64)
+    rng = np.random.default_rng(9)
+    rg = np.linalg.norm(pos[t.perm[groups[:, 0]].astype(np.int64)], axis=1)
+    sel = np.unique(np.r_[rng.choice(groups.shape[0], 200, replace=False), np.argsort(rg)[:16]])
+    ev = oracle.tree_forces(pos, m, eps, 0.5, 8, 64, sel_groups=sel, tree=t, alpha=1e-3,
+                            acc_old=aold)
+    rows = np.nonzero(~np.isnan(ev.pot))[0]
+    e = rel_err(g["acc"][rows], ev.acc[rows])
+    say("  fp64 max %.3g over %d targets" % (e.max(), rows.size))
+    assert e.max() <= FP64_TOL
+
+
+def test_kdk_steps_with_relative_test():
+    say("rel kdk")
+    from paper_1507_01009_amd import binding as B
+    from test_gpu_steps import Dev, ostate
+    w = ics.hernquist_c2(n=32768)
+    dt = 1e-3
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    ctx.forces(d.sys)                  # first evaluation: opening angle
+    ctx.set_mac(True, 1e-3)            # then the relative test on sys acc
+    for _ in range(2):
+        ctx.step_kdk(d.sys, dt)
+    ctx.sync()
+    h = d.host()
+    st = ostate(w)
+    osteps.forces(st)
+    st.alpha = 1e-3
+    for _ in range(2):
+        osteps.kdk_step(st, dt)
+    assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-13 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-12 * np.abs(st.vel).max()
+    assert rel_err(h["acc"], st.acc).max() <= 1e-11
+
+
+def test_errors():
+    say("rel errors")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    pos, m, eps = _work("plummer4096")
+    ctx = B.Context(pos.shape[0])
+    acc = torch.zeros((pos.shape[0], 3), dtype=torch.float64, device="cuda")
+    ctx.build_tree(to_dev(pos))
+    ctx.compute_moments(to_dev(m))
+    for bad in (-1e-3, float("nan"), float("inf")):
+        with pytest.raises(B.TGError) as e:
+            ctx.set_mac(True, bad, acc)
+        assert e.value.status == -1
+    with pytest.raises(B.TGError) as e:
+        B._check(B.lib().tg_set_mac(ctx.h, 7, 1e-3, None))
+    assert e.value.status == -1
+    ctx.set_mac(True, 1e-3, None)       # no old accelerations: walks refuse
+    with pytest.raises(B.TGError) as e:
+        ctx.tree_forces(eps, 0.5, acc)
+    assert e.value.status == -5
+    # theta is not checked in the relative mode, and is again afterwards
+    ctx.set_mac(True, 1e-3, acc)
+    ctx.tree_forces(eps, 0.9, acc)
+    ctx.set_mac(False)
+    with pytest.raises(B.TGError) as e:
+        ctx.tree_forces(eps, 0.9, acc)
+    assert e.value.status == -1
+    ctx.sync()

@@ -1,4 +1,4 @@
-"""GPU parity of whole steps (rows a11-a13) against the oracle's steps.
+"""GPU parity of whole steps (SMBH terms, integrators, graphs) against the oracle's steps.
 
 Forces with SMBHs (FP64 SMBH terms in both precision modes), KDK steps,
 block-time-step substeps with device-side active sets and levels, graph
