@@ -1,0 +1,132 @@
+"""Plain CPU oracle of the chain coupling (TEST INFRASTRUCTURE ONLY).
+
+Nothing in the product library imports this module; only the tests, the
+smoke check and the benchmark's CPU leg do.  It shares no code with the HIP
+path.
+
+What it computes (Sec. 2, the hybrid method):
+
+* Perturbers, Eq. 2: tree particle j perturbs the chain iff
+      r_j < ((2 / gamma_crit) (m_j / M_chain))^(1/3) r_crit,
+  r_j its distance to the chain's centre of mass.  READING: decided without
+  roots, both sides cubed and squared,
+      (r2 r2) r2 < (k k) rc6,   r2 = (dx dx + dy dy) + dz dz,
+      k = c m_j,  c = 2 / (gamma_crit M_chain),  rc6 = (rc2 rc2) rc2,
+      rc2 = r_crit r_crit,
+  every operation rounded on its own, so that the decision is reproducible.
+  Particles with a set exclusion flag (ghosts) are never selected.
+* Radius selection (the chain start, r_j,BH < r_chain,0, and absorption,
+  Eq. 4, r_j,CoM < r_chain): r2 < r r.
+* Coupling forces on the tree particles (READING of the resolved-chain
+  paragraph): every listed, non-excluded star feels the chain as its
+  centre-of-mass particle, a point mass M at R, or, if it is a perturber,
+  as the resolved members; pairs with the chain are unsoftened by default
+  (Sec. 4 softening paragraph), or Plummer-softened with eps_pm.
+* Force on the chain particle: the (direct) force of every non-perturber
+  star on the point R, plus the correction of Eq. 3,
+      a_CoM,corr = (1 / M) sum_i m_i a_i,
+  a_i the force of the perturbers on member i (also returned: the AR-chain
+  integrates the members with it as external perturbation).
+Sums in long double, in index order.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LD = np.longdouble
+
+
+def tidal_constants(m_chain: float, r_crit: float, gamma_crit: float):
+    """c = 2 / (gamma_crit M_chain) and rc6 = (rc2 rc2) rc2 (host doubles)."""
+    c = 2.0 / (float(gamma_crit) * float(m_chain))
+    rc2 = float(r_crit) * float(r_crit)
+    return c, (rc2 * rc2) * rc2
+
+
+def _r2(pos, com):
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    dx = pos[:, 0] - float(com[0])
+    dy = pos[:, 1] - float(com[1])
+    dz = pos[:, 2] - float(com[2])
+    return (dx * dx + dy * dy) + dz * dz
+
+
+def perturbers(pos, mass, com, m_chain, r_crit, gamma_crit, exclude=None):
+    """Ascending indices of the perturbers (Eq. 2, cubed and squared form)."""
+    c, rc6 = tidal_constants(m_chain, r_crit, gamma_crit)
+    r2 = _r2(pos, com)
+    k = c * np.asarray(mass, np.float64)
+    sel = (r2 * r2) * r2 < (k * k) * rc6
+    if exclude is not None:
+        sel &= ~np.asarray(exclude, bool)
+    return np.nonzero(sel)[0].astype(np.int32)
+
+
+def within(pos, center, r, exclude=None):
+    """Ascending indices with |x - center|^2 < r r."""
+    sel = _r2(pos, center) < float(r) * float(r)
+    if exclude is not None:
+        sel &= ~np.asarray(exclude, bool)
+    return np.nonzero(sel)[0].astype(np.int32)
+
+
+def _pair(xs, ms, xt, e2, G):
+    """Force and potential of sources (xs, ms) on one target xt, long double,
+    in source order."""
+    a = np.zeros(3, LD)
+    p = LD(0)
+    for j in range(xs.shape[0]):
+        d = [LD(xs[j, k]) - LD(xt[k]) for k in range(3)]
+        r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + LD(e2)
+        D1 = LD(1) / np.sqrt(r2)
+        gm = LD(G) * LD(ms[j])
+        for k in range(3):
+            a[k] += gm * D1 * D1 * D1 * d[k]
+        p -= gm * D1
+    return a, p
+
+
+def coupling(pos, mass, targets, com, m_chain, mpos, mmass, pert, eps_pm=0.0,
+             exclude=None, G=1.0):
+    """Coupling terms (long double, returned as float64).
+
+    targets: star indices that get their chain term (listed, non-excluded).
+    pert: the perturber indices (from :func:`perturbers`).
+    Returns (acc_add [len(targets), 3], pot_add [len(targets)],
+             a_com [3], a_members [Nc, 3]).
+    """
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    mass = np.asarray(mass, np.float64)
+    mpos = np.asarray(mpos, np.float64).reshape(-1, 3)
+    mmass = np.asarray(mmass, np.float64)
+    e2 = float(eps_pm) * float(eps_pm)
+    is_p = np.zeros(pos.shape[0], bool)
+    is_p[np.asarray(pert, np.int64)] = True
+    ex = np.zeros(pos.shape[0], bool) if exclude is None else np.asarray(exclude, bool)
+    R = np.asarray(com, np.float64).reshape(1, 3)
+    Mv = np.array([m_chain], np.float64)
+    tg = np.asarray(targets, np.int64)
+    acc = np.zeros((tg.size, 3))
+    pot = np.zeros(tg.size)
+    for t, j in enumerate(tg):
+        if ex[j]:
+            continue
+        if is_p[j]:
+            a, p = _pair(mpos, mmass, pos[j], e2, G)
+        else:
+            a, p = _pair(R, Mv, pos[j], 0.0, G)
+        acc[t] = np.asarray(a, np.float64)
+        pot[t] = float(p)
+    # the chain particle: non-perturber, non-excluded stars, unsoftened
+    keep = np.nonzero(~is_p & ~ex)[0]
+    a_com, _ = _pair(pos[keep], mass[keep], R[0], 0.0, G)
+    # members: the perturbers' force, then Eq. 3
+    P = np.asarray(pert, np.int64)
+    am = np.zeros((mpos.shape[0], 3), LD)
+    for i in range(mpos.shape[0]):
+        am[i], _ = _pair(pos[P], mass[P], mpos[i], e2, G)
+    corr = np.zeros(3, LD)
+    for i in range(mpos.shape[0]):
+        corr += LD(mmass[i]) * am[i]
+    a_com = a_com + corr / LD(m_chain)
+    return acc, pot, np.asarray(a_com, np.float64), np.asarray(am, np.float64)
