@@ -67,6 +67,7 @@ typedef enum { TG_FP64 = 0, TG_MIXED = 1 } tg_precision;
 #define TG_ERR_FRONTIER    0x8u  /* walk frontier exceeded frontier_cap */
 #define TG_ERR_LISTS       0x10u /* list dump exceeded its capacity */
 #define TG_ERR_SORT        0x20u /* a radix-sort tile waited too long for its predecessor */
+#define TG_ERR_CHAIN       0x40u /* a selection (perturbers, radius) exceeded its capacity */
 
 typedef struct {
   int64_t max_particles;   /* capacity N for every call (>= 1) */
@@ -253,6 +254,65 @@ tg_status tg_counter_add(tg_ctx *ctx, int64_t *k_dev, int64_t inc);
 tg_status tg_set_external(tg_ctx *ctx, const double *pos_dev,
                           const double *mass_dev, const double *eps_dev,
                           int32_t n_ext, const int64_t *seg_host, int32_t n_sys);
+
+/* ---- chain coupling (Sec. 2, the hybrid method) ------------------------
+ * The stars near an SMBH that the regularised chain integrates ("members",
+ * at most 256, owned and advanced by the caller's chain integrator) act on
+ * the tree particles, and feel them, through these calls.  All arrays are
+ * device memory in the caller's order unless marked host. */
+typedef struct {
+  const double *pos;          /* [n][3] tree particles (stars) */
+  const double *mass;         /* [n] */
+  int64_t n;                  /* 0..max_particles */
+  const uint8_t *exclude;     /* [n] nonzero: not coupled (ghost members); NULL: none */
+  const double *member_pos;   /* [nc][3] chain members, global frame */
+  const double *member_mass;  /* [nc] */
+  int32_t nc;                 /* 1..256 */
+  double com[3];              /* host: the chain's centre of mass R */
+  double m_chain;             /* host: the chain's mass M (sum of member masses), > 0 */
+  double r_crit, gamma_crit;  /* Eq. 2: r_crit = min(r_chain, r_chain,0) >= 0, gamma_crit > 0 */
+  double eps_pm;              /* Plummer softening of perturber-member pairs (0: Newtonian) */
+  int32_t *pert_idx;          /* [pert_cap] out: perturbers, ascending */
+  int32_t pert_cap;
+  int32_t *n_pert;            /* [1] out: perturber count (may exceed pert_cap) */
+} tg_chain;
+
+/* Perturbers by the tidal criterion (Eq. 2): star j perturbs the chain iff
+ * |x_j - R| < ((2 / gamma_crit) (m_j / M))^(1/3) r_crit, decided without
+ * roots as (r2 r2) r2 < (k k) rc6, k = (2 / (gamma_crit M)) m_j,
+ * rc6 = (r_crit^2 r_crit^2) r_crit^2, r2 = (dx dx + dy dy) + dz dz, every
+ * operation rounded separately.  Excluded stars are never perturbers.
+ * Writes the ascending list (at most pert_cap entries) and the count; a
+ * count above pert_cap sets TG_ERR_CHAIN (tg_sync: TG_ECAPACITY).
+ * Errors: TG_EINVAL. */
+tg_status tg_perturbers(tg_ctx *ctx, const tg_chain *chain);
+
+/* Selects the perturbers (as tg_perturbers), then adds the coupling forces:
+ *  - acc_dev / pot_dev ([n][3], [n] or NULL) of each listed star
+ *    (active_idx_dev / n_active_dev as in tg_tree_forces, NULL = all), if not
+ *    excluded: a perturber gets the force of every member (pair softening
+ *    eps_pm), any other star the Newtonian force of the chain particle (mass
+ *    M at R), which stands for the chain in the tree (Sec. 2);
+ *  - member_acc_dev ([nc][3], overwritten): the force of the perturbers on
+ *    each member (the chain integration's external perturbation);
+ *  - com_acc_dev ([3], overwritten): the force on the chain particle, the
+ *    Newtonian force of every non-perturber, non-excluded star plus the
+ *    correction of Eq. 3, (1 / M) sum_i m_i member_acc_i.
+ * Sums are compensated where they run over stars; deterministic.  acc is
+ * added to (call after the tree forces of the same positions).
+ * Errors: TG_EINVAL. */
+tg_status tg_chain_forces(tg_ctx *ctx, const tg_chain *chain,
+                          const int32_t *active_idx_dev, const int32_t *n_active_dev,
+                          double *acc_dev, double *pot_dev, double *com_acc_dev,
+                          double *member_acc_dev);
+
+/* Stars within radius r of center (host [3]): |x - c|^2 < r r, the chain
+ * start around an SMBH (r_chain,0) and absorption into the chain (Eq. 4,
+ * r_chain about R).  Ascending indices (at most cap) and the count in
+ * n_out_dev[0]; a count above cap sets TG_ERR_CHAIN.  Errors: TG_EINVAL. */
+tg_status tg_select_within(tg_ctx *ctx, const double *pos_dev, int64_t n,
+                           const uint8_t *exclude_dev, const double center[3], double r,
+                           int32_t *idx_dev, int32_t cap, int32_t *n_out_dev);
 
 /* ---- whole steps (every stage above in one call; capturable) ---------- */
 typedef struct {

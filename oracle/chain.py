@@ -27,7 +27,7 @@ What it computes (Sec. 2, the hybrid method):
       a_CoM,corr = (1 / M) sum_i m_i a_i,
   a_i the force of the perturbers on member i (also returned: the AR-chain
   integrates the members with it as external perturbation).
-Sums in long double, in index order.
+Sums in long double.
 """
 from __future__ import annotations
 
@@ -70,20 +70,33 @@ def within(pos, center, r, exclude=None):
     return np.nonzero(sel)[0].astype(np.int32)
 
 
-def _pair(xs, ms, xt, e2, G):
-    """Force and potential of sources (xs, ms) on one target xt, long double,
-    in source order."""
-    a = np.zeros(3, LD)
-    p = LD(0)
-    for j in range(xs.shape[0]):
-        d = [LD(xs[j, k]) - LD(xt[k]) for k in range(3)]
-        r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + LD(e2)
+def _field(xs, ms, xt, e2, G):
+    """Force and potential of the sources (xs [k][3], ms [k]) on each target
+    (xt [t][3]), long double: a_t = sum_s G m_s (x_s - x_t) / (r^2 + e2)^(3/2),
+    phi_t = -sum_s G m_s / (r^2 + e2)^(1/2), sources taken in order."""
+    xs = np.asarray(xs, np.float64).reshape(-1, 3).astype(LD)
+    ms = np.asarray(ms, np.float64).astype(LD)
+    xt = np.asarray(xt, np.float64).reshape(-1, 3).astype(LD)
+    a = np.zeros(xt.shape, LD)
+    p = np.zeros(xt.shape[0], LD)
+    for s in range(xs.shape[0]):
+        d = xs[s][None, :] - xt
+        r2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2] + LD(e2)
         D1 = LD(1) / np.sqrt(r2)
-        gm = LD(G) * LD(ms[j])
-        for k in range(3):
-            a[k] += gm * D1 * D1 * D1 * d[k]
+        gm = LD(G) * ms[s]
+        a += (gm * D1 * D1 * D1)[:, None] * d
         p -= gm * D1
     return a, p
+
+
+def _on_point(xs, ms, xt, G):
+    """Newtonian force of many sources on one point, long double sum."""
+    xs = np.asarray(xs, np.float64).reshape(-1, 3).astype(LD)
+    d = xs - np.asarray(xt, np.float64).astype(LD)[None, :]
+    r2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
+    D1 = LD(1) / np.sqrt(r2)
+    w = LD(G) * np.asarray(ms, np.float64).astype(LD) * D1 * D1 * D1
+    return (w[:, None] * d).sum(0)
 
 
 def coupling(pos, mass, targets, com, m_chain, mpos, mmass, pert, eps_pm=0.0,
@@ -104,27 +117,22 @@ def coupling(pos, mass, targets, com, m_chain, mpos, mmass, pert, eps_pm=0.0,
     is_p[np.asarray(pert, np.int64)] = True
     ex = np.zeros(pos.shape[0], bool) if exclude is None else np.asarray(exclude, bool)
     R = np.asarray(com, np.float64).reshape(1, 3)
-    Mv = np.array([m_chain], np.float64)
     tg = np.asarray(targets, np.int64)
     acc = np.zeros((tg.size, 3))
     pot = np.zeros(tg.size)
-    for t, j in enumerate(tg):
-        if ex[j]:
-            continue
-        if is_p[j]:
-            a, p = _pair(mpos, mmass, pos[j], e2, G)
-        else:
-            a, p = _pair(R, Mv, pos[j], 0.0, G)
-        acc[t] = np.asarray(a, np.float64)
-        pot[t] = float(p)
-    # the chain particle: non-perturber, non-excluded stars, unsoftened
+    # perturbers: the resolved members; others: the chain particle
+    rp = np.nonzero(~ex[tg] & is_p[tg])[0]
+    rn = np.nonzero(~ex[tg] & ~is_p[tg])[0]
+    a, p = _field(mpos, mmass, pos[tg[rp]], e2, G)
+    acc[rp], pot[rp] = a.astype(np.float64), p.astype(np.float64)
+    a, p = _field(R, [m_chain], pos[tg[rn]], 0.0, G)
+    acc[rn], pot[rn] = a.astype(np.float64), p.astype(np.float64)
+    # the chain particle: non-perturber, non-excluded stars, Newtonian
     keep = np.nonzero(~is_p & ~ex)[0]
-    a_com, _ = _pair(pos[keep], mass[keep], R[0], 0.0, G)
+    a_com = _on_point(pos[keep], mass[keep], R[0], G)
     # members: the perturbers' force, then Eq. 3
     P = np.asarray(pert, np.int64)
-    am = np.zeros((mpos.shape[0], 3), LD)
-    for i in range(mpos.shape[0]):
-        am[i], _ = _pair(pos[P], mass[P], mpos[i], e2, G)
+    am, _ = _field(pos[P], mass[P], mpos, e2, G)
     corr = np.zeros(3, LD)
     for i in range(mpos.shape[0]):
         corr += LD(mmass[i]) * am[i]

@@ -59,6 +59,15 @@ class tg_blocks(C.Structure):
                 ("dt_max", C.c_double), ("nlev", C.c_int32), ("tau2eps2v", C.c_void_p)]
 
 
+class tg_chain(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("mass", C.c_void_p), ("n", C.c_int64),
+                ("exclude", C.c_void_p), ("member_pos", C.c_void_p),
+                ("member_mass", C.c_void_p), ("nc", C.c_int32),
+                ("com", C.c_double * 3), ("m_chain", C.c_double), ("r_crit", C.c_double),
+                ("gamma_crit", C.c_double), ("eps_pm", C.c_double),
+                ("pert_idx", C.c_void_p), ("pert_cap", C.c_int32), ("n_pert", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -95,6 +104,9 @@ def lib():
             "tg_counter_add": (st, [P, P, i64]),
             "tg_set_external": (st, [P, P, P, P, i32, P, i32]),
             "tg_set_mac": (st, [P, i32, f64, P]),
+            "tg_perturbers": (st, [P, P]),
+            "tg_chain_forces": (st, [P, P, P, P, P, P, P, P]),
+            "tg_select_within": (st, [P, P, i64, P, P, f64, P, i32, P]),
             "tg_forces": (st, [P, P, P, P]),
             "tg_step_kdk": (st, [P, P, f64]),
             "tg_step_dkd": (st, [P, P, f64]),
@@ -125,7 +137,7 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_tree_forces", "tg_get_counts", "tg_reset_counts", "tg_walk_lists",
             "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
             "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac",
-            "tg_forces",
+            "tg_perturbers", "tg_chain_forces", "tg_select_within", "tg_forces",
             "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
@@ -315,6 +327,36 @@ class Context:
         nsys = 1 if arr is None else arr.shape[0] - 1
         n = 0 if mass is None else mass.shape[0]
         _check(lib().tg_set_external(self.h, _ptr(pos), _ptr(mass), _ptr(eps), n, p, nsys))
+
+    # -- chain coupling
+    def make_chain(self, pos, mass, member_pos, member_mass, com, m_chain, r_crit,
+                   gamma_crit, pert_idx, n_pert, eps_pm=0.0, exclude=None):
+        """A tg_chain over device tensors (kept alive by the caller); com and
+        m_chain are host values."""
+        ch = tg_chain()
+        ch.pos, ch.mass, ch.n = _ptr(pos), _ptr(mass), pos.shape[0]
+        ch.exclude = _ptr(exclude)
+        ch.member_pos, ch.member_mass = _ptr(member_pos), _ptr(member_mass)
+        ch.nc = member_mass.shape[0]
+        for k in range(3):
+            ch.com[k] = float(com[k])
+        ch.m_chain, ch.r_crit, ch.gamma_crit = float(m_chain), float(r_crit), float(gamma_crit)
+        ch.eps_pm = float(eps_pm)
+        ch.pert_idx, ch.pert_cap, ch.n_pert = _ptr(pert_idx), pert_idx.shape[0], _ptr(n_pert)
+        return ch
+
+    def perturbers(self, chain):
+        _check(lib().tg_perturbers(self.h, C.byref(chain)))
+
+    def chain_forces(self, chain, acc, com_acc, member_acc, pot=None, active_idx=None,
+                     n_active=None):
+        _check(lib().tg_chain_forces(self.h, C.byref(chain), _ptr(active_idx), _ptr(n_active),
+                                     _ptr(acc), _ptr(pot), _ptr(com_acc), _ptr(member_acc)))
+
+    def select_within(self, pos, center, r, idx, n_out, exclude=None):
+        c3 = (C.c_double * 3)(*[float(x) for x in center])
+        _check(lib().tg_select_within(self.h, _ptr(pos), pos.shape[0], _ptr(exclude), c3,
+                                      float(r), _ptr(idx), idx.shape[0], _ptr(n_out)))
 
     # -- whole steps
     def make_system(self, pos, vel, acc, mass, eps, theta, pot=None, sys_off=None,

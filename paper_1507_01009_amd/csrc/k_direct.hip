@@ -15,17 +15,6 @@
 
 namespace tg {
 
-struct CSum {
-  double s = 0.0, c = 0.0;
-  __device__ __forceinline__ void add(double x) {
-    double t = s + x;
-    double bp = t - s;
-    c += (s - (t - bp)) + (x - bp);
-    s = t;
-  }
-  __device__ __forceinline__ double get() const { return s + c; }
-};
-
 __device__ __forceinline__ int seg_of(const int64_t *off, int nseg, int64_t i) {
   int lo = 0, hi = nseg - 1;
   while (lo < hi) {

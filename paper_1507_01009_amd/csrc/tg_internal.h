@@ -33,6 +33,7 @@ constexpr int kSortStatusBase = 64;               // words before the digit coun
 constexpr int kScanBlocks = 256;
 constexpr int kMaxWavesPerCU = 16;
 constexpr int kMaxExternal = 1024;               // SMBHs / external point masses
+constexpr int kMaxChain = 256;                   // chain members
 constexpr int kSegSlots = 8;                     // cached direct-sum segment tables
 constexpr int kSegSlotLen = 2 * (kMaxSys + 1);
 
@@ -95,6 +96,10 @@ struct Buffers {
   uint32_t *alist = nullptr;      // [N] active group ids
   double *abox = nullptr;         // [N][6] box of active targets per group
   double *arel = nullptr;         // [N] relative test: (alpha alpha) min |a_old|^2 per group
+  // chain coupling
+  uint32_t *cflag = nullptr;      // [N + 1] selection flags (the perturber mask after Eq. 2)
+  uint32_t *coff = nullptr;       // [N + 1] their exclusive scan
+  double *cpart = nullptr;        // [256][6] compensated partials of the chain particle's force
   uint8_t *sact = nullptr;        // [N] active flag per sorted particle
   // walk
   uint32_t *frontier = nullptr;   // [waves][2][frontier_cap]
@@ -183,6 +188,23 @@ hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s,
 hipError_t fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s,
                    const int32_t *gate = nullptr);
 
+// Compensated double sum (error-free TwoSum with a running correction),
+// used by the direct sums and the chain coupling.
+struct CSum {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double x) {
+    double t = s + x;
+    double bp = t - s;
+    c += (s - (t - bp)) + (x - bp);
+    s = t;
+  }
+  __device__ __forceinline__ void merge(const CSum &o) {
+    add(o.s);
+    c += o.c;
+  }
+  __device__ __forceinline__ double get() const { return s + c; }
+};
+
 // k_keys.hip
 hipError_t launch_cube_keys(tg_ctx *c, const double *pos);
 hipError_t launch_sort(tg_ctx *c);
@@ -209,6 +231,15 @@ hipError_t launch_counts_reset(tg_ctx *c);
 hipError_t launch_walk_lists(tg_ctx *c, double theta, int pass,
                              int64_t *info, int64_t cap_groups, uint32_t *ids,
                              int64_t cap_ids, bool rel);
+
+// k_chain.hip
+hipError_t launch_chain_select(tg_ctx *c, const double *pos, const double *mass, int64_t n,
+                               const uint8_t *excl, const double center[3], bool tidal,
+                               double cst, double lim, int32_t *idx, int32_t cap,
+                               int32_t *n_out);
+hipError_t launch_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx,
+                               const int32_t *n_act, double *acc, double *pot,
+                               double *com_acc, double *member_acc);
 
 // k_direct.hip
 hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,

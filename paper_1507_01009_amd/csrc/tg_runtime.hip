@@ -149,6 +149,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.aflag, N + 1));
   A(dalloc(&b.alist, N));
   A(dalloc(&b.abox, 6 * N)); A(dalloc(&b.arel, N));
+  A(dalloc(&b.cflag, N + 1)); A(dalloc(&b.coff, N + 1)); A(dalloc(&b.cpart, 6 * 256));
   A(dalloc(&b.sact, N));
   A(dalloc(&b.frontier, waves * 2 * (int64_t)cfg.frontier_cap));
   A(dalloc(&b.wl_count, 2 * N + 2));
@@ -938,6 +939,77 @@ tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
   return tg_forces(c, y, b->active_idx, b->n_active);
 }
 
+static tg_status check_chain(tg_ctx *c, const tg_chain *ch, const char *who) {
+  if (!c) return fail(TG_EINVAL, std::string(who) + ": NULL context");
+  if (!ch) return fail(TG_EINVAL, std::string(who) + ": NULL chain");
+  if (ch->n < 0 || ch->n > c->cfg.max_particles)
+    return fail(TG_EINVAL, std::string(who) + ": n out of range");
+  if (ch->n > 0 && (!ch->pos || !ch->mass))
+    return fail(TG_EINVAL, std::string(who) + ": NULL star arrays");
+  if (ch->nc < 1 || ch->nc > kMaxChain)
+    return fail(TG_EINVAL, std::string(who) + ": nc must be in 1..256");
+  if (!ch->member_pos || !ch->member_mass)
+    return fail(TG_EINVAL, std::string(who) + ": NULL member arrays");
+  if (!(ch->m_chain > 0.0) || !std::isfinite(ch->m_chain))
+    return fail(TG_EINVAL, std::string(who) + ": m_chain must be positive");
+  if (!(ch->r_crit >= 0.0) || !std::isfinite(ch->r_crit) || !(ch->gamma_crit > 0.0) ||
+      !std::isfinite(ch->gamma_crit))
+    return fail(TG_EINVAL, std::string(who) + ": r_crit >= 0 and gamma_crit > 0 required");
+  if (!(ch->eps_pm >= 0.0) || !std::isfinite(ch->eps_pm))
+    return fail(TG_EINVAL, std::string(who) + ": eps_pm must be >= 0");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(ch->com[k])) return fail(TG_EINVAL, std::string(who) + ": com not finite");
+  if (!ch->pert_idx || !ch->n_pert || ch->pert_cap < 0)
+    return fail(TG_EINVAL, std::string(who) + ": perturber list required");
+  return TG_OK;
+}
+
+tg_status tg_perturbers(tg_ctx *c, const tg_chain *ch) {
+  tg_status st = check_chain(c, ch, "tg_perturbers");
+  if (st != TG_OK) return st;
+  // Eq. 2 without roots: (r2 r2) r2 < (k k) rc6, k = c m_j
+  const double cst = 2.0 / (ch->gamma_crit * ch->m_chain);
+  const double rc2 = ch->r_crit * ch->r_crit;
+  const double rc6 = (rc2 * rc2) * rc2;
+  if (ch->n == 0) {
+    TG_HIP(fill_u32((uint32_t *)ch->n_pert, 0u, 1, c->stream));
+    return TG_OK;
+  }
+  TG_HIP(launch_chain_select(c, ch->pos, ch->mass, ch->n, ch->exclude, ch->com, true, cst, rc6,
+                             ch->pert_idx, ch->pert_cap, ch->n_pert));
+  return TG_OK;
+}
+
+tg_status tg_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx,
+                          const int32_t *n_act, double *acc, double *pot, double *com_acc,
+                          double *member_acc) {
+  tg_status st = check_chain(c, ch, "tg_chain_forces");
+  if (st != TG_OK) return st;
+  if (idx && !n_act) return fail(TG_EINVAL, "tg_chain_forces: n_active required");
+  if (!com_acc || !member_acc) return fail(TG_EINVAL, "tg_chain_forces: NULL outputs");
+  if ((st = tg_perturbers(c, ch)) != TG_OK) return st;
+  if (ch->n == 0) TG_HIP(fill_u32(c->b.cflag, 0u, 1, c->stream));
+  TG_HIP(launch_chain_forces(c, ch, idx, n_act, acc, pot, com_acc, member_acc));
+  return TG_OK;
+}
+
+tg_status tg_select_within(tg_ctx *c, const double *pos, int64_t n, const uint8_t *exclude,
+                           const double center[3], double r, int32_t *idx, int32_t cap,
+                           int32_t *n_out) {
+  if (!c) return fail(TG_EINVAL, "tg_select_within: NULL context");
+  if (n < 0 || n > c->cfg.max_particles) return fail(TG_EINVAL, "tg_select_within: n out of range");
+  if ((n > 0 && !pos) || !center || !idx || !n_out || cap < 0)
+    return fail(TG_EINVAL, "tg_select_within: NULL pointer or negative capacity");
+  if (!(r >= 0.0) || !std::isfinite(r)) return fail(TG_EINVAL, "tg_select_within: r must be >= 0");
+  if (n == 0) {
+    TG_HIP(fill_u32((uint32_t *)n_out, 0u, 1, c->stream));
+    return TG_OK;
+  }
+  TG_HIP(launch_chain_select(c, pos, nullptr, n, exclude, center, false, 0.0, r * r, idx, cap,
+                             n_out));
+  return TG_OK;
+}
+
 tg_status tg_sync(tg_ctx *c, uint32_t *bits) {
   if (!c) return fail(TG_EINVAL, "tg_sync: NULL context");
   if (c->capturing) return fail(TG_ESTATE, "tg_sync: during capture");
@@ -948,8 +1020,8 @@ tg_status tg_sync(tg_ctx *c, uint32_t *bits) {
   if (bits) *bits = h;
   if (h & (TG_ERR_NONFINITE | TG_ERR_MASS))
     return fail(TG_EDATA, "device: non-finite position or non-positive mass");
-  if (h & (TG_ERR_NODES | TG_ERR_FRONTIER | TG_ERR_LISTS))
-    return fail(TG_ECAPACITY, "device: node, frontier or list capacity exceeded");
+  if (h & (TG_ERR_NODES | TG_ERR_FRONTIER | TG_ERR_LISTS | TG_ERR_CHAIN))
+    return fail(TG_ECAPACITY, "device: node, frontier, list or selection capacity exceeded");
   if (h & TG_ERR_SORT)
     return fail(TG_EINTERNAL, "device: radix-sort tile hand-off gave up waiting");
   return TG_OK;
