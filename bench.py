@@ -14,8 +14,10 @@ Prints ONE JSON line.  value = interactions/s (P2P pairs + particle-cell
 pairs per second of whole-step wall time) of the mixed-precision path; the
 FP64 path, forces/s, the errors (mixed vs FP64, both vs the direct sum), the
 walk kernel's roofline and the CPU oracle baseline are reported beside it,
-plus measurements of the other workloads (KDK energy check, block steps,
-batched realisations) unless --no-extra.
+plus measurements selected by --extras (default all, none with --no-extra):
+the relative opening test (alpha = 1e-3) on the same step, the chain
+coupling on the same workload, a KDK energy check, block steps and batched
+realisations.
 """
 from __future__ import annotations
 
@@ -55,6 +57,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--extras", default="relative,chain,kdk,blocksteps,batch",
+                    help="comma list of the extra measurements to run")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
@@ -300,6 +304,73 @@ def cpu_baseline(w, leaf, group, seconds):
 
 
 # ---------------------------------------------------------------- extras
+def extra_relative_mac(w, a, alpha=1e-3, steps=10):
+    """The paper's own opening test on the same workload and step: the
+    relative criterion with tolerance alpha (the runs' 1e-3), old
+    accelerations from the previous evaluation (the first from the opening
+    angle).  Returns the timing and the forces at the initial positions."""
+    from paper_1507_01009_amd import binding as B
+    st = Step(w, B.TG_MIXED, a.leaf, a.group, a.waves, a.dt)
+    st.ctx.set_mac(True, alpha)
+    st.ctx.forces(st.d.sys)
+    st.ctx.sync()
+    acc = st.acc.cpu().numpy().copy()
+    r = time_path(st, steps, 2)
+    r["alpha"] = alpha
+    st.ctx.close()
+    return r, acc
+
+
+def extra_chain(w, reps=50):
+    """Chain coupling on the same workload: both SMBHs and the 30 stars
+    nearest to their centre form the chain (the stars stay as excluded
+    ghosts), r_crit = 0.01, gamma_crit = 1e-4.  Times the perturber
+    selection alone and the whole coupling (selection, star terms, member
+    forces, the chain particle with Eq. 3)."""
+    import numpy as np
+    import torch
+    from paper_1507_01009_amd import binding as B
+    r = np.linalg.norm(w.pos, axis=1)
+    ghosts = np.sort(np.argsort(r)[:30])
+    mpos = np.concatenate([w.bh_pos.reshape(-1, 3), w.pos[ghosts]])
+    mmass = np.concatenate([w.bh_mass, w.mass[ghosts]])
+    M, S = 0.0, np.zeros(3)
+    for i in range(mmass.size):
+        M += mmass[i]
+        S += mmass[i] * mpos[i]
+    excl = np.zeros(w.n, np.uint8)
+    excl[ghosts] = 1
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    f64 = dict(dtype=torch.float64, device="cuda")
+    ctx = B.Context(w.n)
+    pos, mass, dm, dmm, dex = t(w.pos), t(w.mass), t(mpos), t(mmass), t(excl)
+    idx = torch.zeros(8192, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ch = ctx.make_chain(pos, mass, dm, dmm, S / M, M, 0.01, 1e-4, idx, cnt, exclude=dex)
+    acc, pot = torch.zeros((w.n, 3), **f64), torch.zeros(w.n, **f64)
+    com, macc = torch.zeros(3, **f64), torch.zeros((mmass.size, 3), **f64)
+    out = {"members": int(mmass.size)}
+    for name, fn in (("perturbers", lambda: ctx.perturbers(ch)),
+                     ("chain_forces", lambda: ctx.chain_forces(ch, acc, com, macc, pot=pot))):
+        fn()
+        ctx.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        out[name + "_us"] = 1e3 * e0.elapsed_time(e1) / reps
+    ctx.sync()
+    out["n_perturbers"] = int(cnt.cpu().numpy()[0])
+    # selection: position, mass, exclusion flag read, 1-byte flag written,
+    # then the flags read again by the compaction
+    out["select_bytes_per_star"] = 24 + 8 + 1 + 1 + 1
+    out["select_GBps_whole_call"] = w.n * 35 / (out["perturbers_us"] * 1e-6) / 1e9
+    ctx.close()
+    return out
+
+
 def extra_kdk_energy(steps=100):
     """Hernquist N = 131 072 + SMBH, dt = 1e-3: both precisions, energy error."""
     import torch
@@ -454,6 +525,14 @@ def main():
         st.ctx.close()
         del st
         torch.cuda.empty_cache()
+    rel = None
+    ex = set() if a.no_extra else set(a.extras.split(","))
+    if "relative" in ex and "mixed" in paths:
+        log("bench: relative opening test, alpha = 1e-3")
+        rel, accs["mixed_relative"] = extra_relative_mac(w, a)
+        log("bench: relative %.3f ms/step, %.3g interactions/step, walk %.3f ms" % (
+            rel["ms_per_step"], rel["interactions_per_step"], rel["walk_ms_avg"]))
+        torch.cuda.empty_cache()
     err = {}
     if "mixed" in accs and "fp64" in accs:
         e = np.linalg.norm(accs["mixed"] - accs["fp64"], axis=1) / np.linalg.norm(accs["fp64"], axis=1)
@@ -467,7 +546,7 @@ def main():
     roof = {"bound": "alu", "achieved": head["walk_tflops"], "peak": peak, "unit": "TFLOP/s",
             "frac": head["walk_tflops"] / peak,
             "traffic": traffic_for("k_walk.hip", "cusp1m"),
-            "kernel": "k_walk_forces<%s>" % ("true" if head_name == "mixed" else "false"),
+            "kernel": "k_walk_forces<%s, false>" % ("true" if head_name == "mixed" else "false"),
             "avg_launch_ms": head["walk_ms_avg"], "flops_per_launch": head["flops_per_walk"],
             "flops_per_interaction": {"p2p": FLOPS_P2P, "p2m": FLOPS_P2M},
             "peak_note": "published FP32 vector peak; the build disables packed FP32, "
@@ -496,13 +575,21 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 2 * src.numel() * 4
         del src, dst
-    if not a.no_extra:
+    if rel is not None:
+        out["relative_mac"] = rel
+    if "chain" in ex:
+        log("bench: chain coupling (same workload)")
+        out["chain"] = extra_chain(w)
+        torch.cuda.empty_cache()
+    if "kdk" in ex:
         log("bench: KDK energy check (Hernquist 131k)")
         out["kdk_energy"] = extra_kdk_energy()
         torch.cuda.empty_cache()
+    if "blocksteps" in ex:
         log("bench: block steps (Hernquist 4M)")
         out["blocksteps"] = extra_blocksteps()
         torch.cuda.empty_cache()
+    if "batch" in ex:
         log("bench: batch of 32 realisations")
         out["batch"] = extra_batch()
         torch.cuda.empty_cache()

@@ -306,6 +306,20 @@ tg_status tg_chain_forces(tg_ctx *ctx, const tg_chain *chain,
                           double *acc_dev, double *pot_dev, double *com_acc_dev,
                           double *member_acc_dev);
 
+/* The perturbers of the last tg_perturbers / tg_chain_forces on this chain
+ * (pert_idx, n_pert), relative to the chain particle and predicted to first
+ * order in time for the chain integration (Sec. 2: perturber positions are
+ * predicted relative to the chain particle at each chain force evaluation):
+ * row k < min(n_pert, pert_cap), j = pert_idx[k]:
+ *   out_pos[k] = (x_j + v_j dt) - (R + V dt),  out_vel[k] = v_j - V,
+ *   out_mass[k] = m_j (out_mass may be NULL),
+ * V = com_vel (host [3]), R + V dt formed on the host; each operation rounded
+ * separately.  vel_dev: [n][3] star velocities; outputs [pert_cap][3] device.
+ * Rows beyond the count are untouched.  Errors: TG_EINVAL. */
+tg_status tg_predict_perturbers(tg_ctx *ctx, const tg_chain *chain, const double *vel_dev,
+                                const double com_vel[3], double dt, double *out_pos_dev,
+                                double *out_vel_dev, double *out_mass_dev);
+
 /* Stars within radius r of center (host [3]): |x - c|^2 < r r, the chain
  * start around an SMBH (r_chain,0) and absorption into the chain (Eq. 4,
  * r_chain about R).  Ascending indices (at most cap) and the count in

@@ -22,6 +22,11 @@ What it computes (Sec. 2, the hybrid method):
   centre-of-mass particle, a point mass M at R, or, if it is a perturber,
   as the resolved members; pairs with the chain are unsoftened by default
   (Sec. 4 softening paragraph), or Plummer-softened with eps_pm.
+* Prediction of the perturbers for the chain integration (the paper
+  predicts their positions relative to the chain particle to first order
+  at each chain force evaluation): for perturber j and a time offset dt,
+      x_rel = (x_j + v_j dt) - (R + V dt),   v_rel = v_j - V,
+  each operation rounded on its own (R + V dt formed first, per axis).
 * Force on the chain particle: the (direct) force of every non-perturber
   star on the point R, plus the correction of Eq. 3,
       a_CoM,corr = (1 / M) sum_i m_i a_i,
@@ -68,6 +73,20 @@ def within(pos, center, r, exclude=None):
     if exclude is not None:
         sel &= ~np.asarray(exclude, bool)
     return np.nonzero(sel)[0].astype(np.int32)
+
+
+def predict(pos, vel, mass, pert, com, com_vel, dt):
+    """Perturbers relative to the chain particle, predicted by dt:
+    (x_rel [k, 3], v_rel [k, 3], m [k]) for the listed perturbers."""
+    P = np.asarray(pert, np.int64)
+    x = np.asarray(pos, np.float64).reshape(-1, 3)[P]
+    v = np.asarray(vel, np.float64).reshape(-1, 3)[P]
+    R = np.asarray(com, np.float64)
+    V = np.asarray(com_vel, np.float64)
+    Rp = R + V * float(dt)
+    xr = (x + v * float(dt)) - Rp[None, :]
+    vr = v - V[None, :]
+    return xr, vr, np.asarray(mass, np.float64)[P]
 
 
 def _field(xs, ms, xt, e2, G):

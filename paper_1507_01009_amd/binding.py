@@ -107,6 +107,7 @@ def lib():
             "tg_perturbers": (st, [P, P]),
             "tg_chain_forces": (st, [P, P, P, P, P, P, P, P]),
             "tg_select_within": (st, [P, P, i64, P, P, f64, P, i32, P]),
+            "tg_predict_perturbers": (st, [P, P, P, P, f64, P, P, P]),
             "tg_forces": (st, [P, P, P, P]),
             "tg_step_kdk": (st, [P, P, f64]),
             "tg_step_dkd": (st, [P, P, f64]),
@@ -137,7 +138,8 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_tree_forces", "tg_get_counts", "tg_reset_counts", "tg_walk_lists",
             "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
             "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac",
-            "tg_perturbers", "tg_chain_forces", "tg_select_within", "tg_forces",
+            "tg_perturbers", "tg_chain_forces", "tg_select_within",
+            "tg_predict_perturbers", "tg_forces",
             "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
@@ -352,6 +354,11 @@ class Context:
                      n_active=None):
         _check(lib().tg_chain_forces(self.h, C.byref(chain), _ptr(active_idx), _ptr(n_active),
                                      _ptr(acc), _ptr(pot), _ptr(com_acc), _ptr(member_acc)))
+
+    def predict_perturbers(self, chain, vel, com_vel, dt, out_pos, out_vel, out_mass=None):
+        v3 = (C.c_double * 3)(*[float(x) for x in com_vel])
+        _check(lib().tg_predict_perturbers(self.h, C.byref(chain), _ptr(vel), v3, float(dt),
+                                           _ptr(out_pos), _ptr(out_vel), _ptr(out_mass)))
 
     def select_within(self, pos, center, r, idx, n_out, exclude=None):
         c3 = (C.c_double * 3)(*[float(x) for x in center])

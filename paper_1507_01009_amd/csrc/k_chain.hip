@@ -9,10 +9,12 @@
 //           rc6 = r_crit^6 (Eq. 2 cubed and squared: no roots),
 //   radius: r2 < r r,
 // with r2 = (dx dx + dy dy) + dz dz about the centre; an exclusion mask
-// (ghost members) clears flags.  The flags are scanned and the indices of
-// the flagged particles scattered in ascending order (stable, so the list
-// is unique); a list beyond its capacity sets TG_ERR_CHAIN.  The pass is
-// bound by HBM: 32 B read per particle (position, mass) and 4 B of flags.
+// (ghost members) clears flags.  Tiles of 1024 particles count their flags;
+// a second pass gives each tile the sum of the earlier counts and scatters
+// the flagged indices in ascending order (stable, so the list is unique); a
+// list beyond its capacity sets TG_ERR_CHAIN.  Both passes are bound by HBM:
+// 33 B read per particle (position, mass, exclusion) and 1 B of flags
+// written, then the flags read once more.
 //
 // Forces (pairs with the chain are Newtonian; perturber-member pairs may be
 // Plummer-softened with eps_pm):
@@ -21,54 +23,96 @@
 //           perturber, the forces of the resolved members (members in LDS,
 //           summed in member order);
 //   chain particle: the point force at R of every non-perturber,
-//           non-excluded star (compensated sums over a fixed grid, then an
-//           ordered pass) plus the Eq. 3 correction (1 / M) sum_i m_i a_i;
+//           non-excluded star (compensated sums over a fixed grid, combined
+//           in a fixed tree order) plus the Eq. 3 correction
+//           (1 / M) sum_i m_i a_i;
 //   members: a_i = force of the perturbers on member i (one block each,
 //           compensated), returned for the chain integration.
+// Prediction: the listed perturbers relative to the chain particle, moved
+// to first order in time (the chain integration evaluates them at many
+// sub-step times), gathered into compact arrays.
 #include "tg_internal.h"
 
 namespace tg {
 
-constexpr int kChainBlocks = 256;   // partial sums of the chain particle's force
+constexpr int kSelItems = 4;                        // elements per thread and tile
+constexpr int kSelTile = 256 * kSelItems;            // elements per selection tile
 
+// Block sum of one value per thread (256 threads); every thread gets it.
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *lds) {
+  for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+// One tile per block: flag each element (1 byte) and count the tile.
 template <bool kTidal>
 __global__ __launch_bounds__(256) void k_chain_flags(const double *__restrict__ pos,
                                                      const double *__restrict__ mass, int64_t n,
                                                      const uint8_t *__restrict__ excl, double cx,
                                                      double cy, double cz, double c, double lim,
-                                                     uint32_t *__restrict__ flag) {
+                                                     uint8_t *__restrict__ flag,
+                                                     uint32_t *__restrict__ tcount) {
 #pragma clang fp contract(off)
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double dx = __dsub_rn(pos[3 * i], cx);
-    const double dy = __dsub_rn(pos[3 * i + 1], cy);
-    const double dz = __dsub_rn(pos[3 * i + 2], cz);
-    const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  __shared__ uint32_t lds[4];
+  const int64_t base = (int64_t)blockIdx.x * kSelTile;
+  uint32_t cnt = 0;
+#pragma unroll 4
+  for (int r = 0; r < kSelItems; ++r) {
+    const int64_t i = base + r * 256 + threadIdx.x;
+    if (i >= n) break;
+    const double dx = dsub(pos[3 * i], cx);
+    const double dy = dsub(pos[3 * i + 1], cy);
+    const double dz = dsub(pos[3 * i + 2], cz);
+    const double r2 = dadd(dadd(dmul(dx, dx), dmul(dy, dy)), dmul(dz, dz));
     bool s;
     if constexpr (kTidal) {
-      const double k = __dmul_rn(c, mass[i]);
-      s = __dmul_rn(__dmul_rn(r2, r2), r2) < __dmul_rn(__dmul_rn(k, k), lim);
+      const double k = dmul(c, mass[i]);
+      s = dmul(dmul(r2, r2), r2) < dmul(dmul(k, k), lim);
     } else {
       s = r2 < lim;
     }
     if (excl && excl[i]) s = false;
-    flag[i] = s ? 1u : 0u;
+    flag[i] = s ? 1 : 0;
+    cnt += s ? 1u : 0u;
   }
+  cnt = block_sum_u32(cnt, lds);
+  if (threadIdx.x == 0) tcount[blockIdx.x] = cnt;
 }
 
-__global__ __launch_bounds__(256) void k_chain_compact(const uint32_t *__restrict__ flag,
-                                                       const uint32_t *__restrict__ off, int64_t n,
-                                                       const uint32_t *__restrict__ total,
-                                                       int32_t *__restrict__ idx, int32_t cap,
-                                                       int32_t *__restrict__ n_out,
+// One tile per block: its offset is the sum of the earlier tiles' counts;
+// ranks inside the tile follow element order (wave ballots, then the four
+// waves in order), so the list is ascending.  The last tile writes the total.
+__global__ __launch_bounds__(256) void k_chain_compact(const uint8_t *__restrict__ flag,
+                                                       const uint32_t *__restrict__ tcount,
+                                                       int64_t n, int32_t *__restrict__ idx,
+                                                       int32_t cap, int32_t *__restrict__ n_out,
                                                        uint32_t *__restrict__ err) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    if (flag[i] && off[i] < (uint32_t)cap) idx[off[i]] = (int32_t)i;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const uint32_t t = *total;
-    *n_out = (int32_t)t;
-    if (t > (uint32_t)cap) atomicOr(err, TG_ERR_CHAIN);
+  __shared__ uint32_t lds[4];
+  __shared__ uint32_t wtot[4];
+  uint32_t before = 0;
+  for (uint32_t u = threadIdx.x; u < blockIdx.x; u += 256) before += tcount[u];
+  uint32_t off = block_sum_u32(before, lds);
+  const int64_t base = (int64_t)blockIdx.x * kSelTile;
+  const unsigned w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r = 0; r < kSelItems; ++r) {
+    const int64_t i = base + r * 256 + threadIdx.x;
+    const bool s = i < n && flag[i];
+    const unsigned long long m = __ballot(s);
+    __syncthreads();
+    if (lane == 0) wtot[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t pre = 0;
+    for (unsigned v = 0; v < w; ++v) pre += wtot[v];
+    const uint32_t rank = off + pre + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (s && rank < (uint32_t)cap) idx[rank] = (int32_t)i;
+    off += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    *n_out = (int32_t)off;
+    if (off > (uint32_t)cap) atomicOr(err, TG_ERR_CHAIN);
   }
 }
 
@@ -87,7 +131,7 @@ __device__ __forceinline__ void chain_pair(double sx, double sy, double sz, doub
 __global__ __launch_bounds__(256) void k_chain_stars(
     const int32_t *__restrict__ idx, const int32_t *__restrict__ n_act, int64_t n,
     const double *__restrict__ pos, const uint8_t *__restrict__ excl,
-    const uint32_t *__restrict__ pflag, const double *__restrict__ mpos,
+    const uint8_t *__restrict__ pflag, const double *__restrict__ mpos,
     const double *__restrict__ mmass, int nc, double Rx, double Ry, double Rz, double M,
     double e2pm, double G, double *__restrict__ acc, double *__restrict__ pot) {
   __shared__ double s_m[4 * kMaxChain];
@@ -140,7 +184,7 @@ __device__ void block_csum3(CSum &a, CSum &b, CSum &c, double *lds) {
 
 __global__ __launch_bounds__(256) void k_chain_com_part(
     const double *__restrict__ pos, const double *__restrict__ mass, int64_t n,
-    const uint8_t *__restrict__ excl, const uint32_t *__restrict__ pflag, double Rx, double Ry,
+    const uint8_t *__restrict__ excl, const uint8_t *__restrict__ pflag, double Rx, double Ry,
     double Rz, double *__restrict__ part) {
   __shared__ double lds[6 * 256];
   CSum sx, sy, sz;
@@ -181,22 +225,54 @@ __global__ __launch_bounds__(256) void k_chain_members(
   }
 }
 
-// The chain particle: ordered sum of the block partials, then Eq. 3.
-__global__ void k_chain_com_final(const double *__restrict__ part, int nb,
-                                  const double *__restrict__ macc,
-                                  const double *__restrict__ mmass, int nc, double M, double G,
-                                  double *__restrict__ com_acc) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  CSum s[3], q[3];
-  for (int b = 0; b < nb; ++b)
-    for (int k = 0; k < 3; ++k) {
-      CSum o;
-      o.s = part[6 * b + 2 * k]; o.c = part[6 * b + 2 * k + 1];
-      s[k].merge(o);
+// The chain particle: the block partials in a fixed tree order (each thread
+// first merges kChainBlocks / 256 of them in block order), then Eq. 3.
+__global__ __launch_bounds__(256) void k_chain_com_final(const double *__restrict__ part,
+                                                         const double *__restrict__ macc,
+                                                         const double *__restrict__ mmass,
+                                                         int nc, double M, double G,
+                                                         double *__restrict__ com_acc) {
+  __shared__ double lds[6 * 256];
+  CSum sx, sy, sz;
+  for (int b = threadIdx.x * (kChainBlocks / 256); b < (threadIdx.x + 1) * (kChainBlocks / 256);
+       ++b) {
+    CSum o;
+    o.s = part[6 * b]; o.c = part[6 * b + 1]; sx.merge(o);
+    o.s = part[6 * b + 2]; o.c = part[6 * b + 3]; sy.merge(o);
+    o.s = part[6 * b + 4]; o.c = part[6 * b + 5]; sz.merge(o);
+  }
+  block_csum3(sx, sy, sz, lds);
+  if (threadIdx.x == 0) {
+    CSum q[3];
+    for (int i = 0; i < nc; ++i)
+      for (int k = 0; k < 3; ++k) q[k].add(mmass[i] * macc[3 * i + k]);
+    com_acc[0] = G * sx.get() + q[0].get() / M;
+    com_acc[1] = G * sy.get() + q[1].get() / M;
+    com_acc[2] = G * sz.get() + q[2].get() / M;
+  }
+}
+
+// Perturbers relative to the chain particle, predicted to first order:
+// x_rel = (x + v dt) - Rp, v_rel = v - V (Rp = R + V dt formed on the host).
+__global__ __launch_bounds__(256) void k_chain_predict(
+    const int32_t *__restrict__ pidx, const int32_t *__restrict__ n_pert, int32_t cap,
+    const double *__restrict__ pos, const double *__restrict__ vel,
+    const double *__restrict__ mass, double dt, double Rx, double Ry, double Rz, double Vx,
+    double Vy, double Vz, double *__restrict__ out_pos, double *__restrict__ out_vel,
+    double *__restrict__ out_mass) {
+#pragma clang fp contract(off)
+  const int np = min(max(n_pert[0], 0), cap);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x) {
+    const int64_t j = pidx[k];
+    const double R[3] = {Rx, Ry, Rz}, V[3] = {Vx, Vy, Vz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double x = pos[3 * j + a], v = vel[3 * j + a];
+      out_pos[3 * k + a] = dsub(dadd(x, dmul(v, dt)), R[a]);
+      out_vel[3 * k + a] = dsub(v, V[a]);
     }
-  for (int i = 0; i < nc; ++i)
-    for (int k = 0; k < 3; ++k) q[k].add(mmass[i] * macc[3 * i + k]);
-  for (int k = 0; k < 3; ++k) com_acc[k] = G * s[k].get() + q[k].get() / M;
+    if (out_mass) out_mass[k] = mass[j];
+  }
 }
 
 static int grid_for(int64_t n) {
@@ -208,17 +284,24 @@ hipError_t launch_chain_select(tg_ctx *c, const double *pos, const double *mass,
                                double cst, double lim, int32_t *idx, int32_t cap,
                                int32_t *n_out) {
   Buffers &b = c->b;
+  const int tiles = (int)((n + kSelTile - 1) / kSelTile);
   if (tidal)
-    hipLaunchKernelGGL(k_chain_flags<true>, dim3(grid_for(n)), dim3(256), 0, c->stream, pos,
-                       mass, n, excl, center[0], center[1], center[2], cst, lim, b.cflag);
+    hipLaunchKernelGGL(k_chain_flags<true>, dim3(tiles), dim3(256), 0, c->stream, pos, mass, n,
+                       excl, center[0], center[1], center[2], cst, lim, b.cflag, b.ctile);
   else
-    hipLaunchKernelGGL(k_chain_flags<false>, dim3(grid_for(n)), dim3(256), 0, c->stream, pos,
-                       mass, n, excl, center[0], center[1], center[2], cst, lim, b.cflag);
-  hipError_t e = scan_u32(b.cflag, b.coff, (uint32_t)n, nullptr, b.scan_total, b.scan_part,
-                          c->stream);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chain_compact, dim3(grid_for(n)), dim3(256), 0, c->stream, b.cflag,
-                     b.coff, n, b.scan_total, idx, cap, n_out, b.err);
+    hipLaunchKernelGGL(k_chain_flags<false>, dim3(tiles), dim3(256), 0, c->stream, pos, mass, n,
+                       excl, center[0], center[1], center[2], cst, lim, b.cflag, b.ctile);
+  hipLaunchKernelGGL(k_chain_compact, dim3(tiles), dim3(256), 0, c->stream, b.cflag, b.ctile, n,
+                     idx, cap, n_out, b.err);
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_predict(tg_ctx *c, const tg_chain *ch, const double *vel, double dt,
+                                const double rp[3], const double v[3], double *out_pos,
+                                double *out_vel, double *out_mass) {
+  hipLaunchKernelGGL(k_chain_predict, dim3(grid_for(ch->pert_cap)), dim3(256), 0, c->stream,
+                     ch->pert_idx, ch->n_pert, ch->pert_cap, ch->pos, vel, ch->mass, dt, rp[0],
+                     rp[1], rp[2], v[0], v[1], v[2], out_pos, out_vel, out_mass);
   return hipGetLastError();
 }
 
@@ -242,9 +325,8 @@ hipError_t launch_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx
   hipLaunchKernelGGL(k_chain_members, dim3(ch->nc), dim3(256), 0, c->stream, ch->member_pos,
                      ch->pert_idx, ch->n_pert, ch->pert_cap, ch->pos, ch->mass, e2pm, G,
                      member_acc);
-  hipLaunchKernelGGL(k_chain_com_final, dim3(1), dim3(64), 0, c->stream, b.cpart,
-                     kChainBlocks, member_acc, ch->member_mass, ch->nc, ch->m_chain, G,
-                     com_acc);
+  hipLaunchKernelGGL(k_chain_com_final, dim3(1), dim3(256), 0, c->stream, b.cpart, member_acc,
+                     ch->member_mass, ch->nc, ch->m_chain, G, com_acc);
   return hipGetLastError();
 }
 

@@ -114,8 +114,8 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
 }
 
 __device__ __forceinline__ uint64_t quantise(double x, double lo, double sigma) {
-  double t = __dsub_rn(x, lo);
-  double u = __dmul_rn(t, sigma);
+  double t = dsub(x, lo);
+  double u = dmul(t, sigma);
   double f = floor(u);
   uint64_t q = f <= 0.0 ? 0ull : (uint64_t)f;
   return q > 0x1FFFFFull ? 0x1FFFFFull : q;

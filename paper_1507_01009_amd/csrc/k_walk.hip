@@ -115,19 +115,19 @@ __device__ __forceinline__ double box_d2(const double lo[3], const double hi[3],
 #pragma clang fp contract(off)
   double d2 = 0.0;
   {
-    double a = __dsub_rn(lo[0], c.x), b = __dsub_rn(c.x, hi[0]);
+    double a = dsub(lo[0], c.x), b = dsub(c.x, hi[0]);
     const double m = fmax(fmax(a, b), 0.0);
-    d2 = __dadd_rn(d2, __dmul_rn(m, m));
+    d2 = dadd(d2, dmul(m, m));
   }
   {
-    double a = __dsub_rn(lo[1], c.y), b = __dsub_rn(c.y, hi[1]);
+    double a = dsub(lo[1], c.y), b = dsub(c.y, hi[1]);
     const double m = fmax(fmax(a, b), 0.0);
-    d2 = __dadd_rn(d2, __dmul_rn(m, m));
+    d2 = dadd(d2, dmul(m, m));
   }
   {
-    double a = __dsub_rn(lo[2], c.z), b = __dsub_rn(c.z, hi[2]);
+    double a = dsub(lo[2], c.z), b = dsub(c.z, hi[2]);
     const double m = fmax(fmax(a, b), 0.0);
-    d2 = __dadd_rn(d2, __dmul_rn(m, m));
+    d2 = dadd(d2, dmul(m, m));
   }
   return d2;
 }
@@ -135,7 +135,7 @@ __device__ __forceinline__ double box_d2(const double lo[3], const double hi[3],
 // Opening-angle test: accept iff side^2 < theta^2 d^2 (c.w = side^2).
 __device__ __forceinline__ bool mac_accept(const double lo[3], const double hi[3],
                                            double4 c, double th2) {
-  return c.w < __dmul_rn(th2, box_d2(lo, hi, c));
+  return c.w < dmul(th2, box_d2(lo, hi, c));
 }
 
 // Relative test: accept iff P P <= A (d^2 d^2)(d^2 d^2), P = (G M) s^2,
@@ -144,8 +144,8 @@ __device__ __forceinline__ bool mac_accept(const double lo[3], const double hi[3
 __device__ __forceinline__ bool mac_rel(const double lo[3], const double hi[3], double4 c,
                                         double4 r0, double4 r1, double A) {
   const double d2 = box_d2(lo, hi, c);
-  const double d4 = __dmul_rn(d2, d2);
-  const bool near = __dmul_rn(r0.w, r0.w) <= __dmul_rn(A, __dmul_rn(d4, d4));
+  const double d4 = dmul(d2, d2);
+  const bool near = dmul(r0.w, r0.w) <= dmul(A, dmul(d4, d4));
   const bool apart = lo[0] > r1.x || hi[0] < r0.x || lo[1] > r1.y || hi[1] < r0.y ||
                      lo[2] > r1.z || hi[2] < r0.z;
   return near && apart;
@@ -791,8 +791,8 @@ __global__ __launch_bounds__(256) void k_group_active(const int32_t *__restrict_
         any = true;
         if (acc_old) {
           const double *ao = acc_old + 3 * (size_t)perm[gr.x + j];
-          const double a2 = __dadd_rn(__dadd_rn(__dmul_rn(ao[0], ao[0]), __dmul_rn(ao[1], ao[1])),
-                                      __dmul_rn(ao[2], ao[2]));
+          const double a2 = dadd(dadd(dmul(ao[0], ao[0]), dmul(ao[1], ao[1])),
+                                      dmul(ao[2], ao[2]));
           a2min = fmin(a2min, a2);
         }
       }
@@ -806,7 +806,7 @@ __global__ __launch_bounds__(256) void k_group_active(const int32_t *__restrict_
       aflag[g] = mine ? 1u : 0u;
       double *b = abox + 6 * (size_t)g;
       b[0] = lx; b[1] = ly; b[2] = lz; b[3] = hx; b[4] = hy; b[5] = hz;
-      if (acc_old) arel[g] = mine ? __dmul_rn(alpha2, a2min) : 0.0;
+      if (acc_old) arel[g] = mine ? dmul(alpha2, a2min) : 0.0;
     }
   }
 }
@@ -940,15 +940,15 @@ __global__ __launch_bounds__(256) void k_rel_records(const int32_t *__restrict__
       ic[1] |= ((d >> 1) & 1u) << j;
       ic[2] |= (d & 1u) << j;
     }
-    const double h = __dmul_rn(0.6, s);
+    const double h = dmul(0.6, s);
     double lo[3], hi[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double g = __dadd_rn(cb[k], __dmul_rn(__dadd_rn((double)ic[k], 0.5), s));
-      lo[k] = __dsub_rn(g, h);
-      hi[k] = __dadd_rn(g, h);
+      const double g = dadd(cb[k], dmul(dadd((double)ic[k], 0.5), s));
+      lo[k] = dsub(g, h);
+      hi[k] = dadd(g, h);
     }
-    const double P = __dmul_rn(__dmul_rn(G, mom[8 * (size_t)v]), __dmul_rn(s, s));
+    const double P = dmul(dmul(G, mom[8 * (size_t)v]), dmul(s, s));
     rel[2 * (size_t)v] = make_double4(lo[0], lo[1], lo[2], P);
     rel[2 * (size_t)v + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
   }

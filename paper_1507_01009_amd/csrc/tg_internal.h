@@ -34,6 +34,7 @@ constexpr int kScanBlocks = 256;
 constexpr int kMaxWavesPerCU = 16;
 constexpr int kMaxExternal = 1024;               // SMBHs / external point masses
 constexpr int kMaxChain = 256;                   // chain members
+constexpr int kChainBlocks = 1024;               // partial sums of the chain particle's force
 constexpr int kSegSlots = 8;                     // cached direct-sum segment tables
 constexpr int kSegSlotLen = 2 * (kMaxSys + 1);
 
@@ -97,9 +98,9 @@ struct Buffers {
   double *abox = nullptr;         // [N][6] box of active targets per group
   double *arel = nullptr;         // [N] relative test: (alpha alpha) min |a_old|^2 per group
   // chain coupling
-  uint32_t *cflag = nullptr;      // [N + 1] selection flags (the perturber mask after Eq. 2)
-  uint32_t *coff = nullptr;       // [N + 1] their exclusive scan
-  double *cpart = nullptr;        // [256][6] compensated partials of the chain particle's force
+  uint8_t *cflag = nullptr;       // [N + 1] selection flags (the perturber mask after Eq. 2)
+  uint32_t *ctile = nullptr;      // [N / 1024 + 2] flags per 1024-particle tile
+  double *cpart = nullptr;        // [kChainBlocks][6] compensated partials of the chain particle's force
   uint8_t *sact = nullptr;        // [N] active flag per sorted particle
   // walk
   uint32_t *frontier = nullptr;   // [waves][2][frontier_cap]
@@ -188,6 +189,23 @@ hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s,
 hipError_t fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s,
                    const int32_t *gate = nullptr);
 
+// Separately rounded double operations for the decisions that must equal
+// the plain definition bit for bit (keys, opening tests, selections): the
+// operations are created without the contraction flag, so the backend never
+// fuses them into FMAs, whatever the caller's contraction setting.
+__device__ __forceinline__ double dmul(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+__device__ __forceinline__ double dadd(double a, double b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+__device__ __forceinline__ double dsub(double a, double b) {
+#pragma clang fp contract(off)
+  return a - b;
+}
+
 // Compensated double sum (error-free TwoSum with a running correction),
 // used by the direct sums and the chain coupling.
 struct CSum {
@@ -237,6 +255,9 @@ hipError_t launch_chain_select(tg_ctx *c, const double *pos, const double *mass,
                                const uint8_t *excl, const double center[3], bool tidal,
                                double cst, double lim, int32_t *idx, int32_t cap,
                                int32_t *n_out);
+hipError_t launch_chain_predict(tg_ctx *c, const tg_chain *ch, const double *vel, double dt,
+                                const double rp[3], const double v[3], double *out_pos,
+                                double *out_vel, double *out_mass);
 hipError_t launch_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx,
                                const int32_t *n_act, double *acc, double *pot,
                                double *com_acc, double *member_acc);

@@ -149,7 +149,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.aflag, N + 1));
   A(dalloc(&b.alist, N));
   A(dalloc(&b.abox, 6 * N)); A(dalloc(&b.arel, N));
-  A(dalloc(&b.cflag, N + 1)); A(dalloc(&b.coff, N + 1)); A(dalloc(&b.cpart, 6 * 256));
+  A(dalloc(&b.cflag, N + 1)); A(dalloc(&b.ctile, N / 1024 + 2)); A(dalloc(&b.cpart, 6 * kChainBlocks));
   A(dalloc(&b.sact, N));
   A(dalloc(&b.frontier, waves * 2 * (int64_t)cfg.frontier_cap));
   A(dalloc(&b.wl_count, 2 * N + 2));
@@ -988,8 +988,28 @@ tg_status tg_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx,
   if (idx && !n_act) return fail(TG_EINVAL, "tg_chain_forces: n_active required");
   if (!com_acc || !member_acc) return fail(TG_EINVAL, "tg_chain_forces: NULL outputs");
   if ((st = tg_perturbers(c, ch)) != TG_OK) return st;
-  if (ch->n == 0) TG_HIP(fill_u32(c->b.cflag, 0u, 1, c->stream));
   TG_HIP(launch_chain_forces(c, ch, idx, n_act, acc, pot, com_acc, member_acc));
+  return TG_OK;
+}
+
+tg_status tg_predict_perturbers(tg_ctx *c, const tg_chain *ch, const double *vel,
+                                const double com_vel[3], double dt, double *out_pos,
+                                double *out_vel, double *out_mass) {
+#pragma clang fp contract(off)
+  tg_status st = check_chain(c, ch, "tg_predict_perturbers");
+  if (st != TG_OK) return st;
+  if (!com_vel || !std::isfinite(dt))
+    return fail(TG_EINVAL, "tg_predict_perturbers: NULL com_vel or non-finite dt");
+  if (ch->pert_cap > 0 && (!out_pos || !out_vel || (ch->n > 0 && !vel)))
+    return fail(TG_EINVAL, "tg_predict_perturbers: NULL outputs");
+  if (ch->pert_cap == 0 || ch->n == 0) return TG_OK;
+  double rp[3], v[3];
+  for (int k = 0; k < 3; ++k) {
+    const double t = com_vel[k] * dt;
+    rp[k] = ch->com[k] + t;
+    v[k] = com_vel[k];
+  }
+  TG_HIP(launch_chain_predict(c, ch, vel, dt, rp, v, out_pos, out_vel, out_mass));
   return TG_OK;
 }
 

@@ -171,3 +171,28 @@ def test_capacity_and_errors():
     ctx.sync()
     assert int(d["np"].cpu().numpy()[0]) == 0
     assert np.all(com_acc.cpu().numpy() == 0) and np.all(macc.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("n,dt", [(262144, 0.0), (262144, 3e-4), (1048576, -2e-5)])
+def test_prediction_bit_exact(n, dt):
+    say("predict", n, dt)
+    import torch
+    from paper_1507_01009_amd import binding as B
+    w, mpos, mmass, R, M, excl = _setup(n)
+    ctx = B.Context(n)
+    d = _dev_chain(ctx, w, mpos, mmass, R, M, excl, 8192)
+    ctx.perturbers(d["ch"])
+    V = np.array([0.03, -0.11, 0.007])
+    f64 = dict(dtype=torch.float64, device="cuda")
+    op = torch.full((8192, 3), 7.0, **f64)
+    ov = torch.full((8192, 3), 7.0, **f64)
+    om = torch.full((8192,), 7.0, **f64)
+    ctx.predict_perturbers(d["ch"], to_dev(w.vel), V, dt, op, ov, om)
+    ctx.sync()
+    pert = ochain.perturbers(w.pos, w.mass, R, M, RC[n], 1e-4, exclude=excl)
+    xr, vr, m = ochain.predict(w.pos, w.vel, w.mass, pert, R, V, dt)
+    k = pert.size
+    assert np.array_equal(op.cpu().numpy()[:k], xr)
+    assert np.array_equal(ov.cpu().numpy()[:k], vr)
+    assert np.array_equal(om.cpu().numpy()[:k], m)
+    assert np.all(op.cpu().numpy()[k:] == 7.0)

@@ -138,3 +138,19 @@ def test_excluded_stars_get_nothing_and_give_nothing():
     _, _, a_com2, _ = chain.coupling(pos2, mass, np.arange(2000), R, M, mpos, mmass,
                                      pert, exclude=ex)
     assert np.array_equal(a_com, a_com2)
+
+
+def test_prediction_is_first_order_and_relative():
+    pos, mass = _cloud(4000, 9)
+    rng = np.random.default_rng(10)
+    vel = rng.normal(size=(4000, 3))
+    mpos, mmass, R, M = _chain(11)
+    V = np.array([0.1, -0.2, 0.05])
+    pert = chain.perturbers(pos, mass, R, M, 0.02, 1e-4)
+    xr0, vr0, m0 = chain.predict(pos, vel, mass, pert, R, V, 0.0)
+    assert np.array_equal(xr0, pos[pert] - R) and np.array_equal(m0, mass[pert])
+    assert np.allclose(vr0, vel[pert] - V, rtol=0, atol=1e-15)
+    # a straight line: the relative position moves with the relative velocity
+    xr1, vr1, _ = chain.predict(pos, vel, mass, pert, R, V, 1e-3)
+    assert np.allclose(xr1, xr0 + 1e-3 * vr0, rtol=0, atol=1e-14)
+    assert np.array_equal(vr1, vr0)
