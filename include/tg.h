@@ -340,6 +340,10 @@ typedef struct {
   int32_t n_bh;
   const int64_t *bh_seg;           /* host [n_sys+1]: SMBHs of each system */
   double eps, theta;               /* star softening, opening angle (see tg_set_mac) */
+  const uint8_t *frozen;           /* [n] nonzero: star held still in the steps (a ghost chain
+                                      member, Sec. 2: not advanced and never active, so it
+                                      sets no time-step; it stays a source of its tiny
+                                      mass); NULL: none */
 } tg_system;
 
 /* Forces for the listed stars (all when active_idx_dev is NULL): tree +

@@ -10,6 +10,8 @@ Composes the oracle's primitives in the order of the paper's hybrid step
   SMBH feels all stars of its system and the other SMBHs (Sec. 2, the
   perturber / chain force-correction paragraph).
 * KDK step: v += a dt/2 (stars, SMBHs), x += v dt, forces, v += a dt/2.
+* Frozen stars (ghost chain members, Sec. 2) are never kicked, drifted or
+  active; they stay sources of the tree forces.
 * block substep (power-of-two levels, smallest step dt_min):
   closing half kicks of the stars active at k (not at k = 0) with their old
   level, new levels at k, opening half kicks with the new level, SMBH half
@@ -41,6 +43,7 @@ class State:
     leaf_size: int = 8
     group_size: int = 64
     alpha: float = None      # relative opening test (None: opening angle theta)
+    frozen: np.ndarray = None  # bool [n]: stars held still (ghost chain members)
     acc: np.ndarray = field(default=None)
     pot: np.ndarray = field(default=None)
     bh_acc: np.ndarray = field(default=None)
@@ -87,15 +90,39 @@ def forces(st: State, active=None):
     return ev
 
 
+def _moving(st: State):
+    """Indices of the stars that move (all unless some are frozen)."""
+    if st.frozen is None:
+        return None
+    return np.nonzero(~np.asarray(st.frozen, bool))[0]
+
+
+def _kick_stars(st: State, dt, idx=None, level=None):
+    mv = _moving(st)
+    if mv is not None:
+        idx = mv if idx is None else np.asarray(idx)[~np.asarray(st.frozen, bool)[idx]]
+    oracle.kick(st.vel, st.acc, dt, idx=idx, level=level)
+
+
+def _drift_stars(st: State, dt):
+    mv = _moving(st)
+    if mv is None:
+        oracle.drift(st.pos, st.vel, dt)
+        return
+    p = np.ascontiguousarray(st.pos[mv])
+    oracle.drift(p, np.ascontiguousarray(st.vel[mv]), dt)
+    st.pos[mv] = p
+
+
 def kdk_step(st: State, dt: float):
-    oracle.kick(st.vel, st.acc, dt)
+    _kick_stars(st, dt)
     if st.bh_mass.size:
         oracle.kick(st.bh_vel, st.bh_acc, dt)
-    oracle.drift(st.pos, st.vel, dt)
+    _drift_stars(st, dt)
     if st.bh_mass.size:
         oracle.drift(st.bh_pos, st.bh_vel, dt)
     forces(st)
-    oracle.kick(st.vel, st.acc, dt)
+    _kick_stars(st, dt)
     if st.bh_mass.size:
         oracle.kick(st.bh_vel, st.bh_acc, dt)
 
@@ -103,16 +130,23 @@ def kdk_step(st: State, dt: float):
 def dkd_step(st: State, dt: float):
     """Drift-kick-drift (Sec. 2, step 6): x += v dt/2, forces, v += a dt,
     x += v dt/2 (stars and SMBHs)."""
-    oracle.drift(st.pos, st.vel, 0.5 * dt)
+    _drift_stars(st, 0.5 * dt)
     if st.bh_mass.size:
         oracle.drift(st.bh_pos, st.bh_vel, 0.5 * dt)
     forces(st)
-    oracle.kick(st.vel, st.acc, 2.0 * dt)          # kick() applies half its dt
+    _kick_stars(st, 2.0 * dt)                      # kick() applies half its dt
     if st.bh_mass.size:
         oracle.kick(st.bh_vel, st.bh_acc, 2.0 * dt)
-    oracle.drift(st.pos, st.vel, 0.5 * dt)
+    _drift_stars(st, 0.5 * dt)
     if st.bh_mass.size:
         oracle.drift(st.bh_pos, st.bh_vel, 0.5 * dt)
+
+
+def _active(st: State, level, nlev, k):
+    act = oracle.active_at(level, nlev, k)
+    if st.frozen is not None:
+        act = act[~np.asarray(st.frozen, bool)[act]]
+    return act
 
 
 def block_substep(st: State, level: np.ndarray, tau4eps2: np.ndarray, k: int,
@@ -120,7 +154,7 @@ def block_substep(st: State, level: np.ndarray, tau4eps2: np.ndarray, k: int,
     """One substep at counter k; returns k + 1 and the new active set.  With
     tau2eps2v the levels also take the velocity criterion."""
     dt_min = dt_max * 2.0 ** -(nlev - 1)
-    act = oracle.active_at(level, nlev, k)
+    act = _active(st, level, nlev, k)
     if k > 0:
         oracle.kick(st.vel, st.acc, dt_max, idx=act, level=level)
         if st.bh_mass.size:
@@ -133,10 +167,10 @@ def block_substep(st: State, level: np.ndarray, tau4eps2: np.ndarray, k: int,
     oracle.kick(st.vel, st.acc, dt_max, idx=act, level=level)
     if st.bh_mass.size:
         oracle.kick(st.bh_vel, st.bh_acc, dt_min)
-    oracle.drift(st.pos, st.vel, dt_min)
+    _drift_stars(st, dt_min)
     if st.bh_mass.size:
         oracle.drift(st.bh_pos, st.bh_vel, dt_min)
     k += 1
-    act = oracle.active_at(level, nlev, k)
+    act = _active(st, level, nlev, k)
     forces(st, act)
     return k, act

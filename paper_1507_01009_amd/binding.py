@@ -50,7 +50,7 @@ class tg_system(C.Structure):
                 ("bh_pos", C.c_void_p), ("bh_vel", C.c_void_p), ("bh_acc", C.c_void_p),
                 ("bh_pot", C.c_void_p), ("bh_mass", C.c_void_p), ("bh_eps", C.c_void_p),
                 ("n_bh", C.c_int32), ("bh_seg", C.c_void_p), ("eps", C.c_double),
-                ("theta", C.c_double)]
+                ("theta", C.c_double), ("frozen", C.c_void_p)]
 
 
 class tg_blocks(C.Structure):
@@ -368,8 +368,9 @@ class Context:
     # -- whole steps
     def make_system(self, pos, vel, acc, mass, eps, theta, pot=None, sys_off=None,
                     bh_pos=None, bh_vel=None, bh_acc=None, bh_mass=None, bh_eps=None,
-                    bh_pot=None, bh_seg=None):
-        """A tg_system describing device tensors (kept alive by the caller)."""
+                    bh_pot=None, bh_seg=None, frozen=None):
+        """A tg_system describing device tensors (kept alive by the caller);
+        frozen: uint8 [n] device mask of stars held still in the steps."""
         y = tg_system()
         y.pos, y.vel, y.acc, y.pot = (_ptr(pos), _ptr(vel), _ptr(acc), _ptr(pot))
         y.mass, y.n = _ptr(mass), pos.shape[0]
@@ -382,6 +383,7 @@ class Context:
         bs, bp = _i64_host(bh_seg)
         y.bh_seg = bp
         y.eps, y.theta = float(eps), float(theta)
+        y.frozen = _ptr(frozen)
         y._keep = (so, bs)   # host arrays must outlive the calls
         return y
 

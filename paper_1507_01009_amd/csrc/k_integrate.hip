@@ -18,7 +18,8 @@ __global__ void k_kick(double *__restrict__ vel, const double *__restrict__ acc,
                        int64_t n, const int32_t *__restrict__ idx,
                        const int32_t *__restrict__ n_act,
                        const uint8_t *__restrict__ level, double dt,
-                       const int64_t *__restrict__ kctr, int skip_k0) {
+                       const int64_t *__restrict__ kctr, int skip_k0,
+                       const uint8_t *__restrict__ frozen) {
 #pragma clang fp contract(off)
   if (skip_k0 && kctr && kctr[0] == 0) return;
   const int64_t m = idx ? min((int64_t)n_act[0], n) : n;
@@ -26,7 +27,7 @@ __global__ void k_kick(double *__restrict__ vel, const double *__restrict__ acc,
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx ? (int64_t)idx[t] : t;
-    if (i < 0 || i >= n) continue;
+    if (i < 0 || i >= n || (frozen && frozen[i])) continue;
     const double h = level ? ldexp(dt, -(int)level[i]) * 0.5 : h0;
     vel[3 * i + 0] = vel[3 * i + 0] + acc[3 * i + 0] * h;
     vel[3 * i + 1] = vel[3 * i + 1] + acc[3 * i + 1] * h;
@@ -35,11 +36,11 @@ __global__ void k_kick(double *__restrict__ vel, const double *__restrict__ acc,
 }
 
 __global__ void k_drift(double *__restrict__ pos, const double *__restrict__ vel,
-                        int64_t n3, double dt) {
+                        int64_t n3, double dt, const uint8_t *__restrict__ frozen) {
 #pragma clang fp contract(off)
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3;
        i += (int64_t)gridDim.x * blockDim.x)
-    pos[i] = pos[i] + vel[i] * dt;
+    if (!frozen || !frozen[i / 3]) pos[i] = pos[i] + vel[i] * dt;
 }
 
 __device__ __forceinline__ int lmin_at(int64_t k, int nlev) {
@@ -82,12 +83,14 @@ __global__ void k_levels(const double *__restrict__ acc,
 
 __global__ void k_active_flags(const uint8_t *__restrict__ level, int64_t n,
                                int nlev, const int64_t *__restrict__ kctr,
-                               int k_add, uint32_t *__restrict__ flag) {
+                               int k_add, const uint8_t *__restrict__ frozen,
+                               uint32_t *__restrict__ flag) {
   const int64_t k = (kctr ? kctr[0] : 0) + k_add;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int l = min((int)level[i], nlev - 1);
-    flag[i] = (k % ((int64_t)1 << (nlev - 1 - l))) == 0 ? 1u : 0u;
+    const bool on = (k % ((int64_t)1 << (nlev - 1 - l))) == 0 && !(frozen && frozen[i]);
+    flag[i] = on ? 1u : 0u;
   }
 }
 
@@ -113,18 +116,18 @@ static inline int grid_n(int64_t n) {
 hipError_t launch_kick(tg_ctx *c, double *vel, const double *acc, int64_t n,
                        const int32_t *idx, const int32_t *n_act,
                        const uint8_t *level, double dt, const int64_t *k,
-                       int skip_k0) {
+                       int skip_k0, const uint8_t *frozen) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_kick, dim3(grid_n(n)), dim3(256), 0, c->stream, vel, acc,
-                     n, idx, n_act, level, dt, k, skip_k0);
+                     n, idx, n_act, level, dt, k, skip_k0, frozen);
   return hipGetLastError();
 }
 
 hipError_t launch_drift(tg_ctx *c, double *pos, const double *vel, int64_t n,
-                        double dt) {
+                        double dt, const uint8_t *frozen) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_drift, dim3(grid_n(3 * n)), dim3(256), 0, c->stream, pos,
-                     vel, 3 * n, dt);
+                     vel, 3 * n, dt, frozen);
   return hipGetLastError();
 }
 
@@ -142,11 +145,11 @@ hipError_t launch_levels(tg_ctx *c, const double *acc, const double *vel,
 // sized for max_particles entries.
 hipError_t launch_active_set(tg_ctx *c, const uint8_t *level, int64_t n,
                              int nlev, const int64_t *k, int k_add,
-                             int32_t *idx, int32_t *n_out) {
+                             int32_t *idx, int32_t *n_out, const uint8_t *frozen) {
   Buffers &b = c->b;
   if (n == 0) return fill_u32((uint32_t *)n_out, 0u, 1, c->stream);
   hipLaunchKernelGGL(k_active_flags, dim3(grid_n(n)), dim3(256), 0, c->stream,
-                     level, n, nlev, k, k_add, b.wl_count);
+                     level, n, nlev, k, k_add, frozen, b.wl_count);
   hipError_t e = scan_u32(b.wl_count, b.wl_off, (uint32_t)n, nullptr,
                           b.scan_total, b.scan_part, c->stream);
   if (e != hipSuccess) return e;

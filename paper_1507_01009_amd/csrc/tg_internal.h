@@ -271,19 +271,20 @@ hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
                          double *acc, double *pot);
 
 // k_integrate.hip
+// frozen: [n] nonzero = star held still (ghost chain members in whole steps)
 hipError_t launch_kick(tg_ctx *c, double *vel, const double *acc, int64_t n,
                        const int32_t *idx, const int32_t *n_act,
                        const uint8_t *level, double dt, const int64_t *k,
-                       int skip_k0);
+                       int skip_k0, const uint8_t *frozen = nullptr);
 hipError_t launch_drift(tg_ctx *c, double *pos, const double *vel, int64_t n,
-                        double dt);
+                        double dt, const uint8_t *frozen = nullptr);
 hipError_t launch_levels(tg_ctx *c, const double *acc, const double *vel,
                          const double *t4e2, const double *t2e2v, int64_t n,
                          const int32_t *idx, const int32_t *n_act, double dt_max, int nlev,
                          const int64_t *k, uint8_t *level);
 hipError_t launch_active_set(tg_ctx *c, const uint8_t *level, int64_t n,
                              int nlev, const int64_t *k, int k_add,
-                             int32_t *idx, int32_t *n_out);
+                             int32_t *idx, int32_t *n_out, const uint8_t *frozen = nullptr);
 hipError_t launch_counter_add(tg_ctx *c, int64_t *k, int64_t inc);
 
 // ---- small device helpers ----

@@ -590,27 +590,41 @@ static tg_status tg_direct_fp64_eps(tg_ctx *c, const double *spos, const double 
   return TG_OK;
 }
 
-tg_status tg_kick(tg_ctx *c, double *vel, const double *acc, int64_t n,
-                  const int32_t *idx, const int32_t *n_act,
-                  const uint8_t *level, double dt, const int64_t *k,
-                  int32_t skip_k0) {
+// Kick, drift and active set with an optional mask of frozen stars (ghost
+// chain members inside whole steps: no kick, no drift, never active).
+static tg_status kick_impl(tg_ctx *c, double *vel, const double *acc, int64_t n,
+                           const int32_t *idx, const int32_t *n_act, const uint8_t *level,
+                           double dt, const int64_t *k, int32_t skip_k0,
+                           const uint8_t *frozen) {
   if (!c) return fail(TG_EINVAL, "tg_kick: NULL context");
   if (n < 0) return fail(TG_EINVAL, "tg_kick: negative n");
   if (n > 0 && (!vel || !acc)) return fail(TG_EINVAL, "tg_kick: NULL pointer");
   if (idx && !n_act) return fail(TG_EINVAL, "tg_kick: n_active required");
   if (skip_k0 && !k) return fail(TG_EINVAL, "tg_kick: skip_at_k0 needs k");
   if (!std::isfinite(dt)) return fail(TG_EINVAL, "tg_kick: dt not finite");
-  TG_HIP(launch_kick(c, vel, acc, n, idx, n_act, level, dt, k, skip_k0));
+  TG_HIP(launch_kick(c, vel, acc, n, idx, n_act, level, dt, k, skip_k0, frozen));
   return TG_OK;
 }
 
-tg_status tg_drift(tg_ctx *c, double *pos, const double *vel, int64_t n, double dt) {
+tg_status tg_kick(tg_ctx *c, double *vel, const double *acc, int64_t n,
+                  const int32_t *idx, const int32_t *n_act,
+                  const uint8_t *level, double dt, const int64_t *k,
+                  int32_t skip_k0) {
+  return kick_impl(c, vel, acc, n, idx, n_act, level, dt, k, skip_k0, nullptr);
+}
+
+static tg_status drift_impl(tg_ctx *c, double *pos, const double *vel, int64_t n, double dt,
+                            const uint8_t *frozen) {
   if (!c) return fail(TG_EINVAL, "tg_drift: NULL context");
   if (n < 0) return fail(TG_EINVAL, "tg_drift: negative n");
   if (n > 0 && (!pos || !vel)) return fail(TG_EINVAL, "tg_drift: NULL pointer");
   if (!std::isfinite(dt)) return fail(TG_EINVAL, "tg_drift: dt not finite");
-  TG_HIP(launch_drift(c, pos, vel, n, dt));
+  TG_HIP(launch_drift(c, pos, vel, n, dt, frozen));
   return TG_OK;
+}
+
+tg_status tg_drift(tg_ctx *c, double *pos, const double *vel, int64_t n, double dt) {
+  return drift_impl(c, pos, vel, n, dt, nullptr);
 }
 
 tg_status tg_levels_v(tg_ctx *c, const double *acc, const double *vel,
@@ -635,17 +649,23 @@ tg_status tg_levels(tg_ctx *c, const double *acc, const double *t4e2, int64_t n,
   return tg_levels_v(c, acc, nullptr, t4e2, nullptr, n, idx, n_act, dt_max, nlev, k, level);
 }
 
-tg_status tg_active_set(tg_ctx *c, const uint8_t *level, int64_t n, int32_t nlev,
-                        const int64_t *k, int32_t k_add, int32_t *idx,
-                        int32_t *n_out) {
+static tg_status active_set_impl(tg_ctx *c, const uint8_t *level, int64_t n, int32_t nlev,
+                                 const int64_t *k, int32_t k_add, int32_t *idx,
+                                 int32_t *n_out, const uint8_t *frozen) {
   if (!c) return fail(TG_EINVAL, "tg_active_set: NULL context");
   if (n < 0 || n > c->cfg.max_particles)
     return fail(TG_EINVAL, "tg_active_set: n out of range");
   if (nlev < 1 || nlev > 30) return fail(TG_EINVAL, "tg_active_set: nlev must be in 1..30");
   if (!n_out || (n > 0 && (!level || !idx)))
     return fail(TG_EINVAL, "tg_active_set: NULL pointer");
-  TG_HIP(launch_active_set(c, level, n, nlev, k, k_add, idx, n_out));
+  TG_HIP(launch_active_set(c, level, n, nlev, k, k_add, idx, n_out, frozen));
   return TG_OK;
+}
+
+tg_status tg_active_set(tg_ctx *c, const uint8_t *level, int64_t n, int32_t nlev,
+                        const int64_t *k, int32_t k_add, int32_t *idx,
+                        int32_t *n_out) {
+  return active_set_impl(c, level, n, nlev, k, k_add, idx, n_out, nullptr);
 }
 
 tg_status tg_counter_add(tg_ctx *c, int64_t *k, int64_t inc) {
@@ -873,15 +893,15 @@ tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
 tg_status tg_step_kdk(tg_ctx *c, const tg_system *y, double dt) {
   tg_status st = check_system(y, "tg_step_kdk");
   if (st != TG_OK) return st;
-  if ((st = tg_kick(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, dt, nullptr, 0)))
+  if ((st = kick_impl(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, dt, nullptr, 0, y->frozen)))
     return st;
   if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt,
                     nullptr, 0)))
     return st;
-  if ((st = tg_drift(c, y->pos, y->vel, y->n, dt))) return st;
+  if ((st = drift_impl(c, y->pos, y->vel, y->n, dt, y->frozen))) return st;
   if ((st = tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, dt))) return st;
   if ((st = tg_forces(c, y, nullptr, nullptr))) return st;
-  if ((st = tg_kick(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, dt, nullptr, 0)))
+  if ((st = kick_impl(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, dt, nullptr, 0, y->frozen)))
     return st;
   return tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt, nullptr, 0);
 }
@@ -890,15 +910,16 @@ tg_status tg_step_dkd(tg_ctx *c, const tg_system *y, double dt) {
   tg_status st = check_system(y, "tg_step_dkd");
   if (st != TG_OK) return st;
   // tg_kick applies half of its dt: 2 dt gives the full kick
-  if ((st = tg_drift(c, y->pos, y->vel, y->n, 0.5 * dt))) return st;
+  if ((st = drift_impl(c, y->pos, y->vel, y->n, 0.5 * dt, y->frozen))) return st;
   if ((st = tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, 0.5 * dt))) return st;
   if ((st = tg_forces(c, y, nullptr, nullptr))) return st;
-  if ((st = tg_kick(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, 2.0 * dt, nullptr, 0)))
+  if ((st = kick_impl(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, 2.0 * dt, nullptr, 0,
+                       y->frozen)))
     return st;
   if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, 2.0 * dt,
                     nullptr, 0)))
     return st;
-  if ((st = tg_drift(c, y->pos, y->vel, y->n, 0.5 * dt))) return st;
+  if ((st = drift_impl(c, y->pos, y->vel, y->n, 0.5 * dt, y->frozen))) return st;
   return tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, 0.5 * dt);
 }
 
@@ -911,10 +932,11 @@ tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
     return fail(TG_EINVAL, "tg_step_block: bad levels");
   const double dt_min = std::ldexp(b->dt_max, -(b->nlev - 1));
   // closing half kicks of the particles whose step ends now (not at k = 0)
-  if ((st = tg_active_set(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active)))
+  if ((st = active_set_impl(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active,
+                             y->frozen)))
     return st;
-  if ((st = tg_kick(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
-                    b->dt_max, b->k, 1)))
+  if ((st = kick_impl(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
+                      b->dt_max, b->k, 1, y->frozen)))
     return st;
   if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt_min,
                     b->k, 1)))
@@ -924,17 +946,18 @@ tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
                         b->tau2eps2v, y->n, b->active_idx, b->n_active, b->dt_max, b->nlev,
                         b->k, b->level)))
     return st;
-  if ((st = tg_kick(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
-                    b->dt_max, nullptr, 0)))
+  if ((st = kick_impl(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
+                      b->dt_max, nullptr, 0, y->frozen)))
     return st;
   if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt_min,
                     nullptr, 0)))
     return st;
   // everyone drifts by the smallest step; then forces for the next active set
-  if ((st = tg_drift(c, y->pos, y->vel, y->n, dt_min))) return st;
+  if ((st = drift_impl(c, y->pos, y->vel, y->n, dt_min, y->frozen))) return st;
   if ((st = tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, dt_min))) return st;
   if ((st = tg_counter_add(c, b->k, 1))) return st;
-  if ((st = tg_active_set(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active)))
+  if ((st = active_set_impl(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active,
+                             y->frozen)))
     return st;
   return tg_forces(c, y, b->active_idx, b->n_active);
 }

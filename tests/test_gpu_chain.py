@@ -196,3 +196,39 @@ def test_prediction_bit_exact(n, dt):
     assert np.array_equal(ov.cpu().numpy()[:k], vr)
     assert np.array_equal(om.cpu().numpy()[:k], m)
     assert np.all(op.cpu().numpy()[k:] == 7.0)
+
+
+def test_largest_chain_and_zero_capacity():
+    say("chain 256 members")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    w, mpos, mmass, R, M, excl = _setup(65536, n_ghost=254)
+    assert mmass.size == 256
+    ctx = B.Context(65536)
+    d = _dev_chain(ctx, w, mpos, mmass, R, M, excl, 8192)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    acc = torch.zeros((65536, 3), **f64)
+    com_acc = torch.zeros(3, **f64)
+    macc = torch.zeros((256, 3), **f64)
+    ctx.chain_forces(d["ch"], acc, com_acc, macc)
+    ctx.sync()
+    pert = ochain.perturbers(w.pos, w.mass, R, M, RC[65536], 1e-4, exclude=excl)
+    a, _, a_com, am = ochain.coupling(w.pos, w.mass, np.arange(65536), R, M, mpos, mmass, pert,
+                                      exclude=excl)
+    live = np.nonzero(excl == 0)[0]
+    assert rel_err(acc.cpu().numpy()[live], a[live]).max() <= FP64_TOL
+    assert rel_err(macc.cpu().numpy(), am).max() <= FP64_TOL
+    assert np.linalg.norm(com_acc.cpu().numpy() - a_com) <= FP64_TOL * np.linalg.norm(a_com)
+    # no room for a single perturber: the count is still exact, the error is reported
+    z = _dev_chain(ctx, w, mpos, mmass, R, M, excl, 1)
+    z["ch"].pert_cap = 0
+    ctx.perturbers(z["ch"])
+    with pytest.raises(B.TGError) as e:
+        ctx.sync()
+    assert e.value.status == -4
+    assert int(z["np"].cpu().numpy()[0]) == pert.size
+    assert int(z["idx"].cpu().numpy()[0]) == -1
+    bad = _dev_chain(ctx, w, np.zeros((257, 3)), np.full(257, 1e-6), R, M, excl, 10)
+    with pytest.raises(B.TGError) as e:
+        ctx.perturbers(bad["ch"])
+    assert e.value.status == -1

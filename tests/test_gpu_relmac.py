@@ -219,3 +219,23 @@ def test_errors():
         ctx.tree_forces(eps, 0.9, acc)
     assert e.value.status == -1
     ctx.sync()
+
+
+@pytest.mark.parametrize("n,alpha", [(1, 1e-3), (2, 1e-3), (7, 1e30), (65, 1e-3), (2049, 1e30)])
+def test_small_sizes_and_separation_only(n, alpha):
+    say("rel small", n, alpha)
+    pos, _, m = ics.plummer(n, 300 + n)
+    rng = np.random.default_rng(n)
+    aold = rng.normal(size=(n, 3))
+    g = gpu_run(pos, m, 0.01, 0.5, 8, 64, alpha=alpha, acc_old=aold, lists=True)
+    ev = oracle.tree_forces(pos, m, 0.01, 0.5, 8, 64, alpha=alpha, acc_old=aold)
+    if n > 1:
+        assert rel_err(g["acc"], ev.acc).max() <= FP64_TOL
+    else:
+        assert np.all(g["acc"] == 0.0)
+    assert g["counts"]["n_p2p"] == ev.n_p2p and g["counts"]["n_p2m"] == ev.n_p2m
+    ol = oracle_lists(ev, 0.5)
+    gl = gpu_lists_by_group(*g["lists"])
+    assert sorted(gl) == sorted(ol)
+    for k in ol:
+        assert np.array_equal(gl[k][0], ol[k][0]) and np.array_equal(gl[k][1], ol[k][1])

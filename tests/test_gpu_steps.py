@@ -402,3 +402,42 @@ def test_block_substeps_with_velocity_criterion_match_oracle():
     assert np.array_equal(level.cpu().numpy(), olev)
     assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-12 * np.abs(st.pos).max()
     assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-11 * np.abs(st.vel).max()
+
+
+def test_frozen_stars_in_every_step_type():
+    """Ghost chain members held still: KDK, DKD and block substeps against
+    the oracle's steps with the same mask; frozen rows stay bit for bit."""
+    say("frozen stars")
+    from paper_1507_01009_amd import binding as B
+    w = ics.hernquist_c4(n=8192)
+    frozen = np.zeros(w.n, np.uint8)
+    frozen[::37] = 1
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    dfz = to_dev(frozen)
+    d.sys.frozen = B._ptr(dfz)
+    ctx.forces(d.sys)
+    ctx.step_kdk(d.sys, 1e-3)
+    ctx.step_dkd(d.sys, 1e-3)
+    nlev, dt_max = 8, 0.25
+    blk, keep = _blocks(ctx, w, nlev, dt_max)
+    for _ in range(20):
+        ctx.step_block(d.sys, blk)
+    ctx.sync()
+    h = d.host()
+    st = ostate(w)
+    st.frozen = frozen.astype(bool)
+    osteps.forces(st)
+    osteps.kdk_step(st, 1e-3)
+    osteps.dkd_step(st, 1e-3)
+    level = np.zeros(w.n, np.uint8)
+    t4e2 = np.full(w.n, 0.3 ** 4 * w.eps ** 2)
+    k = 0
+    for _ in range(20):
+        k, act = osteps.block_substep(st, level, t4e2, k, dt_max, nlev)
+        assert not np.any(frozen[act])
+    fz = frozen.astype(bool)
+    assert np.array_equal(h["pos"][fz], w.pos[fz]) and np.array_equal(h["vel"][fz], w.vel[fz])
+    assert np.array_equal(keep[0].cpu().numpy(), level)
+    assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-12 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-11 * np.abs(st.vel).max()

@@ -180,3 +180,49 @@ def test_dkd_energy_error_scales_dt_squared_and_is_reversible():
     x, v = _kepler_dkd(x, v, m, 0.01, 0.01, 200)
     v *= -1.0
     assert np.allclose(x, x0, atol=1e-11) and np.allclose(v, v0, atol=1e-11)
+
+
+def test_frozen_stars_stay_put_and_still_pull():
+    """Ghost chain members (Sec. 2) are held still in every step type and
+    never become active, but remain sources: with the ghosts given zero
+    velocity and put on the coarsest level, freezing them changes nothing
+    for the other stars in a KDK step, and a ghost's pull is felt."""
+    from oracle import steps as osteps
+    from paper_1507_01009_amd import ics
+    w = ics.hernquist_c2(n=3000)
+    frozen = np.zeros(3000, bool)
+    frozen[::50] = True
+
+    def state(fr, vel_zero=False):
+        vel = w.vel.copy()
+        if vel_zero:
+            vel[frozen] = 0.0
+        st = osteps.State(w.pos.copy(), vel, w.mass.copy(), w.eps, w.theta,
+                          w.sys_off.copy(), w.bh_pos.reshape(-1, 3).copy(),
+                          w.bh_vel.reshape(-1, 3).copy(), w.bh_mass.copy(), w.bh_eps.copy(),
+                          np.array([0, 1], np.int64), frozen=fr)
+        osteps.forces(st)
+        return st
+
+    a = state(frozen)
+    p0, v0 = a.pos.copy(), a.vel.copy()
+    osteps.kdk_step(a, 1e-3)
+    osteps.dkd_step(a, 1e-3)
+    assert np.array_equal(a.pos[frozen], p0[frozen]) and np.array_equal(a.vel[frozen], v0[frozen])
+    assert not np.array_equal(a.pos[~frozen], p0[~frozen])
+    # the same step without freezing, ghosts at rest: the other stars' first
+    # drift is identical (their later kicks then feel the ghosts' new places)
+    b, c = state(frozen, True), state(None, True)
+    osteps.kdk_step(b, 1e-3)
+    osteps.kdk_step(c, 1e-3)
+    assert np.array_equal(b.pos[~frozen], c.pos[~frozen])
+    assert not np.array_equal(b.pos[frozen], c.pos[frozen])
+    # block steps: frozen stars are never active and keep their level
+    lev = np.zeros(3000, np.uint8)
+    t4 = np.full(3000, 1e-12)
+    d = state(frozen)
+    k, act = osteps.block_substep(d, lev, t4, 0, 2.0 ** -6, 4)
+    assert act.size > 0 and not np.any(frozen[act])
+    assert np.all(lev[frozen] == 0) and np.any(lev[~frozen] > 0)
+    # frozen stars stay sources: the forces do not depend on the mask
+    assert np.array_equal(state(frozen).acc, state(None).acc)
