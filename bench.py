@@ -516,6 +516,11 @@ def main():
         st = Step(w, prec, a.leaf, a.group, a.waves, a.dt)
         st.ctx.sync()
         accs[name] = st.acc.cpu().numpy().copy()
+        if "tree" not in res:
+            t = st.ctx.tree_arrays()
+            res["tree"] = {"n_nodes": int(t["level"].size),
+                           "n_leaves": int((t["nchild"] == 0).sum()),
+                           "n_groups": int(t["groups"].shape[0])}
         r = time_path(st, a.steps, a.warmup)
         r["graph_ms_per_step"] = graph_ms(st.ctx, st.step, max(3, a.steps // 2))
         res[name] = r
@@ -540,6 +545,7 @@ def main():
     err.update(direct_errors_gpu(w, accs))
     if not a.no_cpu:
         err.update(direct_errors(w, accs))
+    tree = res.pop("tree")
     head = res["mixed"] if "mixed" in res else res["fp64"]
     head_name = "mixed" if "mixed" in res else "fp64"
     peak = PEAK_FP32 if head_name == "mixed" else PEAK_FP64
@@ -560,7 +566,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "n_smbh": int(w.bh_mass.shape[0]),
                    "theta": w.theta, "eps": w.eps, "leaf_size": a.leaf,
-                   "group_size": a.group, "precision": head_name, "dt": a.dt},
+                   "group_size": a.group, "precision": head_name, "dt": a.dt,
+                   "tree": tree},
         "forces_per_s": head["forces_per_s"],
         "particle_cell_interactions_per_s": head["particle_cell_per_s"],
         "p2p_interactions_per_s": head["p2p_per_s"],
