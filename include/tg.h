@@ -328,6 +328,47 @@ tg_status tg_select_within(tg_ctx *ctx, const double *pos_dev, int64_t n,
                            const uint8_t *exclude_dev, const double center[3], double r,
                            int32_t *idx_dev, int32_t cap, int32_t *n_out_dev);
 
+/* ---- AR-chain integrator (host, FP64; Sec. 2) --------------------------
+ * The chain members are integrated in the chain's centre-of-mass frame by
+ * algorithmic regularization: the logarithmic-Hamiltonian time-transformed
+ * leapfrog (Mikkola & Tanikawa 1999; Preto & Tremaine 1999) with
+ * Bulirsch-Stoer extrapolation (Mikkola & Aarseth 2002), which follows
+ * close and colliding encounters without softening.  All arrays are HOST
+ * memory; nothing here touches the GPU. */
+typedef struct {
+  int32_t n;                  /* members, 2..256 */
+  double *x, *v;              /* [n][3] centre-of-mass frame (in/out) */
+  const double *m;            /* [n] > 0 */
+  double t;                   /* physical time (in/out) */
+  double B;                   /* binding energy U - T plus the perturbers' work (in/out; set by init) */
+  double ds;                  /* fictitious step suggestion (in/out; <= 0 before init: chosen) */
+} tg_archain;
+
+/* Perturbers as point masses moved to first order, y(t) = x + v (t - t0),
+ * relative to the chain's centre of mass (e.g. from tg_predict_perturbers
+ * with dt = 0); the members feel their tidal part (the mean acceleration is
+ * removed, as the centre of mass is the tree's chain particle). */
+typedef struct {
+  int32_t np;
+  const double *x, *v, *m;    /* [np][3], [np][3], [np] */
+  double t0;
+} tg_archain_perturbers;
+
+/* Sets B = U - T (and ds if <= 0).  Errors: TG_EINVAL (n, masses, G,
+ * coincident members). */
+tg_status tg_archain_init(tg_archain *chain, double G);
+
+/* Advances the members by physical time dt (>= 0) to relative accuracy tol
+ * per extrapolated step; perturbers may be NULL.  The last step is searched
+ * so that t ends at t + dt.  *steps_out (may be NULL) gets the number of
+ * extrapolated steps.  Errors: TG_EINVAL, TG_EINTERNAL (step underflow). */
+tg_status tg_archain_advance(tg_archain *chain, double G, double dt, double tol,
+                             const tg_archain_perturbers *perturbers, int64_t *steps_out);
+
+/* Relative energy bookkeeping error (T - U + B) / U of the chain (0 when the
+ * integration and the work of the perturbers balance exactly). */
+tg_status tg_archain_energy(const tg_archain *chain, double G, double *err_out);
+
 /* ---- whole steps (every stage above in one call; capturable) ---------- */
 typedef struct {
   double *pos, *vel, *acc, *pot;   /* stars [n][3], pot [n] may be NULL */

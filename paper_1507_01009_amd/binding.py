@@ -68,6 +68,16 @@ class tg_chain(C.Structure):
                 ("pert_idx", C.c_void_p), ("pert_cap", C.c_int32), ("n_pert", C.c_void_p)]
 
 
+class tg_archain(C.Structure):
+    _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("v", C.c_void_p), ("m", C.c_void_p),
+                ("t", C.c_double), ("B", C.c_double), ("ds", C.c_double)]
+
+
+class tg_archain_perturbers(C.Structure):
+    _fields_ = [("np", C.c_int32), ("x", C.c_void_p), ("v", C.c_void_p), ("m", C.c_void_p),
+                ("t0", C.c_double)]
+
+
 _lib = None
 
 
@@ -108,6 +118,9 @@ def lib():
             "tg_chain_forces": (st, [P, P, P, P, P, P, P, P]),
             "tg_select_within": (st, [P, P, i64, P, P, f64, P, i32, P]),
             "tg_predict_perturbers": (st, [P, P, P, P, f64, P, P, P]),
+            "tg_archain_init": (st, [P, f64]),
+            "tg_archain_advance": (st, [P, f64, f64, f64, P, P]),
+            "tg_archain_energy": (st, [P, f64, P]),
             "tg_forces": (st, [P, P, P, P]),
             "tg_step_kdk": (st, [P, P, f64]),
             "tg_step_dkd": (st, [P, P, f64]),
@@ -139,7 +152,8 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
             "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac",
             "tg_perturbers", "tg_chain_forces", "tg_select_within",
-            "tg_predict_perturbers", "tg_forces",
+            "tg_predict_perturbers", "tg_archain_init", "tg_archain_advance",
+            "tg_archain_energy", "tg_forces",
             "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
@@ -499,3 +513,44 @@ def _memcpy_d2h(dst, src, nbytes):
     rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), C.c_size_t(nbytes), 2)
     if rc != 0:
         raise RuntimeError("hipMemcpy failed: %d" % rc)
+
+
+class ARChain:
+    """Host AR-chain (tg_archain_*): members in the centre-of-mass frame,
+    numpy float64 arrays owned by this object."""
+
+    def __init__(self, x, v, m, t=0.0, G=1.0):
+        self.x = np.ascontiguousarray(x, np.float64).reshape(-1, 3).copy()
+        self.v = np.ascontiguousarray(v, np.float64).reshape(-1, 3).copy()
+        self.m = np.ascontiguousarray(m, np.float64).copy()
+        self.G = float(G)
+        self.s = tg_archain()
+        self.s.n = self.m.shape[0]
+        self.s.x = self.x.ctypes.data_as(C.c_void_p)
+        self.s.v = self.v.ctypes.data_as(C.c_void_p)
+        self.s.m = self.m.ctypes.data_as(C.c_void_p)
+        self.s.t, self.s.B, self.s.ds = float(t), 0.0, 0.0
+        _check(lib().tg_archain_init(C.byref(self.s), self.G))
+
+    @property
+    def t(self):
+        return self.s.t
+
+    def advance(self, dt, tol=1e-12, px=None, pv=None, pm=None, t0=None):
+        p = None
+        keep = None
+        if pm is not None and len(pm):
+            keep = [np.ascontiguousarray(a, np.float64) for a in (px, pv, pm)]
+            p = tg_archain_perturbers()
+            p.np = keep[2].shape[0]
+            p.x, p.v, p.m = [a.ctypes.data_as(C.c_void_p) for a in keep]
+            p.t0 = self.s.t if t0 is None else float(t0)
+        steps = C.c_int64(0)
+        _check(lib().tg_archain_advance(C.byref(self.s), self.G, float(dt), float(tol),
+                                        C.byref(p) if p is not None else None, C.byref(steps)))
+        return steps.value
+
+    def energy_error(self):
+        e = C.c_double(0.0)
+        _check(lib().tg_archain_energy(C.byref(self.s), self.G, C.byref(e)))
+        return e.value

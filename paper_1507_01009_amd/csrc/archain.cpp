@@ -1,0 +1,309 @@
+// Algorithmic-regularization chain integrator (host, FP64): the few-body
+// subsystem around the SMBH that the hybrid method integrates apart from the
+// tree (Sec. 2), in the chain's centre-of-mass frame.
+//
+// Method (Mikkola & Tanikawa 1999, MNRAS 310, 745; Preto & Tremaine 1999,
+// AJ 118, 2532; Mikkola & Aarseth 2002, CeMDA 84, 343): with the kinetic
+// energy T, the (positive) potential energy U = sum_{i<j} G m_i m_j / r_ij
+// and the binding energy B = U - T carried as a variable, the logarithmic
+// Hamiltonian splits into two exactly solvable flows in a fictitious time s:
+//   drift:  dt/ds = 1 / (T + B),  x += v dt,  t += dt       (v fixed)
+//   kick:   dt/ds = 1 / U,        v += (a + f) dt,           (x, t fixed)
+//           B -= dt sum_i m_i f_i . (v_old + v_new) / 2
+// with a the Newtonian accelerations of the members and f an external
+// perturbation.  A leapfrog D(h/2) [K(h) D(h)]^(n-1) K(h) D(h/2) follows
+// two-body orbits exactly up to a time error, also through collisions, and
+// its error is even in h, so a Bulirsch-Stoer extrapolation in h^2 over the
+// substep counts n = 2, 4, 6, ... brings each step to the tolerance.  The
+// last step before the target time is found by a secant search on its
+// length.
+//
+// Perturbers: point masses moved to first order, y_p(t) = y_p + w_p (t - t0),
+// relative to the chain's centre of mass; the members feel their tidal part,
+// f_i - (1/M) sum_j m_j f_j, so the frame stays centred (the centre of mass
+// itself is the tree's chain particle).  Coordinates are relative to the
+// centre of mass, not chain vectors (see the design notes).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tg_internal.h"
+
+namespace {
+
+struct Chain {
+  int n = 0;
+  const double *m = nullptr;
+  double G = 1.0, M = 0.0;
+  // perturbers
+  int np = 0;
+  const double *py = nullptr, *pw = nullptr, *pm = nullptr;
+  double t0 = 0.0;
+};
+
+// State vector: x [3n], v [3n], t, B.
+struct Y {
+  std::vector<double> d;
+  double *x() { return d.data(); }
+  double *v(int n) { return d.data() + 3 * n; }
+  double &t(int n) { return d[6 * n]; }
+  double &B(int n) { return d[6 * n + 1]; }
+};
+
+double kinetic(const Chain &c, const double *v) {
+  double T = 0.0;
+  for (int i = 0; i < c.n; ++i)
+    T += 0.5 * c.m[i] * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
+  return T;
+}
+
+// Newtonian accelerations of the members; returns U.
+double internal(const Chain &c, const double *x, double *a) {
+  double U = 0.0;
+  std::fill(a, a + 3 * c.n, 0.0);
+  for (int i = 0; i < c.n; ++i)
+    for (int j = i + 1; j < c.n; ++j) {
+      const double dx = x[3 * j] - x[3 * i], dy = x[3 * j + 1] - x[3 * i + 1],
+                   dz = x[3 * j + 2] - x[3 * i + 2];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double r = std::sqrt(r2);
+      const double g = c.G / (r2 * r);
+      U += c.G * c.m[i] * c.m[j] / r;
+      a[3 * i] += g * c.m[j] * dx; a[3 * i + 1] += g * c.m[j] * dy; a[3 * i + 2] += g * c.m[j] * dz;
+      a[3 * j] -= g * c.m[i] * dx; a[3 * j + 1] -= g * c.m[i] * dy; a[3 * j + 2] -= g * c.m[i] * dz;
+    }
+  return U;
+}
+
+// Tidal part of the perturbers' accelerations at time t.
+void external(const Chain &c, const double *x, double t, double *f) {
+  std::fill(f, f + 3 * c.n, 0.0);
+  if (c.np == 0) return;
+  const double dt = t - c.t0;
+  for (int i = 0; i < c.n; ++i) {
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int p = 0; p < c.np; ++p) {
+      const double dx = c.py[3 * p] + c.pw[3 * p] * dt - x[3 * i];
+      const double dy = c.py[3 * p + 1] + c.pw[3 * p + 1] * dt - x[3 * i + 1];
+      const double dz = c.py[3 * p + 2] + c.pw[3 * p + 2] * dt - x[3 * i + 2];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double g = c.G * c.pm[p] / (r2 * std::sqrt(r2));
+      fx += g * dx; fy += g * dy; fz += g * dz;
+    }
+    f[3 * i] = fx; f[3 * i + 1] = fy; f[3 * i + 2] = fz;
+  }
+  double mx = 0.0, my = 0.0, mz = 0.0;
+  for (int i = 0; i < c.n; ++i) {
+    mx += c.m[i] * f[3 * i]; my += c.m[i] * f[3 * i + 1]; mz += c.m[i] * f[3 * i + 2];
+  }
+  mx /= c.M; my /= c.M; mz /= c.M;
+  for (int i = 0; i < c.n; ++i) { f[3 * i] -= mx; f[3 * i + 1] -= my; f[3 * i + 2] -= mz; }
+}
+
+void drift(const Chain &c, Y &y, double h) {
+  const int n = c.n;
+  const double dt = h / (kinetic(c, y.v(n)) + y.B(n));
+  double *x = y.x(), *v = y.v(n);
+  for (int k = 0; k < 3 * n; ++k) x[k] += v[k] * dt;
+  y.t(n) += dt;
+}
+
+void kick(const Chain &c, Y &y, double h, std::vector<double> &a, std::vector<double> &f) {
+  const int n = c.n;
+  const double U = internal(c, y.x(), a.data());
+  const double dt = h / U;
+  external(c, y.x(), y.t(n), f.data());
+  double *v = y.v(n);
+  double work = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      const double v0 = v[3 * i + k];
+      const double v1 = v0 + (a[3 * i + k] + f[3 * i + k]) * dt;
+      work += c.m[i] * f[3 * i + k] * 0.5 * (v0 + v1);
+      v[3 * i + k] = v1;
+    }
+  y.B(n) -= work * dt;
+}
+
+Y leapfrog(const Chain &c, const Y &y0, double H, int nsub, std::vector<double> &a,
+           std::vector<double> &f) {
+  Y y = y0;
+  const double h = H / nsub;
+  drift(c, y, 0.5 * h);
+  for (int k = 0; k < nsub; ++k) {
+    kick(c, y, h, a, f);
+    drift(c, y, k == nsub - 1 ? 0.5 * h : h);
+  }
+  return y;
+}
+
+constexpr int kCols = 10;
+constexpr int kSeq[kCols] = {2, 4, 6, 8, 10, 12, 14, 16, 20, 24};
+
+// One extrapolated step of fictitious length H.  Returns the column at which
+// it converged (or -1) and the result in out.
+int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, std::vector<double> &a,
+            std::vector<double> &f) {
+  const int n = c.n, dim = 6 * n + 2;
+  std::vector<std::vector<double>> T(kCols, std::vector<double>(dim));
+  // error scales: position and velocity magnitudes, the step's time, |B|
+  double xs = 0.0, vs = 0.0;
+  for (int i = 0; i < 3 * n; ++i) {
+    xs = std::max(xs, std::fabs(y0.d[i]));
+    vs = std::max(vs, std::fabs(y0.d[3 * n + i]));
+  }
+  for (int k = 0; k < kCols; ++k) {
+    Y yk = leapfrog(c, y0, H, kSeq[k], a, f);
+    T[k] = yk.d;
+    for (int j = k - 1; j >= 0; --j) {
+      const double r = (double)kSeq[k] / kSeq[j];
+      const double den = r * r - 1.0;
+      for (int q = 0; q < dim; ++q) T[j][q] = T[j + 1][q] + (T[j + 1][q] - T[j][q]) / den;
+    }
+    if (k >= 2) {
+      // T[0] holds the newest extrapolation, T[1] the previous one
+      double err = 0.0;
+      const double ts = std::fabs(T[0][6 * n] - y0.d[6 * n]) + 1e-300;
+      for (int q = 0; q < dim; ++q) {
+        double s;
+        if (q < 3 * n) s = xs;
+        else if (q < 6 * n) s = vs;
+        else if (q == 6 * n) s = ts;
+        else s = std::fabs(y0.d[6 * n + 1]);
+        err = std::max(err, std::fabs(T[0][q] - T[1][q]) / (s + 1e-300));
+      }
+      if (err <= tol) {
+        out.d = T[0];
+        return k;
+      }
+    }
+  }
+  return -1;
+}
+
+}  // namespace
+
+using namespace tg;
+
+extern "C" {
+
+tg_status tg_archain_init(tg_archain *s, double G) {
+  if (!s || !s->x || !s->v || !s->m) return fail(TG_EINVAL, "tg_archain_init: NULL argument");
+  if (s->n < 2 || s->n > kMaxChain) return fail(TG_EINVAL, "tg_archain_init: n must be in 2..256");
+  if (!(G > 0.0)) return fail(TG_EINVAL, "tg_archain_init: G must be positive");
+  Chain c;
+  c.n = s->n; c.m = s->m; c.G = G;
+  std::vector<double> a(3 * s->n);
+  for (int i = 0; i < s->n; ++i)
+    if (!(s->m[i] > 0.0)) return fail(TG_EINVAL, "tg_archain_init: masses must be positive");
+  const double U = internal(c, s->x, a.data());
+  if (!std::isfinite(U)) return fail(TG_EINVAL, "tg_archain_init: coincident members");
+  s->B = U - kinetic(c, s->v);
+  if (!(s->ds > 0.0)) {
+    // a first step of about a hundredth of the fastest pair's dynamical time
+    double tmin = INFINITY;
+    for (int i = 0; i < s->n; ++i)
+      for (int j = i + 1; j < s->n; ++j) {
+        double r2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double d = s->x[3 * j + k] - s->x[3 * i + k];
+          r2 += d * d;
+        }
+        const double r = std::sqrt(r2);
+        tmin = std::min(tmin, std::sqrt(r * r * r / (G * (s->m[i] + s->m[j]))));
+      }
+    s->ds = 0.01 * tmin * U;
+  }
+  return TG_OK;
+}
+
+tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
+                             const tg_archain_perturbers *p, int64_t *steps_out) {
+  if (!s || !s->x || !s->v || !s->m) return fail(TG_EINVAL, "tg_archain_advance: NULL argument");
+  if (s->n < 2 || s->n > kMaxChain) return fail(TG_EINVAL, "tg_archain_advance: n must be in 2..256");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(TG_EINVAL, "tg_archain_advance: dt must be >= 0");
+  if (!(tol > 0.0) || !(s->ds > 0.0)) return fail(TG_EINVAL, "tg_archain_advance: tol and ds must be > 0");
+  if (p && p->np > 0 && (!p->x || !p->v || !p->m))
+    return fail(TG_EINVAL, "tg_archain_advance: NULL perturber arrays");
+  Chain c;
+  c.n = s->n; c.m = s->m; c.G = G;
+  for (int i = 0; i < s->n; ++i) c.M += s->m[i];
+  if (p && p->np > 0) { c.np = p->np; c.py = p->x; c.pw = p->v; c.pm = p->m; c.t0 = p->t0; }
+  const int n = s->n;
+  Y y;
+  y.d.resize(6 * n + 2);
+  std::memcpy(y.x(), s->x, sizeof(double) * 3 * n);
+  std::memcpy(y.v(n), s->v, sizeof(double) * 3 * n);
+  y.t(n) = s->t;
+  y.B(n) = s->B;
+  const double t_end = s->t + dt;
+  std::vector<double> a(3 * n), f(3 * n);
+  int64_t steps = 0;
+  double H = s->ds;
+  Y out;
+  while (y.t(n) < t_end) {
+    int col = bs_step(c, y, H, tol, out, a, f);
+    if (col < 0) {
+      H *= 0.5;
+      if (H < 1e-300 || ++steps > 100000000) return fail(TG_EINTERNAL, "tg_archain_advance: step underflow");
+      continue;
+    }
+    ++steps;
+    if (out.t(n) > t_end) {
+      // the last step: secant (regula falsi) search for the length that
+      // ends at t_end; a trial that does not converge shortens the step and
+      // returns to ordinary stepping
+      double ha = 0.0, ta = y.t(n), hb = H, tb = out.t(n);
+      bool done = false, retry = false;
+      for (int it = 0; it < 100 && !done; ++it) {
+        const double hc = ha + (hb - ha) * (t_end - ta) / (tb - ta);
+        Y yc;
+        if (bs_step(c, y, hc, tol, yc, a, f) < 0) {
+          H = 0.5 * hc;
+          retry = true;
+          break;
+        }
+        const double tc = yc.t(n);
+        if (std::fabs(tc - t_end) <= 1e-14 * std::max(std::fabs(t_end), std::fabs(dt))) {
+          y = yc;
+          done = true;
+        } else if (tc < t_end) {
+          ha = hc; ta = tc;
+        } else {
+          hb = hc; tb = tc;
+        }
+      }
+      if (retry) continue;
+      if (!done) return fail(TG_EINTERNAL, "tg_archain_advance: final step search did not close");
+      y.t(n) = t_end;   // within the search tolerance
+      break;
+    }
+    y = out;
+    // next step: grow when the extrapolation converged early
+    if (col <= 3) H *= 1.5;
+    else if (col >= 6) H *= 0.7;
+  }
+  std::memcpy(s->x, y.x(), sizeof(double) * 3 * n);
+  std::memcpy(s->v, y.v(n), sizeof(double) * 3 * n);
+  s->t = t_end;
+  s->B = y.B(n);
+  s->ds = H;
+  if (steps_out) *steps_out = steps;
+  return TG_OK;
+}
+
+tg_status tg_archain_energy(const tg_archain *s, double G, double *err_out) {
+  if (!s || !s->x || !s->v || !s->m || !err_out) return fail(TG_EINVAL, "tg_archain_energy: NULL argument");
+  if (s->n < 2 || s->n > kMaxChain) return fail(TG_EINVAL, "tg_archain_energy: n must be in 2..256");
+  Chain c;
+  c.n = s->n; c.m = s->m; c.G = G;
+  std::vector<double> a(3 * s->n);
+  const double U = internal(c, s->x, a.data());
+  const double T = kinetic(c, s->v);
+  *err_out = (T - U + s->B) / U;
+  return TG_OK;
+}
+
+}  // extern "C"
