@@ -325,8 +325,9 @@ def extra_chain(w, reps=50):
     """Chain coupling on the same workload: both SMBHs and the 30 stars
     nearest to their centre form the chain (the stars stay as excluded
     ghosts), r_crit = 0.01, gamma_crit = 1e-4.  Times the perturber
-    selection alone and the whole coupling (selection, star terms, member
-    forces, the chain particle with Eq. 3)."""
+    selection alone, the whole coupling (selection, star terms, member
+    forces, the chain particle with Eq. 3) and the host AR-chain over ten
+    tree steps of 1e-5 with the perturbers gathered on the GPU."""
     import numpy as np
     import torch
     from paper_1507_01009_amd import binding as B
@@ -367,6 +368,25 @@ def extra_chain(w, reps=50):
     # then the flags read again by the compaction
     out["select_bytes_per_star"] = 24 + 8 + 1 + 1 + 1
     out["select_GBps_whole_call"] = w.n * 35 / (out["perturbers_us"] * 1e-6) / 1e9
+    # one chain step on the host: the perturbers relative to the chain
+    # particle (GPU gather), then the AR-chain over one tree step
+    npert = min(out["n_perturbers"], idx.shape[0])
+    mvel = np.concatenate([w.bh_vel.reshape(-1, 3), w.vel[ghosts]])
+    V = (mmass[:, None] * mvel).sum(0) / M
+    px, pv = torch.zeros((8192, 3), **f64), torch.zeros((8192, 3), **f64)
+    pm = torch.zeros(8192, **f64)
+    ctx.predict_perturbers(ch, t(w.vel), V, 0.0, px, pv, pm)
+    ctx.sync()
+    px, pv, pm = (a.cpu().numpy()[:npert] for a in (px, pv, pm))
+    chain = B.ARChain(mpos - S / M, mvel - V, mmass)
+    t0 = time.perf_counter()
+    nsteps = 0
+    for _ in range(10):
+        nsteps += chain.advance(1e-5, tol=1e-12, px=px, pv=pv, pm=pm)
+    out["archain_ms_per_tree_step"] = 1e3 * (time.perf_counter() - t0) / 10
+    out["archain_bs_steps_per_tree_step"] = nsteps / 10
+    out["archain_energy_error"] = chain.energy_error()
+    out["archain_tree_step"] = 1e-5
     ctx.close()
     return out
 

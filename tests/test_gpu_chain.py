@@ -232,3 +232,33 @@ def test_largest_chain_and_zero_capacity():
     with pytest.raises(B.TGError) as e:
         ctx.perturbers(bad["ch"])
     assert e.value.status == -1
+
+
+def test_chain_step_round_trip():
+    """Perturbers gathered on the GPU drive the host AR-chain exactly as the
+    oracle's gather does; the chain's energy bookkeeping closes."""
+    say("chain round trip")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    n = 262144
+    w, mpos, mmass, R, M, excl = _setup(n)
+    ghosts = np.nonzero(excl)[0]
+    mvel = np.concatenate([w.bh_vel.reshape(-1, 3), w.vel[ghosts]])
+    V = (mmass[:, None] * mvel).sum(0) / M
+    ctx = B.Context(n)
+    d = _dev_chain(ctx, w, mpos, mmass, R, M, excl, 8192)
+    ctx.perturbers(d["ch"])
+    f64 = dict(dtype=torch.float64, device="cuda")
+    op, ov, om = (torch.zeros((8192, 3), **f64), torch.zeros((8192, 3), **f64),
+                  torch.zeros(8192, **f64))
+    ctx.predict_perturbers(d["ch"], to_dev(w.vel), V, 0.0, op, ov, om)
+    ctx.sync()
+    k = int(d["np"].cpu().numpy()[0])
+    pert = ochain.perturbers(w.pos, w.mass, R, M, RC[n], 1e-4, exclude=excl)
+    xr, vr, m = ochain.predict(w.pos, w.vel, w.mass, pert, R, V, 0.0)
+    a = B.ARChain(mpos - R, mvel - V, mmass)
+    a.advance(2e-4, px=op.cpu().numpy()[:k], pv=ov.cpu().numpy()[:k], pm=om.cpu().numpy()[:k])
+    b = B.ARChain(mpos - R, mvel - V, mmass)
+    b.advance(2e-4, px=xr, pv=vr, pm=m)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.v, b.v)
+    assert abs(a.energy_error()) < 1e-10
