@@ -295,12 +295,32 @@ def cpu_baseline(w, leaf, group, seconds):
         chunk = min(chunk * 2, 4096)
     frac = done / g.shape[0]
     t_step = t_build + t_walk / frac
+    # the same walk on one thread, a smaller random sample
+    oracle.set_threads(1)
+    sel = np.sort(order[:256])
+    t1 = time.perf_counter()
+    ev = oracle.tree_forces(w.pos, w.mass, w.eps, w.theta, leaf, group, sel_groups=sel,
+                            tree=tree)
+    t_one = time.perf_counter() - t1
+    oracle.set_threads(threads)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": (inter / frac) / t_step, "unit": "interactions/s", "cores": threads,
             "kind": "oracle",
             "sample": "full oracle tree build (%.1f s) + walk/evaluation of %d of %d groups "
                       "(random, %.1f s), extrapolated to the whole step" % (
                           t_build, done, g.shape[0], t_walk),
-            "step_seconds_est": t_step}
+            "step_seconds_est": t_step, "build_seconds": t_build,
+            "walk_interactions_per_s": inter / t_walk,
+            "walk_interactions_per_s_1thread": (ev.n_p2p + ev.n_p2m) / t_one,
+            "sample_1thread": "256 random groups on one thread (%.1f s)" % t_one,
+            "host_cpu": model, "host_nproc": os.cpu_count()}
 
 
 # ---------------------------------------------------------------- extras
