@@ -315,7 +315,8 @@ tg_status tg_chain_forces(tg_ctx *ctx, const tg_chain *chain,
  *   out_mass[k] = m_j (out_mass may be NULL),
  * V = com_vel (host [3]), R + V dt formed on the host; each operation rounded
  * separately.  vel_dev: [n][3] star velocities; outputs [pert_cap][3] device.
- * Rows beyond the count are untouched.  Errors: TG_EINVAL. */
+ * Rows beyond the count are untouched; a listed index outside [0, n) (a
+ * list not selected from these stars) gives a NaN row.  Errors: TG_EINVAL. */
 tg_status tg_predict_perturbers(tg_ctx *ctx, const tg_chain *chain, const double *vel_dev,
                                 const double com_vel[3], double dt, double *out_pos_dev,
                                 double *out_vel_dev, double *out_mass_dev);

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_chain_com_part(
 
 __global__ __launch_bounds__(256) void k_chain_members(
     const double *__restrict__ mpos, const int32_t *__restrict__ pidx,
-    const int32_t *__restrict__ n_pert, int32_t cap, const double *__restrict__ pos,
+    const int32_t *__restrict__ n_pert, int32_t cap, int64_t n, const double *__restrict__ pos,
     const double *__restrict__ mass, double e2pm, double G, double *__restrict__ macc) {
   __shared__ double lds[6 * 256];
   const int i = blockIdx.x;
@@ -214,6 +214,7 @@ __global__ __launch_bounds__(256) void k_chain_members(
   CSum sx, sy, sz;
   for (int p = threadIdx.x; p < np; p += blockDim.x) {
     const int64_t j = pidx[p];
+    if (j < 0 || j >= n) continue;   // the list is this call's, so always in range
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
     chain_pair(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], mass[j], x, y, z, e2pm, ax, ay, az,
                ph);
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(256) void k_chain_com_final(const double *__restric
 // x_rel = (x + v dt) - Rp, v_rel = v - V (Rp = R + V dt formed on the host).
 __global__ __launch_bounds__(256) void k_chain_predict(
     const int32_t *__restrict__ pidx, const int32_t *__restrict__ n_pert, int32_t cap,
-    const double *__restrict__ pos, const double *__restrict__ vel,
+    int64_t n, const double *__restrict__ pos, const double *__restrict__ vel,
     const double *__restrict__ mass, double dt, double Rx, double Ry, double Rz, double Vx,
     double Vy, double Vz, double *__restrict__ out_pos, double *__restrict__ out_vel,
     double *__restrict__ out_mass) {
@@ -264,6 +265,12 @@ __global__ __launch_bounds__(256) void k_chain_predict(
   const int np = min(max(n_pert[0], 0), cap);
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x) {
     const int64_t j = pidx[k];
+    if (j < 0 || j >= n) {   // a list not made for these stars: NaN rows
+      const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+      for (int a = 0; a < 3; ++a) out_pos[3 * k + a] = out_vel[3 * k + a] = nanv;
+      if (out_mass) out_mass[k] = nanv;
+      continue;
+    }
     const double R[3] = {Rx, Ry, Rz}, V[3] = {Vx, Vy, Vz};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -300,7 +307,7 @@ hipError_t launch_chain_predict(tg_ctx *c, const tg_chain *ch, const double *vel
                                 const double rp[3], const double v[3], double *out_pos,
                                 double *out_vel, double *out_mass) {
   hipLaunchKernelGGL(k_chain_predict, dim3(grid_for(ch->pert_cap)), dim3(256), 0, c->stream,
-                     ch->pert_idx, ch->n_pert, ch->pert_cap, ch->pos, vel, ch->mass, dt, rp[0],
+                     ch->pert_idx, ch->n_pert, ch->pert_cap, ch->n, ch->pos, vel, ch->mass, dt, rp[0],
                      rp[1], rp[2], v[0], v[1], v[2], out_pos, out_vel, out_mass);
   return hipGetLastError();
 }
@@ -323,7 +330,7 @@ hipError_t launch_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx
                      ch->mass, n, ch->exclude, b.cflag, ch->com[0], ch->com[1], ch->com[2],
                      b.cpart);
   hipLaunchKernelGGL(k_chain_members, dim3(ch->nc), dim3(256), 0, c->stream, ch->member_pos,
-                     ch->pert_idx, ch->n_pert, ch->pert_cap, ch->pos, ch->mass, e2pm, G,
+                     ch->pert_idx, ch->n_pert, ch->pert_cap, ch->n, ch->pos, ch->mass, e2pm, G,
                      member_acc);
   hipLaunchKernelGGL(k_chain_com_final, dim3(1), dim3(256), 0, c->stream, b.cpart, member_acc,
                      ch->member_mass, ch->nc, ch->m_chain, G, com_acc);

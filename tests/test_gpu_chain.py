@@ -262,3 +262,23 @@ def test_chain_step_round_trip():
     b.advance(2e-4, px=xr, pv=vr, pm=m)
     assert np.array_equal(a.x, b.x) and np.array_equal(a.v, b.v)
     assert abs(a.energy_error()) < 1e-10
+
+
+def test_prediction_rejects_foreign_indices():
+    """A perturber list that was not selected from these stars: indices
+    outside [0, n) give NaN rows (the kernel checks every index)."""
+    say("predict foreign list")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    w, mpos, mmass, R, M, excl = _setup(65536)
+    ctx = B.Context(65536)
+    d = _dev_chain(ctx, w, mpos, mmass, R, M, excl, 4)
+    d["idx"].copy_(torch.tensor([3, -1, 65536, 70000], dtype=torch.int32))
+    d["np"].fill_(4)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    op, ov, om = (torch.zeros((4, 3), **f64), torch.zeros((4, 3), **f64), torch.zeros(4, **f64))
+    ctx.predict_perturbers(d["ch"], to_dev(w.vel), [0.0, 0.0, 0.0], 0.0, op, ov, om)
+    ctx.sync()
+    p = op.cpu().numpy()
+    assert np.array_equal(p[0], w.pos[3] - R) and np.all(np.isnan(p[1:]))
+    assert np.all(np.isnan(om.cpu().numpy()[1:]))
