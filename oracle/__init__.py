@@ -62,11 +62,12 @@ def lib():
             "or_moments": (None, [P, P, i64, P, P, P]),
             "or_groups": (i64, [i64, P, P, P, P, P, P, i32, i64, P]),
             "or_group_boxes": (None, [P, P, i64, P, P, P]),
-            "or_rel_records": (None, [i64, P, P, P, P, P, P, f64, P]),
+            "or_rel_records": (None, [i64, P, P, P, P, P, P, f64, P, P]),
+            "or_refit_sides": (None, [i64, P, P, P, P, P, P, P, P]),
             "or_walk_lists": (C.c_int, [i64, P, P, P, P, P, P, P, P, P, i64, f64,
-                                        P, P, P, P, P, P]),
+                                        P, P, P, P, P, P, P]),
             "or_tree_forces": (C.c_int, [i64, P, P, P, P, P, P, P, P, P, P, P, i64,
-                                         P, P, P, f64, f64, P, P, f64, P, P, P]),
+                                         P, P, P, f64, f64, P, P, P, f64, P, P, P]),
             "or_direct": (None, [P, P, P, i32, P, P, i64, f64, P, P, P, i64, f64,
                                  P, P]),
             "or_direct_pairs": (None, [P, P, P, i64, P, P, i64, C.c_int, f64,
@@ -231,14 +232,24 @@ def active_mask(n, active=None):
     return m
 
 
-def rel_records(tree: Tree, mom, G=1.0) -> np.ndarray:
+def rel_records(tree: Tree, mom, G=1.0, side=None) -> np.ndarray:
     """[nn, 8] per cell: the 1.2x cube {lo x, y, z, P = (G M) s^2, hi x, y, z, 0}
-    of the relative opening test."""
+    of the relative opening test (s = side[v] for a refitted tree)."""
     rel = np.zeros((tree.nn, 8), np.float64)
+    side = None if side is None else _c(side, np.float64)
     lib().or_rel_records(tree.nn, _p(tree.level), _p(tree.first), _p(tree.sys),
                          _p(tree.skeys), _p(tree.cube), _p(_c(mom, np.float64)),
-                         float(G), _p(rel))
+                         float(G), _p(side), _p(rel))
     return rel
+
+
+def refit_sides(tree: Tree, spos) -> np.ndarray:
+    """[nn] opening size of every cell of a refitted tree (see or_refit_sides)."""
+    side = np.zeros(tree.nn, np.float64)
+    lib().or_refit_sides(tree.nn, _p(tree.level), _p(tree.first), _p(tree.count),
+                         _p(tree.sys), _p(tree.skeys), _p(tree.cube),
+                         _p(_c(spos, np.float64)), _p(side))
+    return side
 
 
 def group_arel(tree: Tree, g, sactive, acc_old, alpha: float) -> np.ndarray:
@@ -257,7 +268,7 @@ def group_arel(tree: Tree, g, sactive, acc_old, alpha: float) -> np.ndarray:
     return aa * np.where(np.isfinite(m), m, 0.0)
 
 
-def walk_lists(tree: Tree, mom, g, box, sel, theta: float, rel=None, arel=None):
+def walk_lists(tree: Tree, mom, g, box, sel, theta: float, rel=None, arel=None, side=None):
     """Sorted P2M and P2P node-id lists for each selected group (relative
     opening test when rel / arel are given, see :func:`rel_records`)."""
     sel = _c(sel, np.int32)
@@ -266,10 +277,11 @@ def walk_lists(tree: Tree, mom, g, box, sel, theta: float, rel=None, arel=None):
     np2p = np.zeros(ns, np.int64)
     rel = None if rel is None else _c(rel, np.float64)
     arel = None if arel is None else _c(arel, np.float64)
+    side = None if side is None else _c(side, np.float64)
     args = (tree.nn, _p(tree.level), _p(tree.child), _p(tree.nchild),
             _p(tree.sys), _p(_c(mom, np.float64)), _p(tree.cube),
             _p(_c(g, np.uint32)), _p(_c(box, np.float64)), _p(sel), ns,
-            float(theta), _p(rel), _p(arel), _p(np2m), _p(np2p))
+            float(theta), _p(side), _p(rel), _p(arel), _p(np2m), _p(np2p))
     if lib().or_walk_lists(*args, None, None) != 0:
         raise MemoryError("oracle walk")
     sizes = np.stack([np2m, np2p], 1).reshape(-1)
@@ -301,17 +313,20 @@ class Evaluation:
     n_targets: int
     rel: np.ndarray = None   # relative test: cell records and per-group A
     arel: np.ndarray = None
+    side: np.ndarray = None  # refitted tree: opening size per cell
 
 
 def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
                 sys_off=None, G=1.0, sel_groups=None, tree=None, alpha=None,
-                acc_old=None):
+                acc_old=None, refit=False):
     """Build, moments, groups, walk and evaluation, all in the oracle.
 
     ``active``: original indices of the targets (None = all).  ``sel_groups``:
     evaluate only these group indices (None = every group with a target).
     With ``alpha`` (and ``acc_old``, [N, 3] original order) the walk uses the
-    relative opening test instead of theta.
+    relative opening test instead of theta.  ``refit``: ``tree`` is an earlier
+    build kept as it is (order, nodes, groups) for the current positions, the
+    cells opened by their refitted sizes (:func:`refit_sides`).
     Returns an :class:`Evaluation`; acc/pot are NaN for rows not evaluated.
     """
     pos = _c(pos, np.float64).reshape(-1, 3)
@@ -328,9 +343,10 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
     else:
         sel = _c(sel_groups, np.int32)
         sel = sel[nact[sel] > 0]
+    side = refit_sides(tree, spos) if refit else None
     rel = arel = None
     if alpha is not None:
-        rel = rel_records(tree, mom, G)
+        rel = rel_records(tree, mom, G, side)
         arel = group_arel(tree, g, sact, acc_old, alpha)
     sacc = np.full((n, 3), np.nan)
     spot = np.full(n, np.nan)
@@ -339,8 +355,8 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
         tree.nn, _p(tree.level), _p(tree.first), _p(tree.count),
         _p(tree.child), _p(tree.nchild), _p(tree.sys), _p(mom), _p(tree.cube),
         _p(g), _p(box), _p(sel), sel.shape[0], _p(spos), _p(smass), _p(sact),
-        float(eps), float(theta), _p(rel), _p(arel), float(G), _p(sacc), _p(spot),
-        _p(counts))
+        float(eps), float(theta), _p(side), _p(rel), _p(arel), float(G), _p(sacc),
+        _p(spot), _p(counts))
     if rc != 0:
         raise MemoryError("oracle tree forces")
     acc = np.full((n, 3), np.nan)
@@ -349,7 +365,7 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
     acc[p] = sacc
     pot[p] = spot
     return Evaluation(tree, mom, g, box, nact, sel, acc, pot, int(counts[0]),
-                      int(counts[1]), int(counts[2]), rel, arel)
+                      int(counts[1]), int(counts[2]), rel, arel, side)
 
 
 def direct(pos, mass, eps, targets=None, sys_off=None, xpos=None, xmass=None,

@@ -341,31 +341,75 @@ static int or_push(or_vec *a, uint32_t x) {
 /* coordinates i_k in the key prefix of the cell's first particle.          */
 /* rel[8 v] = {g_x - h, g_y - h, g_z - h, P, g_x + h, g_y + h, g_z + h, 0}. */
 /* ---------------------------------------------------------------------- */
+/* Geometric centre g of node v's cell and its side s = L 2^-level. */
+static double or_cell_centre(int64_t v, const uint8_t *level, const uint32_t *first,
+                             const int32_t *sys, const uint64_t *skeys,
+                             const double *cube, double g[3]) {
+  const double *c = cube + 4 * (int64_t)sys[v];
+  int l = (int)level[v];
+  double s = ldexp(c[3], -l);
+  uint64_t pre = skeys[first[v]] >> (3 * (OR_MAXLEVEL - l));
+  uint64_t ic[3] = {0, 0, 0};
+  for (int j = 0; j < l; ++j) {            /* digit j from the bottom */
+    uint64_t d = (pre >> (3 * j)) & 7u;
+    ic[0] |= ((d >> 2) & 1u) << j;
+    ic[1] |= ((d >> 1) & 1u) << j;
+    ic[2] |= (d & 1u) << j;
+  }
+  for (int k = 0; k < 3; ++k) g[k] = c[k] + ((double)ic[k] + 0.5) * s;
+  return s;
+}
+
+/* side == NULL: s = L 2^-level; else side[v] (a refitted tree). */
 void or_rel_records(int64_t nn, const uint8_t *level, const uint32_t *first,
                     const int32_t *sys, const uint64_t *skeys,
                     const double *cube, const double *mom, double G,
-                    double *rel) {
+                    const double *side, double *rel) {
   for (int64_t v = 0; v < nn; ++v) {
-    const double *c = cube + 4 * (int64_t)sys[v];
-    int l = (int)level[v];
-    double s = ldexp(c[3], -l);
-    uint64_t pre = skeys[first[v]] >> (3 * (OR_MAXLEVEL - l));
-    uint64_t ic[3] = {0, 0, 0};
-    for (int j = 0; j < l; ++j) {          /* digit j from the bottom */
-      uint64_t d = (pre >> (3 * j)) & 7u;
-      ic[0] |= ((d >> 2) & 1u) << j;
-      ic[1] |= ((d >> 1) & 1u) << j;
-      ic[2] |= (d & 1u) << j;
-    }
+    double g[3];
+    double s = or_cell_centre(v, level, first, sys, skeys, cube, g);
+    if (side) s = side[v];
     double h = 0.6 * s;
     double *o = rel + 8 * v;
     for (int k = 0; k < 3; ++k) {
-      double g = c[k] + ((double)ic[k] + 0.5) * s;
-      o[k] = g - h;
-      o[4 + k] = g + h;
+      o[k] = g[k] - h;
+      o[4 + k] = g[k] + h;
     }
     o[3] = (G * mom[10 * v]) * (s * s);
     o[7] = 0.0;
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Refit (READING of "update the tree structure if necessary", Sec. 2 step */
+/* 7): between full builds the sort order, nodes and groups stay; moments   */
+/* come from the current positions, and each cell's opening size becomes    */
+/*   s' = max(s, 2 e),  e = max_k max(hi_k - g_k, g_k - lo_k),              */
+/* with [lo, hi] the bounding box of the node's particles (exact min/max)   */
+/* and g the cell's geometric centre: the smallest cube about g that holds  */
+/* the cell and every particle of the node.  Both opening tests take s'.    */
+/* ---------------------------------------------------------------------- */
+void or_refit_sides(int64_t nn, const uint8_t *level, const uint32_t *first,
+                    const uint32_t *count, const int32_t *sys, const uint64_t *skeys,
+                    const double *cube, const double *spos, double *side) {
+  for (int64_t v = 0; v < nn; ++v) {
+    double g[3];
+    double s = or_cell_centre(v, level, first, sys, skeys, cube, g);
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = spos[3 * (int64_t)first[v] + k];
+    for (uint32_t j = first[v]; j < first[v] + count[v]; ++j)
+      for (int k = 0; k < 3; ++k) {
+        double x = spos[3 * (int64_t)j + k];
+        if (x < lo[k]) lo[k] = x;
+        if (x > hi[k]) hi[k] = x;
+      }
+    double e = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double a = hi[k] - g[k], b = g[k] - lo[k];
+      if (a > e) e = a;
+      if (b > e) e = b;
+    }
+    side[v] = (2.0 * e > s) ? 2.0 * e : s;
   }
 }
 
@@ -387,20 +431,21 @@ static int or_rel_accept(const double *glo, const double *ghi,
 }
 
 /* Walk one group; lists come back sorted ascending.  rel == NULL: the      */
-/* geometric test with theta; else the relative test with A = arel.  Root   */
-/* of the group's system: roots are the level-0 nodes in system order.      */
+/* geometric test with theta; else the relative test with A = arel.  side   */
+/* (refitted tree) replaces L 2^-level as the cell size.  Root of the       */
+/* group's system: roots are the level-0 nodes in system order.             */
 static int or_walk_one(uint32_t root, const uint8_t *level,
                        const uint32_t *child, const uint8_t *nchild,
                        const int32_t *sys, const double *mom,
                        const double *cube, const double *box, double theta,
-                       const double *rel, double arel,
+                       const double *side, const double *rel, double arel,
                        or_vec *p2m, or_vec *p2p, or_vec *work) {
   double th2 = theta * theta;
   p2m->n = p2p->n = work->n = 0;
   if (or_push(work, root)) return -1;
   while (work->n > 0) {
     uint32_t c = work->v[--work->n];
-    double s = ldexp(cube[4 * (int64_t)sys[c] + 3], -(int)level[c]);
+    double s = side ? side[c] : ldexp(cube[4 * (int64_t)sys[c] + 3], -(int)level[c]);
     const double *com = mom + 10 * (int64_t)c + 1;
     int acc = rel ? or_rel_accept(box, box + 3, com, rel + 8 * (int64_t)c, arel)
                   : or_mac_accept(box, box + 3, com, s * s, th2);
@@ -431,7 +476,7 @@ static uint32_t or_root_of(int32_t s, int64_t nn, const uint8_t *level,
 int or_walk_lists(int64_t nn, const uint8_t *level, const uint32_t *child,
                   const uint8_t *nchild, const int32_t *sys, const double *mom,
                   const double *cube, const uint32_t *g, const double *box,
-                  const int32_t *sel, int64_t nsel, double theta,
+                  const int32_t *sel, int64_t nsel, double theta, const double *side,
                   const double *rel, const double *arel,
                   int64_t *np2m, int64_t *np2p, const int64_t *lofs,
                   uint32_t *ids) {
@@ -444,7 +489,7 @@ int or_walk_lists(int64_t nn, const uint8_t *level, const uint32_t *child,
       int64_t k = sel[t];
       uint32_t root = or_root_of((int32_t)g[4 * k + 3], nn, level, sys);
       if (or_walk_one(root, level, child, nchild, sys, mom, cube, box + 6 * k,
-                      theta, rel, rel ? arel[k] : 0.0, &p2m, &p2p, &work)) {
+                      theta, side, rel, rel ? arel[k] : 0.0, &p2m, &p2p, &work)) {
         err = 1; continue;
       }
       np2m[t] = p2m.n; np2p[t] = p2p.n;
@@ -552,8 +597,9 @@ int or_tree_forces(int64_t nn, const uint8_t *level, const uint32_t *first,
                    const double *cube, const uint32_t *g, const double *box,
                    const int32_t *sel, int64_t nsel, const double *spos,
                    const double *smass, const uint8_t *sactive, double eps,
-                   double theta, const double *rel, const double *arel,
-                   double G, double *acc, double *pot, int64_t *counts) {
+                   double theta, const double *side, const double *rel,
+                   const double *arel, double G, double *acc, double *pot,
+                   int64_t *counts) {
   int err = 0;
   int64_t npp = 0, npm = 0, ntg = 0;
 #pragma omp parallel reduction(+ : npp, npm, ntg)
@@ -564,7 +610,7 @@ int or_tree_forces(int64_t nn, const uint8_t *level, const uint32_t *first,
       int64_t k = sel[t];
       uint32_t root = or_root_of((int32_t)g[4 * k + 3], nn, level, sys);
       if (or_walk_one(root, level, child, nchild, sys, mom, cube, box + 6 * k,
-                      theta, rel, rel ? arel[k] : 0.0, &p2m, &p2p, &work)) {
+                      theta, side, rel, rel ? arel[k] : 0.0, &p2m, &p2p, &work)) {
         err = 1; continue;
       }
       for (uint32_t i = g[4 * k]; i < g[4 * k] + g[4 * k + 1]; ++i) {

@@ -69,7 +69,7 @@ def oracle_lists(ev, theta):
     """Oracle sorted lists for every evaluated group, keyed by group index
     (relative test when the evaluation used it)."""
     L = oracle.walk_lists(ev.tree, ev.mom, ev.groups, ev.box, ev.sel, theta,
-                          rel=ev.rel, arel=ev.arel)
+                          rel=ev.rel, arel=ev.arel, side=ev.side)
     return {int(g): l for g, l in zip(ev.sel, L)}
 
 
@@ -82,10 +82,10 @@ def gpu_lists_by_group(info, ids):
     return out
 
 
-def mac_margin(tree, mom, box, node, theta):
+def mac_margin(tree, mom, box, node, theta, side=None):
     """Relative distance of one opening decision from its threshold."""
     lev = int(tree.level[node])
-    s = tree.cube[tree.sys[node], 3] * 2.0 ** -lev
+    s = tree.cube[tree.sys[node], 3] * 2.0 ** -lev if side is None else side[node]
     c = mom[node, 1:4]
     lo, hi = box[:3], box[3:]
     m = np.maximum(np.maximum(lo - c, c - hi), 0.0)
