@@ -120,6 +120,21 @@ tg_status tg_build_tree(tg_ctx *ctx, const double *pos_dev, int64_t n,
  * Requires a tree.  Errors: TG_ESTATE. */
 tg_status tg_compute_moments(tg_ctx *ctx, const double *mass_dev);
 
+/* ---- refit: update the tree without rebuilding it (Sec. 2 step 7) -----
+ * For the particles of the last tg_build_tree (same n and systems), moved:
+ * keeps the sort order, nodes and groups of that build, gathers the current
+ * positions and masses (caller order, as for the build; masses > 0, else
+ * TG_ERR_MASS; non-finite positions set TG_ERR_NONFINITE), recomputes the
+ * moments, and gives each node the opening size
+ *   s' = max(s, 2 e),  e = max_k max(hi_k - g_k, g_k - lo_k),
+ * [lo, hi] the bounding box of the node's particles, g its cell's centre and
+ * s its side: the smallest cube about the centre that holds the cell and all
+ * its particles (READING of "update the tree structure if necessary").
+ * Both opening tests use s' until the next tg_build_tree; a cell holding a
+ * target is still never accepted.  Replaces tg_compute_moments.
+ * Errors: TG_EINVAL, TG_ESTATE (no tree). */
+tg_status tg_refit_tree(tg_ctx *ctx, const double *pos_dev, const double *mass_dev);
+
 /* ---- group walk with the opening-angle test, P2P and P2M --------------
  * Forces and potentials on the active particles from all particles of their
  * own system.  active_idx_dev: caller-order indices of the targets, int32,

@@ -114,6 +114,7 @@ def lib():
             "tg_counter_add": (st, [P, P, i64]),
             "tg_set_external": (st, [P, P, P, P, i32, P, i32]),
             "tg_set_mac": (st, [P, i32, f64, P]),
+            "tg_refit_tree": (st, [P, P, P]),
             "tg_perturbers": (st, [P, P]),
             "tg_chain_forces": (st, [P, P, P, P, P, P, P, P]),
             "tg_select_within": (st, [P, P, i64, P, P, f64, P, i32, P]),
@@ -150,7 +151,7 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_set_sizes", "tg_build_tree", "tg_compute_moments",
             "tg_tree_forces", "tg_get_counts", "tg_reset_counts", "tg_walk_lists",
             "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
-            "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac",
+            "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac", "tg_refit_tree",
             "tg_perturbers", "tg_chain_forces", "tg_select_within",
             "tg_predict_perturbers", "tg_archain_init", "tg_archain_advance",
             "tg_archain_energy", "tg_forces",
@@ -275,6 +276,10 @@ class Context:
 
     def reset_counts(self):
         _check(lib().tg_reset_counts(self.h))
+
+    def refit_tree(self, pos, mass):
+        """Moments and opening sizes of the last build for moved particles."""
+        _check(lib().tg_refit_tree(self.h, _ptr(pos), _ptr(mass)))
 
     def set_mac(self, relative=False, alpha=0.0, acc_old=None):
         """Opening test of later walks: the opening angle (default), or the

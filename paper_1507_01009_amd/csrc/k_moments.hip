@@ -1,5 +1,5 @@
-// a7: monopole and quadrupole moments about each node's centre of mass
-// (the multipole expansion of a distant group about its centre of mass).
+// Monopole and quadrupole moments about each node's centre of mass (the
+// multipole expansion of a distant group about its centre of mass).
 //
 // Leaves first, all in one launch: a leaf sums its particles in sorted
 // order, two passes (mass and first moment, then the second moment about
@@ -9,7 +9,14 @@
 //   M = sum M_c,  com = (sum M_c com_c) / M,
 //   S = sum (S_c + M_c d d^T),  d = com_c - com.
 // The cell side s = L 2^-level (exact) is stored squared beside the centre
-// of mass for the opening-angle test.
+// of mass for the opening-angle test, and as the node's opening size.
+//
+// Refit (the tree is an earlier build, the particles have moved): the same
+// passes also take each node's particle bounding box (exact min / max,
+// leaves from their particles, internal nodes from their children) and the
+// opening size becomes s' = max(s, 2 e), e the largest distance from the
+// cell's geometric centre to the box: the smallest cube about the centre
+// that holds the cell and all its particles.
 #include "tg_internal.h"
 
 namespace tg {
@@ -28,12 +35,25 @@ __global__ void k_mass_gather(const int32_t *__restrict__ gate, const double *__
   if (bad) set_err(err, TG_ERR_MASS);
 }
 
-__device__ __forceinline__ void store_moments(uint32_t v, int l, const double *cube,
-                                              const uint32_t *nsys, double M, double cx,
+// Opening size of node v: the cell side s, or with a refit its refitted
+// size from the bounding box [lo, hi] (every operation rounded separately).
+__device__ __forceinline__ double open_size(uint32_t v, int l, const uint32_t *first,
+                                           const uint32_t *nsys, const uint64_t *skey,
+                                           const double *cube, const double lo[3],
+                                           const double hi[3], bool refit) {
+  double g[3];
+  const double s = cell_centre(v, l, first, nsys, skey, cube, g);
+  if (!refit) return s;
+  double e = 0.0;
+  for (int k = 0; k < 3; ++k) e = fmax(fmax(e, dsub(hi[k], g[k])), dsub(g[k], lo[k]));
+  return 2.0 * e > s ? 2.0 * e : s;
+}
+
+__device__ __forceinline__ void store_moments(uint32_t v, double s, double M, double cx,
                                               double cy, double cz, const double S[6],
-                                              double4 *com, double *mom) {
-  const double s = ldexp(cube[4 * nsys[v] + 3], -l);
-  com[v] = make_double4(cx, cy, cz, s * s);
+                                              double4 *com, double *mom, double *side) {
+  com[v] = make_double4(cx, cy, cz, dmul(s, s));
+  side[v] = s;
   double *o = mom + 8 * (size_t)v;
   o[0] = M;
   for (int k = 0; k < 6; ++k) o[1 + k] = S[k];
@@ -41,26 +61,36 @@ __device__ __forceinline__ void store_moments(uint32_t v, int l, const double *c
 }
 
 // Every leaf of the tree (nodes without children), any level.
-__global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restrict__ gate, 
+template <bool kBox>
+__global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restrict__ gate,
     const TreeCounters *ctr, const double *__restrict__ cube,
     const uint8_t *__restrict__ level, const uint8_t *__restrict__ nchild,
     const uint32_t *__restrict__ first, const uint32_t *__restrict__ count,
     const uint32_t *__restrict__ nsys, const double4 *__restrict__ spart,
-    double4 *__restrict__ com, double *__restrict__ mom) {
+    const uint64_t *__restrict__ skey, const int32_t *__restrict__ refit,
+    double4 *__restrict__ com, double *__restrict__ mom, double *__restrict__ side,
+    double4 *__restrict__ bbox, uint32_t *err) {
 #pragma clang fp contract(off)
   if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t nn = ctr->n_nodes;
+  bool bad = false;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
        v += gridDim.x * blockDim.x) {
     if (nchild[v] != 0) continue;
     const uint32_t f = first[v], end = f + count[v];
     double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t j = f; j < end; ++j) {
       const double4 p = spart[j];
       M += p.w;
       sx += p.w * p.x;
       sy += p.w * p.y;
       sz += p.w * p.z;
+      if constexpr (kBox) {
+        lo[0] = fmin(lo[0], p.x); lo[1] = fmin(lo[1], p.y); lo[2] = fmin(lo[2], p.z);
+        hi[0] = fmax(hi[0], p.x); hi[1] = fmax(hi[1], p.y); hi[2] = fmax(hi[2], p.z);
+        bad |= !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z);
+      }
     }
     const double cx = sx / M, cy = sy / M, cz = sz / M;
     double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -70,8 +100,17 @@ __global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restric
       S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
       S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
     }
-    store_moments(v, level[v], cube, nsys, M, cx, cy, cz, S, com, mom);
+    double so;
+    if constexpr (kBox) {
+      bbox[2 * (size_t)v] = make_double4(lo[0], lo[1], lo[2], 0.0);
+      bbox[2 * (size_t)v + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
+      so = open_size(v, level[v], first, nsys, skey, cube, lo, hi, *refit > 0);
+    } else {
+      so = ldexp(cube[4 * nsys[v] + 3], -(int)level[v]);
+    }
+    store_moments(v, so, M, cx, cy, cz, S, com, mom, side);
   }
+  if (kBox && bad) set_err(err, TG_ERR_NONFINITE);
 }
 
 // Sum over the 8 lanes of an aligned lane octet (xor tree: deterministic).
@@ -81,13 +120,27 @@ __device__ __forceinline__ double oct_sum(double v) {
   v += __shfl_xor(v, 4, 64);
   return v;
 }
+__device__ __forceinline__ double oct_min(double v) {
+  v = fmin(v, __shfl_xor(v, 1, 64));
+  v = fmin(v, __shfl_xor(v, 2, 64));
+  return fmin(v, __shfl_xor(v, 4, 64));
+}
+__device__ __forceinline__ double oct_max(double v) {
+  v = fmax(v, __shfl_xor(v, 1, 64));
+  v = fmax(v, __shfl_xor(v, 2, 64));
+  return fmax(v, __shfl_xor(v, 4, 64));
+}
 
 // Internal nodes of level l from their children (level l + 1, done): eight
 // lanes per node, lane k holding child k.
-__global__ __launch_bounds__(256) void k_moments_level(const int32_t *__restrict__ gate, 
+template <bool kBox>
+__global__ __launch_bounds__(256) void k_moments_level(const int32_t *__restrict__ gate,
     int l, const TreeCounters *ctr, const double *__restrict__ cube,
     const uint8_t *__restrict__ nchild, const uint32_t *__restrict__ child,
-    const uint32_t *__restrict__ nsys, double4 *__restrict__ com, double *__restrict__ mom) {
+    const uint32_t *__restrict__ nsys, const uint32_t *__restrict__ first,
+    const uint64_t *__restrict__ skey, const int32_t *__restrict__ refit,
+    double4 *__restrict__ com, double *__restrict__ mom, double *__restrict__ side,
+    double4 *__restrict__ bbox) {
 #pragma clang fp contract(off)
   if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t a = ctr->lvl[l], e = ctr->lvl[l + 1];
@@ -120,23 +173,51 @@ __global__ __launch_bounds__(256) void k_moments_level(const int32_t *__restrict
     S[3] = oct_sum(mine ? o4 + mc * dx * dy : 0.0);
     S[4] = oct_sum(mine ? o5 + mc * dx * dz : 0.0);
     S[5] = oct_sum(mine ? o6 + mc * dy * dz : 0.0);
-    if (live && nch > 0 && k == 0) store_moments(v, l, cube, nsys, M, cx, cy, cz, S, com, mom);
+    double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+    if constexpr (kBox) {
+      double4 b0 = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+      double4 b1 = make_double4(-INFINITY, -INFINITY, -INFINITY, 0.0);
+      if (mine) { b0 = bbox[2 * (size_t)c]; b1 = bbox[2 * (size_t)c + 1]; }
+      lo[0] = oct_min(b0.x); lo[1] = oct_min(b0.y); lo[2] = oct_min(b0.z);
+      hi[0] = oct_max(b1.x); hi[1] = oct_max(b1.y); hi[2] = oct_max(b1.z);
+    }
+    if (live && nch > 0 && k == 0) {
+      double so;
+      if constexpr (kBox) {
+        bbox[2 * (size_t)v] = make_double4(lo[0], lo[1], lo[2], 0.0);
+        bbox[2 * (size_t)v + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
+        so = open_size(v, l, first, nsys, skey, cube, lo, hi, *refit > 0);
+      } else {
+        so = ldexp(cube[4 * nsys[v] + 3], -l);
+      }
+      store_moments(v, so, M, cx, cy, cz, S, com, mom, side);
+    }
   }
 }
 
-hipError_t launch_moments(tg_ctx *c, const double *mass, bool gathered) {
+template <bool kBox>
+static void launch_moment_passes(tg_ctx *c) {
+  Buffers &b = c->b;
+  hipLaunchKernelGGL((k_moments_leaves<kBox>), dim3(1024), dim3(256), 0, c->stream, c->gate,
+                     b.ctr, b.cube, b.level, b.nchild, b.first, b.count, b.nsys, b.spart,
+                     b.key[0], b.refit_flag, b.com, b.mom, b.side, b.bbox, b.err);
+  for (int l = kMaxLevel - 1; l >= 0; --l)     // level 21 holds only leaves
+    hipLaunchKernelGGL((k_moments_level<kBox>), dim3(512), dim3(256), 0, c->stream, c->gate, l,
+                       b.ctr, b.cube, b.nchild, b.child, b.nsys, b.first, b.key[0],
+                       b.refit_flag, b.com, b.mom, b.side, b.bbox);
+}
+
+hipError_t launch_moments(tg_ctx *c, const double *mass, bool gathered, bool refit) {
   Buffers &b = c->b;
   if (c->n == 0) return hipSuccess;
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
   if (!gathered)        // else the build's gather brought the masses already
     hipLaunchKernelGGL(k_mass_gather, dim3(g), dim3(256), 0, c->stream, c->gate, mass,
                        b.val[0], c->n, b.spart, b.err);
-  hipLaunchKernelGGL(k_moments_leaves, dim3(1024), dim3(256), 0, c->stream, c->gate, b.ctr,
-                     b.cube, b.level, b.nchild, b.first, b.count, b.nsys, b.spart, b.com,
-                     b.mom);
-  for (int l = kMaxLevel - 1; l >= 0; --l)     // level 21 holds only leaves
-    hipLaunchKernelGGL(k_moments_level, dim3(512), dim3(256), 0, c->stream, c->gate, l, b.ctr,
-                       b.cube, b.nchild, b.child, b.nsys, b.com, b.mom);
+  if (refit)
+    launch_moment_passes<true>(c);
+  else
+    launch_moment_passes<false>(c);
   return hipGetLastError();
 }
 

@@ -911,10 +911,8 @@ __global__ __launch_bounds__(256) void k_cell_records(const int32_t *__restrict_
 }
 
 // Relative-test records of every node: the cell cube enlarged by 20 %
-// about its geometric centre and P = (G M) s^2.  The centre comes from the
-// integer cell coordinates in the key prefix of the node's first particle:
-// g_k = lo_k + (i_k + 0.5) s, s = L 2^-level, every operation rounded
-// separately (no contraction).
+// about its geometric centre and P = (G M) s^2, s the node's opening size
+// (the cell side, or its refitted size), every operation rounded separately.
 __global__ __launch_bounds__(256) void k_rel_records(const int32_t *__restrict__ gate,
                                                      const TreeCounters *ctr,
                                                      const uint8_t *__restrict__ level,
@@ -922,31 +920,23 @@ __global__ __launch_bounds__(256) void k_rel_records(const int32_t *__restrict__
                                                      const uint32_t *__restrict__ nsys,
                                                      const uint64_t *__restrict__ skey,
                                                      const double *__restrict__ cube,
-                                                     const double *__restrict__ mom, double G,
+                                                     const double *__restrict__ mom,
+                                                     const double *__restrict__ side, double G,
                                                      double4 *__restrict__ rel) {
 #pragma clang fp contract(off)
   if (gate && *gate <= 0) return;   // nothing active: skipped
   const uint32_t nn = ctr->n_nodes;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
        v += gridDim.x * blockDim.x) {
-    const int l = level[v];
-    const double *cb = cube + 4 * (size_t)nsys[v];
-    const double s = ldexp(cb[3], -l);
-    const uint64_t pre = l ? skey[first[v]] >> (3 * (kMaxLevel - l)) : 0ull;
-    uint32_t ic[3] = {0u, 0u, 0u};
-    for (int j = 0; j < l; ++j) {
-      const uint32_t d = (uint32_t)(pre >> (3 * j)) & 7u;
-      ic[0] |= ((d >> 2) & 1u) << j;
-      ic[1] |= ((d >> 1) & 1u) << j;
-      ic[2] |= (d & 1u) << j;
-    }
+    double g[3];
+    cell_centre(v, level[v], first, nsys, skey, cube, g);
+    const double s = side[v];
     const double h = dmul(0.6, s);
     double lo[3], hi[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double g = dadd(cb[k], dmul(dadd((double)ic[k], 0.5), s));
-      lo[k] = dsub(g, h);
-      hi[k] = dadd(g, h);
+      lo[k] = dsub(g[k], h);
+      hi[k] = dadd(g[k], h);
     }
     const double P = dmul(dmul(G, mom[8 * (size_t)v]), dmul(s, s));
     rel[2 * (size_t)v] = make_double4(lo[0], lo[1], lo[2], P);
@@ -957,7 +947,7 @@ __global__ __launch_bounds__(256) void k_rel_records(const int32_t *__restrict__
 static hipError_t launch_rel_records(tg_ctx *c) {
   Buffers &b = c->b;
   hipLaunchKernelGGL(k_rel_records, dim3(1024), dim3(256), 0, c->stream, c->gate, b.ctr,
-                     b.level, b.first, b.nsys, b.key[0], b.cube, b.mom, c->cfg.G, b.rel);
+                     b.level, b.first, b.nsys, b.key[0], b.cube, b.mom, b.side, c->cfg.G, b.rel);
   return hipGetLastError();
 }
 

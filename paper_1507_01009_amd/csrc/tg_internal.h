@@ -81,6 +81,9 @@ struct Buffers {
   double *mom = nullptr;          // [nodes][8]
   uint4 *ninfo = nullptr;         // [nodes] {first, count, child, nchild} for the walk
   double4 *rel = nullptr;         // [nodes][2] relative test {enlarged cube lo, (G M) s^2} {hi, 0}
+  double *side = nullptr;         // [nodes] opening size: the cell side, or refitted
+  double4 *bbox = nullptr;        // [nodes][2] particle bounding box {lo, -} {hi, -} (refit)
+  int32_t *refit_flag = nullptr;  // [1] > 0: moments with bounding boxes take refitted sizes
   double4 *cell = nullptr;        // [nodes][2] walk records {Qxx,Qyy,Qzz,-T eps^2} {Qxy,Qxz,Qyz,M}
                                   // (FP64; the mixed path uses the first half as float4[nodes][2])
   uint8_t *lcp = nullptr;         // [N + 64] common leading digits with predecessor
@@ -206,6 +209,26 @@ __device__ __forceinline__ double dsub(double a, double b) {
   return a - b;
 }
 
+// Geometric centre g of node v's cell, from the integer cell coordinates in
+// the key prefix of its first particle: g_k = lo_k + (i_k + 0.5) s, with
+// s = L 2^-level returned; every operation rounded separately.
+__device__ __forceinline__ double cell_centre(uint32_t v, int l, const uint32_t *first,
+                                              const uint32_t *nsys, const uint64_t *skey,
+                                              const double *cube, double g[3]) {
+  const double *cb = cube + 4 * (size_t)nsys[v];
+  const double s = ldexp(cb[3], -l);
+  const uint64_t pre = l ? skey[first[v]] >> (3 * (kMaxLevel - l)) : 0ull;
+  uint32_t ic[3] = {0u, 0u, 0u};
+  for (int j = 0; j < l; ++j) {
+    const uint32_t d = (uint32_t)(pre >> (3 * j)) & 7u;
+    ic[0] |= ((d >> 2) & 1u) << j;
+    ic[1] |= ((d >> 1) & 1u) << j;
+    ic[2] |= (d & 1u) << j;
+  }
+  for (int k = 0; k < 3; ++k) g[k] = dadd(cb[k], dmul(dadd((double)ic[k], 0.5), s));
+  return s;
+}
+
 // Compensated double sum (error-free TwoSum with a running correction),
 // used by the direct sums and the chain coupling.
 struct CSum {
@@ -234,7 +257,9 @@ hipError_t launch_tree_build(tg_ctx *c);
 hipError_t launch_groups(tg_ctx *c);
 
 // k_moments.hip
-hipError_t launch_moments(tg_ctx *c, const double *mass, bool gathered);
+// refit: bounding boxes and refitted opening sizes (the tree is an earlier
+// build; the gather with its permutation was done by the caller)
+hipError_t launch_moments(tg_ctx *c, const double *mass, bool gathered, bool refit = false);
 
 // k_walk.hip
 // acc_old != nullptr: also the relative test's per-group thresholds

@@ -137,6 +137,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.parent, NN)); A(dalloc(&b.nsys, NN));
   A(dalloc(&b.com, NN)); A(dalloc(&b.mom, 8 * NN));
   A(dalloc(&b.ninfo, NN)); A(dalloc(&b.cell, 2 * NN)); A(dalloc(&b.rel, 2 * NN));
+  A(dalloc(&b.side, NN)); A(dalloc(&b.bbox, 2 * NN)); A(dalloc(&b.refit_flag, 1));
   c->flat_tiles = (N + 255) / 256;
   A(dalloc(&b.lcp, N + 64));
   A(dalloc(&b.fl_lt, std::max<int64_t>(N, 1)));
@@ -296,6 +297,23 @@ tg_status tg_compute_moments(tg_ctx *c, const double *mass) {
   const bool gathered = mass == c->mass_gathered;
   c->mass_gathered = nullptr;
   TG_HIP(launch_moments(c, mass, gathered));
+  c->have_moments = true;
+  return TG_OK;
+}
+
+tg_status tg_refit_tree(tg_ctx *c, const double *pos, const double *mass) {
+  if (!c) return fail(TG_EINVAL, "tg_refit_tree: NULL context");
+  if (!c->have_tree) return fail(TG_ESTATE, "tg_refit_tree: no tree to refit");
+  if (c->n > 0 && (!pos || !mass)) return fail(TG_EINVAL, "tg_refit_tree: NULL positions or masses");
+  if (c->n == 0) {
+    c->have_moments = true;
+    return TG_OK;
+  }
+  c->have_moments = false;
+  c->mass_gathered = nullptr;
+  TG_HIP(fill_u32((uint32_t *)c->b.refit_flag, 1u, 1, c->stream, c->gate));
+  TG_HIP(launch_gather(c, pos, mass));
+  TG_HIP(launch_moments(c, mass, true, true));
   c->have_moments = true;
   return TG_OK;
 }

@@ -1,0 +1,137 @@
+"""GPU parity of the refitted tree (tg_refit_tree) against the oracle's
+refit: the build's order, nodes and groups kept, moments and opening sizes
+from moved particles.  Bar as for the build: lists and counts equal up to
+threshold flips within the rounding of internal-node moments, FP64 forces
+<= 1e-12, mixed precision median <= 1e-5 and p99 <= 1e-4."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1507_01009_amd import ics
+from gpu_helpers import (rel_err, to_dev, oracle_lists, gpu_lists_by_group, mac_margin,
+                         rel_margin)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _run(p0, p1, m, eps, theta, nl=8, ng=64, precision=0, active=None, lists=False,
+         alpha=None, acc_old=None):
+    import torch
+    from paper_1507_01009_amd import binding as B
+    n = p0.shape[0]
+    ctx = B.Context(n, leaf_size=nl, group_size=ng, precision=precision)
+    dm = to_dev(m)
+    ctx.build_tree(to_dev(p0))
+    ctx.compute_moments(dm)
+    d1 = to_dev(p1)
+    ctx.refit_tree(d1, dm)
+    dold = None
+    if alpha is not None:
+        dold = to_dev(acc_old)
+        ctx.set_mac(True, alpha, dold)
+    acc = torch.full((n, 3), float("nan"), dtype=torch.float64, device="cuda")
+    pot = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    didx = dna = None
+    if active is not None:
+        didx = to_dev(np.asarray(active, np.int32))
+        dna = to_dev(np.array([len(active)], np.int32))
+    ctx.tree_forces(eps, theta, acc, pot, didx, dna)
+    ctx.sync()
+    out = {"acc": acc.cpu().numpy(), "pot": pot.cpu().numpy(), "counts": ctx.get_counts()}
+    if lists:
+        out["lists"] = ctx.walk_lists(theta, didx, dna)
+    return out
+
+
+def _drift(n, gamma, seed, dt):
+    pos, vel, m = ics.dehnen(n, gamma, seed)
+    return pos, pos + vel * dt, m
+
+
+@pytest.mark.parametrize("n,gamma,dt,theta,every", [(32768, 1.0, 0.02, 0.5, 1),
+                                                    (32768, 1.5, 0.1, 0.5, 3),
+                                                    (4096, 1.0, 0.3, 0.57, 1),
+                                                    (131072, 1.0, 0.01, 0.5, 1)])
+def test_refit_forces_and_lists_match(n, gamma, dt, theta, every):
+    say("refit", n, gamma, dt, theta, every)
+    p0, p1, m = _drift(n, gamma, 900 + n % 97, dt)
+    active = None if every == 1 else np.arange(0, n, every)
+    g = _run(p0, p1, m, 0.01, theta, active=active, lists=True)
+    t = oracle.build_tree(p0, None, 8)
+    ev = oracle.tree_forces(p1, m, 0.01, theta, 8, 64, active=active, tree=t, refit=True)
+    assert np.mean(ev.side > t.cube[0, 3] * 2.0 ** -t.level.astype(float)) > 0.05
+    rows = np.arange(n) if active is None else active
+    e = rel_err(g["acc"][rows], ev.acc[rows])
+    ep = np.abs(g["pot"][rows] - ev.pot[rows]) / np.abs(ev.pot[rows])
+    say("  max rel acc %.3g pot %.3g" % (e.max(), ep.max()))
+    assert e.max() <= FP64_TOL and ep.max() <= FP64_TOL
+    c = g["counts"]
+    assert (c["n_p2p"], c["n_p2m"], c["n_targets"]) == (ev.n_p2p, ev.n_p2m, ev.n_targets)
+    ol = oracle_lists(ev, theta)
+    gl = gpu_lists_by_group(*g["lists"])
+    assert sorted(gl) == sorted(ol)
+    for k, (om, op) in ol.items():
+        gm, gp = gl[k]
+        if not (np.array_equal(gm, om) and np.array_equal(gp, op)):
+            for v in set(np.setxor1d(gm, om)) | set(np.setxor1d(gp, op)):
+                anc = v
+                while anc != 0xFFFFFFFF:
+                    if mac_margin(ev.tree, ev.mom, ev.box[k], anc, theta, ev.side) < 1e-12:
+                        break
+                    anc = ev.tree.parent[anc]
+                assert anc != 0xFFFFFFFF, (k, v)
+
+
+def test_refit_of_unmoved_particles_is_the_build():
+    say("refit unmoved")
+    from gpu_helpers import gpu_run
+    pos, _, m = ics.dehnen(32768, 1.0, 901)
+    g = _run(pos, pos, m, 0.01, 0.5)
+    b = gpu_run(pos, m, 0.01, 0.5, 8, 64)
+    assert rel_err(g["acc"], b["acc"]).max() <= 1e-13
+
+
+def test_refit_mixed_precision_and_relative_test():
+    say("refit mixed / relative")
+    p0, p1, m = _drift(65536, 1.5, 902, 0.02)
+    t = oracle.build_tree(p0, None, 8)
+    ev = oracle.tree_forces(p1, m, 1e-3, 0.5, tree=t, refit=True)
+    g = _run(p0, p1, m, 1e-3, 0.5, precision=1)
+    e = rel_err(g["acc"], ev.acc)
+    say("  mixed p50 %.3g p99 %.3g" % (np.median(e), np.percentile(e, 99)))
+    assert np.median(e) <= 1e-5 and np.percentile(e, 99) <= 1e-4
+    aold = ev.acc
+    evr = oracle.tree_forces(p1, m, 1e-3, 0.5, tree=t, refit=True, alpha=1e-3, acc_old=aold)
+    gr = _run(p0, p1, m, 1e-3, 0.5, alpha=1e-3, acc_old=aold)
+    er = rel_err(gr["acc"], evr.acc)
+    say("  relative max %.3g" % er.max())
+    assert er.max() <= FP64_TOL
+    assert gr["counts"]["n_p2m"] == evr.n_p2m and gr["counts"]["n_p2p"] == evr.n_p2p
+
+
+def test_refit_errors():
+    say("refit errors")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    pos, _, m = ics.plummer(2048, 903)
+    ctx = B.Context(2048)
+    with pytest.raises(B.TGError) as e:
+        ctx.refit_tree(to_dev(pos), to_dev(m))
+    assert e.value.status == -5
+    ctx.build_tree(to_dev(pos))
+    ctx.compute_moments(to_dev(m))
+    bad = pos.copy()
+    bad[100, 2] = np.inf
+    ctx.refit_tree(to_dev(bad), to_dev(m))
+    with pytest.raises(B.TGError) as e:
+        ctx.sync()
+    assert e.value.status == -6
