@@ -427,6 +427,9 @@ typedef struct {
   double dt_max;                   /* step of level 0 */
   int32_t nlev;                    /* levels 0..nlev-1; smallest step dt_max 2^-(nlev-1) */
   const double *tau2eps2v;         /* [n] tau_vel^2 eps^2 per star (velocity criterion), or NULL */
+  int32_t rebuild_every;           /* > 1: rebuild the tree at substeps k that are multiples of
+                                      it and refit it in between (tg_refit_tree); 0, 1: rebuild
+                                      at every substep with active stars */
 } tg_blocks;
 
 /* One substep of the smallest step: closing half kicks of the stars whose

@@ -44,6 +44,7 @@ class State:
     group_size: int = 64
     alpha: float = None      # relative opening test (None: opening angle theta)
     frozen: np.ndarray = None  # bool [n]: stars held still (ghost chain members)
+    tree: object = None        # the last tree built (refitted between builds)
     acc: np.ndarray = field(default=None)
     pot: np.ndarray = field(default=None)
     bh_acc: np.ndarray = field(default=None)
@@ -59,16 +60,28 @@ class State:
             self.bh_pot = np.zeros(nb)
 
 
-def forces(st: State, active=None):
-    """Tree + SMBH forces for the listed stars; SMBH forces for all SMBHs."""
+def forces(st: State, active=None, k=None, rebuild_every=0):
+    """Tree + SMBH forces for the listed stars; SMBH forces for all SMBHs.
+    With a rebuild period (block steps, substep k) the tree is rebuilt when k
+    is a multiple of it or none was built yet, and refitted otherwise (READING
+    of "update the tree structure if necessary", Sec. 2 step 7).  No tree
+    work when the list is empty."""
     n = st.pos.shape[0]
     S = st.sys_off.shape[0] - 1
-    rel = {} if st.alpha is None else {"alpha": st.alpha, "acc_old": st.acc.copy()}
-    ev = oracle.tree_forces(st.pos, st.mass, st.eps, st.theta, st.leaf_size,
-                            st.group_size, active=active, sys_off=st.sys_off, **rel)
     rows = np.arange(n) if active is None else np.asarray(active, np.int64)
-    st.acc[rows] = ev.acc[rows]
-    st.pot[rows] = ev.pot[rows]
+    if rows.size:
+        rel = {} if st.alpha is None else {"alpha": st.alpha, "acc_old": st.acc.copy()}
+        refit = (rebuild_every > 1 and k is not None and st.tree is not None
+                 and k % rebuild_every != 0)
+        ev = oracle.tree_forces(st.pos, st.mass, st.eps, st.theta, st.leaf_size,
+                                st.group_size, active=active, sys_off=st.sys_off,
+                                tree=st.tree if refit else None, refit=refit, **rel)
+        if not refit:
+            st.tree = ev.tree
+        st.acc[rows] = ev.acc[rows]
+        st.pot[rows] = ev.pot[rows]
+    else:
+        ev = None
     for s in range(S):
         b0, b1 = int(st.bh_seg[s]), int(st.bh_seg[s + 1])
         if b1 == b0:
@@ -150,9 +163,10 @@ def _active(st: State, level, nlev, k):
 
 
 def block_substep(st: State, level: np.ndarray, tau4eps2: np.ndarray, k: int,
-                  dt_max: float, nlev: int, tau2eps2v=None):
+                  dt_max: float, nlev: int, tau2eps2v=None, rebuild_every=0):
     """One substep at counter k; returns k + 1 and the new active set.  With
-    tau2eps2v the levels also take the velocity criterion."""
+    tau2eps2v the levels also take the velocity criterion; with a rebuild
+    period the tree is refitted between rebuilds."""
     dt_min = dt_max * 2.0 ** -(nlev - 1)
     act = _active(st, level, nlev, k)
     if k > 0:
@@ -172,5 +186,5 @@ def block_substep(st: State, level: np.ndarray, tau4eps2: np.ndarray, k: int,
         oracle.drift(st.bh_pos, st.bh_vel, dt_min)
     k += 1
     act = _active(st, level, nlev, k)
-    forces(st, act)
+    forces(st, act, k, rebuild_every)
     return k, act

@@ -56,7 +56,8 @@ class tg_system(C.Structure):
 class tg_blocks(C.Structure):
     _fields_ = [("level", C.c_void_p), ("tau4eps2", C.c_void_p),
                 ("active_idx", C.c_void_p), ("n_active", C.c_void_p), ("k", C.c_void_p),
-                ("dt_max", C.c_double), ("nlev", C.c_int32), ("tau2eps2v", C.c_void_p)]
+                ("dt_max", C.c_double), ("nlev", C.c_int32), ("tau2eps2v", C.c_void_p),
+                ("rebuild_every", C.c_int32)]
 
 
 class tg_chain(C.Structure):
@@ -416,12 +417,13 @@ class Context:
         _check(lib().tg_step_dkd(self.h, C.byref(system), float(dt)))
 
     def make_blocks(self, level, tau4eps2, active_idx, n_active, k, dt_max, nlev,
-                    tau2eps2v=None):
+                    tau2eps2v=None, rebuild_every=0):
         b = tg_blocks()
         b.level, b.tau4eps2 = _ptr(level), _ptr(tau4eps2)
         b.active_idx, b.n_active, b.k = _ptr(active_idx), _ptr(n_active), _ptr(k)
         b.dt_max, b.nlev = float(dt_max), int(nlev)
         b.tau2eps2v = _ptr(tau2eps2v)
+        b.rebuild_every = int(rebuild_every)
         return b
 
     def step_block(self, system, blocks):

@@ -424,4 +424,25 @@ hipError_t launch_groups(tg_ctx *c) {
   return hipGetLastError();
 }
 
+// Block steps with a rebuild period: rebuild at substeps k that are
+// multiples of it (or when no build exists yet), refit otherwise; neither
+// when no star is active.
+__global__ void k_refit_gates(const int32_t *__restrict__ n_act, const int64_t *__restrict__ k,
+                              int32_t every, int32_t *__restrict__ gates,
+                              int32_t *__restrict__ refit_flag) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const bool any = !n_act || n_act[0] > 0;
+  const bool build = any && (k[0] % every == 0 || gates[2] == 0);
+  const bool refit = any && !build;
+  gates[0] = build ? 1 : 0;
+  gates[1] = refit ? 1 : 0;
+  refit_flag[0] = refit ? 1 : 0;
+}
+
+hipError_t launch_refit_gates(tg_ctx *c, const int32_t *n_act, const int64_t *k, int32_t every) {
+  hipLaunchKernelGGL(k_refit_gates, dim3(1), dim3(64), 0, c->stream, n_act, k, every,
+                     c->b.refit_gates, c->b.refit_flag);
+  return hipGetLastError();
+}
+
 }  // namespace tg

@@ -84,6 +84,7 @@ struct Buffers {
   double *side = nullptr;         // [nodes] opening size: the cell side, or refitted
   double4 *bbox = nullptr;        // [nodes][2] particle bounding box {lo, -} {hi, -} (refit)
   int32_t *refit_flag = nullptr;  // [1] > 0: moments with bounding boxes take refitted sizes
+  int32_t *refit_gates = nullptr; // [3] block steps: rebuild now, refit now, a build exists
   double4 *cell = nullptr;        // [nodes][2] walk records {Qxx,Qyy,Qzz,-T eps^2} {Qxy,Qxz,Qyz,M}
                                   // (FP64; the mixed path uses the first half as float4[nodes][2])
   uint8_t *lcp = nullptr;         // [N + 64] common leading digits with predecessor
@@ -255,6 +256,8 @@ hipError_t launch_rank(tg_ctx *c);
 // k_tree.hip
 hipError_t launch_tree_build(tg_ctx *c);
 hipError_t launch_groups(tg_ctx *c);
+// gates[0] = rebuild, gates[1] = refit (and the refit flag) for substep k
+hipError_t launch_refit_gates(tg_ctx *c, const int32_t *n_act, const int64_t *k, int32_t every);
 
 // k_moments.hip
 // refit: bounding boxes and refitted opening sizes (the tree is an earlier

@@ -138,6 +138,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.com, NN)); A(dalloc(&b.mom, 8 * NN));
   A(dalloc(&b.ninfo, NN)); A(dalloc(&b.cell, 2 * NN)); A(dalloc(&b.rel, 2 * NN));
   A(dalloc(&b.side, NN)); A(dalloc(&b.bbox, 2 * NN)); A(dalloc(&b.refit_flag, 1));
+  A(dalloc(&b.refit_gates, 3));
   c->flat_tiles = (N + 255) / 256;
   A(dalloc(&b.lcp, N + 64));
   A(dalloc(&b.fl_lt, std::max<int64_t>(N, 1)));
@@ -169,6 +170,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   }
   A(hipMemset(b.ctr, 0, sizeof(TreeCounters)));
   A(hipMemset(b.err, 0, sizeof(uint32_t)));
+  A(hipMemset(b.refit_gates, 0, 3 * sizeof(int32_t)));
   A(hipDeviceSynchronize());
   if (a != hipSuccess) {
     free_all(c);
@@ -279,6 +281,8 @@ static tg_status build_tree_impl(tg_ctx *c, const double *pos, const double *mas
   TG_HIP(launch_gather(c, pos, mass));
   TG_HIP(launch_tree_build(c));
   TG_HIP(launch_groups(c));
+  // a build exists now (read by the device-side rebuild / refit choice)
+  TG_HIP(fill_u32((uint32_t *)(c->b.refit_gates + 2), 1u, 1, c->stream, c->gate));
   c->have_tree = true;
   c->mass_gathered = mass;
   return TG_OK;
@@ -871,15 +875,40 @@ static tg_status check_system(const tg_system *y, const char *who) {
   return TG_OK;
 }
 
-tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
-                    const int32_t *n_act) {
+// Forces for the listed stars.  With a rebuild period (block steps) the
+// tree is rebuilt when the substep counter k is a multiple of it (or no
+// build exists yet) and refitted otherwise; both choices are made on the
+// device, so a captured substep replays correctly.
+static tg_status forces_impl(tg_ctx *c, const tg_system *y, const int32_t *idx,
+                             const int32_t *n_act, const int64_t *k, int32_t rebuild_every) {
   tg_status st = check_system(y, "tg_forces");
   if (st != TG_OK) return st;
   // with an active list, the build, moments and walk are skipped on the
   // device when it is empty (the SMBH sums below always run)
-  c->gate = idx ? n_act : nullptr;
-  st = build_tree_impl(c, y->pos, y->mass, y->n, y->sys_off, y->n_sys);
-  if (st == TG_OK) st = tg_compute_moments(c, y->mass);
+  const int32_t *gate = idx ? n_act : nullptr;
+  if (rebuild_every > 1 && k && y->n > 0 && c->have_tree && y->n == c->n &&
+      y->n_sys == c->S) {
+    int32_t *gb = c->b.refit_gates, *gr = c->b.refit_gates + 1;
+    TG_HIP(launch_refit_gates(c, gate, k, rebuild_every));
+    c->gate = gb;
+    st = build_tree_impl(c, y->pos, y->mass, y->n, y->sys_off, y->n_sys);
+    if (st == TG_OK) {
+      c->gate = gr;
+      if (hipError_t e = launch_gather(c, y->pos, y->mass); e != hipSuccess)
+        st = hip_fail(e, "launch_gather");
+    }
+    if (st == TG_OK) {
+      c->gate = gate;
+      c->mass_gathered = nullptr;
+      if (hipError_t e = launch_moments(c, y->mass, true, true); e != hipSuccess)
+        st = hip_fail(e, "launch_moments");
+      c->have_moments = st == TG_OK;
+    }
+  } else {
+    c->gate = gate;
+    st = build_tree_impl(c, y->pos, y->mass, y->n, y->sys_off, y->n_sys);
+    if (st == TG_OK) st = tg_compute_moments(c, y->mass);
+  }
   c->gate = nullptr;
   if (st != TG_OK) return st;
   if ((st = tg_set_external(c, y->bh_pos, y->bh_mass, y->bh_eps, y->n_bh,
@@ -906,6 +935,11 @@ tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
     if (st != TG_OK) return st;
   }
   return TG_OK;
+}
+
+tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
+                    const int32_t *n_act) {
+  return forces_impl(c, y, idx, n_act, nullptr, 0);
 }
 
 tg_status tg_step_kdk(tg_ctx *c, const tg_system *y, double dt) {
@@ -977,7 +1011,7 @@ tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
   if ((st = active_set_impl(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active,
                              y->frozen)))
     return st;
-  return tg_forces(c, y, b->active_idx, b->n_active);
+  return forces_impl(c, y, b->active_idx, b->n_active, b->k, b->rebuild_every);
 }
 
 static tg_status check_chain(tg_ctx *c, const tg_chain *ch, const char *who) {

@@ -135,3 +135,74 @@ def test_refit_errors():
     with pytest.raises(B.TGError) as e:
         ctx.sync()
     assert e.value.status == -6
+
+
+@pytest.mark.parametrize("every", [4, 16])
+def test_block_substeps_with_refit_match_oracle(every):
+    """Block steps rebuilding the tree every few substeps and refitting it in
+    between, captured decision on the device, against the oracle's steps
+    with the same period."""
+    say("block refit", every)
+    from oracle import steps as osteps
+    from paper_1507_01009_amd import binding as B
+    from test_gpu_steps import Dev, ostate, _blocks
+    w = ics.hernquist_c4(n=8192)
+    nlev, dt_max = 8, 0.25
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    blk, keep = _blocks(ctx, w, nlev, dt_max)
+    blk.rebuild_every = every
+    ctx.forces(d.sys)
+    for _ in range(40):
+        ctx.step_block(d.sys, blk)
+    ctx.sync()
+    h = d.host()
+    st = ostate(w)
+    osteps.forces(st)
+    level = np.zeros(w.n, np.uint8)
+    t4e2 = np.full(w.n, 0.3 ** 4 * w.eps ** 2)
+    k = 0
+    for _ in range(40):
+        k, act = osteps.block_substep(st, level, t4e2, k, dt_max, nlev, rebuild_every=every)
+    assert np.array_equal(keep[0].cpu().numpy(), level)
+    assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-12 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-11 * np.abs(st.vel).max()
+
+
+def test_block_substep_with_refit_graph_replay():
+    """One captured substep replayed: the device picks build or refit at each
+    replay from the substep counter, bit-equal to the same substeps eager."""
+    say("block refit graph")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    from test_gpu_steps import Dev, _blocks
+    w = ics.hernquist_c4(n=8192)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        runs = []
+        for mode in ("eager", "graph"):
+            ctx = B.Context(w.n, stream=s)
+            d = Dev(ctx, w)
+            blk, keep = _blocks(ctx, w, 8, 0.25)
+            blk.rebuild_every = 4
+            ctx.forces(d.sys)
+            ctx.step_block(d.sys, blk)
+            ctx.sync()
+            if mode == "eager":
+                for _ in range(11):
+                    ctx.step_block(d.sys, blk)
+            else:
+                ctx.graph_begin()
+                ctx.step_block(d.sys, blk)
+                g = ctx.graph_end()
+                for _ in range(11):
+                    g.launch(s)
+                    s.synchronize()
+            s.synchronize()
+            ctx.sync()
+            runs.append((d.host(), keep[0].cpu().numpy(), int(keep[4].item())))
+        (a, la, ka), (b, lb, kb) = runs
+        assert ka == kb == 12
+        assert np.array_equal(la, lb)
+        for key in ("pos", "vel", "acc"):
+            assert np.array_equal(a[key], b[key]), key

@@ -87,3 +87,24 @@ def test_refitted_error_is_that_of_a_fresh_build():
     ef, er = _rel(fresh.acc, ref), _rel(refit.acc, ref)
     assert np.percentile(er, 99) < 1.5 * np.percentile(ef, 99)
     assert np.median(er) < 1.5 * np.median(ef)
+
+
+def test_block_steps_rebuild_on_the_period_and_refit_between():
+    from oracle import steps as osteps
+    w = ics.hernquist_c4(n=4096)
+    st = osteps.State(w.pos.copy(), w.vel.copy(), w.mass.copy(), w.eps, w.theta,
+                      w.sys_off.copy(), w.bh_pos.reshape(-1, 3).copy(),
+                      w.bh_vel.reshape(-1, 3).copy(), w.bh_mass.copy(), w.bh_eps.copy(),
+                      np.array([0, 1], np.int64))
+    osteps.forces(st)
+    level = np.zeros(4096, np.uint8)
+    t4 = np.full(4096, 0.3 ** 4 * w.eps ** 2)
+    k, builds = 0, []
+    for _ in range(24):
+        before = st.tree
+        k, act = osteps.block_substep(st, level, t4, k, 0.25, 6, rebuild_every=4)
+        if st.tree is not before:
+            builds.append(k)
+        if act.size == 0:
+            assert st.tree is before
+    assert builds and all(b % 4 == 0 for b in builds)
