@@ -435,10 +435,12 @@ def extra_kdk_energy(steps=100):
     return out
 
 
-def extra_blocksteps(substeps=1000, n=None):
+def extra_blocksteps(substeps=1000, n=None, driver=False):
     """Hernquist N = 4 194 304 + SMBH, 8 levels, dt_max = 2^-6, tau = 0.3 for
-    the stars (the SMBH takes the smallest step): one captured substep,
-    replayed."""
+    the stars (the SMBH takes the smallest step).  Either one captured
+    substep, replayed (every decision on the device), or the host driver
+    tg_step_blocks, which runs the substeps no star takes part in without
+    the tree's launches."""
     import numpy as np
     import torch
     from paper_1507_01009_amd import binding as B, ics
@@ -457,19 +459,25 @@ def extra_blocksteps(substeps=1000, n=None):
         ctx.forces(d.sys)
         ctx.step_block(d.sys, blk)
         ctx.sync()
-        ctx.graph_begin()
-        ctx.step_block(d.sys, blk)
-        g = ctx.graph_end()
         fr = []
-        for _ in range(128):              # one full cycle of level 0, untimed
-            g.launch(s)
-            s.synchronize()
-            fr.append(int(na.item()) / w.n)
+        if driver:
+            ctx.step_blocks(d.sys, blk, 128)      # one full cycle of level 0, untimed
+        else:
+            ctx.graph_begin()
+            ctx.step_block(d.sys, blk)
+            g = ctx.graph_end()
+            for _ in range(128):                  # one full cycle of level 0, untimed
+                g.launch(s)
+                s.synchronize()
+                fr.append(int(na.item()) / w.n)
         ctx.reset_counts()
         ctx.sync()
         t0 = time.perf_counter()
-        for _ in range(substeps):
-            g.launch(s)
+        if driver:
+            n_idle = ctx.step_blocks(d.sys, blk, substeps)
+        else:
+            for _ in range(substeps):
+                g.launch(s)
         s.synchronize()
         t1 = time.perf_counter()
         ctx.sync()
@@ -477,14 +485,18 @@ def extra_blocksteps(substeps=1000, n=None):
         lv = np.bincount(level.cpu().numpy(), minlength=nlev)
         ctx.close()
     sec = t1 - t0
-    fr = np.array(fr)
-    return {"workload": w.name, "substeps": substeps, "ms_per_substep": 1e3 * sec / substeps,
-            "interactions_per_s": (cnt["n_p2p"] + cnt["n_p2m"]) / sec,
-            "forces_per_s": cnt["n_targets"] / sec,
-            "level_histogram": lv.tolist(),
-            "active_fraction": {"min": float(fr.min()), "median": float(np.median(fr)),
-                                "max": float(fr.max()), "mean": float(fr.mean())},
-            "precision": "mixed", "graph": True}
+    out = {"workload": w.name, "substeps": substeps, "ms_per_substep": 1e3 * sec / substeps,
+           "interactions_per_s": (cnt["n_p2p"] + cnt["n_p2m"]) / sec,
+           "forces_per_s": cnt["n_targets"] / sec,
+           "level_histogram": lv.tolist(), "precision": "mixed"}
+    if driver:
+        out.update({"driver": "tg_step_blocks", "substeps_without_tree": n_idle})
+    else:
+        fr = np.array(fr)
+        out.update({"graph": True,
+                    "active_fraction": {"min": float(fr.min()), "median": float(np.median(fr)),
+                                        "max": float(fr.max()), "mean": float(fr.mean())}})
+    return out
 
 
 def extra_batch(steps=20):
@@ -635,6 +647,8 @@ def main():
     if "blocksteps" in ex:
         log("bench: block steps (Hernquist 4M)")
         out["blocksteps"] = extra_blocksteps()
+        log("block steps, host driver")
+        out["blocksteps_driver"] = extra_blocksteps(driver=True)
         torch.cuda.empty_cache()
     if "batch" in ex:
         log("bench: batch of 32 realisations")

@@ -439,6 +439,21 @@ typedef struct {
  * captured substep can be replayed. */
 tg_status tg_step_block(tg_ctx *ctx, const tg_system *sys, const tg_blocks *blocks);
 
+/* n_sub substeps with the results of n_sub tg_step_block calls, bit for
+ * bit, for callers that drive block steps from the host.  Levels change only
+ * for active stars, so after each substep the finest level held by a star
+ * that is not frozen fixes the next substep at which any star is active
+ * (Sec. 2: forces only for the active particles).  The substeps before it
+ * run as the SMBHs' kicks and drift, the stars' drift and the SMBH sums,
+ * without the tree's launches.  Reads two device words after each substep
+ * that has active stars and waits for the stream there, so it cannot be
+ * graph-captured (TG_ESTATE during a capture).  n_idle (may be NULL)
+ * receives the number of substeps run in the short form.  On return
+ * active_idx / n_active hold the active set at the final k, as after
+ * tg_step_block. */
+tg_status tg_step_blocks(tg_ctx *ctx, const tg_system *sys, const tg_blocks *blocks,
+                         int64_t n_sub, int64_t *n_idle);
+
 /* ---- HIP graphs over any sequence of the calls above ------------------ */
 typedef struct tg_graph tg_graph;
 tg_status tg_graph_begin(tg_ctx *ctx);

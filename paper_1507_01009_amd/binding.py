@@ -127,6 +127,7 @@ def lib():
             "tg_step_kdk": (st, [P, P, f64]),
             "tg_step_dkd": (st, [P, P, f64]),
             "tg_step_block": (st, [P, P, P]),
+            "tg_step_blocks": (st, [P, P, P, i64, P]),
             "tg_graph_begin": (st, [P]),
             "tg_graph_end": (st, [P, P]),
             "tg_graph_launch": (st, [P, P]),
@@ -156,7 +157,7 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_perturbers", "tg_chain_forces", "tg_select_within",
             "tg_predict_perturbers", "tg_archain_init", "tg_archain_advance",
             "tg_archain_energy", "tg_forces",
-            "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_graph_begin",
+            "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_step_blocks", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
             "tg_get_profile", "tg_sync", "tg_last_error",
@@ -428,6 +429,13 @@ class Context:
 
     def step_block(self, system, blocks):
         _check(lib().tg_step_block(self.h, C.byref(system), C.byref(blocks)))
+
+    def step_blocks(self, system, blocks, n_sub):
+        """n_sub substeps; returns how many ran without the tree's launches."""
+        n_idle = C.c_int64(0)
+        _check(lib().tg_step_blocks(self.h, C.byref(system), C.byref(blocks), int(n_sub),
+                                    C.byref(n_idle)))
+        return n_idle.value
 
     # -- HIP graphs
     def graph_begin(self):

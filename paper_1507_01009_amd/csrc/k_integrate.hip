@@ -81,28 +81,139 @@ __global__ void k_levels(const double *__restrict__ acc,
   }
 }
 
-__global__ void k_active_flags(const uint8_t *__restrict__ level, int64_t n,
-                               int nlev, const int64_t *__restrict__ kctr,
-                               int k_add, const uint8_t *__restrict__ frozen,
-                               uint32_t *__restrict__ flag) {
+constexpr int kActItems = 4;                      // stars per thread and tile
+constexpr int kActTile = 256 * kActItems;          // stars per active-set tile
+
+__device__ __forceinline__ bool on_at(int l, int64_t k, int nlev) {
+  return (k & (((int64_t)1 << (nlev - 1 - l)) - 1)) == 0;
+}
+
+// One 1024-star tile per block: the number of active stars at substep
+// k + k_add, and the finest level held by a star that is not frozen (+1, 0
+// for none), packed as count | (level + 1) << 16.
+__global__ __launch_bounds__(256) void k_active_count(const uint8_t *__restrict__ level,
+                                                      int64_t n, int nlev,
+                                                      const int64_t *__restrict__ kctr,
+                                                      int k_add,
+                                                      const uint8_t *__restrict__ frozen,
+                                                      uint32_t *__restrict__ tcount) {
+  __shared__ uint32_t lds[8];
   const int64_t k = (kctr ? kctr[0] : 0) + k_add;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int l = min((int)level[i], nlev - 1);
-    const bool on = (k % ((int64_t)1 << (nlev - 1 - l))) == 0 && !(frozen && frozen[i]);
-    flag[i] = on ? 1u : 0u;
+  const int64_t base = (int64_t)blockIdx.x * kActTile;
+  uint32_t cnt = 0, top = 0;
+#pragma unroll
+  for (int r = 0; r < kActItems; ++r) {
+    const int64_t i = base + r * 256 + threadIdx.x;
+    if (i < n && !(frozen && frozen[i])) {
+      const int l = min((int)level[i], nlev - 1);
+      cnt += on_at(l, k, nlev) ? 1u : 0u;
+      top = max(top, (uint32_t)l + 1u);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    cnt += (uint32_t)__shfl_xor((int)cnt, o, 64);
+    top = max(top, (uint32_t)__shfl_xor((int)top, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    lds[threadIdx.x >> 6] = cnt;
+    lds[4 + (threadIdx.x >> 6)] = top;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    tcount[blockIdx.x] = (lds[0] + lds[1] + lds[2] + lds[3]) |
+                         (max(max(lds[4], lds[5]), max(lds[6], lds[7])) << 16);
+}
+
+// One block: exclusive offsets of the tiles' counts (toff[0..tiles]), the
+// total into n_out and info[0], the finest occupied level into info[1]
+// (-1 when no star is free to move).
+__global__ __launch_bounds__(1024) void k_active_offsets(const uint32_t *__restrict__ tcount,
+                                                         int64_t tiles,
+                                                         uint32_t *__restrict__ toff,
+                                                         int32_t *__restrict__ n_out,
+                                                         int32_t *__restrict__ info) {
+  __shared__ uint32_t sh[16];
+  __shared__ uint32_t top_sh[16];
+  uint32_t base = 0, top = 0;
+  for (int64_t t0 = 0; t0 < tiles; t0 += 1024) {
+    const int64_t t = t0 + threadIdx.x;
+    const uint32_t w = t < tiles ? tcount[t] : 0u;
+    top = max(top, w >> 16);
+    uint32_t tot;
+    const uint32_t e = block_exclusive_scan(w & 0xFFFFu, sh, tot);
+    if (t < tiles) toff[t] = base + e;
+    base += tot;
+  }
+  for (int o = 32; o > 0; o >>= 1) top = max(top, (uint32_t)__shfl_xor((int)top, o, 64));
+  if ((threadIdx.x & 63) == 0) top_sh[threadIdx.x >> 6] = top;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (int w = 0; w < 16; ++w) m = max(m, top_sh[w]);
+    toff[tiles] = base;
+    n_out[0] = (int32_t)base;
+    info[0] = (int32_t)base;
+    info[1] = (int32_t)m - 1;
   }
 }
 
-__global__ void k_active_write(const uint32_t *__restrict__ flag,
-                               const uint32_t *__restrict__ pos, int64_t n,
-                               const uint32_t *__restrict__ total,
-                               int32_t *__restrict__ idx,
-                               int32_t *__restrict__ n_out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    if (flag[i]) idx[pos[i]] = (int32_t)i;
-  if (blockIdx.x == 0 && threadIdx.x == 0) n_out[0] = (int32_t)total[0];
+// One tile per block: the tile's active stars in ascending order at its
+// offset (wave ballots, then the four waves in order).  Empty tiles return.
+__global__ __launch_bounds__(256) void k_active_emit(const uint8_t *__restrict__ level,
+                                                     int64_t n, int nlev,
+                                                     const int64_t *__restrict__ kctr,
+                                                     int k_add,
+                                                     const uint8_t *__restrict__ frozen,
+                                                     const uint32_t *__restrict__ toff,
+                                                     int32_t *__restrict__ idx) {
+  __shared__ uint32_t wtot[4];
+  uint32_t off = toff[blockIdx.x];
+  if (toff[blockIdx.x + 1] == off) return;
+  const int64_t k = (kctr ? kctr[0] : 0) + k_add;
+  const int64_t base = (int64_t)blockIdx.x * kActTile;
+  const unsigned w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r = 0; r < kActItems; ++r) {
+    const int64_t i = base + r * 256 + threadIdx.x;
+    const bool s = i < n && !(frozen && frozen[i]) && on_at(min((int)level[i], nlev - 1), k, nlev);
+    const unsigned long long m = __ballot(s);
+    __syncthreads();
+    if (lane == 0) wtot[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t pre = 0;
+    for (unsigned v = 0; v < w; ++v) pre += wtot[v];
+    if (s) idx[off + pre + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+    off += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+  }
+}
+
+// The SMBHs' part of one block substep (they sit on the finest level):
+// closing half kick (not at k = 0), opening half kick, drift, all with the
+// finest step and the same separately rounded operations as k_kick and
+// k_drift; then the substep counter advances.  With clear_active the active
+// count is also set to 0 (a substep known to have no active star).
+__global__ __launch_bounds__(64) void k_bh_substep(double *__restrict__ pos,
+                                                   double *__restrict__ vel,
+                                                   const double *__restrict__ acc, int n,
+                                                   double dt, int64_t *__restrict__ kctr,
+                                                   int32_t *__restrict__ n_act) {
+#pragma clang fp contract(off)
+  const int64_t k = kctr[0];
+  const double h = dt * 0.5;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) {
+    for (int d = 0; d < 3; ++d) {
+      double v = vel[3 * b + d];
+      const double a = acc[3 * b + d];
+      if (k != 0) v = v + a * h;
+      v = v + a * h;
+      vel[3 * b + d] = v;
+      pos[3 * b + d] = pos[3 * b + d] + v * dt;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    kctr[0] = k + 1;
+    if (n_act) n_act[0] = 0;
+  }
 }
 
 __global__ void k_counter_add(int64_t *k, int64_t inc) {
@@ -141,20 +252,29 @@ hipError_t launch_levels(tg_ctx *c, const double *acc, const double *vel,
   return hipGetLastError();
 }
 
-// Flags and the scan share the context's active-group scratch, which is
-// sized for max_particles entries.
+// Count, offsets, emit: three launches whose shape depends only on n.
 hipError_t launch_active_set(tg_ctx *c, const uint8_t *level, int64_t n,
                              int nlev, const int64_t *k, int k_add,
                              int32_t *idx, int32_t *n_out, const uint8_t *frozen) {
   Buffers &b = c->b;
-  if (n == 0) return fill_u32((uint32_t *)n_out, 0u, 1, c->stream);
-  hipLaunchKernelGGL(k_active_flags, dim3(grid_n(n)), dim3(256), 0, c->stream,
-                     level, n, nlev, k, k_add, frozen, b.wl_count);
-  hipError_t e = scan_u32(b.wl_count, b.wl_off, (uint32_t)n, nullptr,
-                          b.scan_total, b.scan_part, c->stream);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_active_write, dim3(grid_n(n)), dim3(256), 0, c->stream,
-                     b.wl_count, b.wl_off, n, b.scan_total, idx, n_out);
+  const int64_t tiles = (n + kActTile - 1) / kActTile;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_active_count, dim3((unsigned)tiles), dim3(256), 0, c->stream, level, n,
+                       nlev, k, k_add, frozen, b.atile);
+  }
+  hipLaunchKernelGGL(k_active_offsets, dim3(1), dim3(1024), 0, c->stream, b.atile, tiles,
+                     b.aoff, n_out, b.ainfo);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_active_emit, dim3((unsigned)tiles), dim3(256), 0, c->stream, level, n,
+                       nlev, k, k_add, frozen, b.aoff, idx);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bh_substep(tg_ctx *c, double *pos, double *vel, const double *acc, int32_t n,
+                             double dt, int64_t *k, int32_t *n_act) {
+  hipLaunchKernelGGL(k_bh_substep, dim3(1), dim3(64), 0, c->stream, pos, vel, acc, n, dt, k,
+                     n_act);
   return hipGetLastError();
 }
 

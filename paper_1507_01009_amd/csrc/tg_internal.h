@@ -106,6 +106,10 @@ struct Buffers {
   uint32_t *ctile = nullptr;      // [N / 1024 + 2] flags per 1024-particle tile
   double *cpart = nullptr;        // [kChainBlocks][6] compensated partials of the chain particle's force
   uint8_t *sact = nullptr;        // [N] active flag per sorted particle
+  // active sets of block steps, per 1024-star tile
+  uint32_t *atile = nullptr;      // [N / 1024 + 2] count | (finest level + 1) << 16
+  uint32_t *aoff = nullptr;       // [N / 1024 + 2] exclusive offsets, then the total
+  int32_t *ainfo = nullptr;       // [2] active count, finest occupied level of free stars
   // walk
   uint32_t *frontier = nullptr;   // [waves][2][frontier_cap]
   uint32_t *wl_count = nullptr;   // [N][2] list sizes (list mode)
@@ -161,6 +165,7 @@ struct tg_ctx {
   std::vector<int32_t> ext_seg_host;
   std::vector<std::vector<int64_t>> dseg_host;  // tables held in the device slots
   int dseg_next = 0;
+  int64_t *host_words = nullptr;  // pinned [4]: device words read back by tg_step_blocks
   tg::Buffers b;
 };
 
@@ -314,6 +319,10 @@ hipError_t launch_active_set(tg_ctx *c, const uint8_t *level, int64_t n,
                              int nlev, const int64_t *k, int k_add,
                              int32_t *idx, int32_t *n_out, const uint8_t *frozen = nullptr);
 hipError_t launch_counter_add(tg_ctx *c, int64_t *k, int64_t inc);
+// SMBH kicks and drift of one block substep, then k += 1 (and *n_act = 0 if
+// n_act is given)
+hipError_t launch_bh_substep(tg_ctx *c, double *pos, double *vel, const double *acc, int32_t n,
+                             double dt, int64_t *k, int32_t *n_act);
 
 // ---- small device helpers ----
 __device__ __forceinline__ unsigned lane_id() {

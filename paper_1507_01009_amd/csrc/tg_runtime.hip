@@ -67,10 +67,14 @@ static void free_all(tg_ctx *c) {
                   b.child, b.parent, b.nsys, b.com, b.mom, b.ninfo, b.cell, b.lcp, b.fl_lt, b.fl_bits, b.fl_cnt, b.fl_fst, b.fl_tot, b.gflag,
                   b.groups, b.aflag, b.alist, b.abox, b.sact, b.frontier,
                   b.wl_count, b.wl_off, b.scan_part, b.scan_total, b.ctr,
-                  b.err, b.dpart, b.dseg, b.ext_seg};
+                  b.err, b.dpart, b.dseg, b.ext_seg, b.rel, b.side, b.bbox,
+                  b.refit_flag, b.refit_gates, b.arel, b.cflag, b.ctile, b.cpart,
+                  b.atile, b.aoff, b.ainfo};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   b = Buffers();
+  if (c->host_words) (void)hipHostFree(c->host_words);
+  c->host_words = nullptr;
 }
 
 tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
@@ -153,6 +157,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.abox, 6 * N)); A(dalloc(&b.arel, N));
   A(dalloc(&b.cflag, N + 1)); A(dalloc(&b.ctile, N / 1024 + 2)); A(dalloc(&b.cpart, 6 * kChainBlocks));
   A(dalloc(&b.sact, N));
+  A(dalloc(&b.atile, N / 1024 + 2)); A(dalloc(&b.aoff, N / 1024 + 2)); A(dalloc(&b.ainfo, 2));
   A(dalloc(&b.frontier, waves * 2 * (int64_t)cfg.frontier_cap));
   A(dalloc(&b.wl_count, 2 * N + 2));
   A(dalloc(&b.wl_off, 2 * N + 2));
@@ -171,6 +176,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(hipMemset(b.ctr, 0, sizeof(TreeCounters)));
   A(hipMemset(b.err, 0, sizeof(uint32_t)));
   A(hipMemset(b.refit_gates, 0, 3 * sizeof(int32_t)));
+  A(hipHostMalloc((void **)&c->host_words, 4 * sizeof(int64_t), hipHostMallocDefault));
   A(hipDeviceSynchronize());
   if (a != hipSuccess) {
     free_all(c);
@@ -879,6 +885,8 @@ static tg_status check_system(const tg_system *y, const char *who) {
 // tree is rebuilt when the substep counter k is a multiple of it (or no
 // build exists yet) and refitted otherwise; both choices are made on the
 // device, so a captured substep replays correctly.
+static tg_status smbh_sums(tg_ctx *c, const tg_system *y);
+
 static tg_status forces_impl(tg_ctx *c, const tg_system *y, const int32_t *idx,
                              const int32_t *n_act, const int64_t *k, int32_t rebuild_every) {
   tg_status st = check_system(y, "tg_forces");
@@ -919,6 +927,12 @@ static tg_status forces_impl(tg_ctx *c, const tg_system *y, const int32_t *idx,
   if ((st = tree_forces_impl(c, y->eps, y->theta, idx, n_act, y->acc, y->pot, y->acc)) !=
       TG_OK)
     return st;
+  return smbh_sums(c, y);
+}
+
+// SMBH <- star sums over each system's stars, then SMBH <-> SMBH.
+static tg_status smbh_sums(tg_ctx *c, const tg_system *y) {
+  tg_status st = TG_OK;
   if (y->n_bh > 0) {
     // SMBHs feel the stars of their own system, then each other
     std::vector<int64_t> so = c->sysoff_host;
@@ -990,9 +1004,6 @@ tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
   if ((st = kick_impl(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
                       b->dt_max, b->k, 1, y->frozen)))
     return st;
-  if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt_min,
-                    b->k, 1)))
-    return st;
   // new levels, then opening half kicks with the new steps
   if ((st = tg_levels_v(c, y->acc, b->tau2eps2v ? y->vel : nullptr, b->tau4eps2,
                         b->tau2eps2v, y->n, b->active_idx, b->n_active, b->dt_max, b->nlev,
@@ -1001,17 +1012,76 @@ tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
   if ((st = kick_impl(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
                       b->dt_max, nullptr, 0, y->frozen)))
     return st;
-  if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt_min,
-                    nullptr, 0)))
-    return st;
-  // everyone drifts by the smallest step; then forces for the next active set
+  // everyone drifts by the smallest step (the SMBHs, on the finest level,
+  // are kicked and drifted in one launch that also advances k); then forces
+  // for the next active set
   if ((st = drift_impl(c, y->pos, y->vel, y->n, dt_min, y->frozen))) return st;
-  if ((st = tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, dt_min))) return st;
-  if ((st = tg_counter_add(c, b->k, 1))) return st;
+  TG_HIP(launch_bh_substep(c, y->bh_pos, y->bh_vel, y->bh_acc, y->n_bh, dt_min, b->k, nullptr));
   if ((st = active_set_impl(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active,
                              y->frozen)))
     return st;
   return forces_impl(c, y, b->active_idx, b->n_active, b->k, b->rebuild_every);
+}
+
+// A substep in which no star is active at its start or at its end: the
+// SMBHs' kicks and drift (k advances, the active count becomes 0), the
+// stars' drift and the SMBH sums.  These are exactly the launches of
+// tg_step_block that do any work when both active sets are empty.
+static tg_status idle_substep(tg_ctx *c, const tg_system *y, const tg_blocks *b, double dt_min) {
+  tg_status st;
+  if ((st = drift_impl(c, y->pos, y->vel, y->n, dt_min, y->frozen))) return st;
+  TG_HIP(launch_bh_substep(c, y->bh_pos, y->bh_vel, y->bh_acc, y->n_bh, dt_min, b->k,
+                           b->n_active));
+  return smbh_sums(c, y);
+}
+
+tg_status tg_step_blocks(tg_ctx *c, const tg_system *y, const tg_blocks *b, int64_t n_sub,
+                         int64_t *n_idle) {
+  if (!c) return fail(TG_EINVAL, "tg_step_blocks: NULL context");
+  if (n_sub < 0) return fail(TG_EINVAL, "tg_step_blocks: n_sub must be >= 0");
+  if (c->capturing) return fail(TG_ESTATE, "tg_step_blocks: reads the device back, not capturable");
+  if (n_idle) *n_idle = 0;
+  int64_t done = 0, idle_total = 0;
+  while (done < n_sub) {
+    tg_status st = tg_step_block(c, y, b);
+    if (st != TG_OK) return st;
+    ++done;
+    if (done == n_sub) break;
+    // the substep counter and the finest level held by a star free to move,
+    // as left by the active set of the new substep
+    TG_HIP(hipMemcpyAsync(c->host_words, b->k, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          c->stream));
+    TG_HIP(hipMemcpyAsync(c->host_words + 1, c->b.ainfo, 2 * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, c->stream));
+    TG_HIP(hipStreamSynchronize(c->stream));
+    const int64_t k = c->host_words[0];
+    int32_t info[2];
+    std::memcpy(info, c->host_words + 1, sizeof(info));
+    const int lf = info[1];
+    // levels change only for active stars, so until the next multiple m of
+    // the finest occupied level's step nobody is active: substeps k .. m-2
+    // have empty active sets at both ends
+    int64_t idle = 0;
+    if (k >= 0 && info[0] == 0) {
+      if (lf < 0) {
+        idle = n_sub - done;
+      } else {
+        const int64_t p = (int64_t)1 << (b->nlev - 1 - std::min(lf, b->nlev - 1));
+        const int64_t m = (k + p - 1) / p * p;
+        idle = std::max<int64_t>(0, m - 1 - k);
+      }
+    }
+    idle = std::min(idle, n_sub - done);
+    const double dt_min = std::ldexp(b->dt_max, -(b->nlev - 1));
+    for (int64_t i = 0; i < idle; ++i) {
+      st = idle_substep(c, y, b, dt_min);
+      if (st != TG_OK) return st;
+    }
+    done += idle;
+    idle_total += idle;
+  }
+  if (n_idle) *n_idle = idle_total;
+  return TG_OK;
 }
 
 static tg_status check_chain(tg_ctx *c, const tg_chain *ch, const char *who) {
