@@ -435,12 +435,13 @@ def extra_kdk_energy(steps=100):
     return out
 
 
-def extra_blocksteps(substeps=1000, n=None, driver=False):
+def extra_blocksteps(substeps=1000, n=None, driver=False, rebuild_every=0):
     """Hernquist N = 4 194 304 + SMBH, 8 levels, dt_max = 2^-6, tau = 0.3 for
     the stars (the SMBH takes the smallest step).  Either one captured
     substep, replayed (every decision on the device), or the host driver
     tg_step_blocks, which runs the substeps no star takes part in without
-    the tree's launches."""
+    the tree's launches.  rebuild_every > 1: the tree is rebuilt at substeps
+    that are multiples of it and refitted at the others."""
     import numpy as np
     import torch
     from paper_1507_01009_amd import binding as B, ics
@@ -455,7 +456,8 @@ def extra_blocksteps(substeps=1000, n=None, driver=False):
         idx = torch.zeros(w.n, dtype=torch.int32, device="cuda")
         na = torch.zeros(1, dtype=torch.int32, device="cuda")
         k = torch.zeros(1, dtype=torch.int64, device="cuda")
-        blk = ctx.make_blocks(level, t4e2, idx, na, k, dt_max, nlev)
+        blk = ctx.make_blocks(level, t4e2, idx, na, k, dt_max, nlev,
+                              rebuild_every=rebuild_every)
         ctx.forces(d.sys)
         ctx.step_block(d.sys, blk)
         ctx.sync()
@@ -488,7 +490,9 @@ def extra_blocksteps(substeps=1000, n=None, driver=False):
     out = {"workload": w.name, "substeps": substeps, "ms_per_substep": 1e3 * sec / substeps,
            "interactions_per_s": (cnt["n_p2p"] + cnt["n_p2m"]) / sec,
            "forces_per_s": cnt["n_targets"] / sec,
-           "level_histogram": lv.tolist(), "precision": "mixed"}
+           "interactions_per_force": (cnt["n_p2p"] + cnt["n_p2m"]) / max(cnt["n_targets"], 1),
+           "level_histogram": lv.tolist(), "precision": "mixed",
+           "rebuild_every": rebuild_every}
     if driver:
         out.update({"driver": "tg_step_blocks", "substeps_without_tree": n_idle})
     else:
@@ -649,6 +653,8 @@ def main():
         out["blocksteps"] = extra_blocksteps()
         log("block steps, host driver")
         out["blocksteps_driver"] = extra_blocksteps(driver=True)
+        log("block steps, host driver, rebuild every 128 substeps and refit between")
+        out["blocksteps_driver_refit"] = extra_blocksteps(driver=True, rebuild_every=128)
         torch.cuda.empty_cache()
     if "batch" in ex:
         log("bench: batch of 32 realisations")
