@@ -129,7 +129,8 @@ tg_status tg_compute_moments(tg_ctx *ctx, const double *mass_dev);
  *   s' = max(s, 2 e),  e = max_k max(hi_k - g_k, g_k - lo_k),
  * [lo, hi] the bounding box of the node's particles, g its cell's centre and
  * s its side: the smallest cube about the centre that holds the cell and all
- * its particles (READING of "update the tree structure if necessary").
+ * its particles (READING of Sec. 2 step 7, which updates the tree only when
+ * needed).
  * Both opening tests use s' until the next tg_build_tree; a cell holding a
  * target is still never accepted.  Replaces tg_compute_moments.
  * Errors: TG_EINVAL, TG_ESTATE (no tree). */

@@ -67,18 +67,19 @@ def lib():
             "or_walk_lists": (C.c_int, [i64, P, P, P, P, P, P, P, P, P, i64, f64,
                                         P, P, P, P, P, P, P]),
             "or_tree_forces": (C.c_int, [i64, P, P, P, P, P, P, P, P, P, P, P, i64,
-                                         P, P, P, f64, f64, P, P, P, f64, P, P, P]),
+                                         P, P, P, f64, f64, P, P, P, f64, P, P, P, i32]),
             "or_direct": (None, [P, P, P, i32, P, P, i64, f64, P, P, P, i64, f64,
-                                 P, P]),
+                                 P, P, i32]),
             "or_direct_pairs": (None, [P, P, P, i64, P, P, i64, C.c_int, f64,
-                                       C.c_int, P, P]),
+                                       C.c_int, P, P, i32]),
             "or_kick": (None, [P, P, P, i64, P, f64]),
             "or_drift": (None, [P, P, i64, f64]),
             "or_levels": (None, [P, P, P, i64, f64, i32, i64, P]),
             "or_levels_v": (None, [P, P, P, P, P, i64, f64, i32, i64, P]),
             "or_active_at": (i64, [P, i64, i32, i64, P]),
-            "or_p2m_single": (None, [P, P, f64, f64, P]),
-            "or_p2p_single": (None, [P, f64, P, f64, f64, P]),
+            "or_p2m_single": (None, [P, P, f64, f64, P, i32]),
+            "or_p2p_single": (None, [P, f64, P, f64, f64, P, i32]),
+            "or_spline": (None, [f64, f64, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -316,9 +317,28 @@ class Evaluation:
     side: np.ndarray = None  # refitted tree: opening size per cell
 
 
+SOFTENINGS = {"plummer": 0, "spline": 1}
+
+
+def _soft(softening):
+    try:
+        return SOFTENINGS[softening]
+    except KeyError:
+        raise ValueError("softening must be 'plummer' or 'spline'") from None
+
+
+def spline_psi(r, h):
+    """Cubic-spline softening (support 2h): psi, psi_1, psi_2, psi_3 at r,
+    psi_{k+1} = -(1/r) d psi_k / dr, Newtonian 1/r, 1/r^3, 3/r^5, 15/r^7
+    beyond 2h."""
+    out = np.zeros(4)
+    lib().or_spline(float(r), float(h), _p(out))
+    return out
+
+
 def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
                 sys_off=None, G=1.0, sel_groups=None, tree=None, alpha=None,
-                acc_old=None, refit=False):
+                acc_old=None, refit=False, softening="plummer"):
     """Build, moments, groups, walk and evaluation, all in the oracle.
 
     ``active``: original indices of the targets (None = all).  ``sel_groups``:
@@ -327,6 +347,7 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
     relative opening test instead of theta.  ``refit``: ``tree`` is an earlier
     build kept as it is (order, nodes, groups) for the current positions, the
     cells opened by their refitted sizes (:func:`refit_sides`).
+    ``softening``: "plummer" (eps) or "spline" (cubic spline, h = eps).
     Returns an :class:`Evaluation`; acc/pot are NaN for rows not evaluated.
     """
     pos = _c(pos, np.float64).reshape(-1, 3)
@@ -356,7 +377,7 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
         _p(tree.child), _p(tree.nchild), _p(tree.sys), _p(mom), _p(tree.cube),
         _p(g), _p(box), _p(sel), sel.shape[0], _p(spos), _p(smass), _p(sact),
         float(eps), float(theta), _p(side), _p(rel), _p(arel), float(G), _p(sacc),
-        _p(spot), _p(counts))
+        _p(spot), _p(counts), _soft(softening))
     if rc != 0:
         raise MemoryError("oracle tree forces")
     acc = np.full((n, 3), np.nan)
@@ -369,7 +390,7 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
 
 
 def direct(pos, mass, eps, targets=None, sys_off=None, xpos=None, xmass=None,
-           xeps=None, G=1.0):
+           xeps=None, G=1.0, softening="plummer"):
     """Exact softened direct sum (long double) for the listed targets.
 
     Sources: every other particle of the target's own system (softening eps)
@@ -390,12 +411,13 @@ def direct(pos, mass, eps, targets=None, sys_off=None, xpos=None, xmass=None,
     pot = np.zeros(tgt.shape[0])
     lib().or_direct(_p(pos), _p(mass), _p(off), off.shape[0] - 1, _p(sysof),
                     _p(tgt), tgt.shape[0], float(eps), _p(xpos), _p(xmass),
-                    _p(xeps), xmass.shape[0], float(G), _p(acc), _p(pot))
+                    _p(xeps), xmass.shape[0], float(G), _p(acc), _p(pot),
+                    _soft(softening))
     return acc, pot
 
 
 def direct_pairs(spos, sm, seps, tpos, teps, self_pairs=False, G=1.0,
-                 acc=None, pot=None):
+                 acc=None, pot=None, softening="plummer"):
     """Double-precision pair forces, pair softening max(eps_i, eps_j)."""
     spos = _c(spos, np.float64).reshape(-1, 3)
     sm = _c(sm, np.float64)
@@ -408,7 +430,7 @@ def direct_pairs(spos, sm, seps, tpos, teps, self_pairs=False, G=1.0,
         pot = np.zeros(tpos.shape[0])
     lib().or_direct_pairs(_p(spos), _p(sm), _p(seps), sm.shape[0], _p(tpos),
                           _p(teps), tpos.shape[0], int(bool(self_pairs)),
-                          float(G), int(accumulate), _p(acc), _p(pot))
+                          float(G), int(accumulate), _p(acc), _p(pot), _soft(softening))
     return acc, pot
 
 
@@ -450,17 +472,17 @@ def active_at(level, nlev, k):
     return idx[:m].copy()
 
 
-def p2m_single(cell, x, eps, G=1.0):
+def p2m_single(cell, x, eps, G=1.0, softening="plummer"):
     """One multipole term: cell = [M, c(3), S(6)] -> (acc[3], phi)."""
     out = np.zeros(4)
     lib().or_p2m_single(_p(_c(cell, np.float64)), _p(_c(x, np.float64)),
-                        float(eps), float(G), _p(out))
+                        float(eps), float(G), _p(out), _soft(softening))
     return out[:3].copy(), float(out[3])
 
 
-def p2p_single(src, m, x, eps, G=1.0):
+def p2p_single(src, m, x, eps, G=1.0, softening="plummer"):
     """One softened particle term -> (acc[3], phi)."""
     out = np.zeros(4)
     lib().or_p2p_single(_p(_c(src, np.float64)), float(m), _p(_c(x, np.float64)),
-                        float(eps), float(G), _p(out))
+                        float(eps), float(G), _p(out), _soft(softening))
     return out[:3].copy(), float(out[3])

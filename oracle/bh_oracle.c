@@ -11,7 +11,9 @@
  *   - tree force = multipole expansion of a distant group about its centre of
  *     mass, near particles summed directly (Sec. 1; Sec. 2, the integration
  *     regions list),
- *   - Plummer softening of every pair (Sec. 3, the softening paragraph),
+ *   - Plummer softening of every pair (Sec. 3, the softening paragraph), or
+ *     the cubic-spline softening the tree may use instead (Sec. 2, the
+ *     description of the tree part; READING below, or_spline_psi),
  *   - forces only for the active particles, leapfrog driver, individual
  *     hierarchical block time-steps (Sec. 2, the hybrid time-step steps (1),
  *     (6), (7); Sec. 3 for tau_acc = 0.3 for stars and 0.003 for SMBHs).
@@ -140,7 +142,7 @@ int or_sort(const uint64_t *keys, const int64_t *off, int32_t S,
 }
 
 /* ---------------------------------------------------------------------- */
-/* Octree over key prefixes (READING of "update the tree structure").      */
+/* Octree over key prefixes (READING of the tree update, Sec. 2 step 7).   */
 /* One root per non-empty system (level 0, its whole range).  A node is     */
 /* refined iff it holds more than nleaf particles and its level is below   */
 /* 21; its children are the non-empty octants of the next key digit, in   */
@@ -381,8 +383,8 @@ void or_rel_records(int64_t nn, const uint8_t *level, const uint32_t *first,
 }
 
 /* ---------------------------------------------------------------------- */
-/* Refit (READING of "update the tree structure if necessary", Sec. 2 step */
-/* 7): between full builds the sort order, nodes and groups stay; moments   */
+/* Refit (READING of Sec. 2 step 7, which updates the tree structure only  */
+/* when needed): between full builds the sort order, nodes and groups stay; moments   */
 /* come from the current positions, and each cell's opening size becomes    */
 /*   s' = max(s, 2 e),  e = max_k max(hi_k - g_k, g_k - lo_k),              */
 /* with [lo, hi] the bounding box of the node's particles (exact min/max)   */
@@ -516,6 +518,107 @@ int or_walk_lists(int64_t nn, const uint8_t *level, const uint32_t *child,
 /* their particles in sorted order; plain double additions.  The self term */
 /* is left out of the potential too.                                        */
 /* ---------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------- */
+/* Cubic-spline softening.  READING: the paper names spline or Plummer     */
+/* softening for the tree without formulas; the spline is the kernel of    */
+/* Monaghan & Lattanzio (1985) with support 2h, used for gravity as in     */
+/* Hernquist & Katz (1989), with h = eps.  Its mass density is             */
+/*   W(u) = (1/(pi h^3)) (1 - 3/2 u^2 + 3/4 u^3)   0 <= u < 1,             */
+/*        = (1/(pi h^3)) (2 - u)^3 / 4             1 <= u < 2,  u = r/h,   */
+/* and 0 beyond.  psi(r) is the potential of a unit mass so spread, with   */
+/* the sign of 1/r (phi = -G m psi), and psi_{k+1} = -(1/r) d psi_k / dr:  */
+/* a pair force is -G m psi_1(r) x, and beyond 2h the four are the         */
+/* Newtonian 1/r, 1/r^3, 3/r^5, 15/r^7.  psi_3 grows as 1/u near 0; it is   */
+/* only needed for cells, whose centre of mass never sits on the target    */
+/* (it is set to 0 at u = 0, where it multiplies zero).                    */
+/* ---------------------------------------------------------------------- */
+static void or_spline_psi(double r, double h, double psi[4]) {
+  double u = r / h;
+  double ih = 1.0 / h;
+  double ih2 = ih * ih;
+  double ih3 = ih2 * ih, ih5 = ih3 * ih2, ih7 = ih5 * ih2;
+  if (u < 1.0) {
+    double u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u;
+    psi[0] = ih * (7.0 / 5.0 - 2.0 / 3.0 * u2 + 3.0 / 10.0 * u4 - 1.0 / 10.0 * u5);
+    psi[1] = ih3 * (4.0 / 3.0 - 6.0 / 5.0 * u2 + 1.0 / 2.0 * u3);
+    psi[2] = ih5 * (12.0 / 5.0 - 3.0 / 2.0 * u);
+    psi[3] = u > 0.0 ? ih7 * (3.0 / 2.0) / u : 0.0;
+  } else if (u < 2.0) {
+    double u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u, u7 = u5 * u2;
+    psi[0] = ih * (8.0 / 5.0 - 4.0 / 3.0 * u2 + u3 - 3.0 / 10.0 * u4 + 1.0 / 30.0 * u5 -
+                   1.0 / (15.0 * u));
+    psi[1] = ih3 * (8.0 / 3.0 - 3.0 * u + 6.0 / 5.0 * u2 - 1.0 / 6.0 * u3 - 1.0 / (15.0 * u3));
+    psi[2] = ih5 * (3.0 / u - 12.0 / 5.0 + 1.0 / 2.0 * u - 1.0 / (5.0 * u5));
+    psi[3] = ih7 * (3.0 / u3 - 1.0 / (2.0 * u) - 1.0 / u7);
+  } else {
+    double ir = 1.0 / r;
+    double ir2 = ir * ir;
+    psi[0] = ir;
+    psi[1] = ir * ir2;
+    psi[2] = 3.0 * psi[1] * ir2;
+    psi[3] = 5.0 * psi[2] * ir2;
+  }
+}
+
+/* The same in long double, for the direct-sum reference.                  */
+static void or_spline_psi_l(long double r, long double h, long double psi[2]) {
+  long double u = r / h;
+  long double ih = 1.0L / h;
+  if (u < 1.0L) {
+    long double u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u;
+    psi[0] = ih * (7.0L / 5.0L - 2.0L / 3.0L * u2 + 3.0L / 10.0L * u4 - 1.0L / 10.0L * u5);
+    psi[1] = ih * ih * ih * (4.0L / 3.0L - 6.0L / 5.0L * u2 + 1.0L / 2.0L * u3);
+  } else if (u < 2.0L) {
+    long double u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u;
+    psi[0] = ih * (8.0L / 5.0L - 4.0L / 3.0L * u2 + u3 - 3.0L / 10.0L * u4 +
+                   1.0L / 30.0L * u5 - 1.0L / (15.0L * u));
+    psi[1] = ih * ih * ih *
+             (8.0L / 3.0L - 3.0L * u + 6.0L / 5.0L * u2 - 1.0L / 6.0L * u3 - 1.0L / (15.0L * u3));
+  } else {
+    psi[0] = 1.0L / r;
+    psi[1] = psi[0] * psi[0] * psi[0];
+  }
+}
+
+/* Exported for the pins: psi[0..3] at r for softening length h.           */
+void or_spline(double r, double h, double *psi) { or_spline_psi(r, h, psi); }
+
+/* Spline-softened multipole term, the second-order expansion of          */
+/* sum_j m_j psi(|x - y_j|) about the centre of mass for any radial psi:   */
+/*   phi = -G (M psi + 1/2 psi_2 x.S.x - 1/2 psi_1 T)                      */
+/*   a   =  G (-M psi_1 x + psi_2 (S x + T x / 2) - 1/2 psi_3 (x.S.x) x)   */
+/* with x = target - com, S the second moments, T = tr S.  (With the       */
+/* Plummer psi these reduce to or_p2m_term.)                              */
+static void or_p2m_spline(const double *o, double xi, double yi, double zi,
+                          double h, double G, double *out) {
+  double M = o[0];
+  double x = xi - o[1], y = yi - o[2], z = zi - o[3];
+  double Sxx = o[4], Syy = o[5], Szz = o[6], Sxy = o[7], Sxz = o[8], Syz = o[9];
+  double T = Sxx + Syy + Szz;
+  double r = sqrt(x * x + y * y + z * z);
+  double psi[4];
+  or_spline_psi(r, h, psi);
+  double Sx = Sxx * x + Sxy * y + Sxz * z;
+  double Sy = Sxy * x + Syy * y + Syz * z;
+  double Sz = Sxz * x + Syz * y + Szz * z;
+  double xSx = x * Sx + y * Sy + z * Sz;
+  out[0] += G * (-M * psi[1] * x + psi[2] * (Sx + 0.5 * T * x) - 0.5 * psi[3] * xSx * x);
+  out[1] += G * (-M * psi[1] * y + psi[2] * (Sy + 0.5 * T * y) - 0.5 * psi[3] * xSx * y);
+  out[2] += G * (-M * psi[1] * z + psi[2] * (Sz + 0.5 * T * z) - 0.5 * psi[3] * xSx * z);
+  out[3] -= G * (M * psi[0] + 0.5 * psi[2] * xSx - 0.5 * psi[1] * T);
+}
+
+/* Spline-softened particle term (coincident particles feel no force).     */
+static void or_p2p_spline(double xj, double yj, double zj, double m, double xi,
+                          double yi, double zi, double h, double G, double *out) {
+  double x = xi - xj, y = yi - yj, z = zi - zj;
+  double r = sqrt(x * x + y * y + z * z);
+  double psi[4];
+  or_spline_psi(r, h, psi);
+  out[0] -= G * m * psi[1] * x; out[1] -= G * m * psi[1] * y; out[2] -= G * m * psi[1] * z;
+  out[3] -= G * m * psi[0];
+}
+
 /* One multipole (P2M) term: cell o = {M, cx, cy, cz, Sxx, Syy, Szz, Sxy,   */
 /* Sxz, Syz}; target at (xi, yi, zi).  Adds to out[0..3] = ax, ay, az, phi. */
 static void or_p2m_term(const double *o, double xi, double yi, double zi,
@@ -551,35 +654,50 @@ static void or_p2p_term(double xj, double yj, double zj, double m, double xi,
 }
 
 /* Exported single terms, so that tests can probe the expansion alone.      */
+/* soft: 0 Plummer, 1 cubic spline (h = eps).                              */
 void or_p2m_single(const double *cell, const double *x, double eps, double G,
-                   double *out) {
+                   double *out, int32_t soft) {
   out[0] = out[1] = out[2] = out[3] = 0.0;
-  or_p2m_term(cell, x[0], x[1], x[2], eps * eps, G, out);
+  if (soft)
+    or_p2m_spline(cell, x[0], x[1], x[2], eps, G, out);
+  else
+    or_p2m_term(cell, x[0], x[1], x[2], eps * eps, G, out);
 }
 
 void or_p2p_single(const double *src, double m, const double *x, double eps,
-                   double G, double *out) {
+                   double G, double *out, int32_t soft) {
   out[0] = out[1] = out[2] = out[3] = 0.0;
-  or_p2p_term(src[0], src[1], src[2], m, x[0], x[1], x[2], eps * eps, G, out);
+  if (soft)
+    or_p2p_spline(src[0], src[1], src[2], m, x[0], x[1], x[2], eps, G, out);
+  else
+    or_p2p_term(src[0], src[1], src[2], m, x[0], x[1], x[2], eps * eps, G, out);
 }
 
 static void or_eval_target(int64_t i, const double *spos, const double *smass,
                            const uint32_t *first, const uint32_t *count,
                            const double *mom, const or_vec *p2m,
-                           const or_vec *p2p, double eps, double G,
+                           const or_vec *p2p, double eps, double G, int32_t soft,
                            double *acc, double *pot, int64_t *n_pp) {
   double xi = spos[3 * i], yi = spos[3 * i + 1], zi = spos[3 * i + 2];
   double e2 = eps * eps;
   double out[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t t = 0; t < p2m->n; ++t)
-    or_p2m_term(mom + 10 * (int64_t)p2m->v[t], xi, yi, zi, e2, G, out);
+  for (int64_t t = 0; t < p2m->n; ++t) {
+    const double *o = mom + 10 * (int64_t)p2m->v[t];
+    if (soft)
+      or_p2m_spline(o, xi, yi, zi, eps, G, out);
+    else
+      or_p2m_term(o, xi, yi, zi, e2, G, out);
+  }
   int64_t npp = 0;
   for (int64_t t = 0; t < p2p->n; ++t) {
     uint32_t leaf = p2p->v[t];
     for (uint32_t j = first[leaf]; j < first[leaf] + count[leaf]; ++j) {
       if ((int64_t)j == i) continue;
-      or_p2p_term(spos[3 * (int64_t)j], spos[3 * (int64_t)j + 1],
-                  spos[3 * (int64_t)j + 2], smass[j], xi, yi, zi, e2, G, out);
+      const double *q = spos + 3 * (int64_t)j;
+      if (soft)
+        or_p2p_spline(q[0], q[1], q[2], smass[j], xi, yi, zi, eps, G, out);
+      else
+        or_p2p_term(q[0], q[1], q[2], smass[j], xi, yi, zi, e2, G, out);
       ++npp;
     }
   }
@@ -599,7 +717,7 @@ int or_tree_forces(int64_t nn, const uint8_t *level, const uint32_t *first,
                    const double *smass, const uint8_t *sactive, double eps,
                    double theta, const double *side, const double *rel,
                    const double *arel, double G, double *acc, double *pot,
-                   int64_t *counts) {
+                   int64_t *counts, int32_t soft) {
   int err = 0;
   int64_t npp = 0, npm = 0, ntg = 0;
 #pragma omp parallel reduction(+ : npp, npm, ntg)
@@ -615,7 +733,7 @@ int or_tree_forces(int64_t nn, const uint8_t *level, const uint32_t *first,
       }
       for (uint32_t i = g[4 * k]; i < g[4 * k] + g[4 * k + 1]; ++i) {
         if (!sactive[i]) continue;
-        or_eval_target(i, spos, smass, first, count, mom, &p2m, &p2p, eps, G,
+        or_eval_target(i, spos, smass, first, count, mom, &p2m, &p2p, eps, G, soft,
                        acc, pot, &npp);
         npm += p2m.n;
         ++ntg;
@@ -632,13 +750,14 @@ int or_tree_forces(int64_t nn, const uint8_t *level, const uint32_t *first,
 /* sum over every other particle of its own system (same softening eps),    */
 /* plus nx external point masses (SMBHs) with pair softening                */
 /* max(eps, xeps_k) (Sec. 2: eps = max(eps_BH, eps_star)).  Accumulated in  */
-/* long double.  Outputs per listed target: acc[3 t], pot[t].               */
+/* long double.  Outputs per listed target: acc[3 t], pot[t].  soft = 1:    */
+/* every pair takes the cubic spline with that softening as h.              */
 /* ---------------------------------------------------------------------- */
 void or_direct(const double *pos, const double *mass, const int64_t *off,
                int32_t S, const int32_t *sysof, const int64_t *tgt, int64_t nt,
                double eps, const double *xpos, const double *xmass,
                const double *xeps, int64_t nx, double G, double *acc,
-               double *pot) {
+               double *pot, int32_t soft) {
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t t = 0; t < nt; ++t) {
     int64_t i = tgt[t];
@@ -650,18 +769,32 @@ void or_direct(const double *pos, const double *mass, const int64_t *off,
     for (int64_t j = off[s]; j < off[s + 1]; ++j) {
       if (j == i) continue;
       long double x = xi - pos[3 * j], y = yi - pos[3 * j + 1], z = zi - pos[3 * j + 2];
-      long double r2 = x * x + y * y + z * z + e2;
-      long double D1 = 1.0L / sqrtl(r2);
-      long double D3 = D1 * D1 * D1;
+      long double D1, D3;
+      if (soft) {
+        long double ps[2];
+        or_spline_psi_l(sqrtl(x * x + y * y + z * z), (long double)eps, ps);
+        D1 = ps[0]; D3 = ps[1];
+      } else {
+        long double r2 = x * x + y * y + z * z + e2;
+        D1 = 1.0L / sqrtl(r2);
+        D3 = D1 * D1 * D1;
+      }
       ax -= mass[j] * D3 * x; ay -= mass[j] * D3 * y; az -= mass[j] * D3 * z;
       ph -= mass[j] * D1;
     }
     for (int64_t j = 0; j < nx; ++j) {
       double ep = xeps[j] > eps ? xeps[j] : eps;
       long double x = xi - xpos[3 * j], y = yi - xpos[3 * j + 1], z = zi - xpos[3 * j + 2];
-      long double r2 = x * x + y * y + z * z + (long double)ep * (long double)ep;
-      long double D1 = 1.0L / sqrtl(r2);
-      long double D3 = D1 * D1 * D1;
+      long double D1, D3;
+      if (soft) {
+        long double ps[2];
+        or_spline_psi_l(sqrtl(x * x + y * y + z * z), (long double)ep, ps);
+        D1 = ps[0]; D3 = ps[1];
+      } else {
+        long double r2 = x * x + y * y + z * z + (long double)ep * (long double)ep;
+        D1 = 1.0L / sqrtl(r2);
+        D3 = D1 * D1 * D1;
+      }
       ax -= xmass[j] * D3 * x; ay -= xmass[j] * D3 * y; az -= xmass[j] * D3 * z;
       ph -= xmass[j] * D1;
     }
@@ -676,12 +809,13 @@ void or_direct(const double *pos, const double *mass, const int64_t *off,
 /* (Sec. 2: perturber <-> chain-member forces; SMBH <-> star forces), pair  */
 /* softening max(eps_i, eps_j).  When the sets are the same (self != 0) the */
 /* pair i == j is skipped.  Sources summed in index order.  If accumulate, */
-/* the result is added to acc/pot, else it overwrites them.                 */
+/* the result is added to acc/pot, else it overwrites them.  soft = 1: the  */
+/* cubic spline with h = max(eps_i, eps_j) (h = 0: Newtonian).              */
 /* ---------------------------------------------------------------------- */
 void or_direct_pairs(const double *spos, const double *sm, const double *seps,
                      int64_t ns, const double *tpos, const double *teps,
                      int64_t nt, int self, double G, int accumulate,
-                     double *acc, double *pot) {
+                     double *acc, double *pot, int32_t soft) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nt; ++i) {
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
@@ -690,9 +824,16 @@ void or_direct_pairs(const double *spos, const double *sm, const double *seps,
       double ep = seps[j] > teps[i] ? seps[j] : teps[i];
       double x = tpos[3 * i] - spos[3 * j], y = tpos[3 * i + 1] - spos[3 * j + 1],
              z = tpos[3 * i + 2] - spos[3 * j + 2];
-      double r2 = x * x + y * y + z * z + ep * ep;
-      double D1 = 1.0 / sqrt(r2);
-      double D3 = D1 * D1 * D1;
+      double D1, D3;
+      if (soft) {
+        double ps[4];
+        or_spline_psi(sqrt(x * x + y * y + z * z), ep, ps);
+        D1 = ps[0]; D3 = ps[1];
+      } else {
+        double r2 = x * x + y * y + z * z + ep * ep;
+        D1 = 1.0 / sqrt(r2);
+        D3 = D1 * D1 * D1;
+      }
       ax -= G * sm[j] * D3 * x; ay -= G * sm[j] * D3 * y; az -= G * sm[j] * D3 * z;
       ph -= G * sm[j] * D1;
     }

@@ -5,7 +5,7 @@ Composes the oracle's primitives in the order of the paper's hybrid step
 
 * forces: tree forces on the listed stars (opening angle, or with ``alpha``
   the relative test against the stars' current accelerations) plus the FP64
-  Plummer force of the
+  softened (Plummer, or the cubic spline) force of the
   SMBHs of the star's system (pair softening max(eps_star, eps_bh)); every
   SMBH feels all stars of its system and the other SMBHs (Sec. 2, the
   perturber / chain force-correction paragraph).
@@ -45,6 +45,7 @@ class State:
     alpha: float = None      # relative opening test (None: opening angle theta)
     frozen: np.ndarray = None  # bool [n]: stars held still (ghost chain members)
     tree: object = None        # the last tree built (refitted between builds)
+    softening: str = "plummer"  # or "spline" (cubic spline, h = eps)
     acc: np.ndarray = field(default=None)
     pot: np.ndarray = field(default=None)
     bh_acc: np.ndarray = field(default=None)
@@ -64,8 +65,9 @@ def forces(st: State, active=None, k=None, rebuild_every=0):
     """Tree + SMBH forces for the listed stars; SMBH forces for all SMBHs.
     With a rebuild period (block steps, substep k) the tree is rebuilt when k
     is a multiple of it or none was built yet, and refitted otherwise (READING
-    of "update the tree structure if necessary", Sec. 2 step 7).  No tree
-    work when the list is empty."""
+    of Sec. 2 step 7, which updates the tree structure when needed without a
+    rule).  No tree work when the list is empty.  ``st.softening`` applies to
+    every pair, the SMBH ones included."""
     n = st.pos.shape[0]
     S = st.sys_off.shape[0] - 1
     rows = np.arange(n) if active is None else np.asarray(active, np.int64)
@@ -75,7 +77,8 @@ def forces(st: State, active=None, k=None, rebuild_every=0):
                  and k % rebuild_every != 0)
         ev = oracle.tree_forces(st.pos, st.mass, st.eps, st.theta, st.leaf_size,
                                 st.group_size, active=active, sys_off=st.sys_off,
-                                tree=st.tree if refit else None, refit=refit, **rel)
+                                tree=st.tree if refit else None, refit=refit,
+                                softening=st.softening, **rel)
         if not refit:
             st.tree = ev.tree
         st.acc[rows] = ev.acc[rows]
@@ -90,14 +93,16 @@ def forces(st: State, active=None, k=None, rebuild_every=0):
         r = rows[(rows >= lo) & (rows < hi)]
         if r.size:
             a, p = oracle.direct_pairs(st.bh_pos[b0:b1], st.bh_mass[b0:b1],
-                                       st.bh_eps[b0:b1], st.pos[r], st.eps)
+                                       st.bh_eps[b0:b1], st.pos[r], st.eps,
+                                       softening=st.softening)
             st.acc[r] += a
             st.pot[r] += p
         a, p = oracle.direct_pairs(st.pos[lo:hi], st.mass[lo:hi], st.eps,
-                                   st.bh_pos[b0:b1], st.bh_eps[b0:b1])
+                                   st.bh_pos[b0:b1], st.bh_eps[b0:b1],
+                                   softening=st.softening)
         oracle.direct_pairs(st.bh_pos[b0:b1], st.bh_mass[b0:b1], st.bh_eps[b0:b1],
                             st.bh_pos[b0:b1], st.bh_eps[b0:b1], self_pairs=True,
-                            acc=a, pot=p)
+                            acc=a, pot=p, softening=st.softening)
         st.bh_acc[b0:b1] = a
         st.bh_pot[b0:b1] = p
     return ev
