@@ -608,7 +608,7 @@ def main():
     roof = {"bound": "alu", "achieved": head["walk_tflops"], "peak": peak, "unit": "TFLOP/s",
             "frac": head["walk_tflops"] / peak,
             "traffic": traffic_for("k_walk.hip", "cusp1m"),
-            "kernel": "k_walk_forces<%s, false>" % ("true" if head_name == "mixed" else "false"),
+            "kernel": "k_walk_forces<%s, false, false>" % ("true" if head_name == "mixed" else "false"),
             "avg_launch_ms": head["walk_ms_avg"], "flops_per_launch": head["flops_per_walk"],
             "flops_per_interaction": {"p2p": FLOPS_P2P, "p2m": FLOPS_P2M},
             "peak_note": "published FP32 vector peak; the build disables packed FP32, "

@@ -175,6 +175,25 @@ tg_status tg_tree_forces(tg_ctx *ctx, double eps, double theta,
 tg_status tg_set_mac(tg_ctx *ctx, int32_t kind, double alpha,
                      const double *acc_old_dev);
 
+/* Pair softening for everything the context computes afterwards: the walk's
+ * particle and cell terms, the SMBH terms of tg_forces and the steps, and
+ * tg_direct_fp64.  The tree may use spline or Plummer softening (Sec. 2,
+ * the tree part of the hybrid scheme).
+ *   TG_SOFT_PLUMMER (the default): pair potential -G m / sqrt(r^2 + eps^2).
+ *   TG_SOFT_SPLINE: the cubic-spline kernel of Monaghan & Lattanzio (1985)
+ *     with support 2h, h = eps (pairs with an SMBH: h = max(eps_i, eps_j)),
+ *     as used for gravity by Hernquist & Katz (1989): with u = r/h the pair
+ *     potential is -G m psi(r), psi = (7/5 - 2/3 u^2 + 3/10 u^4 - 1/10 u^5)/h
+ *     for u < 1, (8/5 - 4/3 u^2 + u^3 - 3/10 u^4 + 1/30 u^5 - 1/(15 u))/h
+ *     for 1 <= u < 2, and 1/r beyond (h = 0: Newtonian).  Cells use the
+ *     second-order expansion of the same kernel about their centre of mass
+ *     (psi and its derivatives psi_k+1 = -(1/r) d psi_k / dr).
+ * The chain-coupling kernels keep their own softening (tg_chain).  Errors:
+ * TG_EINVAL for another kind. */
+#define TG_SOFT_PLUMMER 0
+#define TG_SOFT_SPLINE 1
+tg_status tg_set_softening(tg_ctx *ctx, int32_t kind);
+
 /* Interaction counts (synchronises the stream).  out[0..3] for the last
  * tg_tree_forces: P2P pairs (target, source particle, j != i), particle-cell
  * (P2M) pairs, targets, active groups walked; out[4..7] the same summed over

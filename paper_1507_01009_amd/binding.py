@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtg.so")
 
 TG_FP64, TG_MIXED = 0, 1
+TG_SOFT_PLUMMER, TG_SOFT_SPLINE = 0, 1
 ERR_NONFINITE, ERR_MASS, ERR_NODES, ERR_FRONTIER, ERR_LISTS = 1, 2, 4, 8, 16
 STATUS = {0: "TG_OK", -1: "TG_EINVAL", -2: "TG_ENOMEM", -3: "TG_EHIP",
           -4: "TG_ECAPACITY", -5: "TG_ESTATE", -6: "TG_EDATA"}
@@ -123,6 +124,7 @@ def lib():
             "tg_archain_init": (st, [P, f64]),
             "tg_archain_advance": (st, [P, f64, f64, f64, P, P]),
             "tg_archain_energy": (st, [P, f64, P]),
+            "tg_set_softening": (st, [P, i32]),
             "tg_forces": (st, [P, P, P, P]),
             "tg_step_kdk": (st, [P, P, f64]),
             "tg_step_dkd": (st, [P, P, f64]),
@@ -153,7 +155,8 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_set_sizes", "tg_build_tree", "tg_compute_moments",
             "tg_tree_forces", "tg_get_counts", "tg_reset_counts", "tg_walk_lists",
             "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
-            "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac", "tg_refit_tree",
+            "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac", "tg_set_softening",
+            "tg_refit_tree",
             "tg_perturbers", "tg_chain_forces", "tg_select_within",
             "tg_predict_perturbers", "tg_archain_init", "tg_archain_advance",
             "tg_archain_energy", "tg_forces",
@@ -289,6 +292,12 @@ class Context:
         ([N, 3] device, caller order; None = the system's acc in forces)."""
         _check(lib().tg_set_mac(self.h, 1 if relative else 0, float(alpha),
                                 _ptr(acc_old)))
+
+    def set_softening(self, kind):
+        """Pair softening of later walks, SMBH terms and direct sums:
+        "plummer" (default) or "spline" (cubic spline, h = eps)."""
+        k = {"plummer": TG_SOFT_PLUMMER, "spline": TG_SOFT_SPLINE}.get(kind, kind)
+        _check(lib().tg_set_softening(self.h, int(k)))
 
     def walk_lists(self, theta, active_idx=None, n_active=None):
         """(info [ng, 4] int64, ids uint32) as numpy; see tg_walk_lists."""

@@ -1,6 +1,6 @@
 // Double-precision direct forces between a source set and a target set
-// (SMBH <-> stars; perturber <-> chain-member corrections), Plummer
-// softening max(eps_i, eps_j) per pair.
+// (SMBH <-> stars; perturber <-> chain-member corrections), softening
+// max(eps_i, eps_j) per pair: Plummer, or the cubic spline with that h.
 //
 // Many targets (stars feeling the SMBHs): one thread per target takes every
 // source of its segment (or of a source chunk, combined in a second ordered
@@ -24,13 +24,29 @@ __device__ __forceinline__ int seg_of(const int64_t *off, int nseg, int64_t i) {
   return lo;
 }
 
+// m/r and m/r^3 with the pair's softening ep (soft: cubic spline, h = ep).
+__device__ __forceinline__ void pair_terms(double dx, double dy, double dz, double ep, double m,
+                                           int soft, double &mD1, double &mD3) {
+  if (soft) {
+    double p0, p1;
+    spline_pair_dp(sqrt(dx * dx + dy * dy + dz * dz), ep, p0, p1);
+    mD1 = m * p0;
+    mD3 = m * p1;
+  } else {
+    const double r2 = dx * dx + dy * dy + dz * dz + ep * ep;
+    const double D1 = 1.0 / sqrt(r2);
+    mD1 = m * D1;
+    mD3 = mD1 * D1 * D1;
+  }
+}
+
 __global__ void k_direct(const double *__restrict__ spos, const double *__restrict__ sm,
                          const double *__restrict__ seps, double seps_all,
                          const double *__restrict__ tpos,
                          const double *__restrict__ teps, int64_t nt,
                          const int64_t *__restrict__ sseg, const int64_t *__restrict__ tseg,
                          int nseg, int64_t chunk, int nchunks, int self_pairs,
-                         int accumulate, double *__restrict__ acc,
+                         int accumulate, int soft, double *__restrict__ acc,
                          double *__restrict__ pot, double *__restrict__ part) {
   const int64_t total = nt * (int64_t)nchunks;
   for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < total;
@@ -47,10 +63,8 @@ __global__ void k_direct(const double *__restrict__ spos, const double *__restri
       if (self_pairs && j == i) continue;
       const double ep = fmax(seps ? seps[j] : seps_all, ei);
       const double dx = xi - spos[3 * j], dy = yi - spos[3 * j + 1], dz = zi - spos[3 * j + 2];
-      const double r2 = dx * dx + dy * dy + dz * dz + ep * ep;
-      const double D1 = 1.0 / sqrt(r2);
-      const double mD1 = sm[j] * D1;
-      const double mD3 = mD1 * D1 * D1;
+      double mD1, mD3;
+      pair_terms(dx, dy, dz, ep, sm[j], soft, mD1, mD3);
       ax.add(-mD3 * dx);
       ay.add(-mD3 * dy);
       az.add(-mD3 * dz);
@@ -101,7 +115,8 @@ __global__ __launch_bounds__(256) void k_direct_few(
     const double *__restrict__ spos, const double *__restrict__ sm,
     const double *__restrict__ seps, double seps_all, const double *__restrict__ tpos,
     const double *__restrict__ teps, int64_t nt, const int64_t *__restrict__ sseg,
-    const int64_t *__restrict__ tseg, int nseg, int self_pairs, double *__restrict__ part) {
+    const int64_t *__restrict__ tseg, int nseg, int self_pairs, int soft,
+    double *__restrict__ part) {
   __shared__ double ss[4][256], sc[4][256];
   const int64_t i = blockIdx.y;
   const int s = seg_of(tseg, nseg, i);
@@ -114,10 +129,8 @@ __global__ __launch_bounds__(256) void k_direct_few(
     if (self_pairs && j == i) continue;
     const double ep = fmax(seps ? seps[j] : seps_all, ei);
     const double dx = xi - spos[3 * j], dy = yi - spos[3 * j + 1], dz = zi - spos[3 * j + 2];
-    const double r2 = dx * dx + dy * dy + dz * dz + ep * ep;
-    const double D1 = 1.0 / sqrt(r2);
-    const double mD1 = sm[j] * D1;
-    const double mD3 = mD1 * D1 * D1;
+    double mD1, mD3;
+    pair_terms(dx, dy, dz, ep, sm[j], soft, mD1, mD3);
     r[0].add(-mD3 * dx);
     r[1].add(-mD3 * dy);
     r[2].add(-mD3 * dz);
@@ -176,7 +189,7 @@ hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
     if (bpt * nt * 8 <= c->b.dpart_cap && bpt <= 65535) {
       hipLaunchKernelGGL(k_direct_few, dim3((unsigned)bpt, (unsigned)nt), dim3(256), 0,
                          c->stream, spos, sm, seps, seps_all, tpos, teps, nt, dseg,
-                         dseg + (nseg + 1), nseg, self_pairs, c->b.dpart);
+                         dseg + (nseg + 1), nseg, self_pairs, c->soft, c->b.dpart);
       hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)std::min<int64_t>(nt, 4096)),
                          dim3(256), 0, c->stream, nt, (int)bpt, accumulate, c->b.dpart,
                          acc, pot);
@@ -198,7 +211,7 @@ hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
   const int g = (int)std::min<int64_t>((total + 255) / 256, 8192);
   hipLaunchKernelGGL(k_direct, dim3(g), dim3(256), 0, c->stream, spos, sm, seps,
                      seps_all, tpos, teps, nt, dseg, dseg + (nseg + 1), nseg,
-                     chunk, (int)nchunks, self_pairs, accumulate, acc, pot,
+                     chunk, (int)nchunks, self_pairs, accumulate, c->soft, acc, pot,
                      c->b.dpart);
   if (nchunks > 1) {
     const int g2 = (int)std::min<int64_t>(nt, 4096);

@@ -215,6 +215,106 @@ __device__ __forceinline__ void p2p_term(typename Vec4<R>::T s, R tx, R ty, R tz
   ph -= mD1;
 }
 
+// Cubic-spline softening (Monaghan-Lattanzio kernel, support 2h, h = eps):
+// with u = r/h, psi is the pair's softened 1/r and psi_k+1 = -(1/r) d psi_k
+// / dr; beyond 2h they are 1/r, 1/r^3, 3/r^5, 15/r^7.  The Newtonian values
+// come from one rsqrt; the polynomial pieces are evaluated only where some
+// lane of the wave has a pair inside 2h.  At r = 0 (a particle and itself,
+// coincident ones, or a zero-mass tile pad at the target) u = 0 selects the
+// inner piece, which is finite; psi_3 (1/u there) is set to 0, since it
+// multiplies x.S.x = 0.
+template <class R>
+__device__ __forceinline__ void spline_psi01(R r2, R h, R ih, R &p0, R &p1) {
+  const R ir = rsq(r2);
+  p0 = ir;
+  p1 = ir * ir * ir;
+  const R u = (r2 > R(0) ? r2 * ir : R(0)) * ih;
+  if (u < R(2)) {
+    const R u2 = u * u, ih3 = ih * ih * ih, iu = h * ir;
+    const R a0 = ih * fma(u2, fma(u2, fma(R(-0.1), u, R(0.3)), R(-2.0 / 3.0)), R(1.4));
+    const R a1 = ih3 * fma(u2, fma(R(0.5), u, R(-1.2)), R(4.0 / 3.0));
+    const R b0 = ih * fma(R(-1.0 / 15.0), iu,
+                          fma(u2, fma(u, fma(u, fma(u, R(1.0 / 30.0), R(-0.3)), R(1)),
+                                      R(-4.0 / 3.0)), R(1.6)));
+    const R b1 = ih3 * fma(R(-1.0 / 15.0), iu * iu * iu,
+                           fma(u, fma(u, fma(u, R(-1.0 / 6.0), R(1.2)), R(-3)), R(8.0 / 3.0)));
+    const bool in = u < R(1);
+    p0 = in ? a0 : b0;
+    p1 = in ? a1 : b1;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void spline_psi0123(R r2, R h, R ih, R &p0, R &p1, R &p2, R &p3) {
+  const R ir = rsq(r2), ir2 = ir * ir;
+  p0 = ir;
+  p1 = ir * ir2;
+  p2 = R(3) * p1 * ir2;
+  p3 = R(5) * p2 * ir2;
+  const R u = (r2 > R(0) ? r2 * ir : R(0)) * ih;
+  if (u < R(2)) {
+    const R u2 = u * u, ih2 = ih * ih, ih3 = ih2 * ih, ih5 = ih3 * ih2, ih7 = ih5 * ih2;
+    const R iu = h * ir, iu2 = iu * iu, iu3 = iu2 * iu, iu5 = iu3 * iu2;
+    const R a0 = ih * fma(u2, fma(u2, fma(R(-0.1), u, R(0.3)), R(-2.0 / 3.0)), R(1.4));
+    const R a1 = ih3 * fma(u2, fma(R(0.5), u, R(-1.2)), R(4.0 / 3.0));
+    const R a2 = ih5 * fma(R(-1.5), u, R(2.4));
+    const R a3 = r2 > R(0) ? ih7 * (R(1.5) * iu) : R(0);   // multiplies V = 0 at r = 0
+    const R b0 = ih * fma(R(-1.0 / 15.0), iu,
+                          fma(u2, fma(u, fma(u, fma(u, R(1.0 / 30.0), R(-0.3)), R(1)),
+                                      R(-4.0 / 3.0)), R(1.6)));
+    const R b1 = ih3 * fma(R(-1.0 / 15.0), iu3,
+                           fma(u, fma(u, fma(u, R(-1.0 / 6.0), R(1.2)), R(-3)), R(8.0 / 3.0)));
+    const R b2 = ih5 * fma(R(-0.2), iu5, fma(R(3), iu, fma(R(0.5), u, R(-2.4))));
+    const R b3 = ih7 * fma(R(-1), iu5 * iu2, fma(R(3), iu3, R(-0.5) * iu));
+    const bool in = u < R(1);
+    p0 = in ? a0 : b0;
+    p1 = in ? a1 : b1;
+    p2 = in ? a2 : b2;
+    p3 = in ? a3 : b3;
+  }
+}
+
+// Spline-softened cell term, x = target - com, cell as for p2m_term but
+// b.w = T.  The second-order expansion of the kernel about the centre of
+// mass, with V = x.Q.x + T |x|^2 (= 3 x.S.x):
+//   a  += -(M psi_1 - 5/6 psi_2 T + psi_3 V / 6) x + (psi_2 / 3) Q x
+//   phi -= M psi + psi_2 V / 6 - psi_1 T / 2
+template <class R>
+__device__ __forceinline__ void p2m_spline(typename Vec4<R>::T a, typename Vec4<R>::T b,
+                                           typename Vec4<R>::T c, R tx, R ty, R tz, R h, R ih,
+                                           R &ax, R &ay, R &az, R &ph) {
+  const R x = tx - a.x, y = ty - a.y, z = tz - a.z;
+  const R r2 = fma(z, z, fma(y, y, x * x));
+  R p0, p1, p2, p3;
+  spline_psi0123<R>(r2, h, ih, p0, p1, p2, p3);
+  const R Qx = fma(c.y, z, fma(c.x, y, b.x * x));
+  const R Qy = fma(c.z, z, fma(b.y, y, c.x * x));
+  const R Qz = fma(b.z, z, fma(c.z, y, c.y * x));
+  const R V = fma(b.w, r2, fma(z, Qz, fma(y, Qy, x * Qx)));
+  const R V6 = V * R(1.0 / 6.0);
+  const R C = fma(p3, V6, fma(R(-5.0 / 6.0) * p2, b.w, a.w * p1));
+  const R q = p2 * R(1.0 / 3.0);
+  ax = fma(q, Qx, fma(-C, x, ax));
+  ay = fma(q, Qy, fma(-C, y, ay));
+  az = fma(q, Qz, fma(-C, z, az));
+  ph -= fma(p2, V6, fma(R(-0.5) * p1, b.w, a.w * p0));
+}
+
+// Spline-softened particle term, source s = {position, m}.
+template <class R>
+__device__ __forceinline__ void p2p_spline(typename Vec4<R>::T s, R tx, R ty, R tz, R h, R ih,
+                                           R &ax, R &ay, R &az, R &ph) {
+  const R dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
+  const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  R p0, p1;
+  spline_psi01<R>(r2, h, ih, p0, p1);
+  const R mp1 = s.w * p1;
+  ax = fma(-mp1, dx, ax);
+  ay = fma(-mp1, dy, ay);
+  az = fma(-mp1, dz, az);
+  ph -= s.w * p0;
+}
+
 // ---------------------------------------------------------------- tiles
 struct P2MTileD { double4 a, b, c; };
 struct P2MTileF { float4 a, b, c; };
@@ -247,7 +347,7 @@ template <> union __align__(16) TileMem<false> {
 };
 
 // ------------------------------------------------------- force-mode sink
-template <bool kMixed>
+template <bool kMixed, bool kSpline>
 struct ForceSink {
   using R = typename std::conditional<kMixed, float, double>::type;
   using R4 = typename Vec4<R>::T;
@@ -260,6 +360,7 @@ struct ForceSink {
   int T, lt, slices, tfull, F, my_s;
   double cgx, cgy, cgz;              // coordinate origin of the group (0 in FP64)
   R e2;
+  R h, ih;                           // spline softening length and its inverse
   R tx[kMaxT], ty[kMaxT], tz[kMaxT];
   // per-target totals in FP64 (mixed: each tile's FP32 partial sums are
   // added here, so rounding accumulates only within a tile)
@@ -275,7 +376,14 @@ struct ForceSink {
 #pragma unroll
     for (int k = 0; k < kT; ++k) ax[k] = ay[k] = az[k] = ph[k] = R(0);
     const auto *e = &tile->m[base];
-    if constexpr (kT == 1) {
+    if constexpr (kSpline) {
+      for (int it = 0; it < trips; ++it) {
+        const R4 a = e[it].a, b = e[it].b, c = e[it].c;
+#pragma unroll
+        for (int k = 0; k < kT; ++k)
+          p2m_spline<R>(a, b, c, tx[k], ty[k], tz[k], h, ih, ax[k], ay[k], az[k], ph[k]);
+      }
+    } else if constexpr (kT == 1) {
 #pragma unroll 2
       for (int it = 0; it < trips; ++it)
         p2m_term<R>(e[it].a, e[it].b, e[it].c, tx[0], ty[0], tz[0], e2, ax[0], ay[0], az[0], ph[0]);
@@ -297,7 +405,14 @@ struct ForceSink {
 #pragma unroll
     for (int k = 0; k < kT; ++k) ax[k] = ay[k] = az[k] = ph[k] = R(0);
     const R4 *e = &tile->p[base];
-    if constexpr (kT == 1) {
+    if constexpr (kSpline) {
+      for (int it = 0; it < trips; ++it) {
+        const R4 s = e[it];
+#pragma unroll
+        for (int k = 0; k < kT; ++k)
+          p2p_spline<R>(s, tx[k], ty[k], tz[k], h, ih, ax[k], ay[k], az[k], ph[k]);
+      }
+    } else if constexpr (kT == 1) {
 #pragma unroll 4
       for (int it = 0; it < trips; ++it)
         p2p_term<R>(e[it], tx[0], ty[0], tz[0], e2, ax[0], ay[0], az[0], ph[0]);
@@ -558,7 +673,7 @@ struct GroupQueue {
 };
 
 // ------------------------------------------------------------ force kernel
-template <bool kMixed, bool kRel>
+template <bool kMixed, bool kRel, bool kSpline>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMixed ? TG_WALK_WAVES_MIXED : TG_WALK_WAVES_FP64)))
 void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
@@ -566,7 +681,7 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
   __shared__ uint32_t s_m[kMCap];
   __shared__ uint32_t s_q[kQCap];
   __shared__ TileMem<kMixed> tile;
-  using Sink = ForceSink<kMixed>;
+  using Sink = ForceSink<kMixed, kSpline>;
   using R = typename Sink::R;
   constexpr int kMaxT = Sink::kMaxT;
   const unsigned lane = lane_id();
@@ -618,6 +733,8 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
       S.cgx = S.cgy = S.cgz = 0.0;
     }
     S.e2 = (R)A.eps2;
+    S.h = (R)A.eps;
+    S.ih = (R)(1.0 / A.eps);
 #pragma unroll
     for (int k = 0; k < kMaxT; ++k) {
       // lane-target j holds targets j, j + lt, ...; missing ones repeat j
@@ -646,8 +763,11 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
       }
       const uint32_t r_t = s_tgt[i];
       const double4 p = A.spart[r_t];
+      // the P2P sums include each target with itself: remove that term
       double self;
-      if constexpr (kMixed)
+      if constexpr (kSpline)
+        self = (double)((R)p.w * (S.ih * R(1.4)));
+      else if constexpr (kMixed)
         self = (double)((float)p.w * __builtin_amdgcn_rsqf((float)A.eps2));
       else
         self = p.w * rsqrt_dp(A.eps2);
@@ -659,9 +779,18 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
           const double es = fmax(A.eps, A.ext_eps[e]);
           const double dx = p.x - A.ext_pos[3 * e], dy = p.y - A.ext_pos[3 * e + 1],
                        dz = p.z - A.ext_pos[3 * e + 2];
-          const double r2 = dx * dx + dy * dy + dz * dz + es * es;
-          const double D1 = 1.0 / sqrt(r2);
-          const double mD1 = A.ext_mass[e] * D1, mD3 = mD1 * D1 * D1;
+          double mD1, mD3;
+          if constexpr (kSpline) {
+            double p0, p1;
+            spline_pair_dp(sqrt(dx * dx + dy * dy + dz * dz), es, p0, p1);
+            mD1 = A.ext_mass[e] * p0;
+            mD3 = A.ext_mass[e] * p1;
+          } else {
+            const double r2 = dx * dx + dy * dy + dz * dz + es * es;
+            const double D1 = 1.0 / sqrt(r2);
+            mD1 = A.ext_mass[e] * D1;
+            mD3 = mD1 * D1 * D1;
+          }
           ex -= mD3 * dx; ey -= mD3 * dy; ez -= mD3 * dz; ep -= mD1;
         }
       }
@@ -888,12 +1017,13 @@ static WalkArgs make_args(tg_ctx *c, double theta) {
   return A;
 }
 
-// Walk records of every node: Q = 3S - T I, -T eps^2 and M, in the walk's
-// precision, formed once per evaluation instead of once per staged cell.
+// Walk records of every node: Q = 3S - T I, -T eps^2 (spline: T) and M, in
+// the walk's precision, formed once per evaluation instead of once per
+// staged cell.
 template <class R>
 __global__ __launch_bounds__(256) void k_cell_records(const int32_t *__restrict__ gate, const TreeCounters *ctr,
                                                       const double *__restrict__ mom,
-                                                      double eps2, void *cell) {
+                                                      double eps2, int spline, void *cell) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
   using R4 = typename Vec4<R>::T;
   R4 *out = reinterpret_cast<R4 *>(cell);
@@ -905,7 +1035,7 @@ __global__ __launch_bounds__(256) void k_cell_records(const int32_t *__restrict_
     // m0 = {M, Sxx, Syy, Szz}, m1 = {Sxy, Sxz, Syz, -}
     const double T = m0.y + m0.z + m0.w;
     out[2 * (size_t)v] = R4{(R)(3.0 * m0.y - T), (R)(3.0 * m0.z - T), (R)(3.0 * m0.w - T),
-                            (R)(-(T * eps2))};
+                            spline ? (R)T : (R)(-(T * eps2))};
     out[2 * (size_t)v + 1] = R4{(R)(3.0 * m1.x), (R)(3.0 * m1.y), (R)(3.0 * m1.z), (R)m0.x};
   }
 }
@@ -955,13 +1085,13 @@ static int walk_grid(tg_ctx *c) {
   return std::max(1, c->n_cu * c->waves_per_cu);
 }
 
-template <bool kRel>
+template <bool kRel, bool kSpline>
 static void launch_force_kernel(tg_ctx *c, const WalkArgs &A) {
   if (c->cfg.precision == TG_MIXED)
-    hipLaunchKernelGGL((k_walk_forces<true, kRel>), dim3(walk_grid(c)), dim3(64), 0,
+    hipLaunchKernelGGL((k_walk_forces<true, kRel, kSpline>), dim3(walk_grid(c)), dim3(64), 0,
                        c->stream, c->gate, A);
   else
-    hipLaunchKernelGGL((k_walk_forces<false, kRel>), dim3(walk_grid(c)), dim3(64), 0,
+    hipLaunchKernelGGL((k_walk_forces<false, kRel, kSpline>), dim3(walk_grid(c)), dim3(64), 0,
                        c->stream, c->gate, A);
 }
 
@@ -973,12 +1103,13 @@ hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
   A.eps = eps;
   A.acc = acc;
   A.pot = pot;
+  const int spline = c->soft == TG_SOFT_SPLINE ? 1 : 0;
   if (c->cfg.precision == TG_MIXED)
     hipLaunchKernelGGL(k_cell_records<float>, dim3(1024), dim3(256), 0, c->stream, c->gate, c->b.ctr,
-                       c->b.mom, A.eps2, (void *)c->b.cell);
+                       c->b.mom, A.eps2, spline, (void *)c->b.cell);
   else
     hipLaunchKernelGGL(k_cell_records<double>, dim3(1024), dim3(256), 0, c->stream, c->gate, c->b.ctr,
-                       c->b.mom, A.eps2, (void *)c->b.cell);
+                       c->b.mom, A.eps2, spline, (void *)c->b.cell);
   if (rel) {
     hipError_t e = launch_rel_records(c);
     if (e != hipSuccess) return e;
@@ -988,10 +1119,13 @@ hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
     hipError_t e = hipEventRecord(before, c->stream);
     if (e != hipSuccess) return e;
   }
-  if (rel)
-    launch_force_kernel<true>(c, A);
-  else
-    launch_force_kernel<false>(c, A);
+  if (spline) {
+    if (rel) launch_force_kernel<true, true>(c, A);
+    else launch_force_kernel<false, true>(c, A);
+  } else {
+    if (rel) launch_force_kernel<true, false>(c, A);
+    else launch_force_kernel<false, false>(c, A);
+  }
   if (after) {
     hipError_t e = hipEventRecord(after, c->stream);
     if (e != hipSuccess) return e;

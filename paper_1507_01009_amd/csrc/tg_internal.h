@@ -145,6 +145,9 @@ struct tg_ctx {
   // opening test of the walk: TG_MAC_GEOMETRIC, or TG_MAC_RELATIVE with
   // alpha and the old accelerations (null: the system's acc in tg_forces)
   int32_t mac = 0;
+  // pair softening of the walk, the SMBH terms and the direct sums:
+  // TG_SOFT_PLUMMER or TG_SOFT_SPLINE
+  int32_t soft = 0;
   double alpha = 0.0;
   const double *acc_old = nullptr;
   // masses gathered into the sorted particles by the last build (or null)
@@ -233,6 +236,28 @@ __device__ __forceinline__ double cell_centre(uint32_t v, int l, const uint32_t 
   }
   for (int k = 0; k < 3; ++k) g[k] = dadd(cb[k], dmul(dadd((double)ic[k], 0.5), s));
   return s;
+}
+
+// Cubic-spline softening (the Monaghan-Lattanzio kernel with support 2h,
+// h = the pair's softening): psi and psi_1 of a pair at distance r, in
+// double with correctly rounded divisions and square roots, for the SMBH
+// terms and the direct sums.  A pair's acceleration is -m psi_1 x and its
+// potential -m psi; beyond 2h (and for h = 0) they are 1/r and 1/r^3.
+__device__ __forceinline__ void spline_pair_dp(double r, double h, double &p0, double &p1) {
+  if (!(r < 2.0 * h)) {
+    p0 = 1.0 / r;
+    p1 = p0 * p0 * p0;
+    return;
+  }
+  const double ih = 1.0 / h, u = r * ih, u2 = u * u, ih3 = ih * ih * ih;
+  if (u < 1.0) {
+    p0 = ih * (1.4 + u2 * (-2.0 / 3.0 + u2 * (0.3 - 0.1 * u)));
+    p1 = ih3 * (4.0 / 3.0 + u2 * (-1.2 + 0.5 * u));
+  } else {
+    const double iu = 1.0 / u;
+    p0 = ih * (1.6 + u2 * (-4.0 / 3.0 + u * (1.0 + u * (-0.3 + u / 30.0))) - iu / 15.0);
+    p1 = ih3 * (8.0 / 3.0 + u * (-3.0 + u * (1.2 - u / 6.0)) - iu * iu * iu / 15.0);
+  }
 }
 
 // Compensated double sum (error-free TwoSum with a running correction),

@@ -409,6 +409,14 @@ tg_status tg_set_mac(tg_ctx *c, int32_t kind, double alpha, const double *acc_ol
   return TG_OK;
 }
 
+tg_status tg_set_softening(tg_ctx *c, int32_t kind) {
+  if (!c) return fail(TG_EINVAL, "tg_set_softening: NULL context");
+  if (kind != TG_SOFT_PLUMMER && kind != TG_SOFT_SPLINE)
+    return fail(TG_EINVAL, "tg_set_softening: unknown kind");
+  c->soft = kind;
+  return TG_OK;
+}
+
 tg_status tg_set_profiling(tg_ctx *c, int32_t on) {
   if (!c) return fail(TG_EINVAL, "tg_set_profiling: NULL context");
   if (c->capturing) return fail(TG_ESTATE, "tg_set_profiling: during capture");

@@ -22,9 +22,11 @@ def to_dev(a, dtype=None):
 
 def gpu_run(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
             sys_off=None, precision=0, lists=False, ctx=None, pot=True,
-            waves_per_cu=0, frontier_cap=0, max_nodes=0, alpha=None, acc_old=None):
+            waves_per_cu=0, frontier_cap=0, max_nodes=0, alpha=None, acc_old=None,
+            softening=None):
     """Build + moments + forces on the GPU; returns a dict of numpy arrays.
-    With alpha the walk uses the relative test against acc_old ([N, 3])."""
+    With alpha the walk uses the relative test against acc_old ([N, 3]);
+    softening "spline" switches the pair softening for this run."""
     torch = torch_dev()
     from paper_1507_01009_amd import binding as B
     n = pos.shape[0]
@@ -48,6 +50,8 @@ def gpu_run(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
     if alpha is not None:
         dold = to_dev(np.asarray(acc_old, np.float64).reshape(-1, 3))
         ctx.set_mac(True, alpha, dold)
+    if softening is not None:
+        ctx.set_softening(softening)
     ctx.build_tree(dpos, sys_off)
     ctx.compute_moments(dm)
     ctx.tree_forces(eps, theta, acc, dpot, didx, dna)
@@ -58,6 +62,8 @@ def gpu_run(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
         out["lists"] = ctx.walk_lists(theta, didx, dna)
     if alpha is not None:
         ctx.set_mac(False)
+    if softening is not None:
+        ctx.set_softening("plummer")
     return out
 
 
