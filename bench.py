@@ -15,9 +15,9 @@ pairs per second of whole-step wall time) of the mixed-precision path; the
 FP64 path, forces/s, the errors (mixed vs FP64, both vs the direct sum), the
 walk kernel's roofline and the CPU oracle baseline are reported beside it,
 plus measurements selected by --extras (default all, none with --no-extra):
-the relative opening test (alpha = 1e-3) on the same step, the chain
-coupling on the same workload, a KDK energy check, block steps and batched
-realisations.
+the relative opening test (alpha = 1e-3) and the spline softening on the
+same step, the chain coupling on the same workload, a KDK energy check,
+block steps and batched realisations.
 """
 from __future__ import annotations
 
@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="relative,chain,kdk,blocksteps,batch",
+    ap.add_argument("--extras", default="relative,spline,chain,kdk,blocksteps,batch",
                     help="comma list of the extra measurements to run")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -236,7 +236,7 @@ def direct_errors(w, accs, n_samples=128):
     return out
 
 
-def direct_errors_gpu(w, accs, n_samples=65536):
+def direct_errors_gpu(w, accs, n_samples=65536, softening="plummer"):
     """Per-percentile error of each path against the FP64 direct sum (stars
     and SMBHs, compensated, tg_direct_fp64, itself parity-tested against the
     oracle) on seeded sample targets.  A target's own pair adds no force."""
@@ -247,6 +247,7 @@ def direct_errors_gpu(w, accs, n_samples=65536):
     tg = np.sort(rng.choice(w.n, min(n_samples, w.n), replace=False))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
     ctx = B.Context(w.n)
+    ctx.set_softening(softening)
     pos, m = dev(w.pos), dev(w.mass)
     seps = torch.full((w.n,), w.eps, dtype=torch.float64, device="cuda")
     tpos = dev(w.pos[tg])
@@ -339,6 +340,33 @@ def extra_relative_mac(w, a, alpha=1e-3, steps=10):
     r["alpha"] = alpha
     st.ctx.close()
     return r, acc
+
+
+def extra_spline(w, a, steps=10):
+    """The tree's other softening (Sec. 2): the cubic spline, h = eps, on the
+    same workload and step, mixed precision; the FP64 path evaluated once for
+    the precision error; both against the FP64 spline direct sum."""
+    import numpy as np
+    from paper_1507_01009_amd import binding as B
+    accs = {}
+    for name, prec in (("fp64", B.TG_FP64), ("mixed", B.TG_MIXED)):
+        st = Step(w, prec, a.leaf, a.group, a.waves, a.dt)
+        st.ctx.set_softening("spline")
+        st.ctx.forces(st.d.sys)
+        st.ctx.sync()
+        accs["spline_" + name] = st.acc.cpu().numpy().copy()
+        if name == "mixed":
+            r = time_path(st, steps, 2)
+            for k in ("walk_tflops", "flops_per_walk"):   # Plummer flop counts
+                r.pop(k)
+        st.ctx.close()
+        del st
+    e = (np.linalg.norm(accs["spline_mixed"] - accs["spline_fp64"], axis=1) /
+         np.linalg.norm(accs["spline_fp64"], axis=1))
+    r["error"] = {"mixed_vs_fp64": percentiles(e)}
+    r["error"].update(direct_errors_gpu(w, accs, softening="spline"))
+    r["softening"] = "cubic spline, h = eps"
+    return r
 
 
 def extra_chain(w, reps=50):
@@ -640,6 +668,11 @@ def main():
         del src, dst
     if rel is not None:
         out["relative_mac"] = rel
+    if "spline" in ex:
+        log("bench: spline softening (same workload)")
+        out["spline"] = extra_spline(w, a)
+        log("bench: spline %.3f ms/step" % out["spline"]["ms_per_step"])
+        torch.cuda.empty_cache()
     if "chain" in ex:
         log("bench: chain coupling (same workload)")
         out["chain"] = extra_chain(w)

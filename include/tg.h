@@ -218,7 +218,8 @@ tg_status tg_walk_lists(tg_ctx *ctx, double theta,
 /* ---- double-precision direct forces (SMBH <-> stars, perturber <->
  * chain members; Sec. 2).  Targets [nt] at tgt_pos_dev with softening
  * tgt_eps_dev feel sources [ns] (src_pos_dev, src_mass_dev, src_eps_dev)
- * with pair softening max(eps_i, eps_j).  With segments (nseg > 0,
+ * with pair softening max(eps_i, eps_j), Plummer or the cubic spline as set
+ * by tg_set_softening (0: Newtonian).  With segments (nseg > 0,
  * src_seg_host/tgt_seg_host ascending offsets [nseg+1]) only pairs in the
  * same segment interact.  If self_pairs != 0 the two sets are the same
  * particles and i == j is skipped.  accumulate != 0 adds to acc/pot, else
