@@ -21,7 +21,7 @@ What it computes (Sec. 2, the hybrid method):
   paragraph): every listed, non-excluded star feels the chain as its
   centre-of-mass particle, a point mass M at R, or, if it is a perturber,
   as the resolved members; pairs with the chain are unsoftened by default
-  (Sec. 4 softening paragraph), or Plummer-softened with eps_pm.
+  (Sec. 3, softening paragraph), or Plummer-softened with eps_pm.
 * Prediction of the perturbers for the chain integration (the paper
   predicts their positions relative to the chain particle to first order
   at each chain force evaluation): for perturber j and a time offset dt,
@@ -157,3 +157,40 @@ def coupling(pos, mass, targets, com, m_chain, mpos, mmass, pert, eps_pm=0.0,
         corr += LD(mmass[i]) * am[i]
     a_com = a_com + corr / LD(m_chain)
     return acc, pot, np.asarray(a_com, np.float64), np.asarray(am, np.float64)
+
+
+def chains_coupling(pos, mass, targets, chains, exclude=None, G=1.0):
+    """Several chains (READING of the extension to several distant SMBHs the
+    paper names as its next step, Sec. 7): every chain couples to the stars
+    as one chain does (:func:`coupling`), with the same exclusion mask, which
+    holds the ghost members of all chains; a star may perturb several chains.
+    The chain particles feel each other as Newtonian point masses.
+
+    chains: list of dicts with com, m_chain, mpos, mmass, r_crit, gamma_crit
+    and optionally eps_pm.  Returns (acc_add, pot_add, a_com [K, 3],
+    a_members [sum nc, 3], perturber lists).
+    """
+    tg = np.asarray(targets, np.int64)
+    acc = np.zeros((tg.size, 3), LD)
+    pot = np.zeros(tg.size, LD)
+    coms, mems, perts = [], [], []
+    for ch in chains:
+        P = perturbers(pos, mass, ch["com"], ch["m_chain"], ch["r_crit"], ch["gamma_crit"],
+                       exclude)
+        a, p, ac, am = coupling(pos, mass, tg, ch["com"], ch["m_chain"], ch["mpos"],
+                                ch["mmass"], P, ch.get("eps_pm", 0.0), exclude, G)
+        acc += a.astype(LD)
+        pot += p.astype(LD)
+        coms.append(ac.astype(LD))
+        mems.append(am)
+        perts.append(P)
+    K = len(chains)
+    for a in range(K):
+        Ra = np.asarray(chains[a]["com"], np.float64)
+        for d in range(K):
+            if d != a:
+                coms[a] = coms[a] + _on_point(np.asarray(chains[d]["com"], np.float64),
+                                              [chains[d]["m_chain"]], Ra, G)
+    return (acc.astype(np.float64), pot.astype(np.float64),
+            np.array([c.astype(np.float64) for c in coms]),
+            np.concatenate(mems), perts)

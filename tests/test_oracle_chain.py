@@ -154,3 +154,60 @@ def test_prediction_is_first_order_and_relative():
     xr1, vr1, _ = chain.predict(pos, vel, mass, pert, R, V, 1e-3)
     assert np.allclose(xr1, xr0 + 1e-3 * vr0, rtol=0, atol=1e-14)
     assert np.array_equal(vr1, vr0)
+
+
+def _two_chains(seed):
+    """A cloud with two SMBH chains 0.5 apart; the members are ghosts in the
+    star arrays (excluded), as in the hybrid scheme."""
+    rng = np.random.default_rng(seed)
+    pos, mass = _cloud(6000, seed)
+    chains, ghost = [], np.zeros(0, np.int64)
+    for k, c in enumerate((np.array([0.25, 0.0, 0.0]), np.array([-0.25, 0.05, 0.0]))):
+        # the chain's members are the SMBH plus the stars nearest to it
+        near = np.argsort(np.linalg.norm(pos - c, axis=1))[:4]
+        mpos = np.concatenate([c[None, :], pos[near]])
+        mmass = np.concatenate([[0.01], mass[near]])
+        M = mmass.sum()
+        R = (mmass[:, None] * mpos).sum(0) / M
+        chains.append({"com": R, "m_chain": M, "mpos": mpos, "mmass": mmass,
+                       "r_crit": 0.05, "gamma_crit": 1e-4})
+        ghost = np.concatenate([ghost, near])
+    excl = np.zeros(pos.shape[0], bool)
+    excl[ghost] = True
+    return pos, mass, chains, excl
+
+
+@pytest.mark.parametrize("seed", [3, 8])
+def test_several_chains_conserve_momentum(seed):
+    """Newton's third law across every sum: stars and chains, perturbers and
+    members, chain particles with each other."""
+    pos, mass, chains, excl = _two_chains(seed)
+    tg = np.nonzero(~excl)[0]
+    acc, pot, a_com, am, perts = chain.chains_coupling(pos, mass, tg, chains, excl)
+    assert all(p.size > 5 for p in perts)
+    tot = (mass[tg, None] * acc).sum(0)
+    for k, ch in enumerate(chains):
+        tot = tot + ch["m_chain"] * a_com[k]
+    scale = np.abs(mass[tg, None] * acc).sum(0)
+    assert np.all(np.abs(tot) <= 1e-12 * scale)
+    assert am.shape == (sum(c["mpos"].shape[0] for c in chains), 3)
+
+
+def test_one_chain_of_several_is_the_single_chain():
+    pos, mass, chains, excl = _two_chains(5)
+    tg = np.nonzero(~excl)[0]
+    acc, pot, a_com, am, perts = chain.chains_coupling(pos, mass, tg, chains[:1], excl)
+    c = chains[0]
+    P = chain.perturbers(pos, mass, c["com"], c["m_chain"], c["r_crit"], c["gamma_crit"], excl)
+    a1, p1, ac1, am1 = chain.coupling(pos, mass, tg, c["com"], c["m_chain"], c["mpos"],
+                                      c["mmass"], P, 0.0, excl)
+    assert np.array_equal(perts[0], P)
+    assert np.allclose(acc, a1, rtol=1e-15, atol=0) and np.allclose(a_com[0], ac1, rtol=1e-15)
+    # with two, chain 0's particle also feels chain 1 as a point mass
+    acc2, _, a_com2, _, _ = chain.chains_coupling(pos, mass, tg, chains, excl)
+    d = chains[1]["com"] - c["com"]
+    pull = chains[1]["m_chain"] * d / np.linalg.norm(d) ** 3
+    a_one_other = chain.chains_coupling(pos, mass, tg, chains[1:], excl)[2][0]
+    assert np.allclose(a_com2[0], ac1 + pull, rtol=1e-12, atol=0)
+    assert np.allclose(a_com2[1] - a_one_other,
+                       -c["m_chain"] * d / np.linalg.norm(d) ** 3, rtol=1e-12, atol=0)
