@@ -439,6 +439,66 @@ def extra_chain(w, reps=50):
     return out
 
 
+def extra_chains(n_each=524288, reps=50):
+    """Several chains: two Dehnen gamma = 1.5 cusps (N = 524 288 each, scale
+    0.2) 1.0 apart, each with an SMBH of 0.01 whose chain holds it and the 20
+    nearest stars (excluded ghosts), r_crit = 0.005, gamma_crit = 1e-4.
+    Times tg_chains_forces for both chains against two single-chain calls."""
+    import numpy as np
+    import torch
+    from paper_1507_01009_amd import binding as B, ics
+    parts, masses, specs, ghosts = [], [], [], []
+    for k, (c, seed) in enumerate(((np.array([0.5, 0.0, 0.0]), 31),
+                                   (np.array([-0.5, 0.1, 0.0]), 32))):
+        p, _, m = ics.dehnen(n_each, 1.5, ics.SEED_BASE + seed)
+        p = p * 0.2 + c
+        near = np.argsort(np.linalg.norm(p - c, axis=1))[:20]
+        ghosts.append(near + k * n_each)
+        mpos = np.concatenate([c[None, :], p[near]])
+        mmass = np.concatenate([[0.01], m[near]])
+        M = mmass.sum()
+        specs.append((mpos, mmass, (mmass[:, None] * mpos).sum(0) / M, M))
+        parts.append(p)
+        masses.append(m)
+    pos, mass = np.concatenate(parts), np.concatenate(masses)
+    n = pos.shape[0]
+    excl = np.zeros(n, np.uint8)
+    excl[np.concatenate(ghosts)] = 1
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    f64 = dict(dtype=torch.float64, device="cuda")
+    ctx = B.Context(n)
+    dpos, dmass, dex = t(pos), t(mass), t(excl)
+    keep, chs = [], []
+    for mpos, mmass, R, M in specs:
+        dm, dmm = t(mpos), t(mmass)
+        idx = torch.zeros(8192, dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+        keep += [dm, dmm, idx, cnt]
+        chs.append(ctx.make_chain(dpos, dmass, dm, dmm, R, M, 0.005, 1e-4, idx, cnt,
+                                  exclude=dex))
+    acc, pot = torch.zeros((n, 3), **f64), torch.zeros(n, **f64)
+    com, macc = torch.zeros((2, 3), **f64), torch.zeros((42, 3), **f64)
+    out = {"workload": "two_dehnen1.5_cusps_n%d" % n, "chains": 2, "members_per_chain": 21}
+    calls = (("chains_forces", lambda: ctx.chains_forces(chs, acc, com, macc, pot=pot)),
+             ("two_single_chain_calls",
+              lambda: [ctx.chain_forces(chs[k], acc, com[k], macc[21 * k:21 * (k + 1)], pot=pot)
+                       for k in range(2)]))
+    for name, fn in calls:
+        fn()
+        ctx.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        out[name + "_us"] = 1e3 * e0.elapsed_time(e1) / reps
+    ctx.sync()
+    out["n_perturbers"] = [int(keep[4 * k + 3].cpu().numpy()[0]) for k in range(2)]
+    ctx.close()
+    return out
+
+
 def extra_kdk_energy(steps=100):
     """Hernquist N = 131 072 + SMBH, dt = 1e-3: both precisions, energy error."""
     import torch
@@ -676,6 +736,8 @@ def main():
     if "chain" in ex:
         log("bench: chain coupling (same workload)")
         out["chain"] = extra_chain(w)
+        log("bench: several chains (two cusps, 1M stars)")
+        out["chains"] = extra_chains()
         torch.cuda.empty_cache()
     if "kdk" in ex:
         log("bench: KDK energy check (Hernquist 131k)")

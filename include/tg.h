@@ -151,7 +151,7 @@ tg_status tg_tree_forces(tg_ctx *ctx, double eps, double theta,
 
 /* ---- relative opening test (alternative to the opening angle) ---------
  * The paper's tree runs open cells with a relative ("Gadget") criterion and
- * an error tolerance (Sec. 4, run set-up) but print no formula; this is the
+ * an error tolerance (Sec. 3, run set-up) but print no formula; this is the
  * relative criterion of Springel 2005 (MNRAS 364, 1105, Sec. 3.1) for a
  * group of targets: a cell of mass M and side s is accepted iff
  *   (G M s^2)^2 <= alpha^2 min|a_old|^2 d^8
@@ -341,6 +341,24 @@ tg_status tg_chain_forces(tg_ctx *ctx, const tg_chain *chain,
                           const int32_t *active_idx_dev, const int32_t *n_active_dev,
                           double *acc_dev, double *pot_dev, double *com_acc_dev,
                           double *member_acc_dev);
+
+/* Several chains at once (the extension to several distant SMBHs that the
+ * paper names as its next step, Sec. 7), READING: every chain couples to
+ * the stars exactly as tg_chain_forces does for one, with the same star
+ * arrays and one exclusion mask that holds the ghost members of all chains;
+ * a star may perturb several chains.  The chain particles feel each other
+ * as Newtonian point masses (M_d at R_d), added to their com_acc; members
+ * feel other chains only through their chain particle.
+ *   chains: host [n_chains] (1..16), sharing pos, mass, n and exclude, each
+ *     with its own perturber list;
+ *   com_acc_dev: [n_chains][3] overwritten;
+ *   member_acc_dev: [sum nc][3] overwritten, the chains' members in order;
+ *   acc_dev / pot_dev / active list as in tg_chain_forces (added to).
+ * Errors: TG_EINVAL (also for two chains with the same centre). */
+tg_status tg_chains_forces(tg_ctx *ctx, const tg_chain *chains, int32_t n_chains,
+                           const int32_t *active_idx_dev, const int32_t *n_active_dev,
+                           double *acc_dev, double *pot_dev, double *com_acc_dev,
+                           double *member_acc_dev);
 
 /* The perturbers of the last tg_perturbers / tg_chain_forces on this chain
  * (pert_idx, n_pert), relative to the chain particle and predicted to first

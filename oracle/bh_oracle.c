@@ -327,7 +327,7 @@ static int or_push(or_vec *a, uint32_t x) {
 
 /* ---------------------------------------------------------------------- */
 /* Relative opening test (READING: the paper names a "Gadget" criterion     */
-/* with an error tolerance, Sec. 4 run set-up, but prints no formula; this  */
+/* with an error tolerance, Sec. 3, run set-up, but prints no formula; this  */
 /* is the relative criterion of Springel 2005, MNRAS 364, 1105, Sec. 3.1,   */
 /* taken for a group of targets).  A cell of mass M and side s is accepted  */
 /* for a target with old acceleration |a| at distance r from the cell's     */

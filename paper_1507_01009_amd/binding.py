@@ -119,6 +119,7 @@ def lib():
             "tg_refit_tree": (st, [P, P, P]),
             "tg_perturbers": (st, [P, P]),
             "tg_chain_forces": (st, [P, P, P, P, P, P, P, P]),
+            "tg_chains_forces": (st, [P, P, i32, P, P, P, P, P, P]),
             "tg_select_within": (st, [P, P, i64, P, P, f64, P, i32, P]),
             "tg_predict_perturbers": (st, [P, P, P, P, f64, P, P, P]),
             "tg_archain_init": (st, [P, f64]),
@@ -157,7 +158,7 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
             "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac", "tg_set_softening",
             "tg_refit_tree",
-            "tg_perturbers", "tg_chain_forces", "tg_select_within",
+            "tg_perturbers", "tg_chain_forces", "tg_chains_forces", "tg_select_within",
             "tg_predict_perturbers", "tg_archain_init", "tg_archain_advance",
             "tg_archain_energy", "tg_forces",
             "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_step_blocks", "tg_graph_begin",
@@ -384,6 +385,14 @@ class Context:
                      n_active=None):
         _check(lib().tg_chain_forces(self.h, C.byref(chain), _ptr(active_idx), _ptr(n_active),
                                      _ptr(acc), _ptr(pot), _ptr(com_acc), _ptr(member_acc)))
+
+    def chains_forces(self, chains, acc, com_acc, member_acc, pot=None, active_idx=None,
+                      n_active=None):
+        """Several chains (a list of tg_chain sharing the star arrays)."""
+        arr = (tg_chain * len(chains))(*chains)
+        _check(lib().tg_chains_forces(self.h, arr, len(chains), _ptr(active_idx),
+                                      _ptr(n_active), _ptr(acc), _ptr(pot), _ptr(com_acc),
+                                      _ptr(member_acc)))
 
     def predict_perturbers(self, chain, vel, com_vel, dt, out_pos, out_vel, out_mass=None):
         v3 = (C.c_double * 3)(*[float(x) for x in com_vel])

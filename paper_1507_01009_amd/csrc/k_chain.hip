@@ -312,6 +312,18 @@ hipError_t launch_chain_predict(tg_ctx *c, const tg_chain *ch, const double *vel
   return hipGetLastError();
 }
 
+// Several chains: out[k] += add.v[k] for k < n3 (the chain particles' mutual
+// point-mass forces, formed on the host from the host centres of mass).
+__global__ void k_add_host_vector(double *__restrict__ out, ChainVec add, int n3) {
+  const int k = (int)threadIdx.x;
+  if (k < n3) out[k] += add.v[k];
+}
+
+hipError_t launch_add_host_vector(tg_ctx *c, double *out, const ChainVec &add, int n3) {
+  hipLaunchKernelGGL(k_add_host_vector, dim3(1), dim3(64), 0, c->stream, out, add, n3);
+  return hipGetLastError();
+}
+
 hipError_t launch_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx,
                                const int32_t *n_act, double *acc, double *pot,
                                double *com_acc, double *member_acc) {

@@ -8,7 +8,7 @@
 // evaluated in double precision with no contraction (bit-identical decisions
 // to the plain definition).  A second mode replaces it by the relative
 // test (G M s^2 / d^4 <= alpha min|a_old|, group box outside the cell cube
-// enlarged by 20 %; the paper's "Gadget" criterion, Sec. 4 run set-up, in
+// enlarged by 20 %; the paper's "Gadget" criterion, Sec. 3, run set-up, in
 // the form of Springel 2005, Sec. 3.1).  Ballot + mbcnt compaction appends accepted
 // cells to an LDS P2M list and the particles of refused leaves to an LDS
 // P2P queue; refused internal cells push their children onto the next

@@ -316,6 +316,11 @@ hipError_t launch_chain_select(tg_ctx *c, const double *pos, const double *mass,
 hipError_t launch_chain_predict(tg_ctx *c, const tg_chain *ch, const double *vel, double dt,
                                 const double rp[3], const double v[3], double *out_pos,
                                 double *out_vel, double *out_mass);
+// several chains (tg_chains_forces): at most kMaxChains, the chain
+// particles' mutual forces added from the host
+constexpr int kMaxChains = 16;
+struct ChainVec { double v[3 * kMaxChains]; };
+hipError_t launch_add_host_vector(tg_ctx *c, double *out, const ChainVec &add, int n3);
 hipError_t launch_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx,
                                const int32_t *n_act, double *acc, double *pot,
                                double *com_acc, double *member_acc);

@@ -1145,6 +1145,55 @@ tg_status tg_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx,
   return TG_OK;
 }
 
+tg_status tg_chains_forces(tg_ctx *c, const tg_chain *chains, int32_t n_chains,
+                           const int32_t *idx, const int32_t *n_act, double *acc, double *pot,
+                           double *com_acc, double *member_acc) {
+  if (!c) return fail(TG_EINVAL, "tg_chains_forces: NULL context");
+  if (!chains || n_chains < 1 || n_chains > kMaxChains)
+    return fail(TG_EINVAL, "tg_chains_forces: n_chains must be in 1..16");
+  if (!com_acc || !member_acc) return fail(TG_EINVAL, "tg_chains_forces: NULL outputs");
+  const tg_chain &c0 = chains[0];
+  for (int k = 0; k < n_chains; ++k) {
+    tg_status st = check_chain(c, &chains[k], "tg_chains_forces");
+    if (st != TG_OK) return st;
+    const tg_chain &ck = chains[k];
+    if (ck.pos != c0.pos || ck.mass != c0.mass || ck.n != c0.n || ck.exclude != c0.exclude)
+      return fail(TG_EINVAL, "tg_chains_forces: chains must share the star arrays and mask");
+    if (ck.pert_idx == c0.pert_idx && k > 0)
+      return fail(TG_EINVAL, "tg_chains_forces: each chain needs its own perturber list");
+  }
+  // every chain couples to the stars on its own (the mask holds all ghosts)
+  int64_t moff = 0;
+  for (int k = 0; k < n_chains; ++k) {
+    tg_status st = tg_chain_forces(c, &chains[k], idx, n_act, acc, pot, com_acc + 3 * k,
+                                   member_acc + 3 * moff);
+    if (st != TG_OK) return st;
+    moff += chains[k].nc;
+  }
+  // the chain particles feel each other as point masses (Newtonian)
+  if (n_chains > 1) {
+    ChainVec add{};
+    const double G = c->cfg.G;
+    for (int a = 0; a < n_chains; ++a) {
+      for (int d = 0; d < n_chains; ++d) {
+        if (d == a) continue;
+        const double dx = chains[d].com[0] - chains[a].com[0];
+        const double dy = chains[d].com[1] - chains[a].com[1];
+        const double dz = chains[d].com[2] - chains[a].com[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (!(r2 > 0.0)) return fail(TG_EINVAL, "tg_chains_forces: two chains share a centre");
+        const double D1 = 1.0 / std::sqrt(r2);
+        const double w = G * chains[d].m_chain * D1 * D1 * D1;
+        add.v[3 * a] += w * dx;
+        add.v[3 * a + 1] += w * dy;
+        add.v[3 * a + 2] += w * dz;
+      }
+    }
+    TG_HIP(launch_add_host_vector(c, com_acc, add, 3 * n_chains));
+  }
+  return TG_OK;
+}
+
 tg_status tg_predict_perturbers(tg_ctx *c, const tg_chain *ch, const double *vel,
                                 const double com_vel[3], double dt, double *out_pos,
                                 double *out_vel, double *out_mass) {

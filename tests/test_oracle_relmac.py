@@ -1,5 +1,5 @@
 """Pins for the oracle's relative opening test (the paper's tree runs use a
-relative "Gadget" criterion with an error tolerance, Sec. 4 run set-up; the
+relative "Gadget" criterion with an error tolerance, Sec. 3, run set-up; the
 rule itself is Springel 2005, MNRAS 364, 1105, Sec. 3.1, taken per group).
 
 Independent references: the cell cubes must contain their particles and tile
