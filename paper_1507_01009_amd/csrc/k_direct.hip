@@ -10,7 +10,10 @@
 // loads, the block's sums combined in a fixed tree order and the per-block
 // partials summed in a second ordered pass.  Every sum is compensated
 // (error-free TwoSum with a running correction), so the result does not
-// depend on the split beyond the last bit and is deterministic.
+// depend on the split beyond the last bit and is deterministic.  Every
+// operation is rounded on its own (no FMA contraction): the TwoSum steps
+// need it, and so does the fused drift-and-sum kernel, whose sums must equal
+// the unfused ones bit for bit.
 #include "tg_internal.h"
 
 namespace tg {
@@ -27,6 +30,7 @@ __device__ __forceinline__ int seg_of(const int64_t *off, int nseg, int64_t i) {
 // m/r and m/r^3 with the pair's softening ep (soft: cubic spline, h = ep).
 __device__ __forceinline__ void pair_terms(double dx, double dy, double dz, double ep, double m,
                                            int soft, double &mD1, double &mD3) {
+#pragma clang fp contract(off)
   if (soft) {
     double p0, p1;
     spline_pair_dp(sqrt(dx * dx + dy * dy + dz * dz), ep, p0, p1);
@@ -48,6 +52,7 @@ __global__ void k_direct(const double *__restrict__ spos, const double *__restri
                          int nseg, int64_t chunk, int nchunks, int self_pairs,
                          int accumulate, int soft, double *__restrict__ acc,
                          double *__restrict__ pot, double *__restrict__ part) {
+#pragma clang fp contract(off)
   const int64_t total = nt * (int64_t)nchunks;
   for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < total;
        w += (int64_t)gridDim.x * blockDim.x) {
@@ -89,7 +94,7 @@ __global__ void k_direct(const double *__restrict__ spos, const double *__restri
 
 // Compensated sums of a 256-thread block combined in a fixed tree order;
 // thread 0 returns with the totals in ss[k][0] + sc[k][0].
-__device__ void block_csum4(CSum r[4], double (*ss)[256], double (*sc)[256]) {
+__device__ __forceinline__ void block_csum4(CSum r[4], double (*ss)[256], double (*sc)[256]) {
   for (int k = 0; k < 4; ++k) { ss[k][threadIdx.x] = r[k].s; sc[k][threadIdx.x] = r[k].c; }
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -117,6 +122,7 @@ __global__ __launch_bounds__(256) void k_direct_few(
     const double *__restrict__ teps, int64_t nt, const int64_t *__restrict__ sseg,
     const int64_t *__restrict__ tseg, int nseg, int self_pairs, int soft,
     double *__restrict__ part) {
+#pragma clang fp contract(off)
   __shared__ double ss[4][256], sc[4][256];
   const int64_t i = blockIdx.y;
   const int s = seg_of(tseg, nseg, i);
@@ -176,6 +182,98 @@ __global__ __launch_bounds__(256) void k_direct_reduce(int64_t nt, int nchunks,
   }
 }
 
+// The stars' drift fused with the SMBH <- star sums of a block substep
+// (one system, at most kDriftSmbhMax SMBHs): block b drifts the stars
+// [b kFewPerBlock, (b + 1) kFewPerBlock) (x <- x + v dt with the operations
+// of k_drift; frozen stars stay) and sums their pull on every SMBH at the
+// drifted positions with the ranges, thread order and block reduction of
+// k_direct_few, so k_direct_reduce turns the partials into the same totals.
+// The stars' positions are read once instead of twice.
+constexpr int kDriftSmbhMax = 4;
+
+template <int kNB>
+__global__ __launch_bounds__(256) void k_drift_smbh(
+    double *__restrict__ pos, const double *__restrict__ vel, const uint8_t *__restrict__ frozen,
+    int64_t n, double dt, const double *__restrict__ sm, double seps,
+    const double *__restrict__ bpos, const double *__restrict__ beps, int soft,
+    double *__restrict__ part) {
+#pragma clang fp contract(off)
+  constexpr int nb = kNB;
+  __shared__ double ss[4][256], sc[4][256];
+  const int64_t j0 = (int64_t)blockIdx.x * kFewPerBlock;
+  const int64_t j1 = min(n, j0 + kFewPerBlock);
+  double bx[nb], by[nb], bz[nb], be[nb];
+#pragma unroll
+  for (int i = 0; i < nb; ++i) {
+    bx[i] = bpos[3 * i]; by[i] = bpos[3 * i + 1]; bz[i] = bpos[3 * i + 2]; be[i] = beps[i];
+  }
+  CSum r[nb][4];
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+    double x = pos[3 * j], y = pos[3 * j + 1], z = pos[3 * j + 2];
+    if (!(frozen && frozen[j])) {
+      x = x + vel[3 * j] * dt;
+      y = y + vel[3 * j + 1] * dt;
+      z = z + vel[3 * j + 2] * dt;
+      pos[3 * j] = x; pos[3 * j + 1] = y; pos[3 * j + 2] = z;
+    }
+    const double m = sm[j];
+#pragma unroll
+    for (int i = 0; i < nb; ++i) {
+      const double ep = fmax(seps, be[i]);
+      const double dx = bx[i] - x, dy = by[i] - y, dz = bz[i] - z;
+      double mD1, mD3;
+      pair_terms(dx, dy, dz, ep, m, soft, mD1, mD3);
+      r[i][0].add(-mD3 * dx);
+      r[i][1].add(-mD3 * dy);
+      r[i][2].add(-mD3 * dz);
+      r[i][3].add(-mD1);
+    }
+  }
+  // static indices keep the sums in registers
+#pragma unroll
+  for (int i = 0; i < nb; ++i) {
+    block_csum4(r[i], ss, sc);
+    if (threadIdx.x == 0) {
+      double *o = part + 8 * (size_t)(blockIdx.x * nb + i);
+      for (int k = 0; k < 4; ++k) { o[2 * k] = ss[k][0]; o[2 * k + 1] = sc[k][0]; }
+    }
+    __syncthreads();
+  }
+}
+
+// Whether the star sums of n stars on nb SMBHs take the few-target path of
+// launch_direct (and so may be fused with the drift).
+static bool few_path(const tg_ctx *c, int64_t n, int64_t nt) {
+  if (!(nt <= 4096 && n >= 2 * kFewPerBlock)) return false;
+  const int64_t bpt = (n + kFewPerBlock - 1) / kFewPerBlock;
+  return bpt * nt * 8 <= c->b.dpart_cap && bpt <= 65535;
+}
+
+bool drift_smbh_fits(const tg_ctx *c, int64_t n, int32_t nb) {
+  return nb >= 1 && nb <= kDriftSmbhMax && few_path(c, n, nb);
+}
+
+hipError_t launch_drift_smbh(tg_ctx *c, double *pos, const double *vel, const uint8_t *frozen,
+                             int64_t n, double dt, const double *mass, double eps,
+                             const double *bpos, const double *beps, int32_t nb,
+                             double *bacc, double *bpot) {
+  const int64_t bpt = (n + kFewPerBlock - 1) / kFewPerBlock;
+  const dim3 g((unsigned)bpt), b(256);
+  switch (nb) {
+    case 1: hipLaunchKernelGGL(k_drift_smbh<1>, g, b, 0, c->stream, pos, vel, frozen, n, dt, mass,
+                               eps, bpos, beps, c->soft, c->b.dpart); break;
+    case 2: hipLaunchKernelGGL(k_drift_smbh<2>, g, b, 0, c->stream, pos, vel, frozen, n, dt, mass,
+                               eps, bpos, beps, c->soft, c->b.dpart); break;
+    case 3: hipLaunchKernelGGL(k_drift_smbh<3>, g, b, 0, c->stream, pos, vel, frozen, n, dt, mass,
+                               eps, bpos, beps, c->soft, c->b.dpart); break;
+    default: hipLaunchKernelGGL(k_drift_smbh<4>, g, b, 0, c->stream, pos, vel, frozen, n, dt, mass,
+                                eps, bpos, beps, c->soft, c->b.dpart); break;
+  }
+  hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)std::min<int64_t>(nb, 4096)), dim3(256), 0,
+                     c->stream, (int64_t)nb, (int)bpt, 0, c->b.dpart, bacc, bpot);
+  return hipGetLastError();
+}
+
 hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
                          const double *sm, const double *seps, double seps_all,
                          int64_t ns, const double *tpos,
@@ -184,9 +282,9 @@ hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
                          double *acc, double *pot) {
   (void)ns;
   if (nt == 0) return hipSuccess;
-  if (nt <= 4096 && max_seg_src >= 2 * kFewPerBlock) {
+  if (few_path(c, max_seg_src, nt)) {
     const int64_t bpt = (max_seg_src + kFewPerBlock - 1) / kFewPerBlock;
-    if (bpt * nt * 8 <= c->b.dpart_cap && bpt <= 65535) {
+    {
       hipLaunchKernelGGL(k_direct_few, dim3((unsigned)bpt, (unsigned)nt), dim3(256), 0,
                          c->stream, spos, sm, seps, seps_all, tpos, teps, nt, dseg,
                          dseg + (nseg + 1), nseg, self_pairs, c->soft, c->b.dpart);

@@ -244,6 +244,7 @@ __device__ __forceinline__ double cell_centre(uint32_t v, int l, const uint32_t 
 // terms and the direct sums.  A pair's acceleration is -m psi_1 x and its
 // potential -m psi; beyond 2h (and for h = 0) they are 1/r and 1/r^3.
 __device__ __forceinline__ void spline_pair_dp(double r, double h, double &p0, double &p1) {
+#pragma clang fp contract(off)
   if (!(r < 2.0 * h)) {
     p0 = 1.0 / r;
     p1 = p0 * p0 * p0;
@@ -326,6 +327,13 @@ hipError_t launch_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx
                                double *com_acc, double *member_acc);
 
 // k_direct.hip
+// stars' drift fused with their sums on the SMBHs (one system); fits says
+// whether the few-target sum path applies (then the totals are bit-equal)
+bool drift_smbh_fits(const tg_ctx *c, int64_t n, int32_t nb);
+hipError_t launch_drift_smbh(tg_ctx *c, double *pos, const double *vel, const uint8_t *frozen,
+                             int64_t n, double dt, const double *mass, double eps,
+                             const double *bpos, const double *beps, int32_t nb,
+                             double *bacc, double *bpot);
 hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
                          const double *sm, const double *seps, double seps_all,
                          int64_t ns, const double *tpos,

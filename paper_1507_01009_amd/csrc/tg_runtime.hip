@@ -893,7 +893,7 @@ static tg_status check_system(const tg_system *y, const char *who) {
 // tree is rebuilt when the substep counter k is a multiple of it (or no
 // build exists yet) and refitted otherwise; both choices are made on the
 // device, so a captured substep replays correctly.
-static tg_status smbh_sums(tg_ctx *c, const tg_system *y);
+static tg_status smbh_sums(tg_ctx *c, const tg_system *y, bool stars_done = false);
 
 static tg_status forces_impl(tg_ctx *c, const tg_system *y, const int32_t *idx,
                              const int32_t *n_act, const int64_t *k, int32_t rebuild_every) {
@@ -938,8 +938,9 @@ static tg_status forces_impl(tg_ctx *c, const tg_system *y, const int32_t *idx,
   return smbh_sums(c, y);
 }
 
-// SMBH <- star sums over each system's stars, then SMBH <-> SMBH.
-static tg_status smbh_sums(tg_ctx *c, const tg_system *y) {
+// SMBH <- star sums over each system's stars (skipped with stars_done: a
+// fused launch already formed them), then SMBH <-> SMBH.
+static tg_status smbh_sums(tg_ctx *c, const tg_system *y, bool stars_done) {
   tg_status st = TG_OK;
   if (y->n_bh > 0) {
     // SMBHs feel the stars of their own system, then each other
@@ -948,9 +949,11 @@ static tg_status smbh_sums(tg_ctx *c, const tg_system *y) {
     for (int s = 0; s <= y->n_sys; ++s) bs[s] = y->bh_seg ? y->bh_seg[s] : (s ? y->n_bh : 0);
     const int nseg = y->n_sys;
     // star softening: the stars' eps for every star
-    st = tg_direct_fp64_eps(c, y->pos, y->mass, y->eps, y->n, y->bh_pos, y->bh_eps,
-                            y->n_bh, so.data(), bs.data(), nseg, y->bh_acc, y->bh_pot);
-    if (st != TG_OK) return st;
+    if (!stars_done) {
+      st = tg_direct_fp64_eps(c, y->pos, y->mass, y->eps, y->n, y->bh_pos, y->bh_eps,
+                              y->n_bh, so.data(), bs.data(), nseg, y->bh_acc, y->bh_pot);
+      if (st != TG_OK) return st;
+    }
     st = tg_direct_fp64(c, y->bh_pos, y->bh_mass, y->bh_eps, y->n_bh, y->bh_pos,
                         y->bh_eps, y->n_bh, bs.data(), bs.data(), nseg, 1, 1, y->bh_acc,
                         y->bh_pot);
@@ -1035,8 +1038,21 @@ tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
 // SMBHs' kicks and drift (k advances, the active count becomes 0), the
 // stars' drift and the SMBH sums.  These are exactly the launches of
 // tg_step_block that do any work when both active sets are empty.
+// With one system and a few SMBHs the stars' drift and their sums on the
+// SMBHs are one launch (the SMBHs move first; the sums come out bit for
+// bit as in tg_step_block).
 static tg_status idle_substep(tg_ctx *c, const tg_system *y, const tg_blocks *b, double dt_min) {
   tg_status st;
+  const bool fused = y->n_sys == 1 && c->sysoff_host.size() == 2 &&
+                     c->sysoff_host[0] == 0 && c->sysoff_host[1] == y->n &&
+                     drift_smbh_fits(c, y->n, y->n_bh);
+  if (fused) {
+    TG_HIP(launch_bh_substep(c, y->bh_pos, y->bh_vel, y->bh_acc, y->n_bh, dt_min, b->k,
+                             b->n_active));
+    TG_HIP(launch_drift_smbh(c, y->pos, y->vel, y->frozen, y->n, dt_min, y->mass, y->eps,
+                             y->bh_pos, y->bh_eps, y->n_bh, y->bh_acc, y->bh_pot));
+    return smbh_sums(c, y, true);
+  }
   if ((st = drift_impl(c, y->pos, y->vel, y->n, dt_min, y->frozen))) return st;
   TG_HIP(launch_bh_substep(c, y->bh_pos, y->bh_vel, y->bh_acc, y->n_bh, dt_min, b->k,
                            b->n_active));
