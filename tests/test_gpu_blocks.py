@@ -61,11 +61,13 @@ def test_active_set_empty_input():
     assert int(na.item()) == 0
 
 
-def _run(w, nlev, dt_max, nsub, driver, frozen=None, every=0):
+def _run(w, nlev, dt_max, nsub, driver, frozen=None, every=0, softening=None):
     import torch
     from paper_1507_01009_amd import binding as B
     from test_gpu_steps import Dev, _blocks
-    ctx = B.Context(w.n)
+    ctx = B.Context(w.n, max_systems=w.sys_off.shape[0] - 1)
+    if softening:
+        ctx.set_softening(softening)
     d = Dev(ctx, w)
     keep_fz = None
     if frozen is not None:
@@ -181,3 +183,23 @@ def test_driver_errors():
         s.synchronize()
         assert int(keep[4].item()) == 1
         del g
+
+
+@pytest.mark.parametrize("case", ["batch3", "spline"])
+def test_driver_other_paths_bitwise(case):
+    """Several systems (idle substeps take the separate drift and sums) and
+    spline softening (the fused drift and sums with the spline kernel)."""
+    say("driver", case)
+    if case == "batch3":
+        w = ics.batch_c5(S=3, nmin=6000, nmax=20000)
+        soft = None
+    else:
+        w = ics.hernquist_c4(n=16384)
+        soft = "spline"
+    a, _ = _run(w, 8, 2.0 ** -6, 150, False, softening=soft)
+    b, n_idle = _run(w, 8, 2.0 ** -6, 150, True, softening=soft)
+    say("  idle substeps %d" % n_idle)
+    assert n_idle > 0 and a["k"] == b["k"] == 150
+    assert a["n_active"] == b["n_active"] and np.array_equal(a["idx"], b["idx"])
+    for key in ("pos", "vel", "acc", "pot", "level", "bpos", "bvel", "bacc"):
+        assert np.array_equal(a[key], b[key]), key
