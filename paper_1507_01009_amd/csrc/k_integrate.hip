@@ -189,8 +189,8 @@ __global__ __launch_bounds__(256) void k_active_emit(const uint8_t *__restrict__
 // The SMBHs' part of one block substep (they sit on the finest level):
 // closing half kick (not at k = 0), opening half kick, drift, all with the
 // finest step and the same separately rounded operations as k_kick and
-// k_drift; then the substep counter advances.  With clear_active the active
-// count is also set to 0 (a substep known to have no active star).
+// k_drift; then the substep counter advances.  A non-null n_act is set to 0
+// (a substep known to have no active star).
 __global__ __launch_bounds__(64) void k_bh_substep(double *__restrict__ pos,
                                                    double *__restrict__ vel,
                                                    const double *__restrict__ acc, int n,
