@@ -194,3 +194,52 @@ def chains_coupling(pos, mass, targets, chains, exclude=None, G=1.0):
     return (acc.astype(np.float64), pot.astype(np.float64),
             np.array([c.astype(np.float64) for c in coms]),
             np.concatenate(mems), perts)
+
+
+def membership(mx, mv, mm, massive, designated, r_chain, r_chain0, gamma, px):
+    """Membership update after a chain step (Sec. 2, Eq. 4 and 5, and the
+    priority rule of Sec. 4), READING:
+
+    * absorption (Eq. 4): perturber p joins if |x_p - R|^2 < r_chain^2, with
+      r_chain the chain radius (largest member distance from the centre of
+      mass in the last chain step);
+    * escape (Eq. 5): member i leaves if |x_i|^2 > r_escape^2, r_escape =
+      gamma r_chain,0, and it recedes, x_i . v_i > 0;
+    * while a perturber is absorbed, escapes wait unless r_chain exceeds
+      1.05 r_escape;
+    * the chain ends if fewer than two members would remain, or if the
+      designated massive particle leaves and no other massive member stays;
+      otherwise the most massive remaining massive member (ties: the lowest
+      index) becomes the designated one.
+    Squares and dot products are summed x, y, z in that order, each
+    operation rounded on its own.  mx, mv: members relative to the centre of
+    mass; px: perturbers relative to it.  Returns a dict with ``absorb``
+    (perturber rows), ``escape`` (member indices), ``terminate`` and
+    ``designated`` (-1 when the chain ends).
+    """
+    mx = np.asarray(mx, np.float64).reshape(-1, 3)
+    mv = np.asarray(mv, np.float64).reshape(-1, 3)
+    px = np.asarray(px, np.float64).reshape(-1, 3)
+    n = mx.shape[0]
+    rc2 = float(r_chain) * float(r_chain)
+    p2 = (px[:, 0] * px[:, 0] + px[:, 1] * px[:, 1]) + px[:, 2] * px[:, 2]
+    absorb = np.nonzero(p2 < rc2)[0].astype(np.int32)
+    r_esc = float(gamma) * float(r_chain0)
+    m2 = (mx[:, 0] * mx[:, 0] + mx[:, 1] * mx[:, 1]) + mx[:, 2] * mx[:, 2]
+    rv = (mx[:, 0] * mv[:, 0] + mx[:, 1] * mv[:, 1]) + mx[:, 2] * mv[:, 2]
+    escape = np.nonzero((m2 > r_esc * r_esc) & (rv > 0.0))[0].astype(np.int32)
+    if absorb.size and escape.size and not (float(r_chain) > 1.05 * r_esc):
+        escape = escape[:0]
+    new_d = int(designated)
+    terminate = False
+    if new_d in set(escape.tolist()):
+        left = [i for i in range(n) if massive[i] and i not in set(escape.tolist())]
+        if left:
+            new_d = max(left, key=lambda i: (float(mm[i]), -i))
+        else:
+            terminate = True
+    if n - escape.size + absorb.size < 2:
+        terminate = True
+    if terminate:
+        new_d = -1
+    return {"absorb": absorb, "escape": escape, "terminate": terminate, "designated": new_d}

@@ -211,3 +211,60 @@ def test_one_chain_of_several_is_the_single_chain():
     assert np.allclose(a_com2[0], ac1 + pull, rtol=1e-12, atol=0)
     assert np.allclose(a_com2[1] - a_one_other,
                        -c["m_chain"] * d / np.linalg.norm(d) ** 3, rtol=1e-12, atol=0)
+
+
+def _members(n=6, seed=1):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, 3)) * 0.01
+    v = rng.normal(size=(n, 3))
+    m = np.concatenate([[0.01], rng.uniform(1e-5, 1e-4, n - 1)])
+    massive = np.zeros(n, bool)
+    massive[0] = True
+    return x, v, m, massive
+
+
+def test_membership_escape_needs_distance_and_recession():
+    x, v, m, mas = _members()
+    x[2] = [0.05, 0.0, 0.0]; v[2] = [1.0, 0.0, 0.0]      # far and receding: escapes
+    x[3] = [0.0, 0.05, 0.0]; v[3] = [0.0, -1.0, 0.0]     # far, approaching: stays
+    x[4] = [0.0, 0.0, 0.02]; v[4] = [0.0, 0.0, 1.0]      # receding inside r_escape: stays
+    r = chain.membership(x, v, m, mas, 0, 0.03, 0.02, 1.5, np.zeros((0, 3)))
+    assert r["escape"].tolist() == [2] and r["absorb"].size == 0
+    assert not r["terminate"] and r["designated"] == 0
+
+
+def test_membership_absorption_inside_the_chain_radius_only():
+    x, v, m, mas = _members()
+    px = np.array([[0.029, 0, 0], [0, 0.031, 0], [0.02, 0.02, 0.0], [0, 0, -0.0299999]])
+    r = chain.membership(x, v, m, mas, 0, 0.03, 0.02, 1.5, px)
+    assert r["absorb"].tolist() == [0, 2, 3]          # |(.02,.02,0)| = .0283 < .03
+
+
+def test_membership_absorption_delays_escape_until_five_percent():
+    x, v, m, mas = _members()
+    x[2] = [0.05, 0.0, 0.0]; v[2] = [1.0, 0.0, 0.0]
+    px = np.array([[0.001, 0.0, 0.0]])
+    r_esc = 1.5 * 0.02
+    for r_chain, escapes in ((1.04 * r_esc, []), (1.06 * r_esc, [2])):
+        r = chain.membership(x, v, m, mas, 0, r_chain, 0.02, 1.5, px)
+        assert r["absorb"].tolist() == [0] and r["escape"].tolist() == escapes
+
+
+def test_membership_termination_and_a_new_designated_particle():
+    x, v, m, mas = _members(3)
+    x[:] = [[0.05, 0, 0], [0.06, 0, 0], [0.001, 0, 0]]
+    v[:] = [[1, 0, 0], [1, 0, 0], [0, 0, 0]]
+    # two of three leave: one member would remain
+    r = chain.membership(x, v, m, mas, 0, 0.03, 0.02, 1.5, np.zeros((0, 3)))
+    assert r["terminate"] and r["designated"] == -1
+    # the designated SMBH leaves; a second, heavier SMBH stays and takes over
+    x, v, m, mas = _members(5)
+    x[0] = [0.05, 0, 0]; v[0] = [1, 0, 0]
+    mas[3] = mas[4] = True
+    m[3], m[4] = 0.004, 0.006
+    r = chain.membership(x, v, m, mas, 0, 0.03, 0.02, 1.5, np.zeros((0, 3)))
+    assert not r["terminate"] and r["designated"] == 4 and r["escape"].tolist() == [0]
+    # no other massive member: the chain ends
+    mas[3] = mas[4] = False
+    r = chain.membership(x, v, m, mas, 0, 0.03, 0.02, 1.5, np.zeros((0, 3)))
+    assert r["terminate"] and r["designated"] == -1
