@@ -424,6 +424,45 @@ tg_status tg_archain_advance(tg_archain *chain, double G, double dt, double tol,
  * integration and the work of the perturbers balance exactly). */
 tg_status tg_archain_energy(const tg_archain *chain, double G, double *err_out);
 
+/* Chain membership after a chain step (host; Sec. 2, Eq. 4 and 5; the
+ * absorption-first rule of Sec. 4).  READING:
+ *  - absorption (Eq. 4): perturber p joins if |px_p|^2 < r_chain^2, px
+ *    relative to the chain's centre of mass (e.g. tg_predict_perturbers
+ *    with dt = 0), r_chain the largest member distance in the last chain
+ *    step;
+ *  - escape (Eq. 5): member i leaves if |x_i|^2 > (gamma r_chain0)^2 and
+ *    x_i . v_i > 0 (it recedes; the paper takes gamma = 1.5);
+ *  - while some perturber joins, escapes wait unless r_chain > 1.05 gamma
+ *    r_chain0;
+ *  - the chain ends if fewer than two members would remain, or if the
+ *    designated massive member leaves and no other massive member stays;
+ *    otherwise the most massive remaining massive member (ties: the lowest
+ *    index) takes over as the chain's centre particle.
+ * Squares and dot products are summed x, y, z in order with every operation
+ * rounded on its own.  All arrays are HOST memory; the caller applies the
+ * result (ghost flags, masses, frames). */
+typedef struct {
+  int32_t n;                  /* members, 1..256 */
+  const double *x, *v;        /* [n][3] relative to the centre of mass */
+  const double *m;            /* [n] */
+  const uint8_t *massive;     /* [n] nonzero: a designated massive particle (SMBH) */
+  int32_t designated;         /* the member that is the chain's centre particle */
+  double r_chain, r_chain0, gamma;
+  int32_t np;                 /* perturbers */
+  const double *px;           /* [np][3] relative to the centre of mass */
+} tg_membership_in;
+
+typedef struct {
+  int32_t *absorb;            /* [np] out: rows of px that join, ascending */
+  int32_t n_absorb;
+  int32_t *escape;            /* [n] out: members that leave, ascending */
+  int32_t n_escape;
+  int32_t terminate;          /* 1: the chain ends (all members back to the tree) */
+  int32_t designated;         /* the centre particle afterwards, -1 when it ends */
+} tg_membership_out;
+
+tg_status tg_chain_membership(const tg_membership_in *in, tg_membership_out *out);
+
 /* ---- whole steps (every stage above in one call; capturable) ---------- */
 typedef struct {
   double *pos, *vel, *acc, *pot;   /* stars [n][3], pot [n] may be NULL */

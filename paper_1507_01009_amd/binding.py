@@ -70,6 +70,18 @@ class tg_chain(C.Structure):
                 ("pert_idx", C.c_void_p), ("pert_cap", C.c_int32), ("n_pert", C.c_void_p)]
 
 
+class tg_membership_in(C.Structure):
+    _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("v", C.c_void_p), ("m", C.c_void_p),
+                ("massive", C.c_void_p), ("designated", C.c_int32), ("r_chain", C.c_double),
+                ("r_chain0", C.c_double), ("gamma", C.c_double), ("np", C.c_int32),
+                ("px", C.c_void_p)]
+
+
+class tg_membership_out(C.Structure):
+    _fields_ = [("absorb", C.c_void_p), ("n_absorb", C.c_int32), ("escape", C.c_void_p),
+                ("n_escape", C.c_int32), ("terminate", C.c_int32), ("designated", C.c_int32)]
+
+
 class tg_archain(C.Structure):
     _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("v", C.c_void_p), ("m", C.c_void_p),
                 ("t", C.c_double), ("B", C.c_double), ("ds", C.c_double)]
@@ -125,6 +137,7 @@ def lib():
             "tg_archain_init": (st, [P, f64]),
             "tg_archain_advance": (st, [P, f64, f64, f64, P, P]),
             "tg_archain_energy": (st, [P, f64, P]),
+            "tg_chain_membership": (st, [P, P]),
             "tg_set_softening": (st, [P, i32]),
             "tg_forces": (st, [P, P, P, P]),
             "tg_step_kdk": (st, [P, P, f64]),
@@ -160,7 +173,7 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_refit_tree",
             "tg_perturbers", "tg_chain_forces", "tg_chains_forces", "tg_select_within",
             "tg_predict_perturbers", "tg_archain_init", "tg_archain_advance",
-            "tg_archain_energy", "tg_forces",
+            "tg_archain_energy", "tg_chain_membership", "tg_forces",
             "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_step_blocks", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
@@ -546,6 +559,27 @@ def _memcpy_d2h(dst, src, nbytes):
     rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), C.c_size_t(nbytes), 2)
     if rc != 0:
         raise RuntimeError("hipMemcpy failed: %d" % rc)
+
+
+def chain_membership(x, v, m, massive, designated, r_chain, r_chain0, gamma, px):
+    """Host membership update after a chain step (tg_chain_membership);
+    numpy in, dict out: absorb (perturber rows), escape (member indices),
+    terminate, designated."""
+    import numpy as np
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    v = np.ascontiguousarray(v, np.float64).reshape(-1, 3)
+    m = np.ascontiguousarray(m, np.float64)
+    mas = np.ascontiguousarray(massive, np.uint8)
+    px = np.ascontiguousarray(px, np.float64).reshape(-1, 3)
+    a = np.zeros(max(px.shape[0], 1), np.int32)
+    e = np.zeros(max(x.shape[0], 1), np.int32)
+    p = lambda arr: arr.ctypes.data_as(C.c_void_p)
+    i = tg_membership_in(x.shape[0], p(x), p(v), p(m), p(mas), int(designated), float(r_chain),
+                         float(r_chain0), float(gamma), px.shape[0], p(px) if px.size else None)
+    o = tg_membership_out(p(a), 0, p(e), 0, 0, 0)
+    _check(lib().tg_chain_membership(C.byref(i), C.byref(o)))
+    return {"absorb": a[:o.n_absorb].copy(), "escape": e[:o.n_escape].copy(),
+            "terminate": bool(o.terminate), "designated": int(o.designated)}
 
 
 class ARChain:
