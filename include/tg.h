@@ -590,6 +590,63 @@ const char *tg_last_error(void);
 /* Library build description (arch, flags), static string. */
 const char *tg_version(void);
 
+/* ---- the hybrid step (Sec. 2): tree stars + one regularised chain -------
+ * A host driver over the calls above for a system with one SMBH, global
+ * kick-drift-kick steps of length dt.  READING of the hybrid recipe:
+ *  - without a chain: one tg_step_kdk; then the stars within r_chain0 of the
+ *    SMBH (tg_select_within) start a chain with it;
+ *  - members are integrated by the AR-chain in the chain's centre-of-mass
+ *    frame; their stars stay in the arrays as ghosts: mass times ghost_mass,
+ *    excluded from the coupling, positions and velocities rewritten from
+ *    the chain after each step (the SMBH's arrays likewise);
+ *  - the chain particle (mass M at R, velocity V; no softening) takes the
+ *    stars' half kicks a_com (tg_chain_forces, with Eq. 3) and drifts with
+ *    them; the members are advanced over the step by tg_archain_advance
+ *    with the perturbers of the last coupling, predicted to first order
+ *    from the start of the step (tg_predict_perturbers, dt = 0);
+ *  - forces after the drift: tg_forces without the SMBH (it is in the
+ *    chain), then tg_chain_forces;
+ *  - after the step tg_chain_membership updates the members (absorbed stars
+ *    become ghosts, escaped ones get their mass and global coordinates
+ *    back; a chain that ends returns everything), the centre of mass is
+ *    re-formed and the forces are evaluated again.
+ * The driver owns the system while it lives: it writes the stars' masses
+ * (ghosts) and the SMBH's arrays, and synchronises the stream every step.
+ * Errors: TG_EINVAL (arguments; the system needs exactly one SMBH),
+ * TG_ECAPACITY (perturbers beyond pert_cap, members beyond 256). */
+typedef struct tg_hybrid tg_hybrid;
+
+typedef struct {
+  double r_chain0;            /* chain start radius about the SMBH, > 0 */
+  double gamma_crit;          /* Eq. 2, > 0 (the paper: 1e-4 ... ) */
+  double gamma_esc;           /* Eq. 5, > 0 (the paper: 1.5) */
+  double tol;                 /* AR-chain tolerance per extrapolated step, > 0 */
+  double ghost_mass;          /* ghost mass factor, in (0, 1) */
+  int32_t pert_cap;           /* perturber list capacity, >= 1 */
+} tg_hybrid_config;
+
+typedef struct {
+  int32_t active;             /* 1 while a chain exists */
+  int32_t n_members;          /* including the SMBH */
+  int32_t n_perturbers;       /* of the last coupling */
+  double com[3], com_vel[3];  /* the chain particle */
+  double m_chain, r_chain;    /* mass; largest member distance from the centre */
+  double energy_error;        /* the AR-chain's bookkeeping error */
+  int64_t steps, starts, absorbed, escaped, ended;
+} tg_hybrid_state;
+
+tg_status tg_hybrid_create(tg_ctx *ctx, const tg_system *sys, const tg_hybrid_config *cfg,
+                           tg_hybrid **out);
+/* Evaluates the forces of the current state (and may start a chain): call
+ * once before the first step. */
+tg_status tg_hybrid_begin(tg_hybrid *h);
+tg_status tg_hybrid_step(tg_hybrid *h, double dt);
+/* members_out (host [n_members] or NULL): star index of each member, -1 for
+ * the SMBH; member x/v (host [n_members][3] or NULL): centre-of-mass frame. */
+tg_status tg_hybrid_state_get(const tg_hybrid *h, tg_hybrid_state *st, int32_t *members_out,
+                              double *member_x, double *member_v);
+void tg_hybrid_destroy(tg_hybrid *h);
+
 #ifdef __cplusplus
 }
 #endif

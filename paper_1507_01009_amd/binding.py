@@ -82,6 +82,19 @@ class tg_membership_out(C.Structure):
                 ("n_escape", C.c_int32), ("terminate", C.c_int32), ("designated", C.c_int32)]
 
 
+class tg_hybrid_config(C.Structure):
+    _fields_ = [("r_chain0", C.c_double), ("gamma_crit", C.c_double), ("gamma_esc", C.c_double),
+                ("tol", C.c_double), ("ghost_mass", C.c_double), ("pert_cap", C.c_int32)]
+
+
+class tg_hybrid_state(C.Structure):
+    _fields_ = [("active", C.c_int32), ("n_members", C.c_int32), ("n_perturbers", C.c_int32),
+                ("com", C.c_double * 3), ("com_vel", C.c_double * 3), ("m_chain", C.c_double),
+                ("r_chain", C.c_double), ("energy_error", C.c_double), ("steps", C.c_int64),
+                ("starts", C.c_int64), ("absorbed", C.c_int64), ("escaped", C.c_int64),
+                ("ended", C.c_int64)]
+
+
 class tg_archain(C.Structure):
     _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("v", C.c_void_p), ("m", C.c_void_p),
                 ("t", C.c_double), ("B", C.c_double), ("ds", C.c_double)]
@@ -138,6 +151,11 @@ def lib():
             "tg_archain_advance": (st, [P, f64, f64, f64, P, P]),
             "tg_archain_energy": (st, [P, f64, P]),
             "tg_chain_membership": (st, [P, P]),
+            "tg_hybrid_create": (st, [P, P, P, P]),
+            "tg_hybrid_begin": (st, [P]),
+            "tg_hybrid_step": (st, [P, f64]),
+            "tg_hybrid_state_get": (st, [P, P, P, P, P]),
+            "tg_hybrid_destroy": (None, [P]),
             "tg_set_softening": (st, [P, i32]),
             "tg_forces": (st, [P, P, P, P]),
             "tg_step_kdk": (st, [P, P, f64]),
@@ -173,7 +191,8 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_refit_tree",
             "tg_perturbers", "tg_chain_forces", "tg_chains_forces", "tg_select_within",
             "tg_predict_perturbers", "tg_archain_init", "tg_archain_advance",
-            "tg_archain_energy", "tg_chain_membership", "tg_forces",
+            "tg_archain_energy", "tg_chain_membership", "tg_hybrid_create", "tg_hybrid_begin",
+            "tg_hybrid_step", "tg_hybrid_state_get", "tg_hybrid_destroy", "tg_forces",
             "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_step_blocks", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
@@ -580,6 +599,50 @@ def chain_membership(x, v, m, massive, designated, r_chain, r_chain0, gamma, px)
     _check(lib().tg_chain_membership(C.byref(i), C.byref(o)))
     return {"absorb": a[:o.n_absorb].copy(), "escape": e[:o.n_escape].copy(),
             "terminate": bool(o.terminate), "designated": int(o.designated)}
+
+
+class Hybrid:
+    """The hybrid step driver (tg_hybrid_*) over a context and a system with
+    one SMBH; keep the system's tensors alive while it lives."""
+
+    def __init__(self, ctx, system, r_chain0, gamma_crit=1e-4, gamma_esc=1.5, tol=1e-12,
+                 ghost_mass=1e-10, pert_cap=8192):
+        cfg = tg_hybrid_config(float(r_chain0), float(gamma_crit), float(gamma_esc), float(tol),
+                               float(ghost_mass), int(pert_cap))
+        self.h = C.c_void_p()
+        self._sys = system
+        _check(lib().tg_hybrid_create(ctx.h, C.byref(system), C.byref(cfg), C.byref(self.h)))
+
+    def begin(self):
+        _check(lib().tg_hybrid_begin(self.h))
+
+    def step(self, dt):
+        _check(lib().tg_hybrid_step(self.h, float(dt)))
+
+    def state(self):
+        import numpy as np
+        s = tg_hybrid_state()
+        _check(lib().tg_hybrid_state_get(self.h, C.byref(s), None, None, None))
+        n = s.n_members
+        ids = np.zeros(max(n, 1), np.int32)
+        x = np.zeros((max(n, 1), 3))
+        v = np.zeros((max(n, 1), 3))
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(lib().tg_hybrid_state_get(self.h, C.byref(s), p(ids), p(x), p(v)))
+        return {"active": bool(s.active), "members": ids[:n].copy(), "x": x[:n].copy(),
+                "v": v[:n].copy(), "n_perturbers": s.n_perturbers, "com": list(s.com),
+                "com_vel": list(s.com_vel), "m_chain": s.m_chain, "r_chain": s.r_chain,
+                "energy_error": s.energy_error, "steps": s.steps, "starts": s.starts,
+                "absorbed": s.absorbed, "escaped": s.escaped, "ended": s.ended}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tg_hybrid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _lib is not None:
+            self.close()
 
 
 class ARChain:

@@ -1,0 +1,520 @@
+// The hybrid step (Sec. 2) on the host: tree stars advanced by kick-drift-
+// kick steps on the GPU, the stars near the SMBH regularised in one chain
+// (AR-chain, host FP64), the two coupled through the perturbers (Eq. 2),
+// the chain particle with the correction of Eq. 3, and the membership
+// rules (Eq. 4, Eq. 5).  Every GPU stage is one of the library's calls;
+// this file holds the bookkeeping: which stars are members (ghosts in the
+// star arrays), the chain's centre of mass, and the order of the stages.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tg_internal.h"
+
+using namespace tg;
+
+struct tg_hybrid {
+  tg_ctx *c = nullptr;
+  tg_system sys{};
+  tg_hybrid_config cfg{};
+  double G = 1.0;
+  bool active = false;
+  // members: star index (-1 for the SMBH), coordinates relative to the
+  // centre of mass, masses (the stars' own, not the ghost masses)
+  std::vector<int32_t> star;
+  std::vector<double> x, v, m;
+  double R[3] = {0, 0, 0}, V[3] = {0, 0, 0}, M = 0.0;
+  double B = 0.0, ds = 0.0;
+  double a_com[3] = {0, 0, 0};
+  double r_chain = 0.0;
+  int32_t n_pert = 0;
+  double energy_error = 0.0;
+  int64_t steps = 0, starts = 0, absorbed = 0, escaped = 0, ended = 0;
+  // device buffers
+  uint8_t *d_excl = nullptr, *d_flag = nullptr;
+  int32_t *d_pidx = nullptr, *d_np = nullptr, *d_ids = nullptr, *d_sel = nullptr,
+          *d_nsel = nullptr;
+  double *d_mpos = nullptr, *d_mmass = nullptr, *d_com = nullptr, *d_macc = nullptr,
+         *d_px = nullptr, *d_pv = nullptr, *d_pm = nullptr, *d_rows = nullptr,
+         *d_vals = nullptr;
+};
+
+namespace {
+
+template <class T>
+hipError_t dalloc(T **p, int64_t n) {
+  return hipMalloc((void **)p, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+}
+
+tg_status to_dev(tg_hybrid *h, void *dst, const void *src, size_t bytes) {
+  if (!bytes) return TG_OK;
+  TG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->c->stream));
+  return TG_OK;
+}
+
+tg_status to_host(tg_hybrid *h, void *dst, const void *src, size_t bytes) {
+  if (!bytes) return TG_OK;
+  TG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->c->stream));
+  TG_HIP(hipStreamSynchronize(h->c->stream));
+  return TG_OK;
+}
+
+int nc(const tg_hybrid *h) { return (int)h->m.size(); }
+
+// Centre of mass from the members' global coordinates (X, W), then the
+// coordinates relative to it.
+void reform(tg_hybrid *h, const std::vector<double> &X, const std::vector<double> &W) {
+#pragma clang fp contract(off)
+  const int n = (int)h->m.size();
+  double M = 0.0, R[3] = {0, 0, 0}, V[3] = {0, 0, 0};
+  for (int i = 0; i < n; ++i) {
+    M += h->m[i];
+    for (int k = 0; k < 3; ++k) {
+      R[k] += h->m[i] * X[3 * i + k];
+      V[k] += h->m[i] * W[3 * i + k];
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    h->R[k] = R[k] / M;
+    h->V[k] = V[k] / M;
+  }
+  h->M = M;
+  h->x.assign(3 * n, 0.0);
+  h->v.assign(3 * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      h->x[3 * i + k] = X[3 * i + k] - h->R[k];
+      h->v[3 * i + k] = W[3 * i + k] - h->V[k];
+    }
+}
+
+// The members' global coordinates R + x, V + v.
+void globals(const tg_hybrid *h, std::vector<double> &X, std::vector<double> &W) {
+#pragma clang fp contract(off)
+  const int n = nc(h);
+  X.resize(3 * n);
+  W.resize(3 * n);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      X[3 * i + k] = h->R[k] + h->x[3 * i + k];
+      W[3 * i + k] = h->V[k] + h->v[3 * i + k];
+    }
+}
+
+double max_radius(const tg_hybrid *h) {
+#pragma clang fp contract(off)
+  double r2 = 0.0;
+  for (int i = 0; i < nc(h); ++i) {
+    const double *a = &h->x[3 * i];
+    r2 = std::max(r2, (a[0] * a[0] + a[1] * a[1]) + a[2] * a[2]);
+  }
+  return std::sqrt(r2);
+}
+
+// Write the members' global coordinates into the star arrays (ghosts) and
+// the SMBH's arrays; also the member positions and masses for the coupling.
+tg_status write_members(tg_hybrid *h) {
+  std::vector<double> X, W;
+  globals(h, X, W);
+  std::vector<int32_t> ids;
+  std::vector<double> px, pv;
+  for (int i = 0; i < nc(h); ++i) {
+    if (h->star[i] < 0) {
+      tg_status st;
+      if ((st = to_dev(h, h->sys.bh_pos, &X[3 * i], 3 * sizeof(double)))) return st;
+      if ((st = to_dev(h, h->sys.bh_vel, &W[3 * i], 3 * sizeof(double)))) return st;
+      continue;
+    }
+    ids.push_back(h->star[i]);
+    px.insert(px.end(), &X[3 * i], &X[3 * i] + 3);
+    pv.insert(pv.end(), &W[3 * i], &W[3 * i] + 3);
+  }
+  const int k = (int)ids.size();
+  tg_status st;
+  if ((st = to_dev(h, h->d_ids, ids.data(), sizeof(int32_t) * k))) return st;
+  if ((st = to_dev(h, h->d_rows, px.data(), sizeof(double) * 3 * k))) return st;
+  TG_HIP(launch_move_rows(h->c, h->sys.pos, h->d_rows, h->d_ids, k, true));
+  if ((st = to_dev(h, h->d_rows + 3 * kMaxChain, pv.data(), sizeof(double) * 3 * k))) return st;
+  TG_HIP(launch_move_rows(h->c, h->sys.vel, h->d_rows + 3 * kMaxChain, h->d_ids, k, true));
+  if ((st = to_dev(h, h->d_mpos, X.data(), sizeof(double) * X.size()))) return st;
+  if ((st = to_dev(h, h->d_mmass, h->m.data(), sizeof(double) * h->m.size()))) return st;
+  TG_HIP(hipStreamSynchronize(h->c->stream));
+  return TG_OK;
+}
+
+// Stars become ghosts (ghost = 1: mass times ghost_mass, excluded) or get
+// their mass back (ghost = 0).
+tg_status set_ghosts(tg_hybrid *h, const std::vector<int32_t> &ids,
+                     const std::vector<double> &mass, bool ghost) {
+  const int k = (int)ids.size();
+  if (!k) return TG_OK;
+  std::vector<double> val(k);
+  std::vector<uint8_t> f(k, ghost ? 1 : 0);
+  for (int i = 0; i < k; ++i) val[i] = ghost ? mass[i] * h->cfg.ghost_mass : mass[i];
+  tg_status st;
+  if ((st = to_dev(h, h->d_ids, ids.data(), sizeof(int32_t) * k))) return st;
+  if ((st = to_dev(h, h->d_vals, val.data(), sizeof(double) * k))) return st;
+  if ((st = to_dev(h, h->d_flag, f.data(), k))) return st;
+  TG_HIP(launch_set_rows(h->c, const_cast<double *>(h->sys.mass), h->d_excl, h->d_ids, h->d_vals,
+                         h->d_flag, k));
+  TG_HIP(hipStreamSynchronize(h->c->stream));
+  return TG_OK;
+}
+
+tg_chain chain_of(tg_hybrid *h) {
+  tg_chain ch{};
+  ch.pos = h->sys.pos;
+  ch.mass = h->sys.mass;
+  ch.n = h->sys.n;
+  ch.exclude = h->d_excl;
+  ch.member_pos = h->d_mpos;
+  ch.member_mass = h->d_mmass;
+  ch.nc = nc(h);
+  for (int k = 0; k < 3; ++k) ch.com[k] = h->R[k];
+  ch.m_chain = h->M;
+  ch.r_crit = std::min(h->r_chain, h->cfg.r_chain0);   // Eq. 2
+  ch.gamma_crit = h->cfg.gamma_crit;
+  ch.eps_pm = 0.0;
+  ch.pert_idx = h->d_pidx;
+  ch.pert_cap = h->cfg.pert_cap;
+  ch.n_pert = h->d_np;
+  return ch;
+}
+
+// Forces of the current state: the tree (without the SMBH while it is in
+// the chain) and the coupling with the chain.
+tg_status forces(tg_hybrid *h) {
+  tg_status st;
+  if (!h->active) {
+    if ((st = tg_forces(h->c, &h->sys, nullptr, nullptr))) return st;
+    return tg_sync(h->c, nullptr);
+  }
+  if ((st = write_members(h))) return st;
+  tg_system y = h->sys;
+  y.n_bh = 0;
+  if ((st = tg_forces(h->c, &y, nullptr, nullptr))) return st;
+  tg_chain ch = chain_of(h);
+  if ((st = tg_chain_forces(h->c, &ch, nullptr, nullptr, h->sys.acc, h->sys.pot, h->d_com,
+                            h->d_macc)))
+    return st;
+  if ((st = tg_sync(h->c, nullptr))) return st;
+  if ((st = to_host(h, h->a_com, h->d_com, 3 * sizeof(double)))) return st;
+  return to_host(h, &h->n_pert, h->d_np, sizeof(int32_t));
+}
+
+// The perturbers of the last coupling relative to the chain particle, at
+// the current time (first-order prediction with dt = 0).
+tg_status perturbers(tg_hybrid *h, std::vector<double> &px, std::vector<double> &pv,
+                     std::vector<double> &pm, std::vector<int32_t> *ids) {
+  const int np = std::min(h->n_pert, h->cfg.pert_cap);
+  px.assign(3 * np, 0.0);
+  pv.assign(3 * np, 0.0);
+  pm.assign(np, 0.0);
+  if (ids) ids->assign(np, 0);
+  if (!np) return TG_OK;
+  tg_chain ch = chain_of(h);
+  tg_status st;
+  if ((st = tg_predict_perturbers(h->c, &ch, h->sys.vel, h->V, 0.0, h->d_px, h->d_pv, h->d_pm)))
+    return st;
+  if ((st = to_host(h, px.data(), h->d_px, sizeof(double) * 3 * np))) return st;
+  if ((st = to_host(h, pv.data(), h->d_pv, sizeof(double) * 3 * np))) return st;
+  if ((st = to_host(h, pm.data(), h->d_pm, sizeof(double) * np))) return st;
+  if (ids && (st = to_host(h, ids->data(), h->d_pidx, sizeof(int32_t) * np))) return st;
+  return TG_OK;
+}
+
+// Global coordinates and masses of the listed stars.
+tg_status read_stars(tg_hybrid *h, const std::vector<int32_t> &ids, std::vector<double> &X,
+                     std::vector<double> &W, std::vector<double> &mass) {
+  const int k = (int)ids.size();
+  X.assign(3 * k, 0.0);
+  W.assign(3 * k, 0.0);
+  mass.assign(k, 0.0);
+  if (!k) return TG_OK;
+  tg_status st;
+  if ((st = to_dev(h, h->d_ids, ids.data(), sizeof(int32_t) * k))) return st;
+  TG_HIP(launch_move_rows(h->c, h->d_rows, h->sys.pos, h->d_ids, k, false));
+  if ((st = to_host(h, X.data(), h->d_rows, sizeof(double) * 3 * k))) return st;
+  TG_HIP(launch_move_rows(h->c, h->d_rows, h->sys.vel, h->d_ids, k, false));
+  if ((st = to_host(h, W.data(), h->d_rows, sizeof(double) * 3 * k))) return st;
+  for (int i = 0; i < k; ++i)
+    if ((st = to_host(h, &mass[i], h->sys.mass + ids[i], sizeof(double)))) return st;
+  return TG_OK;
+}
+
+tg_status ar_init(tg_hybrid *h) {
+  tg_archain s{};
+  s.n = nc(h);
+  s.x = h->x.data();
+  s.v = h->v.data();
+  s.m = h->m.data();
+  s.ds = 0.0;
+  tg_status st = tg_archain_init(&s, h->G);
+  if (st) return st;
+  h->B = s.B;
+  h->ds = s.ds;
+  h->r_chain = max_radius(h);
+  h->energy_error = 0.0;
+  return TG_OK;
+}
+
+// A chain starts when stars come within r_chain0 of the SMBH.
+tg_status maybe_start(tg_hybrid *h) {
+  double bp[3], bv[3], bm;
+  tg_status st;
+  if ((st = to_host(h, bp, h->sys.bh_pos, sizeof(bp)))) return st;
+  if ((st = tg_select_within(h->c, h->sys.pos, h->sys.n, nullptr, bp, h->cfg.r_chain0, h->d_sel,
+                             kMaxChain - 1, h->d_nsel)))
+    return st;
+  if ((st = tg_sync(h->c, nullptr))) return st;
+  int32_t k = 0;
+  if ((st = to_host(h, &k, h->d_nsel, sizeof(int32_t)))) return st;
+  if (k < 1) return TG_OK;
+  std::vector<int32_t> ids(k);
+  if ((st = to_host(h, ids.data(), h->d_sel, sizeof(int32_t) * k))) return st;
+  std::vector<double> X, W, mass;
+  if ((st = read_stars(h, ids, X, W, mass))) return st;
+  if ((st = to_host(h, bv, h->sys.bh_vel, sizeof(bv)))) return st;
+  if ((st = to_host(h, &bm, h->sys.bh_mass, sizeof(double)))) return st;
+  // member 0 is the SMBH, then the stars in ascending order
+  std::vector<double> GX(bp, bp + 3), GW(bv, bv + 3);
+  GX.insert(GX.end(), X.begin(), X.end());
+  GW.insert(GW.end(), W.begin(), W.end());
+  h->star.assign(1, -1);
+  h->star.insert(h->star.end(), ids.begin(), ids.end());
+  h->m.assign(1, bm);
+  h->m.insert(h->m.end(), mass.begin(), mass.end());
+  reform(h, GX, GW);
+  if ((st = ar_init(h))) return st;
+  if ((st = set_ghosts(h, ids, mass, true))) return st;
+  h->active = true;
+  ++h->starts;
+  return forces(h);
+}
+
+// Membership after a step: absorb, escape, or end the chain.
+tg_status membership(tg_hybrid *h) {
+  std::vector<double> px, pv, pm;
+  std::vector<int32_t> pids;
+  tg_status st;
+  if ((st = perturbers(h, px, pv, pm, &pids))) return st;
+  const int n = nc(h);
+  std::vector<uint8_t> massive(n, 0);
+  for (int i = 0; i < n; ++i) massive[i] = h->star[i] < 0 ? 1 : 0;
+  std::vector<int32_t> ab(std::max<size_t>(pids.size(), 1)), es(n);
+  tg_membership_in in{};
+  in.n = n;
+  in.x = h->x.data();
+  in.v = h->v.data();
+  in.m = h->m.data();
+  in.massive = massive.data();
+  in.designated = 0;
+  in.r_chain = h->r_chain;
+  in.r_chain0 = h->cfg.r_chain0;
+  in.gamma = h->cfg.gamma_esc;
+  in.np = (int32_t)pids.size();
+  in.px = px.data();
+  tg_membership_out out{};
+  out.absorb = ab.data();
+  out.escape = es.data();
+  if ((st = tg_chain_membership(&in, &out))) return st;
+  if (n - out.n_escape + out.n_absorb > kMaxChain && !out.terminate)
+    return fail(TG_ECAPACITY, "tg_hybrid_step: more than 256 chain members");
+  if (!out.terminate && out.n_absorb == 0 && out.n_escape == 0) return TG_OK;
+  std::vector<double> X, W;
+  globals(h, X, W);
+  std::vector<int32_t> back;
+  std::vector<double> back_m;
+  std::vector<bool> leaves(n, out.terminate != 0);
+  for (int e = 0; e < out.n_escape; ++e) leaves[es[e]] = true;
+  std::vector<int32_t> star;
+  std::vector<double> m, GX, GW;
+  for (int i = 0; i < n; ++i) {
+    if (leaves[i]) {
+      if (h->star[i] >= 0) {
+        back.push_back(h->star[i]);
+        back_m.push_back(h->m[i]);
+      }
+      continue;
+    }
+    star.push_back(h->star[i]);
+    m.push_back(h->m[i]);
+    GX.insert(GX.end(), &X[3 * i], &X[3 * i] + 3);
+    GW.insert(GW.end(), &W[3 * i], &W[3 * i] + 3);
+  }
+  // the members' global coordinates are already in the arrays
+  if ((st = write_members(h))) return st;
+  if ((st = set_ghosts(h, back, back_m, false))) return st;
+  h->escaped += (int64_t)back.size();
+  if (out.terminate) {
+    h->active = false;
+    h->star.clear();
+    h->x.clear();
+    h->v.clear();
+    h->m.clear();
+    h->n_pert = 0;
+    ++h->ended;
+    return forces(h);
+  }
+  std::vector<int32_t> join;
+  for (int a = 0; a < out.n_absorb; ++a) join.push_back(pids[ab[a]]);
+  std::vector<double> JX, JW, jm;
+  if ((st = read_stars(h, join, JX, JW, jm))) return st;
+  star.insert(star.end(), join.begin(), join.end());
+  m.insert(m.end(), jm.begin(), jm.end());
+  GX.insert(GX.end(), JX.begin(), JX.end());
+  GW.insert(GW.end(), JW.begin(), JW.end());
+  h->star = star;
+  h->m = m;
+  reform(h, GX, GW);
+  if ((st = ar_init(h))) return st;
+  if ((st = set_ghosts(h, join, jm, true))) return st;
+  h->absorbed += (int64_t)join.size();
+  return forces(h);
+}
+
+}  // namespace
+
+extern "C" {
+
+tg_status tg_hybrid_create(tg_ctx *c, const tg_system *y, const tg_hybrid_config *cfg,
+                           tg_hybrid **out) {
+  if (!c || !y || !cfg || !out) return fail(TG_EINVAL, "tg_hybrid_create: NULL argument");
+  *out = nullptr;
+  if (y->n_bh != 1 || y->n_sys != 1 || y->n < 1 || y->frozen)
+    return fail(TG_EINVAL, "tg_hybrid_create: one system, one SMBH, no frozen mask");
+  if (!(cfg->r_chain0 > 0.0) || !(cfg->gamma_crit > 0.0) || !(cfg->gamma_esc > 0.0) ||
+      !(cfg->tol > 0.0) || !(cfg->ghost_mass > 0.0 && cfg->ghost_mass < 1.0) ||
+      cfg->pert_cap < 1)
+    return fail(TG_EINVAL, "tg_hybrid_create: bad configuration");
+  tg_hybrid *h = new tg_hybrid();
+  h->c = c;
+  h->sys = *y;
+  h->cfg = *cfg;
+  h->G = c->cfg.G;
+  hipError_t a = hipSuccess;
+  auto A = [&](hipError_t r) { if (a == hipSuccess) a = r; };
+  A(dalloc(&h->d_excl, y->n));
+  A(dalloc(&h->d_flag, kMaxChain));
+  A(dalloc(&h->d_pidx, cfg->pert_cap));
+  A(dalloc(&h->d_np, 1));
+  A(dalloc(&h->d_ids, kMaxChain));
+  A(dalloc(&h->d_sel, kMaxChain));
+  A(dalloc(&h->d_nsel, 1));
+  A(dalloc(&h->d_mpos, 3 * kMaxChain));
+  A(dalloc(&h->d_mmass, kMaxChain));
+  A(dalloc(&h->d_com, 3));
+  A(dalloc(&h->d_macc, 3 * kMaxChain));
+  A(dalloc(&h->d_px, 3 * (int64_t)cfg->pert_cap));
+  A(dalloc(&h->d_pv, 3 * (int64_t)cfg->pert_cap));
+  A(dalloc(&h->d_pm, cfg->pert_cap));
+  A(dalloc(&h->d_rows, 6 * kMaxChain));
+  A(dalloc(&h->d_vals, kMaxChain));
+  if (a == hipSuccess) A(hipMemset(h->d_excl, 0, (size_t)y->n));
+  if (a == hipSuccess) A(hipDeviceSynchronize());
+  if (a != hipSuccess) {
+    tg_hybrid_destroy(h);
+    return hip_fail(a, "tg_hybrid_create");
+  }
+  *out = h;
+  return TG_OK;
+}
+
+tg_status tg_hybrid_begin(tg_hybrid *h) {
+  if (!h) return fail(TG_EINVAL, "tg_hybrid_begin: NULL");
+  tg_status st = forces(h);
+  if (st) return st;
+  return h->active ? TG_OK : maybe_start(h);
+}
+
+tg_status tg_hybrid_step(tg_hybrid *h, double dt) {
+#pragma clang fp contract(off)
+  if (!h) return fail(TG_EINVAL, "tg_hybrid_step: NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TG_EINVAL, "tg_hybrid_step: dt must be > 0");
+  tg_status st;
+  ++h->steps;
+  if (!h->active) {
+    if ((st = tg_step_kdk(h->c, &h->sys, dt))) return st;
+    if ((st = tg_sync(h->c, nullptr))) return st;
+    return maybe_start(h);
+  }
+  const int64_t n = h->sys.n;
+  // half kick of the stars and of the chain particle
+  if ((st = tg_kick(h->c, h->sys.vel, h->sys.acc, n, nullptr, nullptr, nullptr, dt, nullptr, 0)))
+    return st;
+  for (int k = 0; k < 3; ++k) h->V[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
+  // the perturbers at the start of the step, relative to the chain particle
+  std::vector<double> px, pv, pm;
+  if ((st = perturbers(h, px, pv, pm, nullptr))) return st;
+  // drift; the members move in the chain over the whole step
+  if ((st = tg_drift(h->c, h->sys.pos, h->sys.vel, n, dt))) return st;
+  for (int k = 0; k < 3; ++k) h->R[k] = h->R[k] + h->V[k] * dt;
+  tg_archain s{};
+  s.n = nc(h);
+  s.x = h->x.data();
+  s.v = h->v.data();
+  s.m = h->m.data();
+  s.t = 0.0;
+  s.B = h->B;
+  s.ds = h->ds;
+  tg_archain_perturbers P{};
+  P.np = (int32_t)pm.size();
+  P.x = px.data();
+  P.v = pv.data();
+  P.m = pm.data();
+  P.t0 = 0.0;
+  if ((st = tg_archain_advance(&s, h->G, dt, h->cfg.tol, P.np ? &P : nullptr, nullptr))) return st;
+  h->B = s.B;
+  h->ds = s.ds;
+  if ((st = tg_archain_energy(&s, h->G, &h->energy_error))) return st;
+  h->r_chain = max_radius(h);
+  // forces at the new positions, then the second half kick
+  if ((st = forces(h))) return st;
+  if ((st = tg_kick(h->c, h->sys.vel, h->sys.acc, n, nullptr, nullptr, nullptr, dt, nullptr, 0)))
+    return st;
+  for (int k = 0; k < 3; ++k) h->V[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
+  if ((st = write_members(h))) return st;
+  if ((st = membership(h))) return st;
+  return h->active ? TG_OK : maybe_start(h);
+}
+
+tg_status tg_hybrid_state_get(const tg_hybrid *h, tg_hybrid_state *st, int32_t *members_out,
+                              double *member_x, double *member_v) {
+  if (!h || !st) return fail(TG_EINVAL, "tg_hybrid_state_get: NULL");
+  st->active = h->active ? 1 : 0;
+  st->n_members = h->active ? nc(h) : 0;
+  st->n_perturbers = h->active ? h->n_pert : 0;
+  for (int k = 0; k < 3; ++k) {
+    st->com[k] = h->R[k];
+    st->com_vel[k] = h->V[k];
+  }
+  st->m_chain = h->M;
+  st->r_chain = h->r_chain;
+  st->energy_error = h->energy_error;
+  st->steps = h->steps;
+  st->starts = h->starts;
+  st->absorbed = h->absorbed;
+  st->escaped = h->escaped;
+  st->ended = h->ended;
+  if (h->active) {
+    if (members_out) std::copy(h->star.begin(), h->star.end(), members_out);
+    if (member_x) std::copy(h->x.begin(), h->x.end(), member_x);
+    if (member_v) std::copy(h->v.begin(), h->v.end(), member_v);
+  }
+  return TG_OK;
+}
+
+void tg_hybrid_destroy(tg_hybrid *h) {
+  if (!h) return;
+  void *ptrs[] = {h->d_excl, h->d_flag, h->d_pidx, h->d_np, h->d_ids, h->d_sel, h->d_nsel,
+                  h->d_mpos, h->d_mmass, h->d_com, h->d_macc, h->d_px, h->d_pv, h->d_pm,
+                  h->d_rows, h->d_vals};
+  if (h->c) (void)hipStreamSynchronize(h->c->stream);
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete h;
+}
+
+}  // extern "C"

@@ -324,6 +324,43 @@ hipError_t launch_add_host_vector(tg_ctx *c, double *out, const ChainVec &add, i
   return hipGetLastError();
 }
 
+// Rows of 3 doubles between a packed list and indexed rows of an array
+// (the hybrid driver's members and ghosts): to_rows != 0: dst[idx[r]] =
+// src[r], else dst[r] = src[idx[r]], for r < n.
+__global__ void k_move_rows(double *__restrict__ dst, const double *__restrict__ src,
+                            const int32_t *__restrict__ idx, int n, int to_rows) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const size_t a = 3 * (size_t)(to_rows ? idx[r] : r), b = 3 * (size_t)(to_rows ? r : idx[r]);
+    dst[a] = src[b]; dst[a + 1] = src[b + 1]; dst[a + 2] = src[b + 2];
+  }
+}
+
+// Per-row scalars and flags: mass[idx[r]] = val[r] and flag[idx[r]] = f[r].
+__global__ void k_set_rows(double *__restrict__ mass, uint8_t *__restrict__ flag,
+                           const int32_t *__restrict__ idx, const double *__restrict__ val,
+                           const uint8_t *__restrict__ f, int n) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    mass[idx[r]] = val[r];
+    flag[idx[r]] = f[r];
+  }
+}
+
+hipError_t launch_move_rows(tg_ctx *c, double *dst, const double *src, const int32_t *idx, int n,
+                            bool to_rows) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_move_rows, dim3((n + 255) / 256), dim3(256), 0, c->stream, dst, src, idx, n,
+                     to_rows ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_rows(tg_ctx *c, double *mass, uint8_t *flag, const int32_t *idx,
+                           const double *val, const uint8_t *f, int n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_rows, dim3((n + 255) / 256), dim3(256), 0, c->stream, mass, flag, idx,
+                     val, f, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx,
                                const int32_t *n_act, double *acc, double *pot,
                                double *com_acc, double *member_acc) {

@@ -322,6 +322,12 @@ hipError_t launch_chain_predict(tg_ctx *c, const tg_chain *ch, const double *vel
 constexpr int kMaxChains = 16;
 struct ChainVec { double v[3 * kMaxChains]; };
 hipError_t launch_add_host_vector(tg_ctx *c, double *out, const ChainVec &add, int n3);
+// hybrid driver: rows of 3 doubles to (to_rows) or from indexed rows, and
+// per-row masses and flags
+hipError_t launch_move_rows(tg_ctx *c, double *dst, const double *src, const int32_t *idx, int n,
+                            bool to_rows);
+hipError_t launch_set_rows(tg_ctx *c, double *mass, uint8_t *flag, const int32_t *idx,
+                           const double *val, const uint8_t *f, int n);
 hipError_t launch_chain_forces(tg_ctx *c, const tg_chain *ch, const int32_t *idx,
                                const int32_t *n_act, double *acc, double *pot,
                                double *com_acc, double *member_acc);
