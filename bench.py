@@ -16,8 +16,8 @@ FP64 path, forces/s, the errors (mixed vs FP64, both vs the direct sum), the
 walk kernel's roofline and the CPU oracle baseline are reported beside it,
 plus measurements selected by --extras (default all, none with --no-extra):
 the relative opening test (alpha = 1e-3) and the spline softening on the
-same step, the chain coupling on the same workload, a KDK energy check,
-block steps and batched realisations.
+same step, the chain coupling on the same workload, the hybrid step with
+one chain, a KDK energy check, block steps and batched realisations.
 """
 from __future__ import annotations
 
@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="relative,spline,chain,kdk,blocksteps,batch",
+    ap.add_argument("--extras", default="relative,spline,chain,hybrid,kdk,blocksteps,batch",
                     help="comma list of the extra measurements to run")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -499,6 +499,51 @@ def extra_chains(n_each=524288, reps=50):
     return out
 
 
+def extra_hybrid(steps=10, dt=1e-5):
+    """The hybrid step on a Dehnen gamma = 1.5 cusp of N = 1 048 576 stars
+    with one SMBH of 0.01 at rest at its centre (eps = 1e-3, theta = 0.5,
+    mixed path), r_chain0 = 0.01, gamma_crit = 1e-4, gamma_esc = 1.5; per
+    step against the plain KDK step of the same system."""
+    import numpy as np
+    import torch
+    from paper_1507_01009_amd import binding as B, ics
+    n = 1048576
+    pos, vel, m = ics.dehnen(n, 1.5, ics.SEED_BASE + 61)
+    w = ics.Workload("cusp_n%d_one_smbh" % n, pos, vel, m, 1e-3, 0.5, np.array([0, n]),
+                     np.zeros((1, 3)), np.zeros((1, 3)), np.array([0.01]), np.array([1e-3]),
+                     np.zeros(1, np.int32))
+    out = {"workload": w.name, "dt": dt, "steps": steps, "precision": "mixed"}
+    ctx = B.Context(n, precision=B.TG_MIXED)
+    d = DevState(ctx, w)
+    ctx.forces(d.sys)
+    ctx.step_kdk(d.sys, dt)
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step_kdk(d.sys, dt)
+    ctx.sync()
+    out["kdk_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / steps
+    ctx.close()
+    ctx = B.Context(n, precision=B.TG_MIXED)
+    d = DevState(ctx, w)
+    hy = B.Hybrid(ctx, d.sys, r_chain0=0.01)
+    hy.begin()
+    hy.step(dt)
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hy.step(dt)
+    ctx.sync()
+    out["hybrid_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / steps
+    s = hy.state()
+    out.update({"members": len(s["members"]), "perturbers": s["n_perturbers"],
+                "absorbed": s["absorbed"], "escaped": s["escaped"],
+                "archain_energy_error": s["energy_error"]})
+    hy.close()
+    ctx.close()
+    return out
+
+
 def extra_kdk_energy(steps=100):
     """Hernquist N = 131 072 + SMBH, dt = 1e-3: both precisions, energy error."""
     import torch
@@ -738,6 +783,10 @@ def main():
         out["chain"] = extra_chain(w)
         log("bench: several chains (two cusps, 1M stars)")
         out["chains"] = extra_chains()
+        torch.cuda.empty_cache()
+    if "hybrid" in ex:
+        log("bench: hybrid step (1M cusp, one SMBH)")
+        out["hybrid"] = extra_hybrid()
         torch.cuda.empty_cache()
     if "kdk" in ex:
         log("bench: KDK energy check (Hernquist 131k)")
