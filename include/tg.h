@@ -641,6 +641,15 @@ tg_status tg_hybrid_create(tg_ctx *ctx, const tg_system *sys, const tg_hybrid_co
  * once before the first step. */
 tg_status tg_hybrid_begin(tg_hybrid *h);
 tg_status tg_hybrid_step(tg_hybrid *h, double dt);
+/* One block substep (tg_blocks as for tg_step_block) of the same scheme:
+ * the chain particle sits on the finest level (kicked and drifted every
+ * substep, its force formed every substep), ghosts are frozen (never
+ * active), the members cross each substep in the AR-chain, forces go to the
+ * stars active at the new k only (tree without the SMBH, then the
+ * coupling); stars that leave the chain are put on the finest level and get
+ * their forces at once.  Without a chain: tg_step_block, then the chain
+ * start test. */
+tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *blocks);
 /* members_out (host [n_members] or NULL): star index of each member, -1 for
  * the SMBH; member x/v (host [n_members][3] or NULL): centre-of-mass frame. */
 tg_status tg_hybrid_state_get(const tg_hybrid *h, tg_hybrid_state *st, int32_t *members_out,

@@ -154,6 +154,7 @@ def lib():
             "tg_hybrid_create": (st, [P, P, P, P]),
             "tg_hybrid_begin": (st, [P]),
             "tg_hybrid_step": (st, [P, f64]),
+            "tg_hybrid_step_block": (st, [P, P]),
             "tg_hybrid_state_get": (st, [P, P, P, P, P]),
             "tg_hybrid_destroy": (None, [P]),
             "tg_set_softening": (st, [P, i32]),
@@ -192,7 +193,8 @@ EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_perturbers", "tg_chain_forces", "tg_chains_forces", "tg_select_within",
             "tg_predict_perturbers", "tg_archain_init", "tg_archain_advance",
             "tg_archain_energy", "tg_chain_membership", "tg_hybrid_create", "tg_hybrid_begin",
-            "tg_hybrid_step", "tg_hybrid_state_get", "tg_hybrid_destroy", "tg_forces",
+            "tg_hybrid_step", "tg_hybrid_step_block", "tg_hybrid_state_get", "tg_hybrid_destroy",
+            "tg_forces",
             "tg_step_kdk", "tg_step_dkd", "tg_step_block", "tg_step_blocks", "tg_graph_begin",
             "tg_graph_end", "tg_graph_launch", "tg_graph_destroy",
             "tg_get_tree", "tg_autotune", "tg_set_profiling",
@@ -618,6 +620,9 @@ class Hybrid:
 
     def step(self, dt):
         _check(lib().tg_hybrid_step(self.h, float(dt)))
+
+    def step_block(self, blocks):
+        _check(lib().tg_hybrid_step_block(self.h, C.byref(blocks)))
 
     def state(self):
         import numpy as np

@@ -375,7 +375,161 @@ tg_status membership(tg_hybrid *h) {
   return forces(h);
 }
 
+// Forces for a device list of stars (idx, n_act on the device; NULL: all):
+// the tree without the SMBH while it is a member, then the coupling for the
+// same list; the chain particle's force and the perturber list always.
+tg_status forces_list(tg_hybrid *h, const int32_t *idx, const int32_t *n_act) {
+  tg_status st;
+  if (!h->active) {
+    if ((st = tg_forces(h->c, &h->sys, idx, n_act))) return st;
+    return tg_sync(h->c, nullptr);
+  }
+  if ((st = write_members(h))) return st;
+  tg_system y = h->sys;
+  y.n_bh = 0;
+  if ((st = tg_forces(h->c, &y, idx, n_act))) return st;
+  tg_chain ch = chain_of(h);
+  if ((st = tg_chain_forces(h->c, &ch, idx, n_act, h->sys.acc, h->sys.pot, h->d_com,
+                            h->d_macc)))
+    return st;
+  if ((st = tg_sync(h->c, nullptr))) return st;
+  if ((st = to_host(h, h->a_com, h->d_com, 3 * sizeof(double)))) return st;
+  return to_host(h, &h->n_pert, h->d_np, sizeof(int32_t));
+}
+
+// Block substeps: stars that return to the tree (escaped, or all members of
+// a chain that ends) go to the finest level, which is active at every
+// substep, and get their forces now; the chain particle's force is formed
+// again for the new membership.
+tg_status returned_stars(tg_hybrid *h, const tg_blocks *b, const std::vector<int32_t> &back) {
+  const int k = (int)back.size();
+  std::vector<uint8_t> lv(k, (uint8_t)(b->nlev - 1));
+  tg_status st;
+  for (int i = 0; i < k; ++i)
+    if ((st = to_dev(h, b->level + back[i], &lv[i], 1))) return st;
+  if ((st = to_dev(h, h->d_sel, back.data(), sizeof(int32_t) * k))) return st;
+  if ((st = to_dev(h, h->d_nsel, &k, sizeof(int32_t)))) return st;
+  return forces_list(h, h->d_sel, h->d_nsel);
+}
+
+tg_status membership_block(tg_hybrid *h, const tg_blocks *b) {
+  std::vector<double> px, pv, pm;
+  std::vector<int32_t> pids;
+  tg_status st;
+  if ((st = perturbers(h, px, pv, pm, &pids))) return st;
+  const int n = nc(h);
+  std::vector<uint8_t> massive(n, 0);
+  for (int i = 0; i < n; ++i) massive[i] = h->star[i] < 0 ? 1 : 0;
+  std::vector<int32_t> ab(std::max<size_t>(pids.size(), 1)), es(n);
+  tg_membership_in in{};
+  in.n = n;
+  in.x = h->x.data();
+  in.v = h->v.data();
+  in.m = h->m.data();
+  in.massive = massive.data();
+  in.designated = 0;
+  in.r_chain = h->r_chain;
+  in.r_chain0 = h->cfg.r_chain0;
+  in.gamma = h->cfg.gamma_esc;
+  in.np = (int32_t)pids.size();
+  in.px = px.data();
+  tg_membership_out out{};
+  out.absorb = ab.data();
+  out.escape = es.data();
+  if ((st = tg_chain_membership(&in, &out))) return st;
+  if (!out.terminate && out.n_absorb == 0 && out.n_escape == 0) return TG_OK;
+  if (n - out.n_escape + out.n_absorb > kMaxChain && !out.terminate)
+    return fail(TG_ECAPACITY, "tg_hybrid_step_block: more than 256 chain members");
+  std::vector<double> X, W;
+  globals(h, X, W);
+  std::vector<bool> leaves(n, out.terminate != 0);
+  for (int e = 0; e < out.n_escape; ++e) leaves[es[e]] = true;
+  std::vector<int32_t> back, star;
+  std::vector<double> back_m, m, GX, GW;
+  for (int i = 0; i < n; ++i) {
+    if (leaves[i]) {
+      if (h->star[i] >= 0) {
+        back.push_back(h->star[i]);
+        back_m.push_back(h->m[i]);
+      }
+      continue;
+    }
+    star.push_back(h->star[i]);
+    m.push_back(h->m[i]);
+    GX.insert(GX.end(), &X[3 * i], &X[3 * i] + 3);
+    GW.insert(GW.end(), &W[3 * i], &W[3 * i] + 3);
+  }
+  if ((st = write_members(h))) return st;
+  if ((st = set_ghosts(h, back, back_m, false))) return st;
+  h->escaped += (int64_t)back.size();
+  if (out.terminate) {
+    h->active = false;
+    h->star.clear();
+    h->x.clear();
+    h->v.clear();
+    h->m.clear();
+    h->n_pert = 0;
+    ++h->ended;
+    return returned_stars(h, b, back);
+  }
+  std::vector<int32_t> join;
+  for (int a = 0; a < out.n_absorb; ++a) join.push_back(pids[ab[a]]);
+  std::vector<double> JX, JW, jm;
+  if ((st = read_stars(h, join, JX, JW, jm))) return st;
+  star.insert(star.end(), join.begin(), join.end());
+  m.insert(m.end(), jm.begin(), jm.end());
+  GX.insert(GX.end(), JX.begin(), JX.end());
+  GW.insert(GW.end(), JW.begin(), JW.end());
+  h->star = star;
+  h->m = m;
+  reform(h, GX, GW);
+  if ((st = ar_init(h))) return st;
+  if ((st = set_ghosts(h, join, jm, true))) return st;
+  h->absorbed += (int64_t)join.size();
+  return returned_stars(h, b, back);
+}
+
+// A chain starting inside block substeps: as maybe_start, then only the
+// chain particle's force (no star gets new forces).
+tg_status maybe_start_block(tg_hybrid *h, const tg_blocks *b) {
+  (void)b;
+  const bool was = h->active;
+  double bp[3], bv[3], bm;
+  tg_status st;
+  if ((st = to_host(h, bp, h->sys.bh_pos, sizeof(bp)))) return st;
+  if ((st = tg_select_within(h->c, h->sys.pos, h->sys.n, nullptr, bp, h->cfg.r_chain0, h->d_sel,
+                             kMaxChain - 1, h->d_nsel)))
+    return st;
+  if ((st = tg_sync(h->c, nullptr))) return st;
+  int32_t k = 0;
+  if ((st = to_host(h, &k, h->d_nsel, sizeof(int32_t)))) return st;
+  if (k < 1 || was) return TG_OK;
+  std::vector<int32_t> ids(k);
+  if ((st = to_host(h, ids.data(), h->d_sel, sizeof(int32_t) * k))) return st;
+  std::vector<double> X, W, mass;
+  if ((st = read_stars(h, ids, X, W, mass))) return st;
+  if ((st = to_host(h, bv, h->sys.bh_vel, sizeof(bv)))) return st;
+  if ((st = to_host(h, &bm, h->sys.bh_mass, sizeof(double)))) return st;
+  std::vector<double> GX(bp, bp + 3), GW(bv, bv + 3);
+  GX.insert(GX.end(), X.begin(), X.end());
+  GW.insert(GW.end(), W.begin(), W.end());
+  h->star.assign(1, -1);
+  h->star.insert(h->star.end(), ids.begin(), ids.end());
+  h->m.assign(1, bm);
+  h->m.insert(h->m.end(), mass.begin(), mass.end());
+  reform(h, GX, GW);
+  if ((st = ar_init(h))) return st;
+  if ((st = set_ghosts(h, ids, mass, true))) return st;
+  h->active = true;
+  ++h->starts;
+  const int32_t zero = 0;
+  if ((st = to_dev(h, h->d_nsel, &zero, sizeof(int32_t)))) return st;
+  return forces_list(h, h->d_sel, h->d_nsel);
+}
+
 }  // namespace
+
+extern "C" {}  // namespace
 
 extern "C" {
 
@@ -414,6 +568,7 @@ tg_status tg_hybrid_create(tg_ctx *c, const tg_system *y, const tg_hybrid_config
   A(dalloc(&h->d_vals, kMaxChain));
   if (a == hipSuccess) A(hipMemset(h->d_excl, 0, (size_t)y->n));
   if (a == hipSuccess) A(hipDeviceSynchronize());
+  h->sys.frozen = h->d_excl;   // ghosts are held still in block substeps
   if (a != hipSuccess) {
     tg_hybrid_destroy(h);
     return hip_fail(a, "tg_hybrid_create");
@@ -478,6 +633,55 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) {
   if ((st = write_members(h))) return st;
   if ((st = membership(h))) return st;
   return h->active ? TG_OK : maybe_start(h);
+}
+
+tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) {
+#pragma clang fp contract(off)
+  if (!h || !b) return fail(TG_EINVAL, "tg_hybrid_step_block: NULL");
+  tg_status st;
+  ++h->steps;
+  if (!h->active) {
+    if ((st = tg_step_block(h->c, &h->sys, b))) return st;
+    if ((st = tg_sync(h->c, nullptr))) return st;
+    return maybe_start_block(h, b);
+  }
+  const double dt = std::ldexp(b->dt_max, -(b->nlev - 1));
+  int64_t k0 = 0;
+  if ((st = to_host(h, &k0, b->k, sizeof(int64_t)))) return st;
+  if ((st = block_stars_kick(h->c, &h->sys, b))) return st;
+  // the chain particle sits on the finest level: closing (not at k = 0)
+  // and opening half kicks with the force of the last substep
+  if (k0 != 0)
+    for (int k = 0; k < 3; ++k) h->V[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
+  for (int k = 0; k < 3; ++k) h->V[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
+  std::vector<double> px, pv, pm;
+  if ((st = perturbers(h, px, pv, pm, nullptr))) return st;
+  if ((st = block_stars_drift(h->c, &h->sys, b))) return st;
+  for (int k = 0; k < 3; ++k) h->R[k] = h->R[k] + h->V[k] * dt;
+  tg_archain s{};
+  s.n = nc(h);
+  s.x = h->x.data();
+  s.v = h->v.data();
+  s.m = h->m.data();
+  s.t = 0.0;
+  s.B = h->B;
+  s.ds = h->ds;
+  tg_archain_perturbers P{};
+  P.np = (int32_t)pm.size();
+  P.x = px.data();
+  P.v = pv.data();
+  P.m = pm.data();
+  P.t0 = 0.0;
+  if ((st = tg_archain_advance(&s, h->G, dt, h->cfg.tol, P.np ? &P : nullptr, nullptr))) return st;
+  h->B = s.B;
+  h->ds = s.ds;
+  if ((st = tg_archain_energy(&s, h->G, &h->energy_error))) return st;
+  h->r_chain = max_radius(h);
+  // forces for the stars active at the new k, and the chain particle's
+  if ((st = forces_list(h, b->active_idx, b->n_active))) return st;
+  if ((st = membership_block(h, b))) return st;
+  if (h->active) return write_members(h);
+  return maybe_start_block(h, b);
 }
 
 tg_status tg_hybrid_state_get(const tg_hybrid *h, tg_hybrid_state *st, int32_t *members_out,

@@ -317,6 +317,10 @@ hipError_t launch_chain_select(tg_ctx *c, const double *pos, const double *mass,
 hipError_t launch_chain_predict(tg_ctx *c, const tg_chain *ch, const double *vel, double dt,
                                 const double rp[3], const double v[3], double *out_pos,
                                 double *out_vel, double *out_mass);
+// the stars' part of a block substep in two stages (tg_runtime.hip)
+tg_status block_stars_kick(tg_ctx *c, const tg_system *y, const tg_blocks *b);
+tg_status block_stars_drift(tg_ctx *c, const tg_system *y, const tg_blocks *b);
+
 // several chains (tg_chains_forces): at most kMaxChains, the chain
 // particles' mutual forces added from the host
 constexpr int kMaxChains = 16;

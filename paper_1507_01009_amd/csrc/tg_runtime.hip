@@ -1034,6 +1034,50 @@ tg_status tg_step_block(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
   return forces_impl(c, y, b->active_idx, b->n_active, b->k, b->rebuild_every);
 }
 
+}  // extern "C"
+
+namespace tg {
+
+// The stars' part of a block substep, in two stages around whatever the
+// caller moves with them (the hybrid driver's chain particle): first the
+// active set at k, the closing half kicks (not at k = 0), new levels and
+// the opening half kicks; then the drift of every star that is not frozen,
+// k += 1 and the active set at the new k.  The same launches as
+// tg_step_block's, without the SMBHs and the forces.
+tg_status block_stars_kick(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
+  tg_status st = check_system(y, "block substep");
+  if (st != TG_OK) return st;
+  if (!b || !b->level || !b->tau4eps2 || !b->active_idx || !b->n_active || !b->k)
+    return fail(TG_EINVAL, "block substep: block arrays missing");
+  if (b->nlev < 1 || b->nlev > 30 || !(b->dt_max > 0.0))
+    return fail(TG_EINVAL, "block substep: bad levels");
+  if ((st = active_set_impl(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active,
+                             y->frozen)))
+    return st;
+  if ((st = kick_impl(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level,
+                      b->dt_max, b->k, 1, y->frozen)))
+    return st;
+  if ((st = tg_levels_v(c, y->acc, b->tau2eps2v ? y->vel : nullptr, b->tau4eps2,
+                        b->tau2eps2v, y->n, b->active_idx, b->n_active, b->dt_max, b->nlev,
+                        b->k, b->level)))
+    return st;
+  return kick_impl(c, y->vel, y->acc, y->n, b->active_idx, b->n_active, b->level, b->dt_max,
+                   nullptr, 0, y->frozen);
+}
+
+tg_status block_stars_drift(tg_ctx *c, const tg_system *y, const tg_blocks *b) {
+  const double dt_min = std::ldexp(b->dt_max, -(b->nlev - 1));
+  tg_status st;
+  if ((st = drift_impl(c, y->pos, y->vel, y->n, dt_min, y->frozen))) return st;
+  TG_HIP(launch_counter_add(c, b->k, 1));
+  return active_set_impl(c, b->level, y->n, b->nlev, b->k, 0, b->active_idx, b->n_active,
+                         y->frozen);
+}
+
+}  // namespace tg
+
+extern "C" {
+
 // A substep in which no star is active at its start or at its end: the
 // SMBHs' kicks and drift (k advances, the active count becomes 0), the
 // stars' drift and the SMBH sums.  These are exactly the launches of
