@@ -572,7 +572,8 @@ def extra_hybrid(steps=10, dt=1e-5):
 
 
 def extra_kdk_energy(steps=100):
-    """Hernquist N = 131 072 + SMBH, dt = 1e-3: both precisions, energy error."""
+    """Hernquist N = 131 072 + SMBH, dt = 1e-3: both precisions, energy error,
+    and the step graph-replayed."""
     import torch
     from paper_1507_01009_amd import binding as B, ics
     w = ics.hernquist_c2()
@@ -590,7 +591,10 @@ def extra_kdk_energy(steps=100):
         st.ctx.sync()
         e1 = st.d.energy()
         out[name] = {"ms_per_step": 1e3 * (t1 - t0) / steps,
-                     "rel_energy_error": abs(e1 - e0) / abs(e0)}
+                     "rel_energy_error": abs(e1 - e0) / abs(e0),
+                     # the same step captured once and replayed (after the
+                     # energy check; launch overheads leave the timing)
+                     "graph_ms_per_step": graph_ms(st.ctx, st.step, steps)}
         st.ctx.close()
     return out
 
