@@ -538,7 +538,8 @@ def extra_hybrid(steps=10, dt=1e-5):
     s = hy.state()
     out.update({"members": len(s["members"]), "perturbers": s["n_perturbers"],
                 "absorbed": s["absorbed"], "escaped": s["escaped"],
-                "archain_energy_error": s["energy_error"]})
+                "archain_energy_error": s["energy_error"],
+                "archain_share_of_step_time": s["archain_seconds"] / s["step_seconds"]})
     hy.close()
     ctx.close()
     # block substeps of the same system: 8 levels, dt_max = 2^-6, 32 substeps
@@ -565,6 +566,7 @@ def extra_hybrid(steps=10, dt=1e-5):
     out["block_ms_per_substep"] = 1e3 * (time.perf_counter() - t0) / 32
     s = hy.state()
     out["block_members"] = len(s["members"])
+    out["block_archain_share_of_step_time"] = s["archain_seconds"] / s["step_seconds"]
     out["block_level_histogram"] = np.bincount(level.cpu().numpy(), minlength=8).tolist()
     hy.close()
     ctx.close()

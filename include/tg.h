@@ -633,6 +633,8 @@ typedef struct {
   double m_chain, r_chain;    /* mass; largest member distance from the centre */
   double energy_error;        /* the AR-chain's bookkeeping error */
   int64_t steps, starts, absorbed, escaped, ended;
+  double archain_seconds;     /* host wall time inside the AR-chain, all steps */
+  double step_seconds;        /* host wall time inside the step calls, all steps */
 } tg_hybrid_state;
 
 tg_status tg_hybrid_create(tg_ctx *ctx, const tg_system *sys, const tg_hybrid_config *cfg,

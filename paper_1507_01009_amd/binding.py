@@ -92,7 +92,8 @@ class tg_hybrid_state(C.Structure):
                 ("com", C.c_double * 3), ("com_vel", C.c_double * 3), ("m_chain", C.c_double),
                 ("r_chain", C.c_double), ("energy_error", C.c_double), ("steps", C.c_int64),
                 ("starts", C.c_int64), ("absorbed", C.c_int64), ("escaped", C.c_int64),
-                ("ended", C.c_int64)]
+                ("ended", C.c_int64), ("archain_seconds", C.c_double),
+                ("step_seconds", C.c_double)]
 
 
 class tg_archain(C.Structure):
@@ -638,7 +639,8 @@ class Hybrid:
                 "v": v[:n].copy(), "n_perturbers": s.n_perturbers, "com": list(s.com),
                 "com_vel": list(s.com_vel), "m_chain": s.m_chain, "r_chain": s.r_chain,
                 "energy_error": s.energy_error, "steps": s.steps, "starts": s.starts,
-                "absorbed": s.absorbed, "escaped": s.escaped, "ended": s.ended}
+                "absorbed": s.absorbed, "escaped": s.escaped, "ended": s.ended,
+                "archain_seconds": s.archain_seconds, "step_seconds": s.step_seconds}
 
     def close(self):
         if getattr(self, "h", None):

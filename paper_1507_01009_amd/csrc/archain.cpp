@@ -25,8 +25,10 @@
 // centre of mass, not chain vectors (see the design notes).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "tg_internal.h"
@@ -142,10 +144,25 @@ Y leapfrog(const Chain &c, const Y &y0, double H, int nsub, std::vector<double> 
 constexpr int kCols = 10;
 constexpr int kSeq[kCols] = {2, 4, 6, 8, 10, 12, 14, 16, 20, 24};
 
+// Host threads for the extrapolation columns: one (no threads) for small
+// chains, where starting threads costs more than a column; otherwise up to
+// six, fewer with TG_ARCHAIN_THREADS.  The first batch holds the columns the
+// previous step of the same call converged with (at least three, which the
+// first convergence test needs), so the batch's longest column sets the time.
+int column_threads(const Chain &c) {
+  static const int hw = [] {
+    const char *e = std::getenv("TG_ARCHAIN_THREADS");
+    int t = e ? std::atoi(e) : (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(t, 6));
+  }();
+  const long pairs = (long)c.n * (c.n + c.np);
+  return pairs < 4096 ? 1 : hw;
+}
+
 // One extrapolated step of fictitious length H.  Returns the column at which
 // it converged (or -1) and the result in out.
 int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, std::vector<double> &a,
-            std::vector<double> &f) {
+            std::vector<double> &f, int first = 3) {
   const int n = c.n, dim = 6 * n + 2;
   std::vector<std::vector<double>> T(kCols, std::vector<double>(dim));
   // error scales: position and velocity magnitudes, the step's time, |B|
@@ -154,9 +171,33 @@ int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, std::vect
     xs = std::max(xs, std::fabs(y0.d[i]));
     vs = std::max(vs, std::fabs(y0.d[3 * n + i]));
   }
+  // The columns' leapfrogs are independent: with a large chain they are
+  // computed a batch at a time on host threads (each with its own scratch),
+  // then extrapolated in order exactly as one at a time.
+  const int par = column_threads(c);
+  std::vector<Y> col(kCols);
+  int ready = 0;
   for (int k = 0; k < kCols; ++k) {
-    Y yk = leapfrog(c, y0, H, kSeq[k], a, f);
-    T[k] = yk.d;
+    if (k == ready) {
+      // first the columns the last step needed (at least the three of the
+      // first convergence test), then pairs
+      const int want = k == 0 ? std::max(3, first) : 2;
+      const int hi = std::min(kCols, k + std::min(par, want));
+      if (hi - k > 1) {
+        std::vector<std::thread> th;
+        for (int q = k + 1; q < hi; ++q)
+          th.emplace_back([&, q] {
+            std::vector<double> aq(3 * n), fq(3 * n);
+            col[q] = leapfrog(c, y0, H, kSeq[q], aq, fq);
+          });
+        col[k] = leapfrog(c, y0, H, kSeq[k], a, f);
+        for (auto &t : th) t.join();
+      } else {
+        col[k] = leapfrog(c, y0, H, kSeq[k], a, f);
+      }
+      ready = hi;
+    }
+    T[k] = col[k].d;
     for (int j = k - 1; j >= 0; --j) {
       const double r = (double)kSeq[k] / kSeq[j];
       const double den = r * r - 1.0;
@@ -243,8 +284,10 @@ tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
   int64_t steps = 0;
   double H = s->ds;
   Y out;
+  int hint = 3;   // columns the last extrapolated step converged with
   while (y.t(n) < t_end) {
-    int col = bs_step(c, y, H, tol, out, a, f);
+    int col = bs_step(c, y, H, tol, out, a, f, hint);
+    if (col >= 0) hint = col + 1;
     if (col < 0) {
       H *= 0.5;
       if (H < 1e-300 || ++steps > 100000000) return fail(TG_EINTERNAL, "tg_archain_advance: step underflow");
@@ -260,7 +303,7 @@ tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
       for (int it = 0; it < 100 && !done; ++it) {
         const double hc = ha + (hb - ha) * (t_end - ta) / (tb - ta);
         Y yc;
-        if (bs_step(c, y, hc, tol, yc, a, f) < 0) {
+        if (bs_step(c, y, hc, tol, yc, a, f, hint) < 0) {
           H = 0.5 * hc;
           retry = true;
           break;

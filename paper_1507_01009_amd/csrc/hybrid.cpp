@@ -6,6 +6,7 @@
 // this file holds the bookkeeping: which stars are members (ghosts in the
 // star arrays), the chain's centre of mass, and the order of the stages.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -32,6 +33,7 @@ struct tg_hybrid {
   int32_t n_pert = 0;
   double energy_error = 0.0;
   int64_t steps = 0, starts = 0, absorbed = 0, escaped = 0, ended = 0;
+  double ar_s = 0.0, step_s = 0.0;   // host wall time: AR-chain, whole steps
   // device buffers
   uint8_t *d_excl = nullptr, *d_flag = nullptr;
   int32_t *d_pidx = nullptr, *d_np = nullptr, *d_ids = nullptr, *d_sel = nullptr,
@@ -42,6 +44,19 @@ struct tg_hybrid {
 };
 
 namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// Adds the wall time of a scope to an accumulator.
+struct Timer {
+  double &acc;
+  double t0;
+  explicit Timer(double &a) : acc(a), t0(now_s()) {}
+  ~Timer() { acc += now_s() - t0; }
+};
 
 template <class T>
 hipError_t dalloc(T **p, int64_t n) {
@@ -587,6 +602,7 @@ tg_status tg_hybrid_begin(tg_hybrid *h) {
 tg_status tg_hybrid_step(tg_hybrid *h, double dt) {
 #pragma clang fp contract(off)
   if (!h) return fail(TG_EINVAL, "tg_hybrid_step: NULL");
+  Timer whole(h->step_s);
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TG_EINVAL, "tg_hybrid_step: dt must be > 0");
   tg_status st;
   ++h->steps;
@@ -620,7 +636,11 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) {
   P.v = pv.data();
   P.m = pm.data();
   P.t0 = 0.0;
-  if ((st = tg_archain_advance(&s, h->G, dt, h->cfg.tol, P.np ? &P : nullptr, nullptr))) return st;
+  {
+    Timer tm(h->ar_s);
+    st = tg_archain_advance(&s, h->G, dt, h->cfg.tol, P.np ? &P : nullptr, nullptr);
+  }
+  if (st) return st;
   h->B = s.B;
   h->ds = s.ds;
   if ((st = tg_archain_energy(&s, h->G, &h->energy_error))) return st;
@@ -638,6 +658,7 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) {
 tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) {
 #pragma clang fp contract(off)
   if (!h || !b) return fail(TG_EINVAL, "tg_hybrid_step_block: NULL");
+  Timer whole(h->step_s);
   tg_status st;
   ++h->steps;
   if (!h->active) {
@@ -672,7 +693,11 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) {
   P.v = pv.data();
   P.m = pm.data();
   P.t0 = 0.0;
-  if ((st = tg_archain_advance(&s, h->G, dt, h->cfg.tol, P.np ? &P : nullptr, nullptr))) return st;
+  {
+    Timer tm(h->ar_s);
+    st = tg_archain_advance(&s, h->G, dt, h->cfg.tol, P.np ? &P : nullptr, nullptr);
+  }
+  if (st) return st;
   h->B = s.B;
   h->ds = s.ds;
   if ((st = tg_archain_energy(&s, h->G, &h->energy_error))) return st;
@@ -702,6 +727,8 @@ tg_status tg_hybrid_state_get(const tg_hybrid *h, tg_hybrid_state *st, int32_t *
   st->absorbed = h->absorbed;
   st->escaped = h->escaped;
   st->ended = h->ended;
+  st->archain_seconds = h->ar_s;
+  st->step_seconds = h->step_s;
   if (h->active) {
     if (members_out) std::copy(h->star.begin(), h->star.end(), members_out);
     if (member_x) std::copy(h->x.begin(), h->x.end(), member_x);
