@@ -605,7 +605,9 @@ const char *tg_version(void);
  *    with the perturbers of the last coupling, predicted to first order
  *    from the start of the step (tg_predict_perturbers, dt = 0);
  *  - forces after the drift: tg_forces without the SMBH (it is in the
- *    chain), then tg_chain_forces;
+ *    chain) with the ghosts at R + their offsets from the start of the
+ *    step, queued on the GPU while the AR-chain advances on the host; then
+ *    tg_chain_forces with the advanced members;
  *  - after the step tg_chain_membership updates the members (absorbed stars
  *    become ghosts, escaped ones get their mass and global coordinates
  *    back; a chain that ends returns everything), the centre of mass is

@@ -20,10 +20,12 @@ It composes the oracle's own pieces in the order of the hybrid recipe
 * a step: half kick of every star and of the chain particle (its force from
   the coupling, Eq. 3 included); the perturbers of the last coupling taken
   relative to the chain particle; drift of every star and of the chain
-  particle; the members over the whole step with those perturbers moving on
-  straight lines (their tidal part, the mean force removed), here by a
-  high-order Runge-Kutta integration (scipy DOP853), not the regularised
-  chain; ghosts rewritten; tree forces without the SMBH, then the coupling;
+  particle; tree forces without the SMBH, with the ghosts carried by the
+  chain particle (R plus the members' offsets from the start of the step);
+  the members over the whole step with those perturbers moving on straight
+  lines (their tidal part, the mean force removed), here by a high-order
+  Runge-Kutta integration (scipy DOP853), not the regularised chain; ghosts
+  rewritten; the coupling with the members' new positions;
   second half kick; ghosts rewritten; membership (Eq. 4, Eq. 5); after a
   change the centre of mass is re-formed and the forces evaluated again; a
   chain that ends returns every member, and a new one may start.
@@ -210,6 +212,13 @@ class Hybrid:
         px, pv, pm = self._perturbers()
         oracle.drift(st.pos, st.vel, dt)
         self.R = self.R + self.V * dt
+        # tree forces with the ghosts carried by the chain particle (R plus
+        # the members' offsets from the start of the step)
+        self._write()
+        ev = oracle.tree_forces(st.pos, st.mass, st.eps, st.theta, st.leaf_size, st.group_size,
+                                softening=st.softening)
+        st.acc[:] = ev.acc
+        st.pot[:] = ev.pot
         n = self.m.size
         sol = solve_ivp(_members_rhs(self.m, px, pv, pm, self.G), (0.0, dt),
                         np.concatenate([self.x.ravel(), self.v.ravel()]), method="DOP853",
@@ -217,7 +226,17 @@ class Hybrid:
         self.x = sol.y[:3 * n, -1].reshape(n, 3)
         self.v = sol.y[3 * n:, -1].reshape(n, 3)
         self.r_chain = self._radius()
-        self.forces()
+        # the coupling with the members' new positions
+        self._write()
+        X, _ = self._globals()
+        r_crit = min(self.r_chain, self.r_chain0)
+        self.pert = ochain.perturbers(st.pos, st.mass, self.R, self.M, r_crit, self.gamma_crit,
+                                      self.excl)
+        a, p, ac, _ = ochain.coupling(st.pos, st.mass, np.arange(st.pos.shape[0]), self.R,
+                                      self.M, X, self.m, self.pert, 0.0, self.excl, self.G)
+        st.acc += a
+        st.pot += p
+        self.a_com = ac
         oracle.kick(st.vel, st.acc, dt)
         self.V = self.V + self.a_com * (0.5 * dt)
         self._write()

@@ -219,6 +219,21 @@ tg_status forces(tg_hybrid *h) {
   return to_host(h, &h->n_pert, h->d_np, sizeof(int32_t));
 }
 
+// The coupling alone (the tree forces of the same positions are queued
+// already): members written, chain forces added, the chain particle's force
+// and the perturber count read back.
+tg_status coupling(tg_hybrid *h) {
+  tg_status st;
+  if ((st = write_members(h))) return st;
+  tg_chain ch = chain_of(h);
+  if ((st = tg_chain_forces(h->c, &ch, nullptr, nullptr, h->sys.acc, h->sys.pot, h->d_com,
+                            h->d_macc)))
+    return st;
+  if ((st = tg_sync(h->c, nullptr))) return st;
+  if ((st = to_host(h, h->a_com, h->d_com, 3 * sizeof(double)))) return st;
+  return to_host(h, &h->n_pert, h->d_np, sizeof(int32_t));
+}
+
 // The perturbers of the last coupling relative to the chain particle, at
 // the current time (first-order prediction with dt = 0).
 tg_status perturbers(tg_hybrid *h, std::vector<double> &px, std::vector<double> &pv,
@@ -622,6 +637,15 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) {
   // drift; the members move in the chain over the whole step
   if ((st = tg_drift(h->c, h->sys.pos, h->sys.vel, n, dt))) return st;
   for (int k = 0; k < 3; ++k) h->R[k] = h->R[k] + h->V[k] * dt;
+  // the tree sees the ghosts where the chain particle has carried them (R
+  // plus the members' offsets from the start of the step), so its forces
+  // run on the GPU while the chain advances on the host
+  if ((st = write_members(h))) return st;
+  {
+    tg_system y = h->sys;
+    y.n_bh = 0;
+    if ((st = tg_forces(h->c, &y, nullptr, nullptr))) return st;
+  }
   tg_archain s{};
   s.n = nc(h);
   s.x = h->x.data();
@@ -645,8 +669,8 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) {
   h->ds = s.ds;
   if ((st = tg_archain_energy(&s, h->G, &h->energy_error))) return st;
   h->r_chain = max_radius(h);
-  // forces at the new positions, then the second half kick
-  if ((st = forces(h))) return st;
+  // the coupling with the members' new positions, then the second half kick
+  if ((st = coupling(h))) return st;
   if ((st = tg_kick(h->c, h->sys.vel, h->sys.acc, n, nullptr, nullptr, nullptr, dt, nullptr, 0)))
     return st;
   for (int k = 0; k < 3; ++k) h->V[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
