@@ -339,6 +339,15 @@ class Hybrid:
         osteps._drift_stars(st, dt)
         k += 1
         self.R = self.R + self.V * dt
+        # tree forces of the stars active at the new k, with the ghosts
+        # carried by the chain particle
+        rows = osteps._active(st, level, nlev, k).astype(np.int64)
+        self._write()
+        if rows.size:
+            ev = oracle.tree_forces(st.pos, st.mass, st.eps, st.theta, st.leaf_size,
+                                    st.group_size, active=rows, softening=st.softening)
+            st.acc[rows] = ev.acc[rows]
+            st.pot[rows] = ev.pot[rows]
         n = self.m.size
         sol = solve_ivp(_members_rhs(self.m, px, pv, pm, self.G), (0.0, dt),
                         np.concatenate([self.x.ravel(), self.v.ravel()]), method="DOP853",
@@ -346,7 +355,18 @@ class Hybrid:
         self.x = sol.y[:3 * n, -1].reshape(n, 3)
         self.v = sol.y[3 * n:, -1].reshape(n, 3)
         self.r_chain = self._radius()
-        self._forces_list(osteps._active(st, level, nlev, k))
+        # the coupling for the same stars with the members' new positions
+        self._write()
+        X, _ = self._globals()
+        r_crit = min(self.r_chain, self.r_chain0)
+        self.pert = ochain.perturbers(st.pos, st.mass, self.R, self.M, r_crit, self.gamma_crit,
+                                      self.excl)
+        a, p, ac, _ = ochain.coupling(st.pos, st.mass, rows, self.R, self.M, X, self.m,
+                                      self.pert, 0.0, self.excl, self.G)
+        if rows.size:
+            st.acc[rows] += a
+            st.pot[rows] += p
+        self.a_com = ac
         self._membership_block(level, nlev)
         if self.active:
             self._write()

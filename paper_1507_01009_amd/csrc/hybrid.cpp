@@ -703,6 +703,14 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) {
   if ((st = perturbers(h, px, pv, pm, nullptr))) return st;
   if ((st = block_stars_drift(h->c, &h->sys, b))) return st;
   for (int k = 0; k < 3; ++k) h->R[k] = h->R[k] + h->V[k] * dt;
+  // tree forces of the stars active at the new k, queued while the chain
+  // advances on the host (ghosts carried by the chain particle)
+  if ((st = write_members(h))) return st;
+  {
+    tg_system y = h->sys;
+    y.n_bh = 0;
+    if ((st = tg_forces(h->c, &y, b->active_idx, b->n_active))) return st;
+  }
   tg_archain s{};
   s.n = nc(h);
   s.x = h->x.data();
@@ -726,8 +734,18 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) {
   h->ds = s.ds;
   if ((st = tg_archain_energy(&s, h->G, &h->energy_error))) return st;
   h->r_chain = max_radius(h);
-  // forces for the stars active at the new k, and the chain particle's
-  if ((st = forces_list(h, b->active_idx, b->n_active))) return st;
+  // the coupling for the same stars with the members' new positions, and
+  // the chain particle's force
+  if ((st = write_members(h))) return st;
+  {
+    tg_chain ch = chain_of(h);
+    if ((st = tg_chain_forces(h->c, &ch, b->active_idx, b->n_active, h->sys.acc, h->sys.pot,
+                              h->d_com, h->d_macc)))
+      return st;
+  }
+  if ((st = tg_sync(h->c, nullptr))) return st;
+  if ((st = to_host(h, h->a_com, h->d_com, 3 * sizeof(double)))) return st;
+  if ((st = to_host(h, &h->n_pert, h->d_np, sizeof(int32_t)))) return st;
   if ((st = membership_block(h, b))) return st;
   if (h->active) return write_members(h);
   return maybe_start_block(h, b);
