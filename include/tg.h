@@ -50,7 +50,7 @@ extern "C" {
 typedef enum {
   TG_OK = 0,
   TG_EINVAL = -1,     /* bad argument (NULL pointer, size, range) */
-  TG_ENOMEM = -2,     /* device allocation failed in tg_create */
+  TG_ENOMEM = -2,     /* device allocation failed in tg_create, or a host allocation */
   TG_EHIP = -3,       /* a HIP runtime call failed */
   TG_ECAPACITY = -4,  /* a capacity given at tg_create was exceeded */
   TG_ESTATE = -5,     /* call out of order (e.g. forces before a tree) */

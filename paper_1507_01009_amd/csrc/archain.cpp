@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -184,14 +185,26 @@ int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, std::vect
       const int want = k == 0 ? std::max(3, first) : 2;
       const int hi = std::min(kCols, k + std::min(par, want));
       if (hi - k > 1) {
+        // a column whose thread cannot start, or fails inside, is computed
+        // on this thread afterwards; the result is the same either way
         std::vector<std::thread> th;
-        for (int q = k + 1; q < hi; ++q)
-          th.emplace_back([&, q] {
-            std::vector<double> aq(3 * n), fq(3 * n);
-            col[q] = leapfrog(c, y0, H, kSeq[q], aq, fq);
-          });
+        std::vector<char> done(kCols, 0);
+        try {
+          for (int q = k + 1; q < hi; ++q)
+            th.emplace_back([&, q] {
+              try {
+                std::vector<double> aq(3 * n), fq(3 * n);
+                col[q] = leapfrog(c, y0, H, kSeq[q], aq, fq);
+                done[q] = 1;
+              } catch (...) {
+              }
+            });
+        } catch (const std::system_error &) {
+        }
         col[k] = leapfrog(c, y0, H, kSeq[k], a, f);
         for (auto &t : th) t.join();
+        for (int q = k + 1; q < hi; ++q)
+          if (!done[q]) col[q] = leapfrog(c, y0, H, kSeq[q], a, f);
       } else {
         col[k] = leapfrog(c, y0, H, kSeq[k], a, f);
       }
@@ -230,7 +243,7 @@ using namespace tg;
 
 extern "C" {
 
-tg_status tg_archain_init(tg_archain *s, double G) {
+tg_status tg_archain_init(tg_archain *s, double G) try {
   if (!s || !s->x || !s->v || !s->m) return fail(TG_EINVAL, "tg_archain_init: NULL argument");
   if (s->n < 2 || s->n > kMaxChain) return fail(TG_EINVAL, "tg_archain_init: n must be in 2..256");
   if (!(G > 0.0)) return fail(TG_EINVAL, "tg_archain_init: G must be positive");
@@ -258,10 +271,10 @@ tg_status tg_archain_init(tg_archain *s, double G) {
     s->ds = 0.01 * tmin * U;
   }
   return TG_OK;
-}
+} TG_HOST_CATCH("tg_archain_init")
 
 tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
-                             const tg_archain_perturbers *p, int64_t *steps_out) {
+                             const tg_archain_perturbers *p, int64_t *steps_out) try {
   if (!s || !s->x || !s->v || !s->m) return fail(TG_EINVAL, "tg_archain_advance: NULL argument");
   if (s->n < 2 || s->n > kMaxChain) return fail(TG_EINVAL, "tg_archain_advance: n must be in 2..256");
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(TG_EINVAL, "tg_archain_advance: dt must be >= 0");
@@ -335,9 +348,9 @@ tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
   s->ds = H;
   if (steps_out) *steps_out = steps;
   return TG_OK;
-}
+} TG_HOST_CATCH("tg_archain_advance")
 
-tg_status tg_archain_energy(const tg_archain *s, double G, double *err_out) {
+tg_status tg_archain_energy(const tg_archain *s, double G, double *err_out) try {
   if (!s || !s->x || !s->v || !s->m || !err_out) return fail(TG_EINVAL, "tg_archain_energy: NULL argument");
   if (s->n < 2 || s->n > kMaxChain) return fail(TG_EINVAL, "tg_archain_energy: n must be in 2..256");
   Chain c;
@@ -347,6 +360,6 @@ tg_status tg_archain_energy(const tg_archain *s, double G, double *err_out) {
   const double T = kinetic(c, s->v);
   *err_out = (T - U + s->B) / U;
   return TG_OK;
-}
+} TG_HOST_CATCH("tg_archain_energy")
 
 }  // extern "C"

@@ -523,7 +523,6 @@ tg_status membership_block(tg_hybrid *h, const tg_blocks *b) {
 // chain particle's force (no star gets new forces).
 tg_status maybe_start_block(tg_hybrid *h, const tg_blocks *b) {
   (void)b;
-  const bool was = h->active;
   double bp[3], bv[3], bm;
   tg_status st;
   if ((st = to_host(h, bp, h->sys.bh_pos, sizeof(bp)))) return st;
@@ -533,7 +532,7 @@ tg_status maybe_start_block(tg_hybrid *h, const tg_blocks *b) {
   if ((st = tg_sync(h->c, nullptr))) return st;
   int32_t k = 0;
   if ((st = to_host(h, &k, h->d_nsel, sizeof(int32_t)))) return st;
-  if (k < 1 || was) return TG_OK;
+  if (k < 1) return TG_OK;
   std::vector<int32_t> ids(k);
   if ((st = to_host(h, ids.data(), h->d_sel, sizeof(int32_t) * k))) return st;
   std::vector<double> X, W, mass;
@@ -559,12 +558,10 @@ tg_status maybe_start_block(tg_hybrid *h, const tg_blocks *b) {
 
 }  // namespace
 
-extern "C" {}  // namespace
-
 extern "C" {
 
 tg_status tg_hybrid_create(tg_ctx *c, const tg_system *y, const tg_hybrid_config *cfg,
-                           tg_hybrid **out) {
+                           tg_hybrid **out) try {
   if (!c || !y || !cfg || !out) return fail(TG_EINVAL, "tg_hybrid_create: NULL argument");
   *out = nullptr;
   if (y->n_bh != 1 || y->n_sys != 1 || y->n < 1 || y->frozen)
@@ -605,16 +602,16 @@ tg_status tg_hybrid_create(tg_ctx *c, const tg_system *y, const tg_hybrid_config
   }
   *out = h;
   return TG_OK;
-}
+} TG_HOST_CATCH("tg_hybrid_create")
 
-tg_status tg_hybrid_begin(tg_hybrid *h) {
+tg_status tg_hybrid_begin(tg_hybrid *h) try {
   if (!h) return fail(TG_EINVAL, "tg_hybrid_begin: NULL");
   tg_status st = forces(h);
   if (st) return st;
   return h->active ? TG_OK : maybe_start(h);
-}
+} TG_HOST_CATCH("tg_hybrid_begin")
 
-tg_status tg_hybrid_step(tg_hybrid *h, double dt) {
+tg_status tg_hybrid_step(tg_hybrid *h, double dt) try {
 #pragma clang fp contract(off)
   if (!h) return fail(TG_EINVAL, "tg_hybrid_step: NULL");
   Timer whole(h->step_s);
@@ -677,9 +674,9 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) {
   if ((st = write_members(h))) return st;
   if ((st = membership(h))) return st;
   return h->active ? TG_OK : maybe_start(h);
-}
+} TG_HOST_CATCH("tg_hybrid_step")
 
-tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) {
+tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) try {
 #pragma clang fp contract(off)
   if (!h || !b) return fail(TG_EINVAL, "tg_hybrid_step_block: NULL");
   Timer whole(h->step_s);
@@ -749,7 +746,7 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) {
   if ((st = membership_block(h, b))) return st;
   if (h->active) return write_members(h);
   return maybe_start_block(h, b);
-}
+} TG_HOST_CATCH("tg_hybrid_step_block")
 
 tg_status tg_hybrid_state_get(const tg_hybrid *h, tg_hybrid_state *st, int32_t *members_out,
                               double *member_x, double *member_v) {

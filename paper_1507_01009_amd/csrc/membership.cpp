@@ -30,7 +30,7 @@ double dot3(const double *a, const double *b) {
 
 extern "C" {
 
-tg_status tg_chain_membership(const tg_membership_in *in, tg_membership_out *out) {
+tg_status tg_chain_membership(const tg_membership_in *in, tg_membership_out *out) try {
 #pragma clang fp contract(off)
   if (!in || !out) return fail(TG_EINVAL, "tg_chain_membership: NULL argument");
   if (in->n < 1 || in->n > kMaxChain)
@@ -83,6 +83,6 @@ tg_status tg_chain_membership(const tg_membership_in *in, tg_membership_out *out
   out->terminate = end ? 1 : 0;
   out->designated = end ? -1 : d;
   return TG_OK;
-}
+} TG_HOST_CATCH("tg_chain_membership")
 
 }  // extern "C"

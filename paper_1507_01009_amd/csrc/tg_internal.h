@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -182,6 +184,18 @@ namespace tg {
 // error reporting (tg_runtime.hip)
 tg_status fail(tg_status st, const std::string &msg);
 tg_status hip_fail(hipError_t e, const char *what);
+
+// Host exceptions never cross the C ABI: the entry points (and the helpers)
+// that build host containers are function-try-blocks ending in this
+// handler, which turns an allocation failure into TG_ENOMEM and any other
+// exception (e.g. a thread that cannot start) into TG_EINTERNAL.
+#define TG_HOST_CATCH(name)                                               \
+  catch (const std::bad_alloc &) {                                        \
+    return tg::fail(TG_ENOMEM, name ": host allocation failed");          \
+  }                                                                       \
+  catch (const std::exception &e_) {                                      \
+    return tg::fail(TG_EINTERNAL, std::string(name ": ") + e_.what());    \
+  }
 
 #define TG_HIP(call)                                  \
   do {                                                \

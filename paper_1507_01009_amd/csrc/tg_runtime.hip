@@ -217,7 +217,7 @@ tg_status tg_set_sizes(tg_ctx *c, int32_t leaf_size, int32_t group_size) {
 
 // Upload the system layout and tile table if it changed since the last
 // build (never during graph capture).
-static tg_status set_layout(tg_ctx *c, int64_t n, const int64_t *off, int32_t S) {
+static tg_status set_layout(tg_ctx *c, int64_t n, const int64_t *off, int32_t S) try {
   std::vector<int64_t> so(S + 1);
   if (off) {
     for (int s = 0; s <= S; ++s) so[s] = off[s];
@@ -266,7 +266,7 @@ static tg_status set_layout(tg_ctx *c, int64_t n, const int64_t *off, int32_t S)
   c->S = S;
   c->n_tiles = (int64_t)tiles.size();
   return TG_OK;
-}
+} TG_HOST_CATCH("set_layout")
 
 // mass (may be null): gathered with the positions when the caller has it
 static tg_status build_tree_impl(tg_ctx *c, const double *pos, const double *mass,
@@ -481,7 +481,7 @@ tg_status tg_get_counts(tg_ctx *c, int64_t out[8]) {
 tg_status tg_walk_lists(tg_ctx *c, double theta, const int32_t *idx,
                         const int32_t *n_act, int64_t *info, int64_t cap_groups,
                         uint32_t *ids, int64_t cap_ids, int64_t *n_groups_out,
-                        int64_t *n_ids_out) {
+                        int64_t *n_ids_out) try {
   tg_status st = check_walk_args(c, theta, idx, n_act, "tg_walk_lists");
   if (st != TG_OK) return st;
   const double *aold = nullptr;
@@ -529,13 +529,13 @@ tg_status tg_walk_lists(tg_ctx *c, double theta, const int32_t *idx,
   if (nag)
     TG_HIP(hipMemcpy(info, inf.data(), sizeof(int64_t) * inf.size(), hipMemcpyHostToDevice));
   return TG_OK;
-}
+} TG_HOST_CATCH("tg_walk_lists")
 
 tg_status tg_direct_fp64(tg_ctx *c, const double *spos, const double *sm,
                          const double *seps, int64_t ns, const double *tpos,
                          const double *teps, int64_t nt, const int64_t *sseg,
                          const int64_t *tseg, int32_t nseg, int32_t self_pairs,
-                         int32_t accumulate, double *acc, double *pot) {
+                         int32_t accumulate, double *acc, double *pot) try {
   if (!c) return fail(TG_EINVAL, "tg_direct_fp64: NULL context");
   if (ns < 0 || nt < 0) return fail(TG_EINVAL, "tg_direct_fp64: negative size");
   if (nt == 0) return TG_OK;
@@ -588,7 +588,7 @@ tg_status tg_direct_fp64(tg_ctx *c, const double *spos, const double *sm,
   TG_HIP(launch_direct(c, dseg, spos, sm, seps, 0.0, ns, tpos, teps, nt, ns_eff,
                        max_src, self_pairs, accumulate, acc, pot));
   return TG_OK;
-}
+} TG_HOST_CATCH("tg_direct_fp64")
 
 // Direct sums where every source shares one softening (stars): the same
 // kernels with a broadcast softening.
@@ -596,7 +596,7 @@ static tg_status tg_direct_fp64_eps(tg_ctx *c, const double *spos, const double 
                              double seps, int64_t ns, const double *tpos,
                              const double *teps, int64_t nt,
                              const int64_t *sseg, const int64_t *tseg, int32_t nseg,
-                             double *acc, double *pot) {
+                             double *acc, double *pot) try {
   if (!c) return fail(TG_EINVAL, "tg_direct_fp64_eps: NULL context");
   if (nt == 0) return TG_OK;
   int slot = -1;
@@ -624,7 +624,7 @@ static tg_status tg_direct_fp64_eps(tg_ctx *c, const double *spos, const double 
   TG_HIP(launch_direct(c, c->b.dseg + slot * kSegSlotLen, spos, sm, nullptr, seps, ns,
                        tpos, teps, nt, nseg, max_src, 0, 0, acc, pot));
   return TG_OK;
-}
+} TG_HOST_CATCH("tg_direct_fp64_eps")
 
 // Kick, drift and active set with an optional mask of frozen stars (ghost
 // chain members inside whole steps: no kick, no drift, never active).
@@ -835,7 +835,7 @@ tg_status tg_autotune(tg_ctx *c, const double *pos, const double *mass,
 
 tg_status tg_set_external(tg_ctx *c, const double *pos, const double *mass,
                           const double *eps, int32_t n_ext,
-                          const int64_t *seg_host, int32_t n_sys) {
+                          const int64_t *seg_host, int32_t n_sys) try {
   if (!c) return fail(TG_EINVAL, "tg_set_external: NULL context");
   if (n_ext < 0 || n_ext > kMaxExternal)
     return fail(TG_EINVAL, "tg_set_external: n_ext must be in 0..1024");
@@ -875,7 +875,7 @@ tg_status tg_set_external(tg_ctx *c, const double *pos, const double *mass,
   c->ext_eps = eps;
   c->n_ext = n_ext;
   return TG_OK;
-}
+} TG_HOST_CATCH("tg_set_external")
 
 static tg_status check_system(const tg_system *y, const char *who) {
   if (!y) return fail(TG_EINVAL, std::string(who) + ": NULL system");
@@ -940,7 +940,7 @@ static tg_status forces_impl(tg_ctx *c, const tg_system *y, const int32_t *idx,
 
 // SMBH <- star sums over each system's stars (skipped with stars_done: a
 // fused launch already formed them), then SMBH <-> SMBH.
-static tg_status smbh_sums(tg_ctx *c, const tg_system *y, bool stars_done) {
+static tg_status smbh_sums(tg_ctx *c, const tg_system *y, bool stars_done) try {
   tg_status st = TG_OK;
   if (y->n_bh > 0) {
     // SMBHs feel the stars of their own system, then each other
@@ -960,7 +960,7 @@ static tg_status smbh_sums(tg_ctx *c, const tg_system *y, bool stars_done) {
     if (st != TG_OK) return st;
   }
   return TG_OK;
-}
+} TG_HOST_CATCH("smbh_sums")
 
 tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
                     const int32_t *n_act) {
