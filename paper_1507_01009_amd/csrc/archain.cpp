@@ -62,40 +62,179 @@ double kinetic(const Chain &c, const double *v) {
   return T;
 }
 
-// Newtonian accelerations of the members; returns U.
-double internal(const Chain &c, const double *x, double *a) {
-  double U = 0.0;
-  std::fill(a, a + 3 * c.n, 0.0);
-  for (int i = 0; i < c.n; ++i)
-    for (int j = i + 1; j < c.n; ++j) {
-      const double dx = x[3 * j] - x[3 * i], dy = x[3 * j + 1] - x[3 * i + 1],
-                   dz = x[3 * j + 2] - x[3 * i + 2];
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const double r = std::sqrt(r2);
-      const double g = c.G / (r2 * r);
-      U += c.G * c.m[i] * c.m[j] / r;
-      a[3 * i] += g * c.m[j] * dx; a[3 * i + 1] += g * c.m[j] * dy; a[3 * i + 2] += g * c.m[j] * dz;
-      a[3 * j] -= g * c.m[i] * dx; a[3 * j + 1] -= g * c.m[i] * dy; a[3 * j + 2] -= g * c.m[i] * dz;
-    }
-  return U;
+// Scratch of one thread: accelerations a (members' own) and f (perturbers'
+// tidal part), [n][3]; structure-of-arrays copies of the member and
+// perturber coordinates and masses, padded to whole vectors.
+struct Work {
+  std::vector<double> a, f;
+  std::vector<double> X, Yc, Z, Mw;      // members
+  std::vector<double> PX, PY, PZ, PM;    // perturbers at the kick's time
+  explicit Work(int n = 0) : a(3 * n), f(3 * n) {}
+};
+
+// The pair sums run over 8-wide vectors (clang vector extensions); the
+// same source is compiled for AVX-512, AVX2 + FMA and the baseline, and the
+// widest one the CPU has is taken once per process, so every call (every
+// thread) rounds the same way on a given machine.
+using v8 = double __attribute__((ext_vector_type(8)));
+using l8 = long long __attribute__((ext_vector_type(8)));
+constexpr int kV = 8;
+
+int padded(int n) { return (n + kV - 1) / kV * kV; }
+
+__attribute__((always_inline)) inline v8 load8(const double *p) {
+  v8 r;
+  std::memcpy(&r, p, sizeof(r));
+  return r;
+}
+__attribute__((always_inline)) inline double hsum(v8 v) {
+  return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
 }
 
-// Tidal part of the perturbers' accelerations at time t.
-void external(const Chain &c, const double *x, double t, double *f) {
+// Row i of the members' sums: a_i = G sum_j m_j (x_j - x_i) / r^3 and
+// u_i = sum_j m_j / r (j != i).  Lanes j = i and the padding get a mass of
+// zero and r^2 + 1, so no lane divides by zero.
+__attribute__((always_inline)) inline void internal_row(const Work &w, int n, int i,
+                                                        double *ai, double &ui) {
+  const double xi = w.X[i], yi = w.Yc[i], zi = w.Z[i];
+  v8 ax = 0.0, ay = 0.0, az = 0.0, u = 0.0;
+  const l8 lane = {0, 1, 2, 3, 4, 5, 6, 7};
+  for (int j = 0; j < padded(n); j += kV) {
+    const l8 jj = lane + (long long)j;
+    const v8 live = -__builtin_convertvector((jj != (long long)i) & (jj < (long long)n), v8);
+    const v8 dx = load8(&w.X[j]) - xi, dy = load8(&w.Yc[j]) - yi, dz = load8(&w.Z[j]) - zi;
+    const v8 r2 = dx * dx + dy * dy + dz * dz + (1.0 - live);
+    const v8 ir = 1.0 / __builtin_elementwise_sqrt(r2);
+    const v8 mj = load8(&w.Mw[j]) * live;
+    const v8 mir = mj * ir;
+    const v8 g = mir * (ir * ir);
+    ax += g * dx;
+    ay += g * dy;
+    az += g * dz;
+    u += mir;
+  }
+  ai[0] = hsum(ax);
+  ai[1] = hsum(ay);
+  ai[2] = hsum(az);
+  ui = hsum(u);
+}
+
+// Member i's sum over the perturbers (positions already at the kick's time;
+// padding: mass zero, r^2 + 1).
+__attribute__((always_inline)) inline void external_row(const Work &w, int np, double xi,
+                                                        double yi, double zi, double *fi) {
+  v8 fx = 0.0, fy = 0.0, fz = 0.0;
+  const l8 lane = {0, 1, 2, 3, 4, 5, 6, 7};
+  for (int p = 0; p < padded(np); p += kV) {
+    const v8 live = -__builtin_convertvector(lane + (long long)p < (long long)np, v8);
+    const v8 dx = load8(&w.PX[p]) - xi, dy = load8(&w.PY[p]) - yi, dz = load8(&w.PZ[p]) - zi;
+    const v8 r2 = dx * dx + dy * dy + dz * dz + (1.0 - live);
+    const v8 ir = 1.0 / __builtin_elementwise_sqrt(r2);
+    const v8 g = load8(&w.PM[p]) * (ir * (ir * ir));
+    fx += g * dx;
+    fy += g * dy;
+    fz += g * dz;
+  }
+  fi[0] = hsum(fx);
+  fi[1] = hsum(fy);
+  fi[2] = hsum(fz);
+}
+
+#define TG_PAIR_SUMS(SUFFIX, ATTR)                                                      \
+  ATTR double internal_rows##SUFFIX(const Work &w, int n, double *a) {                  \
+    double U2 = 0.0;                                                                    \
+    for (int i = 0; i < n; ++i) {                                                       \
+      double ui;                                                                        \
+      internal_row(w, n, i, &a[3 * i], ui);                                             \
+      U2 += w.Mw[i] * ui;                                                               \
+    }                                                                                   \
+    return U2;                                                                          \
+  }                                                                                     \
+  ATTR void external_rows##SUFFIX(const Work &w, int n, int np, const double *x,        \
+                                  double *f) {                                          \
+    for (int i = 0; i < n; ++i)                                                         \
+      external_row(w, np, x[3 * i], x[3 * i + 1], x[3 * i + 2], &f[3 * i]);             \
+  }
+// (the sources are compiled as HIP, whose device pass also parses this
+// host-only file: CPU targets and CPU feature tests exist in the host pass)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TG_CPU_TARGET(x)
+#else
+#define TG_CPU_TARGET(x) __attribute__((target(x)))
+#endif
+TG_PAIR_SUMS(_base, )
+TG_PAIR_SUMS(_avx2, TG_CPU_TARGET("avx2,fma"))
+TG_PAIR_SUMS(_avx512, TG_CPU_TARGET("avx512f"))
+#undef TG_PAIR_SUMS
+#undef TG_CPU_TARGET
+
+enum class Isa { base, avx2, avx512 };
+Isa isa() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return Isa::base;
+#else
+  // TG_ARCHAIN_ISA = base or avx2 takes a narrower clone than the CPU
+  // allows (never a wider one)
+  static const Isa k = [] {
+    __builtin_cpu_init();
+    const char *e = std::getenv("TG_ARCHAIN_ISA");
+    const std::string want = e ? e : "";
+    const bool a512 = __builtin_cpu_supports("avx512f");
+    const bool a2 = __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma");
+    if (want == "base") return Isa::base;
+    if (a512 && want != "avx2") return Isa::avx512;
+    if (a2) return Isa::avx2;
+    return Isa::base;
+  }();
+  return k;
+#endif
+}
+
+// Newtonian accelerations of the members (into w.a); returns U.
+double internal(const Chain &c, const double *x, Work &w) {
+  const int n = c.n, np8 = padded(n);
+  w.X.assign(np8, 0.0);
+  w.Yc.assign(np8, 0.0);
+  w.Z.assign(np8, 0.0);
+  w.Mw.assign(np8, 0.0);
+  for (int i = 0; i < n; ++i) {
+    w.X[i] = x[3 * i];
+    w.Yc[i] = x[3 * i + 1];
+    w.Z[i] = x[3 * i + 2];
+    w.Mw[i] = c.m[i];
+  }
+  w.a.resize(3 * n);
+  double U2;
+  switch (isa()) {
+    case Isa::avx512: U2 = internal_rows_avx512(w, n, w.a.data()); break;
+    case Isa::avx2: U2 = internal_rows_avx2(w, n, w.a.data()); break;
+    default: U2 = internal_rows_base(w, n, w.a.data()); break;
+  }
+  for (double &q : w.a) q *= c.G;
+  return 0.5 * c.G * U2;
+}
+
+// Tidal part of the perturbers' accelerations at time t (into w.f).
+void external(const Chain &c, const double *x, double t, Work &w) {
+  double *f = w.f.data();
   std::fill(f, f + 3 * c.n, 0.0);
   if (c.np == 0) return;
   const double dt = t - c.t0;
-  for (int i = 0; i < c.n; ++i) {
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int p = 0; p < c.np; ++p) {
-      const double dx = c.py[3 * p] + c.pw[3 * p] * dt - x[3 * i];
-      const double dy = c.py[3 * p + 1] + c.pw[3 * p + 1] * dt - x[3 * i + 1];
-      const double dz = c.py[3 * p + 2] + c.pw[3 * p + 2] * dt - x[3 * i + 2];
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const double g = c.G * c.pm[p] / (r2 * std::sqrt(r2));
-      fx += g * dx; fy += g * dy; fz += g * dz;
-    }
-    f[3 * i] = fx; f[3 * i + 1] = fy; f[3 * i + 2] = fz;
+  const int np8 = padded(c.np);
+  w.PX.assign(np8, 0.0);
+  w.PY.assign(np8, 0.0);
+  w.PZ.assign(np8, 0.0);
+  w.PM.assign(np8, 0.0);
+  for (int p = 0; p < c.np; ++p) {
+    w.PX[p] = c.py[3 * p] + c.pw[3 * p] * dt;
+    w.PY[p] = c.py[3 * p + 1] + c.pw[3 * p + 1] * dt;
+    w.PZ[p] = c.py[3 * p + 2] + c.pw[3 * p + 2] * dt;
+    w.PM[p] = c.G * c.pm[p];
+  }
+  switch (isa()) {
+    case Isa::avx512: external_rows_avx512(w, c.n, c.np, x, f); break;
+    case Isa::avx2: external_rows_avx2(w, c.n, c.np, x, f); break;
+    default: external_rows_base(w, c.n, c.np, x, f); break;
   }
   double mx = 0.0, my = 0.0, mz = 0.0;
   for (int i = 0; i < c.n; ++i) {
@@ -113,11 +252,12 @@ void drift(const Chain &c, Y &y, double h) {
   y.t(n) += dt;
 }
 
-void kick(const Chain &c, Y &y, double h, std::vector<double> &a, std::vector<double> &f) {
+void kick(const Chain &c, Y &y, double h, Work &w) {
   const int n = c.n;
-  const double U = internal(c, y.x(), a.data());
+  const double U = internal(c, y.x(), w);
   const double dt = h / U;
-  external(c, y.x(), y.t(n), f.data());
+  external(c, y.x(), y.t(n), w);
+  const std::vector<double> &a = w.a, &f = w.f;
   double *v = y.v(n);
   double work = 0.0;
   for (int i = 0; i < n; ++i)
@@ -130,13 +270,12 @@ void kick(const Chain &c, Y &y, double h, std::vector<double> &a, std::vector<do
   y.B(n) -= work * dt;
 }
 
-Y leapfrog(const Chain &c, const Y &y0, double H, int nsub, std::vector<double> &a,
-           std::vector<double> &f) {
+Y leapfrog(const Chain &c, const Y &y0, double H, int nsub, Work &w) {
   Y y = y0;
   const double h = H / nsub;
   drift(c, y, 0.5 * h);
   for (int k = 0; k < nsub; ++k) {
-    kick(c, y, h, a, f);
+    kick(c, y, h, w);
     drift(c, y, k == nsub - 1 ? 0.5 * h : h);
   }
   return y;
@@ -162,8 +301,8 @@ int column_threads(const Chain &c) {
 
 // One extrapolated step of fictitious length H.  Returns the column at which
 // it converged (or -1) and the result in out.
-int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, std::vector<double> &a,
-            std::vector<double> &f, int first = 3) {
+int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, Work &w,
+            int first = 3) {
   const int n = c.n, dim = 6 * n + 2;
   std::vector<std::vector<double>> T(kCols, std::vector<double>(dim));
   // error scales: position and velocity magnitudes, the step's time, |B|
@@ -193,20 +332,20 @@ int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, std::vect
           for (int q = k + 1; q < hi; ++q)
             th.emplace_back([&, q] {
               try {
-                std::vector<double> aq(3 * n), fq(3 * n);
-                col[q] = leapfrog(c, y0, H, kSeq[q], aq, fq);
+                Work wq(n);
+                col[q] = leapfrog(c, y0, H, kSeq[q], wq);
                 done[q] = 1;
               } catch (...) {
               }
             });
         } catch (const std::system_error &) {
         }
-        col[k] = leapfrog(c, y0, H, kSeq[k], a, f);
+        col[k] = leapfrog(c, y0, H, kSeq[k], w);
         for (auto &t : th) t.join();
         for (int q = k + 1; q < hi; ++q)
-          if (!done[q]) col[q] = leapfrog(c, y0, H, kSeq[q], a, f);
+          if (!done[q]) col[q] = leapfrog(c, y0, H, kSeq[q], w);
       } else {
-        col[k] = leapfrog(c, y0, H, kSeq[k], a, f);
+        col[k] = leapfrog(c, y0, H, kSeq[k], w);
       }
       ready = hi;
     }
@@ -249,10 +388,10 @@ tg_status tg_archain_init(tg_archain *s, double G) try {
   if (!(G > 0.0)) return fail(TG_EINVAL, "tg_archain_init: G must be positive");
   Chain c;
   c.n = s->n; c.m = s->m; c.G = G;
-  std::vector<double> a(3 * s->n);
+  Work w(s->n);
   for (int i = 0; i < s->n; ++i)
     if (!(s->m[i] > 0.0)) return fail(TG_EINVAL, "tg_archain_init: masses must be positive");
-  const double U = internal(c, s->x, a.data());
+  const double U = internal(c, s->x, w);
   if (!std::isfinite(U)) return fail(TG_EINVAL, "tg_archain_init: coincident members");
   s->B = U - kinetic(c, s->v);
   if (!(s->ds > 0.0)) {
@@ -293,13 +432,13 @@ tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
   y.t(n) = s->t;
   y.B(n) = s->B;
   const double t_end = s->t + dt;
-  std::vector<double> a(3 * n), f(3 * n);
+  Work w(n);
   int64_t steps = 0;
   double H = s->ds;
   Y out;
   int hint = 3;   // columns the last extrapolated step converged with
   while (y.t(n) < t_end) {
-    int col = bs_step(c, y, H, tol, out, a, f, hint);
+    int col = bs_step(c, y, H, tol, out, w, hint);
     if (col >= 0) hint = col + 1;
     if (col < 0) {
       H *= 0.5;
@@ -316,7 +455,7 @@ tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
       for (int it = 0; it < 100 && !done; ++it) {
         const double hc = ha + (hb - ha) * (t_end - ta) / (tb - ta);
         Y yc;
-        if (bs_step(c, y, hc, tol, yc, a, f, hint) < 0) {
+        if (bs_step(c, y, hc, tol, yc, w, hint) < 0) {
           H = 0.5 * hc;
           retry = true;
           break;
@@ -355,8 +494,8 @@ tg_status tg_archain_energy(const tg_archain *s, double G, double *err_out) try 
   if (s->n < 2 || s->n > kMaxChain) return fail(TG_EINVAL, "tg_archain_energy: n must be in 2..256");
   Chain c;
   c.n = s->n; c.m = s->m; c.G = G;
-  std::vector<double> a(3 * s->n);
-  const double U = internal(c, s->x, a.data());
+  Work w(s->n);
+  const double U = internal(c, s->x, w);
   const double T = kinetic(c, s->v);
   *err_out = (T - U + s->B) / U;
   return TG_OK;

@@ -1,7 +1,8 @@
 """The AR-chain's extrapolation columns computed on host threads give the
 same result, bit for bit, as one at a time (no GPU needed): a 70-member
 chain with 60 perturbers advanced in two processes, TG_ARCHAIN_THREADS = 1
-and 6."""
+and 6.  The vector clones of the pair sums (baseline, AVX2 + FMA, AVX-512)
+agree to 1e-10 relative on the same chain."""
 import json
 import os
 import subprocess
@@ -45,3 +46,24 @@ def test_threaded_columns_are_bit_identical():
     assert a["t"] == b["t"]
     assert np.array_equal(np.array(a["x"]), np.array(b["x"]))
     assert np.array_equal(np.array(a["v"]), np.array(b["v"]))
+
+
+def _run_isa(isa):
+    env = dict(os.environ, TG_ARCHAIN_THREADS="1", TG_ARCHAIN_ISA=isa)
+    out = subprocess.run([sys.executable, "-c", SCRIPT], env=env, capture_output=True, text=True,
+                         timeout=300, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def test_vector_clones_agree():
+    """The pair sums compiled for AVX-512, AVX2 + FMA and the baseline
+    round differently but agree to the integration's tolerance; a wrong
+    clone (a dropped lane, a bad mask) would not."""
+    ref = _run_isa("base")
+    for isa in ("avx2", "auto"):
+        b = _run_isa(isa)
+        assert b["t"] == ref["t"]
+        sx = np.abs(np.array(ref["x"])).max()
+        sv = np.abs(np.array(ref["v"])).max()
+        assert np.max(np.abs(np.array(b["x"]) - np.array(ref["x"]))) <= 1e-10 * sx
+        assert np.max(np.abs(np.array(b["v"]) - np.array(ref["v"]))) <= 1e-10 * sv
