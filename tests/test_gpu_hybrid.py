@@ -85,6 +85,43 @@ def test_hybrid_steps_match_the_oracle(steps):
     hy.close()
 
 
+def test_hybrid_chain_ends_and_restarts():
+    """r_chain0 = 0.02, gamma_esc = 1.0, dt = 2e-3 on the same cusp: the
+    chain formed at the start ends after one step (its one star escapes),
+    a new chain starts later and then absorbs and loses stars; every event,
+    member list and the final state as in the oracle."""
+    say("hybrid end and restart")
+    from paper_1507_01009_amd import binding as B
+    from test_gpu_steps import Dev
+    w = _workload()
+    dt = 2e-3
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    hy = B.Hybrid(ctx, d.sys, r_chain0=0.02, gamma_esc=1.0)
+    hy.begin()
+    oh = ohybrid.Hybrid(_ostate(w), r_chain0=0.02, gamma_esc=1.0)
+    oh.begin()
+    for k in range(40):
+        hy.step(dt)
+        oh.step(dt)
+        s = hy.state()
+        assert s["active"] == oh.active, k
+        assert s["members"].tolist() == oh.star, k
+        assert (s["starts"], s["absorbed"], s["escaped"], s["ended"]) == (
+            oh.starts, oh.absorbed, oh.escaped, oh.ended), k
+    say("  starts %d ended %d absorbed %d escaped %d" % (s["starts"], s["ended"], s["absorbed"],
+                                                         s["escaped"]))
+    assert s["ended"] >= 1 and s["starts"] >= 2 and s["absorbed"] > 0 and s["escaped"] > 0
+    ctx.sync()
+    h = d.host()
+    st = oh.st
+    live = ~oh.excl
+    assert np.max(np.abs(h["pos"][live] - st.pos[live])) <= 1e-9 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"][live] - st.vel[live])) <= 1e-9 * np.abs(st.vel).max()
+    assert np.array_equal(d.mass.cpu().numpy(), st.mass)
+    hy.close()
+
+
 def test_hybrid_errors():
     say("hybrid errors")
     from paper_1507_01009_amd import binding as B
