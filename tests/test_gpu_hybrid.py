@@ -179,3 +179,44 @@ def test_hybrid_block_substeps_match_the_oracle():
     assert np.allclose(s["com"], oh.R, rtol=0, atol=1e-12)
     assert np.max(np.abs(s["x"] - oh.x)) <= 1e-9 * np.abs(oh.x).max()
     hy.close()
+
+
+def test_hybrid_block_chain_ends_and_restarts():
+    """Block substeps (8 levels, dt_max = 2^-6) with r_chain0 = 0.02 and
+    gamma_esc = 1.0: the first chain ends at substep 16, its star returns
+    on the finest level, and a new chain starts at substep 345; events,
+    member lists, levels and the final state as in the oracle."""
+    say("hybrid block end and restart")
+    from paper_1507_01009_amd import binding as B
+    from test_gpu_steps import Dev, _blocks
+    w = _workload()
+    nlev, dt_max, nsub = 8, 2.0 ** -6, 360
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    blk, keep = _blocks(ctx, w, nlev, dt_max)
+    hy = B.Hybrid(ctx, d.sys, r_chain0=0.02, gamma_esc=1.0)
+    hy.begin()
+    oh = ohybrid.Hybrid(_ostate(w), r_chain0=0.02, gamma_esc=1.0)
+    oh.begin()
+    level = np.zeros(w.n, np.uint8)
+    t4e2 = np.full(w.n, 0.3 ** 4 * w.eps ** 2)
+    k = 0
+    for i in range(nsub):
+        hy.step_block(blk)
+        k = oh.step_block(level, t4e2, k, dt_max, nlev)
+        s = hy.state()
+        assert s["members"].tolist() == oh.star, i
+        assert (s["starts"], s["absorbed"], s["escaped"], s["ended"]) == (
+            oh.starts, oh.absorbed, oh.escaped, oh.ended), i
+    say("  starts %d ended %d members %d" % (s["starts"], s["ended"], len(s["members"])))
+    assert s["ended"] >= 1 and s["starts"] >= 2 and s["active"]
+    ctx.sync()
+    assert int(keep[4].item()) == k == nsub
+    assert np.array_equal(keep[0].cpu().numpy()[~oh.excl], level[~oh.excl])
+    h = d.host()
+    st = oh.st
+    live = ~oh.excl
+    assert np.max(np.abs(h["pos"][live] - st.pos[live])) <= 1e-9 * np.abs(st.pos).max()
+    assert np.max(np.abs(h["vel"][live] - st.vel[live])) <= 1e-9 * np.abs(st.vel).max()
+    assert np.array_equal(d.mass.cpu().numpy(), st.mass)
+    hy.close()
