@@ -36,14 +36,31 @@ struct tg_hybrid {
   double ar_s = 0.0, step_s = 0.0;   // host wall time: AR-chain, whole steps
   // device buffers
   uint8_t *d_excl = nullptr, *d_flag = nullptr;
-  int32_t *d_pidx = nullptr, *d_np = nullptr, *d_ids = nullptr, *d_sel = nullptr,
-          *d_nsel = nullptr;
-  double *d_mpos = nullptr, *d_mmass = nullptr, *d_com = nullptr, *d_macc = nullptr,
-         *d_px = nullptr, *d_pv = nullptr, *d_pm = nullptr, *d_rows = nullptr,
+  int32_t *d_pidx = nullptr, *d_sel = nullptr, *d_nsel = nullptr;
+  double *d_macc = nullptr, *d_px = nullptr, *d_pv = nullptr, *d_pm = nullptr,
          *d_vals = nullptr;
+  // what a step uploads, in one device block with a pinned host image (one
+  // copy per upload): member star ids | their rows (positions, then
+  // velocities) | all members' positions | masses | SMBH position, velocity
+  char *d_stage = nullptr, *h_stage = nullptr;
+  int32_t *d_ids = nullptr;
+  double *d_rows = nullptr, *d_mpos = nullptr, *d_mmass = nullptr, *d_bh = nullptr;
+  // the chain particle's force [3] and the perturber count, adjacent (one read)
+  double *d_com = nullptr;
+  int32_t *d_np = nullptr;
+  // pinned landing area for reads: force and count [4], then the
+  // perturbers' positions, velocities, masses [7 pert_cap] and ids
+  double *h_read = nullptr;
 };
 
 namespace {
+
+constexpr size_t kOffIds = 0;
+constexpr size_t kOffRows = (sizeof(int32_t) * kMaxChain + 255) / 256 * 256;
+constexpr size_t kOffMpos = kOffRows + sizeof(double) * 6 * kMaxChain;
+constexpr size_t kOffMmass = kOffMpos + sizeof(double) * 3 * kMaxChain;
+constexpr size_t kOffBh = kOffMmass + sizeof(double) * kMaxChain;
+constexpr size_t kStageBytes = kOffBh + sizeof(double) * 6;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -130,32 +147,63 @@ double max_radius(const tg_hybrid *h) {
 
 // Write the members' global coordinates into the star arrays (ghosts) and
 // the SMBH's arrays; also the member positions and masses for the coupling.
+// One upload of the staged block, two row scatters, the SMBH's rows copied
+// on the device.
 tg_status write_members(tg_hybrid *h) {
-  std::vector<double> X, W;
-  globals(h, X, W);
-  std::vector<int32_t> ids;
-  std::vector<double> px, pv;
-  for (int i = 0; i < nc(h); ++i) {
+#pragma clang fp contract(off)
+  const int n = nc(h);
+  int32_t *ids = reinterpret_cast<int32_t *>(h->h_stage + kOffIds);
+  double *rows = reinterpret_cast<double *>(h->h_stage + kOffRows);
+  double *mpos = reinterpret_cast<double *>(h->h_stage + kOffMpos);
+  double *mmass = reinterpret_cast<double *>(h->h_stage + kOffMmass);
+  double *bh = reinterpret_cast<double *>(h->h_stage + kOffBh);
+  int k = 0;
+  bool smbh = false;
+  for (int i = 0; i < n; ++i) {
+    double X[3], W[3];
+    for (int d = 0; d < 3; ++d) {
+      X[d] = h->R[d] + h->x[3 * i + d];
+      W[d] = h->V[d] + h->v[3 * i + d];
+      mpos[3 * i + d] = X[d];
+    }
+    mmass[i] = h->m[i];
     if (h->star[i] < 0) {
-      tg_status st;
-      if ((st = to_dev(h, h->sys.bh_pos, &X[3 * i], 3 * sizeof(double)))) return st;
-      if ((st = to_dev(h, h->sys.bh_vel, &W[3 * i], 3 * sizeof(double)))) return st;
+      for (int d = 0; d < 3; ++d) {
+        bh[d] = X[d];
+        bh[3 + d] = W[d];
+      }
+      smbh = true;
       continue;
     }
-    ids.push_back(h->star[i]);
-    px.insert(px.end(), &X[3 * i], &X[3 * i] + 3);
-    pv.insert(pv.end(), &W[3 * i], &W[3 * i] + 3);
+    ids[k] = h->star[i];
+    for (int d = 0; d < 3; ++d) {
+      rows[3 * k + d] = X[d];
+      rows[3 * kMaxChain + 3 * k + d] = W[d];
+    }
+    ++k;
   }
-  const int k = (int)ids.size();
-  tg_status st;
-  if ((st = to_dev(h, h->d_ids, ids.data(), sizeof(int32_t) * k))) return st;
-  if ((st = to_dev(h, h->d_rows, px.data(), sizeof(double) * 3 * k))) return st;
+  hipStream_t sm = h->c->stream;
+  TG_HIP(hipMemcpyAsync(h->d_stage, h->h_stage, kStageBytes, hipMemcpyHostToDevice, sm));
   TG_HIP(launch_move_rows(h->c, h->sys.pos, h->d_rows, h->d_ids, k, true));
-  if ((st = to_dev(h, h->d_rows + 3 * kMaxChain, pv.data(), sizeof(double) * 3 * k))) return st;
   TG_HIP(launch_move_rows(h->c, h->sys.vel, h->d_rows + 3 * kMaxChain, h->d_ids, k, true));
-  if ((st = to_dev(h, h->d_mpos, X.data(), sizeof(double) * X.size()))) return st;
-  if ((st = to_dev(h, h->d_mmass, h->m.data(), sizeof(double) * h->m.size()))) return st;
+  if (smbh) {
+    TG_HIP(hipMemcpyAsync(h->sys.bh_pos, h->d_bh, 3 * sizeof(double), hipMemcpyDeviceToDevice,
+                          sm));
+    TG_HIP(hipMemcpyAsync(h->sys.bh_vel, h->d_bh + 3, 3 * sizeof(double),
+                          hipMemcpyDeviceToDevice, sm));
+  }
+  TG_HIP(hipStreamSynchronize(sm));
+  return TG_OK;
+}
+
+// The chain particle's force and the perturber count of the last coupling
+// (the stream is synchronised by the read).
+tg_status read_coupling(tg_hybrid *h) {
+  TG_HIP(hipMemcpyAsync(h->h_read, h->d_com, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                        h->c->stream));
   TG_HIP(hipStreamSynchronize(h->c->stream));
+  for (int k = 0; k < 3; ++k) h->a_com[k] = h->h_read[k];
+  std::memcpy(&h->n_pert, h->h_read + 3, sizeof(int32_t));
   return TG_OK;
 }
 
@@ -215,8 +263,7 @@ tg_status forces(tg_hybrid *h) {
                             h->d_macc)))
     return st;
   if ((st = tg_sync(h->c, nullptr))) return st;
-  if ((st = to_host(h, h->a_com, h->d_com, 3 * sizeof(double)))) return st;
-  return to_host(h, &h->n_pert, h->d_np, sizeof(int32_t));
+  return read_coupling(h);
 }
 
 // The coupling alone (the tree forces of the same positions are queued
@@ -230,8 +277,7 @@ tg_status coupling(tg_hybrid *h) {
                             h->d_macc)))
     return st;
   if ((st = tg_sync(h->c, nullptr))) return st;
-  if ((st = to_host(h, h->a_com, h->d_com, 3 * sizeof(double)))) return st;
-  return to_host(h, &h->n_pert, h->d_np, sizeof(int32_t));
+  return read_coupling(h);
 }
 
 // The perturbers of the last coupling relative to the chain particle, at
@@ -248,10 +294,21 @@ tg_status perturbers(tg_hybrid *h, std::vector<double> &px, std::vector<double> 
   tg_status st;
   if ((st = tg_predict_perturbers(h->c, &ch, h->sys.vel, h->V, 0.0, h->d_px, h->d_pv, h->d_pm)))
     return st;
-  if ((st = to_host(h, px.data(), h->d_px, sizeof(double) * 3 * np))) return st;
-  if ((st = to_host(h, pv.data(), h->d_pv, sizeof(double) * 3 * np))) return st;
-  if ((st = to_host(h, pm.data(), h->d_pm, sizeof(double) * np))) return st;
-  if (ids && (st = to_host(h, ids->data(), h->d_pidx, sizeof(int32_t) * np))) return st;
+  // four reads queued into the pinned area, one wait
+  const int cap = h->cfg.pert_cap;
+  double *rx = h->h_read + 4, *rv = rx + 3 * cap, *rm = rv + 3 * cap;
+  int32_t *ri = reinterpret_cast<int32_t *>(rm + cap);
+  hipStream_t sm = h->c->stream;
+  TG_HIP(hipMemcpyAsync(rx, h->d_px, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, sm));
+  TG_HIP(hipMemcpyAsync(rv, h->d_pv, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, sm));
+  TG_HIP(hipMemcpyAsync(rm, h->d_pm, sizeof(double) * np, hipMemcpyDeviceToHost, sm));
+  if (ids)
+    TG_HIP(hipMemcpyAsync(ri, h->d_pidx, sizeof(int32_t) * np, hipMemcpyDeviceToHost, sm));
+  TG_HIP(hipStreamSynchronize(sm));
+  std::copy(rx, rx + 3 * np, px.begin());
+  std::copy(rv, rv + 3 * np, pv.begin());
+  std::copy(rm, rm + np, pm.begin());
+  if (ids) std::copy(ri, ri + np, ids->begin());
   return TG_OK;
 }
 
@@ -423,8 +480,7 @@ tg_status forces_list(tg_hybrid *h, const int32_t *idx, const int32_t *n_act) {
                             h->d_macc)))
     return st;
   if ((st = tg_sync(h->c, nullptr))) return st;
-  if ((st = to_host(h, h->a_com, h->d_com, 3 * sizeof(double)))) return st;
-  return to_host(h, &h->n_pert, h->d_np, sizeof(int32_t));
+  return read_coupling(h);
 }
 
 // Block substeps: stars that return to the tree (escaped, or all members of
@@ -580,19 +636,29 @@ tg_status tg_hybrid_create(tg_ctx *c, const tg_system *y, const tg_hybrid_config
   A(dalloc(&h->d_excl, y->n));
   A(dalloc(&h->d_flag, kMaxChain));
   A(dalloc(&h->d_pidx, cfg->pert_cap));
-  A(dalloc(&h->d_np, 1));
-  A(dalloc(&h->d_ids, kMaxChain));
   A(dalloc(&h->d_sel, kMaxChain));
   A(dalloc(&h->d_nsel, 1));
-  A(dalloc(&h->d_mpos, 3 * kMaxChain));
-  A(dalloc(&h->d_mmass, kMaxChain));
-  A(dalloc(&h->d_com, 3));
+  A(dalloc(&h->d_com, 4));
   A(dalloc(&h->d_macc, 3 * kMaxChain));
   A(dalloc(&h->d_px, 3 * (int64_t)cfg->pert_cap));
   A(dalloc(&h->d_pv, 3 * (int64_t)cfg->pert_cap));
   A(dalloc(&h->d_pm, cfg->pert_cap));
-  A(dalloc(&h->d_rows, 6 * kMaxChain));
   A(dalloc(&h->d_vals, kMaxChain));
+  A(dalloc(&h->d_stage, (int64_t)kStageBytes));
+  A(hipHostMalloc((void **)&h->h_stage, kStageBytes, hipHostMallocDefault));
+  A(hipHostMalloc((void **)&h->h_read,
+                  sizeof(double) * (4 + 7 * (size_t)cfg->pert_cap) +
+                      sizeof(int32_t) * (size_t)cfg->pert_cap,
+                  hipHostMallocDefault));
+  if (h->d_stage) {
+    h->d_ids = reinterpret_cast<int32_t *>(h->d_stage + kOffIds);
+    h->d_rows = reinterpret_cast<double *>(h->d_stage + kOffRows);
+    h->d_mpos = reinterpret_cast<double *>(h->d_stage + kOffMpos);
+    h->d_mmass = reinterpret_cast<double *>(h->d_stage + kOffMmass);
+    h->d_bh = reinterpret_cast<double *>(h->d_stage + kOffBh);
+  }
+  if (h->d_com) h->d_np = reinterpret_cast<int32_t *>(h->d_com + 3);
+  if (h->h_stage) std::memset(h->h_stage, 0, kStageBytes);
   if (a == hipSuccess) A(hipMemset(h->d_excl, 0, (size_t)y->n));
   if (a == hipSuccess) A(hipDeviceSynchronize());
   h->sys.frozen = h->d_excl;   // ghosts are held still in block substeps
@@ -741,8 +807,7 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) try {
       return st;
   }
   if ((st = tg_sync(h->c, nullptr))) return st;
-  if ((st = to_host(h, h->a_com, h->d_com, 3 * sizeof(double)))) return st;
-  if ((st = to_host(h, &h->n_pert, h->d_np, sizeof(int32_t)))) return st;
+  if ((st = read_coupling(h))) return st;
   if ((st = membership_block(h, b))) return st;
   if (h->active) return write_members(h);
   return maybe_start_block(h, b);
@@ -778,12 +843,13 @@ tg_status tg_hybrid_state_get(const tg_hybrid *h, tg_hybrid_state *st, int32_t *
 
 void tg_hybrid_destroy(tg_hybrid *h) {
   if (!h) return;
-  void *ptrs[] = {h->d_excl, h->d_flag, h->d_pidx, h->d_np, h->d_ids, h->d_sel, h->d_nsel,
-                  h->d_mpos, h->d_mmass, h->d_com, h->d_macc, h->d_px, h->d_pv, h->d_pm,
-                  h->d_rows, h->d_vals};
+  void *ptrs[] = {h->d_excl, h->d_flag, h->d_pidx, h->d_sel, h->d_nsel, h->d_com,
+                  h->d_macc, h->d_px, h->d_pv, h->d_pm, h->d_vals, h->d_stage};
   if (h->c) (void)hipStreamSynchronize(h->c->stream);
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  if (h->h_stage) (void)hipHostFree(h->h_stage);
+  if (h->h_read) (void)hipHostFree(h->h_read);
   delete h;
 }
 
