@@ -27,6 +27,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <string>
 #include <system_error>
 #include <thread>
@@ -254,6 +257,7 @@ void drift(const Chain &c, Y &y, double h) {
 
 void kick(const Chain &c, Y &y, double h, Work &w) {
   const int n = c.n;
+  w.f.resize(3 * n);
   const double U = internal(c, y.x(), w);
   const double dt = h / U;
   external(c, y.x(), y.t(n), w);
@@ -299,6 +303,81 @@ int column_threads(const Chain &c) {
   return pairs < 4096 ? 1 : hw;
 }
 
+// Host threads started once (at the first threaded batch) that take the
+// columns of a batch; the calling thread takes columns too.  One batch runs
+// at a time in a process; the workers are never joined (they wait on a
+// condition variable until the process ends).
+class ColumnPool {
+ public:
+  static ColumnPool &get(int workers) {
+    static ColumnPool *p = new ColumnPool(workers);
+    return *p;
+  }
+  // f(q) for every q in [lo, hi); returns when all have finished.  f must
+  // not throw.
+  void run(int lo, int hi, const std::function<void(int)> &f) {
+    std::lock_guard<std::mutex> one(batch_mu_);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      f_ = &f;
+      next_ = lo;
+      end_ = hi;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [&] { return next_ >= end_ && busy_ == 0; });
+    f_ = nullptr;
+  }
+
+ private:
+  explicit ColumnPool(int workers) {
+    for (int i = 0; i < workers; ++i) {
+      try {
+        std::thread(&ColumnPool::loop, this).detach();
+      } catch (const std::system_error &) {
+        break;   // fewer workers; the caller takes what is left
+      }
+    }
+  }
+  void work() {
+    for (;;) {
+      const std::function<void(int)> *f;
+      int q;
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (!f_ || next_ >= end_) return;
+        f = f_;
+        q = next_++;
+        ++busy_;
+      }
+      (*f)(q);
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        --busy_;
+      }
+      done_cv_.notify_all();
+    }
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+      }
+      work();
+    }
+  }
+  std::mutex batch_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)> *f_ = nullptr;
+  int next_ = 0, end_ = 0, busy_ = 0;
+  uint64_t gen_ = 0;
+};
+
 // One extrapolated step of fictitious length H.  Returns the column at which
 // it converged (or -1) and the result in out.
 int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, Work &w,
@@ -324,25 +403,19 @@ int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, Work &w,
       const int want = k == 0 ? std::max(3, first) : 2;
       const int hi = std::min(kCols, k + std::min(par, want));
       if (hi - k > 1) {
-        // a column whose thread cannot start, or fails inside, is computed
-        // on this thread afterwards; the result is the same either way
-        std::vector<std::thread> th;
+        // a column that fails on a pool thread is computed again on this
+        // one; the result is the same on any thread
         std::vector<char> done(kCols, 0);
-        try {
-          for (int q = k + 1; q < hi; ++q)
-            th.emplace_back([&, q] {
-              try {
-                Work wq(n);
-                col[q] = leapfrog(c, y0, H, kSeq[q], wq);
-                done[q] = 1;
-              } catch (...) {
-              }
-            });
-        } catch (const std::system_error &) {
-        }
-        col[k] = leapfrog(c, y0, H, kSeq[k], w);
-        for (auto &t : th) t.join();
-        for (int q = k + 1; q < hi; ++q)
+        const std::function<void(int)> job = [&](int q) {
+          try {
+            thread_local Work tw;
+            col[q] = leapfrog(c, y0, H, kSeq[q], tw);
+            done[q] = 1;
+          } catch (...) {
+          }
+        };
+        ColumnPool::get(par - 1).run(k, hi, job);
+        for (int q = k; q < hi; ++q)
           if (!done[q]) col[q] = leapfrog(c, y0, H, kSeq[q], w);
       } else {
         col[k] = leapfrog(c, y0, H, kSeq[k], w);
