@@ -720,8 +720,8 @@ def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU (requested %d); "
-              "multi-GPU sharding is design-only" % max(a.gpus, world), file=sys.stderr)
+        print("bench.py: the library runs on one GPU (requested %d); sharding a system "
+              "across GPUs is not implemented" % max(a.gpus, world), file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
