@@ -613,7 +613,11 @@ const char *tg_version(void);
  *    back; a chain that ends returns everything), the centre of mass is
  *    re-formed and the forces are evaluated again.
  * The driver owns the system while it lives: it writes the stars' masses
- * (ghosts) and the SMBH's arrays, and synchronises the stream every step.
+ * (ghosts) and the SMBH's arrays, and synchronises the stream every step,
+ * so its calls cannot be graph-captured.  tg_hybrid_create allocates the
+ * driver's own device buffers and pinned host staging (freed by
+ * tg_hybrid_destroy); the AR-chain's host threads start at its first
+ * threaded batch and live until the process ends.
  * Errors: TG_EINVAL (arguments; the system needs exactly one SMBH),
  * TG_ECAPACITY (perturbers beyond pert_cap, members beyond 256). */
 typedef struct tg_hybrid tg_hybrid;
