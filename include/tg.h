@@ -662,6 +662,8 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *blocks);
  * the SMBH; member x/v (host [n_members][3] or NULL): centre-of-mass frame. */
 tg_status tg_hybrid_state_get(const tg_hybrid *h, tg_hybrid_state *st, int32_t *members_out,
                               double *member_x, double *member_v);
+/* Destroy the driver before its context (it synchronises the context's
+ * stream); NULL is ignored. */
 void tg_hybrid_destroy(tg_hybrid *h);
 
 #ifdef __cplusplus

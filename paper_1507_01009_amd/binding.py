@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -270,6 +271,9 @@ class Context:
         self.cfg = cfg
 
     def close(self):
+        # drivers built on this context go first (they use its stream)
+        for d in list(getattr(self, "_deps", ())):
+            d.close()
         if getattr(self, "h", None):
             lib().tg_destroy(self.h)
             self.h = None
@@ -614,7 +618,11 @@ class Hybrid:
                                float(ghost_mass), int(pert_cap))
         self.h = C.c_void_p()
         self._sys = system
+        self._ctx = ctx            # the context outlives the driver
         _check(lib().tg_hybrid_create(ctx.h, C.byref(system), C.byref(cfg), C.byref(self.h)))
+        if not hasattr(ctx, "_deps"):
+            ctx._deps = weakref.WeakSet()
+        ctx._deps.add(self)
 
     def begin(self):
         _check(lib().tg_hybrid_begin(self.h))

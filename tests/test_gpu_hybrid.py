@@ -220,3 +220,19 @@ def test_hybrid_block_chain_ends_and_restarts():
     assert np.max(np.abs(h["vel"][live] - st.vel[live])) <= 1e-9 * np.abs(st.vel).max()
     assert np.array_equal(d.mass.cpu().numpy(), st.mass)
     hy.close()
+
+
+def test_context_close_closes_the_driver_first():
+    """Closing the context while a driver lives closes the driver first (it
+    uses the context's stream); closing the driver again is a no-op."""
+    say("hybrid lifetime")
+    from paper_1507_01009_amd import binding as B
+    from test_gpu_steps import Dev
+    w = _workload(4096)
+    ctx = B.Context(w.n)
+    d = Dev(ctx, w)
+    hy = B.Hybrid(ctx, d.sys, r_chain0=0.04)
+    hy.begin()
+    ctx.close()
+    assert not hy.h and not ctx.h
+    hy.close()
