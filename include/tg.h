@@ -536,6 +536,8 @@ tg_status tg_step_blocks(tg_ctx *ctx, const tg_system *sys, const tg_blocks *blo
 typedef struct tg_graph tg_graph;
 tg_status tg_graph_begin(tg_ctx *ctx);
 tg_status tg_graph_end(tg_ctx *ctx, tg_graph **out);
+/* A graph replays kernels on its context's buffers: launch it only while
+ * the context lives (destroying it afterwards is fine). */
 tg_status tg_graph_launch(tg_graph *g, void *stream);
 void tg_graph_destroy(tg_graph *g);
 

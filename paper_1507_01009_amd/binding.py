@@ -19,7 +19,7 @@ TG_FP64, TG_MIXED = 0, 1
 TG_SOFT_PLUMMER, TG_SOFT_SPLINE = 0, 1
 ERR_NONFINITE, ERR_MASS, ERR_NODES, ERR_FRONTIER, ERR_LISTS = 1, 2, 4, 8, 16
 STATUS = {0: "TG_OK", -1: "TG_EINVAL", -2: "TG_ENOMEM", -3: "TG_EHIP",
-          -4: "TG_ECAPACITY", -5: "TG_ESTATE", -6: "TG_EDATA"}
+          -4: "TG_ECAPACITY", -5: "TG_ESTATE", -6: "TG_EDATA", -7: "TG_EINTERNAL"}
 
 
 class TGError(RuntimeError):
@@ -231,10 +231,17 @@ def _stream_handle(stream):
 
 
 class Graph:
-    def __init__(self, handle):
+    """A captured sequence of calls; it replays kernels on its context's
+    buffers, so it keeps the context alive and refuses to launch once the
+    context is closed."""
+
+    def __init__(self, handle, ctx):
         self.h = handle
+        self._ctx = ctx
 
     def launch(self, stream=None):
+        if not getattr(self._ctx, "h", None):
+            raise TGError(-5, "tg_graph_launch: the graph's context is closed")
         _check(lib().tg_graph_launch(self.h, _stream_handle(stream)))
 
     def __del__(self):
@@ -501,7 +508,7 @@ class Context:
     def graph_end(self):
         g = C.c_void_p()
         _check(lib().tg_graph_end(self.h, C.byref(g)))
-        return Graph(g)
+        return Graph(g, self)
 
     # -- inspection
     def get_tree(self):

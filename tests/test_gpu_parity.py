@@ -376,6 +376,11 @@ def test_graph_replay_equals_eager():
             assert torch.equal(acc_g, acc_e), rep
             ctx.build_tree(dp); ctx.compute_moments(dm); ctx.tree_forces(eps, 0.5, acc_e)
             ctx.sync()
+        # a graph replays kernels on its context's buffers: once the context
+        # is closed, launching it is refused on the host (nothing runs)
+        ctx.close()
+        with pytest.raises(B.TGError):
+            graph.launch(s)
 
 
 def test_deterministic_bitwise():
