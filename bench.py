@@ -219,20 +219,24 @@ def traffic_for(kernel_file, workload):
         return None
 
 
-def direct_errors(w, accs, n_samples=128):
-    """Per-percentile error of each path against the exact direct sum (stars
-    and SMBHs, long double) on seeded sample targets."""
+def direct_errors(w, accs, n_samples=4096, softening="plummer"):
+    """Per-percentile error of each path against the oracle's exact direct
+    sum (stars and SMBHs, long double accumulation) on seeded sample
+    targets: the reference the reported error percentiles rest on."""
     import numpy as np
     import oracle
     rng = np.random.default_rng(99)
-    tg = np.sort(rng.choice(w.n, n_samples, replace=False))
+    tg = np.sort(rng.choice(w.n, min(n_samples, w.n), replace=False))
     ref, _ = oracle.direct(w.pos, w.mass, w.eps, tg, xpos=w.bh_pos, xmass=w.bh_mass,
-                           xeps=w.bh_eps)
+                           xeps=w.bh_eps, softening=softening)
     out = {}
     for name, a in accs.items():
         e = np.linalg.norm(a[tg] - ref, axis=1) / np.linalg.norm(ref, axis=1)
         out[name + "_vs_direct_sum"] = percentiles(e)
-    out["direct_sum_samples"] = int(n_samples)
+    out["direct_sum_samples"] = int(tg.size)
+    out["direct_sum_reference"] = (
+        "oracle long-double direct sum over all stars and SMBHs, %d seeded targets, "
+        "%d host threads" % (tg.size, oracle.max_threads()))
     return out
 
 
@@ -265,6 +269,9 @@ def direct_errors_gpu(w, accs, n_samples=65536, softening="plummer"):
         e = np.linalg.norm(a[tg] - ref, axis=1) / np.linalg.norm(ref, axis=1)
         out[name + "_vs_direct_sum_fp64_gpu"] = percentiles(e)
     out["direct_sum_fp64_gpu_samples"] = int(tg.size)
+    out["direct_sum_fp64_gpu_reference"] = (
+        "tg_direct_fp64 (compensated FP64 on the GPU) on %d seeded targets; its parity "
+        "with the oracle's long-double sum at all 1M sources is a GPU test" % tg.size)
     return out
 
 
@@ -364,6 +371,8 @@ def extra_spline(w, a, steps=10):
     e = (np.linalg.norm(accs["spline_mixed"] - accs["spline_fp64"], axis=1) /
          np.linalg.norm(accs["spline_fp64"], axis=1))
     r["error"] = {"mixed_vs_fp64": percentiles(e)}
+    if not a.no_cpu:
+        r["error"].update(direct_errors(w, accs, 1024, softening="spline"))
     r["error"].update(direct_errors_gpu(w, accs, softening="spline"))
     r["softening"] = "cubic spline, h = eps"
     return r
@@ -764,9 +773,11 @@ def main():
     if "mixed" in accs and "fp64" in accs:
         e = np.linalg.norm(accs["mixed"] - accs["fp64"], axis=1) / np.linalg.norm(accs["fp64"], axis=1)
         err["mixed_vs_fp64"] = percentiles(e)
-    err.update(direct_errors_gpu(w, accs))
+        err["mixed_vs_fp64_reference"] = "the FP64 GPU path on all targets (identical lists)"
     if not a.no_cpu:
+        log("bench: errors against the oracle's direct sum (4096 targets)")
         err.update(direct_errors(w, accs))
+    err.update(direct_errors_gpu(w, accs))
     tree = res.pop("tree")
     head = res["mixed"] if "mixed" in res else res["fp64"]
     head_name = "mixed" if "mixed" in res else "fp64"
