@@ -234,6 +234,38 @@ tg_status tg_direct_fp64(tg_ctx *ctx, const double *src_pos_dev,
                          int32_t self_pairs, int32_t accumulate,
                          double *acc_dev, double *pot_dev);
 
+/* ---- the same direct forces with no allocation at all ----------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sums
+ * of tg_direct_fp64 with no context.  It calls no hipMalloc, hipFree or
+ * other allocating routine; its scratch (the segment table and the
+ * per-block compensated partial sums) is one fixed device array inside the
+ * library, TG_NOALLOC_SCRATCH_BYTES long, which each GPU that calls it holds
+ * until the process ends.  Arguments as for tg_direct_fp64, plus
+ * softening (TG_SOFT_PLUMMER or TG_SOFT_SPLINE, pair h = max(eps_i, eps_j))
+ * and stream (a hipStream_t of the current HIP device; NULL = the default
+ * stream); the work is enqueued on that stream and nothing is synchronised.
+ * The partial sums have the capacity of a context's, so the results equal
+ * tg_direct_fp64's bit for bit.  Nothing in the scratch needs clearing:
+ * every call writes what it reads.  Every call on one GPU shares that GPU's
+ * array, so calls that overlap on one GPU (other streams, other host
+ * threads) race: order them.  Errors (on the host, before any work):
+ * TG_EINVAL as tg_direct_fp64, TG_ECAPACITY for nseg > TG_NOALLOC_MAX_SEG,
+ * TG_EHIP if the scratch address or a launch fails; tg_last_error gives the
+ * message without allocating. */
+#define TG_NOALLOC_MAX_SEG 64
+#define TG_NOALLOC_SCRATCH_BYTES (4096 + 8 * 8 * 131072)
+tg_status tg_direct_fp64_noalloc(const double *src_pos_dev,
+                                 const double *src_mass_dev,
+                                 const double *src_eps_dev, int64_t ns,
+                                 const double *tgt_pos_dev,
+                                 const double *tgt_eps_dev, int64_t nt,
+                                 const int64_t *src_seg_host,
+                                 const int64_t *tgt_seg_host, int32_t nseg,
+                                 int32_t self_pairs, int32_t accumulate,
+                                 int32_t softening, double *acc_dev,
+                                 double *pot_dev, void *stream);
+
 /* ---- leapfrog (kick-drift-kick) and block time-steps ------------------
  * kick: v += a h for the listed particles (all n when active_idx_dev is
  * NULL; then n_active_dev is ignored and n gives the count).  h = dt / 2,

@@ -135,6 +135,8 @@ def lib():
             "tg_walk_lists": (st, [P, f64, P, P, P, i64, P, i64, P, P]),
             "tg_direct_fp64": (st, [P, P, P, P, i64, P, P, i64, P, P, i32, i32,
                                     i32, P, P]),
+            "tg_direct_fp64_noalloc": (st, [P, P, P, i64, P, P, i64, P, P, i32, i32, i32,
+                                            i32, P, P, P]),
             "tg_kick": (st, [P, P, P, i64, P, P, P, f64, P, i32]),
             "tg_drift": (st, [P, P, P, i64, f64]),
             "tg_levels": (st, [P, P, P, i64, P, P, f64, i32, P, P]),
@@ -189,7 +191,7 @@ def lib():
 EXPORTED = ("tg_default_config", "tg_create", "tg_destroy", "tg_set_stream",
             "tg_set_sizes", "tg_build_tree", "tg_compute_moments",
             "tg_tree_forces", "tg_get_counts", "tg_reset_counts", "tg_walk_lists",
-            "tg_direct_fp64", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
+            "tg_direct_fp64", "tg_direct_fp64_noalloc", "tg_kick", "tg_drift", "tg_levels", "tg_levels_v",
             "tg_active_set", "tg_counter_add", "tg_set_external", "tg_set_mac", "tg_set_softening",
             "tg_refit_tree",
             "tg_perturbers", "tg_chain_forces", "tg_chains_forces", "tg_select_within",
@@ -222,6 +224,20 @@ def _i64_host(a):
         return None, None
     arr = np.ascontiguousarray(a, dtype=np.int64)
     return arr, arr.ctypes.data_as(C.c_void_p)
+
+
+def direct_fp64_noalloc(src_pos, src_mass, src_eps, tgt_pos, tgt_eps, acc, pot=None,
+                        src_seg=None, tgt_seg=None, self_pairs=False, accumulate=False,
+                        softening=TG_SOFT_PLUMMER, stream=None):
+    """tg_direct_fp64_noalloc on device tensors (no context; the library's
+    fixed scratch array; torch's current stream unless one is given)."""
+    sa, sp = _i64_host(src_seg)
+    ta, tp = _i64_host(tgt_seg)
+    nseg = 0 if sa is None else sa.shape[0] - 1
+    _check(lib().tg_direct_fp64_noalloc(
+        _ptr(src_pos), _ptr(src_mass), _ptr(src_eps), src_mass.shape[0], _ptr(tgt_pos),
+        _ptr(tgt_eps), tgt_pos.shape[0], sp, tp, nseg, int(bool(self_pairs)),
+        int(bool(accumulate)), int(softening), _ptr(acc), _ptr(pot), _stream_handle(stream)))
 
 
 def _stream_handle(stream):

@@ -241,16 +241,17 @@ __global__ __launch_bounds__(256) void k_drift_smbh(
   }
 }
 
-// Whether the star sums of n stars on nb SMBHs take the few-target path of
-// launch_direct (and so may be fused with the drift).
-static bool few_path(const tg_ctx *c, int64_t n, int64_t nt) {
+// Whether sums of n sources on nt targets take the few-target path of
+// launch_direct (part_cap doubles of partials; the star sums on the SMBHs
+// that take it may be fused with the drift).
+static bool few_path(int64_t part_cap, int64_t n, int64_t nt) {
   if (!(nt <= 4096 && n >= 2 * kFewPerBlock)) return false;
   const int64_t bpt = (n + kFewPerBlock - 1) / kFewPerBlock;
-  return bpt * nt * 8 <= c->b.dpart_cap && bpt <= 65535;
+  return bpt * nt * 8 <= part_cap && bpt <= 65535;
 }
 
 bool drift_smbh_fits(const tg_ctx *c, int64_t n, int32_t nb) {
-  return nb >= 1 && nb <= kDriftSmbhMax && few_path(c, n, nb);
+  return nb >= 1 && nb <= kDriftSmbhMax && few_path(c->b.dpart_cap, n, nb);
 }
 
 hipError_t launch_drift_smbh(tg_ctx *c, double *pos, const double *vel, const uint8_t *frozen,
@@ -274,6 +275,47 @@ hipError_t launch_drift_smbh(tg_ctx *c, double *pos, const double *vel, const ui
   return hipGetLastError();
 }
 
+hipError_t launch_direct_env(const DirectEnv &e, const int64_t *dseg, const double *spos,
+                             const double *sm, const double *seps, double seps_all,
+                             const double *tpos, const double *teps, int64_t nt, int nseg,
+                             int64_t max_seg_src, int self_pairs, int accumulate,
+                             double *acc, double *pot) {
+  if (nt == 0) return hipSuccess;
+  if (few_path(e.part_cap, max_seg_src, nt)) {
+    const int64_t bpt = (max_seg_src + kFewPerBlock - 1) / kFewPerBlock;
+    hipLaunchKernelGGL(k_direct_few, dim3((unsigned)bpt, (unsigned)nt), dim3(256), 0,
+                       e.stream, spos, sm, seps, seps_all, tpos, teps, nt, dseg,
+                       dseg + (nseg + 1), nseg, self_pairs, e.soft, e.part);
+    hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)std::min<int64_t>(nt, 4096)),
+                       dim3(256), 0, e.stream, nt, (int)bpt, accumulate, e.part, acc, pot);
+    return hipGetLastError();
+  }
+  // aim for >= 2^16 independent (target, chunk) sums; with part_cap >= 2^19
+  // doubles the partials of nt < 2^16 targets always fit at some chunk
+  int64_t nchunks = 1, chunk = std::max<int64_t>(max_seg_src, 1);
+  if (nt < 65536 && max_seg_src > 256) {
+    int64_t want = (65536 + nt - 1) / nt;
+    chunk = std::max<int64_t>(256, (max_seg_src + want - 1) / want);
+    nchunks = (max_seg_src + chunk - 1) / chunk;
+    while (nchunks > 1 && nchunks * nt * 8 > e.part_cap) {
+      chunk *= 2;
+      nchunks = (max_seg_src + chunk - 1) / chunk;
+    }
+  }
+  const int64_t total = nt * nchunks;
+  const int g = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_direct, dim3(g), dim3(256), 0, e.stream, spos, sm, seps,
+                     seps_all, tpos, teps, nt, dseg, dseg + (nseg + 1), nseg,
+                     chunk, (int)nchunks, self_pairs, accumulate, e.soft, acc, pot,
+                     e.part);
+  if (nchunks > 1) {
+    const int g2 = (int)std::min<int64_t>(nt, 4096);
+    hipLaunchKernelGGL(k_direct_reduce, dim3(g2), dim3(256), 0, e.stream, nt,
+                       (int)nchunks, accumulate, e.part, acc, pot);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
                          const double *sm, const double *seps, double seps_all,
                          int64_t ns, const double *tpos,
@@ -281,42 +323,9 @@ hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
                          int64_t max_seg_src, int self_pairs, int accumulate,
                          double *acc, double *pot) {
   (void)ns;
-  if (nt == 0) return hipSuccess;
-  if (few_path(c, max_seg_src, nt)) {
-    const int64_t bpt = (max_seg_src + kFewPerBlock - 1) / kFewPerBlock;
-    {
-      hipLaunchKernelGGL(k_direct_few, dim3((unsigned)bpt, (unsigned)nt), dim3(256), 0,
-                         c->stream, spos, sm, seps, seps_all, tpos, teps, nt, dseg,
-                         dseg + (nseg + 1), nseg, self_pairs, c->soft, c->b.dpart);
-      hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)std::min<int64_t>(nt, 4096)),
-                         dim3(256), 0, c->stream, nt, (int)bpt, accumulate, c->b.dpart,
-                         acc, pot);
-      return hipGetLastError();
-    }
-  }
-  // aim for >= 2^16 independent (target, chunk) sums
-  int64_t nchunks = 1, chunk = std::max<int64_t>(max_seg_src, 1);
-  if (nt < 65536 && max_seg_src > 256) {
-    int64_t want = (65536 + nt - 1) / nt;
-    chunk = std::max<int64_t>(256, (max_seg_src + want - 1) / want);
-    nchunks = (max_seg_src + chunk - 1) / chunk;
-    while (nchunks * nt * 8 > c->b.dpart_cap) {
-      chunk *= 2;
-      nchunks = (max_seg_src + chunk - 1) / chunk;
-    }
-  }
-  const int64_t total = nt * nchunks;
-  const int g = (int)std::min<int64_t>((total + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_direct, dim3(g), dim3(256), 0, c->stream, spos, sm, seps,
-                     seps_all, tpos, teps, nt, dseg, dseg + (nseg + 1), nseg,
-                     chunk, (int)nchunks, self_pairs, accumulate, c->soft, acc, pot,
-                     c->b.dpart);
-  if (nchunks > 1) {
-    const int g2 = (int)std::min<int64_t>(nt, 4096);
-    hipLaunchKernelGGL(k_direct_reduce, dim3(g2), dim3(256), 0, c->stream, nt,
-                       (int)nchunks, accumulate, c->b.dpart, acc, pot);
-  }
-  return hipGetLastError();
+  const DirectEnv e{c->stream, c->soft, c->b.dpart, c->b.dpart_cap};
+  return launch_direct_env(e, dseg, spos, sm, seps, seps_all, tpos, teps, nt, nseg,
+                           max_seg_src, self_pairs, accumulate, acc, pot);
 }
 
 }  // namespace tg

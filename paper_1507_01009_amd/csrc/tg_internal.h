@@ -184,6 +184,8 @@ namespace tg {
 // error reporting (tg_runtime.hip)
 tg_status fail(tg_status st, const std::string &msg);
 tg_status hip_fail(hipError_t e, const char *what);
+// msg must outlive the thread's next error (a literal or a HIP string)
+tg_status fail_literal(tg_status st, const char *msg);
 
 // Host exceptions never cross the C ABI: the entry points (and the helpers)
 // that build host containers are function-try-blocks ending in this
@@ -364,6 +366,19 @@ hipError_t launch_direct(tg_ctx *c, const int64_t *dseg, const double *spos,
                          const double *teps, int64_t nt, int nseg,
                          int64_t max_seg_src, int self_pairs, int accumulate,
                          double *acc, double *pot);
+// The same sums on any stream, softening and partial-sum buffer (part_cap
+// doubles, at least 2^19): the context's own, or the allocation-free one.
+struct DirectEnv {
+  hipStream_t stream;
+  int soft;
+  double *part;
+  int64_t part_cap;
+};
+hipError_t launch_direct_env(const DirectEnv &e, const int64_t *dseg, const double *spos,
+                             const double *sm, const double *seps, double seps_all,
+                             const double *tpos, const double *teps, int64_t nt, int nseg,
+                             int64_t max_seg_src, int self_pairs, int accumulate,
+                             double *acc, double *pot);
 
 // k_integrate.hip
 // frozen: [n] nonzero = star held still (ghost chain members in whole steps)

@@ -18,13 +18,24 @@ thread_local std::string g_last_error;
 
 namespace tg {
 
+// A message that is a string literal (or a HIP runtime string) is kept by
+// pointer, so reporting it allocates nothing.
+thread_local const char *g_last_literal = nullptr;
+
 tg_status fail(tg_status st, const std::string &msg) {
   g_last_error = msg;
+  g_last_literal = nullptr;
+  return st;
+}
+
+tg_status fail_literal(tg_status st, const char *msg) {
+  g_last_literal = msg;
   return st;
 }
 
 tg_status hip_fail(hipError_t e, const char *what) {
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  g_last_literal = nullptr;
   return TG_EHIP;
 }
 
@@ -39,7 +50,7 @@ using namespace tg;
 
 extern "C" {
 
-const char *tg_last_error(void) { return g_last_error.c_str(); }
+const char *tg_last_error(void) { return g_last_literal ? g_last_literal : g_last_error.c_str(); }
 
 const char *tg_version(void) {
   return "libtg gfx950 (HIP, wave64, FP64 + mixed walk)";
