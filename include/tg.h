@@ -568,8 +568,15 @@ tg_status tg_step_blocks(tg_ctx *ctx, const tg_system *sys, const tg_blocks *blo
 typedef struct tg_graph tg_graph;
 tg_status tg_graph_begin(tg_ctx *ctx);
 tg_status tg_graph_end(tg_ctx *ctx, tg_graph **out);
-/* A graph replays kernels on its context's buffers: launch it only while
- * the context lives (destroying it afterwards is fine). */
+/* A graph replays the captured kernels with the pointers, sizes and
+ * system layout they had, on its context's buffers: launch it only while
+ * the context lives (destroying it afterwards is fine).  The context's
+ * device tables that a graph reads (system offsets and sort tiles,
+ * direct-sum segment tables, external segments) are overwritten by a later
+ * eager call with a new layout (a tg_build_tree with other offsets, a
+ * segment table that evicts one of the 8 slots, tg_set_external with new
+ * segments); tg_graph_launch then returns TG_ESTATE without launching
+ * anything, and the step must be captured again. */
 tg_status tg_graph_launch(tg_graph *g, void *stream);
 void tg_graph_destroy(tg_graph *g);
 

@@ -170,6 +170,10 @@ struct tg_ctx {
   std::vector<int32_t> ext_seg_host;
   std::vector<std::vector<int64_t>> dseg_host;  // tables held in the device slots
   int dseg_next = 0;
+  // bumped whenever a device table that a captured graph may point into is
+  // overwritten (system layout and tiles, an evicted segment slot, the
+  // external segments); a graph replays only at its capture's generation
+  uint64_t layout_gen = 0;
   int64_t *host_words = nullptr;  // pinned [4]: device words read back by tg_step_blocks
   tg::Buffers b;
 };
@@ -177,6 +181,8 @@ struct tg_ctx {
 struct tg_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  const tg_ctx *ctx = nullptr;   // the context it was captured on
+  uint64_t gen = 0;              // ctx->layout_gen at the end of the capture
 };
 
 namespace tg {
@@ -344,6 +350,8 @@ struct ChainVec { double v[3 * kMaxChains]; };
 hipError_t launch_add_host_vector(tg_ctx *c, double *out, const ChainVec &add, int n3);
 // hybrid driver: rows of 3 doubles to (to_rows) or from indexed rows, and
 // per-row masses and flags
+hipError_t launch_gather_bytes(tg_ctx *c, uint8_t *dst, const uint8_t *src, const int32_t *idx,
+                               int n);
 hipError_t launch_move_rows(tg_ctx *c, double *dst, const double *src, const int32_t *idx, int n,
                             bool to_rows);
 hipError_t launch_set_rows(tg_ctx *c, double *mass, uint8_t *flag, const int32_t *idx,

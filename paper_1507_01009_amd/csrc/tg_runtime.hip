@@ -264,6 +264,7 @@ static tg_status set_layout(tg_ctx *c, int64_t n, const int64_t *off, int32_t S)
   if ((int64_t)tiles.size() > c->max_tiles)
     return fail(TG_ECAPACITY, "tg_build_tree: tile table too large");
   Buffers &b = c->b;
+  ++c->layout_gen;
   TG_HIP(hipMemcpyAsync(b.sysoff, so.data(), sizeof(int64_t) * (S + 1),
                         hipMemcpyHostToDevice, c->stream));
   TG_HIP(hipMemcpyAsync(b.sys_tile0, t0.data(), sizeof(uint32_t) * (S + 1),
@@ -589,6 +590,7 @@ tg_status tg_direct_fp64(tg_ctx *c, const double *spos, const double *sm,
       slot = c->dseg_next;
       c->dseg_next = (c->dseg_next + 1) % kSegSlots;
       c->dseg_host[slot] = seg;
+      ++c->layout_gen;          // an evicted slot is overwritten
     }
     TG_HIP(hipMemcpyAsync(c->b.dseg + slot * kSegSlotLen, seg.data(),
                           sizeof(int64_t) * seg.size(), hipMemcpyHostToDevice,
@@ -627,6 +629,7 @@ static tg_status tg_direct_fp64_eps(tg_ctx *c, const double *spos, const double 
       slot = c->dseg_next;
       c->dseg_next = (c->dseg_next + 1) % kSegSlots;
       c->dseg_host[slot] = seg;
+      ++c->layout_gen;          // an evicted slot is overwritten
     }
     TG_HIP(hipMemcpyAsync(c->b.dseg + slot * kSegSlotLen, seg.data(),
                           sizeof(int64_t) * seg.size(), hipMemcpyHostToDevice, c->stream));
@@ -742,12 +745,17 @@ tg_status tg_graph_end(tg_ctx *c, tg_graph **out) {
     delete g;
     return hip_fail(e, "tg_graph_end");
   }
+  g->ctx = c;
+  g->gen = c->layout_gen;
   *out = g;
   return TG_OK;
 }
 
 tg_status tg_graph_launch(tg_graph *g, void *stream) {
   if (!g) return fail(TG_EINVAL, "tg_graph_launch: NULL graph");
+  if (g->ctx && g->ctx->layout_gen != g->gen)
+    return fail(TG_ESTATE, "tg_graph_launch: the context's system layout or segment tables "
+                           "changed since the capture (capture again)");
   TG_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
   return TG_OK;
 }
@@ -876,6 +884,7 @@ tg_status tg_set_external(tg_ctx *c, const double *pos, const double *mass,
   if (seg != c->ext_seg_host) {
     if (c->capturing)
       return fail(TG_ESTATE, "tg_set_external: new segment layout during capture");
+    ++c->layout_gen;
     TG_HIP(hipMemcpyAsync(c->b.ext_seg, seg.data(), sizeof(int32_t) * (n_sys + 1),
                           hipMemcpyHostToDevice, c->stream));
     TG_HIP(hipStreamSynchronize(c->stream));

@@ -441,3 +441,55 @@ def test_frozen_stars_in_every_step_type():
     assert np.array_equal(keep[0].cpu().numpy(), level)
     assert np.max(np.abs(h["pos"] - st.pos)) <= 1e-12 * np.abs(st.pos).max()
     assert np.max(np.abs(h["vel"] - st.vel)) <= 1e-11 * np.abs(st.vel).max()
+
+
+def test_graph_refuses_launch_after_its_tables_change():
+    """A captured step reads the context's system offsets, sort tiles and
+    segment tables; an eager call that overwrites one of them (a build with
+    another layout, or enough new direct-sum segment tables to evict a slot)
+    makes tg_graph_launch refuse on the host, and a new capture runs again."""
+    say("graph refuses after a layout change")
+    import torch
+    from paper_1507_01009_amd import binding as B
+    w = ics.batch_c5(S=3, nmin=3000, nmax=6000)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = B.Context(w.n, max_systems=3, stream=s)
+        d = Dev(ctx, w)
+
+        def capture():
+            ctx.forces(d.sys)                   # layout and tables seen eagerly
+            ctx.sync()
+            ctx.graph_begin()
+            ctx.step_kdk(d.sys, 1e-3)
+            return ctx.graph_end()
+
+        g = capture()
+        g.launch(s)
+        s.synchronize()
+        ctx.sync()
+        # another layout: one system over all particles
+        ctx.build_tree(d.pos)
+        ctx.sync()
+        with pytest.raises(B.TGError) as e:
+            g.launch(s)
+        assert e.value.status == -5 and "capture again" in str(e.value)
+        g = capture()
+        g.launch(s)
+        s.synchronize()
+        ctx.sync()
+        # nine new segment tables evict at least one slot the graph uses
+        x = torch.zeros((8, 3), dtype=torch.float64, device="cuda")
+        x[:, 0] = torch.arange(8, dtype=torch.float64, device="cuda")
+        m = torch.ones(8, dtype=torch.float64, device="cuda")
+        ep = torch.full((8,), 0.1, dtype=torch.float64, device="cuda")
+        out = torch.zeros((8, 3), dtype=torch.float64, device="cuda")
+        for k in range(9):
+            seg = np.array([0, k % 8, 8]) if k < 8 else np.array([0, 8])
+            ctx.direct_fp64(x, m, ep, x, ep, out, src_seg=seg, tgt_seg=np.array([0, 4, 8])
+                            if k < 8 else np.array([0, 8]))
+        ctx.sync()
+        with pytest.raises(B.TGError) as e:
+            g.launch(s)
+        assert e.value.status == -5
+        del g
