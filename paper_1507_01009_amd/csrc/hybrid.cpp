@@ -4,7 +4,11 @@
 // the chain particle with the correction of Eq. 3, and the membership
 // rules (Eq. 4, Eq. 5).  Every GPU stage is one of the library's calls;
 // this file holds the bookkeeping: which stars are members (ghosts in the
-// star arrays), the chain's centre of mass, and the order of the stages.
+// star arrays, never advanced: their rows keep the state they had when they
+// joined), the chain's centre of mass, and the order of the stages (the
+// chain step before the tree forces; membership when chain and tree share
+// a time; in block substeps every velocity brought into step at a
+// hand-off).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -122,19 +126,6 @@ void reform(tg_hybrid *h, const std::vector<double> &X, const std::vector<double
     }
 }
 
-// The members' global coordinates R + x, V + v.
-void globals(const tg_hybrid *h, std::vector<double> &X, std::vector<double> &W) {
-#pragma clang fp contract(off)
-  const int n = nc(h);
-  X.resize(3 * n);
-  W.resize(3 * n);
-  for (int i = 0; i < n; ++i)
-    for (int k = 0; k < 3; ++k) {
-      X[3 * i + k] = h->R[k] + h->x[3 * i + k];
-      W[3 * i + k] = h->V[k] + h->v[3 * i + k];
-    }
-}
-
 double max_radius(const tg_hybrid *h) {
 #pragma clang fp contract(off)
   double r2 = 0.0;
@@ -145,47 +136,31 @@ double max_radius(const tg_hybrid *h) {
   return std::sqrt(r2);
 }
 
-// Write the members' global coordinates into the star arrays (ghosts) and
-// the SMBH's arrays; also the member positions and masses for the coupling.
-// One upload of the staged block, two row scatters, the SMBH's rows copied
-// on the device.
-tg_status write_members(tg_hybrid *h) {
+// Stage the members' global positions and masses for the coupling, and
+// write the SMBH member's global coordinates (velocity relative to Vref)
+// into its arrays (reference only: it is not a tree particle).  One upload
+// of the staged block and, with the SMBH a member, two device copies.  The
+// ghosts' rows are not touched.
+tg_status stage_members(tg_hybrid *h, const double *Vref) {
 #pragma clang fp contract(off)
   const int n = nc(h);
-  int32_t *ids = reinterpret_cast<int32_t *>(h->h_stage + kOffIds);
-  double *rows = reinterpret_cast<double *>(h->h_stage + kOffRows);
   double *mpos = reinterpret_cast<double *>(h->h_stage + kOffMpos);
   double *mmass = reinterpret_cast<double *>(h->h_stage + kOffMmass);
   double *bh = reinterpret_cast<double *>(h->h_stage + kOffBh);
-  int k = 0;
   bool smbh = false;
   for (int i = 0; i < n; ++i) {
-    double X[3], W[3];
-    for (int d = 0; d < 3; ++d) {
-      X[d] = h->R[d] + h->x[3 * i + d];
-      W[d] = h->V[d] + h->v[3 * i + d];
-      mpos[3 * i + d] = X[d];
-    }
+    for (int d = 0; d < 3; ++d) mpos[3 * i + d] = h->R[d] + h->x[3 * i + d];
     mmass[i] = h->m[i];
     if (h->star[i] < 0) {
       for (int d = 0; d < 3; ++d) {
-        bh[d] = X[d];
-        bh[3 + d] = W[d];
+        bh[d] = mpos[3 * i + d];
+        bh[3 + d] = Vref[d] + h->v[3 * i + d];
       }
       smbh = true;
-      continue;
     }
-    ids[k] = h->star[i];
-    for (int d = 0; d < 3; ++d) {
-      rows[3 * k + d] = X[d];
-      rows[3 * kMaxChain + 3 * k + d] = W[d];
-    }
-    ++k;
   }
   hipStream_t sm = h->c->stream;
   TG_HIP(hipMemcpyAsync(h->d_stage, h->h_stage, kStageBytes, hipMemcpyHostToDevice, sm));
-  TG_HIP(launch_move_rows(h->c, h->sys.pos, h->d_rows, h->d_ids, k, true));
-  TG_HIP(launch_move_rows(h->c, h->sys.vel, h->d_rows + 3 * kMaxChain, h->d_ids, k, true));
   if (smbh) {
     TG_HIP(hipMemcpyAsync(h->sys.bh_pos, h->d_bh, 3 * sizeof(double), hipMemcpyDeviceToDevice,
                           sm));
@@ -194,6 +169,47 @@ tg_status write_members(tg_hybrid *h) {
   }
   TG_HIP(hipStreamSynchronize(sm));
   return TG_OK;
+}
+
+// The SMBH's arrays := X, W (a freed SMBH, or the member's reference copy).
+tg_status write_smbh(tg_hybrid *h, const double *X, const double *W) {
+  double *bh = reinterpret_cast<double *>(h->h_stage + kOffBh);
+  for (int d = 0; d < 3; ++d) {
+    bh[d] = X[d];
+    bh[3 + d] = W[d];
+  }
+  hipStream_t sm = h->c->stream;
+  TG_HIP(hipMemcpyAsync(h->sys.bh_pos, bh, 3 * sizeof(double), hipMemcpyHostToDevice, sm));
+  TG_HIP(hipMemcpyAsync(h->sys.bh_vel, bh + 3, 3 * sizeof(double), hipMemcpyHostToDevice, sm));
+  TG_HIP(hipStreamSynchronize(sm));
+  return TG_OK;
+}
+
+tg_status set_ghosts(tg_hybrid *h, const std::vector<int32_t> &ids,
+                     const std::vector<double> &mass, bool ghost);
+
+// Stars that leave the chain: rows := their global coordinates (X, W per
+// star, [k][3]), mass restored, no longer excluded.
+tg_status restore_rows(tg_hybrid *h, const std::vector<int32_t> &ids,
+                       const std::vector<double> &X, const std::vector<double> &W,
+                       const std::vector<double> &mass) {
+  const int k = (int)ids.size();
+  if (!k) return TG_OK;
+  int32_t *sid = reinterpret_cast<int32_t *>(h->h_stage + kOffIds);
+  double *rows = reinterpret_cast<double *>(h->h_stage + kOffRows);
+  for (int i = 0; i < k; ++i) {
+    sid[i] = ids[i];
+    for (int d = 0; d < 3; ++d) {
+      rows[3 * i + d] = X[3 * i + d];
+      rows[3 * kMaxChain + 3 * i + d] = W[3 * i + d];
+    }
+  }
+  hipStream_t sm = h->c->stream;
+  TG_HIP(hipMemcpyAsync(h->d_stage, h->h_stage, kStageBytes, hipMemcpyHostToDevice, sm));
+  TG_HIP(launch_move_rows(h->c, h->sys.pos, h->d_rows, h->d_ids, k, true));
+  TG_HIP(launch_move_rows(h->c, h->sys.vel, h->d_rows + 3 * kMaxChain, h->d_ids, k, true));
+  TG_HIP(hipStreamSynchronize(sm));
+  return set_ghosts(h, ids, mass, false);
 }
 
 // The chain particle's force and the perturber count of the last coupling
@@ -254,7 +270,7 @@ tg_status forces(tg_hybrid *h) {
     if ((st = tg_forces(h->c, &h->sys, nullptr, nullptr))) return st;
     return tg_sync(h->c, nullptr);
   }
-  if ((st = write_members(h))) return st;
+  if ((st = stage_members(h, h->V))) return st;
   tg_system y = h->sys;
   y.n_bh = 0;
   if ((st = tg_forces(h->c, &y, nullptr, nullptr))) return st;
@@ -271,7 +287,7 @@ tg_status forces(tg_hybrid *h) {
 // and the perturber count read back.
 tg_status coupling(tg_hybrid *h) {
   tg_status st;
-  if ((st = write_members(h))) return st;
+  if ((st = stage_members(h, h->V))) return st;
   tg_chain ch = chain_of(h);
   if ((st = tg_chain_forces(h->c, &ch, nullptr, nullptr, h->sys.acc, h->sys.pot, h->d_com,
                             h->d_macc)))
@@ -381,16 +397,57 @@ tg_status maybe_start(tg_hybrid *h) {
   return forces(h);
 }
 
-// Membership after a step: absorb, escape, or end the chain.
-tg_status membership(tg_hybrid *h) {
-  std::vector<double> px, pv, pm;
-  std::vector<int32_t> pids;
+// Accelerations of the listed stars ([k][3]).
+tg_status read_acc(tg_hybrid *h, const std::vector<int32_t> &ids, std::vector<double> &A) {
+  const int k = (int)ids.size();
+  A.assign(3 * k, 0.0);
+  if (!k) return TG_OK;
   tg_status st;
-  if ((st = perturbers(h, px, pv, pm, &pids))) return st;
+  if ((st = to_dev(h, h->d_ids, ids.data(), sizeof(int32_t) * k))) return st;
+  TG_HIP(launch_move_rows(h->c, h->d_rows, h->sys.acc, h->d_ids, k, false));
+  return to_host(h, A.data(), h->d_rows, sizeof(double) * 3 * k);
+}
+
+// Block levels of the listed stars (in batches of kMaxChain).
+tg_status read_levels(tg_hybrid *h, const tg_blocks *b, const std::vector<int32_t> &ids,
+                      std::vector<uint8_t> &lv) {
+  lv.assign(ids.size(), 0);
+  tg_status st;
+  for (size_t o = 0; o < ids.size(); o += kMaxChain) {
+    const int k = (int)std::min<size_t>(kMaxChain, ids.size() - o);
+    if ((st = to_dev(h, h->d_ids, ids.data() + o, sizeof(int32_t) * k))) return st;
+    TG_HIP(launch_gather_bytes(h->c, h->d_flag, b->level, h->d_ids, k));
+    if ((st = to_host(h, lv.data() + o, h->d_flag, (size_t)k))) return st;
+  }
+  return TG_OK;
+}
+
+// Whether a star on level l ends a step at substep k.
+bool ends_at(uint8_t l, int64_t k, int nlev) {
+  const int64_t per = (int64_t)1 << (nlev - 1 - (int)l);
+  return k % per == 0;
+}
+
+// Velocities of stars at the end of their own step: W = v + a h with the
+// pending closing half kick h = (dt_max 2^-level) / 2 (the kick's rounding).
+void sync_vel(const std::vector<double> &v, const std::vector<double> &a,
+              const std::vector<uint8_t> &lv, double dt_max, std::vector<double> &W) {
+#pragma clang fp contract(off)
+  W.resize(v.size());
+  for (size_t i = 0; i < lv.size(); ++i) {
+    const double hk = std::ldexp(dt_max, -(int)lv[i]) * 0.5;
+    for (int d = 0; d < 3; ++d) W[3 * i + d] = v[3 * i + d] + a[3 * i + d] * hk;
+  }
+}
+
+// The membership routine on the members and the listed perturber offsets.
+tg_status decide(tg_hybrid *h, const std::vector<double> &px, int np,
+                 std::vector<int32_t> &ab, std::vector<int32_t> &es, tg_membership_out &out) {
   const int n = nc(h);
   std::vector<uint8_t> massive(n, 0);
   for (int i = 0; i < n; ++i) massive[i] = h->star[i] < 0 ? 1 : 0;
-  std::vector<int32_t> ab(std::max<size_t>(pids.size(), 1)), es(n);
+  ab.assign(std::max(np, 1), 0);
+  es.assign(std::max(n, 1), 0);
   tg_membership_in in{};
   in.n = n;
   in.x = h->x.data();
@@ -401,28 +458,46 @@ tg_status membership(tg_hybrid *h) {
   in.r_chain = h->r_chain;
   in.r_chain0 = h->cfg.r_chain0;
   in.gamma = h->cfg.gamma_esc;
-  in.np = (int32_t)pids.size();
+  in.np = np;
   in.px = px.data();
-  tg_membership_out out{};
+  out = tg_membership_out{};
   out.absorb = ab.data();
   out.escape = es.data();
-  if ((st = tg_chain_membership(&in, &out))) return st;
-  if (n - out.n_escape + out.n_absorb > kMaxChain && !out.terminate)
-    return fail(TG_ECAPACITY, "tg_hybrid_step: more than 256 chain members");
-  if (!out.terminate && out.n_absorb == 0 && out.n_escape == 0) return TG_OK;
-  std::vector<double> X, W;
-  globals(h, X, W);
-  std::vector<int32_t> back;
-  std::vector<double> back_m;
+  return tg_chain_membership(&in, &out);
+}
+
+// The chain after a membership decision: the leaving members go back to
+// the tree with their global coordinates (velocities relative to Vref),
+// the joining stars (global X, W given) are appended and become ghosts.
+// Returns the rows of the stars that left in *back.
+tg_status apply_membership(tg_hybrid *h, const tg_membership_out &out,
+                           const std::vector<int32_t> &es, const double *Vref,
+                           const std::vector<int32_t> &join, const std::vector<double> &JX,
+                           const std::vector<double> &JW, const std::vector<double> &jm,
+                           std::vector<int32_t> *back) {
+#pragma clang fp contract(off)
+  const int n = nc(h);
+  std::vector<double> X(3 * n), W(3 * n);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      X[3 * i + k] = h->R[k] + h->x[3 * i + k];
+      W[3 * i + k] = Vref[k] + h->v[3 * i + k];
+    }
   std::vector<bool> leaves(n, out.terminate != 0);
   for (int e = 0; e < out.n_escape; ++e) leaves[es[e]] = true;
   std::vector<int32_t> star;
-  std::vector<double> m, GX, GW;
+  std::vector<double> m, GX, GW, BX, BW, bm;
+  back->clear();
+  tg_status st;
   for (int i = 0; i < n; ++i) {
     if (leaves[i]) {
       if (h->star[i] >= 0) {
-        back.push_back(h->star[i]);
-        back_m.push_back(h->m[i]);
+        back->push_back(h->star[i]);
+        bm.push_back(h->m[i]);
+        BX.insert(BX.end(), &X[3 * i], &X[3 * i] + 3);
+        BW.insert(BW.end(), &W[3 * i], &W[3 * i] + 3);
+      } else if ((st = write_smbh(h, &X[3 * i], &W[3 * i]))) {
+        return st;
       }
       continue;
     }
@@ -431,10 +506,8 @@ tg_status membership(tg_hybrid *h) {
     GX.insert(GX.end(), &X[3 * i], &X[3 * i] + 3);
     GW.insert(GW.end(), &W[3 * i], &W[3 * i] + 3);
   }
-  // the members' global coordinates are already in the arrays
-  if ((st = write_members(h))) return st;
-  if ((st = set_ghosts(h, back, back_m, false))) return st;
-  h->escaped += (int64_t)back.size();
+  if ((st = restore_rows(h, *back, BX, BW, bm))) return st;
+  h->escaped += (int64_t)back->size();
   if (out.terminate) {
     h->active = false;
     h->star.clear();
@@ -442,13 +515,10 @@ tg_status membership(tg_hybrid *h) {
     h->v.clear();
     h->m.clear();
     h->n_pert = 0;
+    for (int k = 0; k < 3; ++k) h->a_com[k] = 0.0;
     ++h->ended;
-    return forces(h);
+    return TG_OK;
   }
-  std::vector<int32_t> join;
-  for (int a = 0; a < out.n_absorb; ++a) join.push_back(pids[ab[a]]);
-  std::vector<double> JX, JW, jm;
-  if ((st = read_stars(h, join, JX, JW, jm))) return st;
   star.insert(star.end(), join.begin(), join.end());
   m.insert(m.end(), jm.begin(), jm.end());
   GX.insert(GX.end(), JX.begin(), JX.end());
@@ -459,6 +529,29 @@ tg_status membership(tg_hybrid *h) {
   if ((st = ar_init(h))) return st;
   if ((st = set_ghosts(h, join, jm, true))) return st;
   h->absorbed += (int64_t)join.size();
+  return TG_OK;
+}
+
+// Membership at the end of a step (positions and velocities in step):
+// absorb, escape, or end the chain; the forces again after a change.
+tg_status membership(tg_hybrid *h) {
+  std::vector<double> px, pv, pm;
+  std::vector<int32_t> pids, ab, es;
+  tg_status st;
+  if ((st = perturbers(h, px, pv, pm, &pids))) return st;
+  tg_membership_out out;
+  if ((st = decide(h, px, (int)pids.size(), ab, es, out))) return st;
+  if (!out.terminate && out.n_absorb == 0 && out.n_escape == 0) return TG_OK;
+  if (nc(h) - out.n_escape + out.n_absorb > kMaxChain && !out.terminate)
+    return fail(TG_ECAPACITY, "tg_hybrid_step: more than 256 chain members");
+  std::vector<int32_t> join, back;
+  std::vector<double> JX, JW, jm;
+  if (!out.terminate) {
+    for (int a = 0; a < out.n_absorb; ++a) join.push_back(pids[ab[a]]);
+    if ((st = read_stars(h, join, JX, JW, jm))) return st;
+  }
+  const double V0[3] = {h->V[0], h->V[1], h->V[2]};
+  if ((st = apply_membership(h, out, es, V0, join, JX, JW, jm, &back))) return st;
   return forces(h);
 }
 
@@ -471,7 +564,7 @@ tg_status forces_list(tg_hybrid *h, const int32_t *idx, const int32_t *n_act) {
     if ((st = tg_forces(h->c, &h->sys, idx, n_act))) return st;
     return tg_sync(h->c, nullptr);
   }
-  if ((st = write_members(h))) return st;
+  if ((st = stage_members(h, h->V))) return st;
   tg_system y = h->sys;
   y.n_bh = 0;
   if ((st = tg_forces(h->c, &y, idx, n_act))) return st;
@@ -484,9 +577,11 @@ tg_status forces_list(tg_hybrid *h, const int32_t *idx, const int32_t *n_act) {
 }
 
 // Block substeps: stars that return to the tree (escaped, or all members of
-// a chain that ends) go to the finest level, which is active at every
-// substep, and get their forces now; the chain particle's force is formed
-// again for the new membership.
+// a chain that ends) go to the finest level, which ends a step at every
+// substep, and get their forces now (with a chain, the chain particle's
+// force is formed again for the new membership; without, the SMBH's).
+// Their velocities, in step, are then stored half a kick back, so the next
+// substep's closing half kick brings them into step.
 tg_status returned_stars(tg_hybrid *h, const tg_blocks *b, const std::vector<int32_t> &back) {
   const int k = (int)back.size();
   std::vector<uint8_t> lv(k, (uint8_t)(b->nlev - 1));
@@ -495,91 +590,75 @@ tg_status returned_stars(tg_hybrid *h, const tg_blocks *b, const std::vector<int
     if ((st = to_dev(h, b->level + back[i], &lv[i], 1))) return st;
   if ((st = to_dev(h, h->d_sel, back.data(), sizeof(int32_t) * k))) return st;
   if ((st = to_dev(h, h->d_nsel, &k, sizeof(int32_t)))) return st;
-  return forces_list(h, h->d_sel, h->d_nsel);
+  if ((st = forces_list(h, h->d_sel, h->d_nsel))) return st;
+  if (k)
+    TG_HIP(launch_kick(h->c, h->sys.vel, h->sys.acc, h->sys.n, h->d_sel, h->d_nsel, b->level,
+                       -b->dt_max, nullptr, 0, nullptr));
+  return TG_OK;
 }
 
-tg_status membership_block(tg_hybrid *h, const tg_blocks *b) {
+// Membership at substep k (the new counter), every velocity in step: the
+// chain particle's with its pending closing half kick; perturbers are
+// absorbed only at a substep where their own step ends.
+tg_status membership_block(tg_hybrid *h, const tg_blocks *b, int64_t k) {
+#pragma clang fp contract(off)
+  const double dt_min = std::ldexp(b->dt_max, -(b->nlev - 1));
+  double Vs[3];
+  for (int d = 0; d < 3; ++d) Vs[d] = h->V[d] + h->a_com[d] * (0.5 * dt_min);
   std::vector<double> px, pv, pm;
-  std::vector<int32_t> pids;
+  std::vector<int32_t> pids, ab, es;
   tg_status st;
   if ((st = perturbers(h, px, pv, pm, &pids))) return st;
-  const int n = nc(h);
-  std::vector<uint8_t> massive(n, 0);
-  for (int i = 0; i < n; ++i) massive[i] = h->star[i] < 0 ? 1 : 0;
-  std::vector<int32_t> ab(std::max<size_t>(pids.size(), 1)), es(n);
-  tg_membership_in in{};
-  in.n = n;
-  in.x = h->x.data();
-  in.v = h->v.data();
-  in.m = h->m.data();
-  in.massive = massive.data();
-  in.designated = 0;
-  in.r_chain = h->r_chain;
-  in.r_chain0 = h->cfg.r_chain0;
-  in.gamma = h->cfg.gamma_esc;
-  in.np = (int32_t)pids.size();
-  in.px = px.data();
-  tg_membership_out out{};
-  out.absorb = ab.data();
-  out.escape = es.data();
-  if ((st = tg_chain_membership(&in, &out))) return st;
-  if (!out.terminate && out.n_absorb == 0 && out.n_escape == 0) return TG_OK;
-  if (n - out.n_escape + out.n_absorb > kMaxChain && !out.terminate)
-    return fail(TG_ECAPACITY, "tg_hybrid_step_block: more than 256 chain members");
-  std::vector<double> X, W;
-  globals(h, X, W);
-  std::vector<bool> leaves(n, out.terminate != 0);
-  for (int e = 0; e < out.n_escape; ++e) leaves[es[e]] = true;
-  std::vector<int32_t> back, star;
-  std::vector<double> back_m, m, GX, GW;
-  for (int i = 0; i < n; ++i) {
-    if (leaves[i]) {
-      if (h->star[i] >= 0) {
-        back.push_back(h->star[i]);
-        back_m.push_back(h->m[i]);
+  const int np = (int)pids.size();
+  tg_membership_out out;
+  if ((st = decide(h, px, np, ab, es, out))) return st;
+  if (out.n_absorb > 0) {
+    // candidates whose step does not end now are out of reach this substep
+    std::vector<int32_t> cand;
+    for (int a = 0; a < out.n_absorb; ++a) cand.push_back(pids[ab[a]]);
+    std::vector<uint8_t> lv;
+    if ((st = read_levels(h, b, cand, lv))) return st;
+    bool again = false;
+    for (int a = 0; a < out.n_absorb; ++a)
+      if (!ends_at(lv[a], k, b->nlev)) {
+        for (int d = 0; d < 3; ++d) px[3 * ab[a] + d] = 1e100;
+        again = true;
       }
-      continue;
-    }
-    star.push_back(h->star[i]);
-    m.push_back(h->m[i]);
-    GX.insert(GX.end(), &X[3 * i], &X[3 * i] + 3);
-    GW.insert(GW.end(), &W[3 * i], &W[3 * i] + 3);
+    if (again && (st = decide(h, px, np, ab, es, out))) return st;
   }
-  if ((st = write_members(h))) return st;
-  if ((st = set_ghosts(h, back, back_m, false))) return st;
-  h->escaped += (int64_t)back.size();
-  if (out.terminate) {
-    h->active = false;
-    h->star.clear();
-    h->x.clear();
-    h->v.clear();
-    h->m.clear();
-    h->n_pert = 0;
-    ++h->ended;
-    return returned_stars(h, b, back);
+  if (!out.terminate && out.n_absorb == 0 && out.n_escape == 0) return TG_OK;
+  if (nc(h) - out.n_escape + out.n_absorb > kMaxChain && !out.terminate)
+    return fail(TG_ECAPACITY, "tg_hybrid_step_block: more than 256 chain members");
+  std::vector<int32_t> join, back;
+  std::vector<double> JX, JV, JW, jm, JA;
+  if (!out.terminate) {
+    for (int a = 0; a < out.n_absorb; ++a) join.push_back(pids[ab[a]]);
+    std::vector<uint8_t> jl;
+    if ((st = read_stars(h, join, JX, JV, jm))) return st;
+    if ((st = read_acc(h, join, JA))) return st;
+    if ((st = read_levels(h, b, join, jl))) return st;
+    sync_vel(JV, JA, jl, b->dt_max, JW);
   }
-  std::vector<int32_t> join;
-  for (int a = 0; a < out.n_absorb; ++a) join.push_back(pids[ab[a]]);
-  std::vector<double> JX, JW, jm;
-  if ((st = read_stars(h, join, JX, JW, jm))) return st;
-  star.insert(star.end(), join.begin(), join.end());
-  m.insert(m.end(), jm.begin(), jm.end());
-  GX.insert(GX.end(), JX.begin(), JX.end());
-  GW.insert(GW.end(), JW.begin(), JW.end());
-  h->star = star;
-  h->m = m;
-  reform(h, GX, GW);
-  if ((st = ar_init(h))) return st;
-  if ((st = set_ghosts(h, join, jm, true))) return st;
-  h->absorbed += (int64_t)join.size();
-  return returned_stars(h, b, back);
+  const bool ends = out.terminate != 0;
+  if ((st = apply_membership(h, out, es, Vs, join, JX, JW, jm, &back))) return st;
+  if ((st = returned_stars(h, b, back))) return st;
+  if (ends) {
+    TG_HIP(launch_kick(h->c, h->sys.bh_vel, h->sys.bh_acc, 1, nullptr, nullptr, nullptr,
+                       -dt_min, nullptr, 0, nullptr));
+    return tg_sync(h->c, nullptr);
+  }
+  for (int d = 0; d < 3; ++d) h->V[d] = h->V[d] - h->a_com[d] * (0.5 * dt_min);
+  return tg_sync(h->c, nullptr);
 }
 
-// A chain starting inside block substeps: as maybe_start, then only the
-// chain particle's force (no star gets new forces).
-tg_status maybe_start_block(tg_hybrid *h, const tg_blocks *b) {
-  (void)b;
-  double bp[3], bv[3], bm;
+// A chain starting at substep k (the new counter): the stars within
+// r_chain0 of the SMBH whose own step ends at k join it; every velocity is
+// brought into step (the SMBH's and the stars' pending closing half
+// kicks); then only the chain particle's force (no star gets new forces),
+// and the chain particle is stored half a kick back.
+tg_status maybe_start_block(tg_hybrid *h, const tg_blocks *b, int64_t kk) {
+#pragma clang fp contract(off)
+  double bp[3], bv[3], ba[3], bm;
   tg_status st;
   if ((st = to_host(h, bp, h->sys.bh_pos, sizeof(bp)))) return st;
   if ((st = tg_select_within(h->c, h->sys.pos, h->sys.n, nullptr, bp, h->cfg.r_chain0, h->d_sel,
@@ -589,12 +668,24 @@ tg_status maybe_start_block(tg_hybrid *h, const tg_blocks *b) {
   int32_t k = 0;
   if ((st = to_host(h, &k, h->d_nsel, sizeof(int32_t)))) return st;
   if (k < 1) return TG_OK;
-  std::vector<int32_t> ids(k);
-  if ((st = to_host(h, ids.data(), h->d_sel, sizeof(int32_t) * k))) return st;
-  std::vector<double> X, W, mass;
-  if ((st = read_stars(h, ids, X, W, mass))) return st;
+  std::vector<int32_t> all(k), ids;
+  if ((st = to_host(h, all.data(), h->d_sel, sizeof(int32_t) * k))) return st;
+  std::vector<uint8_t> lv;
+  if ((st = read_levels(h, b, all, lv))) return st;
+  for (int i = 0; i < k; ++i)
+    if (ends_at(lv[i], kk, b->nlev)) ids.push_back(all[i]);
+  if (ids.empty()) return TG_OK;
+  std::vector<double> X, V, A, W, mass;
+  std::vector<uint8_t> il;
+  if ((st = read_stars(h, ids, X, V, mass))) return st;
+  if ((st = read_acc(h, ids, A))) return st;
+  if ((st = read_levels(h, b, ids, il))) return st;
+  sync_vel(V, A, il, b->dt_max, W);
   if ((st = to_host(h, bv, h->sys.bh_vel, sizeof(bv)))) return st;
+  if ((st = to_host(h, ba, h->sys.bh_acc, sizeof(ba)))) return st;
   if ((st = to_host(h, &bm, h->sys.bh_mass, sizeof(double)))) return st;
+  const double dt_min = std::ldexp(b->dt_max, -(b->nlev - 1));
+  for (int d = 0; d < 3; ++d) bv[d] = bv[d] + ba[d] * (dt_min * 0.5);
   std::vector<double> GX(bp, bp + 3), GW(bv, bv + 3);
   GX.insert(GX.end(), X.begin(), X.end());
   GW.insert(GW.end(), W.begin(), W.end());
@@ -609,7 +700,9 @@ tg_status maybe_start_block(tg_hybrid *h, const tg_blocks *b) {
   ++h->starts;
   const int32_t zero = 0;
   if ((st = to_dev(h, h->d_nsel, &zero, sizeof(int32_t)))) return st;
-  return forces_list(h, h->d_sel, h->d_nsel);
+  if ((st = forces_list(h, h->d_sel, h->d_nsel))) return st;
+  for (int d = 0; d < 3; ++d) h->V[d] = h->V[d] - h->a_com[d] * (0.5 * dt_min);
+  return TG_OK;
 }
 
 }  // namespace
@@ -690,20 +783,18 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) try {
     return maybe_start(h);
   }
   const int64_t n = h->sys.n;
-  // half kick of the stars and of the chain particle
-  if ((st = tg_kick(h->c, h->sys.vel, h->sys.acc, n, nullptr, nullptr, nullptr, dt, nullptr, 0)))
-    return st;
+  // (6) opening half kick of the stars (ghosts stay) and of the chain particle
+  TG_HIP(launch_kick(h->c, h->sys.vel, h->sys.acc, n, nullptr, nullptr, nullptr, dt, nullptr, 0,
+                     h->d_excl));
   for (int k = 0; k < 3; ++k) h->V[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
-  // the perturbers at the start of the step, relative to the chain particle
+  // (3) the chain step: the perturbers of the last coupling on the straight
+  // lines of this step's drift, relative to the chain particle
   std::vector<double> px, pv, pm;
   if ((st = perturbers(h, px, pv, pm, nullptr))) return st;
-  // drift; the members move in the chain over the whole step
-  if ((st = tg_drift(h->c, h->sys.pos, h->sys.vel, n, dt))) return st;
+  // (6) drift, and the tree forces at the new positions (ghosts where they
+  // joined, no SMBH), queued on the GPU while the chain advances on the host
+  TG_HIP(launch_drift(h->c, h->sys.pos, h->sys.vel, n, dt, h->d_excl));
   for (int k = 0; k < 3; ++k) h->R[k] = h->R[k] + h->V[k] * dt;
-  // the tree sees the ghosts where the chain particle has carried them (R
-  // plus the members' offsets from the start of the step), so its forces
-  // run on the GPU while the chain advances on the host
-  if ((st = write_members(h))) return st;
   {
     tg_system y = h->sys;
     y.n_bh = 0;
@@ -732,12 +823,13 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) try {
   h->ds = s.ds;
   if ((st = tg_archain_energy(&s, h->G, &h->energy_error))) return st;
   h->r_chain = max_radius(h);
-  // the coupling with the members' new positions, then the second half kick
+  // (6b) the coupling with the members' new positions, (6c) closing half kick
   if ((st = coupling(h))) return st;
-  if ((st = tg_kick(h->c, h->sys.vel, h->sys.acc, n, nullptr, nullptr, nullptr, dt, nullptr, 0)))
-    return st;
+  TG_HIP(launch_kick(h->c, h->sys.vel, h->sys.acc, n, nullptr, nullptr, nullptr, dt, nullptr, 0,
+                     h->d_excl));
   for (int k = 0; k < 3; ++k) h->V[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
-  if ((st = write_members(h))) return st;
+  if ((st = stage_members(h, h->V))) return st;
+  // (4)-(5) with chain and tree at the same time, then (8)
   if ((st = membership(h))) return st;
   return h->active ? TG_OK : maybe_start(h);
 } TG_HOST_CATCH("tg_hybrid_step")
@@ -748,27 +840,30 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) try {
   Timer whole(h->step_s);
   tg_status st;
   ++h->steps;
+  int64_t k0 = 0;
   if (!h->active) {
     if ((st = tg_step_block(h->c, &h->sys, b))) return st;
     if ((st = tg_sync(h->c, nullptr))) return st;
-    return maybe_start_block(h, b);
+    if ((st = to_host(h, &k0, b->k, sizeof(int64_t)))) return st;
+    return maybe_start_block(h, b, k0);
   }
   const double dt = std::ldexp(b->dt_max, -(b->nlev - 1));
-  int64_t k0 = 0;
   if ((st = to_host(h, &k0, b->k, sizeof(int64_t)))) return st;
+  // the stars' closing kicks, levels and opening kicks (ghosts are frozen)
   if ((st = block_stars_kick(h->c, &h->sys, b))) return st;
   // the chain particle sits on the finest level: closing (not at k = 0)
   // and opening half kicks with the force of the last substep
   if (k0 != 0)
     for (int k = 0; k < 3; ++k) h->V[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
   for (int k = 0; k < 3; ++k) h->V[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
+  // (3) the chain step over the substep, the perturbers on the straight
+  // lines of their drift
   std::vector<double> px, pv, pm;
   if ((st = perturbers(h, px, pv, pm, nullptr))) return st;
   if ((st = block_stars_drift(h->c, &h->sys, b))) return st;
   for (int k = 0; k < 3; ++k) h->R[k] = h->R[k] + h->V[k] * dt;
   // tree forces of the stars active at the new k, queued while the chain
-  // advances on the host (ghosts carried by the chain particle)
-  if ((st = write_members(h))) return st;
+  // advances on the host
   {
     tg_system y = h->sys;
     y.n_bh = 0;
@@ -799,7 +894,7 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) try {
   h->r_chain = max_radius(h);
   // the coupling for the same stars with the members' new positions, and
   // the chain particle's force
-  if ((st = write_members(h))) return st;
+  if ((st = stage_members(h, h->V))) return st;
   {
     tg_chain ch = chain_of(h);
     if ((st = tg_chain_forces(h->c, &ch, b->active_idx, b->n_active, h->sys.acc, h->sys.pot,
@@ -808,9 +903,14 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) try {
   }
   if ((st = tg_sync(h->c, nullptr))) return st;
   if ((st = read_coupling(h))) return st;
-  if ((st = membership_block(h, b))) return st;
-  if (h->active) return write_members(h);
-  return maybe_start_block(h, b);
+  // (4)-(5) with every velocity in step, then (8)
+  if ((st = membership_block(h, b, k0 + 1))) return st;
+  if (h->active) {
+    double Vs[3];
+    for (int k = 0; k < 3; ++k) Vs[k] = h->V[k] + h->a_com[k] * (0.5 * dt);
+    return stage_members(h, Vs);
+  }
+  return maybe_start_block(h, b, k0 + 1);
 } TG_HOST_CATCH("tg_hybrid_step_block")
 
 tg_status tg_hybrid_state_get(const tg_hybrid *h, tg_hybrid_state *st, int32_t *members_out,

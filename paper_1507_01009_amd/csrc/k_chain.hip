@@ -345,6 +345,21 @@ __global__ void k_set_rows(double *__restrict__ mass, uint8_t *__restrict__ flag
   }
 }
 
+// Bytes of listed rows: dst[r] = src[idx[r]] (levels of a few stars).
+__global__ void k_gather_bytes(uint8_t *__restrict__ dst, const uint8_t *__restrict__ src,
+                               const int32_t *__restrict__ idx, int n) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    dst[r] = src[idx[r]];
+}
+
+hipError_t launch_gather_bytes(tg_ctx *c, uint8_t *dst, const uint8_t *src, const int32_t *idx,
+                               int n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_bytes, dim3((n + 255) / 256), dim3(256), 0, c->stream, dst, src,
+                     idx, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_move_rows(tg_ctx *c, double *dst, const double *src, const int32_t *idx, int n,
                             bool to_rows) {
   if (n <= 0) return hipSuccess;
