@@ -420,8 +420,17 @@ tg_status tg_select_within(tg_ctx *ctx, const double *pos_dev, int64_t n,
  * algorithmic regularization: the logarithmic-Hamiltonian time-transformed
  * leapfrog (Mikkola & Tanikawa 1999; Preto & Tremaine 1999) with
  * Bulirsch-Stoer extrapolation (Mikkola & Aarseth 2002), which follows
- * close and colliding encounters without softening.  All arrays are HOST
- * memory; nothing here touches the GPU. */
+ * close and colliding encounters without softening.  The integrated
+ * variables are the chain vectors (Sec. 2: the chain of inter-particle
+ * vectors, Mikkola & Aarseth 1990, 1993): with the members ordered along a
+ * chain c[0..n-1], X_k = x_c[k+1] - x_c[k] and W_k = v_c[k+1] - v_c[k].
+ * Pairs one or two links apart take their separation from the chain
+ * vectors, so a close pair keeps its digits wherever it sits; the chain is
+ * built by the members' mutual forces (Sec. 2: sorted by gravitational
+ * force, not distance): the strongest pair first, then at either end the
+ * member pulled hardest by that end.  It is rebuilt before every
+ * extrapolated step from sums of the old chain vectors.  All arrays are
+ * HOST memory; nothing here touches the GPU. */
 typedef struct {
   int32_t n;                  /* members, 2..256 */
   double *x, *v;              /* [n][3] centre-of-mass frame (in/out) */
@@ -429,6 +438,14 @@ typedef struct {
   double t;                   /* physical time (in/out) */
   double B;                   /* binding energy U - T plus the perturbers' work (in/out; set by init) */
   double ds;                  /* fictitious step suggestion (in/out; <= 0 before init: chosen) */
+  /* Optional chain state kept between calls (NULL: none).  With chain_valid
+   * nonzero, init, advance and energy start from chain / cx / cv instead
+   * of x, v (which are then outputs only); every call that has the arrays
+   * writes them and sets chain_valid.  A caller that changes x, v (new
+   * members) clears chain_valid. */
+  int32_t *chain;             /* [n] member indices in chain order */
+  double *cx, *cv;            /* [n-1][3] chain vectors X_k, W_k */
+  int32_t chain_valid;
 } tg_archain;
 
 /* Perturbers as point masses moved to first order, y(t) = x + v (t - t0),
@@ -633,32 +650,36 @@ const char *tg_version(void);
 
 /* ---- the hybrid step (Sec. 2): tree stars + one regularised chain -------
  * A host driver over the calls above for a system with one SMBH, global
- * kick-drift-kick steps of length dt.  READING of the hybrid recipe:
+ * kick-drift-kick steps of length dt, in the order of the paper's step list
+ * (Sec. 2, steps (1)-(8)).  READING of the hybrid recipe:
  *  - without a chain: one tg_step_kdk; then the stars within r_chain0 of the
- *    SMBH (tg_select_within) start a chain with it;
+ *    SMBH (tg_select_within) start a chain with it (step (8));
  *  - members are integrated by the AR-chain in the chain's centre-of-mass
- *    frame; their stars stay in the arrays as ghosts: mass times ghost_mass,
- *    excluded from the coupling, positions and velocities rewritten from
- *    the chain after each step (the SMBH's arrays likewise);
- *  - the chain particle (mass M at R, velocity V; no softening) takes the
- *    stars' half kicks a_com (tg_chain_forces, with Eq. 3) and drifts with
- *    them; the members are advanced over the step by tg_archain_advance
- *    with the perturbers of the last coupling, predicted to first order
- *    from the start of the step (tg_predict_perturbers, dt = 0);
- *  - forces after the drift: tg_forces without the SMBH (it is in the
- *    chain) with the ghosts at R + their offsets from the start of the
- *    step, queued on the GPU while the AR-chain advances on the host; then
- *    tg_chain_forces with the advanced members;
- *  - after the step tg_chain_membership updates the members (absorbed stars
- *    become ghosts, escaped ones get their mass and global coordinates
- *    back; a chain that ends returns everything), the centre of mass is
- *    re-formed and the forces are evaluated again.
+ *    frame; their stars stay in the arrays as ghosts with no further
+ *    advancement: mass times ghost_mass, excluded from the coupling, never
+ *    kicked or drifted, their position and velocity those they had when
+ *    they joined (the SMBH's arrays get the member's global coordinates,
+ *    for reference only: the SMBH is not a tree particle);
+ *  - a step: the opening half kick of the stars and of the chain particle
+ *    (mass M at R, velocity V; no softening; its force a_com from
+ *    tg_chain_forces, with Eq. 3); the chain step (3): the members cross dt
+ *    in tg_archain_advance with the perturbers of the last coupling moving
+ *    on the straight lines of this step's drift (tg_predict_perturbers,
+ *    dt = 0); the drift; the tree forces (6b) without the SMBH, queued on
+ *    the GPU while the AR-chain advances on the host (they do not depend on
+ *    the chain: the ghosts stay where they joined); tg_chain_forces with
+ *    the advanced members; the closing half kick;
+ *  - then, chain and tree at the same time, tg_chain_membership (steps
+ *    (4)-(5)): absorbed stars become ghosts, escaped ones get their mass
+ *    and global coordinates back, a chain that ends returns everything; the
+ *    centre of mass is re-formed and the forces are evaluated again.
  * The driver owns the system while it lives: it writes the stars' masses
- * (ghosts) and the SMBH's arrays, and synchronises the stream every step,
- * so its calls cannot be graph-captured.  tg_hybrid_create allocates the
- * driver's own device buffers and pinned host staging (freed by
- * tg_hybrid_destroy); the AR-chain's host threads start at its first
- * threaded batch and live until the process ends.
+ * (ghosts), the rows of stars that leave the chain and the SMBH's arrays,
+ * and synchronises the stream every step, so its calls cannot be
+ * graph-captured.  tg_hybrid_create allocates the driver's own device
+ * buffers and pinned host staging (freed by tg_hybrid_destroy); the
+ * AR-chain's host threads start at its first threaded batch and live until
+ * the process ends.
  * Errors: TG_EINVAL (arguments; the system needs exactly one SMBH),
  * TG_ECAPACITY (perturbers beyond pert_cap, members beyond 256). */
 typedef struct tg_hybrid tg_hybrid;
@@ -695,9 +716,14 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt);
  * substep, its force formed every substep), ghosts are frozen (never
  * active), the members cross each substep in the AR-chain, forces go to the
  * stars active at the new k only (tree without the SMBH, then the
- * coupling); stars that leave the chain are put on the finest level and get
- * their forces at once.  Without a chain: tg_step_block, then the chain
- * start test. */
+ * coupling).  At a hand-off every velocity is brought to the substep's
+ * time first: the chain particle's by its pending closing half kick; a
+ * star joins (and a chain starts with it) only at a substep where its own
+ * step ends, with its pending closing half kick; stars that leave go to
+ * the finest level, get their forces at once and are stored half a kick
+ * back (W - a dt_min / 2), as are the re-formed chain particle and a freed
+ * SMBH, so the next substep's closing half kicks bring them into step.
+ * Without a chain: tg_step_block, then the chain start test. */
 tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *blocks);
 /* members_out (host [n_members] or NULL): star index of each member, -1 for
  * the SMBH; member x/v (host [n_members][3] or NULL): centre-of-mass frame. */

@@ -99,7 +99,9 @@ class tg_hybrid_state(C.Structure):
 
 class tg_archain(C.Structure):
     _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("v", C.c_void_p), ("m", C.c_void_p),
-                ("t", C.c_double), ("B", C.c_double), ("ds", C.c_double)]
+                ("t", C.c_double), ("B", C.c_double), ("ds", C.c_double),
+                ("chain", C.c_void_p), ("cx", C.c_void_p), ("cv", C.c_void_p),
+                ("chain_valid", C.c_int32)]
 
 
 class tg_archain_perturbers(C.Structure):
@@ -692,13 +694,27 @@ class ARChain:
         self.v = np.ascontiguousarray(v, np.float64).reshape(-1, 3).copy()
         self.m = np.ascontiguousarray(m, np.float64).copy()
         self.G = float(G)
+        n = self.m.shape[0]
+        # the chain state kept between calls (order and chain vectors)
+        self.chain = np.zeros(max(n, 1), np.int32)
+        self.cx = np.zeros((max(n - 1, 1), 3))
+        self.cv = np.zeros((max(n - 1, 1), 3))
         self.s = tg_archain()
-        self.s.n = self.m.shape[0]
+        self.s.n = n
         self.s.x = self.x.ctypes.data_as(C.c_void_p)
         self.s.v = self.v.ctypes.data_as(C.c_void_p)
         self.s.m = self.m.ctypes.data_as(C.c_void_p)
         self.s.t, self.s.B, self.s.ds = float(t), 0.0, 0.0
+        self.s.chain = self.chain.ctypes.data_as(C.c_void_p)
+        self.s.cx = self.cx.ctypes.data_as(C.c_void_p)
+        self.s.cv = self.cv.ctypes.data_as(C.c_void_p)
+        self.s.chain_valid = 0
         _check(lib().tg_archain_init(C.byref(self.s), self.G))
+
+    def reset_from_xv(self):
+        """Take x, v (centre-of-mass frame) as the state again (after they
+        were changed by hand); the chain is rebuilt from them."""
+        self.s.chain_valid = 0
 
     @property
     def t(self):

@@ -18,11 +18,25 @@
 // last step before the target time is found by a secant search on its
 // length.
 //
+// Coordinates: the chain of inter-particle vectors (Mikkola & Aarseth
+// 1990, CeMDA 47, 375; 1993, CeMDA 57, 439).  The members are ordered along
+// a chain c[0..n-1] and the integrated variables are X_k = x_c[k+1] -
+// x_c[k], W_k = v_c[k+1] - v_c[k] (k < n - 1): a drift moves X_k by W_k dt
+// and a kick moves W_k by (A_c[k+1] - A_c[k]) dt.  Pairs one or two links
+// apart take their separation from X_k (or X_k + X_k+1), so a close pair
+// keeps its digits however far it is from the centre of mass; the other
+// pairs and the perturbers use centre-of-mass coordinates rebuilt from the
+// chain.  The chain is built by force (Sec. 2: members sorted by their
+// gravitational forces, not by distance): the pair with the largest
+// m_i m_j / r^2 first, then at either end the member that end pulls
+// hardest, until all are in.  Before every extrapolated step the chain is
+// built again and, if it changed, the new vectors are sums of the old ones
+// along the old chain.
+//
 // Perturbers: point masses moved to first order, y_p(t) = y_p + w_p (t - t0),
 // relative to the chain's centre of mass; the members feel their tidal part,
 // f_i - (1/M) sum_j m_j f_j, so the frame stays centred (the centre of mass
-// itself is the tree's chain particle).  Coordinates are relative to the
-// centre of mass, not chain vectors (see the design notes).
+// itself is the tree's chain particle).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -47,32 +61,135 @@ struct Chain {
   int np = 0;
   const double *py = nullptr, *pw = nullptr, *pm = nullptr;
   double t0 = 0.0;
+  // the chain: members in chain order, and each member's place in it
+  std::vector<int> ord, pos;
 };
 
-// State vector: x [3n], v [3n], t, B.
+// State vector: chain vectors X [3(n-1)], their velocities W [3(n-1)], t, B.
 struct Y {
   std::vector<double> d;
-  double *x() { return d.data(); }
-  double *v(int n) { return d.data() + 3 * n; }
-  double &t(int n) { return d[6 * n]; }
-  double &B(int n) { return d[6 * n + 1]; }
+  double *X() { return d.data(); }
+  const double *X() const { return d.data(); }
+  double *W(int n) { return d.data() + 3 * (n - 1); }
+  const double *W(int n) const { return d.data() + 3 * (n - 1); }
+  double &t(int n) { return d[6 * (n - 1)]; }
+  double &B(int n) { return d[6 * (n - 1) + 1]; }
 };
 
-double kinetic(const Chain &c, const double *v) {
+// Centre-of-mass coordinates [n][3] (member order) from chain vectors:
+// x_c[0] = -(1/M) sum_k S_k X_k with S_k the mass after link k, then
+// x_c[k+1] = x_c[k] + X_k.
+void to_com(const Chain &c, const double *X, double *x) {
+  double s[3] = {0.0, 0.0, 0.0}, before = 0.0;
+  for (int k = 0; k < c.n - 1; ++k) {
+    before += c.m[c.ord[k]];
+    const double S = c.M - before;
+    for (int d = 0; d < 3; ++d) s[d] += S * X[3 * k + d];
+  }
+  double *x0 = x + 3 * c.ord[0];
+  for (int d = 0; d < 3; ++d) x0[d] = -s[d] / c.M;
+  for (int k = 0; k < c.n - 1; ++k) {
+    const double *a = x + 3 * c.ord[k];
+    double *b = x + 3 * c.ord[k + 1];
+    for (int d = 0; d < 3; ++d) b[d] = a[d] + X[3 * k + d];
+  }
+}
+
+// Chain vectors of the order in c from centre-of-mass coordinates.
+void from_com(const Chain &c, const double *x, double *X) {
+  for (int k = 0; k < c.n - 1; ++k)
+    for (int d = 0; d < 3; ++d) X[3 * k + d] = x[3 * c.ord[k + 1] + d] - x[3 * c.ord[k] + d];
+}
+
+double kinetic_com(const Chain &c, const double *v) {
   double T = 0.0;
   for (int i = 0; i < c.n; ++i)
     T += 0.5 * c.m[i] * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
   return T;
 }
 
+// The chain by force over centre-of-mass coordinates x: the strongest pair
+// (largest m_i m_j / r^2; ties to the lower indices), then repeatedly the
+// member outside the chain pulled hardest by either end, attached to that
+// end (ties: the tail, then the lower index).
+void build_order(Chain &c, const double *x) {
+  const int n = c.n;
+  std::vector<double> F((size_t)n * n, 0.0);
+  int bi = 0, bj = 1;
+  double best = -1.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      double r2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        const double q = x[3 * j + d] - x[3 * i + d];
+        r2 += q * q;
+      }
+      const double f = c.m[i] * c.m[j] / r2;
+      F[(size_t)i * n + j] = F[(size_t)j * n + i] = f;
+      if (f > best) { best = f; bi = i; bj = j; }
+    }
+  std::vector<int> chain{bi, bj};
+  std::vector<char> in(n, 0);
+  in[bi] = in[bj] = 1;
+  while ((int)chain.size() < n) {
+    const int head = chain.front(), tail = chain.back();
+    int k_best = -1;
+    bool at_tail = true;
+    double f_best = -1.0;
+    for (int k = 0; k < n; ++k) {
+      if (in[k]) continue;
+      const double ft = F[(size_t)k * n + tail], fh = F[(size_t)k * n + head];
+      if (ft > f_best) { f_best = ft; k_best = k; at_tail = true; }
+      if (fh > f_best) { f_best = fh; k_best = k; at_tail = false; }
+    }
+    in[k_best] = 1;
+    if (at_tail) chain.push_back(k_best);
+    else chain.insert(chain.begin(), k_best);
+  }
+  c.ord = chain;
+  c.pos.assign(n, 0);
+  for (int k = 0; k < n; ++k) c.pos[c.ord[k]] = k;
+}
+
+// Rebuild the chain by force at the state y (chain vectors of c.ord); if
+// the order changes, the new vectors are sums of the old ones along the
+// old chain (no round trip through centre-of-mass coordinates).
+void rechain(Chain &c, Y &y) {
+  const int n = c.n;
+  if (n < 3) return;
+  std::vector<double> x(3 * n);
+  to_com(c, y.X(), x.data());
+  const std::vector<int> old_pos = c.pos;
+  build_order(c, x.data());
+  bool same = true;
+  for (int i = 0; i < n; ++i) same = same && (c.pos[i] == old_pos[i]);
+  if (same) return;
+  const std::vector<double> X0(y.X(), y.X() + 3 * (n - 1)), W0(y.W(n), y.W(n) + 3 * (n - 1));
+  for (int k = 0; k < n - 1; ++k) {
+    const int pa = old_pos[c.ord[k]], pb = old_pos[c.ord[k + 1]];
+    const int lo = std::min(pa, pb), hi = std::max(pa, pb);
+    const double sg = pa < pb ? 1.0 : -1.0;
+    for (int d = 0; d < 3; ++d) {
+      double sx = 0.0, sw = 0.0;
+      for (int l = lo; l < hi; ++l) {
+        sx += X0[3 * l + d];
+        sw += W0[3 * l + d];
+      }
+      y.X()[3 * k + d] = sg * sx;
+      y.W(n)[3 * k + d] = sg * sw;
+    }
+  }
+}
+
 // Scratch of one thread: accelerations a (members' own) and f (perturbers'
-// tidal part), [n][3]; structure-of-arrays copies of the member and
-// perturber coordinates and masses, padded to whole vectors.
+// tidal part), [n][3]; centre-of-mass coordinates xc, vc; structure-of-
+// arrays copies of the member coordinates, masses and chain places and of
+// the perturbers, padded to whole vectors.
 struct Work {
-  std::vector<double> a, f;
-  std::vector<double> X, Yc, Z, Mw;      // members
+  std::vector<double> a, f, xc, vc;
+  std::vector<double> X, Yc, Z, Mw, P;   // members
   std::vector<double> PX, PY, PZ, PM;    // perturbers at the kick's time
-  explicit Work(int n = 0) : a(3 * n), f(3 * n) {}
+  explicit Work(int n = 0) : a(3 * n), f(3 * n), xc(3 * n), vc(3 * n) {}
 };
 
 // The pair sums run over 8-wide vectors (clang vector extensions); the
@@ -94,17 +211,19 @@ __attribute__((always_inline)) inline double hsum(v8 v) {
   return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
 }
 
-// Row i of the members' sums: a_i = G sum_j m_j (x_j - x_i) / r^3 and
-// u_i = sum_j m_j / r (j != i).  Lanes j = i and the padding get a mass of
-// zero and r^2 + 1, so no lane divides by zero.
+// Row i of the members' sums over the pairs more than two links apart in
+// the chain: a_i = sum_j m_j (x_j - x_i) / r^3 and u_i = sum_j m_j / r.
+// Other lanes (near pairs, j = i, padding) get a mass of zero and r^2 + 1,
+// so no lane divides by zero.
 __attribute__((always_inline)) inline void internal_row(const Work &w, int n, int i,
                                                         double *ai, double &ui) {
-  const double xi = w.X[i], yi = w.Yc[i], zi = w.Z[i];
+  const double xi = w.X[i], yi = w.Yc[i], zi = w.Z[i], pi = w.P[i];
   v8 ax = 0.0, ay = 0.0, az = 0.0, u = 0.0;
   const l8 lane = {0, 1, 2, 3, 4, 5, 6, 7};
   for (int j = 0; j < padded(n); j += kV) {
     const l8 jj = lane + (long long)j;
-    const v8 live = -__builtin_convertvector((jj != (long long)i) & (jj < (long long)n), v8);
+    const v8 dp = load8(&w.P[j]) - pi;
+    const v8 live = -__builtin_convertvector(((dp > 2.5) | (dp < -2.5)) & (jj < (long long)n), v8);
     const v8 dx = load8(&w.X[j]) - xi, dy = load8(&w.Yc[j]) - yi, dz = load8(&w.Z[j]) - zi;
     const v8 r2 = dx * dx + dy * dy + dz * dz + (1.0 - live);
     const v8 ir = 1.0 / __builtin_elementwise_sqrt(r2);
@@ -193,18 +312,36 @@ Isa isa() {
 #endif
 }
 
-// Newtonian accelerations of the members (into w.a); returns U.
-double internal(const Chain &c, const double *x, Work &w) {
+// One pair from its separation r = x_j - x_i: a_i += m_j r / |r|^3,
+// a_j -= m_i r / |r|^3; returns 2 m_i m_j / |r| (the pair counted from both
+// ends, as the rows count it).
+inline double near_pair(const Chain &c, int i, int j, const double r[3], double *a) {
+  const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  const double ir = 1.0 / std::sqrt(r2), g = ir * ir * ir;
+  for (int d = 0; d < 3; ++d) {
+    a[3 * i + d] += c.m[j] * g * r[d];
+    a[3 * j + d] -= c.m[i] * g * r[d];
+  }
+  return 2.0 * c.m[i] * c.m[j] * ir;
+}
+
+// Newtonian accelerations of the members (into w.a, member order) and the
+// centre-of-mass positions (w.xc); returns U.
+double internal(const Chain &c, const double *X, Work &w) {
   const int n = c.n, np8 = padded(n);
+  w.xc.resize(3 * n);
+  to_com(c, X, w.xc.data());
   w.X.assign(np8, 0.0);
   w.Yc.assign(np8, 0.0);
   w.Z.assign(np8, 0.0);
   w.Mw.assign(np8, 0.0);
+  w.P.assign(np8, -1e9);
   for (int i = 0; i < n; ++i) {
-    w.X[i] = x[3 * i];
-    w.Yc[i] = x[3 * i + 1];
-    w.Z[i] = x[3 * i + 2];
+    w.X[i] = w.xc[3 * i];
+    w.Yc[i] = w.xc[3 * i + 1];
+    w.Z[i] = w.xc[3 * i + 2];
     w.Mw[i] = c.m[i];
+    w.P[i] = (double)c.pos[i];
   }
   w.a.resize(3 * n);
   double U2;
@@ -213,12 +350,23 @@ double internal(const Chain &c, const double *x, Work &w) {
     case Isa::avx2: U2 = internal_rows_avx2(w, n, w.a.data()); break;
     default: U2 = internal_rows_base(w, n, w.a.data()); break;
   }
+  // pairs one and two links apart, from the chain vectors
+  for (int k = 0; k + 1 < n; ++k) {
+    U2 += near_pair(c, c.ord[k], c.ord[k + 1], &X[3 * k], w.a.data());
+    if (k + 2 < n) {
+      const double r[3] = {X[3 * k] + X[3 * k + 3], X[3 * k + 1] + X[3 * k + 4],
+                           X[3 * k + 2] + X[3 * k + 5]};
+      U2 += near_pair(c, c.ord[k], c.ord[k + 2], r, w.a.data());
+    }
+  }
   for (double &q : w.a) q *= c.G;
   return 0.5 * c.G * U2;
 }
 
-// Tidal part of the perturbers' accelerations at time t (into w.f).
+// Tidal part of the perturbers' accelerations at time t on the members at
+// centre-of-mass positions x (into w.f).
 void external(const Chain &c, const double *x, double t, Work &w) {
+  w.f.resize(3 * c.n);
   double *f = w.f.data();
   std::fill(f, f + 3 * c.n, 0.0);
   if (c.np == 0) return;
@@ -247,40 +395,53 @@ void external(const Chain &c, const double *x, double t, Work &w) {
   for (int i = 0; i < c.n; ++i) { f[3 * i] -= mx; f[3 * i + 1] -= my; f[3 * i + 2] -= mz; }
 }
 
-void drift(const Chain &c, Y &y, double h) {
+double kinetic(const Chain &c, const double *W, Work &w) {
+  w.vc.resize(3 * c.n);
+  to_com(c, W, w.vc.data());
+  return kinetic_com(c, w.vc.data());
+}
+
+void drift(const Chain &c, Y &y, double h, Work &w) {
   const int n = c.n;
-  const double dt = h / (kinetic(c, y.v(n)) + y.B(n));
-  double *x = y.x(), *v = y.v(n);
-  for (int k = 0; k < 3 * n; ++k) x[k] += v[k] * dt;
+  const double dt = h / (kinetic(c, y.W(n), w) + y.B(n));
+  double *X = y.X();
+  const double *W = y.W(n);
+  for (int k = 0; k < 3 * (n - 1); ++k) X[k] += W[k] * dt;
   y.t(n) += dt;
 }
 
+// v_i changes by (a_i + f_i) dt, so W_k by the difference along link k;
+// B loses the perturbers' work at the mean velocity of the kick.
 void kick(const Chain &c, Y &y, double h, Work &w) {
   const int n = c.n;
-  w.f.resize(3 * n);
-  const double U = internal(c, y.x(), w);
+  const double U = internal(c, y.X(), w);
   const double dt = h / U;
-  external(c, y.x(), y.t(n), w);
+  external(c, w.xc.data(), y.t(n), w);
+  w.vc.resize(3 * n);
+  to_com(c, y.W(n), w.vc.data());
   const std::vector<double> &a = w.a, &f = w.f;
-  double *v = y.v(n);
   double work = 0.0;
   for (int i = 0; i < n; ++i)
-    for (int k = 0; k < 3; ++k) {
-      const double v0 = v[3 * i + k];
-      const double v1 = v0 + (a[3 * i + k] + f[3 * i + k]) * dt;
-      work += c.m[i] * f[3 * i + k] * 0.5 * (v0 + v1);
-      v[3 * i + k] = v1;
+    for (int d = 0; d < 3; ++d) {
+      const double dv = (a[3 * i + d] + f[3 * i + d]) * dt;
+      work += c.m[i] * f[3 * i + d] * (w.vc[3 * i + d] + 0.5 * dv);
     }
+  double *W = y.W(n);
+  for (int k = 0; k + 1 < n; ++k) {
+    const int i = c.ord[k], j = c.ord[k + 1];
+    for (int d = 0; d < 3; ++d)
+      W[3 * k + d] += ((a[3 * j + d] + f[3 * j + d]) - (a[3 * i + d] + f[3 * i + d])) * dt;
+  }
   y.B(n) -= work * dt;
 }
 
 Y leapfrog(const Chain &c, const Y &y0, double H, int nsub, Work &w) {
   Y y = y0;
   const double h = H / nsub;
-  drift(c, y, 0.5 * h);
+  drift(c, y, 0.5 * h, w);
   for (int k = 0; k < nsub; ++k) {
     kick(c, y, h, w);
-    drift(c, y, k == nsub - 1 ? 0.5 * h : h);
+    drift(c, y, k == nsub - 1 ? 0.5 * h : h, w);
   }
   return y;
 }
@@ -382,13 +543,29 @@ class ColumnPool {
 // it converged (or -1) and the result in out.
 int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, Work &w,
             int first = 3) {
-  const int n = c.n, dim = 6 * n + 2;
+  const int n = c.n, nv = 3 * (n - 1), dim = 2 * nv + 2;
   std::vector<std::vector<double>> T(kCols, std::vector<double>(dim));
-  // error scales: position and velocity magnitudes, the step's time, |B|
-  double xs = 0.0, vs = 0.0;
-  for (int i = 0; i < 3 * n; ++i) {
-    xs = std::max(xs, std::fabs(y0.d[i]));
-    vs = std::max(vs, std::fabs(y0.d[3 * n + i]));
+  // error scales: every chain vector and its velocity relative to their
+  // own lengths (a close pair is resolved on its own scale), with floors at
+  // 1e-12 of the longest vector and 1e-6 of the fastest or of the system's
+  // circular speed; the step's time; |B|
+  std::vector<double> sc(dim, 0.0);
+  double xmax = 0.0, vmax = 0.0;
+  for (int k = 0; k < n - 1; ++k) {
+    const double *X = &y0.d[3 * k], *W = &y0.d[nv + 3 * k];
+    const double lx = std::sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    const double lw = std::sqrt(W[0] * W[0] + W[1] * W[1] + W[2] * W[2]);
+    for (int d = 0; d < 3; ++d) {
+      sc[3 * k + d] = lx;
+      sc[nv + 3 * k + d] = lw;
+    }
+    xmax = std::max(xmax, lx);
+    vmax = std::max(vmax, lw);
+  }
+  const double vfloor = 1e-6 * std::max(vmax, std::sqrt(c.G * c.M / xmax));
+  for (int q = 0; q < nv; ++q) {
+    sc[q] = std::max(sc[q], 1e-12 * xmax);
+    sc[nv + q] = std::max(sc[nv + q], vfloor);
   }
   // The columns' leapfrogs are independent: with a large chain they are
   // computed a batch at a time on host threads (each with its own scratch),
@@ -431,13 +608,12 @@ int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, Work &w,
     if (k >= 2) {
       // T[0] holds the newest extrapolation, T[1] the previous one
       double err = 0.0;
-      const double ts = std::fabs(T[0][6 * n] - y0.d[6 * n]) + 1e-300;
+      const double ts = std::fabs(T[0][2 * nv] - y0.d[2 * nv]) + 1e-300;
       for (int q = 0; q < dim; ++q) {
         double s;
-        if (q < 3 * n) s = xs;
-        else if (q < 6 * n) s = vs;
-        else if (q == 6 * n) s = ts;
-        else s = std::fabs(y0.d[6 * n + 1]);
+        if (q < 2 * nv) s = sc[q];
+        else if (q == 2 * nv) s = ts;
+        else s = std::fabs(y0.d[2 * nv + 1]);
         err = std::max(err, std::fabs(T[0][q] - T[1][q]) / (s + 1e-300));
       }
       if (err <= tol) {
@@ -447,6 +623,48 @@ int bs_step(const Chain &c, const Y &y0, double H, double tol, Y &out, Work &w,
     }
   }
   return -1;
+}
+
+// The chain and the chain vectors of the caller's state: the kept chain
+// state when it is valid, else the chain by force over x, v.  Returns false
+// if a kept chain is not a permutation of the members.
+bool load_state(const tg_archain *s, Chain &c, Y &y) {
+  const int n = s->n;
+  y.d.assign(6 * (n - 1) + 2, 0.0);
+  if (s->chain_valid && s->chain && s->cx && s->cv) {
+    std::vector<char> seen(n, 0);
+    for (int k = 0; k < n; ++k) {
+      const int i = s->chain[k];
+      if (i < 0 || i >= n || seen[i]) return false;
+      seen[i] = 1;
+    }
+    c.ord.assign(s->chain, s->chain + n);
+    c.pos.assign(n, 0);
+    for (int k = 0; k < n; ++k) c.pos[c.ord[k]] = k;
+    std::memcpy(y.X(), s->cx, sizeof(double) * 3 * (n - 1));
+    std::memcpy(y.W(n), s->cv, sizeof(double) * 3 * (n - 1));
+  } else {
+    build_order(c, s->x);
+    from_com(c, s->x, y.X());
+    from_com(c, s->v, y.W(n));
+  }
+  y.t(n) = s->t;
+  y.B(n) = s->B;
+  return true;
+}
+
+// x, v (centre-of-mass frame) from the chain state, and the chain state
+// itself where the caller keeps it.
+void store_state(const Chain &c, const Y &y, tg_archain *s) {
+  const int n = s->n;
+  to_com(c, y.X(), s->x);
+  to_com(c, y.W(n), s->v);
+  if (s->chain && s->cx && s->cv) {
+    std::copy(c.ord.begin(), c.ord.end(), s->chain);
+    std::memcpy(s->cx, y.X(), sizeof(double) * 3 * (n - 1));
+    std::memcpy(s->cv, y.W(n), sizeof(double) * 3 * (n - 1));
+    s->chain_valid = 1;
+  }
 }
 
 }  // namespace
@@ -462,11 +680,18 @@ tg_status tg_archain_init(tg_archain *s, double G) try {
   Chain c;
   c.n = s->n; c.m = s->m; c.G = G;
   Work w(s->n);
-  for (int i = 0; i < s->n; ++i)
+  for (int i = 0; i < s->n; ++i) {
     if (!(s->m[i] > 0.0)) return fail(TG_EINVAL, "tg_archain_init: masses must be positive");
-  const double U = internal(c, s->x, w);
+    c.M += s->m[i];
+  }
+  for (int i = 0; i < 3 * s->n; ++i)
+    if (!std::isfinite(s->x[i]) || !std::isfinite(s->v[i]))
+      return fail(TG_EINVAL, "tg_archain_init: non-finite coordinates");
+  Y y;
+  if (!load_state(s, c, y)) return fail(TG_EINVAL, "tg_archain_init: chain is not a permutation");
+  const double U = internal(c, y.X(), w);
   if (!std::isfinite(U)) return fail(TG_EINVAL, "tg_archain_init: coincident members");
-  s->B = U - kinetic(c, s->v);
+  s->B = U - kinetic(c, y.W(s->n), w);
   if (!(s->ds > 0.0)) {
     // a first step of about a hundredth of the fastest pair's dynamical time
     double tmin = INFINITY;
@@ -474,7 +699,7 @@ tg_status tg_archain_init(tg_archain *s, double G) try {
       for (int j = i + 1; j < s->n; ++j) {
         double r2 = 0.0;
         for (int k = 0; k < 3; ++k) {
-          const double d = s->x[3 * j + k] - s->x[3 * i + k];
+          const double d = w.xc[3 * j + k] - w.xc[3 * i + k];
           r2 += d * d;
         }
         const double r = std::sqrt(r2);
@@ -482,6 +707,8 @@ tg_status tg_archain_init(tg_archain *s, double G) try {
       }
     s->ds = 0.01 * tmin * U;
   }
+  y.B(s->n) = s->B;
+  store_state(c, y, s);
   return TG_OK;
 } TG_HOST_CATCH("tg_archain_init")
 
@@ -499,11 +726,7 @@ tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
   if (p && p->np > 0) { c.np = p->np; c.py = p->x; c.pw = p->v; c.pm = p->m; c.t0 = p->t0; }
   const int n = s->n;
   Y y;
-  y.d.resize(6 * n + 2);
-  std::memcpy(y.x(), s->x, sizeof(double) * 3 * n);
-  std::memcpy(y.v(n), s->v, sizeof(double) * 3 * n);
-  y.t(n) = s->t;
-  y.B(n) = s->B;
+  if (!load_state(s, c, y)) return fail(TG_EINVAL, "tg_archain_advance: chain is not a permutation");
   const double t_end = s->t + dt;
   Work w(n);
   int64_t steps = 0;
@@ -511,6 +734,7 @@ tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
   Y out;
   int hint = 3;   // columns the last extrapolated step converged with
   while (y.t(n) < t_end) {
+    rechain(c, y);
     int col = bs_step(c, y, H, tol, out, w, hint);
     if (col >= 0) hint = col + 1;
     if (col < 0) {
@@ -553,8 +777,7 @@ tg_status tg_archain_advance(tg_archain *s, double G, double dt, double tol,
     if (col <= 3) H *= 1.5;
     else if (col >= 6) H *= 0.7;
   }
-  std::memcpy(s->x, y.x(), sizeof(double) * 3 * n);
-  std::memcpy(s->v, y.v(n), sizeof(double) * 3 * n);
+  store_state(c, y, s);
   s->t = t_end;
   s->B = y.B(n);
   s->ds = H;
@@ -567,9 +790,12 @@ tg_status tg_archain_energy(const tg_archain *s, double G, double *err_out) try 
   if (s->n < 2 || s->n > kMaxChain) return fail(TG_EINVAL, "tg_archain_energy: n must be in 2..256");
   Chain c;
   c.n = s->n; c.m = s->m; c.G = G;
+  for (int i = 0; i < s->n; ++i) c.M += s->m[i];
   Work w(s->n);
-  const double U = internal(c, s->x, w);
-  const double T = kinetic(c, s->v);
+  Y y;
+  if (!load_state(s, c, y)) return fail(TG_EINVAL, "tg_archain_energy: chain is not a permutation");
+  const double U = internal(c, y.X(), w);
+  const double T = kinetic(c, y.W(s->n), w);
   *err_out = (T - U + s->B) / U;
   return TG_OK;
 } TG_HOST_CATCH("tg_archain_energy")

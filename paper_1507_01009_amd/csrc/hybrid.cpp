@@ -30,6 +30,11 @@ struct tg_hybrid {
   // centre of mass, masses (the stars' own, not the ghost masses)
   std::vector<int32_t> star;
   std::vector<double> x, v, m;
+  // the AR-chain's chain state kept between steps (order, chain vectors);
+  // rebuilt from x, v whenever the membership changes
+  std::vector<int32_t> chain;
+  std::vector<double> cx, cv;
+  int32_t chain_valid = 0;
   double R[3] = {0, 0, 0}, V[3] = {0, 0, 0}, M = 0.0;
   double B = 0.0, ds = 0.0;
   double a_com[3] = {0, 0, 0};
@@ -347,17 +352,36 @@ tg_status read_stars(tg_hybrid *h, const std::vector<int32_t> &ids, std::vector<
   return TG_OK;
 }
 
-tg_status ar_init(tg_hybrid *h) {
+// The AR-chain's view of the members (with the kept chain state).
+tg_archain archain_of(tg_hybrid *h) {
   tg_archain s{};
   s.n = nc(h);
   s.x = h->x.data();
   s.v = h->v.data();
   s.m = h->m.data();
-  s.ds = 0.0;
+  s.t = 0.0;
+  s.B = h->B;
+  s.ds = h->ds;
+  s.chain = h->chain.data();
+  s.cx = h->cx.data();
+  s.cv = h->cv.data();
+  s.chain_valid = h->chain_valid;
+  return s;
+}
+
+tg_status ar_init(tg_hybrid *h) {
+  const int n = nc(h);
+  h->chain.assign(n, 0);
+  h->cx.assign(3 * (n - 1), 0.0);
+  h->cv.assign(3 * (n - 1), 0.0);
+  h->chain_valid = 0;
+  h->ds = 0.0;
+  tg_archain s = archain_of(h);
   tg_status st = tg_archain_init(&s, h->G);
   if (st) return st;
   h->B = s.B;
   h->ds = s.ds;
+  h->chain_valid = s.chain_valid;
   h->r_chain = max_radius(h);
   h->energy_error = 0.0;
   return TG_OK;
@@ -800,14 +824,7 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) try {
     y.n_bh = 0;
     if ((st = tg_forces(h->c, &y, nullptr, nullptr))) return st;
   }
-  tg_archain s{};
-  s.n = nc(h);
-  s.x = h->x.data();
-  s.v = h->v.data();
-  s.m = h->m.data();
-  s.t = 0.0;
-  s.B = h->B;
-  s.ds = h->ds;
+  tg_archain s = archain_of(h);
   tg_archain_perturbers P{};
   P.np = (int32_t)pm.size();
   P.x = px.data();
@@ -821,6 +838,7 @@ tg_status tg_hybrid_step(tg_hybrid *h, double dt) try {
   if (st) return st;
   h->B = s.B;
   h->ds = s.ds;
+  h->chain_valid = s.chain_valid;
   if ((st = tg_archain_energy(&s, h->G, &h->energy_error))) return st;
   h->r_chain = max_radius(h);
   // (6b) the coupling with the members' new positions, (6c) closing half kick
@@ -869,14 +887,7 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) try {
     y.n_bh = 0;
     if ((st = tg_forces(h->c, &y, b->active_idx, b->n_active))) return st;
   }
-  tg_archain s{};
-  s.n = nc(h);
-  s.x = h->x.data();
-  s.v = h->v.data();
-  s.m = h->m.data();
-  s.t = 0.0;
-  s.B = h->B;
-  s.ds = h->ds;
+  tg_archain s = archain_of(h);
   tg_archain_perturbers P{};
   P.np = (int32_t)pm.size();
   P.x = px.data();
@@ -890,6 +901,7 @@ tg_status tg_hybrid_step_block(tg_hybrid *h, const tg_blocks *b) try {
   if (st) return st;
   h->B = s.B;
   h->ds = s.ds;
+  h->chain_valid = s.chain_valid;
   if ((st = tg_archain_energy(&s, h->G, &h->energy_error))) return st;
   h->r_chain = max_radius(h);
   // the coupling for the same stars with the members' new positions, and
