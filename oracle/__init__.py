@@ -59,6 +59,9 @@ def lib():
             "or_keys": (None, [P, P, i32, P, P]),
             "or_sort": (C.c_int, [P, P, i32, P]),
             "or_build": (i64, [P, P, i32, i32, i64, P, P, P, P, P, P, P]),
+            "or_keys42": (None, [P, P, i32, P, P, P]),
+            "or_sort42": (C.c_int, [P, P, P, i32, P]),
+            "or_build42": (i64, [P, P, P, i32, i32, i64, P, P, P, P, P, P, P]),
             "or_moments": (None, [P, P, i64, P, P, P]),
             "or_groups": (i64, [i64, P, P, P, P, P, P, i32, i64, P]),
             "or_group_boxes": (None, [P, P, i64, P, P, P]),
@@ -129,13 +132,17 @@ class Tree:
     sys: np.ndarray      # int32 [nn]
     parent: np.ndarray   # uint32 [nn] (0xffffffff for roots)
     leaf_size: int
+    levels: int = MAX_LEVEL          # 21, or 42 with two key words
+    keys_lo: np.ndarray = None       # 42 levels: uint64 [N] last 21 digits, original order
+    skeys_lo: np.ndarray = None      # 42 levels: the same, sorted
 
     @property
     def nn(self) -> int:
         return int(self.level.shape[0])
 
     def prefix(self) -> np.ndarray:
-        """Key prefix of every node: key >> 3 * (21 - level)."""
+        """Key prefix of every node: key >> 3 * (21 - level) (21 levels)."""
+        assert self.levels == MAX_LEVEL
         sh = (3 * (MAX_LEVEL - self.level.astype(np.uint64))).astype(np.uint64)
         return self.skeys[self.first.astype(np.int64)] >> sh
 
@@ -153,10 +160,13 @@ def cube_keys(pos, sys_off=None):
     return off, cube, keys
 
 
-def build_tree(pos, sys_off=None, leaf_size: int = 8) -> Tree:
-    """Cube -> keys -> stable sort -> breadth-first octree."""
+def build_tree(pos, sys_off=None, leaf_size: int = 8, levels: int = MAX_LEVEL) -> Tree:
+    """Cube -> keys -> stable sort -> breadth-first octree (21 or 42 levels)."""
     pos = _c(pos, np.float64).reshape(-1, 3)
     n = pos.shape[0]
+    if levels == 42:
+        return _build_tree42(pos, sys_off, leaf_size)
+    assert levels == MAX_LEVEL
     off, cube, keys = cube_keys(pos, off_or_none(sys_off, n))
     S = off.shape[0] - 1
     perm = np.zeros(n, np.uint32)
@@ -182,6 +192,41 @@ def build_tree(pos, sys_off=None, leaf_size: int = 8) -> Tree:
                 first[:nn].copy(), count[:nn].copy(), child[:nn].copy(),
                 nchild[:nn].copy(), sysid[:nn].copy(), parent[:nn].copy(),
                 int(leaf_size))
+
+
+def _build_tree42(pos, sys_off, leaf_size):
+    n = pos.shape[0]
+    off = _offsets(n, off_or_none(sys_off, n))
+    S = off.shape[0] - 1
+    cube = np.zeros((S, 4), np.float64)
+    lib().or_cube(_p(pos), _p(off), S, _p(cube))
+    khi = np.zeros(n, np.uint64)
+    klo = np.zeros(n, np.uint64)
+    lib().or_keys42(_p(pos), _p(off), S, _p(cube), _p(khi), _p(klo))
+    perm = np.zeros(n, np.uint32)
+    if lib().or_sort42(_p(khi), _p(klo), _p(off), S, _p(perm)) != 0:
+        raise MemoryError("oracle sort")
+    p = perm.astype(np.int64)
+    skhi = khi[p] if n else khi.copy()
+    sklo = klo[p] if n else klo.copy()
+    cap = 4 * n + S + 64
+    while True:
+        level = np.zeros(cap, np.uint8)
+        first = np.zeros(cap, np.uint32)
+        count = np.zeros(cap, np.uint32)
+        child = np.zeros(cap, np.uint32)
+        nchild = np.zeros(cap, np.uint8)
+        sysid = np.zeros(cap, np.int32)
+        parent = np.zeros(cap, np.uint32)
+        nn = lib().or_build42(_p(skhi), _p(sklo), _p(off), S, int(leaf_size), cap,
+                              _p(level), _p(first), _p(count), _p(child),
+                              _p(nchild), _p(sysid), _p(parent))
+        if nn >= 0:
+            break
+        cap *= 2
+    return Tree(off, cube, khi, perm, skhi, level[:nn].copy(), first[:nn].copy(),
+                count[:nn].copy(), child[:nn].copy(), nchild[:nn].copy(), sysid[:nn].copy(),
+                parent[:nn].copy(), int(leaf_size), 42, klo, sklo)
 
 
 def off_or_none(sys_off, n):
@@ -338,7 +383,7 @@ def spline_psi(r, h):
 
 def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
                 sys_off=None, G=1.0, sel_groups=None, tree=None, alpha=None,
-                acc_old=None, refit=False, softening="plummer"):
+                acc_old=None, refit=False, softening="plummer", levels=MAX_LEVEL):
     """Build, moments, groups, walk and evaluation, all in the oracle.
 
     ``active``: original indices of the targets (None = all).  ``sel_groups``:
@@ -353,7 +398,9 @@ def tree_forces(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
     pos = _c(pos, np.float64).reshape(-1, 3)
     n = pos.shape[0]
     if tree is None:
-        tree = build_tree(pos, sys_off, leaf_size)
+        tree = build_tree(pos, sys_off, leaf_size, levels)
+    if tree.levels != MAX_LEVEL and (alpha is not None or refit):
+        raise ValueError("the relative test and refit take 21-level trees")
     spos, smass = sorted_arrays(tree, pos, mass)
     mom = moments(tree, spos, smass)
     g = groups(tree, group_size)

@@ -185,6 +185,111 @@ int64_t or_build(const uint64_t *skey, const int64_t *off, int32_t S,
 }
 
 /* ---------------------------------------------------------------------- */
+/* 42 levels: the same definitions with 42-bit quantised coordinates, for   */
+/* systems whose extent leaves the centre unresolved at 21 levels (escapers, */
+/* untruncated initial conditions).  q = min(floor((x - lo) (2^42 / L)),    */
+/* 2^42 - 1); the 126-bit key interleaves the bits from the top, x first,   */
+/* and is kept as two words: khi = the first 21 digits (levels 1..21),      */
+/* klo = the last 21 (levels 22..42).                                       */
+/* ---------------------------------------------------------------------- */
+#define OR_BITS42 42
+#define OR_QMAX42 ((1ull << OR_BITS42) - 1ull)
+#define OR_MAXLEVEL42 42
+
+void or_keys42(const double *pos, const int64_t *off, int32_t S,
+               const double *cube, uint64_t *khi, uint64_t *klo) {
+  for (int32_t s = 0; s < S; ++s) {
+    const double *c = cube + 4 * (int64_t)s;
+    double sigma = 4398046511104.0 / c[3];
+    for (int64_t i = off[s]; i < off[s + 1]; ++i) {
+      uint64_t q[3];
+      for (int k = 0; k < 3; ++k) {
+        double t = pos[3 * i + k] - c[k];
+        double u = t * sigma;
+        double f = floor(u);
+        uint64_t qi = (f <= 0.0) ? 0u : (uint64_t)f;
+        if (qi > OR_QMAX42) qi = OR_QMAX42;
+        q[k] = qi;
+      }
+      unsigned __int128 key = 0;
+      for (int j = OR_BITS42 - 1; j >= 0; --j)
+        key = (key << 3) | (((q[0] >> j) & 1u) << 2) |
+              (((q[1] >> j) & 1u) << 1) | ((q[2] >> j) & 1u);
+      khi[i] = (uint64_t)(key >> 63);
+      klo[i] = (uint64_t)(key & (((unsigned __int128)1 << 63) - 1));
+    }
+  }
+}
+
+typedef struct { unsigned __int128 key; uint32_t idx; } or_kv42;
+
+static int or_kv42_cmp(const void *pa, const void *pb) {
+  const or_kv42 *a = (const or_kv42 *)pa, *b = (const or_kv42 *)pb;
+  if (a->key != b->key) return a->key < b->key ? -1 : 1;
+  if (a->idx != b->idx) return a->idx < b->idx ? -1 : 1;
+  return 0;
+}
+
+/* Sort by the 126-bit key, ties by index, within each system. */
+int or_sort42(const uint64_t *khi, const uint64_t *klo, const int64_t *off, int32_t S,
+              uint32_t *perm) {
+  for (int32_t s = 0; s < S; ++s) {
+    int64_t a = off[s], n = off[s + 1] - off[s];
+    if (n <= 0) continue;
+    or_kv42 *kv = (or_kv42 *)malloc(sizeof(or_kv42) * (size_t)n);
+    if (!kv) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+      kv[i].key = ((unsigned __int128)khi[a + i] << 63) | klo[a + i];
+      kv[i].idx = (uint32_t)(a + i);
+    }
+    qsort(kv, (size_t)n, sizeof(or_kv42), or_kv42_cmp);
+    for (int64_t i = 0; i < n; ++i) perm[a + i] = kv[i].idx;
+    free(kv);
+  }
+  return 0;
+}
+
+/* The octree of or_build over 126-bit sorted keys (skhi, sklo): refined    */
+/* below level 42; leaves at level 42 may hold more than nleaf particles.   */
+int64_t or_build42(const uint64_t *skhi, const uint64_t *sklo, const int64_t *off,
+                   int32_t S, int32_t nleaf, int64_t cap, uint8_t *level,
+                   uint32_t *first, uint32_t *count, uint32_t *child, uint8_t *nchild,
+                   int32_t *sys, uint32_t *parent) {
+  int64_t nn = 0;
+  for (int32_t s = 0; s < S; ++s) {
+    if (off[s + 1] <= off[s]) continue;
+    if (nn >= cap) return -1;
+    level[nn] = 0; first[nn] = (uint32_t)off[s];
+    count[nn] = (uint32_t)(off[s + 1] - off[s]);
+    sys[nn] = s; parent[nn] = 0xffffffffu;
+    ++nn;
+  }
+  for (int64_t i = 0; i < nn; ++i) {
+    child[i] = 0; nchild[i] = 0;
+    if (count[i] <= (uint32_t)nleaf || level[i] >= OR_MAXLEVEL42) continue;
+    int shift = 3 * (OR_MAXLEVEL42 - 1 - level[i]);
+    uint32_t j = first[i], end = first[i] + count[i];
+    child[i] = (uint32_t)nn;
+    while (j < end) {
+      unsigned __int128 kj = ((unsigned __int128)skhi[j] << 63) | sklo[j];
+      uint32_t d = (uint32_t)(kj >> shift) & 7u;
+      uint32_t k = j;
+      while (k < end) {
+        unsigned __int128 kk = ((unsigned __int128)skhi[k] << 63) | sklo[k];
+        if (((uint32_t)(kk >> shift) & 7u) != d) break;
+        ++k;
+      }
+      if (nn >= cap) return -1;
+      level[nn] = (uint8_t)(level[i] + 1); first[nn] = j; count[nn] = k - j;
+      sys[nn] = sys[i]; parent[nn] = (uint32_t)i;
+      ++nn; ++nchild[i];
+      j = k;
+    }
+  }
+  return nn;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Moments about the centre of mass (Sec. 1: multipole expansion about the  */
 /* group's centre of mass).  Straight from the particles of each node, in   */
 /* sorted order, two passes:                                                */
