@@ -297,32 +297,52 @@ int64_t or_build42(const uint64_t *skhi, const uint64_t *sklo, const int64_t *of
 /* mom[10 v ..] = M, cx, cy, cz, Sxx, Syy, Szz, Sxy, Sxz, Syz.              */
 /* spos/smass are the particles in sorted order.                            */
 /* ---------------------------------------------------------------------- */
+/* The sums are compensated (Neumaier 1974): s + x is rounded to t and its  */
+/* exact error, (s - t) + x if |s| >= |x| else (x - t) + s, is added to a   */
+/* running correction c; the sum is s + c.  A plain sum over the 10^5      */
+/* particles of a node drifts by ~1e-12 relative, the size of the FP64     */
+/* parity bar; the compensated one stays within a few ulp.                  */
+typedef struct { double s, c; } or_ksum;
+
+static void or_kadd(or_ksum *k, double x) {
+  double t = k->s + x;
+  if (fabs(k->s) >= fabs(x))
+    k->c += (k->s - t) + x;
+  else
+    k->c += (x - t) + k->s;
+  k->s = t;
+}
+
+static double or_kget(const or_ksum *k) { return k->s + k->c; }
+
 void or_moments(const double *spos, const double *smass, int64_t nn,
                 const uint32_t *first, const uint32_t *count, double *mom) {
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t v = 0; v < nn; ++v) {
     uint32_t a = first[v], b = first[v] + count[v];
-    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    or_ksum M = {0, 0}, sx = {0, 0}, sy = {0, 0}, sz = {0, 0};
     for (uint32_t j = a; j < b; ++j) {
       double m = smass[j];
-      M += m;
-      sx += m * spos[3 * (int64_t)j + 0];
-      sy += m * spos[3 * (int64_t)j + 1];
-      sz += m * spos[3 * (int64_t)j + 2];
+      or_kadd(&M, m);
+      or_kadd(&sx, m * spos[3 * (int64_t)j + 0]);
+      or_kadd(&sy, m * spos[3 * (int64_t)j + 1]);
+      or_kadd(&sz, m * spos[3 * (int64_t)j + 2]);
     }
-    double cx = sx / M, cy = sy / M, cz = sz / M;
-    double S[6] = {0, 0, 0, 0, 0, 0};
+    double Mt = or_kget(&M);
+    double cx = or_kget(&sx) / Mt, cy = or_kget(&sy) / Mt, cz = or_kget(&sz) / Mt;
+    or_ksum S[6];
+    for (int k = 0; k < 6; ++k) S[k].s = S[k].c = 0.0;
     for (uint32_t j = a; j < b; ++j) {
       double m = smass[j];
       double dx = spos[3 * (int64_t)j + 0] - cx;
       double dy = spos[3 * (int64_t)j + 1] - cy;
       double dz = spos[3 * (int64_t)j + 2] - cz;
-      S[0] += m * dx * dx; S[1] += m * dy * dy; S[2] += m * dz * dz;
-      S[3] += m * dx * dy; S[4] += m * dx * dz; S[5] += m * dy * dz;
+      or_kadd(&S[0], m * dx * dx); or_kadd(&S[1], m * dy * dy); or_kadd(&S[2], m * dz * dz);
+      or_kadd(&S[3], m * dx * dy); or_kadd(&S[4], m * dx * dz); or_kadd(&S[5], m * dy * dz);
     }
     double *o = mom + 10 * v;
-    o[0] = M; o[1] = cx; o[2] = cy; o[3] = cz;
-    for (int k = 0; k < 6; ++k) o[4 + k] = S[k];
+    o[0] = Mt; o[1] = cx; o[2] = cy; o[3] = cz;
+    for (int k = 0; k < 6; ++k) o[4 + k] = or_kget(&S[k]);
   }
 }
 

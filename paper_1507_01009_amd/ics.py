@@ -202,6 +202,16 @@ def dehnen(n, gamma, seed, mass_fraction=0.99, chunk=1 << 18):
     return pos, vel, np.full(n, 1.0 / n)
 
 
+def clump_in_halo(n, seed, width=1e-7, centre=(1.25, -2.5, 3.75)):
+    """A wide Gaussian cloud (dispersion 100) holding a tight Gaussian clump
+    (dispersion ``width``) of half the particles at ``centre``: a cell side
+    of 2^-21 of the cube does not split the clump, 2^-42 does."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wide = rng.normal(size=(n // 2, 3)) * 100.0
+    clump = np.asarray(centre, np.float64) + rng.normal(size=(n - n // 2, 3)) * width
+    return np.concatenate([wide, clump])
+
+
 # --------------------------------------------------------------------------
 # The five workloads (sizes and parameters of the benchmark configurations)
 # --------------------------------------------------------------------------

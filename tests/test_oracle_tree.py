@@ -219,6 +219,31 @@ def test_moments_parallel_axis_from_children():
         assert np.all(np.abs(S - mom[v, 4:10]) <= 1e-12 * scale)
 
 
+def test_moments_of_large_nodes_are_correctly_summed():
+    """Node masses and centres of mass against exact rational arithmetic:
+    100 000 particles of mass 1e-5 (not a binary fraction) in a clump and a
+    cloud.  Compensated sums stay within 4 ulp; a plain left-to-right sum is
+    off by ~1e-12 at the root (the FP64 parity bar)."""
+    from fractions import Fraction
+    n = 100000
+    pos = ics.clump_in_halo(n, 4, 1e-7, (0.0, 0.0, 0.0))
+    m = np.full(n, 1.0 / n)
+    t = oracle.build_tree(pos, None, 8, 42)
+    sp, sm = oracle.sorted_arrays(t, pos, m)
+    mom = oracle.moments(t, sp, sm)
+    mf = Fraction(float(m[0]))
+    for v in np.argsort(-t.count.astype(np.int64))[:6]:
+        exact = mf * int(t.count[v])
+        assert abs(Fraction(float(mom[v, 0])) - exact) <= 4 * 2.0 ** -53 * exact
+        a, b = int(t.first[v]), int(t.first[v] + t.count[v])
+        for k in range(3):
+            # exact sum of the rounded products m x, as the definition forms them
+            sx = sum((Fraction(float(x)) for x in (sm[a:b] * sp[a:b, k])), Fraction(0))
+            c = sx / (mf * int(t.count[v]))
+            scale = Fraction(float(np.abs(sp[a:b, k]).max()))
+            assert abs(Fraction(float(mom[v, 1 + k])) - c) <= 8 * 2.0 ** -53 * scale
+
+
 # ---------------------------------------------------------------- groups
 @pytest.mark.parametrize("nl,ng", [(8, 64), (8, 8), (16, 32), (4, 1)])
 def test_groups_partition_and_definition(nl, ng):

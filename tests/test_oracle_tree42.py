@@ -64,10 +64,7 @@ def _geometric_tree(q, nleaf):
 def _deep_cluster(n, seed):
     """A wide sphere with a tight clump at a point: 21 levels cannot split
     the clump, 42 can."""
-    rng = np.random.default_rng(seed)
-    wide = rng.normal(size=(n // 2, 3)) * 100.0
-    clump = np.array([1.25, -2.5, 3.75]) + rng.normal(size=(n - n // 2, 3)) * 1e-7
-    return np.concatenate([wide, clump])
+    return ics.clump_in_halo(n, seed)
 
 
 @pytest.mark.parametrize("seed,nleaf", [(1, 1), (2, 4), (3, 8)])
