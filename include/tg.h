@@ -79,6 +79,14 @@ typedef struct {
   int32_t frontier_cap;    /* walk frontier entries per wave; 0 = 16384 */
   int32_t waves_per_cu;    /* resident walk waves per compute unit; 0 = 16 */
   double G;                /* gravitational constant (paper units: 1) */
+  int32_t key_levels;      /* octree depth: 21 (0 = 21) or 42.  42 levels quantise
+                              coordinates to 42 bits and keep the 126-bit key as
+                              two words (the first 21 digits are the 21-level
+                              key), for escapers and untruncated initial
+                              conditions that 21 levels leave in over-full
+                              leaves; it costs a second 8-pass sort and 16 more
+                              bytes per particle.  The relative opening test and
+                              refit take 21-level trees (TG_EINVAL with 42). */
 } tg_config;
 
 typedef struct tg_ctx tg_ctx;
@@ -601,7 +609,8 @@ void tg_graph_destroy(tg_graph *g);
 typedef struct {
   int64_t n, n_nodes, n_groups;
   int32_t n_sys;
-  const uint64_t *skeys;     /* [n] sorted keys */
+  const uint64_t *skeys;     /* [n] sorted keys (42 levels: the first 21 digits) */
+  const uint64_t *skeys_lo;  /* [n] 42 levels: the last 21 digits of the sorted keys; else NULL */
   const uint32_t *perm;      /* [n] sorted rank -> caller index */
   const uint8_t *level;      /* [n_nodes] */
   const uint8_t *nchild;     /* [n_nodes] */

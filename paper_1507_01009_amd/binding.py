@@ -33,13 +33,14 @@ class tg_config(C.Structure):
                 ("leaf_size", C.c_int32), ("group_size", C.c_int32),
                 ("precision", C.c_int32), ("max_nodes", C.c_int64),
                 ("frontier_cap", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("G", C.c_double)]
+                ("G", C.c_double), ("key_levels", C.c_int32)]
 
 
 class tg_tree_view(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_nodes", C.c_int64), ("n_groups", C.c_int64),
                 ("n_sys", C.c_int32),
-                ("skeys", C.c_void_p), ("perm", C.c_void_p), ("level", C.c_void_p),
+                ("skeys", C.c_void_p), ("skeys_lo", C.c_void_p), ("perm", C.c_void_p),
+                ("level", C.c_void_p),
                 ("nchild", C.c_void_p), ("first", C.c_void_p), ("count", C.c_void_p),
                 ("child", C.c_void_p), ("parent", C.c_void_p), ("cube", C.c_void_p),
                 ("com", C.c_void_p), ("mom", C.c_void_p), ("groups", C.c_void_p)]
@@ -273,7 +274,7 @@ class Context:
 
     def __init__(self, max_particles, max_systems=1, leaf_size=8, group_size=64,
                  precision=TG_FP64, max_nodes=0, frontier_cap=0, waves_per_cu=0,
-                 G=1.0, stream=None):
+                 G=1.0, stream=None, key_levels=21):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libtg needs a visible MI355X (no CPU fallback)")
@@ -289,6 +290,7 @@ class Context:
         cfg.frontier_cap = int(frontier_cap)
         cfg.waves_per_cu = int(waves_per_cu)
         cfg.G = float(G)
+        cfg.key_levels = int(key_levels)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = C.c_void_p()
         _check(L.tg_create(C.byref(cfg), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
@@ -550,6 +552,7 @@ class Context:
 
         return {
             "skeys": grab(v.skeys, n, np.uint64), "perm": grab(v.perm, n, np.uint32),
+            "skeys_lo": grab(v.skeys_lo, n, np.uint64) if v.skeys_lo else None,
             "level": grab(v.level, nn, np.uint8), "nchild": grab(v.nchild, nn, np.uint8),
             "first": grab(v.first, nn, np.uint32), "count": grab(v.count, nn, np.uint32),
             "child": grab(v.child, nn, np.uint32), "parent": grab(v.parent, nn, np.uint32),

@@ -1,5 +1,6 @@
-// Bounding cube per system, 21-bit Morton keys, stable LSD radix sort
-// of (key, index), and the gather of positions into sorted order.
+// Bounding cube per system, 21-bit Morton keys (or 42-bit, as two words),
+// stable LSD radix sort of (key, index), and the gather of positions into
+// sorted order.
 //
 // Work is cut into tiles of kSortTile consecutive particles that never cross
 // a system boundary, so one launch handles every system of a batch and the
@@ -113,38 +114,102 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
   return v;
 }
 
-__device__ __forceinline__ uint64_t quantise(double x, double lo, double sigma) {
+// q = min(floor((x - lo) sigma), qmax), sigma = 2^bits / L.
+__device__ __forceinline__ uint64_t quantise(double x, double lo, double sigma, uint64_t qmax) {
   double t = dsub(x, lo);
   double u = dmul(t, sigma);
   double f = floor(u);
   uint64_t q = f <= 0.0 ? 0ull : (uint64_t)f;
-  return q > 0x1FFFFFull ? 0x1FFFFFull : q;
+  return q > qmax ? qmax : q;
 }
 
-// Keys (x bit above y above z at every level) and the identity values.
+// Interleave the low 21 bits of three coordinates (x above y above z).
+__device__ __forceinline__ uint64_t morton21(uint64_t qx, uint64_t qy, uint64_t qz) {
+  return (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+}
+
+// 42 levels: 2^42 / L is 2^21 / L scaled by a power of two, so the top 21
+// bits of each 42-bit coordinate are the 21-bit coordinate and the first
+// key word is the 21-level key; the second word holds the last 21 digits.
+__device__ __forceinline__ void keys42(const double *p, const double *c, double sigma,
+                                       uint64_t &hi, uint64_t &lo) {
+  const uint64_t m = (1ull << 42) - 1ull;
+  const uint64_t qx = quantise(p[0], c[0], sigma, m), qy = quantise(p[1], c[1], sigma, m),
+                 qz = quantise(p[2], c[2], sigma, m);
+  hi = morton21(qx >> 21, qy >> 21, qz >> 21);
+  lo = morton21(qx, qy, qz);
+}
+
+__device__ __forceinline__ int system_of_tile(const uint32_t *sys_tile0, int S, uint32_t t) {
+  int lo_s = 0, hi_s = S - 1;     // last s with sys_tile0[s] <= t
+  while (lo_s < hi_s) {
+    int mid = (lo_s + hi_s + 1) >> 1;
+    if (sys_tile0[mid] <= t) lo_s = mid; else hi_s = mid - 1;
+  }
+  return lo_s;
+}
+
+// Keys (x bit above y above z at every level) and the identity values;
+// with kDeep the 42-level key's first word goes to key and its second to
+// klo.
+template <bool kDeep>
 __global__ __launch_bounds__(256) void k_keys(const int32_t *__restrict__ gate, const double *__restrict__ pos,
                                               const Tile *__restrict__ tiles,
                                               const uint32_t *__restrict__ sys_tile0,
                                               int S, const double *__restrict__ cube,
                                               uint64_t *__restrict__ key,
+                                              uint64_t *__restrict__ klo,
                                               uint32_t *__restrict__ val) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
   const Tile t = tiles[blockIdx.x];
-  // system of this tile: last s with sys_tile0[s] <= tile
-  int lo_s = 0, hi_s = S - 1;
-  while (lo_s < hi_s) {
-    int mid = (lo_s + hi_s + 1) >> 1;
-    if (sys_tile0[mid] <= blockIdx.x) lo_s = mid; else hi_s = mid - 1;
-  }
-  const double *c = cube + 4 * lo_s;
-  const double sigma = 2097152.0 / c[3];
+  const double *c = cube + 4 * system_of_tile(sys_tile0, S, blockIdx.x);
+  const double sigma = (kDeep ? 4398046511104.0 : 2097152.0) / c[3];
   for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u) {
-    uint64_t qx = quantise(pos[3 * (size_t)i + 0], c[0], sigma);
-    uint64_t qy = quantise(pos[3 * (size_t)i + 1], c[1], sigma);
-    uint64_t qz = quantise(pos[3 * (size_t)i + 2], c[2], sigma);
-    key[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    if constexpr (kDeep) {
+      uint64_t hi, lo;
+      keys42(pos + 3 * (size_t)i, c, sigma, hi, lo);
+      key[i] = hi;
+      klo[i] = lo;
+    } else {
+      const uint64_t m = 0x1FFFFFull;
+      key[i] = morton21(quantise(pos[3 * (size_t)i + 0], c[0], sigma, m),
+                        quantise(pos[3 * (size_t)i + 1], c[1], sigma, m),
+                        quantise(pos[3 * (size_t)i + 2], c[2], sigma, m));
+    }
     val[i] = i;
   }
+}
+
+// 42 levels, after the sort: the second key words in sorted order, from
+// the positions of the sorted particles (slo[r] for perm[r]).
+__global__ void k_keys_lo_sorted(const int32_t *__restrict__ gate, const double *__restrict__ pos,
+                                 const uint32_t *__restrict__ perm, int64_t n,
+                                 const int64_t *__restrict__ sysoff, int S,
+                                 const double *__restrict__ cube, uint64_t *__restrict__ slo) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    int a = 0, b = S - 1;          // last s with sysoff[s] <= r
+    while (a < b) {
+      const int mid = (a + b + 1) >> 1;
+      if (sysoff[mid] <= r) a = mid; else b = mid - 1;
+    }
+    const double *c = cube + 4 * a;
+    uint64_t hi, lo;
+    keys42(pos + 3 * (size_t)perm[r], c, 4398046511104.0 / c[3], hi, lo);
+    slo[r] = lo;
+  }
+}
+
+// 42 levels, between the two sort phases: first words in the order of the
+// first phase (sorted by the second word), hi_out[r] = hi_in[perm[r]].
+__global__ void k_gather_u64(const int32_t *__restrict__ gate, const uint64_t *__restrict__ in,
+                             const uint32_t *__restrict__ perm, int64_t n,
+                             uint64_t *__restrict__ out) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x)
+    out[r] = in[perm[r]];
 }
 
 // ---- radix sort, 8-bit digits ----------------------------------------
@@ -377,9 +442,38 @@ hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
                        b.tiles, b.cube_part, b.err);
   hipLaunchKernelGGL(k_cube_final, dim3(c->S), dim3(256), 0, c->stream, c->gate,
                      b.cube_part, b.sys_tile0, b.cube);
-  if (nt > 0)
-    hipLaunchKernelGGL(k_keys, dim3(nt), dim3(256), 0, c->stream, c->gate, pos, b.tiles,
-                       b.sys_tile0, c->S, b.cube, b.key[0], b.val[0]);
+  if (nt > 0 && c->max_level > kMaxLevel)
+    // first words in caller order to key[1], second words to klo[0] (sorted first)
+    hipLaunchKernelGGL(k_keys<true>, dim3(nt), dim3(256), 0, c->stream, c->gate, pos, b.tiles,
+                       b.sys_tile0, c->S, b.cube, b.key[1], b.klo[0], b.val[0]);
+  else if (nt > 0)
+    hipLaunchKernelGGL(k_keys<false>, dim3(nt), dim3(256), 0, c->stream, c->gate, pos, b.tiles,
+                       b.sys_tile0, c->S, b.cube, b.key[0], nullptr, b.val[0]);
+  return hipGetLastError();
+}
+
+// 8 passes of (ka, va) with (kb, vb) as the other buffers: the result is
+// back in ka / va.
+static hipError_t sort8(tg_ctx *c, uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb) {
+  Buffers &b = c->b;
+  const int nt = (int)c->n_tiles;
+  // [8 tickets | pad | counts [S][8][256] | status [8][nt][256]], all zero
+  uint32_t *tickets = b.hist, *cnt = b.hist + kSortStatusBase;
+  uint32_t *status = cnt + (size_t)c->S * 8 * 256;
+  hipError_t e = fill_u32(b.hist, 0u, kSortStatusBase + (int64_t)8 * 256 * (c->S + nt),
+                          c->stream, c->gate);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sort_count, dim3(nt), dim3(256), 0, c->stream, c->gate, ka, b.tiles,
+                     b.sys_tile0, c->S, cnt);
+  uint64_t *k2[2] = {ka, kb};
+  uint32_t *v2[2] = {va, vb};
+  for (int pass = 0; pass < 8; ++pass) {
+    const int src = pass & 1, dst = src ^ 1;
+    hipLaunchKernelGGL(k_sort_pass, dim3(nt), dim3(256), 0, c->stream, c->gate, k2[src],
+                       v2[src], k2[dst], v2[dst], b.tiles, b.sys_tile0, c->S,
+                       b.sysoff, pass, cnt, status + (size_t)pass * 256 * nt,
+                       tickets + pass, b.err);
+  }
   return hipGetLastError();
 }
 
@@ -387,22 +481,27 @@ hipError_t launch_sort(tg_ctx *c) {
   Buffers &b = c->b;
   const int nt = (int)c->n_tiles;
   if (nt == 0) return hipSuccess;
-  // [8 tickets | pad | counts [S][8][256] | status [8][nt][256]], all zero
-  uint32_t *tickets = b.hist, *cnt = b.hist + kSortStatusBase;
-  uint32_t *status = cnt + (size_t)c->S * 8 * 256;
-  hipError_t e = fill_u32(b.hist, 0u, kSortStatusBase + (int64_t)8 * 256 * (c->S + nt),
-                          c->stream, c->gate);
+  if (c->max_level <= kMaxLevel)
+    return sort8(c, b.key[0], b.val[0], b.key[1], b.val[1]);   // result in key[0] / val[0]
+  // 42 levels, least significant word first: sort by the second words,
+  // carry the first words into that order, sort them (stable), then the
+  // second words of the final order from the positions
+  hipError_t e = sort8(c, b.klo[0], b.val[0], b.klo[1], b.val[1]);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sort_count, dim3(nt), dim3(256), 0, c->stream, c->gate, b.key[0], b.tiles,
-                     b.sys_tile0, c->S, cnt);
-  for (int pass = 0; pass < 8; ++pass) {
-    const int src = pass & 1, dst = src ^ 1;
-    hipLaunchKernelGGL(k_sort_pass, dim3(nt), dim3(256), 0, c->stream, c->gate, b.key[src],
-                       b.val[src], b.key[dst], b.val[dst], b.tiles, b.sys_tile0, c->S,
-                       b.sysoff, pass, cnt, status + (size_t)pass * 256 * nt,
-                       tickets + pass, b.err);
-  }
-  return hipGetLastError();   // 8 passes: result back in key[0] / val[0]
+  const int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_gather_u64, dim3(g), dim3(256), 0, c->stream, c->gate, b.key[1],
+                     b.val[0], c->n, b.key[0]);
+  return sort8(c, b.key[0], b.val[0], b.key[1], b.val[1]);
+}
+
+// 42 levels: the second key words of the sorted particles (klo[0]).
+hipError_t launch_keys_lo(tg_ctx *c, const double *pos) {
+  Buffers &b = c->b;
+  if (c->max_level <= kMaxLevel || c->n == 0) return hipSuccess;
+  const int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_keys_lo_sorted, dim3(g), dim3(256), 0, c->stream, c->gate, pos,
+                     b.val[0], c->n, b.sysoff, c->S, b.cube, b.klo[0]);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather(tg_ctx *c, const double *pos, const double *mass) {

@@ -78,28 +78,32 @@ __global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restric
        v += gridDim.x * blockDim.x) {
     if (nchild[v] != 0) continue;
     const uint32_t f = first[v], end = f + count[v];
-    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    // compensated sums: a leaf may hold any number of coincident particles
+    CSum Mc, sxc, syc, szc;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t j = f; j < end; ++j) {
       const double4 p = spart[j];
-      M += p.w;
-      sx += p.w * p.x;
-      sy += p.w * p.y;
-      sz += p.w * p.z;
+      Mc.add(p.w);
+      sxc.add(p.w * p.x);
+      syc.add(p.w * p.y);
+      szc.add(p.w * p.z);
       if constexpr (kBox) {
         lo[0] = fmin(lo[0], p.x); lo[1] = fmin(lo[1], p.y); lo[2] = fmin(lo[2], p.z);
         hi[0] = fmax(hi[0], p.x); hi[1] = fmax(hi[1], p.y); hi[2] = fmax(hi[2], p.z);
         bad |= !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z);
       }
     }
-    const double cx = sx / M, cy = sy / M, cz = sz / M;
-    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double M = Mc.get();
+    const double cx = sxc.get() / M, cy = syc.get() / M, cz = szc.get() / M;
+    CSum Sc[6];
     for (uint32_t j = f; j < end; ++j) {
       const double4 p = spart[j];
       const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
-      S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
-      S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
+      Sc[0].add(p.w * dx * dx); Sc[1].add(p.w * dy * dy); Sc[2].add(p.w * dz * dz);
+      Sc[3].add(p.w * dx * dy); Sc[4].add(p.w * dx * dz); Sc[5].add(p.w * dy * dz);
     }
+    double S[6];
+    for (int k = 0; k < 6; ++k) S[k] = Sc[k].get();
     double so;
     if constexpr (kBox) {
       bbox[2 * (size_t)v] = make_double4(lo[0], lo[1], lo[2], 0.0);
@@ -201,7 +205,7 @@ static void launch_moment_passes(tg_ctx *c) {
   hipLaunchKernelGGL((k_moments_leaves<kBox>), dim3(1024), dim3(256), 0, c->stream, c->gate,
                      b.ctr, b.cube, b.level, b.nchild, b.first, b.count, b.nsys, b.spart,
                      b.key[0], b.refit_flag, b.com, b.mom, b.side, b.bbox, b.err);
-  for (int l = kMaxLevel - 1; l >= 0; --l)     // level 21 holds only leaves
+  for (int l = c->max_level - 1; l >= 0; --l)    // the deepest level holds only leaves
     hipLaunchKernelGGL((k_moments_level<kBox>), dim3(512), dim3(256), 0, c->stream, c->gate, l,
                        b.ctr, b.cube, b.nchild, b.child, b.nsys, b.first, b.key[0],
                        b.refit_flag, b.com, b.mom, b.side, b.bbox);

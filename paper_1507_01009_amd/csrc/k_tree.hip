@@ -1,13 +1,13 @@
 // Octree over the sorted keys, all levels at once, and the walk groups.
 //
 // d[i] = number of equal leading key digits of sorted particles i-1 and i
-// (0 at the first particle of every system and at the end, 21 for equal
-// keys).  A level-l run is a maximal range of equal first l digits; one
-// starts at i exactly when d[i] < l (l >= 1; level 0 is the whole system).
-// A node is a run whose parent run holds more than n_L particles (and
-// splits only if l < 21), so with lo = d[i] + 1 the nodes starting at i are
-// the levels [lo, top] with
-//   top = min(21, max(lo, m + 1)),  m = min(d[i+1 .. i+n_L]),
+// (0 at the first particle of every system and at the end, D for equal
+// keys, D = 21 with one key word and 42 with two).  A level-l run is a
+// maximal range of equal first l digits; one starts at i exactly when
+// d[i] < l (l >= 1; level 0 is the whole system).  A node is a run whose
+// parent run holds more than n_L particles (and splits only if l < D), so
+// with lo = d[i] + 1 the nodes starting at i are the levels [lo, top] with
+//   top = min(D, max(lo, m + 1)),  m = min(d[i+1 .. i+n_L]),
 // provided the parent run of the first of them is longer than n_L, which
 // is decided inside a window of n_L bytes on either side of i.  A system's
 // root always exists and splits if the system holds more than n_L.
@@ -46,9 +46,16 @@ __device__ void load_sysoff(int64_t *so, const int64_t *sysoff, int S) {
   __syncthreads();
 }
 
+__device__ __forceinline__ uint32_t common_digits(uint64_t a, uint64_t b) {
+  const uint64_t x = a ^ b;
+  return x == 0 ? 21u : (uint32_t)(__clzll((long long)x) - 1) / 3u;   // bit 63 is 0
+}
+
 // d for [0, n + 64): the common leading digits with the predecessor, 0 at
-// every system start and from n on.
-__global__ __launch_bounds__(256) void k_lcp(const int32_t *__restrict__ gate, const uint64_t *__restrict__ skey, int64_t n,
+// every system start and from n on.  With second key words (skey_lo not
+// null) the digits continue into them when the first words are equal.
+__global__ __launch_bounds__(256) void k_lcp(const int32_t *__restrict__ gate, const uint64_t *__restrict__ skey,
+                                             const uint64_t *__restrict__ skey_lo, int64_t n,
                                              const int64_t *__restrict__ sysoff, int S,
                                              uint8_t *__restrict__ d) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
@@ -58,8 +65,8 @@ __global__ __launch_bounds__(256) void k_lcp(const int32_t *__restrict__ gate, c
        i += (int64_t)gridDim.x * blockDim.x) {
     uint32_t v = 0;
     if (i > 0 && i < n && so[sys_of(so, S, i)] != i) {
-      const uint64_t x = skey[i - 1] ^ skey[i];
-      v = x == 0 ? 21u : (uint32_t)(__clzll((long long)x) - 1) / 3u;   // bit 63 is 0
+      v = common_digits(skey[i - 1], skey[i]);
+      if (skey_lo && v == 21u) v += common_digits(skey_lo[i - 1], skey_lo[i]);
     }
     d[i] = (uint8_t)v;
   }
@@ -68,7 +75,9 @@ __global__ __launch_bounds__(256) void k_lcp(const int32_t *__restrict__ gate, c
 // Per tile b of kFT particles: lt[i] = lo | top << 8 of the nodes starting
 // at i (0xffff: none); bits[l][4 b + w] = ballot of "a level-l node starts
 // here" of wave w; cnt[l][b] = nodes of level l in the tile; fst[l][b] =
-// first run start of level l in the tile (first i with d[i] < l).
+// first run start of level l in the tile (first i with d[i] < l).  ML is
+// the deepest level.
+template <int ML>
 __global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ gate, int64_t n, int nleaf, int S,
                                                     const int64_t *__restrict__ sysoff,
                                                     const uint8_t *__restrict__ d,
@@ -79,15 +88,16 @@ __global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ 
   if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint8_t sd[kHalo + kFT + 2 * kHalo];
   __shared__ int64_t so[kMaxSys + 1];
-  __shared__ uint32_t wc[kFT / 64][kLevels];
-  __shared__ uint32_t mj[kLevels];
+  constexpr int kL = ML + 1;
+  __shared__ uint32_t wc[kFT / 64][kL];
+  __shared__ uint32_t mj[kL];
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x, t0 = b * kFT, i = t0 + tid;
   for (int k = tid; k < kHalo + kFT + 2 * kHalo; k += kFT) {
     const int64_t p = t0 - kHalo + k;
     sd[k] = (p >= 0 && p < n + 64) ? d[p] : (uint8_t)0;
   }
-  if (tid < kLevels) mj[tid] = 0xffffffffu;
+  if (tid < kL) mj[tid] = 0xffffffffu;
   load_sysoff(so, sysoff, S);
   const bool valid = i < n;
   bool ex = false;
@@ -102,11 +112,11 @@ __global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ 
     if (seg) {
       ex = true;
       lo = 0;
-      top = size > nleaf ? min(21u, max(1u, m + 1)) : 0u;
+      top = size > nleaf ? min((uint32_t)ML, max(1u, m + 1)) : 0u;
     } else {
       const uint32_t p = di[0];
       lo = p + 1;
-      if (lo <= 21u) {
+      if (lo <= (uint32_t)ML) {
         if (p == 0) {
           ex = size > nleaf;                  // the parent is the root
         } else {
@@ -120,7 +130,7 @@ __global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ 
               if (di[k] < p) { ex = false; break; }
           }
         }
-        top = min(21u, max(lo, m + 1));
+        top = min((uint32_t)ML, max(lo, m + 1));
       }
     }
     atomicMin(&mj[di[0]], (uint32_t)i);
@@ -128,7 +138,7 @@ __global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ 
   if (valid) lt[i] = ex ? (uint16_t)(lo | (top << 8)) : (uint16_t)0xffff;
   const int w = tid >> 6, lane = tid & 63;
 #pragma unroll
-  for (int l = 0; l < kLevels; ++l) {
+  for (int l = 0; l < kL; ++l) {
     const unsigned long long msk = __ballot(ex && lo <= (uint32_t)l && (uint32_t)l <= top);
     if (lane == 0) {
       bits[l * wl + 4 * b + w] = msk;
@@ -136,7 +146,7 @@ __global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ 
     }
   }
   __syncthreads();
-  if (tid < kLevels) {
+  if (tid < kL) {
     const int l = tid;
     uint32_t c = 0;
     for (int q = 0; q < kFT / 64; ++q) c += wc[q][l];
@@ -210,7 +220,8 @@ __device__ __forceinline__ uint32_t rank_of(const uint64_t *__restrict__ bl,
   return r;
 }
 
-// Nodes of tile b written at their canonical ids.
+// Nodes of tile b written at their canonical ids (ML: the deepest level).
+template <int ML>
 __global__ __launch_bounds__(kFT) void k_flat_emit(const int32_t *__restrict__ gate, 
     int64_t n, int S, const int64_t *__restrict__ sysoff, const uint8_t *__restrict__ d,
     const uint16_t *__restrict__ lt, const uint64_t *__restrict__ bits, int64_t wl,
@@ -224,21 +235,22 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(const int32_t *__restrict__ g
   __shared__ uint8_t sd[kFT];
   __shared__ uint8_t mn8[kFT / 8], mn64[kFT / 64];
   __shared__ int64_t so[kMaxSys + 1];
-  __shared__ uint32_t lv[kLevels + 1];
+  constexpr int kL = ML + 1;
+  __shared__ uint32_t lv[kL + 1];
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x, t0 = b * kFT, i = t0 + tid;
   if (tid == 0) {
     uint32_t a = 0;
-    for (int l = 0; l < kLevels; ++l) { lv[l] = a; a += tot[l]; }
-    lv[kLevels] = a;
+    for (int l = 0; l < kL; ++l) { lv[l] = a; a += tot[l]; }
+    lv[kL] = a;
   }
   sd[tid] = i < n + 64 ? d[i] : (uint8_t)0;
   load_sysoff(so, sysoff, S);               // (includes a barrier)
-  const uint32_t nn = lv[kLevels];
+  const uint32_t nn = lv[kL];
   const bool ovf = (int64_t)nn > max_nodes;
   if (b == 0 && tid == 0) {
-    for (int l = 0; l <= kLevels; ++l) ctr->lvl[l] = ovf ? 0u : lv[l];
-    ctr->lvl[kLevels + 1] = ovf ? 0u : nn;
+    for (int l = 0; l <= kL; ++l) ctr->lvl[l] = ovf ? 0u : lv[l];
+    ctr->lvl[kL + 1] = ovf ? 0u : nn;
     ctr->n_nodes = ovf ? 0u : nn;
     ctr->overflow = ovf ? 1u : 0u;
     if (ovf) set_err(err, TG_ERR_NODES);
@@ -332,23 +344,35 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(const int32_t *__restrict__ g
   }
 }
 
-hipError_t launch_tree_build(tg_ctx *c) {
+template <int ML>
+static void launch_flat(tg_ctx *c, int64_t T) {
   Buffers &b = c->b;
-  const int64_t n = c->n, T = (n + kFT - 1) / kFT;
+  const int64_t n = c->n;
   const int64_t wl = 4 * (c->flat_tiles + 1), tl = c->flat_tiles + 1;
-  hipLaunchKernelGGL(k_lcp, dim3((int)std::min<int64_t>((n + 64 + 255) / 256, 4096)),
-                     dim3(256), 0, c->stream, c->gate, b.key[0], n, b.sysoff, c->S, b.lcp);
   if (T > 0)
-    hipLaunchKernelGGL(k_flat_flags, dim3((unsigned)T), dim3(kFT), 0, c->stream, c->gate, n,
+    hipLaunchKernelGGL(k_flat_flags<ML>, dim3((unsigned)T), dim3(kFT), 0, c->stream, c->gate, n,
                        c->leaf_size, c->S, b.sysoff, b.lcp, b.fl_lt, b.fl_bits, wl,
                        b.fl_cnt, b.fl_fst, tl);
-  hipLaunchKernelGGL(k_flat_scan, dim3(kLevels), dim3(1024), 0, c->stream, c->gate, T, n,
+  hipLaunchKernelGGL(k_flat_scan, dim3(ML + 1), dim3(1024), 0, c->stream, c->gate, T, n,
                      b.fl_cnt, b.fl_fst, tl, b.fl_tot);
-  hipLaunchKernelGGL(k_flat_emit, dim3((unsigned)std::max<int64_t>(T, 1)), dim3(kFT), 0,
+  hipLaunchKernelGGL(k_flat_emit<ML>, dim3((unsigned)std::max<int64_t>(T, 1)), dim3(kFT), 0,
                      c->stream, c->gate, n, c->S, b.sysoff, b.lcp, b.fl_lt, b.fl_bits, wl,
                      b.fl_cnt, b.fl_fst, tl, b.fl_tot, c->max_nodes, b.ctr, b.err,
                      b.root_of, b.level, b.nchild, b.first, b.count, b.child, b.parent,
                      b.nsys, b.ninfo);
+}
+
+hipError_t launch_tree_build(tg_ctx *c) {
+  Buffers &b = c->b;
+  const int64_t n = c->n, T = (n + kFT - 1) / kFT;
+  const bool deep = c->max_level > kMaxLevel;
+  hipLaunchKernelGGL(k_lcp, dim3((int)std::min<int64_t>((n + 64 + 255) / 256, 4096)),
+                     dim3(256), 0, c->stream, c->gate, b.key[0], deep ? b.klo[0] : nullptr, n,
+                     b.sysoff, c->S, b.lcp);
+  if (deep)
+    launch_flat<kMaxLevelDeep>(c, T);
+  else
+    launch_flat<kMaxLevel>(c, T);
   return hipGetLastError();
 }
 

@@ -200,13 +200,14 @@ __device__ __forceinline__ void p2m_term(typename Vec4<R>::T a, typename Vec4<R>
   ph = fma(-D1, fma(R(0.5), k, a.w), ph);      // M D1 + 0.5 D5 W
 }
 
-// Softened particle term, source s = {position, m}.
+// Softened particle term, source s = {position, m}; keep = false drops the
+// pair (a target and itself).
 template <class R>
 __device__ __forceinline__ void p2p_term(typename Vec4<R>::T s, R tx, R ty, R tz, R e2,
-                                         R &ax, R &ay, R &az, R &ph) {
+                                         R &ax, R &ay, R &az, R &ph, bool keep = true) {
   const R dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
   const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-  const R D1 = rsq(r2);
+  const R D1 = keep ? rsq(r2) : R(0);
   const R mD1 = s.w * D1;
   const R mD3 = mD1 * (D1 * D1);
   ax = fma(-mD3, dx, ax);
@@ -300,10 +301,11 @@ __device__ __forceinline__ void p2m_spline(typename Vec4<R>::T a, typename Vec4<
   ph -= fma(p2, V6, fma(R(-0.5) * p1, b.w, a.w * p0));
 }
 
-// Spline-softened particle term, source s = {position, m}.
+// Spline-softened particle term, source s = {position, m}; keep = false
+// drops the pair (a target and itself: x = 0, only the potential term).
 template <class R>
 __device__ __forceinline__ void p2p_spline(typename Vec4<R>::T s, R tx, R ty, R tz, R h, R ih,
-                                           R &ax, R &ay, R &az, R &ph) {
+                                           R &ax, R &ay, R &az, R &ph, bool keep = true) {
   const R dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
   const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   R p0, p1;
@@ -312,7 +314,7 @@ __device__ __forceinline__ void p2p_spline(typename Vec4<R>::T s, R tx, R ty, R 
   ax = fma(-mp1, dx, ax);
   ay = fma(-mp1, dy, ay);
   az = fma(-mp1, dz, az);
-  ph -= s.w * p0;
+  ph -= keep ? s.w * p0 : R(0);
 }
 
 // ---------------------------------------------------------------- tiles
@@ -362,6 +364,13 @@ struct ForceSink {
   R e2;
   R h, ih;                           // spline softening length and its inverse
   R tx[kMaxT], ty[kMaxT], tz[kMaxT];
+  const uint32_t *s_tgt;             // sorted indices of the nt targets (LDS)
+  int nt;
+  // The group's own particles [g0, g0 + gn) met in refused leaves are not
+  // queued: bit b of own (own0 | own1 << 64) marks particle g0 + b, and
+  // they are evaluated last, each target without its own pair.
+  uint32_t g0, gn;
+  unsigned long long own0, own1;     // wave-uniform
   // per-target totals in FP64 (mixed: each tile's FP32 partial sums are
   // added here, so rounding accumulates only within a tile)
   double hax[kMaxT], hay[kMaxT], haz[kMaxT], hph[kMaxT];
@@ -399,13 +408,26 @@ struct ForceSink {
     for (int k = 0; k < kT; ++k) add(k, ax[k], ay[k], az[k], ph[k]);
   }
 
-  template <int kT>
-  __device__ void eval_p(int base, int trips) {
+  // kOwn: entry et[k] of the tile is target k itself, its pair dropped
+  template <int kT, bool kOwn = false>
+  __device__ void eval_p(int base, int trips, const uint32_t *et = nullptr) {
     R ax[kT], ay[kT], az[kT], ph[kT];
 #pragma unroll
     for (int k = 0; k < kT; ++k) ax[k] = ay[k] = az[k] = ph[k] = R(0);
     const R4 *e = &tile->p[base];
-    if constexpr (kSpline) {
+    if constexpr (kOwn) {
+      for (int it = 0; it < trips; ++it) {
+        const R4 s = e[it];
+        const uint32_t en = (uint32_t)(base + it);
+#pragma unroll
+        for (int k = 0; k < kT; ++k) {
+          if constexpr (kSpline)
+            p2p_spline<R>(s, tx[k], ty[k], tz[k], h, ih, ax[k], ay[k], az[k], ph[k], en != et[k]);
+          else
+            p2p_term<R>(s, tx[k], ty[k], tz[k], e2, ax[k], ay[k], az[k], ph[k], en != et[k]);
+        }
+      }
+    } else if constexpr (kSpline) {
       for (int it = 0; it < trips; ++it) {
         const R4 s = e[it];
 #pragma unroll
@@ -492,6 +514,64 @@ struct ForceSink {
     __syncthreads();
   }
 
+  // rank among the own particles of bit b (b < 128)
+  __device__ uint32_t own_rank(uint32_t b) const {
+    return b < 64u ? (uint32_t)__popcll(own0 & ((1ull << b) - 1ull))
+                   : (uint32_t)__popcll(own0) +
+                         (uint32_t)__popcll(own1 & ((1ull << (b - 64u)) - 1ull));
+  }
+
+  __device__ bool own_bit(uint32_t b) const {
+    return b < 64u ? ((own0 >> b) & 1ull) != 0ull : ((own1 >> (b - 64u)) & 1ull) != 0ull;
+  }
+
+  // One tile of the kq queued particles s_q[0, kq) followed by the own
+  // particles of ranks [o, o + k) at entries kq + rank - o, each target
+  // without itself.
+  __device__ void flush_own(const WalkArgs &A, int kq, uint32_t o, int k) {
+    const uint32_t lane = lane_id();
+    const int trips = trips_for(kq + k);
+    const int ne = slices * trips;
+    for (int e = (int)lane; e < kq; e += 64) stage_part(A, e, true, s_q[e]);
+    for (uint32_t b = lane; b < 128u; b += 64u) {
+      if (b < gn && own_bit(b)) {
+        const int e = (int)(own_rank(b) - o);
+        if (e >= 0 && e < k) stage_part(A, kq + e, true, g0 + b);
+      }
+    }
+    for (int e = kq + k + (int)lane; e < ne; e += 64) stage_part(A, e, false, 0u);
+    // the lane's targets as placed at the start (missing ones repeat j)
+    const int j = (int)lane % lt;
+    uint32_t et[kMaxT];
+#pragma unroll
+    for (int q = 0; q < kMaxT; ++q) {
+      const int i = j + q * lt;
+      const uint32_t b = s_tgt[i < nt ? i : j] - g0;   // < gn: targets lie in the group
+      et[q] = own_bit(b) ? own_rank(b) - o + (uint32_t)kq : 0xffffffffu;
+    }
+    __syncthreads();
+    const int base = my_s * trips;
+    if (T == 1) eval_p<1, true>(base, trips, et);
+    else if constexpr (kMaxT >= 2) {
+      if (T == 2) eval_p<2, true>(base, trips, et);
+      else if constexpr (kMaxT >= 3) eval_p<3, true>(base, trips, et);
+    }
+    __syncthreads();
+  }
+
+  // Queue the particles [lf, lf + lc), flushing whenever a tile is full.
+  __device__ void append_run(const WalkArgs &A, uint32_t lf, uint32_t lc) {
+    uint32_t o = 0;
+    while (o < lc) {
+      const uint32_t take = min(lc - o, (uint32_t)kQCap - nq);
+      for (uint32_t j = lane_id(); j < take; j += 64u) s_q[nq + j] = lf + o + j;
+      nq += take;
+      o += take;
+      __syncthreads();
+      drain_q(A);
+    }
+  }
+
   __device__ void p2m(const WalkArgs &A, bool pred, uint32_t node) {
     const unsigned long long mask = __ballot(pred);
     if (mask == 0ull) return;
@@ -521,35 +601,59 @@ struct ForceSink {
     const unsigned long long mask = __ballot(pred);
     if (mask == 0ull) return;
     parts += tot;
+    // the leaf minus the group's own particles: [f, oa) and [ob, f + c)
+    uint32_t oa = f + c, ob = f + c;
+    if (pred) {
+      oa = min(max(f, g0), f + c);
+      ob = min(max(f, g0 + gn), f + c);
+    }
+    const unsigned long long omask = __ballot(ob > oa);
+    if (omask != 0ull) {
+      // rare (the group's own leaves): mark them, queue the rest
+      unsigned long long m = omask;
+      while (m) {
+        const int L = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)oa, L) - g0;
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)ob, L) - g0;
+        for (uint32_t q = a; q < b; ++q) {     // at most gn <= 128 bits in all
+          if (q < 64u) own0 |= 1ull << q; else own1 |= 1ull << (q - 64u);
+        }
+      }
+      pre = wave_excl_scan(c - (ob - oa), tot);
+    }
+    const uint32_t left = oa - f, right = f + c - ob;
     if (nq + tot <= (uint32_t)kQCap) {
-      for (uint32_t k = 0; k < c; ++k) s_q[nq + pre + k] = f + k;
+      for (uint32_t k = 0; k < left; ++k) s_q[nq + pre + k] = f + k;
+      for (uint32_t k = 0; k < right; ++k) s_q[nq + pre + left + k] = ob + k;
       nq += tot;
       __syncthreads();
       drain_q(A);
       return;
     }
-    // rare: many large leaves at once; one leaf at a time
+    // rare: many large leaves at once; one run at a time
     unsigned long long m = mask;
     while (m) {
       const int L = __ffsll((long long)m) - 1;
       m &= m - 1ull;
-      const uint32_t lf = __shfl(f, L, 64), lc = __shfl(c, L, 64);
-      uint32_t o = 0;
-      while (o < lc) {
-        const uint32_t take = min(lc - o, (uint32_t)kQCap - nq);
-        for (uint32_t j = lane_id(); j < take; j += 64u) s_q[nq + j] = lf + o + j;
-        nq += take;
-        o += take;
-        __syncthreads();
-        drain_q(A);
-      }
+      append_run(A, (uint32_t)__shfl((int)f, L, 64), (uint32_t)__shfl((int)left, L, 64));
+      append_run(A, (uint32_t)__shfl((int)ob, L, 64), (uint32_t)__shfl((int)right, L, 64));
     }
   }
 
   __device__ void finish(const WalkArgs &A) {
     if (nm > 0) flush_p2m(A, s_m, (int)nm);
-    if (nq > 0) flush_p2p(A, s_q, (int)nq);
-    nm = nq = 0;
+    nm = 0;
+    // the queue's rest (nq < F) and the own particles share the last tiles
+    const uint32_t no = (uint32_t)(__popcll(own0) + __popcll(own1));
+    uint32_t o = 0;
+    while (nq + (no - o) > 0u) {
+      const uint32_t k = min(no - o, (uint32_t)F - nq);
+      flush_own(A, (int)nq, o, (int)k);
+      nq = 0;
+      o += k;
+    }
+    own0 = own1 = 0ull;
   }
 };
 
@@ -719,6 +823,8 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
     Sink S;
     S.s_m = s_m; S.s_q = s_q; S.tile = &tile;
     S.nm = 0; S.nq = 0; S.cells = 0; S.parts = 0;
+    S.g0 = gr.x; S.gn = gr.y; S.own0 = S.own1 = 0ull;
+    S.s_tgt = s_tgt; S.nt = nt;
     S.T = T; S.lt = lt; S.slices = slices;
     S.tfull = (64 + slices - 1) / slices;
     S.F = slices * S.tfull;
@@ -763,14 +869,6 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
       }
       const uint32_t r_t = s_tgt[i];
       const double4 p = A.spart[r_t];
-      // the P2P sums include each target with itself: remove that term
-      double self;
-      if constexpr (kSpline)
-        self = (double)((R)p.w * (S.ih * R(1.4)));
-      else if constexpr (kMixed)
-        self = (double)((float)p.w * __builtin_amdgcn_rsqf((float)A.eps2));
-      else
-        self = p.w * rsqrt_dp(A.eps2);
       const uint32_t orig = A.perm[r_t];
       const double nanv = __longlong_as_double(0x7ff8000000000000ll);
       double ex = 0.0, ey = 0.0, ez = 0.0, ep = 0.0;
@@ -797,7 +895,7 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
       A.acc[3 * (size_t)orig + 0] = ok ? A.G * (ax + ex) : nanv;
       A.acc[3 * (size_t)orig + 1] = ok ? A.G * (ay + ey) : nanv;
       A.acc[3 * (size_t)orig + 2] = ok ? A.G * (az + ez) : nanv;
-      if (A.pot) A.pot[orig] = ok ? A.G * (ph + self + ep) : nanv;
+      if (A.pot) A.pot[orig] = ok ? A.G * (ph + ep) : nanv;
     }
     tot_p2m += S.cells * (unsigned long long)nt;
     tot_p2p += S.parts * (unsigned long long)nt - (unsigned long long)nt;

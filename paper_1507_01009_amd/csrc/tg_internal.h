@@ -21,9 +21,11 @@
 
 namespace tg {
 
-constexpr int kBits = 21;             // key bits per axis
-constexpr int kMaxLevel = 21;         // deepest octree level
+constexpr int kBits = 21;             // key bits per axis (one key word)
+constexpr int kMaxLevel = 21;         // deepest octree level of one key word
 constexpr int kLevels = kMaxLevel + 1;
+constexpr int kMaxLevelDeep = 42;     // two key words (tg_config.key_levels = 42)
+constexpr int kLevelsMax = kMaxLevelDeep + 1;
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int kMaxLeaf = 16;          // largest n_L (bounds the walk's LDS queue)
 constexpr int kMaxGroup = 128;        // targets of one walk (one wave, up to 3 per lane)
@@ -50,7 +52,7 @@ struct Tile {
 // Per-level bookkeeping kept on the device so that graph replays need no
 // host round trip.  lvl[l] = first node id of level l, lvl[l+1] = end.
 struct TreeCounters {
-  uint32_t lvl[kLevels + 2];
+  uint32_t lvl[kLevelsMax + 2];
   uint32_t n_nodes;
   uint32_t n_groups;
   uint32_t n_active_groups;
@@ -71,6 +73,7 @@ struct Buffers {
   uint32_t *root_of = nullptr;    // [S]
   // sort
   uint64_t *key[2] = {nullptr, nullptr};
+  uint64_t *klo[2] = {nullptr, nullptr};   // 42 levels: the keys' last 21 digits
   uint32_t *val[2] = {nullptr, nullptr};
   uint32_t *hist = nullptr;       // sort: [tickets | digit counts [S][8][256] | tile status [8][tiles][256]]
   uint32_t *rank = nullptr;       // [N]
@@ -138,6 +141,7 @@ struct tg_ctx {
   int64_t n = 0;
   int32_t S = 0;
   int32_t leaf_size = 8, group_size = 64, waves_per_cu = 8;
+  int32_t max_level = tg::kMaxLevel;   // octree depth: 21, or 42 with two key words
   int64_t max_nodes = 0;
   int64_t max_tiles = 0;
   int64_t flat_tiles = 0;          // 256-particle tiles of max_particles
@@ -242,7 +246,9 @@ __device__ __forceinline__ double dsub(double a, double b) {
 
 // Geometric centre g of node v's cell, from the integer cell coordinates in
 // the key prefix of its first particle: g_k = lo_k + (i_k + 0.5) s, with
-// s = L 2^-level returned; every operation rounded separately.
+// s = L 2^-level returned; every operation rounded separately.  Reads one
+// key word, so l <= 21 (trees of 42 levels have neither refits nor the
+// relative test, the two callers).
 __device__ __forceinline__ double cell_centre(uint32_t v, int l, const uint32_t *first,
                                               const uint32_t *nsys, const uint64_t *skey,
                                               const double *cube, double g[3]) {
@@ -284,7 +290,7 @@ __device__ __forceinline__ void spline_pair_dp(double r, double h, double &p0, d
 }
 
 // Compensated double sum (error-free TwoSum with a running correction),
-// used by the direct sums and the chain coupling.
+// used by the direct sums, the chain coupling and the leaf moments.
 struct CSum {
   double s = 0.0, c = 0.0;
   __device__ __forceinline__ void add(double x) {
@@ -303,6 +309,8 @@ struct CSum {
 // k_keys.hip
 hipError_t launch_cube_keys(tg_ctx *c, const double *pos);
 hipError_t launch_sort(tg_ctx *c);
+// 42 levels: second key words of the sorted particles (after launch_sort)
+hipError_t launch_keys_lo(tg_ctx *c, const double *pos);
 hipError_t launch_gather(tg_ctx *c, const double *pos, const double *mass);
 hipError_t launch_rank(tg_ctx *c);
 

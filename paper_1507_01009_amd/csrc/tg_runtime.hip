@@ -80,7 +80,7 @@ static void free_all(tg_ctx *c) {
                   b.wl_count, b.wl_off, b.scan_part, b.scan_total, b.ctr,
                   b.err, b.dpart, b.dseg, b.ext_seg, b.rel, b.side, b.bbox,
                   b.refit_flag, b.refit_gates, b.arel, b.cflag, b.ctile, b.cpart,
-                  b.atile, b.aoff, b.ainfo};
+                  b.atile, b.aoff, b.ainfo, b.klo[0], b.klo[1]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   b = Buffers();
@@ -113,6 +113,9 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   if (cfg.waves_per_cu == 0) cfg.waves_per_cu = 16;
   if (cfg.waves_per_cu < 1 || cfg.waves_per_cu > kMaxWavesPerCU)
     return fail(TG_EINVAL, "tg_create: waves_per_cu must be in 1..16");
+  if (cfg.key_levels == 0) cfg.key_levels = kMaxLevel;
+  if (cfg.key_levels != kMaxLevel && cfg.key_levels != kMaxLevelDeep)
+    return fail(TG_EINVAL, "tg_create: key_levels must be 21 or 42");
 
   tg_ctx *c = new tg_ctx();
   c->cfg = cfg;
@@ -121,6 +124,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   c->group_size = cfg.group_size;
   c->waves_per_cu = cfg.waves_per_cu;
   c->max_nodes = cfg.max_nodes;
+  c->max_level = cfg.key_levels;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess)
     e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
@@ -143,6 +147,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.sys_tile0, S + 1));
   A(dalloc(&b.root_of, S));
   A(dalloc(&b.key[0], N)); A(dalloc(&b.key[1], N));
+  if (c->max_level > kMaxLevel) { A(dalloc(&b.klo[0], N)); A(dalloc(&b.klo[1], N)); }
   A(dalloc(&b.val[0], N)); A(dalloc(&b.val[1], N));
   A(dalloc(&b.hist, kSortStatusBase + 8 * 256 * (S + c->max_tiles)));
   A(dalloc(&b.rank, N));
@@ -157,10 +162,11 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   c->flat_tiles = (N + 255) / 256;
   A(dalloc(&b.lcp, N + 64));
   A(dalloc(&b.fl_lt, std::max<int64_t>(N, 1)));
-  A(dalloc(&b.fl_bits, (int64_t)kLevels * 4 * (c->flat_tiles + 1)));
-  A(dalloc(&b.fl_cnt, (int64_t)kLevels * (c->flat_tiles + 1)));
-  A(dalloc(&b.fl_fst, (int64_t)kLevels * (c->flat_tiles + 1)));
-  A(dalloc(&b.fl_tot, kLevels + 2));
+  const int64_t levels = c->max_level + 1;
+  A(dalloc(&b.fl_bits, levels * 4 * (c->flat_tiles + 1)));
+  A(dalloc(&b.fl_cnt, levels * (c->flat_tiles + 1)));
+  A(dalloc(&b.fl_fst, levels * (c->flat_tiles + 1)));
+  A(dalloc(&b.fl_tot, levels + 2));
   A(dalloc(&b.gflag, N + 1));
   A(dalloc(&b.groups, N));
   A(dalloc(&b.aflag, N + 1));
@@ -296,6 +302,7 @@ static tg_status build_tree_impl(tg_ctx *c, const double *pos, const double *mas
   c->have_tree = c->have_moments = false;
   TG_HIP(launch_cube_keys(c, pos));
   TG_HIP(launch_sort(c));
+  TG_HIP(launch_keys_lo(c, pos));
   TG_HIP(launch_gather(c, pos, mass));
   TG_HIP(launch_tree_build(c));
   TG_HIP(launch_groups(c));
@@ -325,6 +332,7 @@ tg_status tg_compute_moments(tg_ctx *c, const double *mass) {
 
 tg_status tg_refit_tree(tg_ctx *c, const double *pos, const double *mass) {
   if (!c) return fail(TG_EINVAL, "tg_refit_tree: NULL context");
+  if (c->max_level > kMaxLevel) return fail(TG_EINVAL, "tg_refit_tree: takes a 21-level tree");
   if (!c->have_tree) return fail(TG_ESTATE, "tg_refit_tree: no tree to refit");
   if (c->n > 0 && (!pos || !mass)) return fail(TG_EINVAL, "tg_refit_tree: NULL positions or masses");
   if (c->n == 0) {
@@ -415,6 +423,8 @@ tg_status tg_set_mac(tg_ctx *c, int32_t kind, double alpha, const double *acc_ol
     return TG_OK;
   }
   if (kind != TG_MAC_RELATIVE) return fail(TG_EINVAL, "tg_set_mac: unknown kind");
+  if (c->max_level > kMaxLevel)
+    return fail(TG_EINVAL, "tg_set_mac: the relative test takes a 21-level tree");
   if (!(alpha >= 0.0) || !std::isfinite(alpha))
     return fail(TG_EINVAL, "tg_set_mac: alpha must be finite and >= 0");
   c->mac = kind; c->alpha = alpha; c->acc_old = acc_old;
@@ -780,6 +790,7 @@ tg_status tg_get_tree(tg_ctx *c, tg_tree_view *v) {
   v->n_groups = c->n ? h.n_groups : 0;
   v->n_sys = c->S;
   v->skeys = b.key[0];
+  v->skeys_lo = c->max_level > kMaxLevel ? b.klo[0] : nullptr;
   v->perm = b.val[0];
   v->level = b.level;
   v->nchild = b.nchild;
@@ -919,6 +930,8 @@ static tg_status forces_impl(tg_ctx *c, const tg_system *y, const int32_t *idx,
                              const int32_t *n_act, const int64_t *k, int32_t rebuild_every) {
   tg_status st = check_system(y, "tg_forces");
   if (st != TG_OK) return st;
+  if (rebuild_every > 1 && c->max_level > kMaxLevel)
+    return fail(TG_EINVAL, "block steps: refit between rebuilds takes a 21-level tree");
   // with an active list, the build, moments and walk are skipped on the
   // device when it is empty (the SMBH sums below always run)
   const int32_t *gate = idx ? n_act : nullptr;

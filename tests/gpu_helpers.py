@@ -23,7 +23,7 @@ def to_dev(a, dtype=None):
 def gpu_run(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
             sys_off=None, precision=0, lists=False, ctx=None, pot=True,
             waves_per_cu=0, frontier_cap=0, max_nodes=0, alpha=None, acc_old=None,
-            softening=None):
+            softening=None, key_levels=21):
     """Build + moments + forces on the GPU; returns a dict of numpy arrays.
     With alpha the walk uses the relative test against acc_old ([N, 3]);
     softening "spline" switches the pair softening for this run."""
@@ -36,7 +36,7 @@ def gpu_run(pos, mass, eps, theta, leaf_size=8, group_size=64, active=None,
         ctx = B.Context(max(n, 1), max_systems=S, leaf_size=leaf_size,
                         group_size=group_size, precision=precision,
                         waves_per_cu=waves_per_cu, frontier_cap=frontier_cap,
-                        max_nodes=max_nodes)
+                        max_nodes=max_nodes, key_levels=key_levels)
     dpos = to_dev(pos.reshape(-1, 3).astype(np.float64))
     dm = to_dev(mass.astype(np.float64))
     acc = torch.full((max(n, 1), 3), float("nan"), dtype=torch.float64, device="cuda")
