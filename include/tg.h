@@ -76,7 +76,8 @@ typedef struct {
   int32_t group_size;      /* n_G: particles sharing one walk (1..128) */
   int32_t precision;       /* tg_precision of the walk and P2P/P2M sums */
   int64_t max_nodes;       /* octree node capacity; 0 = 2 * max_particles + 64 * max_systems */
-  int32_t frontier_cap;    /* walk frontier entries per wave; 0 = 16384 */
+  int32_t frontier_cap;    /* walk frontier per wave and level, in 32-bit words
+                              (an opened cell takes two); 0 = 16384 */
   int32_t waves_per_cu;    /* resident walk waves per compute unit; 0 = 16 */
   double G;                /* gravitational constant (paper units: 1) */
   int32_t key_levels;      /* octree depth: 21 (0 = 21) or 42.  42 levels quantise

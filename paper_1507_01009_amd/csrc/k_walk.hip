@@ -25,7 +25,7 @@
 // decisions stay double; targets and sources are taken relative to the
 // group's box centre c_g in double and rounded to float, the interaction
 // arithmetic is float with the hardware rsqrt, and each tile's float
-// partial sums (at most 127 sources per lane slice) are added into per-target
+// partial sums (at most 128 sources per lane slice) are added into per-target
 // double accumulators (one conversion and one FP64 add, both full rate).
 //
 // Flops per interaction as written in p2p_term / p2m_term (FMA = 2; the
@@ -57,7 +57,7 @@ namespace tg {
 #define TG_WALK_WAVES_FP64 2
 #endif
 
-constexpr int kTile = 128;                  // source tile entries (a flush uses <= 127)
+constexpr int kTile = 128;                  // source tile entries (a flush uses <= 128)
 constexpr int kMCap = 128 + 64;             // P2M cell list (LDS): < one flush + one append
 constexpr int kQCap = 128 + 64 * 8;         // P2P particle queue (LDS); overflow goes leaf by leaf
 
@@ -334,8 +334,10 @@ template <bool kMixed> struct Shape {
 // trips) with trips = ceil(k / slices), the entries past k with zero mass;
 // slice s evaluates the contiguous entries [s trips, (s + 1) trips), so every
 // lane runs the same trip count with no masking.  Full flushes take exactly
-// slices * ceil(64 / slices) (<= 127) sources.  `red` holds the per-lane
-// sums of the final slice reduction.
+// slices * floor(128 / slices) (65..128) sources, so the fixed cost of a
+// flush (two barriers, the staging set-up, the FP64 accumulation) is shared
+// by as many sources as the tile holds.  `red` holds the per-lane sums of
+// the final slice reduction.
 template <bool kMixed> union TileMem;
 template <> union __align__(16) TileMem<true> {
   P2MTileF m[kTile];
@@ -380,7 +382,8 @@ struct ForceSink {
   }
 
   template <int kT>
-  __device__ void eval_m(int base, int trips) {
+  __device__ void eval_m(int base, int trips_in) {
+    const int trips = __builtin_amdgcn_readfirstlane(trips_in);
     R ax[kT], ay[kT], az[kT], ph[kT];
 #pragma unroll
     for (int k = 0; k < kT; ++k) ax[k] = ay[k] = az[k] = ph[k] = R(0);
@@ -410,7 +413,8 @@ struct ForceSink {
 
   // kOwn: entry et[k] of the tile is target k itself, its pair dropped
   template <int kT, bool kOwn = false>
-  __device__ void eval_p(int base, int trips, const uint32_t *et = nullptr) {
+  __device__ void eval_p(int base, int trips_in, const uint32_t *et = nullptr) {
+    const int trips = __builtin_amdgcn_readfirstlane(trips_in);
     R ax[kT], ay[kT], az[kT], ph[kT];
 #pragma unroll
     for (int k = 0; k < kT; ++k) ax[k] = ay[k] = az[k] = ph[k] = R(0);
@@ -688,27 +692,35 @@ struct FillSink {
 };
 
 // ---------------------------------------------------------- traversal
-// Breadth-first walk of the group's system tree.  Returns false if the
-// frontier overflowed (the group's results are then invalid).
+// Breadth-first walk of the group's system tree.  The frontier holds the
+// cells opened on the level above as {first child, child count} (children
+// have consecutive ids); a pass takes eight of them, lane 8 j + k testing
+// child k of cell j, so an opened cell is pushed with one store and no
+// per-child loop.  The walk starts from the range {root, 1}.  Returns false
+// if the frontier overflowed (the group's results are then invalid).
 template <bool kRel, class Sink>
 __device__ bool traverse(const WalkArgs &A, Sink &sink, uint32_t root,
                          const double lo[3], const double hi[3], double arel) {
   const unsigned lane = lane_id();
-  uint32_t *cur = A.frontier + (size_t)blockIdx.x * 2 * A.fcap;
-  uint32_t *nxt = cur + A.fcap;
-  if (lane == 0) cur[0] = root;
+  const uint32_t cap = (uint32_t)A.fcap >> 1;     // ranges per half (two words each)
+  uint2 *cur = reinterpret_cast<uint2 *>(A.frontier + (size_t)blockIdx.x * 2 * A.fcap);
+  uint2 *nxt = cur + cap;
+  if (lane == 0) cur[0] = make_uint2(root, 1u);
   __threadfence_block();
   __syncthreads();
   uint32_t fsize = 1;
+  const uint32_t kk = lane & 7u;
   while (fsize > 0) {
     uint32_t nf = 0;
-    for (uint32_t base = 0; base < fsize; base += 64) {
-      const uint32_t i = base + lane;
-      const bool valid = i < fsize;
+    for (uint32_t base = 0; base < fsize; base += 8) {
+      const uint32_t i = base + (lane >> 3);
+      uint2 r = make_uint2(0u, 0u);
+      if (i < fsize) r = cur[i];
+      const bool valid = kk < r.y;
       uint32_t node = 0, nch = 0, ch = 0, f = 0, cnt = 0;
       bool acc = false;
       if (valid) {
-        node = cur[i];
+        node = r.x + kk;
         const double4 c = A.com[node];
         const uint4 nf = A.ninfo[node];
         f = nf.x; cnt = nf.y; ch = nf.z; nch = nf.w;
@@ -719,33 +731,24 @@ __device__ bool traverse(const WalkArgs &A, Sink &sink, uint32_t root,
       }
       const bool leaf = valid && !acc && nch == 0;
       const bool open = valid && !acc && nch > 0;
-      // prefix sums of the particles of refused leaves and of the children
-      // of opened cells: one scan of packed 16-bit halves unless a leaf
-      // holds 1024 or more particles
+      // prefix sum of the particles of refused leaves (most passes have none)
       const uint32_t pc = leaf ? cnt : 0u;
-      const uint32_t c = open ? nch : 0u;
-      uint32_t ppre, ptot, pre, tot;
-      if (__ballot(pc >= 1024u) == 0ull) {
-        uint32_t t2;
-        const uint32_t e2 = wave_excl_scan(pc | (c << 16), t2);
-        ppre = e2 & 0xffffu; ptot = t2 & 0xffffu;
-        pre = e2 >> 16; tot = t2 >> 16;
-      } else {
-        ppre = wave_excl_scan(pc, ptot);
-        pre = wave_excl_scan(c, tot);
-      }
+      uint32_t ptot = 0, ppre = 0;
+      if (__ballot(leaf) != 0ull) ppre = wave_excl_scan(pc, ptot);
       sink.p2m(A, acc, node);
       sink.p2p(A, leaf, node, f, pc, ppre, ptot);
-      if (nf + tot > (uint32_t)A.fcap) {
+      const unsigned long long om = __ballot(open);
+      const uint32_t no = (uint32_t)__popcll(om);
+      if (nf + no > cap) {
         if (lane == 0) set_err(A.err, TG_ERR_FRONTIER);
         return false;
       }
-      for (uint32_t k = 0; k < c; ++k) nxt[nf + pre + k] = ch + k;
-      nf += tot;
+      if (open) nxt[nf + lanes_below(om)] = make_uint2(ch, nch);
+      nf += no;
     }
     __threadfence_block();
     __syncthreads();
-    uint32_t *tmp = cur;
+    uint2 *tmp = cur;
     cur = nxt;
     nxt = tmp;
     fsize = nf;
@@ -826,7 +829,7 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
     S.g0 = gr.x; S.gn = gr.y; S.own0 = S.own1 = 0ull;
     S.s_tgt = s_tgt; S.nt = nt;
     S.T = T; S.lt = lt; S.slices = slices;
-    S.tfull = (64 + slices - 1) / slices;
+    S.tfull = 128 / slices;
     S.F = slices * S.tfull;
     const int j = (int)lane % lt;
     const int sl = (int)lane / lt;
