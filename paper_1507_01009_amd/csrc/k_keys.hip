@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
     const Tile *__restrict__ tiles, const uint32_t *__restrict__ sys_tile0, int S,
     const int64_t *__restrict__ sysoff, int pass, const uint32_t *__restrict__ cnt,
-    uint32_t *status, uint32_t *ticket, uint32_t *err) {
+    uint32_t *status, uint32_t *ticket, uint32_t *err, uint32_t *__restrict__ rank) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint64_t sk[kSortTile];
   __shared__ uint32_t sv[kSortTile];
@@ -400,6 +400,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
       const uint32_t dst = glob_off[d] + (idx - loc_off[d]);
       kout[dst] = kk;
       vout[dst] = sv[idx];
+      if (rank) rank[sv[idx]] = dst;   // last pass: caller index -> sorted position
     }
   }
 }
@@ -407,32 +408,27 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
 // Sorted particles {x, y, z, m}; the masses come with them when the caller
 // has them at build time (else the moments pass fills them in).
 __global__ void k_gather(const int32_t *__restrict__ gate, const double *__restrict__ pos,
-                         const double *__restrict__ mass, const uint32_t *__restrict__ perm,
+                         const double *__restrict__ mass, const uint32_t *__restrict__ rank,
                          int64_t n, double4 *__restrict__ spart, uint32_t *err) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
   bool bad = false;
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
-       r += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t o = perm[r];
+  // caller order in, sorted order out: the reads are coalesced, each
+  // particle is one 32-byte write (reading the caller's arrays in sorted
+  // order would fetch a cache line per 24-byte position and 8-byte mass)
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
     double m = 0.0;
     if (mass) {
-      m = mass[o];
+      m = mass[i];
       bad |= !(m > 0.0) || !isfinite(m);
     }
-    spart[r] = make_double4(pos[3 * (size_t)o], pos[3 * (size_t)o + 1],
-                            pos[3 * (size_t)o + 2], m);
+    spart[rank[i]] = make_double4(pos[3 * (size_t)i], pos[3 * (size_t)i + 1],
+                                  pos[3 * (size_t)i + 2], m);
   }
   if (bad) set_err(err, TG_ERR_MASS);
 }
 
 // Inverse permutation (caller index -> sorted rank), needed for active lists.
-__global__ void k_rank(const int32_t *__restrict__ gate, const uint32_t *__restrict__ perm,
-                       int64_t n, uint32_t *__restrict__ rank) {
-  if (gate && *gate <= 0) return;   // nothing active: skipped
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
-       r += (int64_t)gridDim.x * blockDim.x)
-    rank[perm[r]] = (uint32_t)r;
-}
 
 hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
   Buffers &b = c->b;
@@ -454,7 +450,10 @@ hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
 
 // 8 passes of (ka, va) with (kb, vb) as the other buffers: the result is
 // back in ka / va.
-static hipError_t sort8(tg_ctx *c, uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb) {
+// rank (may be null): the last pass also writes each caller index's sorted
+// position.
+static hipError_t sort8(tg_ctx *c, uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb,
+                        uint32_t *rank) {
   Buffers &b = c->b;
   const int nt = (int)c->n_tiles;
   // [8 tickets | pad | counts [S][8][256] | status [8][nt][256]], all zero
@@ -472,7 +471,7 @@ static hipError_t sort8(tg_ctx *c, uint64_t *ka, uint32_t *va, uint64_t *kb, uin
     hipLaunchKernelGGL(k_sort_pass, dim3(nt), dim3(256), 0, c->stream, c->gate, k2[src],
                        v2[src], k2[dst], v2[dst], b.tiles, b.sys_tile0, c->S,
                        b.sysoff, pass, cnt, status + (size_t)pass * 256 * nt,
-                       tickets + pass, b.err);
+                       tickets + pass, b.err, pass == 7 ? rank : nullptr);
   }
   return hipGetLastError();
 }
@@ -482,16 +481,16 @@ hipError_t launch_sort(tg_ctx *c) {
   const int nt = (int)c->n_tiles;
   if (nt == 0) return hipSuccess;
   if (c->max_level <= kMaxLevel)
-    return sort8(c, b.key[0], b.val[0], b.key[1], b.val[1]);   // result in key[0] / val[0]
+    return sort8(c, b.key[0], b.val[0], b.key[1], b.val[1], b.rank);   // result in key[0] / val[0]
   // 42 levels, least significant word first: sort by the second words,
   // carry the first words into that order, sort them (stable), then the
   // second words of the final order from the positions
-  hipError_t e = sort8(c, b.klo[0], b.val[0], b.klo[1], b.val[1]);
+  hipError_t e = sort8(c, b.klo[0], b.val[0], b.klo[1], b.val[1], nullptr);
   if (e != hipSuccess) return e;
   const int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_gather_u64, dim3(g), dim3(256), 0, c->stream, c->gate, b.key[1],
                      b.val[0], c->n, b.key[0]);
-  return sort8(c, b.key[0], b.val[0], b.key[1], b.val[1]);
+  return sort8(c, b.key[0], b.val[0], b.key[1], b.val[1], b.rank);
 }
 
 // 42 levels: the second key words of the sorted particles (klo[0]).
@@ -508,15 +507,7 @@ hipError_t launch_gather(tg_ctx *c, const double *pos, const double *mass) {
   if (c->n == 0) return hipSuccess;
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, c->gate, pos, mass,
-                     c->b.val[0], c->n, c->b.spart, c->b.err);
-  return hipGetLastError();
-}
-
-hipError_t launch_rank(tg_ctx *c) {
-  if (c->n == 0) return hipSuccess;
-  int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_rank, dim3(g), dim3(256), 0, c->stream, c->gate, c->b.val[0], c->n,
-                     c->b.rank);
+                     c->b.rank, c->n, c->b.spart, c->b.err);
   return hipGetLastError();
 }
 

@@ -1082,7 +1082,6 @@ hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
   Buffers &b = c->b;
   if (c->n == 0) return fill_u32(&b.ctr->n_active_groups, 0u, 1, c->stream);
   hipError_t e = fill_u8(b.sact, 0, c->n, c->stream, c->gate);
-  if (e == hipSuccess && idx) e = launch_rank(c);
   if (e != hipSuccess) return e;
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_mark_active, dim3(g), dim3(256), 0, c->stream, c->gate, idx,

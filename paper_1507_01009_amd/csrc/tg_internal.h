@@ -2,7 +2,8 @@
 // Device data layouts (all in HBM, owned by the context):
 //   sorted particles   spart[N]   double4 {x, y, z, m}      (32 B each)
 //   sort keys / perm   key[N] u64, perm[N] u32 (sorted rank -> caller index),
-//                      rank[N] u32 (caller index -> sorted rank)
+//                      rank[N] u32 (caller index -> sorted rank, written by
+//                      the last sort pass)
 //   nodes (SoA)        level u8, nchild u8, first u32, count u32, child u32,
 //                      parent u32, sys u32; com double4 {cx, cy, cz, side^2};
 //                      mom double[8] {M, Sxx, Syy, Szz, Sxy, Sxz, Syz, 0}
@@ -312,7 +313,6 @@ hipError_t launch_sort(tg_ctx *c);
 // 42 levels: second key words of the sorted particles (after launch_sort)
 hipError_t launch_keys_lo(tg_ctx *c, const double *pos);
 hipError_t launch_gather(tg_ctx *c, const double *pos, const double *mass);
-hipError_t launch_rank(tg_ctx *c);
 
 // k_tree.hip
 hipError_t launch_tree_build(tg_ctx *c);
