@@ -31,6 +31,16 @@ _CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
 MAX_LEVEL = 21
 
 
+def build_sanitized(path: str) -> str:
+    """Compile bh_oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer
+    into ``path`` (for the CPU test that runs the oracle under them; load it
+    through TG_ORACLE_LIB with the ASan runtime preloaded)."""
+    subprocess.check_call(["gcc", *_CFLAGS, "-O1", "-g", "-fno-omit-frame-pointer",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-o", path, _SRC, "-lm"])
+    return path
+
+
 def build(force: bool = True) -> str:
     """Compile bh_oracle.c into liboracle.so next to it (gcc)."""
     if force or not os.path.exists(_LIB) or (
@@ -47,9 +57,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = C.CDLL(_LIB)
+        path = os.environ.get("TG_ORACLE_LIB")   # a sanitized build (tests)
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        L = C.CDLL(path)
         P = C.c_void_p
         i64, i32, f64 = C.c_int64, C.c_int32, C.c_double
         sig = {

@@ -585,8 +585,9 @@ static int or_walk_one(uint32_t root, const uint8_t *level,
         if (or_push(work, child[c] + k)) return -1;
     }
   }
-  qsort(p2m->v, (size_t)p2m->n, sizeof(uint32_t), or_u32_cmp);
-  qsort(p2p->v, (size_t)p2p->n, sizeof(uint32_t), or_u32_cmp);
+  /* an empty list may never have been allocated (qsort needs an array) */
+  if (p2m->n > 1) qsort(p2m->v, (size_t)p2m->n, sizeof(uint32_t), or_u32_cmp);
+  if (p2p->n > 1) qsort(p2p->v, (size_t)p2p->n, sizeof(uint32_t), or_u32_cmp);
   return 0;
 }
 
@@ -621,8 +622,8 @@ int or_walk_lists(int64_t nn, const uint8_t *level, const uint32_t *child,
       }
       np2m[t] = p2m.n; np2p[t] = p2p.n;
       if (ids) {
-        memcpy(ids + lofs[2 * t], p2m.v, sizeof(uint32_t) * (size_t)p2m.n);
-        memcpy(ids + lofs[2 * t + 1], p2p.v, sizeof(uint32_t) * (size_t)p2p.n);
+        if (p2m.n) memcpy(ids + lofs[2 * t], p2m.v, sizeof(uint32_t) * (size_t)p2m.n);
+        if (p2p.n) memcpy(ids + lofs[2 * t + 1], p2p.v, sizeof(uint32_t) * (size_t)p2p.n);
       }
     }
     free(p2m.v); free(p2p.v); free(work.v);
