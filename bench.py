@@ -691,6 +691,7 @@ def extra_batch(steps=20):
     best = ctx.autotune(d.pos, d.mass, w.eps, w.theta, sys_off=w.sys_off,
                         leaf_list=[8, 12, 16], group_list=[48, 64], waves_list=[12, 16],
                         repeats=2)
+    best["times"] = [round(float(t), 4) for t in best["times"]]   # per candidate, list order
     ctx.forces(d.sys)
     ctx.reset_counts()
     ms_graph = graph_ms(ctx, lambda: ctx.step_kdk(d.sys, 1e-3), steps)

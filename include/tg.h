@@ -632,13 +632,17 @@ tg_status tg_get_tree(tg_ctx *ctx, tg_tree_view *out);
  * Times build + moments + forces on the given particles for every candidate
  * (leaf sizes x group sizes x waves per CU, 0-terminated lists; NULL = the
  * built-in lists), keeps the fastest in the context and reports it in
- * best[3] = {leaf_size, group_size, waves_per_cu} and *best_ms. */
+ * best[3] = {leaf_size, group_size, waves_per_cu} and *best_ms.  times (may
+ * be NULL): host array, one entry per candidate in list order (leaf
+ * outermost, waves innermost), the fastest of `repeats` timed runs after
+ * one warm-up run, in ms. */
 tg_status tg_autotune(tg_ctx *ctx, const double *pos_dev,
                       const double *mass_dev, int64_t n,
                       const int64_t *sys_off_host, int32_t n_sys, double eps,
                       double theta, const int32_t *leaf_list,
                       const int32_t *group_list, const int32_t *waves_list,
-                      int32_t repeats, int32_t best[3], double *best_ms);
+                      int32_t repeats, int32_t best[3], double *best_ms,
+                      double *times);
 
 /* ---- measurement ---------------------------------------------------------
  * With profiling on, every tg_tree_forces outside graph capture records a

@@ -176,7 +176,7 @@ def lib():
             "tg_graph_destroy": (None, [P]),
             "tg_get_tree": (st, [P, P]),
             "tg_autotune": (st, [P, P, P, i64, P, i32, f64, f64, P, P, P, i32,
-                                 P, P]),
+                                 P, P, P]),
             "tg_set_profiling": (st, [P, i32]),
             "tg_get_profile": (st, [P, P, P]),
             "tg_sync": (st, [P, P]),
@@ -576,11 +576,16 @@ class Context:
         wa, wp = lst(waves_list)
         best = np.zeros(3, np.int32)
         ms = C.c_double()
+        nl = len(leaf_list) if leaf_list is not None else 4
+        ng = len(group_list) if group_list is not None else 4
+        nw = len(waves_list) if waves_list is not None else 3
+        times = np.full(nl * ng * nw, np.nan)
         _check(lib().tg_autotune(self.h, _ptr(pos), _ptr(mass), pos.shape[0], p, S,
                                  float(eps), float(theta), lp, gp, wp, int(repeats),
-                                 best.ctypes.data_as(C.c_void_p), C.byref(ms)))
+                                 best.ctypes.data_as(C.c_void_p), C.byref(ms),
+                                 times.ctypes.data_as(C.c_void_p)))
         return {"leaf_size": int(best[0]), "group_size": int(best[1]),
-                "waves_per_cu": int(best[2]), "ms": ms.value}
+                "waves_per_cu": int(best[2]), "ms": ms.value, "times": times}
 
     def set_profiling(self, on=True):
         _check(lib().tg_set_profiling(self.h, int(bool(on))))

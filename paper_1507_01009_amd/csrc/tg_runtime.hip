@@ -809,7 +809,8 @@ tg_status tg_autotune(tg_ctx *c, const double *pos, const double *mass,
                       int64_t n, const int64_t *sys_off, int32_t S, double eps,
                       double theta, const int32_t *leaf_list,
                       const int32_t *group_list, const int32_t *waves_list,
-                      int32_t repeats, int32_t best[3], double *best_ms) {
+                      int32_t repeats, int32_t best[3], double *best_ms,
+                      double *times) {
   if (!c || !best || !best_ms) return fail(TG_EINVAL, "tg_autotune: NULL argument");
   if (c->capturing) return fail(TG_ESTATE, "tg_autotune: during capture");
   static const int32_t dl[] = {4, 8, 12, 16, 0};
@@ -827,6 +828,7 @@ tg_status tg_autotune(tg_ctx *c, const double *pos, const double *mass,
   double bms = 1e300;
   int32_t b3[3] = {c->leaf_size, c->group_size, c->waves_per_cu};
   tg_status st = TG_OK;
+  int64_t cand = 0;
   for (const int32_t *L = leaf_list; *L && st == TG_OK; ++L)
     for (const int32_t *Gs = group_list; *Gs && st == TG_OK; ++Gs)
       for (const int32_t *W = waves_list; *W && st == TG_OK; ++W) {
@@ -847,6 +849,8 @@ tg_status tg_autotune(tg_ctx *c, const double *pos, const double *mass,
         }
         uint32_t bits = 0;
         if (st == TG_OK) st = tg_sync(c, &bits);
+        if (st == TG_OK && times) times[cand] = tmin;
+        ++cand;
         if (st == TG_OK && tmin < bms) {
           bms = tmin;
           b3[0] = *L; b3[1] = *Gs; b3[2] = *W;

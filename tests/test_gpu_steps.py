@@ -240,16 +240,25 @@ def test_batch_kdk_graph_matches_separate_oracle_runs():
         assert np.array_equal(o1.pos, st.pos[lo:hi])
 
 
-def test_autotune_returns_a_listed_config():
+def test_autotune_picks_the_fastest_measured_config():
+    """Every candidate is timed; the pick is the argmin of those times and is
+    applied to the context; a poor candidate (one particle per leaf and per
+    walk) is measured slower and not picked."""
     say("autotune")
     from paper_1507_01009_amd import binding as B
     w = ics.plummer_c1()
     ctx = B.Context(w.n)
     pos, mass = to_dev(w.pos), to_dev(w.mass)
-    best = ctx.autotune(pos, mass, w.eps, w.theta, leaf_list=[4, 8], group_list=[32, 64],
-                        waves_list=[8, 16], repeats=2)
-    assert best["leaf_size"] in (4, 8) and best["group_size"] in (32, 64)
-    assert best["waves_per_cu"] in (8, 16) and best["ms"] > 0
+    leaves, groups, waves = [1, 4, 8], [1, 32, 64], [8, 16]
+    best = ctx.autotune(pos, mass, w.eps, w.theta, leaf_list=leaves, group_list=groups,
+                        waves_list=waves, repeats=2)
+    t = best["times"].reshape(len(leaves), len(groups), len(waves))
+    assert np.all(np.isfinite(t)) and np.all(t > 0)
+    i, j, k = np.unravel_index(int(np.argmin(t)), t.shape)
+    assert (best["leaf_size"], best["group_size"], best["waves_per_cu"]) == \
+        (leaves[i], groups[j], waves[k])
+    assert best["ms"] == t[i, j, k]
+    assert t[0, 0].min() > 2.0 * best["ms"] and (i, j) != (0, 0)
     import torch
     acc = torch.zeros((w.n, 3), dtype=torch.float64, device="cuda")
     ctx.build_tree(pos)
