@@ -13,7 +13,7 @@ import weakref
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtg.so")
+LIB_PATH = os.environ.get("TG_LIB") or os.path.join(_HERE, "libtg.so")   # TG_LIB: a test build
 
 TG_FP64, TG_MIXED = 0, 1
 TG_SOFT_PLUMMER, TG_SOFT_SPLINE = 0, 1

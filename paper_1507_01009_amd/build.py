@@ -35,5 +35,18 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(path: str) -> str:
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    in its host code only (the AR-chain, membership and driver code; device
+    code is built as usual), for the CPU test that runs the host-side tests
+    against it."""
+    san = ["-g", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer"]
+    subprocess.check_call([HIPCC, *FLAGS, *san, "-o", path, *sources()])
+    return path
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
