@@ -201,27 +201,20 @@ __global__ void k_keys_lo_sorted(const int32_t *__restrict__ gate, const double 
   }
 }
 
-// 42 levels, between the two sort phases: first words in the order of the
-// first phase (sorted by the second word), hi_out[r] = hi_in[perm[r]].
-__global__ void k_gather_u64(const int32_t *__restrict__ gate, const uint64_t *__restrict__ in,
-                             const uint32_t *__restrict__ perm, int64_t n,
-                             uint64_t *__restrict__ out) {
-  if (gate && *gate <= 0) return;   // nothing active: skipped
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
-       r += (int64_t)gridDim.x * blockDim.x)
-    out[r] = in[perm[r]];
-}
-
-// ---- radix sort, 8-bit digits ----------------------------------------
-// Stable LSD sort of (key, index), 8 passes of 8 bits, each system sorted
-// on its own (tiles never straddle systems).  One counting kernel gives the
-// digit totals of all passes per system; then one kernel per pass: a tile
-// (taken in dispatch order from a ticket) ranks its keys in LDS, publishes
-// its per-digit counts, adds up the counts of the earlier tiles of its
-// system by looking back through their published words (each a flag and a
-// count in one 32-bit word, written and read with agent-scope atomics), and
-// scatters.  The lowest waiting tile never waits on a later one, so every
-// wait ends; a wait is still bounded and reports TG_ERR_SORT if exceeded.
+// ---- radix sort, 9-bit digits ----------------------------------------
+// Stable LSD sort of (key, index), 7 passes of 9 bits (the 63 bits of a key
+// word), each system sorted on its own (tiles never straddle systems).  One
+// counting kernel gives the digit totals of all passes per system; then one
+// kernel per pass: a tile (taken in dispatch order from a ticket) ranks its
+// keys in LDS, publishes its per-digit counts, adds up the counts of the
+// earlier tiles of its system by looking back through their published words
+// (each a flag and a count in one 32-bit word, written and read with
+// agent-scope atomics), and scatters.  The lowest waiting tile never waits
+// on a later one, so every wait ends; a wait is still bounded and reports
+// TG_ERR_SORT if exceeded.
+constexpr uint32_t kSortMask = kSortDigits - 1;
+static_assert(kSortBits * kSortPasses == 63, "a key word holds 63 bits");
+static_assert(kSortDigits == kSortThreads, "each thread owns one digit");
 constexpr uint32_t kStAgg = 1u << 30, kStIncl = 2u << 30, kStVal = (1u << 30) - 1u;
 
 __device__ __forceinline__ int tile_system(const uint32_t *sys_tile0, int S, uint32_t t) {
@@ -239,45 +232,53 @@ __global__ __launch_bounds__(256) void k_sort_count(const int32_t *__restrict__ 
                                                     const uint32_t *__restrict__ sys_tile0,
                                                     int S, uint32_t *__restrict__ cnt) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
-  __shared__ uint32_t c[8][256];
+  __shared__ uint32_t c[kSortPasses][kSortDigits];
   const Tile t = tiles[blockIdx.x];
   const int s = tile_system(sys_tile0, S, blockIdx.x);
 #pragma unroll
-  for (int p = 0; p < 8; ++p) c[p][threadIdx.x] = 0;
+  for (int p = 0; p < kSortPasses; ++p) {
+    c[p][threadIdx.x] = 0;
+    c[p][threadIdx.x + 256] = 0;
+  }
   __syncthreads();
   for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u) {
     const uint64_t k = key[i];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) atomicAdd(&c[p][(uint32_t)(k >> (8 * p)) & 255u], 1u);
+    for (int p = 0; p < kSortPasses; ++p)
+      atomicAdd(&c[p][(uint32_t)(k >> (kSortBits * p)) & kSortMask], 1u);
   }
   __syncthreads();
 #pragma unroll
-  for (int p = 0; p < 8; ++p) {
-    const uint32_t v = c[p][threadIdx.x];
-    if (v) atomicAdd(&cnt[(size_t)(s * 8 + p) * 256 + threadIdx.x], v);
+  for (int p = 0; p < kSortPasses; ++p) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t d = threadIdx.x + 256u * h;
+      const uint32_t v = c[p][d];
+      if (v) atomicAdd(&cnt[(size_t)(s * kSortPasses + p) * kSortDigits + d], v);
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ gate, 
+__global__ __launch_bounds__(kSortThreads) void k_sort_pass(const int32_t *__restrict__ gate, 
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
     const Tile *__restrict__ tiles, const uint32_t *__restrict__ sys_tile0, int S,
     const int64_t *__restrict__ sysoff, int pass, const uint32_t *__restrict__ cnt,
     uint32_t *status, uint32_t *ticket, uint32_t *err, uint32_t *__restrict__ rank) {
+  constexpr int kWaves = kSortThreads / 64;
   if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint64_t sk[kSortTile];
   __shared__ uint32_t sv[kSortTile];
-  __shared__ uint32_t wcnt[4][256];
-  __shared__ uint32_t running[256];
-  __shared__ uint32_t loc_off[256];
-  __shared__ uint32_t glob_off[256];
-  __shared__ uint32_t scan_sh[4];
+  __shared__ uint32_t wcnt[kWaves][kSortDigits];
+  __shared__ uint32_t loc_off[kSortDigits];
+  __shared__ uint32_t glob_off[kSortDigits];
+  __shared__ uint32_t scan_sh[kWaves];
   __shared__ uint32_t s_tile;
   const unsigned tid = threadIdx.x, w = tid >> 6, lane = tid & 63u;
-  const int shift = 8 * pass;
+  const int shift = kSortBits * pass;
   if (tid == 0) s_tile = atomicAdd(ticket, 1u);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) wcnt[q][tid] = 0;
+  for (int q = 0; q < kWaves; ++q) wcnt[q][tid] = 0;
   __syncthreads();
   const uint32_t tb = s_tile;
   const Tile t = tiles[tb];
@@ -301,10 +302,10 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   for (int r = 0; r < kSortItems; ++r) {
     const uint32_t idx = 64u * kSortItems * w + 64u * r + lane;
     const bool valid = idx < n_in;
-    const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & kSortMask;
     unsigned long long peers = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < kSortBits; ++bit) {
       const unsigned long long bb = __ballot((d >> bit) & 1u);
       peers &= ((d >> bit) & 1u) ? bb : ~bb;
     }
@@ -314,24 +315,22 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
     if (valid && lr == 0) wcnt[w][d] = base + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  // digit tid: counts of the four waves -> their exclusive offsets in place
-  {
-    const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-    wcnt[0][tid] = 0u;
-    wcnt[1][tid] = c0;
-    wcnt[2][tid] = c0 + c1;
-    wcnt[3][tid] = c0 + c1 + c2;
-    running[tid] = c0 + c1 + c2 + c3;
+  // digit tid: counts of the waves -> their exclusive offsets in place
+  uint32_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) {
+    const uint32_t cq = wcnt[q][tid];
+    wcnt[q][tid] = mine;
+    mine += cq;
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & kSortMask;
     rk[r] += wcnt[w][d];
   }
   // publish this tile's count of digit tid, then look back for the prefix
-  const uint32_t mine = running[tid];
-  uint32_t *st = status + (size_t)tb * 256 + tid;
+  uint32_t *st = status + (size_t)tb * kSortDigits + tid;
   __hip_atomic_store(st, (tb == first_tile ? kStIncl : kStAgg) | mine, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
   uint32_t prefix = 0;
@@ -347,7 +346,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
 #pragma unroll
       for (int j = 0; j < kW; ++j)
         x[j] = (uint32_t)j < avail
-                   ? __hip_atomic_load(status + (size_t)(q - 1 - j) * 256 + tid,
+                   ? __hip_atomic_load(status + (size_t)(q - 1 - j) * kSortDigits + tid,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                    : 0u;
       uint32_t used = 0;
@@ -375,8 +374,8 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   }
   // digit starts inside the system: sysoff + counts of smaller digits
   uint32_t tot;
-  const uint32_t dbase = block_exclusive_scan(cnt[(size_t)(s * 8 + pass) * 256 + tid],
-                                              scan_sh, tot);
+  const uint32_t dbase = block_exclusive_scan(
+      cnt[(size_t)(s * kSortPasses + pass) * kSortDigits + tid], scan_sh, tot);
   glob_off[tid] = (uint32_t)sysoff[s] + dbase + prefix;
   loc_off[tid] = block_exclusive_scan(mine, scan_sh, tot);
   __syncthreads();
@@ -384,7 +383,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   for (int r = 0; r < kSortItems; ++r) {
     const uint32_t idx = 64u * kSortItems * w + 64u * r + lane;
     if (idx < n_in) {
-      const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+      const uint32_t d = (uint32_t)(k[r] >> shift) & kSortMask;
       const uint32_t p = loc_off[d] + rk[r];
       sk[p] = k[r];
       sv[p] = v[r];
@@ -393,10 +392,10 @@ __global__ __launch_bounds__(256) void k_sort_pass(const int32_t *__restrict__ g
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t idx = r * 256u + tid;
+    const uint32_t idx = r * (uint32_t)kSortThreads + tid;
     if (idx < n_in) {
       const uint64_t kk = sk[idx];
-      const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+      const uint32_t d = (uint32_t)(kk >> shift) & kSortMask;
       const uint32_t dst = glob_off[d] + (idx - loc_off[d]);
       kout[dst] = kk;
       vout[dst] = sv[idx];
@@ -428,8 +427,6 @@ __global__ void k_gather(const int32_t *__restrict__ gate, const double *__restr
   if (bad) set_err(err, TG_ERR_MASS);
 }
 
-// Inverse permutation (caller index -> sorted rank), needed for active lists.
-
 hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
   Buffers &b = c->b;
   const int nt = (int)c->n_tiles;
@@ -438,59 +435,76 @@ hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
                        b.tiles, b.cube_part, b.err);
   hipLaunchKernelGGL(k_cube_final, dim3(c->S), dim3(256), 0, c->stream, c->gate,
                      b.cube_part, b.sys_tile0, b.cube);
+  // the sort takes its input from the second buffers (an odd number of
+  // passes leaves the result in the first)
   if (nt > 0 && c->max_level > kMaxLevel)
-    // first words in caller order to key[1], second words to klo[0] (sorted first)
+    // first words in caller order to key[0], second words to klo[1] (sorted first)
     hipLaunchKernelGGL(k_keys<true>, dim3(nt), dim3(256), 0, c->stream, c->gate, pos, b.tiles,
-                       b.sys_tile0, c->S, b.cube, b.key[1], b.klo[0], b.val[0]);
+                       b.sys_tile0, c->S, b.cube, b.key[0], b.klo[1], b.val[1]);
   else if (nt > 0)
     hipLaunchKernelGGL(k_keys<false>, dim3(nt), dim3(256), 0, c->stream, c->gate, pos, b.tiles,
-                       b.sys_tile0, c->S, b.cube, b.key[0], nullptr, b.val[0]);
+                       b.sys_tile0, c->S, b.cube, b.key[1], nullptr, b.val[1]);
   return hipGetLastError();
 }
 
-// 8 passes of (ka, va) with (kb, vb) as the other buffers: the result is
-// back in ka / va.
+// The passes of a sort whose input is in (kb, vb): passes alternate
+// between the two buffer pairs and the result ends in (ka, va).
 // rank (may be null): the last pass also writes each caller index's sorted
 // position.
-static hipError_t sort8(tg_ctx *c, uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb,
-                        uint32_t *rank) {
+static hipError_t sort_passes(tg_ctx *c, uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb,
+                              uint32_t *rank) {
+  static_assert(kSortPasses % 2 == 1, "the input starts in the second buffers");
   Buffers &b = c->b;
   const int nt = (int)c->n_tiles;
-  // [8 tickets | pad | counts [S][8][256] | status [8][nt][256]], all zero
+  // [tickets | pad | counts [S][passes][digits] | status [passes][nt][digits]], all zero
   uint32_t *tickets = b.hist, *cnt = b.hist + kSortStatusBase;
-  uint32_t *status = cnt + (size_t)c->S * 8 * 256;
-  hipError_t e = fill_u32(b.hist, 0u, kSortStatusBase + (int64_t)8 * 256 * (c->S + nt),
-                          c->stream, c->gate);
+  uint32_t *status = cnt + (size_t)c->S * kSortPasses * kSortDigits;
+  hipError_t e = fill_u32(b.hist, 0u, sort_hist_words(c->S, nt), c->stream, c->gate);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sort_count, dim3(nt), dim3(256), 0, c->stream, c->gate, ka, b.tiles,
+  hipLaunchKernelGGL(k_sort_count, dim3(nt), dim3(256), 0, c->stream, c->gate, kb, b.tiles,
                      b.sys_tile0, c->S, cnt);
   uint64_t *k2[2] = {ka, kb};
   uint32_t *v2[2] = {va, vb};
-  for (int pass = 0; pass < 8; ++pass) {
-    const int src = pass & 1, dst = src ^ 1;
-    hipLaunchKernelGGL(k_sort_pass, dim3(nt), dim3(256), 0, c->stream, c->gate, k2[src],
-                       v2[src], k2[dst], v2[dst], b.tiles, b.sys_tile0, c->S,
-                       b.sysoff, pass, cnt, status + (size_t)pass * 256 * nt,
-                       tickets + pass, b.err, pass == 7 ? rank : nullptr);
+  for (int pass = 0; pass < kSortPasses; ++pass) {
+    const int dst = pass & 1, src = dst ^ 1;
+    hipLaunchKernelGGL(k_sort_pass, dim3(nt), dim3(kSortThreads), 0, c->stream, c->gate, k2[src],
+                       v2[src], k2[dst], v2[dst], b.tiles, b.sys_tile0, c->S, b.sysoff, pass,
+                       cnt, status + (size_t)pass * kSortDigits * nt, tickets + pass,
+                       b.err, pass == kSortPasses - 1 ? rank : nullptr);
   }
   return hipGetLastError();
+}
+
+// 42 levels, between the two sort phases: first words in the order of the
+// first phase (sorted by the second word) and that order itself, both into
+// the second buffers where the next phase starts.
+__global__ void k_gather_hi(const int32_t *__restrict__ gate, const uint64_t *__restrict__ hi,
+                            const uint32_t *__restrict__ perm, int64_t n,
+                            uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+  if (gate && *gate <= 0) return;   // nothing active: skipped
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = perm[r];
+    kout[r] = hi[p];
+    vout[r] = p;
+  }
 }
 
 hipError_t launch_sort(tg_ctx *c) {
   Buffers &b = c->b;
   const int nt = (int)c->n_tiles;
   if (nt == 0) return hipSuccess;
-  if (c->max_level <= kMaxLevel)
-    return sort8(c, b.key[0], b.val[0], b.key[1], b.val[1], b.rank);   // result in key[0] / val[0]
+  if (c->max_level <= kMaxLevel)      // key[1] / val[1] -> key[0] / val[0]
+    return sort_passes(c, b.key[0], b.val[0], b.key[1], b.val[1], b.rank);
   // 42 levels, least significant word first: sort by the second words,
   // carry the first words into that order, sort them (stable), then the
   // second words of the final order from the positions
-  hipError_t e = sort8(c, b.klo[0], b.val[0], b.klo[1], b.val[1], nullptr);
+  hipError_t e = sort_passes(c, b.klo[0], b.val[0], b.klo[1], b.val[1], nullptr);
   if (e != hipSuccess) return e;
   const int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_gather_u64, dim3(g), dim3(256), 0, c->stream, c->gate, b.key[1],
-                     b.val[0], c->n, b.key[0]);
-  return sort8(c, b.key[0], b.val[0], b.key[1], b.val[1], b.rank);
+  hipLaunchKernelGGL(k_gather_hi, dim3(g), dim3(256), 0, c->stream, c->gate, b.key[0],
+                     b.val[0], c->n, b.key[1], b.val[1]);
+  return sort_passes(c, b.key[0], b.val[0], b.key[1], b.val[1], b.rank);
 }
 
 // 42 levels: the second key words of the sorted particles (klo[0]).

@@ -31,10 +31,16 @@ constexpr uint32_t kNone = 0xffffffffu;
 constexpr int kMaxLeaf = 16;          // largest n_L (bounds the walk's LDS queue)
 constexpr int kMaxGroup = 128;        // targets of one walk (one wave, up to 3 per lane)
 constexpr int kMaxSys = 256;
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortThreads = 512;             // one digit per thread in the sort passes
+constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
-constexpr int kSortStatusBase = 64;               // words before the digit counts (8 tickets + pad)
+constexpr int kSortStatusBase = 64;               // words before the digit counts (tickets + pad)
+constexpr int kSortBits = 9, kSortDigits = 1 << kSortBits, kSortPasses = 7;
+// sort scratch words: tickets and pad, digit counts [S][passes][digits],
+// tile status [passes][tiles][digits]
+constexpr int64_t sort_hist_words(int64_t S, int64_t tiles) {
+  return kSortStatusBase + (int64_t)kSortPasses * kSortDigits * (S + tiles);
+}
 constexpr int kScanBlocks = 256;
 constexpr int kMaxWavesPerCU = 16;
 constexpr int kMaxExternal = 1024;               // SMBHs / external point masses
@@ -76,7 +82,7 @@ struct Buffers {
   uint64_t *key[2] = {nullptr, nullptr};
   uint64_t *klo[2] = {nullptr, nullptr};   // 42 levels: the keys' last 21 digits
   uint32_t *val[2] = {nullptr, nullptr};
-  uint32_t *hist = nullptr;       // sort: [tickets | digit counts [S][8][256] | tile status [8][tiles][256]]
+  uint32_t *hist = nullptr;       // sort: [tickets | digit counts [S][7][512] | tile status [7][tiles][512]]
   uint32_t *rank = nullptr;       // [N]
   double4 *spart = nullptr;       // [N]
   // nodes

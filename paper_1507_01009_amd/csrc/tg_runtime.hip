@@ -149,7 +149,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.key[0], N)); A(dalloc(&b.key[1], N));
   if (c->max_level > kMaxLevel) { A(dalloc(&b.klo[0], N)); A(dalloc(&b.klo[1], N)); }
   A(dalloc(&b.val[0], N)); A(dalloc(&b.val[1], N));
-  A(dalloc(&b.hist, kSortStatusBase + 8 * 256 * (S + c->max_tiles)));
+  A(dalloc(&b.hist, sort_hist_words(S, c->max_tiles)));
   A(dalloc(&b.rank, N));
   A(dalloc(&b.spart, N));
   A(dalloc(&b.level, NN)); A(dalloc(&b.nchild, NN));
