@@ -770,7 +770,9 @@ struct GroupQueue {
       const uint32_t hi = (uint32_t)(((uint64_t)(q + 1u) * G) >> 3);
       uint32_t g = 0;
       if (lane_id() == 0) g = atomicAdd(&ctr->xq[q], 1u);
-      g = (uint32_t)__shfl((int)g, 0, 64);
+      // every lane is active here: the first lane is lane 0, and the group
+      // index (with all that is loaded from it) is known to be uniform
+      g = (uint32_t)__builtin_amdgcn_readfirstlane((int)g);
       if (lo + g < hi) return lo + g;
       q = (q + 1u) & 7u;
       ++tried;
