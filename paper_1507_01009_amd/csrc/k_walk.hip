@@ -45,7 +45,10 @@ namespace tg {
 // Most targets a lane holds (the per-group choice is 1..this), and the
 // occupancy the kernel is compiled for, per precision mode.
 #ifndef TG_WALK_MAXT_MIXED
-#define TG_WALK_MAXT_MIXED 2
+#define TG_WALK_MAXT_MIXED 3
+#endif
+#ifndef TG_WALK_MAXT_MIXED_SPLINE
+#define TG_WALK_MAXT_MIXED_SPLINE 2        // the spline terms need more registers
 #endif
 #ifndef TG_WALK_MAXT_FP64
 #define TG_WALK_MAXT_FP64 3
@@ -325,10 +328,14 @@ struct P2MTileF { float4 a, b, c; };
 // lt = ceil(nt / T) lane-targets (each lane holding up to T targets) times
 // slices = floor(64 / lt) source slices; T is chosen per group to minimise
 // the evaluations per source, T / slices.
-template <bool kMixed> struct Shape {
-  static constexpr int kMaxT = kMixed ? TG_WALK_MAXT_MIXED : TG_WALK_MAXT_FP64;
+template <bool kMixed, bool kSpline> struct Shape {
+  static constexpr int kMaxT =
+      kMixed ? (kSpline ? TG_WALK_MAXT_MIXED_SPLINE : TG_WALK_MAXT_MIXED) : TG_WALK_MAXT_FP64;
   static_assert(kMaxT >= 1 && kMaxT <= 3, "1..3 targets per lane");
 };
+template <bool kMixed>
+constexpr int kRedT = Shape<kMixed, false>::kMaxT > Shape<kMixed, true>::kMaxT
+                          ? Shape<kMixed, false>::kMaxT : Shape<kMixed, true>::kMaxT;
 
 // Source tiles in LDS.  A flush of k sources fills entries [0, slices *
 // trips) with trips = ceil(k / slices), the entries past k with zero mass;
@@ -342,12 +349,12 @@ template <bool kMixed> union TileMem;
 template <> union __align__(16) TileMem<true> {
   P2MTileF m[kTile];
   float4 p[kTile];
-  double red[Shape<true>::kMaxT * 256];
+  double red[kRedT<true> * 256];
 };
 template <> union __align__(16) TileMem<false> {
   P2MTileD m[kTile];
   double4 p[kTile];
-  double red[Shape<false>::kMaxT * 256];
+  double red[kRedT<false> * 256];
 };
 
 // ------------------------------------------------------- force-mode sink
@@ -355,7 +362,7 @@ template <bool kMixed, bool kSpline>
 struct ForceSink {
   using R = typename std::conditional<kMixed, float, double>::type;
   using R4 = typename Vec4<R>::T;
-  static constexpr int kMaxT = Shape<kMixed>::kMaxT;
+  static constexpr int kMaxT = Shape<kMixed, kSpline>::kMaxT;
   uint32_t *s_m;
   uint32_t *s_q;
   TileMem<kMixed> *tile;
@@ -713,24 +720,26 @@ __device__ bool traverse(const WalkArgs &A, Sink &sink, uint32_t root,
   while (fsize > 0) {
     uint32_t nf = 0;
     for (uint32_t base = 0; base < fsize; base += 8) {
+      // Lanes with no child to test take the first child of their range
+      // (lanes past the frontier the first range) and are masked off after
+      // the test: the wave runs one path, with no branch around the loads
+      // and the test.
       const uint32_t i = base + (lane >> 3);
-      uint2 r = make_uint2(0u, 0u);
-      if (i < fsize) r = cur[i];
-      const bool valid = kk < r.y;
-      uint32_t node = 0, nch = 0, ch = 0, f = 0, cnt = 0;
-      bool acc = false;
-      if (valid) {
-        node = r.x + kk;
-        const double4 c = A.com[node];
-        const uint4 nf = A.ninfo[node];
-        f = nf.x; cnt = nf.y; ch = nf.z; nch = nf.w;
-        if constexpr (kRel)
-          acc = mac_rel(lo, hi, c, A.rel[2 * (size_t)node], A.rel[2 * (size_t)node + 1], arel);
-        else
-          acc = mac_accept(lo, hi, c, A.th2);
-      }
-      const bool leaf = valid && !acc && nch == 0;
-      const bool open = valid && !acc && nch > 0;
+      const uint2 r = cur[i < fsize ? i : 0u];
+      const bool valid = (i < fsize) & (kk < r.y);
+      const uint32_t node = r.x + (valid ? kk : 0u);
+      const double4 c = A.com[node];
+      const uint4 ni = A.ninfo[node];
+      const uint32_t f = ni.x, cnt = ni.y, ch = ni.z, nch = ni.w;
+      bool acc;
+      if constexpr (kRel)
+        acc = mac_rel(lo, hi, c, A.rel[2 * (size_t)node], A.rel[2 * (size_t)node + 1], arel);
+      else
+        acc = mac_accept(lo, hi, c, A.th2);
+      acc = acc & valid;
+      const bool refused = valid & !acc;
+      const bool leaf = refused & (nch == 0u);
+      const bool open = refused & (nch > 0u);
       // prefix sum of the particles of refused leaves (most passes have none)
       const uint32_t pc = leaf ? cnt : 0u;
       uint32_t ptot = 0, ppre = 0;
@@ -816,14 +825,19 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
     __syncthreads();
     if (nt == 0) continue;   // cannot happen for a listed group; keeps s_tgt reads defined
     // shape: T targets per lane (at least ceil(nt / 64)), lt lane-targets,
-    // slices source slices; minimise T / slices, ties to the larger T
+    // slices source slices; minimise T / slices.  Ties go to the larger T
+    // (fewer tile reads per pair), except that in mixed precision three
+    // targets to a lane are taken only where they evaluate strictly fewer
+    // pairs: measured on the 1M cusp, ties between two and three ran slower
+    // with three.
     int T = (nt + 63) / 64;
     int lt = (nt + T - 1) / T, slices = 64 / lt;
 #pragma unroll
     for (int t = 2; t <= kMaxT; ++t) {
       if (t <= T) continue;
       const int l2 = (nt + t - 1) / t, s2 = 64 / l2;
-      if (t * slices <= T * s2) { T = t; lt = l2; slices = s2; }
+      const bool better = (kMixed && t >= 3) ? t * slices < T * s2 : t * slices <= T * s2;
+      if (better) { T = t; lt = l2; slices = s2; }
     }
     Sink S;
     S.s_m = s_m; S.s_q = s_q; S.tile = &tile;
