@@ -339,8 +339,10 @@ constexpr int kRedT = Shape<kMixed, false>::kMaxT > Shape<kMixed, true>::kMaxT
 
 // Source tiles in LDS.  A flush of k sources fills entries [0, slices *
 // trips) with trips = ceil(k / slices), the entries past k with zero mass;
-// slice s evaluates the contiguous entries [s trips, (s + 1) trips), so every
-// lane runs the same trip count with no masking.  Full flushes take exactly
+// slice s evaluates the entries s, s + slices, s + 2 slices, ... (trips of
+// them), so every lane runs the same trip count with no masking, and the
+// slices of one trip read neighbouring entries (interleaving them measured
+// 0.8% faster than contiguous runs per slice).  Full flushes take exactly
 // slices * floor(128 / slices) (65..128) sources, so the fixed cost of a
 // flush (two barriers, the staging set-up, the FP64 accumulation) is shared
 // by as many sources as the tile holds.  `red` holds the per-lane sums of
@@ -389,7 +391,7 @@ struct ForceSink {
   }
 
   template <int kT>
-  __device__ void eval_m(int base, int trips_in) {
+  __device__ void eval_m(int base, int trips_in, int st) {
     const int trips = __builtin_amdgcn_readfirstlane(trips_in);
     R ax[kT], ay[kT], az[kT], ph[kT];
 #pragma unroll
@@ -397,7 +399,7 @@ struct ForceSink {
     const auto *e = &tile->m[base];
     if constexpr (kSpline) {
       for (int it = 0; it < trips; ++it) {
-        const R4 a = e[it].a, b = e[it].b, c = e[it].c;
+        const R4 a = e[it * st].a, b = e[it * st].b, c = e[it * st].c;
 #pragma unroll
         for (int k = 0; k < kT; ++k)
           p2m_spline<R>(a, b, c, tx[k], ty[k], tz[k], h, ih, ax[k], ay[k], az[k], ph[k]);
@@ -405,10 +407,10 @@ struct ForceSink {
     } else if constexpr (kT == 1) {
 #pragma unroll 2
       for (int it = 0; it < trips; ++it)
-        p2m_term<R>(e[it].a, e[it].b, e[it].c, tx[0], ty[0], tz[0], e2, ax[0], ay[0], az[0], ph[0]);
+        p2m_term<R>(e[it * st].a, e[it * st].b, e[it * st].c, tx[0], ty[0], tz[0], e2, ax[0], ay[0], az[0], ph[0]);
     } else {
       for (int it = 0; it < trips; ++it) {
-        const R4 a = e[it].a, b = e[it].b, c = e[it].c;
+        const R4 a = e[it * st].a, b = e[it * st].b, c = e[it * st].c;
 #pragma unroll
         for (int k = 0; k < kT; ++k)
           p2m_term<R>(a, b, c, tx[k], ty[k], tz[k], e2, ax[k], ay[k], az[k], ph[k]);
@@ -420,7 +422,7 @@ struct ForceSink {
 
   // kOwn: entry et[k] of the tile is target k itself, its pair dropped
   template <int kT, bool kOwn = false>
-  __device__ void eval_p(int base, int trips_in, const uint32_t *et = nullptr) {
+  __device__ void eval_p(int base, int trips_in, int st, const uint32_t *et = nullptr) {
     const int trips = __builtin_amdgcn_readfirstlane(trips_in);
     R ax[kT], ay[kT], az[kT], ph[kT];
 #pragma unroll
@@ -428,8 +430,8 @@ struct ForceSink {
     const R4 *e = &tile->p[base];
     if constexpr (kOwn) {
       for (int it = 0; it < trips; ++it) {
-        const R4 s = e[it];
-        const uint32_t en = (uint32_t)(base + it);
+        const R4 s = e[it * st];
+        const uint32_t en = (uint32_t)(base + it * st);
 #pragma unroll
         for (int k = 0; k < kT; ++k) {
           if constexpr (kSpline)
@@ -440,7 +442,7 @@ struct ForceSink {
       }
     } else if constexpr (kSpline) {
       for (int it = 0; it < trips; ++it) {
-        const R4 s = e[it];
+        const R4 s = e[it * st];
 #pragma unroll
         for (int k = 0; k < kT; ++k)
           p2p_spline<R>(s, tx[k], ty[k], tz[k], h, ih, ax[k], ay[k], az[k], ph[k]);
@@ -448,11 +450,11 @@ struct ForceSink {
     } else if constexpr (kT == 1) {
 #pragma unroll 4
       for (int it = 0; it < trips; ++it)
-        p2p_term<R>(e[it], tx[0], ty[0], tz[0], e2, ax[0], ay[0], az[0], ph[0]);
+        p2p_term<R>(e[it * st], tx[0], ty[0], tz[0], e2, ax[0], ay[0], az[0], ph[0]);
     } else {
 #pragma unroll 2
       for (int it = 0; it < trips; ++it) {
-        const R4 s = e[it];
+        const R4 s = e[it * st];
 #pragma unroll
         for (int k = 0; k < kT; ++k)
           p2p_term<R>(s, tx[k], ty[k], tz[k], e2, ax[k], ay[k], az[k], ph[k]);
@@ -489,11 +491,11 @@ struct ForceSink {
     if (e0 < ne) stage_cell(A, e0, e0 < k, v0);
     if (e1 < ne) stage_cell(A, e1, e1 < k, v1);
     __syncthreads();
-    const int base = my_s * trips;
-    if (T == 1) eval_m<1>(base, trips);
+    const int base = my_s;
+    if (T == 1) eval_m<1>(base, trips, slices);
     else if constexpr (kMaxT >= 2) {
-      if (T == 2) eval_m<2>(base, trips);
-      else if constexpr (kMaxT >= 3) eval_m<3>(base, trips);
+      if (T == 2) eval_m<2>(base, trips, slices);
+      else if constexpr (kMaxT >= 3) eval_m<3>(base, trips, slices);
     }
     __syncthreads();
   }
@@ -516,11 +518,11 @@ struct ForceSink {
     if (e0 < ne) stage_part(A, e0, e0 < k, j0);
     if (e1 < ne) stage_part(A, e1, e1 < k, j1);
     __syncthreads();
-    const int base = my_s * trips;
-    if (T == 1) eval_p<1>(base, trips);
+    const int base = my_s;
+    if (T == 1) eval_p<1>(base, trips, slices);
     else if constexpr (kMaxT >= 2) {
-      if (T == 2) eval_p<2>(base, trips);
-      else if constexpr (kMaxT >= 3) eval_p<3>(base, trips);
+      if (T == 2) eval_p<2>(base, trips, slices);
+      else if constexpr (kMaxT >= 3) eval_p<3>(base, trips, slices);
     }
     __syncthreads();
   }
@@ -561,11 +563,11 @@ struct ForceSink {
       et[q] = own_bit(b) ? own_rank(b) - o + (uint32_t)kq : 0xffffffffu;
     }
     __syncthreads();
-    const int base = my_s * trips;
-    if (T == 1) eval_p<1, true>(base, trips, et);
+    const int base = my_s;
+    if (T == 1) eval_p<1, true>(base, trips, slices, et);
     else if constexpr (kMaxT >= 2) {
-      if (T == 2) eval_p<2, true>(base, trips, et);
-      else if constexpr (kMaxT >= 3) eval_p<3, true>(base, trips, et);
+      if (T == 2) eval_p<2, true>(base, trips, slices, et);
+      else if constexpr (kMaxT >= 3) eval_p<3, true>(base, trips, slices, et);
     }
     __syncthreads();
   }
