@@ -45,6 +45,26 @@ def test_kepler_orbit_exact(e):
     assert abs(ch.energy_error()) < 1e-11
 
 
+@pytest.mark.parametrize("e", [0.5, 0.99])
+def test_many_short_advances_land_on_their_end_times(e):
+    """Sixty calls over one period: every call ends with the search for its
+    last step, closed in physical time where the gap is short against the
+    pair's crossing time (and refused near pericentre where it is not); the
+    orbit still follows Kepler's solution and each call ends on its time."""
+    m = np.array([1.0, 1e-3])
+    x0, v0 = _kepler(m[0], m[1], 1.0, e, 0.0)
+    ch = B.ARChain(x0, v0, m)
+    T = 2 * np.pi / np.sqrt(m.sum())
+    for k in range(1, 61):
+        t = k * T / 60
+        ch.advance(t - ch.t, tol=1e-13)
+        assert ch.t == t or abs(ch.t - t) <= 1e-15 * t
+    x, v = _kepler(m[0], m[1], 1.0, e, ch.t)
+    assert np.linalg.norm((ch.x[1] - ch.x[0]) - (x[1] - x[0])) <= 1e-8
+    assert np.linalg.norm((ch.v[1] - ch.v[0]) - (v[1] - v[0])) <= 1e-7
+    assert abs(ch.energy_error()) < 1e-11
+
+
 def _cluster(seed, n=6):
     rng = np.random.default_rng(seed)
     m = np.concatenate([[1.0], rng.uniform(1e-4, 1e-3, n - 1)])
