@@ -52,8 +52,6 @@ constexpr int kSegSlotLen = 2 * (kMaxSys + 1);
 // A tile of consecutive particles inside one system (sort, cube, keys).
 struct Tile {
   uint32_t start, end;    // particle range
-  uint32_t hist0;         // histogram slot of digit 0 for this tile
-  uint32_t hstride;       // slots between digits (= tiles of the system)
 };
 
 // Per-level bookkeeping kept on the device so that graph replays need no
@@ -111,6 +109,8 @@ struct Buffers {
   uint4 *groups = nullptr;        // [N]
   uint32_t *aflag = nullptr;      // [N + 1] active-group flags / scan
   uint32_t *alist = nullptr;      // [N] active group ids
+  uint32_t *acnt = nullptr;       // [N] active targets per group
+  uint32_t *gorder = nullptr;     // [N] active group ids in the force walk's order
   double *abox = nullptr;         // [N][6] box of active targets per group
   double *arel = nullptr;         // [N] relative test: (alpha alpha) min |a_old|^2 per group
   // chain coupling

@@ -76,7 +76,7 @@ static void free_all(tg_ctx *c) {
                   b.root_of, b.key[0], b.key[1], b.val[0], b.val[1], b.hist,
                   b.rank, b.spart, b.level, b.nchild, b.first, b.count,
                   b.child, b.parent, b.nsys, b.com, b.mom, b.ninfo, b.cell, b.lcp, b.fl_lt, b.fl_bits, b.fl_cnt, b.fl_fst, b.fl_tot, b.gflag,
-                  b.groups, b.aflag, b.alist, b.abox, b.sact, b.frontier,
+                  b.groups, b.aflag, b.alist, b.acnt, b.gorder, b.abox, b.sact, b.frontier,
                   b.wl_count, b.wl_off, b.scan_part, b.scan_total, b.ctr,
                   b.err, b.dpart, b.dseg, b.ext_seg, b.rel, b.side, b.bbox,
                   b.refit_flag, b.refit_gates, b.arel, b.cflag, b.ctile, b.cpart,
@@ -170,7 +170,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.gflag, N + 1));
   A(dalloc(&b.groups, N));
   A(dalloc(&b.aflag, N + 1));
-  A(dalloc(&b.alist, N));
+  A(dalloc(&b.alist, N)); A(dalloc(&b.acnt, N)); A(dalloc(&b.gorder, N));
   A(dalloc(&b.abox, 6 * N)); A(dalloc(&b.arel, N));
   A(dalloc(&b.cflag, N + 1)); A(dalloc(&b.ctile, N / 1024 + 2)); A(dalloc(&b.cpart, 6 * kChainBlocks));
   A(dalloc(&b.sact, N));
@@ -251,7 +251,6 @@ static tg_status set_layout(tg_ctx *c, int64_t n, const int64_t *off, int32_t S)
     return fail(TG_ESTATE, "tg_build_tree: system layout changed during graph capture");
   std::vector<Tile> tiles;
   std::vector<uint32_t> t0(S + 1);
-  uint32_t hbase = 0;
   for (int s = 0; s < S; ++s) {
     t0[s] = (uint32_t)tiles.size();
     const int64_t ns = so[s + 1] - so[s];
@@ -260,11 +259,8 @@ static tg_status set_layout(tg_ctx *c, int64_t n, const int64_t *off, int32_t S)
       Tile t;
       t.start = (uint32_t)(so[s] + (int64_t)k * kSortTile);
       t.end = (uint32_t)std::min<int64_t>(so[s + 1], so[s] + (int64_t)(k + 1) * kSortTile);
-      t.hist0 = hbase + k;
-      t.hstride = nts;
       tiles.push_back(t);
     }
-    hbase += 256u * nts;
   }
   t0[S] = (uint32_t)tiles.size();
   if ((int64_t)tiles.size() > c->max_tiles)
