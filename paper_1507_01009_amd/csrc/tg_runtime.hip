@@ -76,7 +76,7 @@ static void free_all(tg_ctx *c) {
                   b.root_of, b.key[0], b.key[1], b.val[0], b.val[1], b.hist,
                   b.rank, b.spart, b.level, b.nchild, b.first, b.count,
                   b.child, b.parent, b.nsys, b.com, b.mom, b.ninfo, b.cell, b.lcp, b.fl_lt, b.fl_bits, b.fl_cnt, b.fl_fst, b.fl_tot, b.gflag,
-                  b.groups, b.aflag, b.alist, b.acnt, b.gorder, b.abox, b.sact, b.frontier,
+                  b.groups, b.aflag, b.alist, b.acnt, b.gorder, b.abox, b.sact, b.frontier, b.wtot,
                   b.wl_count, b.wl_off, b.scan_part, b.scan_total, b.ctr,
                   b.err, b.dpart, b.dseg, b.ext_seg, b.rel, b.side, b.bbox,
                   b.refit_flag, b.refit_gates, b.arel, b.cflag, b.ctile, b.cpart,
@@ -176,6 +176,7 @@ tg_status tg_create(const tg_config *cfg_in, void *stream, tg_ctx **out) {
   A(dalloc(&b.sact, N));
   A(dalloc(&b.atile, N / 1024 + 2)); A(dalloc(&b.aoff, N / 1024 + 2)); A(dalloc(&b.ainfo, 2));
   A(dalloc(&b.frontier, waves * 2 * (int64_t)cfg.frontier_cap));
+  A(dalloc(&b.wtot, waves * 4));
   A(dalloc(&b.wl_count, 2 * N + 2));
   A(dalloc(&b.wl_off, 2 * N + 2));
   A(dalloc(&b.scan_part, kScanBlocks + 1));
