@@ -1107,36 +1107,44 @@ __global__ void k_compact_groups(const int32_t *__restrict__ gate, const TreeCou
 
 // The order in which the force walk takes the active groups: each XCD's
 // queue range [q G / 8, (q + 1) G / 8) of the compacted list keeps its
-// groups (and so its part of the tree), reordered by active targets, most
-// first.  The walk's wall time ends with the last groups taken, so ending on
-// the small ones shortens the tail in which few waves are left (measured on
-// the 1M cusp: about 12% of the waves' time was spent waiting for the last
-// groups in Morton order).  The order inside a size is that of the atomics;
-// no result depends on the order in which groups are walked.
+// groups (and so its part of the tree), taken by size class, largest class
+// first (kSizeClass thresholds on the active targets), and in tree order
+// within a class.  The walk's wall time ends with the last groups taken, so
+// ending on the small ones shortens the tail in which few waves are left;
+// keeping tree order inside a class keeps neighbouring groups, which share
+// most of their cells, close in time for the XCD's L2.  Stable: each thread
+// takes a contiguous run of the range, and its offsets within each class
+// come from a block scan.  No result depends on the order in which groups
+// are walked.
+constexpr int kSizeClasses = 4;
+__device__ __forceinline__ int size_class(uint32_t nt) {
+  return nt >= 48u ? 0 : nt >= 32u ? 1 : nt >= 16u ? 2 : 3;
+}
+
 __global__ __launch_bounds__(256) void k_order_groups(const int32_t *__restrict__ gate,
                                                       const TreeCounters *ctr,
                                                       const uint32_t *__restrict__ alist,
                                                       const uint32_t *__restrict__ acnt,
                                                       uint32_t *__restrict__ order) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
-  __shared__ uint32_t slot[kMaxGroup + 1];   // [kMaxGroup - active targets]
   __shared__ uint32_t scan_sh[4];
   const uint32_t G = ctr->n_active_groups;
   const uint32_t lo = (uint32_t)(((uint64_t)blockIdx.x * G) >> 3);
   const uint32_t hi = (uint32_t)(((uint64_t)(blockIdx.x + 1) * G) >> 3);
-  for (uint32_t b = threadIdx.x; b <= (uint32_t)kMaxGroup; b += blockDim.x) slot[b] = 0u;
-  __syncthreads();
-  for (uint32_t p = lo + threadIdx.x; p < hi; p += blockDim.x)
-    atomicAdd(&slot[kMaxGroup - min(acnt[alist[p]], (uint32_t)kMaxGroup)], 1u);
-  __syncthreads();
-  uint32_t tot;
-  const uint32_t v = threadIdx.x <= (uint32_t)kMaxGroup ? slot[threadIdx.x] : 0u;
-  const uint32_t start = block_exclusive_scan(v, scan_sh, tot);
-  if (threadIdx.x <= (uint32_t)kMaxGroup) slot[threadIdx.x] = start;
-  __syncthreads();
-  for (uint32_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
+  const uint32_t per = (hi - lo + blockDim.x - 1) / blockDim.x;
+  const uint32_t a = min(hi, lo + per * threadIdx.x), b = min(hi, a + per);
+  uint32_t cnt[kSizeClasses] = {};
+  for (uint32_t p = a; p < b; ++p) ++cnt[size_class(acnt[alist[p]])];
+  uint32_t off[kSizeClasses], base = lo;
+#pragma unroll
+  for (int k = 0; k < kSizeClasses; ++k) {
+    uint32_t tot;
+    off[k] = block_exclusive_scan(cnt[k], scan_sh, tot) + base;
+    base += tot;
+  }
+  for (uint32_t p = a; p < b; ++p) {
     const uint32_t g = alist[p];
-    order[lo + atomicAdd(&slot[kMaxGroup - min(acnt[g], (uint32_t)kMaxGroup)], 1u)] = g;
+    order[off[size_class(acnt[g])]++] = g;
   }
 }
 
@@ -1183,7 +1191,6 @@ hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_compact_groups, dim3(1024), dim3(256), 0, c->stream, c->gate,
                      b.ctr, b.aflag, b.gflag, b.alist);
-  static_assert(kMaxGroup + 1 <= 256, "one size class per thread");
   hipLaunchKernelGGL(k_order_groups, dim3(8), dim3(256), 0, c->stream, c->gate, b.ctr,
                      b.alist, b.acnt, b.gorder);
   return hipGetLastError();
