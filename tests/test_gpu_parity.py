@@ -475,3 +475,36 @@ def test_direct_fp64_at_1m_sources_against_oracle():
     say("  max rel %.3g" % e.max())
     assert e.max() <= 1e-12
     ctx.close()
+
+
+def test_running_counts_add_up_over_walks():
+    """The force walk's counts are summed per workgroup after each walk: the
+    last walk's equal the oracle's, the running totals add them up over
+    walks, an evaluation with no active star adds nothing and reports zero,
+    and a reset clears the totals."""
+    import torch
+    pos, m, eps = _w("hernquist32k")
+    ev = oracle.tree_forces(pos, m, eps, 0.5, 8, 64)
+    g = gpu_run(pos, m, eps, 0.5, 8, 64)
+    ctx = g["ctx"]
+    one = (ev.n_p2p, ev.n_p2m, ev.n_targets)
+    assert (g["counts"]["n_p2p"], g["counts"]["n_p2m"], g["counts"]["n_targets"]) == one
+    acc = torch.zeros((pos.shape[0], 3), dtype=torch.float64, device="cuda")
+    ctx.reset_counts()
+    for k in range(3):
+        ctx.tree_forces(eps, 0.5, acc)
+    ctx.sync()
+    c = ctx.get_cumulative_counts()
+    assert (c["n_p2p"], c["n_p2m"], c["n_targets"]) == tuple(3 * v for v in one)
+    # nothing active: the walk is skipped on the device
+    didx = to_dev(np.zeros(1, np.int32))
+    dna = to_dev(np.zeros(1, np.int32))
+    ctx.tree_forces(eps, 0.5, acc, None, didx, dna)
+    ctx.sync()
+    last, run = ctx.get_counts(), ctx.get_cumulative_counts()
+    assert (last["n_p2p"], last["n_p2m"], last["n_targets"]) == (0, 0, 0)
+    assert (run["n_p2p"], run["n_p2m"], run["n_targets"]) == tuple(3 * v for v in one)
+    ctx.reset_counts()
+    ctx.sync()
+    z = ctx.get_cumulative_counts()
+    assert (z["n_p2p"], z["n_p2m"], z["n_targets"], z["n_groups"]) == (0, 0, 0, 0)
