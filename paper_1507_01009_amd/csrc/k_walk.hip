@@ -941,11 +941,13 @@ void k_walk_forces(const int32_t *__restrict__ gate, WalkArgs A) {
 
 // The force walk's counts: the sums of the nb workgroups' totals, into the
 // last walk's counts and added to the running ones.
-__global__ __launch_bounds__(256) void k_walk_sum(const int32_t *__restrict__ gate, TreeCounters *ctr,
+constexpr int kSumThreads = 1024;
+
+__global__ __launch_bounds__(kSumThreads) void k_walk_sum(const int32_t *__restrict__ gate, TreeCounters *ctr,
                                                   const unsigned long long *__restrict__ wtot,
                                                   int nb) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
-  __shared__ unsigned long long part[4][4];
+  __shared__ unsigned long long part[kSumThreads / 64][4];
   unsigned long long v[4] = {0, 0, 0, 0};
   for (int b = threadIdx.x; b < nb; b += blockDim.x)
 #pragma unroll
@@ -961,7 +963,8 @@ __global__ __launch_bounds__(256) void k_walk_sum(const int32_t *__restrict__ ga
   __syncthreads();
   if (threadIdx.x < 4) {
     const unsigned k = threadIdx.x;
-    const unsigned long long t = part[0][k] + part[1][k] + part[2][k] + part[3][k];
+    unsigned long long t = 0;
+    for (int q = 0; q < kSumThreads / 64; ++q) t += part[q][k];
     (&ctr->n_p2p)[k] = t;
     (&ctr->cum_p2p)[k] += t;
   }
@@ -1121,13 +1124,15 @@ __device__ __forceinline__ int size_class(uint32_t nt) {
   return nt >= 48u ? 0 : nt >= 32u ? 1 : nt >= 16u ? 2 : 3;
 }
 
-__global__ __launch_bounds__(256) void k_order_groups(const int32_t *__restrict__ gate,
+constexpr int kOrderThreads = 1024;   // short runs per thread: the loads of a run are dependent
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_groups(const int32_t *__restrict__ gate,
                                                       const TreeCounters *ctr,
                                                       const uint32_t *__restrict__ alist,
                                                       const uint32_t *__restrict__ acnt,
                                                       uint32_t *__restrict__ order) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
-  __shared__ uint32_t scan_sh[4];
+  __shared__ uint32_t scan_sh[kOrderThreads / 64];
   const uint32_t G = ctr->n_active_groups;
   const uint32_t lo = (uint32_t)(((uint64_t)blockIdx.x * G) >> 3);
   const uint32_t hi = (uint32_t)(((uint64_t)(blockIdx.x + 1) * G) >> 3);
@@ -1191,7 +1196,7 @@ hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_compact_groups, dim3(1024), dim3(256), 0, c->stream, c->gate,
                      b.ctr, b.aflag, b.gflag, b.alist);
-  hipLaunchKernelGGL(k_order_groups, dim3(8), dim3(256), 0, c->stream, c->gate, b.ctr,
+  hipLaunchKernelGGL(k_order_groups, dim3(8), dim3(kOrderThreads), 0, c->stream, c->gate, b.ctr,
                      b.alist, b.acnt, b.gorder);
   return hipGetLastError();
 }
@@ -1329,7 +1334,7 @@ hipError_t launch_walk_forces(tg_ctx *c, double eps, double theta,
     hipError_t e = hipEventRecord(after, c->stream);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_walk_sum, dim3(1), dim3(256), 0, c->stream, c->gate, c->b.ctr, c->b.wtot,
+  hipLaunchKernelGGL(k_walk_sum, dim3(1), dim3(kSumThreads), 0, c->stream, c->gate, c->b.ctr, c->b.wtot,
                      walk_grid(c));
   return hipGetLastError();
 }
