@@ -159,8 +159,13 @@ __global__ __launch_bounds__(256) void k_keys(const int32_t *__restrict__ gate, 
                                               int S, const double *__restrict__ cube,
                                               uint64_t *__restrict__ key,
                                               uint64_t *__restrict__ klo,
-                                              uint32_t *__restrict__ val) {
+                                              uint32_t *__restrict__ val,
+                                              uint32_t *__restrict__ zero, int64_t nzero) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
+  // the sort's counters and tile status, cleared for the sort that follows
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nzero;
+       w += (int64_t)gridDim.x * blockDim.x)
+    zero[w] = 0u;
   const Tile t = tiles[blockIdx.x];
   const double *c = cube + 4 * system_of_tile(sys_tile0, S, blockIdx.x);
   const double sigma = (kDeep ? 4398046511104.0 : 2097152.0) / c[3];
@@ -440,10 +445,12 @@ hipError_t launch_cube_keys(tg_ctx *c, const double *pos) {
   if (nt > 0 && c->max_level > kMaxLevel)
     // first words in caller order to key[0], second words to klo[1] (sorted first)
     hipLaunchKernelGGL(k_keys<true>, dim3(nt), dim3(256), 0, c->stream, c->gate, pos, b.tiles,
-                       b.sys_tile0, c->S, b.cube, b.key[0], b.klo[1], b.val[1]);
+                       b.sys_tile0, c->S, b.cube, b.key[0], b.klo[1], b.val[1], b.hist,
+                       sort_hist_words(c->S, nt));
   else if (nt > 0)
     hipLaunchKernelGGL(k_keys<false>, dim3(nt), dim3(256), 0, c->stream, c->gate, pos, b.tiles,
-                       b.sys_tile0, c->S, b.cube, b.key[1], nullptr, b.val[1]);
+                       b.sys_tile0, c->S, b.cube, b.key[1], nullptr, b.val[1], b.hist,
+                       sort_hist_words(c->S, nt));
   return hipGetLastError();
 }
 
@@ -456,11 +463,10 @@ static hipError_t sort_passes(tg_ctx *c, uint64_t *ka, uint32_t *va, uint64_t *k
   static_assert(kSortPasses % 2 == 1, "the input starts in the second buffers");
   Buffers &b = c->b;
   const int nt = (int)c->n_tiles;
-  // [tickets | pad | counts [S][passes][digits] | status [passes][nt][digits]], all zero
+  // [tickets | pad | counts [S][passes][digits] | status [passes][nt][digits]],
+  // all zero: cleared by the kernel before the sort (k_keys, k_gather_hi)
   uint32_t *tickets = b.hist, *cnt = b.hist + kSortStatusBase;
   uint32_t *status = cnt + (size_t)c->S * kSortPasses * kSortDigits;
-  hipError_t e = fill_u32(b.hist, 0u, sort_hist_words(c->S, nt), c->stream, c->gate);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sort_count, dim3(nt), dim3(256), 0, c->stream, c->gate, kb, b.tiles,
                      b.sys_tile0, c->S, cnt);
   uint64_t *k2[2] = {ka, kb};
@@ -480,8 +486,13 @@ static hipError_t sort_passes(tg_ctx *c, uint64_t *ka, uint32_t *va, uint64_t *k
 // the second buffers where the next phase starts.
 __global__ void k_gather_hi(const int32_t *__restrict__ gate, const uint64_t *__restrict__ hi,
                             const uint32_t *__restrict__ perm, int64_t n,
-                            uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+                            uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                            uint32_t *__restrict__ zero, int64_t nzero) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
+  // the sort's counters and tile status, cleared for the second sort
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nzero;
+       w += (int64_t)gridDim.x * blockDim.x)
+    zero[w] = 0u;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t p = perm[r];
@@ -503,7 +514,7 @@ hipError_t launch_sort(tg_ctx *c) {
   if (e != hipSuccess) return e;
   const int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_gather_hi, dim3(g), dim3(256), 0, c->stream, c->gate, b.key[0],
-                     b.val[0], c->n, b.key[1], b.val[1]);
+                     b.val[0], c->n, b.key[1], b.val[1], b.hist, sort_hist_words(c->S, nt));
   return sort_passes(c, b.key[0], b.val[0], b.key[1], b.val[1], b.rank);
 }
 

@@ -28,31 +28,30 @@ __global__ __launch_bounds__(256) void k_scan_part(const int32_t *__restrict__ g
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_top(const int32_t *__restrict__ gate, uint32_t *part, int nb,
-                                                  uint32_t *total) {
-  if (gate && *gate <= 0) return;   // nothing active: skipped
-  __shared__ uint32_t sh[4];
-  uint32_t v = (int)threadIdx.x < nb ? part[threadIdx.x] : 0u;
-  uint32_t tot;
-  uint32_t e = block_exclusive_scan(v, sh, tot);
-  if ((int)threadIdx.x < nb) part[threadIdx.x] = e;
-  if (threadIdx.x == 0) {
-    part[nb] = tot;
-    if (total) *total = tot;
-  }
-}
+// Each block first scans the blocks' partial sums itself (there are as many
+// as a block has threads) for its own offset; block 0 also stores the total.
+static_assert(kScanBlocks <= 256, "one partial sum per thread");
 
 __global__ __launch_bounds__(256) void k_scan_final(const int32_t *__restrict__ gate, const uint32_t *in,
                                                     uint32_t *out,
                                                     uint32_t n_host,
                                                     const uint32_t *n_dev,
-                                                    const uint32_t *part) {
+                                                    const uint32_t *part, uint32_t *total) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint32_t sh[4];
+  __shared__ uint32_t s_base;
   uint32_t n = n_dev ? *n_dev : n_host;
   uint32_t a, b;
   chunk_of(n, a, b);
-  uint32_t base = part[blockIdx.x];
+  {
+    const uint32_t v = threadIdx.x < gridDim.x ? part[threadIdx.x] : 0u;
+    uint32_t tot;
+    const uint32_t e = block_exclusive_scan(v, sh, tot);
+    if (threadIdx.x == blockIdx.x) s_base = e;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && total) *total = tot;
+    __syncthreads();
+  }
+  uint32_t base = s_base;
   for (uint32_t t0 = a; t0 < b; t0 += 256u) {
     uint32_t i = t0 + threadIdx.x;
     uint32_t v = i < b ? in[i] : 0u;
@@ -68,10 +67,8 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, uint32_t n_host,
                     hipStream_t s, const int32_t *gate) {
   hipLaunchKernelGGL(k_scan_part, dim3(kScanBlocks), dim3(256), 0, s, gate, in,
                      n_host, n_dev, part);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, gate, part, kScanBlocks,
-                     total_dev);
   hipLaunchKernelGGL(k_scan_final, dim3(kScanBlocks), dim3(256), 0, s, gate, in,
-                     out, n_host, n_dev, part);
+                     out, n_host, n_dev, part, total_dev);
   return hipGetLastError();
 }
 

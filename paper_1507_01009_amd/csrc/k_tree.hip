@@ -57,12 +57,13 @@ __device__ __forceinline__ uint32_t common_digits(uint64_t a, uint64_t b) {
 __global__ __launch_bounds__(256) void k_lcp(const int32_t *__restrict__ gate, const uint64_t *__restrict__ skey,
                                              const uint64_t *__restrict__ skey_lo, int64_t n,
                                              const int64_t *__restrict__ sysoff, int S,
-                                             uint8_t *__restrict__ d) {
+                                             uint8_t *__restrict__ d, uint32_t *__restrict__ gflag) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ int64_t so[kMaxSys + 1];
   load_sysoff(so, sysoff, S);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n + 64;
        i += (int64_t)gridDim.x * blockDim.x) {
+    if (i <= n) gflag[i] = 0u;   // the group-start flags [0, n], cleared for k_group_flags
     uint32_t v = 0;
     if (i > 0 && i < n && so[sys_of(so, S, i)] != i) {
       v = common_digits(skey[i - 1], skey[i]);
@@ -368,7 +369,7 @@ hipError_t launch_tree_build(tg_ctx *c) {
   const bool deep = c->max_level > kMaxLevel;
   hipLaunchKernelGGL(k_lcp, dim3((int)std::min<int64_t>((n + 64 + 255) / 256, 4096)),
                      dim3(256), 0, c->stream, c->gate, b.key[0], deep ? b.klo[0] : nullptr, n,
-                     b.sysoff, c->S, b.lcp);
+                     b.sysoff, c->S, b.lcp, b.gflag);
   if (deep)
     launch_flat<kMaxLevelDeep>(c, T);
   else
@@ -433,13 +434,12 @@ hipError_t launch_groups(tg_ctx *c) {
   if (c->n == 0) {
     return fill_u32(&b.ctr->n_groups, 0u, 1, c->stream);
   }
-  hipError_t e = fill_u32(b.gflag, 0u, c->n + 1, c->stream, c->gate);
-  if (e != hipSuccess) return e;
+  // the flags were cleared by k_lcp in the build
   const int g = 1024;
   hipLaunchKernelGGL(k_group_flags, dim3(g), dim3(256), 0, c->stream, c->gate, b.ctr,
                      (uint32_t)c->group_size, b.nchild, b.first, b.count,
                      b.parent, b.gflag);
-  e = scan_u32(b.gflag, b.gflag, (uint32_t)c->n, nullptr, &b.ctr->n_groups,
+  hipError_t e = scan_u32(b.gflag, b.gflag, (uint32_t)c->n, nullptr, &b.ctr->n_groups,
                b.scan_part, c->stream, c->gate);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_group_write, dim3(g), dim3(256), 0, c->stream, c->gate, b.ctr,
