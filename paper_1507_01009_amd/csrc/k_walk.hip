@@ -1182,8 +1182,11 @@ hipError_t launch_active_groups(tg_ctx *c, const int32_t *idx,
                                 double alpha) {
   Buffers &b = c->b;
   if (c->n == 0) return fill_u32(&b.ctr->n_active_groups, 0u, 1, c->stream);
-  hipError_t e = fill_u8(b.sact, 0, c->n, c->stream, c->gate);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (idx) {   // without a list every particle is marked active below
+    e = fill_u8(b.sact, 0, c->n, c->stream, c->gate);
+    if (e != hipSuccess) return e;
+  }
   int g = (int)std::min<int64_t>((c->n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_mark_active, dim3(g), dim3(256), 0, c->stream, c->gate, idx,
                      n_act, c->n, b.rank, b.sact);
