@@ -60,7 +60,13 @@ __device__ __forceinline__ void store_moments(uint32_t v, double s, double M, do
   o[7] = 0.0;
 }
 
-// Every leaf of the tree (nodes without children), any level.
+// Every leaf of the tree (nodes without children), any level.  The first
+// kLeafRegs particles of a leaf are loaded into registers at once, so both
+// passes over them wait for memory once; particles beyond (over-full leaves
+// of the deepest level, or leaves of a larger leaf size) are read in the
+// passes.  The sums take the particles in the same order either way.
+constexpr uint32_t kLeafRegs = 8;
+
 template <bool kBox>
 __global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restrict__ gate,
     const TreeCounters *ctr, const double *__restrict__ cube,
@@ -77,12 +83,15 @@ __global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restric
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
        v += gridDim.x * blockDim.x) {
     if (nchild[v] != 0) continue;
-    const uint32_t f = first[v], end = f + count[v];
+    const uint32_t f = first[v], n = count[v];
+    double4 pr[kLeafRegs];
+#pragma unroll
+    for (uint32_t q = 0; q < kLeafRegs; ++q)
+      if (q < n) pr[q] = spart[f + q];
     // compensated sums: a leaf may hold any number of coincident particles
     CSum Mc, sxc, syc, szc;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (uint32_t j = f; j < end; ++j) {
-      const double4 p = spart[j];
+    auto first_moments = [&](const double4 &p) {
       Mc.add(p.w);
       sxc.add(p.w * p.x);
       syc.add(p.w * p.y);
@@ -92,16 +101,23 @@ __global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restric
         hi[0] = fmax(hi[0], p.x); hi[1] = fmax(hi[1], p.y); hi[2] = fmax(hi[2], p.z);
         bad |= !isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z);
       }
-    }
+    };
+#pragma unroll
+    for (uint32_t q = 0; q < kLeafRegs; ++q)
+      if (q < n) first_moments(pr[q]);
+    for (uint32_t j = f + kLeafRegs; j < f + n; ++j) first_moments(spart[j]);
     const double M = Mc.get();
     const double cx = sxc.get() / M, cy = syc.get() / M, cz = szc.get() / M;
     CSum Sc[6];
-    for (uint32_t j = f; j < end; ++j) {
-      const double4 p = spart[j];
+    auto second_moments = [&](const double4 &p) {
       const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
       Sc[0].add(p.w * dx * dx); Sc[1].add(p.w * dy * dy); Sc[2].add(p.w * dz * dz);
       Sc[3].add(p.w * dx * dy); Sc[4].add(p.w * dx * dz); Sc[5].add(p.w * dy * dz);
-    }
+    };
+#pragma unroll
+    for (uint32_t q = 0; q < kLeafRegs; ++q)
+      if (q < n) second_moments(pr[q]);
+    for (uint32_t j = f + kLeafRegs; j < f + n; ++j) second_moments(spart[j]);
     double S[6];
     for (int k = 0; k < 6; ++k) S[k] = Sc[k].get();
     double so;
