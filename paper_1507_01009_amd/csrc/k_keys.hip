@@ -3,10 +3,13 @@
 // sorted order.
 //
 // Work is cut into tiles of kSortTile consecutive particles that never cross
-// a system boundary, so one launch handles every system of a batch and the
-// histogram layout [system][digit][tile-of-system] makes the sort segmented
-// for free: the exclusive scan of the whole histogram already places each
-// system after the previous one.
+// a system boundary, so one launch handles every system of a batch.  One
+// kernel counts each system's digits for all passes; in each pass a tile
+// ranks its keys, publishes its per-digit counts and adds those of the
+// earlier tiles of its own system (a look-back that ends at the system's
+// first tile).  A key's place is the system's first index + the system's
+// keys of smaller digits + the earlier tiles' keys of its digit + its rank
+// in the tile, so the sort is segmented by system.
 //
 // Bit-exactness: the quantisation is t = x - lo, u = t * (2^21 / L), floor,
 // clamp, with no contraction possible (one subtract, one multiply), and the
@@ -264,6 +267,26 @@ __global__ __launch_bounds__(256) void k_sort_count(const int32_t *__restrict__ 
   }
 }
 
+// Exclusive prefix sums over the block of two values per thread at once
+// (one barrier).  The wave totals stay in sh; the caller's next barrier
+// comes before sh is written again.
+__device__ __forceinline__ void block_exclusive_scan2(uint32_t a, uint32_t b, uint2 *sh,
+                                                      uint32_t &ea, uint32_t &eb) {
+  const unsigned lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  uint32_t x = a, y = b;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t xo = __shfl_up(x, o, 64), yo = __shfl_up(y, o, 64);
+    if (lane >= (unsigned)o) { x += xo; y += yo; }
+  }
+  if (lane == 63u) sh[w] = make_uint2(x, y);
+  __syncthreads();
+  uint32_t ba = 0, bb = 0;
+  for (unsigned q = 0; q < w; ++q) { ba += sh[q].x; bb += sh[q].y; }
+  ea = ba + x - a;
+  eb = bb + y - b;
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const int32_t *__restrict__ gate, 
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -277,7 +300,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const int32_t *__res
   __shared__ uint32_t wcnt[kWaves][kSortDigits];
   __shared__ uint32_t loc_off[kSortDigits];
   __shared__ uint32_t glob_off[kSortDigits];
-  __shared__ uint32_t scan_sh[kWaves];
+  __shared__ uint2 scan_sh[kWaves];
   __shared__ uint32_t s_tile;
   const unsigned tid = threadIdx.x, w = tid >> 6, lane = tid & 63u;
   const int shift = kSortBits * pass;
@@ -290,6 +313,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const int32_t *__res
   const int s = tile_system(sys_tile0, S, tb);
   const uint32_t first_tile = sys_tile0[s];
   const uint32_t n_in = t.end - t.start;
+  // the system's count of digit tid (all tiles) and its first index
+  const uint32_t gcnt = cnt[(size_t)(s * kSortPasses + pass) * kSortDigits + tid];
+  const int64_t soff = sysoff[s];
 
   // wave w holds the tile's keys [64 kSortItems w, 64 kSortItems (w + 1)) in index order
   uint64_t k[kSortItems];
@@ -334,10 +360,28 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const int32_t *__res
     const uint32_t d = (uint32_t)(k[r] >> shift) & kSortMask;
     rk[r] += wcnt[w][d];
   }
-  // publish this tile's count of digit tid, then look back for the prefix
+  // publish this tile's count of digit tid
   uint32_t *st = status + (size_t)tb * kSortDigits + tid;
   __hip_atomic_store(st, (tb == first_tile ? kStIncl : kStAgg) | mine, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
+  // before waiting on the predecessors: the digit starts inside the system
+  // (counts of smaller digits) and inside the tile, and the tile's keys
+  // placed in LDS in digit order
+  uint32_t dbase, lbase;
+  block_exclusive_scan2(gcnt, mine, scan_sh, dbase, lbase);
+  loc_off[tid] = lbase;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t idx = 64u * kSortItems * w + 64u * r + lane;
+    if (idx < n_in) {
+      const uint32_t d = (uint32_t)(k[r] >> shift) & kSortMask;
+      const uint32_t p = loc_off[d] + rk[r];
+      sk[p] = k[r];
+      sv[p] = v[r];
+    }
+  }
+  // look back for the prefix of digit tid over the earlier tiles
   uint32_t prefix = 0;
   if (tb != first_tile) {
     // windows of up to 16 predecessors read at once; walk down from the
@@ -377,23 +421,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(const int32_t *__res
     __hip_atomic_store(st, kStIncl | (prefix + mine), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
-  // digit starts inside the system: sysoff + counts of smaller digits
-  uint32_t tot;
-  const uint32_t dbase = block_exclusive_scan(
-      cnt[(size_t)(s * kSortPasses + pass) * kSortDigits + tid], scan_sh, tot);
-  glob_off[tid] = (uint32_t)sysoff[s] + dbase + prefix;
-  loc_off[tid] = block_exclusive_scan(mine, scan_sh, tot);
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
-    const uint32_t idx = 64u * kSortItems * w + 64u * r + lane;
-    if (idx < n_in) {
-      const uint32_t d = (uint32_t)(k[r] >> shift) & kSortMask;
-      const uint32_t p = loc_off[d] + rk[r];
-      sk[p] = k[r];
-      sv[p] = v[r];
-    }
-  }
+  glob_off[tid] = (uint32_t)soff + dbase + prefix;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
