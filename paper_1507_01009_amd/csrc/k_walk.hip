@@ -1115,16 +1115,45 @@ __global__ void k_compact_groups(const int32_t *__restrict__ gate, const TreeCou
 // within a class.  The walk's wall time ends with the last groups taken, so
 // ending on the small ones shortens the tail in which few waves are left;
 // keeping tree order inside a class keeps neighbouring groups, which share
-// most of their cells, close in time for the XCD's L2.  Stable: each thread
-// takes a contiguous run of the range, and its offsets within each class
-// come from a block scan.  No result depends on the order in which groups
-// are walked.
+// most of their cells, close in time for the XCD's L2.  One block per range:
+// a first sweep counts the classes (coalesced reads), then the range is
+// taken in chunks staged in LDS, each thread placing a contiguous run of
+// the chunk at offsets from one block scan of its four class counts packed
+// in 16-bit fields.  Stable, so deterministic.  No result depends on the
+// order in which groups are walked.
 constexpr int kSizeClasses = 4;
-__device__ __forceinline__ int size_class(uint32_t nt) {
-  return nt >= 48u ? 0 : nt >= 32u ? 1 : nt >= 16u ? 2 : 3;
+__device__ __forceinline__ uint32_t size_class(uint32_t nt) {
+  return nt >= 48u ? 0u : nt >= 32u ? 1u : nt >= 16u ? 2u : 3u;
 }
 
-constexpr int kOrderThreads = 1024;   // short runs per thread: the loads of a run are dependent
+constexpr int kOrderThreads = 1024;
+constexpr uint32_t kOrderItems = 8;                                // per thread and chunk
+constexpr uint32_t kOrderChunk = kOrderThreads * kOrderItems;      // < 2^16 per class field
+static_assert(kOrderChunk < 65536u, "a chunk's class counts fit 16-bit fields");
+
+// Exclusive block prefix of a 64-bit value (four 16-bit fields; no carries
+// between fields since every field's total stays below 2^16).
+__device__ __forceinline__ uint64_t block_exclusive_scan64(uint64_t v, uint64_t *sh,
+                                                          uint64_t &total) {
+  const unsigned lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  uint64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o, 64);
+    if (lane >= (unsigned)o) x += y;
+  }
+  if (lane == 63u) sh[w] = x;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+  for (unsigned q = 0; q < blockDim.x / 64u; ++q) {
+    const uint64_t t = sh[q];
+    base += q < w ? t : 0ull;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return base + x - v;
+}
 
 __global__ __launch_bounds__(kOrderThreads) void k_order_groups(const int32_t *__restrict__ gate,
                                                       const TreeCounters *ctr,
@@ -1132,24 +1161,81 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_groups(const int32_t *_
                                                       const uint32_t *__restrict__ acnt,
                                                       uint32_t *__restrict__ order) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
-  __shared__ uint32_t scan_sh[kOrderThreads / 64];
+  __shared__ uint64_t scan_sh[kOrderThreads / 64];
+  __shared__ uint32_t s_g[kOrderChunk];
+  __shared__ uint8_t s_c[kOrderChunk];
+  const uint32_t tid = threadIdx.x;
   const uint32_t G = ctr->n_active_groups;
   const uint32_t lo = (uint32_t)(((uint64_t)blockIdx.x * G) >> 3);
   const uint32_t hi = (uint32_t)(((uint64_t)(blockIdx.x + 1) * G) >> 3);
-  const uint32_t per = (hi - lo + blockDim.x - 1) / blockDim.x;
-  const uint32_t a = min(hi, lo + per * threadIdx.x), b = min(hi, a + per);
+  // class totals of the range
   uint32_t cnt[kSizeClasses] = {};
-  for (uint32_t p = a; p < b; ++p) ++cnt[size_class(acnt[alist[p]])];
-  uint32_t off[kSizeClasses], base = lo;
+  for (uint32_t p0 = lo + tid; p0 < hi; p0 += kOrderThreads * kOrderItems) {
+    uint32_t gg[kOrderItems];       // the loads of kOrderItems groups in flight at once
+#pragma unroll
+    for (uint32_t j = 0; j < kOrderItems; ++j) {
+      const uint32_t p = p0 + j * kOrderThreads;
+      gg[j] = p < hi ? alist[p] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kOrderItems; ++j) {
+      if (p0 + j * kOrderThreads >= hi) continue;
+      const uint32_t k = size_class(acnt[gg[j]]);
+#pragma unroll
+      for (uint32_t q = 0; q < kSizeClasses; ++q) cnt[q] += k == q ? 1u : 0u;
+    }
+  }
+  uint32_t next[kSizeClasses];      // next free slot of each class
+  uint32_t base = lo;
 #pragma unroll
   for (int k = 0; k < kSizeClasses; ++k) {
     uint32_t tot;
-    off[k] = block_exclusive_scan(cnt[k], scan_sh, tot) + base;
+    block_exclusive_scan(cnt[k], reinterpret_cast<uint32_t *>(scan_sh), tot);
+    next[k] = base;
     base += tot;
   }
-  for (uint32_t p = a; p < b; ++p) {
-    const uint32_t g = alist[p];
-    order[off[size_class(acnt[g])]++] = g;
+  for (uint32_t c0 = lo; c0 < hi; c0 += kOrderChunk) {
+    const uint32_t m = min(kOrderChunk, hi - c0);
+    uint32_t gg[kOrderItems];
+#pragma unroll
+    for (uint32_t j = 0; j < kOrderItems; ++j) {
+      const uint32_t i = tid + j * kOrderThreads;
+      gg[j] = i < m ? alist[c0 + i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kOrderItems; ++j) {
+      const uint32_t i = tid + j * kOrderThreads;
+      if (i < m) {
+        s_g[i] = gg[j];
+        s_c[i] = (uint8_t)size_class(acnt[gg[j]]);
+      }
+    }
+    __syncthreads();
+    // this thread's run [kOrderItems tid, kOrderItems (tid + 1)) of the chunk
+    const uint32_t r0 = kOrderItems * tid;
+    uint64_t mine = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kOrderItems; ++j)
+      if (r0 + j < m) mine += 1ull << (16u * s_c[r0 + j]);
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan64(mine, scan_sh, tot);
+    uint32_t at[kSizeClasses];
+#pragma unroll
+    for (uint32_t q = 0; q < kSizeClasses; ++q) at[q] = next[q] + (uint32_t)((ex >> (16u * q)) & 0xffffu);
+#pragma unroll
+    for (uint32_t j = 0; j < kOrderItems; ++j) {
+      if (r0 + j >= m) break;
+      const uint32_t k = s_c[r0 + j];
+      uint32_t dst = at[0];
+#pragma unroll
+      for (uint32_t q = 1; q < kSizeClasses; ++q) dst = k == q ? at[q] : dst;
+#pragma unroll
+      for (uint32_t q = 0; q < kSizeClasses; ++q) at[q] += k == q ? 1u : 0u;
+      order[dst] = s_g[r0 + j];
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kSizeClasses; ++q) next[q] += (uint32_t)((tot >> (16u * q)) & 0xffffu);
+    __syncthreads();                // the chunk's LDS is read before the next is staged
   }
 }
 
