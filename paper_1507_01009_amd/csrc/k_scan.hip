@@ -12,6 +12,11 @@ __device__ __forceinline__ void chunk_of(uint32_t n, uint32_t &a, uint32_t &b) {
   b = min(n, a + chunk);
 }
 
+// A block's chunk is taken kScanSub elements at a time, kScanItems per
+// thread, all loads of a sub-chunk in flight at once.
+constexpr uint32_t kScanItems = 16;
+constexpr uint32_t kScanSub = 256 * kScanItems;
+
 __global__ __launch_bounds__(256) void k_scan_part(const int32_t *__restrict__ gate, const uint32_t *in,
                                                    uint32_t n_host,
                                                    const uint32_t *n_dev,
@@ -22,7 +27,13 @@ __global__ __launch_bounds__(256) void k_scan_part(const int32_t *__restrict__ g
   uint32_t a, b;
   chunk_of(n, a, b);
   uint32_t s = 0;
-  for (uint32_t i = a + threadIdx.x; i < b; i += 256u) s += in[i];
+  for (uint32_t t0 = a; t0 < b; t0 += kScanSub) {
+#pragma unroll
+    for (uint32_t j = 0; j < kScanItems; ++j) {
+      const uint32_t i = t0 + 256u * j + threadIdx.x;
+      s += i < b ? in[i] : 0u;
+    }
+  }
   uint32_t tot;
   block_exclusive_scan(s, sh, tot);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -30,7 +41,14 @@ __global__ __launch_bounds__(256) void k_scan_part(const int32_t *__restrict__ g
 
 // Each block first scans the blocks' partial sums itself (there are as many
 // as a block has threads) for its own offset; block 0 also stores the total.
+// A sub-chunk is read into LDS with coalesced loads, each thread scans a
+// contiguous run of kScanItems there, one block scan of the run totals
+// places the runs, and the results leave through LDS with coalesced
+// stores.  in and out may be the same array: a sub-chunk is read whole
+// before any of it is written, and blocks own disjoint chunks.
 static_assert(kScanBlocks <= 256, "one partial sum per thread");
+
+__device__ __forceinline__ uint32_t scan_pad(uint32_t p) { return p + (p >> 5); }
 
 __global__ __launch_bounds__(256) void k_scan_final(const int32_t *__restrict__ gate, const uint32_t *in,
                                                     uint32_t *out,
@@ -40,25 +58,49 @@ __global__ __launch_bounds__(256) void k_scan_final(const int32_t *__restrict__ 
   if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint32_t sh[4];
   __shared__ uint32_t s_base;
+  __shared__ uint32_t buf[kScanSub + kScanSub / 32];
+  const uint32_t tid = threadIdx.x;
   uint32_t n = n_dev ? *n_dev : n_host;
   uint32_t a, b;
   chunk_of(n, a, b);
   {
-    const uint32_t v = threadIdx.x < gridDim.x ? part[threadIdx.x] : 0u;
+    const uint32_t v = tid < gridDim.x ? part[tid] : 0u;
     uint32_t tot;
     const uint32_t e = block_exclusive_scan(v, sh, tot);
-    if (threadIdx.x == blockIdx.x) s_base = e;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && total) *total = tot;
+    if (tid == blockIdx.x) s_base = e;
+    if (blockIdx.x == 0 && tid == 0 && total) *total = tot;
     __syncthreads();
   }
   uint32_t base = s_base;
-  for (uint32_t t0 = a; t0 < b; t0 += 256u) {
-    uint32_t i = t0 + threadIdx.x;
-    uint32_t v = i < b ? in[i] : 0u;
+  for (uint32_t t0 = a; t0 < b; t0 += kScanSub) {
+    const uint32_t m = min(kScanSub, b - t0);
+#pragma unroll
+    for (uint32_t j = 0; j < kScanItems; ++j) {
+      const uint32_t p = 256u * j + tid;
+      buf[scan_pad(p)] = p < m ? in[t0 + p] : 0u;
+    }
+    __syncthreads();
+    uint32_t run[kScanItems], sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kScanItems; ++j) {
+      run[j] = buf[scan_pad(kScanItems * tid + j)];
+      sum += run[j];
+    }
     uint32_t tot;
-    uint32_t e = block_exclusive_scan(v, sh, tot);
-    if (i < b) out[i] = base + e;
+    uint32_t e = base + block_exclusive_scan(sum, sh, tot);
+#pragma unroll
+    for (uint32_t j = 0; j < kScanItems; ++j) {
+      buf[scan_pad(kScanItems * tid + j)] = e;
+      e += run[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kScanItems; ++j) {
+      const uint32_t p = 256u * j + tid;
+      if (p < m) out[t0 + p] = buf[scan_pad(p)];
+    }
     base += tot;
+    __syncthreads();                // the sub-chunk is written out before the next is read in
   }
 }
 
