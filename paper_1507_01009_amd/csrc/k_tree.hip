@@ -160,53 +160,106 @@ __global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ 
 
 // One block per level: exclusive prefix of cnt[l][0..T) in place with
 // cnt[l][T] = total (also tot[l]); fst[l][b] <- first run start of level l
-// after tile b (suffix minimum over later tiles; n past the last).
+// after tile b (suffix minimum over later tiles; n past the last).  The
+// tiles are taken kFSSub at a time: read into LDS with all loads in flight,
+// each thread combining a contiguous run of kFSItems, one block-wide pass
+// over the run totals, and written back from LDS.
+constexpr int kFSItems = 4;
+constexpr int kFSSub = 1024 * kFSItems;
+__device__ __forceinline__ int fs_pad(int p) { return p + (p >> 5); }
+
 __global__ __launch_bounds__(1024) void k_flat_scan(const int32_t *__restrict__ gate, int64_t T, int64_t n,
                                                     uint32_t *__restrict__ cnt,
                                                     uint32_t *__restrict__ fst, int64_t tl,
                                                     uint32_t *__restrict__ tot) {
   if (gate && *gate <= 0) return;   // nothing active: skipped
   __shared__ uint32_t sh[16];
+  __shared__ uint32_t buf[kFSSub + kFSSub / 32];
   const int l = blockIdx.x;
   uint32_t *c = cnt + l * tl, *f = fst + l * tl;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   uint32_t run = 0;
-  for (int64_t base = 0; base < T; base += 1024) {
-    const int64_t k = base + tid;
-    const uint32_t v = k < T ? c[k] : 0u;
+  for (int64_t base = 0; base < T; base += kFSSub) {
+    const int m = (int)min<int64_t>(kFSSub, T - base);
+#pragma unroll
+    for (int j = 0; j < kFSItems; ++j) {
+      const int q = 1024 * j + tid;
+      buf[fs_pad(q)] = q < m ? c[base + q] : 0u;
+    }
+    __syncthreads();
+    uint32_t r[kFSItems], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kFSItems; ++j) {
+      r[j] = buf[fs_pad(kFSItems * tid + j)];
+      sum += r[j];
+    }
     uint32_t t;
-    const uint32_t e = block_exclusive_scan(v, sh, t);
-    if (k < T) c[k] = run + e;
+    uint32_t e = run + block_exclusive_scan(sum, sh, t);
+#pragma unroll
+    for (int j = 0; j < kFSItems; ++j) {
+      buf[fs_pad(kFSItems * tid + j)] = e;
+      e += r[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kFSItems; ++j) {
+      const int q = 1024 * j + tid;
+      if (q < m) c[base + q] = buf[fs_pad(q)];
+    }
     run += t;
+    __syncthreads();
   }
   if (tid == 0) { c[T] = run; tot[l] = run; }
-  // suffix minimum, chunks from the end
+  // suffix minimum, chunks from the end; positions past the chunk's m hold
+  // the identity
   uint32_t carry = (uint32_t)n;
-  for (int64_t hi = T; hi > 0; hi -= 1024) {
-    const int64_t k = hi - 1 - tid;           // thread tid takes the tid-th from the end
-    const uint32_t v = k >= 0 ? f[k] : 0xffffffffu;
-    // exclusive suffix minimum across the chunk: min over threads < tid
-    uint32_t x = v;
-    const int lane = tid & 63, wv = tid >> 6;
+  for (int64_t hi = T; hi > 0; hi -= kFSSub) {
+    const int m = (int)min<int64_t>(kFSSub, hi);
+    const int64_t lo = hi - m;
+#pragma unroll
+    for (int j = 0; j < kFSItems; ++j) {
+      const int q = 1024 * j + tid;
+      buf[fs_pad(q)] = q < m ? f[lo + q] : 0xffffffffu;
+    }
+    __syncthreads();
+    uint32_t r[kFSItems], rm = 0xffffffffu;
+#pragma unroll
+    for (int j = 0; j < kFSItems; ++j) {
+      r[j] = buf[fs_pad(kFSItems * tid + j)];
+      rm = min(rm, r[j]);
+    }
+    // minimum over the later runs: inclusive suffix over the wave's lanes,
+    // then over the later waves
+    uint32_t x = rm;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o, 64);
-      if (lane >= o) x = min(x, y);
+      const uint32_t y = __shfl_down(x, o, 64);
+      if (lane + o < 64) x = min(x, y);
     }
+    if (lane == 0) sh[wv] = x;
     __syncthreads();
-    if (lane == 63) sh[wv] = x;
-    __syncthreads();
-    uint32_t before = carry, all = carry;
+    uint32_t later = carry, all = carry;
     for (int q = 0; q < 16; ++q) {
-      const uint32_t t = sh[q];
-      if (q < wv) before = min(before, t);
-      all = min(all, t);
+      const uint32_t v = sh[q];
+      if (q > wv) later = min(later, v);
+      all = min(all, v);
     }
-    // x - own value: exclusive within the wave
-    uint32_t ex = __shfl_up(x, 1, 64);
-    if (lane == 0) ex = 0xffffffffu;
-    if (k >= 0) f[k] = min(before, ex);
+    const uint32_t xl = __shfl_down(x, 1, 64);   // later lanes of the wave
+    if (lane < 63) later = min(later, xl);
+    uint32_t cur = later;
+#pragma unroll
+    for (int j = kFSItems - 1; j >= 0; --j) {
+      buf[fs_pad(kFSItems * tid + j)] = cur;
+      cur = min(cur, r[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kFSItems; ++j) {
+      const int q = 1024 * j + tid;
+      if (q < m) f[lo + q] = buf[fs_pad(q)];
+    }
     carry = all;
+    __syncthreads();
   }
 }
 
