@@ -82,8 +82,11 @@ __global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restric
   bool bad = false;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nn;
        v += gridDim.x * blockDim.x) {
-    if (nchild[v] != 0) continue;
-    const uint32_t f = first[v], n = count[v];
+    // every per-node read at once, before the leaf test
+    const uint32_t nc = nchild[v], f = first[v], n = count[v];
+    const int lv = level[v];
+    const double cside = kBox ? 0.0 : cube[4 * nsys[v] + 3];
+    if (nc != 0) continue;
     double4 pr[kLeafRegs];
 #pragma unroll
     for (uint32_t q = 0; q < kLeafRegs; ++q)
@@ -124,9 +127,9 @@ __global__ __launch_bounds__(256) void k_moments_leaves(const int32_t *__restric
     if constexpr (kBox) {
       bbox[2 * (size_t)v] = make_double4(lo[0], lo[1], lo[2], 0.0);
       bbox[2 * (size_t)v + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
-      so = open_size(v, level[v], first, nsys, skey, cube, lo, hi, *refit > 0);
+      so = open_size(v, lv, first, nsys, skey, cube, lo, hi, *refit > 0);
     } else {
-      so = ldexp(cube[4 * nsys[v] + 3], -(int)level[v]);
+      so = ldexp(cside, -lv);
     }
     store_moments(v, so, M, cx, cy, cz, S, com, mom, side);
   }
@@ -170,9 +173,12 @@ __global__ __launch_bounds__(256) void k_moments_level(const int32_t *__restrict
   for (uint32_t v0 = a; v0 < e; v0 += n_oct) {      // uniform over the wave
     const uint32_t v = v0 + oct;
     const bool live = v < e;
+    // the node's reads at once: child count, first child, cell side
     const uint32_t nch = live ? nchild[v] : 0u;
+    const uint32_t c0 = live ? child[v] : 0u;
+    const double cside = (!kBox && live) ? cube[4 * nsys[v] + 3] : 0.0;
     const bool mine = k < nch;
-    const uint32_t c = mine ? child[v] + k : 0u;
+    const uint32_t c = mine ? c0 + k : 0u;
     double mc = 0.0, cx_ = 0.0, cy_ = 0.0, cz_ = 0.0;
     double4 cc = make_double4(0.0, 0.0, 0.0, 0.0);
     double o1 = 0.0, o2 = 0.0, o3 = 0.0, o4 = 0.0, o5 = 0.0, o6 = 0.0;
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(256) void k_moments_level(const int32_t *__restrict
         bbox[2 * (size_t)v + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
         so = open_size(v, l, first, nsys, skey, cube, lo, hi, *refit > 0);
       } else {
-        so = ldexp(cube[4 * nsys[v] + 3], -l);
+        so = ldexp(cside, -l);
       }
       store_moments(v, so, M, cx, cy, cz, S, com, mom, side);
     }
