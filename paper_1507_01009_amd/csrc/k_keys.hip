@@ -41,7 +41,8 @@ __global__ __launch_bounds__(256) void k_cube_part(const int32_t *__restrict__ g
   double lo[3] = {INFINITY, INFINITY, INFINITY};
   double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
-  for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u) {
+#pragma unroll 4
+  for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u) {   // unrolled: loads in flight together
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       double x = pos[3 * (size_t)i + k];
@@ -172,7 +173,8 @@ __global__ __launch_bounds__(256) void k_keys(const int32_t *__restrict__ gate, 
   const Tile t = tiles[blockIdx.x];
   const double *c = cube + 4 * system_of_tile(sys_tile0, S, blockIdx.x);
   const double sigma = (kDeep ? 4398046511104.0 : 2097152.0) / c[3];
-  for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u) {
+#pragma unroll 4
+  for (uint32_t i = t.start + threadIdx.x; i < t.end; i += 256u) {   // unrolled: loads in flight together
     if constexpr (kDeep) {
       uint64_t hi, lo;
       keys42(pos + 3 * (size_t)i, c, sigma, hi, lo);
