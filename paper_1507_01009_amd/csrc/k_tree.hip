@@ -264,13 +264,18 @@ __global__ __launch_bounds__(1024) void k_flat_scan(const int32_t *__restrict__ 
 }
 
 // rank of x among the level-l node starts: base of x's tile + bits before x
+// (All four bitmap words of x's tile are read at once and masked; a tile's
+// words are allocated up to and including the tile past the last.)
 __device__ __forceinline__ uint32_t rank_of(const uint64_t *__restrict__ bl,
                                             const uint32_t *__restrict__ cl, int64_t x) {
   const int64_t q = x >> 8;
+  const uint32_t wq = (uint32_t)((x & 255) >> 6), bq = (uint32_t)(x & 63);
+  const uint64_t *wv = bl + 4 * q;
+  const uint64_t part = bq ? (1ull << bq) - 1ull : 0ull;
   uint32_t r = cl[q];
-  const int wq = (int)((x & 255) >> 6), bq = (int)(x & 63);
-  for (int k = 0; k < wq; ++k) r += (uint32_t)__popcll(bl[4 * q + k]);
-  if (bq) r += (uint32_t)__popcll(bl[4 * q + wq] & ((1ull << bq) - 1ull));
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k)
+    r += (uint32_t)__popcll(wv[k] & (k < wq ? ~0ull : k == wq ? part : 0ull));
   return r;
 }
 
@@ -353,7 +358,16 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(const int32_t *__restrict__ g
     {
     const uint64_t *bl = bits + l * wl;
     const uint32_t *cl = cnt + l * tl;
-    const uint32_t id = lv[l] + rank_of(bl, cl, i);
+    // the ranks that do not depend on the node's end, read together: the
+    // node's own, its parent's (last level-(l - 1) start at or before i) and
+    // its first child's
+    const bool inner = l < top;
+    const uint64_t *bc = bits + (inner ? l + 1 : l) * wl;
+    const uint32_t *cc = cnt + (inner ? l + 1 : l) * tl;
+    const uint32_t rid = rank_of(bl, cl, i);
+    const uint32_t rpar = l == 0 ? 0u : rank_of(bits + (l - 1) * wl, cnt + (l - 1) * tl, i + 1);
+    const uint32_t r0 = inner ? rank_of(bc, cc, i) : 0u;
+    const uint32_t id = lv[l] + rid;
     // end: first j > i with d[j] < l (root: the system end)
     int64_t e;
     if (l == 0) {
@@ -382,12 +396,9 @@ __global__ __launch_bounds__(kFT) void k_flat_emit(const int32_t *__restrict__ g
     first[id] = (uint32_t)i;
     count[id] = (uint32_t)(e - i);
     nsys[id] = (uint32_t)s;
-    parent[id] = l == 0 ? kNone : lv[l - 1] + rank_of(bits + (l - 1) * wl, cnt + (l - 1) * tl, i + 1) - 1u;
+    parent[id] = l == 0 ? kNone : lv[l - 1] + rpar - 1u;
     uint32_t ch = 0, nch = 0;
-    if (l < top) {
-      const uint64_t *bc = bits + (l + 1) * wl;
-      const uint32_t *cc = cnt + (l + 1) * tl;
-      const uint32_t r0 = rank_of(bc, cc, i);
+    if (inner) {
       ch = lv[l + 1] + r0;
       nch = rank_of(bc, cc, e) - r0;
     }
