@@ -91,6 +91,7 @@ __global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ 
   __shared__ int64_t so[kMaxSys + 1];
   constexpr int kL = ML + 1;
   __shared__ uint32_t wc[kFT / 64][kL];
+  __shared__ unsigned long long wm[kFT / 64][kL];
   __shared__ uint32_t mj[kL];
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x, t0 = b * kFT, i = t0 + tid;
@@ -138,13 +139,20 @@ __global__ __launch_bounds__(kFT) void k_flat_flags(const int32_t *__restrict__ 
   }
   if (valid) lt[i] = ex ? (uint16_t)(lo | (top << 8)) : (uint16_t)0xffff;
   const int w = tid >> 6, lane = tid & 63;
+  // the wave's mask of every level first, then lane l stores level l's
+  unsigned long long msk[kL];
 #pragma unroll
-  for (int l = 0; l < kL; ++l) {
-    const unsigned long long msk = __ballot(ex && lo <= (uint32_t)l && (uint32_t)l <= top);
-    if (lane == 0) {
-      bits[l * wl + 4 * b + w] = msk;
-      wc[w][l] = (uint32_t)__popcll(msk);
-    }
+  for (int l = 0; l < kL; ++l)
+    msk[l] = __ballot(ex && lo <= (uint32_t)l && (uint32_t)l <= top);
+  if (lane == 0) {
+#pragma unroll
+    for (int l = 0; l < kL; ++l) wm[w][l] = msk[l];
+  }
+  // one wave's LDS accesses execute in order
+  if (lane < kL) {
+    const unsigned long long m = wm[w][lane];
+    bits[lane * wl + 4 * b + w] = m;
+    wc[w][lane] = (uint32_t)__popcll(m);
   }
   __syncthreads();
   if (tid < kL) {
