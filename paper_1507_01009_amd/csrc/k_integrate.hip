@@ -43,6 +43,31 @@ __global__ void k_drift(double *__restrict__ pos, const double *__restrict__ vel
     if (!frozen || !frozen[i / 3]) pos[i] = pos[i] + vel[i] * dt;
 }
 
+// The opening half kick and the drift of a whole KDK step in one pass over
+// the stars and then the SMBHs (the operations of k_kick and k_drift, in
+// that order, per particle): v <- v + a dt/2, x <- x + v dt.
+__global__ void k_kick_drift(double *__restrict__ pos, double *__restrict__ vel,
+                             const double *__restrict__ acc, const uint8_t *__restrict__ frozen,
+                             int64_t n, double *__restrict__ bpos, double *__restrict__ bvel,
+                             const double *__restrict__ bacc, int64_t nb, double dt) {
+#pragma clang fp contract(off)
+  const double h = dt * 0.5;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n + nb;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const bool star = t < n;
+    const int64_t i = star ? t : t - n;
+    if (star && frozen && frozen[i]) continue;
+    double *x = star ? pos : bpos, *v = star ? vel : bvel;
+    const double *a = star ? acc : bacc;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double vk = v[3 * i + k] + a[3 * i + k] * h;
+      v[3 * i + k] = vk;
+      x[3 * i + k] = x[3 * i + k] + vk * dt;
+    }
+  }
+}
+
 __device__ __forceinline__ int lmin_at(int64_t k, int nlev) {
   int l = 0;
   while (l < nlev - 1 && (k % ((int64_t)1 << (nlev - 1 - l))) != 0) ++l;
@@ -239,6 +264,15 @@ hipError_t launch_drift(tg_ctx *c, double *pos, const double *vel, int64_t n,
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_drift, dim3(grid_n(3 * n)), dim3(256), 0, c->stream, pos,
                      vel, 3 * n, dt, frozen);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(tg_ctx *c, double *pos, double *vel, const double *acc,
+                             const uint8_t *frozen, int64_t n, double *bpos, double *bvel,
+                             const double *bacc, int64_t nb, double dt) {
+  if (n + nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kick_drift, dim3(grid_n(n + nb)), dim3(256), 0, c->stream, pos, vel,
+                     acc, frozen, n, bpos, bvel, bacc, nb, dt);
   return hipGetLastError();
 }
 

@@ -1004,13 +1004,11 @@ tg_status tg_forces(tg_ctx *c, const tg_system *y, const int32_t *idx,
 tg_status tg_step_kdk(tg_ctx *c, const tg_system *y, double dt) {
   tg_status st = check_system(y, "tg_step_kdk");
   if (st != TG_OK) return st;
-  if ((st = kick_impl(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, dt, nullptr, 0, y->frozen)))
-    return st;
-  if ((st = tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt,
-                    nullptr, 0)))
-    return st;
-  if ((st = drift_impl(c, y->pos, y->vel, y->n, dt, y->frozen))) return st;
-  if ((st = tg_drift(c, y->bh_pos, y->bh_vel, y->n_bh, dt))) return st;
+  if (!c) return fail(TG_EINVAL, "tg_step_kdk: NULL context");
+  if (!std::isfinite(dt)) return fail(TG_EINVAL, "tg_step_kdk: dt not finite");
+  // opening half kicks and drifts of stars and SMBHs, one launch
+  TG_HIP(launch_kick_drift(c, y->pos, y->vel, y->acc, y->frozen, y->n, y->bh_pos, y->bh_vel,
+                           y->bh_acc, y->n_bh, dt));
   if ((st = tg_forces(c, y, nullptr, nullptr))) return st;
   if ((st = kick_impl(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, dt, nullptr, 0, y->frozen)))
     return st;
