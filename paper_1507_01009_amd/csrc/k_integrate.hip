@@ -43,27 +43,35 @@ __global__ void k_drift(double *__restrict__ pos, const double *__restrict__ vel
     if (!frozen || !frozen[i / 3]) pos[i] = pos[i] + vel[i] * dt;
 }
 
-// The opening half kick and the drift of a whole KDK step in one pass over
-// the stars and then the SMBHs (the operations of k_kick and k_drift, in
-// that order, per particle): v <- v + a dt/2, x <- x + v dt.
+// The half kicks of a whole KDK step in one pass over the stars and then
+// the SMBHs, the opening one followed by the drift (the operations of
+// k_kick and k_drift, in that order, per particle): v <- v + a dt/2, and
+// with drift set x <- x + v dt.
+__device__ __forceinline__ void kick_drift_one(double *__restrict__ x, double *__restrict__ v,
+                                               const double *__restrict__ a, double h, double dt,
+                                               int drift) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double vk = v[k] + a[k] * h;
+    v[k] = vk;
+    if (drift) x[k] = x[k] + vk * dt;
+  }
+}
+
 __global__ void k_kick_drift(double *__restrict__ pos, double *__restrict__ vel,
                              const double *__restrict__ acc, const uint8_t *__restrict__ frozen,
                              int64_t n, double *__restrict__ bpos, double *__restrict__ bvel,
-                             const double *__restrict__ bacc, int64_t nb, double dt) {
+                             const double *__restrict__ bacc, int64_t nb, double dt, int drift) {
 #pragma clang fp contract(off)
   const double h = dt * 0.5;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n + nb;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const bool star = t < n;
-    const int64_t i = star ? t : t - n;
-    if (star && frozen && frozen[i]) continue;
-    double *x = star ? pos : bpos, *v = star ? vel : bvel;
-    const double *a = star ? acc : bacc;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double vk = v[3 * i + k] + a[3 * i + k] * h;
-      v[3 * i + k] = vk;
-      x[3 * i + k] = x[3 * i + k] + vk * dt;
+    if (t < n) {
+      if (!(frozen && frozen[t])) kick_drift_one(pos + 3 * t, vel + 3 * t, acc + 3 * t, h, dt, drift);
+    } else {
+      const int64_t i = t - n;
+      kick_drift_one(bpos + 3 * i, bvel + 3 * i, bacc + 3 * i, h, dt, drift);
     }
   }
 }
@@ -269,10 +277,10 @@ hipError_t launch_drift(tg_ctx *c, double *pos, const double *vel, int64_t n,
 
 hipError_t launch_kick_drift(tg_ctx *c, double *pos, double *vel, const double *acc,
                              const uint8_t *frozen, int64_t n, double *bpos, double *bvel,
-                             const double *bacc, int64_t nb, double dt) {
+                             const double *bacc, int64_t nb, double dt, bool drift) {
   if (n + nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_n(n + nb)), dim3(256), 0, c->stream, pos, vel,
-                     acc, frozen, n, bpos, bvel, bacc, nb, dt);
+                     acc, frozen, n, bpos, bvel, bacc, nb, dt, drift ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -415,7 +415,7 @@ hipError_t launch_kick(tg_ctx *c, double *vel, const double *acc, int64_t n,
                        int skip_k0, const uint8_t *frozen = nullptr);
 hipError_t launch_kick_drift(tg_ctx *c, double *pos, double *vel, const double *acc,
                              const uint8_t *frozen, int64_t n, double *bpos, double *bvel,
-                             const double *bacc, int64_t nb, double dt);
+                             const double *bacc, int64_t nb, double dt, bool drift);
 hipError_t launch_drift(tg_ctx *c, double *pos, const double *vel, int64_t n,
                         double dt, const uint8_t *frozen = nullptr);
 hipError_t launch_levels(tg_ctx *c, const double *acc, const double *vel,

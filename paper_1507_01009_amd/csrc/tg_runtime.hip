@@ -1008,11 +1008,12 @@ tg_status tg_step_kdk(tg_ctx *c, const tg_system *y, double dt) {
   if (!std::isfinite(dt)) return fail(TG_EINVAL, "tg_step_kdk: dt not finite");
   // opening half kicks and drifts of stars and SMBHs, one launch
   TG_HIP(launch_kick_drift(c, y->pos, y->vel, y->acc, y->frozen, y->n, y->bh_pos, y->bh_vel,
-                           y->bh_acc, y->n_bh, dt));
+                           y->bh_acc, y->n_bh, dt, true));
   if ((st = tg_forces(c, y, nullptr, nullptr))) return st;
-  if ((st = kick_impl(c, y->vel, y->acc, y->n, nullptr, nullptr, nullptr, dt, nullptr, 0, y->frozen)))
-    return st;
-  return tg_kick(c, y->bh_vel, y->bh_acc, y->n_bh, nullptr, nullptr, nullptr, dt, nullptr, 0);
+  // closing half kicks, one launch
+  TG_HIP(launch_kick_drift(c, y->pos, y->vel, y->acc, y->frozen, y->n, y->bh_pos, y->bh_vel,
+                           y->bh_acc, y->n_bh, dt, false));
+  return TG_OK;
 }
 
 tg_status tg_step_dkd(tg_ctx *c, const tg_system *y, double dt) {
